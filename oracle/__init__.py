@@ -1,0 +1,424 @@
+"""Plain FP64 CPU oracle of the GRHD Runge-Kutta substep (ctypes binding).
+
+TEST INFRASTRUCTURE ONLY.  This package is the slow, obviously-correct
+reference that the GPU library is checked against.  Only ``tests/``,
+``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may
+import it; the product package never does, and it never imports the product
+package.  The C sources follow Lam & Shibata (arXiv 2502.03223) Sec. II.C;
+see the header comments of ``or_hydro.c``, ``or_riemann.c`` and ``or_mlp.c``.
+
+Plain-data conventions shared with the callers (data formats, not code):
+  grid   dict(nx, nz, ng, pitch, x0, z0, dx, dz, geom='cyl'|'cart',
+              bc=(xlo, xhi, zlo, zhi) names from BC_NAMES)
+  eos    dict(kind='ideal'|'hybrid', K=[..], G=[..], rho_b=[..], Gth=..)
+  metric dict name -> array (nz+2ng, pitch) or float; missing names take the
+         flat-space value (alp=1, W=1, gxx=gyy=gzz=1, others 0)
+  c2p    dict(w_max, rho_atm)
+Cell fields are float64 arrays of shape (nfield, nz+2ng, pitch).
+"""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRCS = ["or_hydro.c", "or_riemann.c", "or_mlp.c"]
+
+METRIC_NAMES = ["alp", "bx", "by", "bz", "W", "gxx", "gxy", "gxz", "gyy",
+                "gyz", "gzz", "kxx", "kxy", "kxz", "kyy", "kyz", "kzz"]
+FLAT = {"alp": 1.0, "W": 1.0, "gxx": 1.0, "gyy": 1.0, "gzz": 1.0}
+BC_NAMES = {"outflow": 0, "periodic": 1, "axis": 2, "reflect": 3, "external": 4}
+RECON = {"ppm": 0, "minmod": 1}
+RIEMANN = {"hllc": 0, "tvdlf": 1}
+NPARAM_MLP = 4481
+
+
+def build(force=True):
+    """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
+    srcs = [os.path.join(_HERE, s) for s in _SRCS]
+    if not force and os.path.exists(_SO) and all(
+            os.path.getmtime(_SO) >= os.path.getmtime(s) for s in srcs):
+        return _SO
+    tmp = _SO + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off",
+           "-fno-fast-math", "-Wall", "-o", tmp] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _SO)
+    return _SO
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int), ("nz", C.c_int), ("ng", C.c_int),
+                ("pitch", C.c_int64), ("x0", C.c_double), ("z0", C.c_double),
+                ("dx", C.c_double), ("dz", C.c_double), ("geom", C.c_int),
+                ("bc", C.c_int * 4)]
+
+
+class Eos(C.Structure):
+    _fields_ = [("kind", C.c_int), ("n", C.c_int), ("K", C.c_double * 8),
+                ("G", C.c_double * 8), ("rho_b", C.c_double * 8),
+                ("Gth", C.c_double)]
+
+
+class Metric(C.Structure):
+    _fields_ = [("f", C.c_void_p * 17), ("c", C.c_double * 17)]
+
+
+class C2P(C.Structure):
+    _fields_ = [("w_max", C.c_double), ("rho_atm", C.c_double)]
+
+
+class Stage(C.Structure):
+    _fields_ = [("a", C.c_double), ("b", C.c_double), ("c", C.c_double),
+                ("dt", C.c_double), ("g", C.c_double), ("d", C.c_double),
+                ("e", C.c_double)]
+
+
+class Diag(C.Structure):
+    _fields_ = [("max_courant", C.c_double), ("Mb", C.c_double),
+                ("J", C.c_double), ("n_rescale", C.c_ulonglong),
+                ("n_cold", C.c_ulonglong), ("n_atm", C.c_ulonglong),
+                ("n_fail", C.c_ulonglong)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        _lib = C.CDLL(_SO)
+        d, p, i = C.c_double, C.c_void_p, C.c_int
+        sig = {
+            "or_eos_press": (d, [p, d, d]),
+            "or_eos_eps_cold": (d, [p, d]),
+            "or_eos_press_cold": (d, [p, d]),
+            "or_eos_cs2": (d, [p, d, d, d]),
+            "or_prim2con_point": (None, [p, p, d, i, p, p]),
+            "or_con2prim_point": (C.c_uint, [p, p, d, i, p, p, p, p]),
+            "or_c2p_master": (d, [p, d, d, d, d]),
+            "or_valencia_flux_point": (None, [p, p, i, p, p]),
+            "or_face_flux_point": (None, [p, p, i, i, p, p, p, p]),
+            "or_source_point": (None, [p, p, p, d, i, p, p]),
+            "or_recon_line": (None, [i, i, p, p, p]),
+            "or_lagrange6": (d, [p]),
+            "or_deriv6": (d, [p, d]),
+            "or_prim2con": (None, [p, p, p, p, p, i]),
+            "or_con2prim": (None, [p, p, p, p, p, p, p, p]),
+            "or_fill_ghosts": (None, [p, p]),
+            "or_reconstruct": (None, [p, i, i, p, p, p]),
+            "or_face_flux": (None, [p, i, i, p, p, p, p, p, p]),
+            "or_rhs": (None, [p, p, p, p, p, p, p]),
+            "or_rk_substep": (i, [p, p, p, i, i, p, p, p, p, p, p, p, p, p, p, p]),
+            "or_riemann_solve": (i, [d, d, d, d, d, d, d, p]),
+            "or_riemann_sample": (None, [d, p, d, p, p, p]),
+            "or_riemann_cellavg": (i, [d, d, d, d, d, d, d, d, d, i, p, i, p, p, p]),
+            "or_mlp_forward": (None, [p, i, p, p]),
+            "or_mlp_loss_grad": (d, [p, i, p, p, p]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(_lib, name)
+            fn.restype = res
+            fn.argtypes = args
+    return _lib
+
+
+# ---------------------------------------------------------------- marshalling
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def make_grid(g):
+    s = Grid()
+    s.nx, s.nz, s.ng, s.pitch = g["nx"], g["nz"], g["ng"], g["pitch"]
+    s.x0, s.z0, s.dx, s.dz = g["x0"], g["z0"], g["dx"], g["dz"]
+    s.geom = 0 if g["geom"] == "cyl" else 1
+    for k in range(4):
+        s.bc[k] = BC_NAMES[g["bc"][k]]
+    return s
+
+
+def make_eos(e):
+    s = Eos()
+    s.kind = 0 if e["kind"] == "ideal" else 1
+    K, G = list(e["K"]), list(e["G"])
+    s.n = len(K)
+    for k in range(len(K)):
+        s.K[k], s.G[k] = K[k], G[k]
+    for k, r in enumerate(e.get("rho_b", [])):
+        s.rho_b[k] = r
+    s.Gth = e["Gth"]
+    return s
+
+
+def make_metric(m, keep):
+    """m: dict name -> array or float.  keep: list that holds array refs."""
+    s = Metric()
+    for k, name in enumerate(METRIC_NAMES):
+        v = m.get(name, FLAT.get(name, 0.0))
+        if isinstance(v, np.ndarray):
+            a = _f64(v)
+            keep.append(a)
+            s.f[k] = a.ctypes.data
+            s.c[k] = 0.0
+        else:
+            s.f[k] = None
+            s.c[k] = float(v)
+    return s
+
+
+def metric_point(m):
+    """17 metric values at a point from a dict of floats."""
+    return np.array([float(m.get(n, FLAT.get(n, 0.0))) for n in METRIC_NAMES])
+
+
+def make_c2p(c):
+    s = C2P()
+    s.w_max, s.rho_atm = c["w_max"], c["rho_atm"]
+    return s
+
+
+def _fieldptrs(arr, nf):
+    assert arr.dtype == np.float64 and arr.flags["C_CONTIGUOUS"]
+    assert arr.shape[0] == nf
+    ptrs = (C.c_void_p * nf)()
+    for c in range(nf):
+        ptrs[c] = arr[c].ctypes.data
+    return ptrs
+
+
+# ---------------------------------------------------------------- pointwise
+
+def eos_press(eos, rho, eps):
+    return lib().or_eos_press(C.byref(make_eos(eos)), rho, eps)
+
+
+def eos_cs2(eos, rho, eps, P):
+    return lib().or_eos_cs2(C.byref(make_eos(eos)), rho, eps, P)
+
+
+def eos_eps_cold(eos, rho):
+    return lib().or_eos_eps_cold(C.byref(make_eos(eos)), rho)
+
+
+def eos_press_cold(eos, rho):
+    return lib().or_eos_press_cold(C.byref(make_eos(eos)), rho)
+
+
+def prim2con_point(eos, g, x, geom, p):
+    g, p = _f64(g), _f64(p)
+    q = np.zeros(5)
+    lib().or_prim2con_point(C.byref(make_eos(eos)), _ptr(g), x,
+                            0 if geom == "cyl" else 1, _ptr(p), _ptr(q))
+    return q
+
+
+def con2prim_point(eos, g, x, geom, c2p, q):
+    g = _f64(g)
+    q = np.array(q, dtype=np.float64)
+    p = np.zeros(6)
+    z = np.zeros(1)
+    f = lib().or_con2prim_point(C.byref(make_eos(eos)), _ptr(g), x,
+                                0 if geom == "cyl" else 1,
+                                C.byref(make_c2p(c2p)), _ptr(q), _ptr(p), _ptr(z))
+    return p, q, int(f), float(z[0])
+
+
+def c2p_master(eos, D, qq, r, z):
+    return lib().or_c2p_master(C.byref(make_eos(eos)), D, qq, r, z)
+
+
+def valencia_flux_point(eos, g, dirn, p):
+    g, p = _f64(g), _f64(p)
+    F = np.zeros(5)
+    lib().or_valencia_flux_point(C.byref(make_eos(eos)), _ptr(g), dirn, _ptr(p), _ptr(F))
+    return F
+
+
+def face_flux_point(eos, g, dirn, riemann, pL, pR):
+    g, pL, pR = _f64(g), _f64(pL), _f64(pR)
+    F = np.zeros(5)
+    sp = np.zeros(1)
+    lib().or_face_flux_point(C.byref(make_eos(eos)), _ptr(g), dirn, RIEMANN[riemann],
+                             _ptr(pL), _ptr(pR), _ptr(F), _ptr(sp))
+    return F, float(sp[0])
+
+
+def source_point(eos, g, dg, x, geom, p):
+    g, dg, p = _f64(g), _f64(dg), _f64(p)
+    s = np.zeros(5)
+    lib().or_source_point(C.byref(make_eos(eos)), _ptr(g), _ptr(dg), x,
+                          0 if geom == "cyl" else 1, _ptr(p), _ptr(s))
+    return s
+
+
+def recon_line(recon, a):
+    a = _f64(a)
+    n = a.size
+    aL = np.zeros(max(n - 5, 0))
+    aR = np.zeros(max(n - 5, 0))
+    lib().or_recon_line(RECON[recon], n, _ptr(a), _ptr(aL), _ptr(aR))
+    return aL, aR
+
+
+def lagrange6(a):
+    a = _f64(a)
+    return lib().or_lagrange6(_ptr(a))
+
+
+def deriv6(a, h):
+    a = _f64(a)
+    return lib().or_deriv6(_ptr(a), h)
+
+
+# ---------------------------------------------------------------- grid level
+
+def prim2con(grid, eos, metric, p, with_ghosts=False):
+    keep = []
+    q = np.zeros((5,) + p.shape[1:])
+    lib().or_prim2con(C.byref(make_grid(grid)), C.byref(make_eos(eos)),
+                      C.byref(make_metric(metric, keep)), _fieldptrs(p, 6),
+                      _fieldptrs(q, 5), 1 if with_ghosts else 0)
+    return q
+
+
+def con2prim(grid, eos, metric, c2p, q):
+    """Returns (p, q_corrected, flags, diag).  q is not modified."""
+    keep = []
+    q = q.copy()
+    p = np.zeros((6,) + q.shape[1:])
+    flags = np.zeros(q.shape[1:], dtype=np.uint8)
+    d = Diag()
+    lib().or_con2prim(C.byref(make_grid(grid)), C.byref(make_eos(eos)),
+                      C.byref(make_metric(metric, keep)), C.byref(make_c2p(c2p)),
+                      _fieldptrs(q, 5), _fieldptrs(p, 6), _ptr(flags), C.byref(d))
+    return p, q, flags, d.as_dict()
+
+
+def fill_ghosts(grid, p):
+    p = p.copy()
+    lib().or_fill_ghosts(C.byref(make_grid(grid)), _fieldptrs(p, 6))
+    return p
+
+
+def face_shape(grid, dirn):
+    nx, nz = grid["nx"], grid["nz"]
+    return (nz, nx + 1) if dirn == 0 else (nz + 1, nx)
+
+
+def reconstruct(grid, dirn, recon, p):
+    shp = face_shape(grid, dirn)
+    pL = np.zeros((6,) + shp)
+    pR = np.zeros((6,) + shp)
+    lib().or_reconstruct(C.byref(make_grid(grid)), dirn, RECON[recon],
+                         _fieldptrs(p, 6), _fieldptrs(pL, 6), _fieldptrs(pR, 6))
+    return pL, pR
+
+
+def face_flux(grid, dirn, riemann, eos, metric, pL, pR):
+    keep = []
+    F = np.zeros((5,) + pL.shape[1:])
+    sp = np.zeros(1)
+    lib().or_face_flux(C.byref(make_grid(grid)), dirn, RIEMANN[riemann],
+                       C.byref(make_eos(eos)), C.byref(make_metric(metric, keep)),
+                       _fieldptrs(_f64(pL), 6), _fieldptrs(_f64(pR), 6),
+                       _fieldptrs(F, 5), _ptr(sp))
+    return F, float(sp[0])
+
+
+def rhs(grid, eos, metric, p, Fx, Fz):
+    keep = []
+    L = np.zeros((5,) + p.shape[1:])
+    lib().or_rhs(C.byref(make_grid(grid)), C.byref(make_eos(eos)),
+                 C.byref(make_metric(metric, keep)), _fieldptrs(p, 6),
+                 _fieldptrs(_f64(Fx), 5), _fieldptrs(_f64(Fz), 5), _fieldptrs(L, 5))
+    return L
+
+
+SSPRK3 = [dict(a=0.0, b=1.0, c=1.0), dict(a=0.75, b=0.25, c=0.25),
+          dict(a=1.0 / 3.0, b=2.0 / 3.0, c=2.0 / 3.0)]
+
+
+def rk_substep(grid, eos, metric, opts, stage, qn, qs, acc_in=None, want_acc=False):
+    """One substep.  Returns dict(qout, qs (corrected), p, flags, diag,
+    flux_reg, acc).  Inputs are not modified."""
+    keep = []
+    qs = qs.copy()
+    qout = np.zeros_like(qs)
+    p = np.zeros((6,) + qs.shape[1:])
+    flags = np.zeros(qs.shape[1:], dtype=np.uint8)
+    nb = 2 * grid["nz"] + 2 * grid["nx"]
+    freg = np.zeros(5 * nb)
+    d = Diag()
+    st = Stage()
+    st.a, st.b, st.c, st.dt = stage["a"], stage["b"], stage["c"], stage["dt"]
+    st.g, st.d, st.e = stage.get("g", 0.0), stage.get("d", 0.0), stage.get("e", 0.0)
+    acc_out = np.zeros_like(qs) if want_acc else None
+    qn_ptr = _fieldptrs(qn, 5) if qn is not None else None
+    lib().or_rk_substep(
+        C.byref(make_grid(grid)), C.byref(make_eos(eos)),
+        C.byref(make_metric(metric, keep)), RECON[opts.get("recon", "ppm")],
+        RIEMANN[opts.get("riemann", "hllc")], C.byref(make_c2p(opts["c2p"])),
+        C.byref(st), qn_ptr if qn is not None else _fieldptrs(qs, 5),
+        _fieldptrs(qs, 5), _fieldptrs(qout, 5), _fieldptrs(p, 6),
+        _fieldptrs(acc_in, 5) if acc_in is not None else None,
+        _fieldptrs(acc_out, 5) if acc_out is not None else None,
+        _ptr(freg), _ptr(flags), C.byref(d))
+    return dict(qout=qout, qs=qs, p=p, flags=flags, diag=d.as_dict(),
+                flux_reg=freg.reshape(5, nb), acc=acc_out)
+
+
+# ---------------------------------------------------------------- exact Riemann
+
+def riemann_solve(gam, L, R):
+    sol = np.zeros(16)
+    rc = lib().or_riemann_solve(gam, L[0], L[1], L[2], R[0], R[1], R[2], _ptr(sol))
+    if rc:
+        raise ValueError("Riemann problem produces vacuum")
+    return sol
+
+
+def riemann_sample(gam, sol, xi):
+    r, p, v = C.c_double(), C.c_double(), C.c_double()
+    lib().or_riemann_sample(gam, _ptr(_f64(sol)), xi, C.byref(r), C.byref(p), C.byref(v))
+    return r.value, p.value, v.value
+
+
+def riemann_cellavg(gam, L, R, xint, t, xface, nsub=64):
+    xface = _f64(xface)
+    n = xface.size - 1
+    rho, p, v = np.zeros(n), np.zeros(n), np.zeros(n)
+    rc = lib().or_riemann_cellavg(gam, L[0], L[1], L[2], R[0], R[1], R[2], xint, t,
+                                  n, _ptr(xface), nsub, _ptr(rho), _ptr(p), _ptr(v))
+    if rc:
+        raise ValueError("Riemann problem produces vacuum")
+    return rho, p, v
+
+
+# ---------------------------------------------------------------- MLP
+
+def mlp_forward(params, X):
+    params, X = _f64(params), _f64(X)
+    y = np.zeros(X.shape[0])
+    lib().or_mlp_forward(_ptr(params), X.shape[0], _ptr(X), _ptr(y))
+    return y
+
+
+def mlp_loss_grad(params, X, t):
+    params, X, t = _f64(params), _f64(X), _f64(t)
+    g = np.zeros(NPARAM_MLP)
+    loss = lib().or_mlp_loss_grad(_ptr(params), X.shape[0], _ptr(X), _ptr(t), _ptr(g))
+    return loss, g

@@ -1,0 +1,290 @@
+"""Seeded synthetic inputs for the GRHD substep (shared by tests and bench).
+
+This module holds no arithmetic of the hydro method itself: it only lays out
+grids, draws seeded random states, integrates the TOV equations for the
+initial star and the Cowling metric, and writes PRIMITIVE variables and
+metric fields.  The conversion to conserved variables is done separately by
+each side (the oracle's prim2con, the GPU's grhd_prim2con).
+
+Workload recipes (all synthetic; the paper's own runs use external initial
+data that is not available):
+  * Riemann problems on a flat metric, ideal gas G = 5/3, x in [0, 1],
+    interface at x = 0.5; states rho ~ logU[0.1, 10], p ~ logU[1e-3, 20],
+    v_x ~ U[-0.5, 0.5], v_y = v_z = 0, redrawn when the exact solution
+    contains vacuum (closed-form test below).
+  * TOV polytrope K = 100, G = 2 (G = c = Msun = 1), rho_c = 1.28e-3, mapped
+    onto a cylindrical (varpi, z) grid in isotropic coordinates; Cowling
+    metric alpha(r), W = psi^-2; beta = 0, conformal metric = identity,
+    K_ij = 0; atmosphere rho_atm = 1e-10; density perturbed by 1e-4 xi,
+    xi ~ U[-1, 1] iid per cell; P = K rho^G, u_i = 0.
+  * A differentially rotating field for the standalone recovery workload:
+    rho ~ logU[1e-10, 1e-2], eps = 100 rho (1 + theta), theta ~ U[0, 1],
+    Lorentz factor w(varpi) = 1 + 9 (varpi / 20)(1 + 0.05 xi) clipped to
+    [1, 10], u_y = w v, u_x = u_z = 0; flat metric.
+"""
+import math
+
+import numpy as np
+
+NG = 3
+
+
+def make_grid(nx, nz, x0, z0, dx, dz, geom, bc, ng=NG, pad=64):
+    """Cell-centred grid with ng ghosts; the row pitch is padded to a
+    multiple of `pad` doubles."""
+    row = nx + 2 * ng
+    pitch = ((row + pad - 1) // pad) * pad
+    return dict(nx=nx, nz=nz, ng=ng, pitch=pitch, x0=float(x0), z0=float(z0),
+                dx=float(dx), dz=float(dz), geom=geom, bc=tuple(bc))
+
+
+def cell_coords(grid):
+    """x and z of every stored cell (ghosts included), shape (rows, pitch);
+    padding columns get the coordinate of a far-right ghost."""
+    ng, pitch = grid["ng"], grid["pitch"]
+    rows = grid["nz"] + 2 * ng
+    j = np.arange(pitch) - ng
+    k = np.arange(rows) - ng
+    x = grid["x0"] + (j + 0.5) * grid["dx"]
+    z = grid["z0"] + (k + 0.5) * grid["dz"]
+    X, Z = np.meshgrid(x, z)
+    return X, Z
+
+
+def interior(grid, a):
+    """View of the interior cells of a field array (..., rows, pitch)."""
+    ng = grid["ng"]
+    return a[..., ng:ng + grid["nz"], ng:ng + grid["nx"]]
+
+
+def empty_fields(grid, nf):
+    return np.zeros((nf, grid["nz"] + 2 * grid["ng"], grid["pitch"]))
+
+
+# ------------------------------------------------------------------ EOS specs
+
+def ideal_eos(gamma, K=1.0):
+    """Gamma-law gas P = (G-1) rho eps; K is only used for the atmosphere."""
+    return dict(kind="ideal", K=[K], G=[gamma], rho_b=[], Gth=gamma)
+
+
+# ------------------------------------------------------------------ Riemann
+
+def _rapid(v):
+    return 0.5 * math.log((1 + v) / (1 - v))
+
+
+def riemann_has_vacuum(gam, L, R):
+    """Closed-form admissibility test: vacuum forms when the two
+    rarefactions expanded to zero pressure do not meet."""
+    def cs(rho, p):
+        h = 1 + gam / (gam - 1) * p / rho
+        return math.sqrt(gam * p / (rho * h))
+
+    def Fc(c):
+        s = math.sqrt(gam - 1)
+        return math.log((s + c) / (s - c)) / s
+    v0L = math.tanh(_rapid(L[2]) + Fc(cs(L[0], L[1])))
+    v0R = math.tanh(_rapid(R[2]) - Fc(cs(R[0], R[1])))
+    return v0L <= v0R
+
+
+def riemann_states(seed, n=1, gam=5.0 / 3.0):
+    """n seeded (L, R) states (rho, p, v_x), vacuum-free."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        rho = np.exp(rng.uniform(math.log(0.1), math.log(10.0), 2))
+        p = np.exp(rng.uniform(math.log(1e-3), math.log(20.0), 2))
+        v = rng.uniform(-0.5, 0.5, 2)
+        L = (float(rho[0]), float(p[0]), float(v[0]))
+        R = (float(rho[1]), float(p[1]), float(v[1]))
+        if not riemann_has_vacuum(gam, L, R):
+            out.append((L, R))
+    return out
+
+
+PAPER_SHOCK_TUBE = ((10.0, 40.0 / 3.0, 0.0), (1.0, 0.0, 0.0))
+
+
+def riemann_grid(nx, nz=8, length=1.0, geom="cart", direction="x"):
+    d = length / nx
+    if direction == "x":
+        return make_grid(nx, nz, 0.0, 0.0, d, d, geom,
+                         ("outflow", "outflow", "periodic", "periodic"))
+    return make_grid(nz, nx, 0.0, 0.0, d, d, geom,
+                     ("periodic", "periodic", "outflow", "outflow"))
+
+
+def riemann_prims(grid, L, R, gam=5.0 / 3.0, xint=0.5, direction="x"):
+    """Primitive arrays (rho, u_x, u_y, u_z, P, eps) of a flat-space
+    Riemann problem (covariant u_i = w v_i in flat space)."""
+    X, Z = cell_coords(grid)
+    s = X if direction == "x" else Z
+    left = s < xint
+    p = empty_fields(grid, 6)
+    for (st, mask) in ((L, left), (R, ~left)):
+        rho, pr, v = st
+        w = 1.0 / math.sqrt(1.0 - v * v)
+        p[0][mask] = rho
+        p[1 if direction == "x" else 3][mask] = w * v
+        p[4][mask] = pr
+        p[5][mask] = pr / ((gam - 1.0) * rho)
+    return p
+
+
+# ------------------------------------------------------------------ TOV star
+
+MSUN_KM = 1.476625
+
+
+def tov_solve(K=100.0, G=2.0, rho_c=1.28e-3, npts=20001):
+    """Spherical polytropic star: integrate the TOV equations in
+    Schwarzschild r, then the isotropic radius, lapse and baryon mass.
+    Returns a dict of tabulated profiles and the global numbers."""
+    from scipy.integrate import solve_ivp
+
+    # the density is integrated instead of the pressure (dP = G K rho^(G-1)
+    # drho): for G = 2 it falls linearly at the surface, which keeps the
+    # right-hand side smooth up to the surface.
+    def rhs(r, y):
+        m, rho, phi, ell, mb = y
+        rho = max(rho, 0.0)
+        P = K * rho ** G
+        e = rho + P / (G - 1.0)
+        f = 1.0 - 2.0 * m / r
+        dm = 4 * math.pi * r * r * e
+        dphi = (m + 4 * math.pi * r ** 3 * P) / (r * r * f)
+        dP = -(e + P) * dphi
+        drho = dP / (G * K * rho ** (G - 1.0)) if rho > 0 else 0.0
+        dell = (1.0 / math.sqrt(f) - 1.0) / r
+        dmb = 4 * math.pi * r * r * rho / math.sqrt(f)
+        return [dm, drho, dphi, dell, dmb]
+
+    Pc = K * rho_c ** G
+    ec = rho_c + Pc / (G - 1.0)
+    r0 = 1e-6
+    m0 = 4.0 / 3.0 * math.pi * r0 ** 3 * ec
+    y0 = [m0, rho_c, 0.0, 0.0, 4.0 / 3.0 * math.pi * r0 ** 3 * rho_c]
+
+    def surf(r, y):
+        return y[1]
+    surf.terminal = True
+    surf.direction = -1
+    sol = solve_ivp(rhs, [r0, 200.0], y0, method="DOP853", rtol=1e-12,
+                    atol=1e-16, events=surf, dense_output=True)
+    R = float(sol.t_events[0][0])
+    yR = sol.sol(R)
+    M, phiR, ellR, Mb = float(yR[0]), float(yR[2]), float(yR[3]), float(yR[4])
+    rbarR = 0.5 * (R - M + math.sqrt(R * R - 2 * M * R))
+    r = np.linspace(r0, R, npts)
+    Y = sol.sol(r)
+    phi_shift = 0.5 * math.log(1.0 - 2.0 * M / R) - phiR
+    ell_shift = math.log(rbarR / R) - ellR
+    ell = Y[3] + ell_shift
+    rbar = r * np.exp(ell)
+    rho = np.maximum(Y[1], 0.0)
+    alp = np.exp(Y[2] + phi_shift)
+    W = np.exp(ell)          # W = psi^-2 = rbar / r
+    return dict(K=K, G=G, rho_c=rho_c, R=R, M=M, Mb=Mb, Rbar=rbarR,
+                rbar=rbar, rho=rho, alp=alp, W=W)
+
+
+def tov_fields(tov, rbar):
+    """rho, alpha, W at isotropic radius rbar (array); exterior is the
+    isotropic Schwarzschild solution and rho = 0."""
+    from scipy.interpolate import CubicSpline
+    key = "_splines"
+    if key not in tov:
+        xs = np.concatenate(([0.0], tov["rbar"]))
+        tov[key] = tuple(CubicSpline(xs, np.concatenate(([v[0]], v)))
+                         for v in (tov["rho"], tov["alp"], tov["W"]))
+    srho, salp, sW = tov[key]
+    rb = np.asarray(rbar, dtype=np.float64)
+    inside = rb < tov["Rbar"]
+    M = tov["M"]
+    rs = np.maximum(rb, 1e-300)
+    psi = 1.0 + M / (2.0 * rs)
+    alp_out = (1.0 - M / (2.0 * rs)) / psi
+    W_out = 1.0 / (psi * psi)
+    rho = np.where(inside, np.maximum(srho(np.minimum(rb, tov["Rbar"])), 0.0), 0.0)
+    alp = np.where(inside, salp(np.minimum(rb, tov["Rbar"])), alp_out)
+    W = np.where(inside, sW(np.minimum(rb, tov["Rbar"])), W_out)
+    return rho, alp, W
+
+
+def star_grid(n, extent=20.0):
+    d = extent / n
+    return make_grid(n, n, 0.0, 0.0, d, d, "cyl",
+                     ("axis", "outflow", "reflect", "outflow"))
+
+
+def star_problem(grid, seed, tov=None, rho_atm=1e-10, pert=1e-4):
+    """(prims, metric dict, eos) for the perturbed TOV star on `grid`."""
+    if tov is None:
+        tov = tov_solve()
+    K, G = tov["K"], tov["G"]
+    X, Z = cell_coords(grid)
+    rbar = np.sqrt(X * X + Z * Z)
+    rho0, alp, W = tov_fields(tov, rbar)
+    rng = np.random.default_rng(seed)
+    xi = rng.uniform(-1.0, 1.0, size=rho0.shape)
+    rho = rho0 * (1.0 + pert * xi)
+    rho = np.maximum(rho, rho_atm)
+    p = empty_fields(grid, 6)
+    p[0] = rho
+    p[4] = K * rho ** G
+    p[5] = p[4] / ((G - 1.0) * rho)
+    metric = dict(alp=np.ascontiguousarray(alp), W=np.ascontiguousarray(W))
+    eos = ideal_eos(G, K=K)
+    return p, metric, eos
+
+
+def fmr_levels(nlev=6, n=256, finest_extent=20.0):
+    """Nested levels anchored at the origin, 2:1 refinement; level l covers
+    [0, finest_extent * 2^(nlev-1-l)]^2."""
+    return [star_grid(n, finest_extent * 2 ** (nlev - 1 - l)) for l in range(nlev)]
+
+
+def riemann_patch_sizes(seed, npatch=64, lo=128, hi=2048):
+    rng = np.random.default_rng(seed)
+    return [int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+            for _ in range(npatch)]
+
+
+# ------------------------------------------------------------------ recovery field
+
+def rotating_field(grid, seed):
+    """Primitive arrays of the differentially rotating recovery workload."""
+    rng = np.random.default_rng(seed)
+    X, Z = cell_coords(grid)
+    shp = X.shape
+    rho = np.exp(rng.uniform(math.log(1e-10), math.log(1e-2), shp))
+    theta = rng.uniform(0.0, 1.0, shp)
+    eps = 100.0 * rho * (1.0 + theta)
+    xi = rng.uniform(-1.0, 1.0, shp)
+    w = np.clip(1.0 + 9.0 * (np.abs(X) / 20.0) * (1.0 + 0.05 * xi), 1.0, 10.0)
+    v = np.sqrt(1.0 - 1.0 / (w * w))
+    p = empty_fields(grid, 6)
+    p[0] = rho
+    p[2] = w * v
+    p[5] = eps
+    p[4] = (2.0 - 1.0) * rho * eps   # gamma-law G = 2 pressure of (rho, eps)
+    return p
+
+
+def recovery_samples(seed, n):
+    """n primitive states (rho, u_x, u_y, u_z, P, eps) drawn from the same
+    distributions as the rotating field, flat metric (training inputs)."""
+    rng = np.random.default_rng(seed)
+    rho = np.exp(rng.uniform(math.log(1e-10), math.log(1e-2), n))
+    theta = rng.uniform(0.0, 1.0, n)
+    eps = 100.0 * rho * (1.0 + theta)
+    w = rng.uniform(1.0, 10.0, n)
+    v = np.sqrt(1.0 - 1.0 / (w * w))
+    out = np.zeros((n, 6))
+    out[:, 0] = rho
+    out[:, 2] = w * v
+    out[:, 5] = eps
+    out[:, 4] = rho * eps
+    return out

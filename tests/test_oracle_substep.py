@@ -1,0 +1,219 @@
+"""Pins of the oracle's whole substep (paper Sec. II.C.1, the discretised
+volume-averaged equations, and Sec. II.D's time integrator).
+
+- uniform states are kept bitwise in Cartesian geometry and to round-off in
+  cylindrical geometry (flat and TOV metric at rest need a truncation-level
+  residual only);
+- the totals sum(q dV) of every conserved component are kept to round-off on
+  doubly periodic Cartesian grids, and in cylindrical geometry the change of
+  M_b = sum(q_D dV) and J = sum(q_Sphi dV) equals the flux through the outer
+  face recorded in the flux register (the axis face has zero area);
+- the paper's shock tube converges to the exact solution (Sec. III.B.1);
+- a stationary contact is kept exactly by HLLC;
+- mirror and x<->z transpose symmetry.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+OPTS = dict(recon="ppm", riemann="hllc", c2p=dict(w_max=100.0, rho_atm=1e-12))
+SSP = [dict(a=0.0, b=1.0, c=1.0), dict(a=0.75, b=0.25, c=0.25),
+       dict(a=1.0 / 3.0, b=2.0 / 3.0, c=2.0 / 3.0)]
+
+
+def evolve(orc, grid, eos, metric, q, dt, nsteps, opts=OPTS):
+    for _ in range(nsteps):
+        qn = q
+        qs = q
+        for st in SSP:
+            stage = dict(st, dt=dt)
+            r = orc.rk_substep(grid, eos, metric, opts, stage, qn, qs)
+            if st["a"] == 0.0:
+                qn = r["qs"]   # corrected q^n (same buffer as q_s in stage 1)
+            qs = r["qout"]
+        q = qs
+    return q
+
+
+def uniform_prims(grid, rho, u, P, eps):
+    p = synth.empty_fields(grid, 6)
+    p[0], p[1], p[2], p[3], p[4], p[5] = rho, u[0], u[1], u[2], P, eps
+    return p
+
+
+@pytest.mark.parametrize("riemann", ["hllc", "tvdlf"])
+@pytest.mark.parametrize("recon", ["ppm", "minmod"])
+def test_uniform_state_bitwise_cartesian(orc, riemann, recon):
+    eos = synth.ideal_eos(5.0 / 3.0)
+    grid = synth.make_grid(12, 9, 0.0, 0.0, 0.1, 0.1, "cart", ("periodic",) * 4)
+    p = uniform_prims(grid, 0.8, (0.3, -0.2, 0.5), 0.4, 0.75)
+    q = orc.prim2con(grid, eos, {}, p, with_ghosts=True)
+    opts = dict(OPTS, recon=recon, riemann=riemann)
+    r = orc.rk_substep(grid, eos, {}, opts, dict(SSP[0], dt=0.04), q, q)
+    assert np.array_equal(synth.interior(grid, r["qout"]), synth.interior(grid, q))
+    # the right-hand side itself is exactly zero (stage a=b=0, c=dt=1 returns L)
+    r = orc.rk_substep(grid, eos, {}, opts, dict(a=0.0, b=0.0, c=1.0, dt=1.0), q, q)
+    assert not np.any(synth.interior(grid, r["qout"]))
+
+
+def test_uniform_rest_cylindrical(orc):
+    eos = synth.ideal_eos(2.0, 100.0)
+    grid = synth.make_grid(20, 8, 0.0, 0.0, 0.05, 0.05, "cyl",
+                           ("axis", "outflow", "reflect", "outflow"))
+    p = uniform_prims(grid, 1e-3, (0, 0, 0), 1e-4, 0.1)
+    q = orc.prim2con(grid, eos, {}, p, with_ghosts=True)
+    r = orc.rk_substep(grid, eos, {}, OPTS, dict(SSP[0], dt=0.02), q, q)
+    qi, qo = synth.interior(grid, q), synth.interior(grid, r["qout"])
+    assert np.abs(qo - qi).max() <= 1e-15 * np.abs(qi).max()
+
+
+def smooth_state(grid, rng):
+    X, Z = synth.cell_coords(grid)
+    kx = 2 * math.pi / (grid["nx"] * grid["dx"])
+    kz = 2 * math.pi / (grid["nz"] * grid["dz"])
+    ph = rng.uniform(0, 2 * math.pi, 6)
+    p = synth.empty_fields(grid, 6)
+    p[0] = 1.0 + 0.3 * np.sin(kx * X + ph[0]) * np.cos(kz * Z + ph[1])
+    p[1] = 0.4 * np.sin(kx * X + ph[2])
+    p[2] = 0.2 * np.cos(kz * Z + ph[3])
+    p[3] = 0.3 * np.sin(kx * X + kz * Z + ph[4])
+    p[4] = 0.5 + 0.2 * np.cos(kx * X - kz * Z + ph[5])
+    p[5] = p[4] / ((5.0 / 3.0 - 1.0) * p[0])
+    return p
+
+
+@pytest.mark.parametrize("riemann", ["hllc", "tvdlf"])
+def test_conservation_periodic_cartesian(orc, riemann):
+    eos = synth.ideal_eos(5.0 / 3.0)
+    grid = synth.make_grid(24, 20, 0.0, 0.0, 1 / 24, 1 / 20, "cart", ("periodic",) * 4)
+    p = smooth_state(grid, np.random.default_rng(1))
+    q = orc.prim2con(grid, eos, {}, p, with_ghosts=True)
+    tot0 = synth.interior(grid, q).sum(axis=(1, 2))
+    q1 = evolve(orc, grid, eos, {}, q, 0.01, 3, dict(OPTS, riemann=riemann))
+    tot1 = synth.interior(grid, q1).sum(axis=(1, 2))
+    scale = synth.interior(grid, np.abs(q)).sum(axis=(1, 2))
+    assert np.all(np.abs(tot1 - tot0) <= 1e-14 * scale)
+
+
+def test_conservation_cylindrical_with_flux_register(orc):
+    eos = synth.ideal_eos(5.0 / 3.0)
+    nx, nz, d = 24, 16, 1 / 24
+    grid = synth.make_grid(nx, nz, 0.0, 0.0, d, d, "cyl",
+                           ("axis", "outflow", "periodic", "periodic"))
+    p = smooth_state(grid, np.random.default_rng(2))
+    p[2] *= 3.0   # rotation: nonzero angular momentum
+    q = orc.prim2con(grid, eos, {}, p, with_ghosts=True)
+    X, _ = synth.cell_coords(grid)
+    dV = synth.interior(grid, 2 * math.pi * X * d * d)
+    dt = 0.01
+    r = orc.rk_substep(grid, eos, {}, OPTS, dict(SSP[0], dt=dt), q, q)
+    nb = 2 * nz + 2 * nx
+    freg = r["flux_reg"]
+    xhi = nx * d
+    for comp, name in ((0, "Mb"), (2, "J")):
+        before = (synth.interior(grid, r["qs"])[comp] * dV).sum()
+        after = r["diag"][name]
+        assert after == pytest.approx((synth.interior(grid, r["qout"])[comp] * dV).sum(), rel=1e-14)
+        # outer face flux (area 2 pi x dz), axis face has zero area, z periodic
+        outflow = dt * 2 * math.pi * xhi * d * freg[comp, nz:2 * nz].sum()
+        assert after - before == pytest.approx(-outflow, rel=1e-9, abs=1e-15 * abs(before))
+        assert np.all(freg[comp, 0:nz] * 0.0 == 0.0)
+
+
+def shock_tube(orc, n, riemann="hllc"):
+    eos = synth.ideal_eos(5.0 / 3.0)
+    L, R = synth.PAPER_SHOCK_TUBE
+    grid = synth.riemann_grid(n, nz=1)
+    p = synth.riemann_prims(grid, L, R)
+    q = orc.prim2con(grid, eos, {}, p, with_ghosts=True)
+    dt = 0.4 * grid["dx"]
+    nsteps = int(round(0.4 / dt))
+    q = evolve(orc, grid, eos, {}, q, dt, nsteps, dict(OPTS, riemann=riemann))
+    pf, _, _, _ = orc.con2prim(grid, eos, {}, OPTS["c2p"], q)
+    xf = np.arange(n + 1) * grid["dx"]
+    ex = orc.riemann_cellavg(5.0 / 3.0, L, R, 0.5, 0.4, xf, 64)
+    return xf, synth.interior(grid, pf)[:, 0], ex
+
+
+def shock_tube_l1(orc, n, riemann="hllc"):
+    xf, pi, ex = shock_tube(orc, n, riemann)
+    return np.abs(pi[0] - ex[0]).sum() * (xf[1] - xf[0])
+
+
+@pytest.mark.parametrize("riemann", ["hllc", "tvdlf"])
+def test_shock_tube_converges(orc, riemann):
+    """The paper's shock tube at t = 0.4: L1(rho) falls with resolution
+    (contact-limited, order > 0.6) and the star-region plateau between the
+    rarefaction tail and the contact matches the exact solution."""
+    e1 = shock_tube_l1(orc, 100, riemann)
+    e2 = shock_tube_l1(orc, 200, riemann)
+    xf, pi, ex = shock_tube(orc, 400, riemann)
+    e3 = np.abs(pi[0] - ex[0]).sum() * (xf[1] - xf[0])
+    assert e2 < e1 and e3 < e2
+    assert math.log(e1 / e3, 4) > 0.6
+    assert e3 < 0.04
+    xc = 0.5 * (xf[1:] + xf[:-1])
+    m = (xc > 0.65) & (xc < 0.75)
+    W = np.sqrt(1 + pi[1] ** 2)
+    assert pi[0][m].mean() == pytest.approx(ex[0][m].mean(), rel=2e-3)
+    assert pi[4][m].mean() == pytest.approx(ex[1][m].mean(), rel=2e-3)
+    assert (pi[1] / W)[m].mean() == pytest.approx(ex[2][m].mean(), rel=2e-3)
+
+
+def test_stationary_contact_hllc(orc):
+    eos = synth.ideal_eos(5.0 / 3.0)
+    grid = synth.riemann_grid(40, nz=2)
+    p = synth.riemann_prims(grid, (1.0, 1.0, 0.0), (0.1, 1.0, 0.0))
+    q = orc.prim2con(grid, eos, {}, p, with_ghosts=True)
+    q1 = evolve(orc, grid, eos, {}, q, 0.01, 5)
+    assert np.array_equal(synth.interior(grid, q1), synth.interior(grid, q))
+    q2 = evolve(orc, grid, eos, {}, q, 0.01, 5, dict(OPTS, riemann="tvdlf"))
+    assert not np.array_equal(synth.interior(grid, q2)[0], synth.interior(grid, q)[0])
+
+
+def test_mirror_and_transpose(orc):
+    eos = synth.ideal_eos(5.0 / 3.0)
+    (L, R), = synth.riemann_states(7, 1)
+    n = 48
+    gx = synth.riemann_grid(n, nz=4)
+    px = synth.riemann_prims(gx, L, R)
+    qx = orc.prim2con(gx, eos, {}, px, with_ghosts=True)
+    dt = 0.4 / n
+    ox = orc.rk_substep(gx, eos, {}, OPTS, dict(SSP[0], dt=dt), qx, qx)["qout"]
+    # transpose: same problem along z
+    gz = synth.riemann_grid(n, nz=4, direction="z")
+    pz = synth.riemann_prims(gz, L, R, direction="z")
+    qz = orc.prim2con(gz, eos, {}, pz, with_ghosts=True)
+    oz = orc.rk_substep(gz, eos, {}, OPTS, dict(SSP[0], dt=dt), qz, qz)["qout"]
+    ix, iz = synth.interior(gx, ox), synth.interior(gz, oz)
+    assert np.array_equal(ix[0], iz[0].T) and np.array_equal(ix[1], iz[3].T)
+    assert np.array_equal(ix[4], iz[4].T)
+    # mirror: reflect the problem about x = 1/2
+    pm = synth.riemann_prims(gx, (R[0], R[1], -R[2]), (L[0], L[1], -L[2]))
+    qm = orc.prim2con(gx, eos, {}, pm, with_ghosts=True)
+    om = orc.rk_substep(gx, eos, {}, OPTS, dict(SSP[0], dt=dt), qm, qm)["qout"]
+    im = synth.interior(gx, om)
+    assert np.allclose(im[0][:, ::-1], ix[0], rtol=1e-14)
+    assert np.allclose(-im[1][:, ::-1], ix[1], rtol=1e-14, atol=1e-14)
+    assert np.allclose(im[4][:, ::-1], ix[4], rtol=1e-14)
+
+
+def test_star_at_rest_residual_is_truncation(orc):
+    """TOV star in its Cowling metric: L(q) -> 0 with resolution away from
+    the surface (hydrostatic balance of flux divergence and sources)."""
+    tov = synth.tov_solve()
+    res = []
+    for n in (32, 64):
+        grid = synth.star_grid(n, extent=12.0)
+        p, metric, eos = synth.star_problem(grid, seed=0, tov=tov, pert=0.0)
+        q = orc.prim2con(grid, eos, metric, p, with_ghosts=True)
+        r = orc.rk_substep(grid, eos, metric, dict(OPTS, c2p=dict(w_max=100.0, rho_atm=1e-10)),
+                           dict(SSP[0], dt=1.0), q, q)
+        X, Z = synth.cell_coords(grid)
+        core = synth.interior(grid, np.sqrt(X ** 2 + Z ** 2) < 0.5 * tov["Rbar"])
+        dS = synth.interior(grid, r["qout"] - q)[1][core]
+        res.append(np.abs(dS).max())
+    assert res[1] < 0.6 * res[0]   # at least first order (PPM clips the central maximum)
