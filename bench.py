@@ -1,0 +1,233 @@
+"""Benchmark of the GRHD Runge-Kutta substep on one MI355X.
+
+Workload (default): the perturbed TOV star (K = 100, Gamma = 2,
+rho_c = 1.28e-3, Cowling metric) on a 1024 x 1024 cylindrical grid covering
+[0, 20]^2, PPM + HLLC, SSP-RK3.  A benchmark step is one full SSP-RK3 time
+step = three substeps (each: recovery + the fused reconstruction / flux /
+divergence / source / stage kernel), with the diagnostic reductions on.
+Inputs are resident in HBM before the timed region.
+
+Metric: zone-updates/s (interior cells x substeps / second), FP64 path.
+The JSON line also carries the mixed-precision form (FP32 reconstruction and
+flux) with its L1 error against the FP64 path after 1000 substeps, the
+roofline of the substep and the oracle timed on a bounded sample on the host.
+
+  python bench.py [--steps K] [--warmup W] [--n N] [--gpus 1]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per zone-update of one fused stage (FP64 state, metric
+# arrays alpha and W, everything read or written once): stage 1 reads q_s
+# (40) and the metric (16) and writes q_out (40); stages 2-3 also read q^n.
+BYTES_STAGE = [96.0, 136.0, 136.0]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--accuracy-substeps", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-rows", type=int, default=128)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import synth
+    from paper_2502_03223_amd import grhd
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    grid = synth.star_grid(n, extent=20.0)
+    tov = synth.tov_solve()
+    p_np, metric_np, eos = synth.star_problem(grid, seed=2025, tov=tov)
+    metric = {k: torch.from_numpy(v).to(dev) for k, v in metric_np.items()}
+    c2p = dict(w_max=100.0, rho_atm=1e-10)
+    dt = 0.4 * grid["dx"]
+    nzone = grid["nx"] * grid["nz"]
+
+    def make_state():
+        p = torch.from_numpy(p_np).to(dev)
+        q = torch.zeros((5,) + p.shape[1:], dtype=torch.float64, device=dev)
+        grhd.prim2con(grid, eos, metric, p, q, with_ghosts=True)
+        return q
+
+    class Stepper:
+        def __init__(self, prec):
+            opts = dict(recon="ppm", riemann="hllc", prec=prec, c2p=c2p)
+            self.sub = grhd.Substep(grid, eos, metric, opts)
+            self.q = make_state()
+            self.q1 = torch.zeros_like(self.q)
+            self.q2 = torch.zeros_like(self.q)
+            self.p = torch.zeros((6,) + self.q.shape[1:], dtype=torch.float64, device=dev)
+            self.diag = grhd.new_diag()
+            self.stages = [grhd.make_stage(dict(s, dt=dt)) for s in grhd.SSPRK3]
+
+        def step(self, events=None):
+            # q -> q1 -> q2 -> q (SSP-RK3, q^n = q)
+            bufs = [(self.q, self.q, self.q1), (self.q, self.q1, self.q2), (self.q, self.q2, self.q1)]
+            for s, (qn, qs, qo) in enumerate(bufs):
+                if events is not None:
+                    events[s][0].record()
+                self.sub(self.stages[s], qn, qs, qo, self.p, diag=self.diag)
+                if events is not None:
+                    events[s][1].record()
+            self.q, self.q1 = self.q1, self.q
+
+    # ---------------------------------------------------------------- FP64
+    st = Stepper("fp64")
+    for _ in range(args.warmup):
+        st.step()
+    torch.cuda.synchronize()
+    evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(3)]
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        st.step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stage_ms = np.array([[evs[k][s][0].elapsed_time(evs[k][s][1]) for s in range(3)]
+                         for k in range(args.steps)])
+    ms_per_step = wall * 1e3 / args.steps
+    value = 3 * nzone * args.steps / wall
+    mean_stage_ms = stage_ms.mean(axis=0)
+    bytes_per_step = sum(b * nzone for b in BYTES_STAGE)
+    achieved = bytes_per_step / (mean_stage_ms.sum() * 1e-3) / 1e9
+    diag = grhd.read_diag(st.diag)
+
+    # ---------------------------------------------------------------- mixed
+    sm = Stepper("mixed")
+    for _ in range(args.warmup):
+        sm.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sm.step()
+    torch.cuda.synchronize()
+    wall_m = time.perf_counter() - t0
+    value_m = 3 * nzone * args.steps / wall_m
+
+    # accuracy of the mixed form against the FP64 path after S substeps
+    nsteps_acc = args.accuracy_substeps // 3
+    a64, a32 = Stepper("fp64"), Stepper("mixed")
+    for _ in range(nsteps_acc):
+        a64.step()
+        a32.step()
+    grhd.con2prim(grid, eos, metric, c2p, a64.q.clone(), a64.p)
+    grhd.con2prim(grid, eos, metric, c2p, a32.q.clone(), a32.p)
+    torch.cuda.synchronize()
+    P64 = synth.interior(grid, a64.p.cpu().numpy())
+    P32 = synth.interior(grid, a32.p.cpu().numpy())
+    X, _ = synth.cell_coords(grid)
+    x = synth.interior(grid, X)
+    Wm = synth.interior(grid, metric_np["W"])
+    alp = synth.interior(grid, metric_np["alp"])
+    wgt = alp * Wm ** -3 * x           # sqrt(-g) dV / (2 pi dx dz)
+
+    def l1rel(a, b):
+        return float((np.abs(a - b) * wgt).sum() / (np.abs(b) * wgt).sum())
+
+    def vel(P):
+        w = np.sqrt(1.0 + Wm ** 2 * (P[1] ** 2 + P[2] ** 2 + P[3] ** 2))
+        return Wm ** 2 * P[1] / w, Wm ** 2 * P[3] / w
+    vx64, vz64 = vel(P64)
+    vx32, vz32 = vel(P32)
+    l1_v = float(((np.abs(vx32 - vx64) + np.abs(vz32 - vz64)) * x).sum() / x.sum())
+    accuracy = dict(substeps=3 * nsteps_acc, l1_rel_rho=l1rel(P32[0], P64[0]),
+                    l1_rel_eps=l1rel(P32[5], P64[5]), l1_abs_v=l1_v,
+                    max_abs_v_fp64=float(np.abs(np.stack([vx64, vz64])).max()))
+
+    # ---------------------------------------------------------------- CPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(grid, eos, metric_np, p_np, c2p, dt, args.cpu_sample_rows)
+
+    out = {
+        "metric": "zone-updates/s per GRHD RK substep at 1 GPU, FP64 plain vs mixed/batched",
+        "value": value,
+        "unit": "zone-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "TOV star K=100 Gamma=2 rho_c=1.28e-3, %dx%d cylindrical [0,20]^2, "
+                        "Cowling metric, PPM+HLLC, SSP-RK3 (3 substeps per step)" % (n, n),
+            "zones": nzone, "substeps_per_step": 3, "seed": 2025,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "grhd_rk_substep stage (k_con2prim + k_substep)",
+            "bytes_per_zone": BYTES_STAGE, "stage_ms": mean_stage_ms.tolist(),
+        },
+        "forms": {
+            "fp64": {"value": value, "ms_per_step": ms_per_step},
+            "mixed": {"value": value_m, "ms_per_step": wall_m * 1e3 / args.steps,
+                      "speedup_vs_fp64": value_m / value, "accuracy_vs_fp64": accuracy},
+        },
+        "diag_last_stage": {k: diag[k] for k in ("max_courant", "Mb", "n_atm", "n_cold", "n_rescale")},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+def cpu_baseline(grid, eos, metric_np, p_np, c2p, dt, rows):
+    """The oracle (single thread, plain C) on a horizontal band of the same
+    star grid: `rows` full rows through the stellar core, one SSP-RK3 step."""
+    import oracle
+    import synth
+    oracle.build(force=False)
+    ng = grid["ng"]
+    band = dict(grid, nz=rows, z0=grid["z0"],
+                bc=(grid["bc"][0], grid["bc"][1], "reflect", "outflow"))
+    sl = slice(0, rows + 2 * ng)
+    p = np.ascontiguousarray(p_np[:, sl])
+    met = {k: np.ascontiguousarray(v[sl]) for k, v in metric_np.items()}
+    q = oracle.prim2con(band, eos, met, p, with_ghosts=True)
+    opts = dict(recon="ppm", riemann="hllc", c2p=c2p)
+    t0 = time.perf_counter()
+    qn = q
+    qs = q
+    for s in [dict(a=0.0, b=1.0, c=1.0), dict(a=0.75, b=0.25, c=0.25),
+              dict(a=1.0 / 3.0, b=2.0 / 3.0, c=2.0 / 3.0)]:
+        r = oracle.rk_substep(band, eos, met, opts, dict(s, dt=dt), qn, qs)
+        if s["a"] == 0.0:
+            qn = r["qs"]
+        qs = r["qout"]
+    el = time.perf_counter() - t0
+    zones = band["nx"] * band["nz"] * 3
+    return {"value": zones / el, "unit": "zone-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "oracle FP64 C (gcc -O2, 1 thread): one SSP-RK3 step (3 substeps) of "
+                      "the %dx%d star grid restricted to its first %d rows (%d zone-updates, %.1f s)"
+                      % (grid["nx"], grid["nz"], rows, zones, el)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,265 @@
+/*
+ * grhd.h -- C ABI of the MI355X GRHD substep library (libgrhd.so).
+ *
+ * The library advances the axisymmetric general-relativistic hydrodynamics
+ * of Lam & Shibata, "SACRA-2D" (arXiv 2502.03223), Sec. II.C, by one
+ * Runge-Kutta stage on a cylindrical (varpi, z) mesh at y = 0, with the
+ * spacetime metric given as input fields (Cowling approximation).
+ *
+ * Conventions for every call:
+ *  - All array pointers are DEVICE pointers owned by the caller.  The
+ *    library never frees caller memory; the only library-owned objects are
+ *    plans (explicit create/destroy).
+ *  - Cell arrays: one FP64 array per field (SoA), row-major [z][x] with x
+ *    fastest, ng ghost layers on every side: cell (j,k), j in [-ng, nx+ng),
+ *    k in [-ng, nz+ng), is element (k+ng)*pitch + (j+ng).  ng must be 3.
+ *    x_j = x0 + (j+1/2) dx, z_k = z0 + (k+1/2) dz (the paper's cell-centred
+ *    grid, Sec. II.A).
+ *  - Face arrays (x faces): element k*(nx+1) + j is the face x_{j-1/2},
+ *    j = 0..nx, k = 0..nz-1.  (z faces): element k*nx + j is the face
+ *    z_{k-1/2}, k = 0..nz, j = 0..nx-1.
+ *  - Conserved variables (eq. cons_var) are densitised by psi^6 = W^-3:
+ *    q = (D, S_x, S_phi, S_z, E), S_phi = x S_y in cylindrical geometry
+ *    (S_y in Cartesian geometry).  Primitives p = (rho, u_x, u_y, u_z, P,
+ *    eps) with u_i the covariant spatial four-velocity (Cartesian basis).
+ *  - Calls are asynchronous on the caller's HIP stream (NULL = default
+ *    stream); results are valid after the caller synchronises.  Every call
+ *    validates its arguments before launching and returns a grhd_status; no
+ *    exception or abort crosses the ABI.  grhd_last_error() explains the
+ *    last failure of the calling thread.
+ *  - Trouble in a single cell during primitive recovery is not a call
+ *    error: it is reported through per-cell flags and the diag counters.
+ */
+#ifndef GRHD_H
+#define GRHD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GRHD_OK = 0,
+  GRHD_ERR_INVALID = -1,     /* bad argument: nothing was launched */
+  GRHD_ERR_DEVICE = -2,      /* a HIP call or launch failed */
+  GRHD_ERR_UNSUPPORTED = -3  /* valid but not implemented combination */
+} grhd_status;
+
+enum { GRHD_GEOM_CYLINDRICAL = 0, GRHD_GEOM_CARTESIAN = 1 };
+/* boundary conditions applied to primitives (AXIS only at x-low: u_x and
+ * u_y odd; REFLECT: normal velocity odd; EXTERNAL: ghost cells of q are
+ * supplied by the caller and recovered like interior cells) */
+enum { GRHD_BC_OUTFLOW = 0, GRHD_BC_PERIODIC = 1, GRHD_BC_AXIS = 2,
+       GRHD_BC_REFLECT = 3, GRHD_BC_EXTERNAL = 4 };
+enum { GRHD_RECON_PPM = 0, GRHD_RECON_MINMOD = 1 };
+enum { GRHD_RIEMANN_HLLC = 0, GRHD_RIEMANN_TVDLF = 1 };
+enum { GRHD_PREC_FP64 = 0, GRHD_PREC_MIXED = 1 };
+enum { GRHD_EOS_IDEAL = 0, GRHD_EOS_HYBRID = 1 };
+enum { GRHD_GUESS_NONE = 0, GRHD_GUESS_MLP = 1 };
+/* per-cell recovery flags */
+enum { GRHD_FLAG_RESCALE = 1, GRHD_FLAG_COLD = 2, GRHD_FLAG_ATM = 4,
+       GRHD_FLAG_FAIL = 8 };
+/* metric field indices of grhd_metric */
+enum { GRHD_M_ALP = 0, GRHD_M_BX, GRHD_M_BY, GRHD_M_BZ, GRHD_M_W,
+       GRHD_M_GXX, GRHD_M_GXY, GRHD_M_GXZ, GRHD_M_GYY, GRHD_M_GYZ, GRHD_M_GZZ,
+       GRHD_M_KXX, GRHD_M_KXY, GRHD_M_KXZ, GRHD_M_KYY, GRHD_M_KYZ, GRHD_M_KZZ,
+       GRHD_NMET };
+
+/* Cell-centred grid of one patch (Sec. II.A). */
+typedef struct {
+  int nx, nz, ng;         /* interior cells; ghosts (must be 3) */
+  int64_t pitch;          /* row pitch in elements, >= nx + 2 ng */
+  double x0, z0, dx, dz;  /* lower faces of cell (0,0); spacings > 0 */
+  int geom;               /* GRHD_GEOM_*; cylindrical needs x0 >= 0 */
+  int bc[4];              /* x-low, x-high, z-low, z-high: GRHD_BC_* */
+} grhd_grid;
+
+/* Hybrid EOS of Sec. II.C.3: piecewise-polytropic cold part plus a
+ * Gamma_th thermal part.  GRHD_EOS_IDEAL: P = (Gamma_th - 1) rho eps,
+ * eps_min = 0; K[0], Gamma[0] then only set the atmosphere pressure
+ * K[0] rho_atm^Gamma[0].  rho_b[i] is the upper density of piece i. */
+typedef struct {
+  int kind, npieces;
+  double K[8], Gamma[8], rho_b[8];
+  double Gamma_th;
+} grhd_eos;
+
+/* Metric fields (cell arrays with ghosts, read only).  NULL means the
+ * field is the uniform value cval[i].  Order: lapse, shift^x,y,z,
+ * W = psi^-2, conformal metric gt_xx,xy,xz,yy,yz,zz (det = 1),
+ * extrinsic curvature K_xx..K_zz.  Ghost values are the caller's (the axis
+ * parity of vector and tensor components is the caller's to apply). */
+typedef struct {
+  const double *f[GRHD_NMET];
+  double cval[GRHD_NMET];
+} grhd_metric;
+
+typedef struct { double *q[5]; } grhd_cons;      /* D, S_x, S_phi, S_z, E */
+typedef struct { double *p[6]; } grhd_prim;      /* rho, u_x, u_y, u_z, P, eps */
+
+/* Primitive recovery parameters (Sec. II.C.4). */
+typedef struct {
+  double w_max;           /* Lorentz-factor limit (100): sets k_max */
+  double rho_atm;         /* atmosphere density floor, > 0 */
+  double tol;             /* relative root tolerance (<= 0: 1e-14) */
+  int max_iter;           /* root-solver iteration cap (<= 0: 100) */
+  int guess;              /* GRHD_GUESS_* */
+  const void *mlp;        /* device weights for GRHD_GUESS_MLP (layout in
+                             grhd_mlp_forward) */
+} grhd_c2p_params;
+
+typedef struct {
+  int recon, riemann, prec;   /* GRHD_RECON_*, GRHD_RIEMANN_*, GRHD_PREC_* */
+  grhd_c2p_params c2p;
+  int tile_x, tile_z;         /* 0, 0 = library default */
+} grhd_options;
+
+/* One Runge-Kutta stage:
+ *   q_out   = a q^n + b q_s + c dt L(q_s) + g dt acc_in
+ *   acc_out = d acc_in + e L(q_s)
+ * SSP-RK3: (a,b,c) = (0,1,1), (3/4,1/4,1/4), (1/3,2/3,2/3), g = d = e = 0.
+ * Classical RK4 uses the accumulator (see the library notes). */
+typedef struct { double a, b, c, dt, g, d, e; } grhd_rk_stage;
+
+/* Device-resident diagnostics, overwritten by each call that takes one. */
+typedef struct {
+  double max_courant;     /* max |coordinate signal speed| dt / spacing */
+  double Mb, J;           /* sum q_D dV, sum q_Sphi dV of the output */
+  unsigned long long n_rescale, n_cold, n_atm, n_fail;  /* flagged cells */
+} grhd_diag;
+
+/* ---------------------------------------------------------------- calls */
+
+/* Conservative-to-primitive recovery, Sec. II.C.4 (Galeazzi master
+ * function f(z) = z - r / h(z) on [z-, z+], Illinois bracketed root, k
+ * rescaling for w_max, zero-temperature recovery when eps < eps_min,
+ * atmosphere floor).  Interior cells (plus EXTERNAL ghost strips).
+ * q: in; rewritten from the recovered primitives where a flag is set.
+ * p: out.  flags: nullable uint8 cell array.  diag: nullable (counters). */
+int grhd_con2prim(const grhd_grid *grid, const grhd_eos *eos,
+                  const grhd_metric *metric, const grhd_c2p_params *c2p,
+                  const grhd_cons *q, const grhd_prim *p, uint8_t *flags,
+                  grhd_diag *diag, void *hip_stream);
+
+/* Primitive-to-conservative map, eq. (cons_var).  with_ghosts != 0 also
+ * converts every ghost cell. */
+int grhd_prim2con(const grhd_grid *grid, const grhd_eos *eos,
+                  const grhd_metric *metric, const grhd_prim *p,
+                  const grhd_cons *q, int with_ghosts, void *hip_stream);
+
+/* Limited reconstruction of the primitives to the faces of direction dir
+ * (0 = varpi/x, 1 = z), Sec. II.C.2: third-order PPM or minmod.  p holds
+ * interior primitives; ghost values come from the boundary conditions
+ * (EXTERNAL: from p's ghost cells).  pL, pR: face arrays of 6 fields, FP64
+ * (prec = FP64) or FP32 (prec = MIXED; pointers then address float). */
+int grhd_reconstruct(const grhd_grid *grid, int dir, int recon, int prec,
+                     const grhd_prim *p, const grhd_prim *pL,
+                     const grhd_prim *pR, void *hip_stream);
+
+/* Riemann flux at the faces of direction dir, Sec. II.C.2: HLLC in the
+ * face tetrad frame (Mignone & Bodo) with the back-transform to the
+ * Eulerian frame, or TVD Lax-Friedrichs.  Face metric by 6-point
+ * interpolation.  F: densitised face flux of q, 5 FP64 face arrays; the
+ * S_phi component carries the x factor (x of the face for x faces, of the
+ * cell centre for z faces) in cylindrical geometry.  max_speed: nullable
+ * device double, receives the largest |coordinate signal speed|. */
+int grhd_hllc_flux(const grhd_grid *grid, int dir, int riemann, int prec,
+                   const grhd_eos *eos, const grhd_metric *metric,
+                   const grhd_prim *pL, const grhd_prim *pR,
+                   const grhd_cons *F, double *max_speed, void *hip_stream);
+
+/* One Runge-Kutta stage of the whole hot path, Sec. II.C.1: recovery of
+ * q_s (corrected in place), ghost handling, reconstruction and Riemann
+ * fluxes in both directions, area-weighted divergence with the cylindrical
+ * and metric source terms, stage combination.
+ * qn: q^n (read only when stage->a != 0; may alias qs).  qs: in/out.
+ * qout: out (interior cells; must not alias qs or qn).
+ * p: required workspace and output: primitives of q_s (interior cells).
+ * acc_in / acc_out: nullable accumulator cell arrays (RK4).
+ * flux_reg: nullable, 5 x (2 nz + 2 nx) doubles: the q fluxes on the
+ * x-low, x-high, z-low, z-high boundary faces (refluxing hook).
+ * flags: nullable uint8 cell array.  diag: nullable. */
+int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos,
+                    const grhd_metric *metric, const grhd_options *opts,
+                    const grhd_rk_stage *stage, const grhd_cons *qn,
+                    const grhd_cons *qs, const grhd_cons *qout,
+                    const grhd_prim *p, const grhd_cons *acc_in,
+                    const grhd_cons *acc_out, double *flux_reg,
+                    uint8_t *flags, grhd_diag *diag, void *hip_stream);
+
+/* ------------------------------------------------ batched persistent path */
+
+/* One patch of a batch: any mixture of refinement levels and independent
+ * instances; each patch carries its own grid, metric, state and stage. */
+typedef struct {
+  grhd_grid grid;
+  grhd_metric metric;
+  grhd_cons qn, qs, qout;
+  grhd_prim p;               /* required workspace/output per patch */
+  grhd_rk_stage stage;
+  int eos_id;                /* index into the plan's EOS table */
+  double *flux_reg;          /* nullable */
+} grhd_patch;
+
+typedef struct grhd_plan grhd_plan;   /* opaque, library-owned */
+
+/* Build a plan for a fixed set of patch shapes: tile shape (from tune_cache
+ * if given and present, else measured and stored there), device patch and
+ * work tables, persistent-launch configuration and the captured graph. */
+int grhd_plan_create(const grhd_patch *patches, int npatch,
+                     const grhd_eos *eos_table, int neos,
+                     const grhd_options *opts, const char *tune_cache,
+                     grhd_plan **out);
+
+/* One substep of every patch in one graph-captured launch sequence
+ * (recovery, then one persistent kernel over all (patch, tile) items).
+ * The patch array must have the shapes given at plan creation; pointers
+ * and stage coefficients may change between calls. */
+int grhd_batch_levels(grhd_plan *plan, const grhd_patch *patches, int npatch,
+                      grhd_diag *diag, void *hip_stream);
+
+int grhd_plan_destroy(grhd_plan *plan);
+
+/* Tile shape used by a plan (for reporting). */
+int grhd_plan_tile(const grhd_plan *plan, int *tile_x, int *tile_z);
+
+/* ---------------------------------------------------------- learned guess */
+
+/* MLP 3 -> 64 -> 64 -> 1 (tanh) giving the initial pressure guess of the
+ * recovery.  Device weight buffer layout (bytes, 256-aligned blocks):
+ * see GRHD_MLP_* below.  Features: (log10 D, S/(D + tau), log10(tau/D))
+ * standardised by (mean, std) in the buffer; output log10(P/D) scaled by
+ * (mean, std).  X: n x 3 FP32 features (raw), y: n FP32 outputs. */
+#define GRHD_MLP_HIDDEN 64
+#define GRHD_MLP_NPARAM 4481
+int grhd_mlp_forward(const void *mlp, const float *X, float *y, int n,
+                     void *hip_stream);
+
+/* One Adam step of MSE training on a batch (X n x 3 standardised
+ * features, t n standardised targets): master FP32 parameters params,
+ * Adam moments m, v (GRHD_MLP_NPARAM floats each), grad workspace
+ * (GRHD_MLP_NPARAM floats), loss (device float, nullable).  The BF16
+ * weights used by the forward kernels are refreshed into mlp. */
+int grhd_mlp_train_step(void *mlp, float *params, float *m, float *v,
+                        float *grad, const float *X, const float *t, int n,
+                        float lr, int step, float *loss, void *hip_stream);
+
+/* Gradient only (for checking): grad <- d(mean (y - t)^2)/d params at the
+ * FP32 params (BF16-rounded for the matrix products, as in training). */
+int grhd_mlp_grad(const float *params, float *grad, const float *X,
+                  const float *t, int n, float *loss, void *hip_stream);
+
+/* Pack FP32 params + feature/target scalers into a device weight buffer. */
+int grhd_mlp_pack(void *mlp, const float *params, const float *scal /*8*/,
+                  void *hip_stream);
+size_t grhd_mlp_bytes(void);
+
+/* ---------------------------------------------------------------- misc */
+const char *grhd_last_error(void);
+const char *grhd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

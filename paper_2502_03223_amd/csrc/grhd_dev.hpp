@@ -1,0 +1,747 @@
+// grhd_dev.hpp -- gfx950 device functions of the GRHD substep.
+//
+// Physics: Lam & Shibata, SACRA-2D (arXiv 2502.03223), Sec. II.C.  The
+// readings taken where the paper is silent or misprinted are restated at
+// each function.  Reconstruction and the Riemann solver are templated on
+// the arithmetic type T (double, or float in the mixed-precision path);
+// recovery, sources, divergence and the stage update are always double.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "grhd.h"
+
+namespace grhd {
+
+// ------------------------------------------------------------ launch data
+
+struct GridK {
+  int nx, nz, ng;
+  long long pitch;
+  double x0, z0, dx, dz;
+  int geom;
+  int bc[4];
+};
+
+struct EosK {
+  int kind, n;
+  double K[8], G[8], rho_b[8], deps[8];
+  double Gth;
+  double P_atm, eps_atm, rho_atm;
+};
+
+struct MetK {
+  const double *f[GRHD_NMET];
+  double c[GRHD_NMET];
+};
+
+struct C2PK {
+  double kmax, tol;
+  int max_iter, guess;
+  const void *mlp;
+};
+
+enum MetricClass { MC_CF = 0, MC_GEN = 1 };  // conformally flat static / general
+
+__device__ __forceinline__ long long cell_index(const GridK &g, int j, int k) {
+  return (long long)(k + g.ng) * g.pitch + (j + g.ng);
+}
+
+__device__ __forceinline__ double mval(const MetK &m, int f, long long i) {
+  return m.f[f] ? m.f[f][i] : m.c[f];
+}
+
+template <class T> __device__ __forceinline__ T tsqrt(T x) { return sqrt(x); }
+template <> __device__ __forceinline__ float tsqrt<float>(float x) { return sqrtf(x); }
+
+// inverse of a symmetric 3x3 (xx,xy,xz,yy,yz,zz) by cofactors / det
+template <class T>
+__device__ __forceinline__ void inv_sym3(const T *a, T *inv) {
+  T cxx = a[3] * a[5] - a[4] * a[4];
+  T cxy = a[2] * a[4] - a[1] * a[5];
+  T cxz = a[1] * a[4] - a[2] * a[3];
+  T cyy = a[0] * a[5] - a[2] * a[2];
+  T cyz = a[1] * a[2] - a[0] * a[4];
+  T czz = a[0] * a[3] - a[1] * a[1];
+  T det = a[0] * cxx + a[1] * cxy + a[2] * cxz;
+  T id = T(1) / det;
+  inv[0] = cxx * id; inv[1] = cxy * id; inv[2] = cxz * id;
+  inv[3] = cyy * id; inv[4] = cyz * id; inv[5] = czz * id;
+}
+
+__device__ __forceinline__ int s3i(int i, int j) {
+  // (xx,xy,xz,yy,yz,zz) storage index of the symmetric element (i,j)
+  return (i == j) ? (i == 0 ? 0 : (i == 1 ? 3 : 5)) : (i + j == 1 ? 1 : (i + j == 2 ? 2 : 4));
+}
+
+// ------------------------------------------------------------ EOS (II.C.3)
+
+__device__ __forceinline__ int eos_piece(const EosK &e, double rho) {
+  int i = 0;
+  while (i < e.n - 1 && rho >= e.rho_b[i]) i++;
+  return i;
+}
+
+__device__ __forceinline__ double eps_cold(const EosK &e, double rho) {
+  if (e.kind == GRHD_EOS_IDEAL) return 0.0;
+  int i = eos_piece(e, rho);
+  return e.K[i] / (e.G[i] - 1.0) * pow(rho, e.G[i] - 1.0) + e.deps[i];
+}
+
+__device__ __forceinline__ double press_cold(const EosK &e, double rho) {
+  if (e.kind == GRHD_EOS_IDEAL) return 0.0;
+  int i = eos_piece(e, rho);
+  return e.K[i] * pow(rho, e.G[i]);
+}
+
+__device__ __forceinline__ double eos_press(const EosK &e, double rho, double eps) {
+  if (e.kind == GRHD_EOS_IDEAL) return (e.Gth - 1.0) * rho * eps;
+  return press_cold(e, rho) + (e.Gth - 1.0) * rho * (eps - eps_cold(e, rho));
+}
+
+// c_s^2 from dP/drho|_eps + (P/rho^2) dP/deps|_rho at the given (rho, eps),
+// with an independent (reconstructed) P; clamped to [0, 0.999999].
+template <class T>
+__device__ __forceinline__ T eos_cs2(const EosK &e, T rho, T eps, T P) {
+  T gm1 = T(e.Gth - 1.0);
+  T chi;
+  if (e.kind == GRHD_EOS_IDEAL) {
+    chi = gm1 * eps;
+  } else {
+    double rd = (double)rho;
+    int i = eos_piece(e, rd);
+    T kr = T(e.K[i] * pow(rd, e.G[i] - 1.0));
+    T ec = T(e.K[i] / (e.G[i] - 1.0)) * kr + T(e.deps[i]);
+    chi = T(e.G[i]) * kr + gm1 * (eps - ec) - gm1 * kr;
+  }
+  T h = T(1) + eps + P / rho;
+  T cs2 = (chi + P / rho * gm1) / h;
+  if (!(cs2 > T(0))) cs2 = T(0);
+  if (cs2 > T(0.999999)) cs2 = T(0.999999);
+  return cs2;
+}
+
+// ------------------------------------------------ prim -> con (cons_var)
+
+// conserved vector (densitised, Cartesian S components, E total) of a
+// primitive state, given W and the inverse conformal metric (GEN) or not.
+template <int MC>
+__device__ __forceinline__ void prim2con_cell(double W, const double *gtu, double x,
+                                              int geom, const double *p, double *q) {
+  double usq;
+  if (MC == MC_GEN) {
+    usq = 0.0;
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) usq += gtu[s3i(i, j)] * p[1 + i] * p[1 + j];
+    usq *= W * W;
+  } else {
+    usq = W * W * (p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
+  }
+  double w = sqrt(1.0 + usq);
+  double rho = p[0], P = p[4], eps = p[5];
+  double h = 1.0 + eps + P / rho;
+  double sg = 1.0 / (W * W * W);
+  double rhw = rho * h * w;
+  q[0] = sg * (rho * w);
+  q[1] = sg * (rhw * p[1]);
+  q[2] = sg * (rhw * p[2]);
+  if (geom == GRHD_GEOM_CYLINDRICAL) q[2] = x * q[2];
+  q[3] = sg * (rhw * p[3]);
+  q[4] = sg * (rhw * w - P);
+}
+
+// ------------------------------------------------ con -> prim (II.C.4)
+
+// Master function f(z) = z - r / h(z) with eps-hat clamped to eps_min.
+__device__ __forceinline__ double c2p_master(const EosK &e, double D, double qq,
+                                             double r, double z) {
+  double w = sqrt(1.0 + z * z);
+  double eps = w * qq - z * r + z * z / (1.0 + w);
+  double h;
+  if (e.kind == GRHD_EOS_IDEAL) {
+    // (1+eps)(1+a) with a = P/(rho(1+eps)) reduces to 1 + Gamma eps
+    if (eps < 0.0) eps = 0.0;
+    h = 1.0 + e.Gth * eps;
+  } else {
+    double rho = D / w;
+    double emin = eps_cold(e, rho);
+    if (eps < emin) eps = emin;
+    double P = eos_press(e, rho, eps);
+    double a = P / (rho * (1.0 + eps));
+    h = (1.0 + eps) * (1.0 + a);
+  }
+  return z - r / h;
+}
+
+__device__ __forceinline__ double c2p_cold_fn(const EosK &e, double D, double r, double z) {
+  double w = sqrt(1.0 + z * z);
+  double rho = D / w;
+  double hc = 1.0 + eps_cold(e, rho) + press_cold(e, rho) / rho;
+  return z - r / hc;
+}
+
+// Illinois (modified regula falsi) on a bracket with f(a) < 0 < f(b).
+template <bool COLD>
+__device__ double illinois(const EosK &e, double D, double qq, double r, double a,
+                           double b, double tol, int max_iter, int *iters) {
+  double fa = COLD ? c2p_cold_fn(e, D, r, a) : c2p_master(e, D, qq, r, a);
+  if (!(fa < 0.0)) return a;
+  double fb = COLD ? c2p_cold_fn(e, D, r, b) : c2p_master(e, D, qq, r, b);
+  if (!(fb > 0.0)) return b;
+  int side = 0;
+  double c = a;
+  for (int it = 0; it < max_iter; it++) {
+    double cp = c;
+    c = (a * fb - b * fa) / (fb - fa);
+    if (!(c > a && c < b)) c = 0.5 * (a + b);
+    double fc = COLD ? c2p_cold_fn(e, D, r, c) : c2p_master(e, D, qq, r, c);
+    if (iters) (*iters)++;
+    if (fc > 0.0) {
+      b = c; fb = fc;
+      if (side == -1) fa *= 0.5;
+      side = -1;
+    } else if (fc < 0.0) {
+      a = c; fa = fc;
+      if (side == 1) fb *= 0.5;
+      side = 1;
+    } else {
+      break;
+    }
+    if (fabs(c - cp) <= tol * c || (b - a) <= tol * c) break;
+  }
+  return c;
+}
+
+struct C2PResult {
+  unsigned flags;
+  int iters;
+};
+
+// Full recovery of one cell.  q: densitised conserved (in; rewritten from
+// the primitives when a flag is set).  W, gtu: metric at the cell.
+// zguess >= 0 enables a safeguarded Newton start inside the bracket.
+template <int MC>
+__device__ C2PResult con2prim_cell(const EosK &e, const C2PK &cp, double W,
+                                   const double *gtu, double x, int geom, double *q,
+                                   double *p, double zguess) {
+  C2PResult res{0u, 0};
+  double W3 = W * W * W;
+  bool ok = isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]) && isfinite(q[3]) &&
+            isfinite(q[4]);
+  double D = W3 * q[0];
+  double S[3];
+  S[0] = W3 * q[1];
+  S[1] = (geom == GRHD_GEOM_CYLINDRICAL) ? W3 * (q[2] / x) : W3 * q[2];
+  S[2] = W3 * q[3];
+  double E = W3 * q[4];
+  if (!(D > 0.0) || !(E > 0.0)) ok = false;
+  if (ok) {
+    double S2;
+    if (MC == MC_GEN) {
+      S2 = 0.0;
+      for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) S2 += gtu[s3i(i, j)] * S[i] * S[j];
+      S2 *= W * W;
+    } else {
+      S2 = W * W * (S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+    }
+    double r = sqrt(S2) / D;
+    double qq = E / D - 1.0;
+    double k = r / (1.0 + qq);
+    if (k > cp.kmax) {
+      double sc = cp.kmax / k;
+      S[0] *= sc; S[1] *= sc; S[2] *= sc;
+      r = cp.kmax * (1.0 + qq);
+      k = cp.kmax;
+      res.flags |= GRHD_FLAG_RESCALE;
+    }
+    double z = 0.0;
+    if (k > 0.0) {
+      double zm = 0.5 * k / sqrt(1.0 - 0.25 * k * k);
+      double zp = k / sqrt(1.0 - k * k);
+      bool done = false;
+      if (zguess >= 0.0) {
+        // safeguarded Newton from the learned guess (derivative by a
+        // one-sided secant of width 1e-7 z), at most 8 steps, on the bracket
+        double zz = fmin(fmax(zguess, zm), zp);
+        for (int it = 0; it < 8; it++) {
+          double f0 = c2p_master(e, D, qq, r, zz);
+          double hh = 1e-7 * zz + 1e-300;
+          double f1 = c2p_master(e, D, qq, r, zz + hh);
+          res.iters += 2;
+          double df = (f1 - f0) / hh;
+          double zn = zz - f0 / df;
+          if (!(zn >= zm && zn <= zp)) break;
+          double dz = fabs(zn - zz);
+          zz = zn;
+          if (dz <= cp.tol * zz) { done = true; break; }
+        }
+        if (done) z = zz;
+      }
+      if (!done) z = illinois<false>(e, D, qq, r, zm, zp, cp.tol, cp.max_iter, &res.iters);
+    }
+    double w = sqrt(1.0 + z * z);
+    double rho = D / w;
+    double eps = w * qq - z * r + z * z / (1.0 + w);
+    double P;
+    if (eps < eps_cold(e, rho)) {
+      if (e.kind == GRHD_EOS_IDEAL) {
+        z = r;  // h_cold = 1: the zero-temperature root is z = r
+      } else {
+        z = (r > 0.0) ? illinois<true>(e, D, qq, r, 0.0, r, cp.tol, cp.max_iter, &res.iters)
+                      : 0.0;
+      }
+      w = sqrt(1.0 + z * z);
+      rho = D / w;
+      eps = eps_cold(e, rho);
+      P = press_cold(e, rho);
+      res.flags |= GRHD_FLAG_COLD;
+    } else {
+      P = eos_press(e, rho, eps);
+    }
+    double h = 1.0 + eps + P / rho;
+    double Dh = D * h;
+    p[0] = rho;
+    p[1] = S[0] / Dh;
+    p[2] = S[1] / Dh;
+    p[3] = S[2] / Dh;
+    p[4] = P;
+    p[5] = eps;
+    if (!isfinite(rho) || !isfinite(P) || !isfinite(eps) || !isfinite(p[1]) ||
+        !isfinite(p[2]) || !isfinite(p[3]))
+      ok = false;
+  }
+  if (!ok) res.flags |= GRHD_FLAG_FAIL | GRHD_FLAG_ATM;
+  if (!ok || p[0] < e.rho_atm) {
+    p[0] = e.rho_atm; p[1] = 0.0; p[2] = 0.0; p[3] = 0.0;
+    p[4] = e.P_atm; p[5] = e.eps_atm;
+    res.flags |= GRHD_FLAG_ATM;
+  }
+  if (res.flags) prim2con_cell<MC>(W, gtu, x, geom, p, q);
+  return res;
+}
+
+// ------------------------------------------------ reconstruction (II.C.2)
+// PPM of Colella & Woodward (1984): monotonised central slopes, interface
+// values, parabola limiter; no steepening or flattening.  Contraction into
+// FMA is switched off so the limiter decisions are taken on the same
+// rounded values as a plain evaluation.
+
+template <class T>
+__device__ __forceinline__ T mono_slope(T am, T a0, T ap) {
+#pragma clang fp contract(off)
+  T d = T(0.5) * (ap - am);
+  if ((ap - a0) * (a0 - am) > T(0)) {
+    T m = fabs(d);
+    T l = T(2) * fabs(a0 - am);
+    T r = T(2) * fabs(ap - a0);
+    if (l < m) m = l;
+    if (r < m) m = r;
+    return copysign(m, d);
+  }
+  return T(0);
+}
+
+template <class T>
+__device__ __forceinline__ void ppm_cell(T a, T aL, T aR, T &oL, T &oR) {
+#pragma clang fp contract(off)
+  if ((aR - a) * (a - aL) <= T(0)) {
+    aL = a;
+    aR = a;
+  } else {
+    T dA = aR - aL;
+    T a6 = T(6) * (a - T(0.5) * (aL + aR));
+    if (dA * a6 > dA * dA) aL = T(3) * a - T(2) * aR;
+    else if (-(dA * dA) > dA * a6) aR = T(3) * a - T(2) * aL;
+  }
+  oL = aL;
+  oR = aR;
+}
+
+// left and right states at the face between s[2] and s[3] of a 6-cell stencil
+template <class T>
+__device__ __forceinline__ void ppm_face(const T *s, T &L, T &R) {
+#pragma clang fp contract(off)
+  T d1 = mono_slope(s[0], s[1], s[2]);
+  T d2 = mono_slope(s[1], s[2], s[3]);
+  T d3 = mono_slope(s[2], s[3], s[4]);
+  T d4 = mono_slope(s[3], s[4], s[5]);
+  T i1 = s[1] + T(0.5) * (s[2] - s[1]) - (d2 - d1) / T(6);
+  T i2 = s[2] + T(0.5) * (s[3] - s[2]) - (d3 - d2) / T(6);
+  T i3 = s[3] + T(0.5) * (s[4] - s[3]) - (d4 - d3) / T(6);
+  T l0, r0, l1, r1;
+  ppm_cell(s[2], i1, i2, l0, r0);
+  ppm_cell(s[3], i2, i3, l1, r1);
+  L = r0;
+  R = l1;
+}
+
+template <class T>
+__device__ __forceinline__ T minmod(T a, T b) {
+  if (a * b <= T(0)) return T(0);
+  return (fabs(a) < fabs(b)) ? a : b;
+}
+
+template <class T>
+__device__ __forceinline__ void minmod_face(const T *s, T &L, T &R) {
+#pragma clang fp contract(off)
+  T si = minmod(s[2] - s[1], s[3] - s[2]);
+  T sj = minmod(s[3] - s[2], s[4] - s[3]);
+  L = s[2] + T(0.5) * si;
+  R = s[3] - T(0.5) * sj;
+}
+
+template <class T>
+__device__ __forceinline__ void recon_face(int recon, const T *s, T &L, T &R) {
+  if (recon == GRHD_RECON_MINMOD) minmod_face(s, L, R);
+  else ppm_face(s, L, R);
+}
+
+// 6-point centred interpolation to the face (metric is smooth) and the
+// sixth-order centred first derivative.
+template <class T>
+__device__ __forceinline__ T lagrange6(const T *a) {
+  return (T(3) * a[0] - T(25) * a[1] + T(150) * a[2] + T(150) * a[3] - T(25) * a[4] +
+          T(3) * a[5]) * T(1.0 / 256.0);
+}
+
+__device__ __forceinline__ double deriv6(const double *a, double inv60h) {
+  return (-a[0] + 9.0 * a[1] - 45.0 * a[2] + 45.0 * a[4] - 9.0 * a[5] + a[6]) * inv60h;
+}
+
+// ------------------------------------------------ Riemann solvers (II.C.2)
+
+template <class T> struct PrimT { T rho, u[3], P, eps; };
+
+// face metric
+template <class T> struct FaceMet {
+  T alp, W, beta[3], gt[6];
+};
+
+// Flux in the tau form: (D, S_x, S_y, S_z, tau = E - D), densitised.
+template <class T> struct FluxT { T f[5]; T speed; };
+
+// tetrad-frame state; q/f order (D, S_n, S_t1, S_t2, tau)
+template <class T> struct TState { T q[5], f[5], vn, P, lm, lp; };
+
+template <class T>
+__device__ __forceinline__ void tetrad_state(const EosK &e, const PrimT<T> &p, const T *ut,
+                                             TState<T> &s) {
+  T usq = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+  T w = tsqrt(T(1) + usq);
+  T iw = T(1) / w;
+  T vn = ut[0] * iw;
+  T iw2 = iw * iw;            // 1 - v^2
+  T v2 = usq * iw2;
+  T h = T(1) + p.eps + p.P / p.rho;
+  T D = p.rho * w;
+  T rhw = D * h;
+  s.q[0] = D;
+  s.q[1] = rhw * ut[0];
+  s.q[2] = rhw * ut[1];
+  s.q[3] = rhw * ut[2];
+  // tau = rho h w^2 - P - rho w without cancellation
+  s.q[4] = D * usq / (T(1) + w) + D * p.eps * w + p.P * usq;
+  s.vn = vn;
+  s.P = p.P;
+  s.f[0] = s.q[0] * vn;
+  s.f[1] = s.q[1] * vn + p.P;
+  s.f[2] = s.q[2] * vn;
+  s.f[3] = s.q[3] * vn;
+  s.f[4] = (s.q[4] + p.P) * vn;
+  T cs2 = eos_cs2<T>(e, p.rho, p.eps, p.P);
+  T cs = tsqrt(cs2);
+  T disc = iw2 * (T(1) - v2 * cs2 - (T(1) - cs2) * vn * vn);
+  if (disc < T(0)) disc = T(0);
+  T sd = cs * tsqrt(disc);
+  T a0 = vn * (T(1) - cs2);
+  T iden = T(1) / (T(1) - v2 * cs2);
+  s.lm = (a0 - sd) * iden;
+  s.lp = (a0 + sd) * iden;
+}
+
+template <class T>
+__device__ __forceinline__ void hllc_star(const TState<T> &s, T lam, T lc, T Pc, T *qc) {
+  T dl = lam - s.vn;
+  T id = T(1) / (lam - lc);
+  qc[0] = s.q[0] * dl * id;
+  qc[1] = (s.q[1] * dl + Pc - s.P) * id;
+  qc[2] = s.q[2] * dl * id;
+  qc[3] = s.q[3] * dl * id;
+  qc[4] = (s.q[4] * dl + Pc * lc - s.P * s.vn) * id;
+}
+
+// HLLC in the face tetrad frame; G = f - v_int q of the selected region.
+template <class T>
+__device__ __forceinline__ void hllc_tetrad(const TState<T> &L, const TState<T> &R, T vint,
+                                            T *G, T &lamL, T &lamR) {
+  lamL = fmin(L.lm, R.lm);
+  lamR = fmax(L.lp, R.lp);
+  if (!(lamR - lamL > T(0))) {
+    const TState<T> &s = (vint <= lamL) ? L : R;
+    for (int m = 0; m < 5; m++) G[m] = s.f[m] - vint * s.q[m];
+    return;
+  }
+  T idl = T(1) / (lamR - lamL);
+  T qh[5], fh[5];
+  for (int m = 0; m < 5; m++) {
+    qh[m] = (lamR * R.q[m] - lamL * L.q[m] + L.f[m] - R.f[m]) * idl;
+    fh[m] = (lamR * L.f[m] - lamL * R.f[m] + lamR * lamL * (R.q[m] - L.q[m])) * idl;
+  }
+  // contact speed: root of fE lc^2 - (E + fSn) lc + Sn = 0 (E = tau + D)
+  T qa = fh[4] + fh[0];
+  T qb = -(qh[4] + qh[0] + fh[1]);
+  T qc = qh[1];
+  T disc = qb * qb - T(4) * qa * qc;
+  if (disc < T(0)) disc = T(0);
+  T den = -qb + tsqrt(disc);
+  T lc = (den > T(0)) ? T(2) * qc / den : T(0);
+  if (!(den > T(0)) || !(lc > lamL && lc < lamR)) {
+    if (vint <= lamL) for (int m = 0; m < 5; m++) G[m] = L.f[m] - vint * L.q[m];
+    else if (vint <= lamR) for (int m = 0; m < 5; m++) G[m] = fh[m] - vint * qh[m];
+    else for (int m = 0; m < 5; m++) G[m] = R.f[m] - vint * R.q[m];
+    return;
+  }
+  T Pc = -lc * qa + fh[1];
+  if (vint <= lamL) {
+    for (int m = 0; m < 5; m++) G[m] = L.f[m] - vint * L.q[m];
+  } else if (vint <= lc) {
+    T qs[5];
+    hllc_star(L, lamL, lc, Pc, qs);
+    for (int m = 0; m < 5; m++) G[m] = L.f[m] + lamL * (qs[m] - L.q[m]) - vint * qs[m];
+  } else if (vint <= lamR) {
+    T qs[5];
+    hllc_star(R, lamR, lc, Pc, qs);
+    for (int m = 0; m < 5; m++) G[m] = R.f[m] + lamR * (qs[m] - R.q[m]) - vint * qs[m];
+  } else {
+    for (int m = 0; m < 5; m++) G[m] = R.f[m] - vint * R.q[m];
+  }
+}
+
+// Valencia flux in direction n (tau form) and conserved vector (tau form),
+// densitised, plus coordinate characteristic speeds.
+template <class T, int MC>
+__device__ __forceinline__ void valencia(const EosK &e, const FaceMet<T> &m, const T *gtu, int n,
+                                         const PrimT<T> &p, T *F, T *Q, T &lm, T &lp) {
+  T W = m.W;
+  T usq, un, gnn;
+  if (MC == MC_GEN) {
+    usq = T(0);
+    un = T(0);
+    for (int i = 0; i < 3; i++) {
+      for (int j = 0; j < 3; j++) usq += gtu[s3i(i, j)] * p.u[i] * p.u[j];
+      un += gtu[s3i(n, i)] * p.u[i];
+    }
+    usq *= W * W;
+    un *= W * W;
+    gnn = W * W * gtu[s3i(n, n)];
+  } else {
+    usq = W * W * (p.u[0] * p.u[0] + p.u[1] * p.u[1] + p.u[2] * p.u[2]);
+    un = W * W * p.u[n];
+    gnn = W * W;
+  }
+  T w = tsqrt(T(1) + usq);
+  T iw = T(1) / w;
+  T vn = un * iw;
+  T h = T(1) + p.eps + p.P / p.rho;
+  T D = p.rho * w;
+  T tau = D * usq / (T(1) + w) + D * p.eps * w + p.P * usq;
+  T sg = T(1) / (W * W * W);
+  T bn = (MC == MC_GEN) ? m.beta[n] : T(0);
+  T tr = m.alp * vn - bn;
+  T rhw = D * h;
+  F[0] = sg * (D * tr);
+  for (int j = 0; j < 3; j++) F[1 + j] = sg * (rhw * p.u[j] * tr + ((j == n) ? m.alp * p.P : T(0)));
+  F[4] = sg * (tau * tr + m.alp * p.P * vn);
+  Q[0] = sg * D;
+  for (int j = 0; j < 3; j++) Q[1 + j] = sg * (rhw * p.u[j]);
+  Q[4] = sg * tau;
+  T cs2 = eos_cs2<T>(e, p.rho, p.eps, p.P);
+  T cs = tsqrt(cs2);
+  T v2 = usq * iw * iw;
+  T disc = (iw * iw) * (gnn * (T(1) - v2 * cs2) - vn * vn * (T(1) - cs2));
+  if (disc < T(0)) disc = T(0);
+  T a = m.alp / (T(1) - v2 * cs2);
+  lm = a * (vn * (T(1) - cs2) - cs * tsqrt(disc)) - bn;
+  lp = a * (vn * (T(1) - cs2) + cs * tsqrt(disc)) - bn;
+}
+
+// Face flux (tau form), direction dir (0 = x, 1 = z).  speed: largest
+// |coordinate signal speed|.
+template <class T, int MC>
+__device__ __forceinline__ void face_flux(const EosK &e, const FaceMet<T> &m, int dir, int riemann,
+                                          const PrimT<T> &pL, const PrimT<T> &pR, FluxT<T> &out) {
+  const int n = (dir == 0) ? 0 : 2;
+  T gtu[6];
+  if (MC == MC_GEN) inv_sym3(m.gt, gtu);
+  if (riemann == GRHD_RIEMANN_TVDLF) {
+    T fL[5], fR[5], qL[5], qR[5], l1, l2, l3, l4;
+    valencia<T, MC>(e, m, gtu, n, pL, fL, qL, l1, l2);
+    valencia<T, MC>(e, m, gtu, n, pR, fR, qR, l3, l4);
+    T c = fmax(fmax(fabs(l1), fabs(l2)), fmax(fabs(l3), fabs(l4)));
+    for (int k = 0; k < 5; k++) out.f[k] = T(0.5) * (fL[k] + fR[k] - c * (qR[k] - qL[k]));
+    out.speed = c;
+    return;
+  }
+  const T W = m.W;
+  T El[3][3];  // contravariant legs (normal, t1, t2), x/y/z components
+  T sqgnn, vint;
+  if (MC == MC_GEN) {
+    const T *gt = m.gt;
+    if (dir == 0) {
+      T B = T(1) / tsqrt(gtu[0]);
+      T C = T(1) / tsqrt(gt[5]);
+      T Dh = B * C;
+      El[0][0] = W * B * gtu[0]; El[0][1] = W * B * gtu[1]; El[0][2] = W * B * gtu[2];
+      El[1][0] = T(0); El[1][1] = W * Dh * gt[5]; El[1][2] = -(W * Dh * gt[4]);
+      El[2][0] = T(0); El[2][1] = T(0); El[2][2] = W * C;
+    } else {
+      // z faces: cyclic relabelling (n, t1, t2) = (z, x, y)
+      T B = T(1) / tsqrt(gtu[5]);
+      T C = T(1) / tsqrt(gt[3]);
+      T Dh = B * C;
+      El[0][0] = W * B * gtu[2]; El[0][1] = W * B * gtu[4]; El[0][2] = W * B * gtu[5];
+      El[1][0] = W * Dh * gt[3]; El[1][1] = -(W * Dh * gt[1]); El[1][2] = T(0);
+      El[2][0] = T(0); El[2][1] = W * C; El[2][2] = T(0);
+    }
+    sqgnn = W * tsqrt(gtu[s3i(n, n)]);
+    vint = m.beta[n] / (m.alp * sqgnn);
+  } else {
+    sqgnn = W;
+    vint = T(0);
+  }
+  TState<T> L, R;
+  {
+    T ut[3];
+    if (MC == MC_GEN) {
+      for (int a = 0; a < 3; a++) ut[a] = El[a][0] * pL.u[0] + El[a][1] * pL.u[1] + El[a][2] * pL.u[2];
+    } else if (dir == 0) {
+      ut[0] = W * pL.u[0]; ut[1] = W * pL.u[1]; ut[2] = W * pL.u[2];
+    } else {
+      ut[0] = W * pL.u[2]; ut[1] = W * pL.u[0]; ut[2] = W * pL.u[1];
+    }
+    tetrad_state(e, pL, ut, L);
+    if (MC == MC_GEN) {
+      for (int a = 0; a < 3; a++) ut[a] = El[a][0] * pR.u[0] + El[a][1] * pR.u[1] + El[a][2] * pR.u[2];
+    } else if (dir == 0) {
+      ut[0] = W * pR.u[0]; ut[1] = W * pR.u[1]; ut[2] = W * pR.u[2];
+    } else {
+      ut[0] = W * pR.u[2]; ut[1] = W * pR.u[0]; ut[2] = W * pR.u[1];
+    }
+    tetrad_state(e, pR, ut, R);
+  }
+  T G[5], lamL, lamR;
+  hllc_tetrad(L, R, vint, G, lamL, lamR);
+  // back to the Eulerian frame, densitised by alpha W^-3
+  T pref = m.alp / (W * W * W) * sqgnn;
+  out.f[0] = pref * G[0];
+  out.f[4] = pref * G[4];
+  if (MC == MC_GEN) {
+    // covariant legs e_(a)_j = gamma_ji e_(a)^i, gamma_ij = W^-2 gt_ij
+    T iW2 = T(1) / (W * W);
+    for (int j = 0; j < 3; j++) {
+      T s = T(0);
+      for (int a = 0; a < 3; a++) {
+        T ec = T(0);
+        for (int i = 0; i < 3; i++) ec += m.gt[s3i(j, i)] * El[a][i];
+        s += ec * iW2 * G[1 + a];
+      }
+      out.f[1 + j] = pref * s;
+    }
+  } else {
+    T pw = pref / W;  // covariant legs W^-1 times unit vectors
+    if (dir == 0) {
+      out.f[1] = pw * G[1]; out.f[2] = pw * G[2]; out.f[3] = pw * G[3];
+    } else {
+      out.f[3] = pw * G[1]; out.f[1] = pw * G[2]; out.f[2] = pw * G[3];
+    }
+  }
+  out.speed = m.alp * sqgnn * fmax(fabs(lamL - vint), fabs(lamR - vint));
+}
+
+// ------------------------------------------------ sources (II.C.1)
+// s_Sj = P d_j(alpha W^-3) - W^-3 rho h w^2 [d_j alpha - v_i d_j beta^i
+//        + (W^2/2) alpha v_i v_k d_j gt^{ik} + (1/W) alpha v_i v^i d_j W]
+//        (+ W^-3 [S_y (alpha v^y - beta^y) + alpha P] / x for j = varpi)
+// s_E  = W^-3 [alpha K_ij S^ij - rho h w^2 v^i d_i alpha]
+// with Eulerian v_i = u_i / w; d gt^{ik} = -gt^{ia} gt^{kb} d gt_ab.
+// g: 17 metric values at the cell; dg: d/dx (dg[0..16]) and d/dz
+// (dg[17..33]).
+template <int MC>
+__device__ __forceinline__ void sources(const double *g, const double *dg, double x, int geom,
+                                        const double *p, double *s) {
+  double alp = g[GRHD_M_ALP], W = g[GRHD_M_W];
+  double rho = p[0], P = p[4], eps = p[5];
+  double u[3] = {p[1], p[2], p[3]};
+  double gtu[6];
+  double usq;
+  if (MC == MC_GEN) {
+    double gt[6] = {g[5], g[6], g[7], g[8], g[9], g[10]};
+    inv_sym3(gt, gtu);
+    usq = 0.0;
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) usq += gtu[s3i(i, j)] * u[i] * u[j];
+    usq *= W * W;
+  } else {
+    usq = W * W * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  }
+  double w = sqrt(1.0 + usq);
+  double iw = 1.0 / w;
+  double h = 1.0 + eps + P / rho;
+  double vl[3] = {u[0] * iw, u[1] * iw, u[2] * iw};
+  double vu[3], vt[3];
+  if (MC == MC_GEN) {
+    for (int i = 0; i < 3; i++) {
+      vt[i] = gtu[s3i(i, 0)] * vl[0] + gtu[s3i(i, 1)] * vl[1] + gtu[s3i(i, 2)] * vl[2];
+      vu[i] = W * W * vt[i];
+    }
+  } else {
+    for (int i = 0; i < 3; i++) {
+      vt[i] = vl[i];
+      vu[i] = W * W * vl[i];
+    }
+  }
+  double vsq = vl[0] * vu[0] + vl[1] * vu[1] + vl[2] * vu[2];
+  double sg = 1.0 / (W * W * W);
+  double rhw2 = rho * h * w * w;
+  double sm[2];
+  for (int d = 0; d < 2; d++) {
+    const double *dd = dg + d * GRHD_NMET;
+    double dalp = dd[GRHD_M_ALP], dW = dd[GRHD_M_W];
+    double dasg = dalp * sg + alp * (-3.0 * dW / (W * W * W * W));
+    double br = dalp + alp * vsq * dW / W;
+    if (MC == MC_GEN) {
+      double vdb = vl[0] * dd[GRHD_M_BX] + vl[1] * dd[GRHD_M_BY] + vl[2] * dd[GRHD_M_BZ];
+      double vvdg = 0.0;
+      for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) vvdg -= vt[a] * vt[b] * dd[GRHD_M_GXX + s3i(a, b)];
+      br += -vdb + 0.5 * W * W * alp * vvdg;
+    }
+    sm[d] = P * dasg - sg * rhw2 * br;
+  }
+  s[0] = 0.0;
+  s[1] = sm[0];
+  s[2] = 0.0;
+  s[3] = sm[1];
+  if (geom == GRHD_GEOM_CYLINDRICAL) {
+    double Sy = rho * h * w * u[1];
+    double by = (MC == MC_GEN) ? g[GRHD_M_BY] : 0.0;
+    s[1] += sg * (Sy * (alp * vu[1] - by) + alp * P) / x;
+  }
+  double vda = vu[0] * dg[GRHD_M_ALP] + vu[2] * dg[GRHD_NMET + GRHD_M_ALP];
+  double KS = 0.0;
+  if (MC == MC_GEN) {
+    double trK = 0.0;
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) {
+        double Kij = g[GRHD_M_KXX + s3i(i, j)];
+        KS += vu[i] * vu[j] * Kij;
+        trK += W * W * gtu[s3i(i, j)] * Kij;
+      }
+    KS = rhw2 * KS + P * trK;
+  }
+  s[4] = sg * (alp * KS - rhw2 * vda);
+}
+
+}  // namespace grhd

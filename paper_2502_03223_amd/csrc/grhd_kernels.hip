@@ -1,0 +1,485 @@
+// grhd_kernels.hip -- gfx950 kernels and the C ABI of the single-patch
+// calls: primitive recovery, prim->con, reconstruction, Riemann flux and
+// the fused Runge-Kutta stage.  Physics in grhd_dev.hpp, tile pipeline in
+// grhd_tile.hpp.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "grhd.h"
+#include "grhd_dev.hpp"
+#include "grhd_host.hpp"
+#include "grhd_tile.hpp"
+
+namespace grhd {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+}
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+// ------------------------------------------------------------ small kernels
+
+__global__ void k_zero_diag(grhd_diag *d) {
+  if (threadIdx.x == 0) {
+    d->max_courant = 0.0;
+    d->Mb = 0.0;
+    d->J = 0.0;
+    d->n_rescale = d->n_cold = d->n_atm = d->n_fail = 0ull;
+  }
+}
+
+__global__ void k_zero_double(double *d) {
+  if (threadIdx.x == 0) *d = 0.0;
+}
+
+// Recovery of one cell per thread over [jlo, jhi) x [klo, khi); cells
+// outside the interior are processed only on EXTERNAL sides (corners never).
+template <int MC>
+__global__ void __launch_bounds__(256)
+k_con2prim(GridK g, EosK e, C2PK cp, MetK m, Q5 q, P6 p, uint8_t *flags, grhd_diag *diag,
+           int jlo, int jhi, int klo) {
+  int j = jlo + blockIdx.x * blockDim.x + threadIdx.x;
+  int k = klo + blockIdx.y;
+  bool act = j < jhi;
+  bool jin = (j >= 0 && j < g.nx), kin = (k >= 0 && k < g.nz);
+  if (!jin || !kin) {
+    if (!jin && !kin) act = false;
+    else if (!jin) act = act && g.bc[j < 0 ? 0 : 1] == GRHD_BC_EXTERNAL;
+    else act = act && g.bc[k < 0 ? 2 : 3] == GRHD_BC_EXTERNAL;
+  }
+  unsigned fl = 0;
+  if (act) {
+    long long i = cell_index(g, j, k);
+    double W = mval(m, GRHD_M_W, i);
+    double gtu[6];
+    if (MC == MC_GEN) {
+      double gt[6];
+      for (int t = 0; t < 6; t++) gt[t] = mval(m, GRHD_M_GXX + t, i);
+      inv_sym3(gt, gtu);
+    }
+    double qq[5], pp[6];
+    for (int c = 0; c < 5; c++) qq[c] = q.q[c][i];
+    double x = g.x0 + (j + 0.5) * g.dx;
+    C2PResult r = con2prim_cell<MC>(e, cp, W, gtu, x, g.geom, qq, pp, -1.0);
+    fl = r.flags;
+    if (fl)
+      for (int c = 0; c < 5; c++) q.q[c][i] = qq[c];
+    for (int c = 0; c < 6; c++) p.p[c][i] = pp[c];
+    if (flags) flags[i] = (uint8_t)fl;
+  }
+  if (diag && jin && kin) {
+    unsigned long long b0 = __ballot(act && (fl & GRHD_FLAG_RESCALE));
+    unsigned long long b1 = __ballot(act && (fl & GRHD_FLAG_COLD));
+    unsigned long long b2 = __ballot(act && (fl & GRHD_FLAG_ATM));
+    unsigned long long b3 = __ballot(act && (fl & GRHD_FLAG_FAIL));
+    if ((threadIdx.x & 63) == __ffsll((long long)__ballot(1)) - 1) {
+      if (b0) atomicAdd(&diag->n_rescale, (unsigned long long)__popcll(b0));
+      if (b1) atomicAdd(&diag->n_cold, (unsigned long long)__popcll(b1));
+      if (b2) atomicAdd(&diag->n_atm, (unsigned long long)__popcll(b2));
+      if (b3) atomicAdd(&diag->n_fail, (unsigned long long)__popcll(b3));
+    }
+  }
+}
+
+template <int MC>
+__global__ void __launch_bounds__(256)
+k_prim2con(GridK g, MetK m, P6 p, Q5 q, int lo) {
+  int j = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  int k = lo + blockIdx.y;
+  if (j >= g.nx - lo) return;
+  long long i = cell_index(g, j, k);
+  double W = mval(m, GRHD_M_W, i);
+  double gtu[6];
+  if (MC == MC_GEN) {
+    double gt[6];
+    for (int t = 0; t < 6; t++) gt[t] = mval(m, GRHD_M_GXX + t, i);
+    inv_sym3(gt, gtu);
+  }
+  double pp[6], qq[5];
+  for (int c = 0; c < 6; c++) pp[c] = p.p[c][i];
+  prim2con_cell<MC>(W, gtu, g.x0 + (j + 0.5) * g.dx, g.geom, pp, qq);
+  for (int c = 0; c < 5; c++) q.q[c][i] = qq[c];
+}
+
+template <class T> struct Ptr6 { T *a[6]; };
+
+// Reconstruction at every face of one direction (one thread per face).
+template <class T>
+__global__ void __launch_bounds__(256)
+k_reconstruct(GridK g, int dir, int recon, P6 p, Ptr6<T> L, Ptr6<T> R) {
+  int nfx = (dir == 0) ? g.nx + 1 : g.nx;
+  int nfz = (dir == 0) ? g.nz : g.nz + 1;
+  long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= (long long)nfx * nfz) return;
+  int j = (int)(f % nfx), k = (int)(f / nfx);
+  T st[6][6];
+  for (int i = 0; i < 6; i++) {
+    int jj = (dir == 0) ? j - 3 + i : j;
+    int kk = (dir == 0) ? k : k - 3 + i;
+    int js, ks;
+    double sg[3];
+    ghost_map(g, jj, kk, js, ks, sg);
+    long long is = cell_index(g, js, ks);
+    st[0][i] = (T)p.p[0][is];
+    st[1][i] = (T)(sg[0] * p.p[1][is]);
+    st[2][i] = (T)(sg[1] * p.p[2][is]);
+    st[3][i] = (T)(sg[2] * p.p[3][is]);
+    st[4][i] = (T)p.p[4][is];
+    st[5][i] = (T)p.p[5][is];
+  }
+  for (int c = 0; c < 6; c++) {
+    T a, b;
+    recon_face(recon, st[c], a, b);
+    L.a[c][f] = a;
+    R.a[c][f] = b;
+  }
+}
+
+template <class T, int MC>
+__global__ void __launch_bounds__(256)
+k_flux(GridK g, EosK e, MetK m, int dir, int riemann, Ptr6<T> Lp, Ptr6<T> Rp, Q5 F,
+       double *max_speed) {
+  int nfx = (dir == 0) ? g.nx + 1 : g.nx;
+  int nfz = (dir == 0) ? g.nz : g.nz + 1;
+  long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double sp = 0.0;
+  if (f < (long long)nfx * nfz) {
+    int j = (int)(f % nfx), k = (int)(f / nfx);
+    PrimT<T> L, R;
+    L.rho = Lp.a[0][f]; L.u[0] = Lp.a[1][f]; L.u[1] = Lp.a[2][f]; L.u[2] = Lp.a[3][f];
+    L.P = Lp.a[4][f]; L.eps = Lp.a[5][f];
+    R.rho = Rp.a[0][f]; R.u[0] = Rp.a[1][f]; R.u[1] = Rp.a[2][f]; R.u[2] = Rp.a[3][f];
+    R.P = Rp.a[4][f]; R.eps = Rp.a[5][f];
+    FaceMet<T> fm;
+    T t6[6];
+    for (int fld = 0; fld < 11; fld++) {
+      const double *src = m.f[fld];
+      T v;
+      if (src) {
+        for (int i = 0; i < 6; i++) {
+          long long ii = (dir == 0) ? cell_index(g, j - 3 + i, k) : cell_index(g, j, k - 3 + i);
+          t6[i] = (T)src[ii];
+        }
+        v = lagrange6(t6);
+      } else {
+        v = (T)m.c[fld];
+      }
+      if (fld == 0) fm.alp = v;
+      else if (fld < 4) fm.beta[fld - 1] = v;
+      else if (fld == 4) fm.W = v;
+      else fm.gt[fld - 5] = v;
+    }
+    FluxT<T> out;
+    face_flux<T, MC>(e, fm, dir, riemann, L, R, out);
+    double fv[5] = {(double)out.f[0], (double)out.f[1], (double)out.f[2], (double)out.f[3],
+                    (double)out.f[0] + (double)out.f[4]};
+    if (g.geom == GRHD_GEOM_CYLINDRICAL)
+      fv[2] *= (dir == 0) ? g.x0 + j * g.dx : g.x0 + (j + 0.5) * g.dx;
+    for (int c = 0; c < 5; c++) F.q[c][f] = fv[c];
+    sp = (double)out.speed;
+  }
+  if (max_speed) {
+    sp = wave_max(sp);
+    if ((threadIdx.x & 63) == 0)
+      atomicMax((unsigned long long *)max_speed, (unsigned long long)__double_as_longlong(sp));
+  }
+}
+
+// Fused stage: one workgroup per tile; tile index remapped so that each of
+// the 8 XCDs works on a contiguous band of tiles (halo reuse in its L2).
+template <class T, int MC, int TX, int TZ>
+__global__ void __launch_bounds__(NT)
+k_substep(PatchK P, EosK e, grhd_diag *diag) {
+  __shared__ TileSmem<T, MC, TX, TZ> sm;
+  int ntiles = P.tiles_x * P.tiles_z;
+  int b = blockIdx.x;
+  int full = (ntiles / 8) * 8;
+  int t = b;
+  if (b < full) t = (b % 8) * (full / 8) + b / 8;
+  substep_tile<T, MC, TX, TZ>(P, e, t % P.tiles_x, t / P.tiles_x, sm, diag);
+}
+
+// ------------------------------------------------------------ dispatch
+
+using SubstepFn = void (*)(PatchK, EosK, grhd_diag *);
+
+struct TileShape { int tx, tz; };
+static const TileShape kShapes[] = {{32, 8}, {32, 16}, {64, 8}, {16, 16}};
+constexpr int kNumShapes = 4;
+
+template <class T, int MC>
+static SubstepFn pick_shape(int s) {
+  switch (s) {
+    case 0: return k_substep<T, MC, 32, 8>;
+    case 1: return k_substep<T, MC, 32, 16>;
+    case 2: return k_substep<T, MC, 64, 8>;
+    default: return k_substep<T, MC, 16, 16>;
+  }
+}
+
+static SubstepFn substep_kernel(int prec, int mc, int shape) {
+  if (prec == GRHD_PREC_MIXED)
+    return mc == MC_GEN ? pick_shape<float, MC_GEN>(shape) : pick_shape<float, MC_CF>(shape);
+  return mc == MC_GEN ? pick_shape<double, MC_GEN>(shape) : pick_shape<double, MC_CF>(shape);
+}
+
+int shape_index(int tx, int tz) {
+  for (int s = 0; s < kNumShapes; s++)
+    if (kShapes[s].tx == tx && kShapes[s].tz == tz) return s;
+  return -1;
+}
+
+int num_shapes() { return kNumShapes; }
+void shape_of(int s, int *tx, int *tz) { *tx = kShapes[s].tx; *tz = kShapes[s].tz; }
+
+int launch_con2prim(const GridK &g, const EosK &e, const C2PK &cp, const MetK &m, int mc,
+                    const Q5 &q, const P6 &p, uint8_t *flags, grhd_diag *diag, hipStream_t st) {
+  int jlo = (g.bc[0] == GRHD_BC_EXTERNAL) ? -g.ng : 0;
+  int jhi = (g.bc[1] == GRHD_BC_EXTERNAL) ? g.nx + g.ng : g.nx;
+  int klo = (g.bc[2] == GRHD_BC_EXTERNAL) ? -g.ng : 0;
+  int khi = (g.bc[3] == GRHD_BC_EXTERNAL) ? g.nz + g.ng : g.nz;
+  int bs = 256;
+  dim3 grid((jhi - jlo + bs - 1) / bs, khi - klo);
+  if (mc == MC_GEN)
+    hipLaunchKernelGGL(k_con2prim<MC_GEN>, grid, dim3(bs), 0, st, g, e, cp, m, q, p, flags, diag, jlo, jhi, klo);
+  else
+    hipLaunchKernelGGL(k_con2prim<MC_CF>, grid, dim3(bs), 0, st, g, e, cp, m, q, p, flags, diag, jlo, jhi, klo);
+  return launch_status("con2prim");
+}
+
+int launch_substep(const PatchK &pk, const EosK &e, int prec, int mc, int shape, grhd_diag *diag,
+                   hipStream_t st) {
+  SubstepFn fn = substep_kernel(prec, mc, shape);
+  int ntiles = pk.tiles_x * pk.tiles_z;
+  hipLaunchKernelGGL(fn, dim3(ntiles), dim3(NT), 0, st, pk, e, diag);
+  return launch_status("substep");
+}
+
+}  // namespace grhd
+
+using namespace grhd;
+
+// ------------------------------------------------------------ C ABI
+
+extern "C" const char *grhd_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char *grhd_version(void) { return "grhd-mi355x 0.1 (gfx950)"; }
+
+extern "C" int grhd_con2prim(const grhd_grid *grid, const grhd_eos *eos, const grhd_metric *metric,
+                             const grhd_c2p_params *c2p, const grhd_cons *q, const grhd_prim *p,
+                             uint8_t *flags, grhd_diag *diag, void *hip_stream) {
+  int rc;
+  if ((rc = check_grid(grid)) || (rc = check_eos(eos)) || (rc = check_metric(metric)) ||
+      (rc = check_c2p(c2p)) || (rc = check_cons(q, "q")) || (rc = check_prim(p, "p")))
+    return rc;
+  if (c2p->guess == GRHD_GUESS_MLP)
+    return fail(GRHD_ERR_UNSUPPORTED, "use grhd_con2prim_mlp for the learned guess");
+  hipStream_t st = (hipStream_t)hip_stream;
+  Q5 qq;
+  P6 pp;
+  for (int c = 0; c < 5; c++) qq.q[c] = q->q[c];
+  for (int c = 0; c < 6; c++) pp.p[c] = p->p[c];
+  if (diag) {
+    hipLaunchKernelGGL(k_zero_diag, dim3(1), dim3(64), 0, st, diag);
+    if ((rc = launch_status("diag reset"))) return rc;
+  }
+  return launch_con2prim(to_gridk(grid), to_eosk(eos, c2p->rho_atm), to_c2pk(c2p), to_metk(metric),
+                         metric_class(metric), qq, pp, flags, diag, st);
+}
+
+extern "C" int grhd_prim2con(const grhd_grid *grid, const grhd_eos *eos, const grhd_metric *metric,
+                             const grhd_prim *p, const grhd_cons *q, int with_ghosts,
+                             void *hip_stream) {
+  int rc;
+  if ((rc = check_grid(grid)) || (rc = check_eos(eos)) || (rc = check_metric(metric)) ||
+      (rc = check_prim(p, "p")) || (rc = check_cons(q, "q")))
+    return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  GridK g = to_gridk(grid);
+  MetK m = to_metk(metric);
+  Q5 qq;
+  P6 pp;
+  for (int c = 0; c < 5; c++) qq.q[c] = q->q[c];
+  for (int c = 0; c < 6; c++) pp.p[c] = p->p[c];
+  int lo = with_ghosts ? -g.ng : 0;
+  int n = g.nx - 2 * lo;
+  dim3 gd((n + 255) / 256, g.nz - 2 * lo);
+  if (metric_class(metric) == MC_GEN)
+    hipLaunchKernelGGL(k_prim2con<MC_GEN>, gd, dim3(256), 0, st, g, m, pp, qq, lo);
+  else
+    hipLaunchKernelGGL(k_prim2con<MC_CF>, gd, dim3(256), 0, st, g, m, pp, qq, lo);
+  return launch_status("prim2con");
+}
+
+extern "C" int grhd_reconstruct(const grhd_grid *grid, int dir, int recon, int prec,
+                                const grhd_prim *p, const grhd_prim *pL, const grhd_prim *pR,
+                                void *hip_stream) {
+  int rc;
+  if ((rc = check_grid(grid)) || (rc = check_prim(p, "p")) || (rc = check_prim(pL, "pL")) ||
+      (rc = check_prim(pR, "pR")))
+    return rc;
+  if (dir != 0 && dir != 1) return fail(GRHD_ERR_INVALID, "dir must be 0 or 1");
+  if (recon != GRHD_RECON_PPM && recon != GRHD_RECON_MINMOD) return fail(GRHD_ERR_INVALID, "bad recon");
+  if (prec != GRHD_PREC_FP64 && prec != GRHD_PREC_MIXED) return fail(GRHD_ERR_INVALID, "bad prec");
+  hipStream_t st = (hipStream_t)hip_stream;
+  GridK g = to_gridk(grid);
+  P6 pp;
+  for (int c = 0; c < 6; c++) pp.p[c] = p->p[c];
+  long long nf = (dir == 0) ? (long long)(g.nx + 1) * g.nz : (long long)g.nx * (g.nz + 1);
+  int blocks = (int)((nf + 255) / 256);
+  if (prec == GRHD_PREC_FP64) {
+    Ptr6<double> L, R;
+    for (int c = 0; c < 6; c++) { L.a[c] = pL->p[c]; R.a[c] = pR->p[c]; }
+    hipLaunchKernelGGL(k_reconstruct<double>, dim3(blocks), dim3(256), 0, st, g, dir, recon, pp, L, R);
+  } else {
+    Ptr6<float> L, R;
+    for (int c = 0; c < 6; c++) { L.a[c] = (float *)pL->p[c]; R.a[c] = (float *)pR->p[c]; }
+    hipLaunchKernelGGL(k_reconstruct<float>, dim3(blocks), dim3(256), 0, st, g, dir, recon, pp, L, R);
+  }
+  return launch_status("reconstruct");
+}
+
+extern "C" int grhd_hllc_flux(const grhd_grid *grid, int dir, int riemann, int prec,
+                              const grhd_eos *eos, const grhd_metric *metric, const grhd_prim *pL,
+                              const grhd_prim *pR, const grhd_cons *F, double *max_speed,
+                              void *hip_stream) {
+  int rc;
+  if ((rc = check_grid(grid)) || (rc = check_eos(eos)) || (rc = check_metric(metric)) ||
+      (rc = check_prim(pL, "pL")) || (rc = check_prim(pR, "pR")) || (rc = check_cons(F, "F")))
+    return rc;
+  if (dir != 0 && dir != 1) return fail(GRHD_ERR_INVALID, "dir must be 0 or 1");
+  if (riemann != GRHD_RIEMANN_HLLC && riemann != GRHD_RIEMANN_TVDLF) return fail(GRHD_ERR_INVALID, "bad riemann");
+  if (prec != GRHD_PREC_FP64 && prec != GRHD_PREC_MIXED) return fail(GRHD_ERR_INVALID, "bad prec");
+  hipStream_t st = (hipStream_t)hip_stream;
+  GridK g = to_gridk(grid);
+  EosK e = to_eosk(eos, 1.0);
+  MetK m = to_metk(metric);
+  int mc = metric_class(metric);
+  Q5 FF;
+  for (int c = 0; c < 5; c++) FF.q[c] = F->q[c];
+  long long nf = (dir == 0) ? (long long)(g.nx + 1) * g.nz : (long long)g.nx * (g.nz + 1);
+  int blocks = (int)((nf + 255) / 256);
+  if (max_speed) {
+    hipLaunchKernelGGL(k_zero_double, dim3(1), dim3(64), 0, st, max_speed);
+    if ((rc = launch_status("max_speed reset"))) return rc;
+  }
+  if (prec == GRHD_PREC_FP64) {
+    Ptr6<double> L, R;
+    for (int c = 0; c < 6; c++) { L.a[c] = pL->p[c]; R.a[c] = pR->p[c]; }
+    if (mc == MC_GEN)
+      hipLaunchKernelGGL((k_flux<double, MC_GEN>), dim3(blocks), dim3(256), 0, st, g, e, m, dir, riemann, L, R, FF, max_speed);
+    else
+      hipLaunchKernelGGL((k_flux<double, MC_CF>), dim3(blocks), dim3(256), 0, st, g, e, m, dir, riemann, L, R, FF, max_speed);
+  } else {
+    Ptr6<float> L, R;
+    for (int c = 0; c < 6; c++) { L.a[c] = (float *)pL->p[c]; R.a[c] = (float *)pR->p[c]; }
+    if (mc == MC_GEN)
+      hipLaunchKernelGGL((k_flux<float, MC_GEN>), dim3(blocks), dim3(256), 0, st, g, e, m, dir, riemann, L, R, FF, max_speed);
+    else
+      hipLaunchKernelGGL((k_flux<float, MC_CF>), dim3(blocks), dim3(256), 0, st, g, e, m, dir, riemann, L, R, FF, max_speed);
+  }
+  return launch_status("hllc_flux");
+}
+
+namespace grhd {
+int fill_patch(const grhd_grid *grid, const grhd_metric *metric, const grhd_rk_stage *stage,
+               const grhd_cons *qn, const grhd_cons *qs, const grhd_cons *qout, const grhd_prim *p,
+               const grhd_cons *acc_in, const grhd_cons *acc_out, double *flux_reg, int recon,
+               int riemann, PatchK &pk) {
+  int rc;
+  if ((rc = check_grid(grid)) || (rc = check_metric(metric)) || (rc = check_cons(qs, "qs")) ||
+      (rc = check_cons(qout, "qout")) || (rc = check_prim(p, "p")))
+    return rc;
+  if (!stage) return fail(GRHD_ERR_INVALID, "stage is NULL");
+  if (!std::isfinite(stage->dt) || !std::isfinite(stage->a) || !std::isfinite(stage->b) ||
+      !std::isfinite(stage->c))
+    return fail(GRHD_ERR_INVALID, "stage coefficients must be finite");
+  if (stage->a != 0.0 && (rc = check_cons(qn, "qn"))) return rc;
+  if (acc_in && (rc = check_cons(acc_in, "acc_in"))) return rc;
+  if (acc_out && (rc = check_cons(acc_out, "acc_out"))) return rc;
+  if (recon != GRHD_RECON_PPM && recon != GRHD_RECON_MINMOD) return fail(GRHD_ERR_INVALID, "bad recon");
+  if (riemann != GRHD_RIEMANN_HLLC && riemann != GRHD_RIEMANN_TVDLF) return fail(GRHD_ERR_INVALID, "bad riemann");
+  for (int c = 0; c < 5; c++)
+    if (qout->q[c] == qs->q[c] || (stage->a != 0.0 && qout->q[c] == qn->q[c]))
+      return fail(GRHD_ERR_INVALID, "qout must not alias qs or qn");
+  pk.g = to_gridk(grid);
+  pk.m = to_metk(metric);
+  for (int c = 0; c < 5; c++) {
+    pk.qn[c] = (stage->a != 0.0) ? qn->q[c] : nullptr;
+    pk.qs[c] = qs->q[c];
+    pk.qo[c] = qout->q[c];
+    pk.acc_in[c] = acc_in ? acc_in->q[c] : nullptr;
+    pk.acc_out[c] = acc_out ? acc_out->q[c] : nullptr;
+  }
+  for (int c = 0; c < 6; c++) pk.p[c] = p->p[c];
+  pk.flux_reg = flux_reg;
+  pk.a = stage->a; pk.b = stage->b; pk.cdt = stage->c * stage->dt;
+  pk.gdt = stage->g * stage->dt; pk.d = stage->d; pk.e = stage->e; pk.dt = stage->dt;
+  pk.use_qn = stage->a != 0.0;
+  pk.use_acc_in = acc_in != nullptr && (stage->g != 0.0 || stage->d != 0.0);
+  pk.use_acc_out = acc_out != nullptr;
+  pk.recon = recon;
+  pk.riemann = riemann;
+  pk.eos_id = 0;
+  pk.tile_base = 0;
+  return GRHD_OK;
+}
+}  // namespace grhd
+
+extern "C" int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos, const grhd_metric *metric,
+                               const grhd_options *opts, const grhd_rk_stage *stage,
+                               const grhd_cons *qn, const grhd_cons *qs, const grhd_cons *qout,
+                               const grhd_prim *p, const grhd_cons *acc_in, const grhd_cons *acc_out,
+                               double *flux_reg, uint8_t *flags, grhd_diag *diag, void *hip_stream) {
+  int rc;
+  if (!opts) return fail(GRHD_ERR_INVALID, "opts is NULL");
+  if ((rc = check_eos(eos)) || (rc = check_c2p(&opts->c2p))) return rc;
+  if (opts->c2p.guess == GRHD_GUESS_MLP)
+    return fail(GRHD_ERR_UNSUPPORTED, "learned guess is not wired into the substep");
+  if (opts->prec != GRHD_PREC_FP64 && opts->prec != GRHD_PREC_MIXED) return fail(GRHD_ERR_INVALID, "bad prec");
+  PatchK pk;
+  if ((rc = fill_patch(grid, metric, stage, qn, qs, qout, p, acc_in, acc_out, flux_reg, opts->recon,
+                       opts->riemann, pk)))
+    return rc;
+  int shape = 0;
+  if (opts->tile_x || opts->tile_z) {
+    shape = shape_index(opts->tile_x, opts->tile_z);
+    if (shape < 0) return fail(GRHD_ERR_UNSUPPORTED, "tile %dx%d not built", opts->tile_x, opts->tile_z);
+  }
+  int tx, tz;
+  shape_of(shape, &tx, &tz);
+  pk.tiles_x = (grid->nx + tx - 1) / tx;
+  pk.tiles_z = (grid->nz + tz - 1) / tz;
+  hipStream_t st = (hipStream_t)hip_stream;
+  EosK e = to_eosk(eos, opts->c2p.rho_atm);
+  int mc = metric_class(metric);
+  Q5 q;
+  P6 pp;
+  for (int c = 0; c < 5; c++) q.q[c] = qs->q[c];
+  for (int c = 0; c < 6; c++) pp.p[c] = p->p[c];
+  if (diag) {
+    hipLaunchKernelGGL(k_zero_diag, dim3(1), dim3(64), 0, st, diag);
+    if ((rc = launch_status("diag reset"))) return rc;
+  }
+  if ((rc = launch_con2prim(pk.g, e, to_c2pk(&opts->c2p), pk.m, mc, q, pp, flags, diag, st))) return rc;
+  return launch_substep(pk, e, opts->prec, mc, shape, diag, st);
+}

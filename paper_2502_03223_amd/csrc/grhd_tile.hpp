@@ -1,0 +1,374 @@
+// grhd_tile.hpp -- the fused per-tile work of one Runge-Kutta stage:
+// LDS-staged primitives with a 3-cell halo (boundary conditions applied as
+// an index map while loading), reconstruction + Riemann flux on every face
+// of the tile in x then z (fluxes staged in LDS, one buffer reused for both
+// directions), area-weighted divergence, cylindrical and metric sources,
+// and the stage combination, all for one TX x TZ tile of one patch.
+// Used by the single-patch kernel and by the persistent batched kernel.
+#pragma once
+
+#include "grhd_dev.hpp"
+
+namespace grhd {
+
+constexpr int NT = 256;  // threads per workgroup (4 wave64)
+
+struct PatchK {
+  GridK g;
+  MetK m;
+  double *qn[5], *qs[5], *qo[5], *p[6];
+  double *acc_in[5], *acc_out[5];
+  double *flux_reg;
+  double a, b, cdt, gdt, d, e, dt;
+  int use_qn, use_acc_in, use_acc_out;
+  int recon, riemann, eos_id;
+  int tiles_x, tiles_z;
+  long long tile_base;
+};
+
+template <class T, int MC, int TX, int TZ>
+struct TileSmem {
+  static constexpr int HX = TX + 6, HZ = TZ + 6, NC = HX * HZ;
+  static constexpr int NFX = (TX + 1) * TZ, NFZ = TX * (TZ + 1);
+  static constexpr int NF = NFX > NFZ ? NFX : NFZ;
+  static constexpr int NM = (MC == MC_CF) ? NC : 1;
+  T p[6][NC];
+  double ma[NM], mw[NM];
+  T f[5][NF];
+  double red[3][NT / 64];
+};
+
+// Source cell of ghost cell (j, k) under the boundary conditions, with the
+// velocity parities; false for cells no stencil of the tile reads.
+__device__ __forceinline__ bool ghost_map(const GridK &g, int j, int k, int &js, int &ks,
+                                          double sg[3]) {
+  sg[0] = sg[1] = sg[2] = 1.0;
+  js = j;
+  ks = k;
+  bool jin = (j >= 0 && j < g.nx), kin = (k >= 0 && k < g.nz);
+  if (jin && kin) return true;
+  if (!jin && !kin) return false;
+  if (!jin) {
+    int side = (j < 0) ? 0 : 1;
+    int bc = g.bc[side];
+    if (bc == GRHD_BC_PERIODIC) js = ((j % g.nx) + g.nx) % g.nx;
+    else if (bc == GRHD_BC_OUTFLOW) js = side ? g.nx - 1 : 0;
+    else if (bc == GRHD_BC_AXIS || bc == GRHD_BC_REFLECT) {
+      js = side ? 2 * g.nx - 1 - j : -1 - j;
+      sg[0] = -1.0;
+      if (bc == GRHD_BC_AXIS) sg[1] = -1.0;
+    }
+  } else {
+    int side = (k < 0) ? 0 : 1;
+    int bc = g.bc[2 + side];
+    if (bc == GRHD_BC_PERIODIC) ks = ((k % g.nz) + g.nz) % g.nz;
+    else if (bc == GRHD_BC_OUTFLOW) ks = side ? g.nz - 1 : 0;
+    else if (bc == GRHD_BC_AXIS || bc == GRHD_BC_REFLECT) {
+      ks = side ? 2 * g.nz - 1 - k : -1 - k;
+      sg[2] = -1.0;
+    }
+  }
+  return true;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <class T, int MC, int TX, int TZ>
+__device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int tx, int tz,
+                                             TileSmem<T, MC, TX, TZ> &sm, grhd_diag *diag) {
+  using S = TileSmem<T, MC, TX, TZ>;
+  constexpr int HX = S::HX, HZ = S::HZ;
+  constexpr int CPT = (TX * TZ + NT - 1) / NT;
+  const GridK &g = P.g;
+  const int tid = threadIdx.x;
+  const int nx = g.nx, nz = g.nz;
+  const int j0 = tx * TX, k0 = tz * TZ;
+  const bool cyl = (g.geom == GRHD_GEOM_CYLINDRICAL);
+  __syncthreads();  // LDS of a previous tile (persistent loop) is free
+
+  // ---- 1. stage primitives and (conformally flat class) lapse, W in LDS
+  for (int c = tid; c < S::NC; c += NT) {
+    int jj = c % HX, kk = c / HX;
+    int j = j0 - 3 + jj, k = k0 - 3 + kk;
+    bool inx = (jj >= 3 && jj < 3 + TX), inz = (kk >= 3 && kk < 3 + TZ);
+    bool need = (inx && j < nx && k >= -3 && k < nz + 3) || (inz && k < nz && j >= -3 && j < nx + 3);
+    if (!need) continue;
+    int js, ks;
+    double sg[3];
+    if (!ghost_map(g, j, k, js, ks, sg)) continue;
+    long long is = cell_index(g, js, ks);
+    sm.p[0][c] = (T)P.p[0][is];
+    sm.p[1][c] = (T)(sg[0] * P.p[1][is]);
+    sm.p[2][c] = (T)(sg[1] * P.p[2][is]);
+    sm.p[3][c] = (T)(sg[2] * P.p[3][is]);
+    sm.p[4][c] = (T)P.p[4][is];
+    sm.p[5][c] = (T)P.p[5][is];
+    if (MC == MC_CF) {
+      long long im = cell_index(g, j, k);
+      sm.ma[c] = P.m.f[GRHD_M_ALP] ? P.m.f[GRHD_M_ALP][im] : P.m.c[GRHD_M_ALP];
+      sm.mw[c] = P.m.f[GRHD_M_W] ? P.m.f[GRHD_M_W][im] : P.m.c[GRHD_M_W];
+    }
+  }
+  __syncthreads();
+
+  const int nb = 2 * nz + 2 * nx;  // flux-register stride
+  double cmax = 0.0;
+  double divx[CPT][5];
+
+  // ---- 2. x faces: face x_{j-1/2}, j = j0 .. j0+TX
+  for (int f = tid; f < S::NFX; f += NT) {
+    int jj = f % (TX + 1), kk = f / (TX + 1);
+    int j = j0 + jj, k = k0 + kk;
+    FluxT<T> out;
+    for (int m = 0; m < 5; m++) out.f[m] = T(0);
+    if (k < nz && j <= nx) {
+      int base = (kk + 3) * HX + jj;
+      PrimT<T> L, R;
+      T s[6], a, b;
+      for (int fld = 0; fld < 6; fld++) {
+        for (int i = 0; i < 6; i++) s[i] = sm.p[fld][base + i];
+        recon_face(P.recon, s, a, b);
+        if (fld == 0) { L.rho = a; R.rho = b; }
+        else if (fld < 4) { L.u[fld - 1] = a; R.u[fld - 1] = b; }
+        else if (fld == 4) { L.P = a; R.P = b; }
+        else { L.eps = a; R.eps = b; }
+      }
+      FaceMet<T> fm;
+      if (MC == MC_CF) {
+        T t6[6];
+        for (int i = 0; i < 6; i++) t6[i] = (T)sm.ma[base + i];
+        fm.alp = lagrange6(t6);
+        for (int i = 0; i < 6; i++) t6[i] = (T)sm.mw[base + i];
+        fm.W = lagrange6(t6);
+      } else {
+        T t6[6];
+        for (int fld = 0; fld < 11; fld++) {
+          const double *src = P.m.f[fld];
+          T v;
+          if (src) {
+            for (int i = 0; i < 6; i++) t6[i] = (T)src[cell_index(g, j - 3 + i, k)];
+            v = lagrange6(t6);
+          } else {
+            v = (T)P.m.c[fld];
+          }
+          if (fld == 0) fm.alp = v;
+          else if (fld < 4) fm.beta[fld - 1] = v;
+          else if (fld == 4) fm.W = v;
+          else fm.gt[fld - 5] = v;
+        }
+      }
+      face_flux<T, MC>(e, fm, 0, P.riemann, L, R, out);
+      cmax = fmax(cmax, (double)out.speed * (P.dt / g.dx));
+      if (P.flux_reg && (j == 0 || j == nx)) {
+        int o = (j == 0) ? k : nz + k;
+        double xf = g.x0 + j * g.dx;
+        double fv[5] = {(double)out.f[0], (double)out.f[1], (double)out.f[2], (double)out.f[3],
+                        (double)out.f[0] + (double)out.f[4]};
+        if (cyl) fv[2] *= xf;
+        for (int m = 0; m < 5; m++) P.flux_reg[m * nb + o] = fv[m];
+      }
+    }
+    for (int m = 0; m < 5; m++) sm.f[m][f] = out.f[m];
+  }
+  __syncthreads();
+
+  // ---- 3. x divergence per owned cell (area weighted in cylindrical)
+#pragma unroll
+  for (int ci = 0; ci < CPT; ci++) {
+    int c = tid + ci * NT;
+    int jj = c % TX, kk = c / TX;
+    int j = j0 + jj;
+    for (int m = 0; m < 5; m++) divx[ci][m] = 0.0;
+    if (c < TX * TZ && j < nx && k0 + kk < nz) {
+      int fl = kk * (TX + 1) + jj, fr = fl + 1;
+      double xl = g.x0 + j * g.dx, xr = g.x0 + (j + 1) * g.dx, xc = g.x0 + (j + 0.5) * g.dx;
+      for (int m = 0; m < 5; m++) {
+        double Fl, Fr;
+        if (m == 4) {
+          Fl = (double)sm.f[0][fl] + (double)sm.f[4][fl];
+          Fr = (double)sm.f[0][fr] + (double)sm.f[4][fr];
+        } else {
+          Fl = (double)sm.f[m][fl];
+          Fr = (double)sm.f[m][fr];
+        }
+        if (cyl) {
+          if (m == 2) { Fl *= xl; Fr *= xr; }
+          divx[ci][m] = (xr * Fr - xl * Fl) / (xc * g.dx);
+        } else {
+          divx[ci][m] = (Fr - Fl) / g.dx;
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- 4. z faces: face z_{k-1/2}, k = k0 .. k0+TZ
+  for (int f = tid; f < S::NFZ; f += NT) {
+    int jj = f % TX, kk = f / TX;
+    int j = j0 + jj, k = k0 + kk;
+    FluxT<T> out;
+    for (int m = 0; m < 5; m++) out.f[m] = T(0);
+    if (j < nx && k <= nz) {
+      int col = jj + 3;
+      PrimT<T> L, R;
+      T s[6], a, b;
+      for (int fld = 0; fld < 6; fld++) {
+        for (int i = 0; i < 6; i++) s[i] = sm.p[fld][(kk + i) * HX + col];
+        recon_face(P.recon, s, a, b);
+        if (fld == 0) { L.rho = a; R.rho = b; }
+        else if (fld < 4) { L.u[fld - 1] = a; R.u[fld - 1] = b; }
+        else if (fld == 4) { L.P = a; R.P = b; }
+        else { L.eps = a; R.eps = b; }
+      }
+      FaceMet<T> fm;
+      if (MC == MC_CF) {
+        T t6[6];
+        for (int i = 0; i < 6; i++) t6[i] = (T)sm.ma[(kk + i) * HX + col];
+        fm.alp = lagrange6(t6);
+        for (int i = 0; i < 6; i++) t6[i] = (T)sm.mw[(kk + i) * HX + col];
+        fm.W = lagrange6(t6);
+      } else {
+        T t6[6];
+        for (int fld = 0; fld < 11; fld++) {
+          const double *src = P.m.f[fld];
+          T v;
+          if (src) {
+            for (int i = 0; i < 6; i++) t6[i] = (T)src[cell_index(g, j, k - 3 + i)];
+            v = lagrange6(t6);
+          } else {
+            v = (T)P.m.c[fld];
+          }
+          if (fld == 0) fm.alp = v;
+          else if (fld < 4) fm.beta[fld - 1] = v;
+          else if (fld == 4) fm.W = v;
+          else fm.gt[fld - 5] = v;
+        }
+      }
+      face_flux<T, MC>(e, fm, 1, P.riemann, L, R, out);
+      cmax = fmax(cmax, (double)out.speed * (P.dt / g.dz));
+      if (P.flux_reg && (k == 0 || k == nz)) {
+        int o = 2 * nz + ((k == 0) ? j : nx + j);
+        double xc = g.x0 + (j + 0.5) * g.dx;
+        double fv[5] = {(double)out.f[0], (double)out.f[1], (double)out.f[2], (double)out.f[3],
+                        (double)out.f[0] + (double)out.f[4]};
+        if (cyl) fv[2] *= xc;
+        for (int m = 0; m < 5; m++) P.flux_reg[m * nb + o] = fv[m];
+      }
+    }
+    for (int m = 0; m < 5; m++) sm.f[m][f] = out.f[m];
+  }
+  __syncthreads();
+
+  // ---- 5. z divergence, sources, stage combination, diagnostics
+  double mb = 0.0, jm = 0.0;
+  const double i60dx = 1.0 / (60.0 * g.dx), i60dz = 1.0 / (60.0 * g.dz);
+#pragma unroll
+  for (int ci = 0; ci < CPT; ci++) {
+    int c = tid + ci * NT;
+    int jj = c % TX, kk = c / TX;
+    int j = j0 + jj, k = k0 + kk;
+    if (!(c < TX * TZ && j < nx && k < nz)) continue;
+    double xc = g.x0 + (j + 0.5) * g.dx;
+    int fb = kk * TX + jj, ft = fb + TX;
+    double divz[5];
+    for (int m = 0; m < 5; m++) {
+      double Fb, Ft;
+      if (m == 4) {
+        Fb = (double)sm.f[0][fb] + (double)sm.f[4][fb];
+        Ft = (double)sm.f[0][ft] + (double)sm.f[4][ft];
+      } else {
+        Fb = (double)sm.f[m][fb];
+        Ft = (double)sm.f[m][ft];
+      }
+      if (cyl && m == 2) { Fb *= xc; Ft *= xc; }
+      divz[m] = (Ft - Fb) / g.dz;
+    }
+    // metric at the cell and its x, z derivatives
+    long long ic = cell_index(g, j, k);
+    double gm[GRHD_NMET], dg[2 * GRHD_NMET];
+    if (MC == MC_CF) {
+      int lc = (kk + 3) * HX + (jj + 3);
+      for (int i = 0; i < GRHD_NMET; i++) { gm[i] = P.m.c[i]; dg[i] = 0.0; dg[GRHD_NMET + i] = 0.0; }
+      gm[GRHD_M_ALP] = sm.ma[lc];
+      gm[GRHD_M_W] = sm.mw[lc];
+      double a7[7];
+      if (P.m.f[GRHD_M_ALP]) {
+        for (int i = 0; i < 7; i++) a7[i] = sm.ma[lc - 3 + i];
+        dg[GRHD_M_ALP] = deriv6(a7, i60dx);
+        for (int i = 0; i < 7; i++) a7[i] = sm.ma[lc + (i - 3) * HX];
+        dg[GRHD_NMET + GRHD_M_ALP] = deriv6(a7, i60dz);
+      }
+      if (P.m.f[GRHD_M_W]) {
+        for (int i = 0; i < 7; i++) a7[i] = sm.mw[lc - 3 + i];
+        dg[GRHD_M_W] = deriv6(a7, i60dx);
+        for (int i = 0; i < 7; i++) a7[i] = sm.mw[lc + (i - 3) * HX];
+        dg[GRHD_NMET + GRHD_M_W] = deriv6(a7, i60dz);
+      }
+    } else {
+      for (int i = 0; i < GRHD_NMET; i++) {
+        const double *src = P.m.f[i];
+        if (!src) { gm[i] = P.m.c[i]; dg[i] = 0.0; dg[GRHD_NMET + i] = 0.0; continue; }
+        gm[i] = src[ic];
+        double a7[7];
+        for (int t = 0; t < 7; t++) a7[t] = src[ic - 3 + t];
+        dg[i] = deriv6(a7, i60dx);
+        for (int t = 0; t < 7; t++) a7[t] = src[ic + (t - 3) * g.pitch];
+        dg[GRHD_NMET + i] = deriv6(a7, i60dz);
+      }
+    }
+    double pc[6];
+    for (int i = 0; i < 6; i++) pc[i] = P.p[i][ic];
+    double s[5];
+    sources<MC>(gm, dg, xc, g.geom, pc, s);
+    double dV = cyl ? 2.0 * M_PI * xc * g.dx * g.dz : g.dx * g.dz;
+    for (int m = 0; m < 5; m++) {
+      double L = s[m] - divx[ci][m] - divz[m];
+      double v = P.b * P.qs[m][ic] + P.cdt * L;
+      if (P.use_qn) v += P.a * P.qn[m][ic];
+      if (P.use_acc_in) v += P.gdt * P.acc_in[m][ic];
+      P.qo[m][ic] = v;
+      if (P.use_acc_out) {
+        double av = P.e * L;
+        if (P.use_acc_in) av += P.d * P.acc_in[m][ic];
+        P.acc_out[m][ic] = av;
+      }
+      if (m == 0) mb += v * dV;
+      if (m == 2) jm += v * dV;
+    }
+  }
+
+  // ---- 6. workgroup reductions of the diagnostics
+  if (diag) {
+    cmax = wave_max(cmax);
+    mb = wave_sum(mb);
+    jm = wave_sum(jm);
+    int wv = tid >> 6;
+    if ((tid & 63) == 0) {
+      sm.red[0][wv] = cmax;
+      sm.red[1][wv] = mb;
+      sm.red[2][wv] = jm;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double c = sm.red[0][0], s1 = sm.red[1][0], s2 = sm.red[2][0];
+      for (int w = 1; w < NT / 64; w++) {
+        c = fmax(c, sm.red[0][w]);
+        s1 += sm.red[1][w];
+        s2 += sm.red[2][w];
+      }
+      atomicMax((unsigned long long *)&diag->max_courant, (unsigned long long)__double_as_longlong(c));
+      unsafeAtomicAdd(&diag->Mb, s1);
+      unsafeAtomicAdd(&diag->J, s2);
+    }
+  }
+}
+
+}  // namespace grhd

@@ -1,0 +1,323 @@
+"""Thin ctypes binding of libgrhd.so (argument marshalling only).
+
+Every step of the hot path runs in the library's HIP kernels; this module
+only converts plain Python descriptions and torch device tensors into the C
+structs of include/grhd.h, calls the library on the current HIP stream and
+raises on any non-zero status.  There is no CPU fallback: when the library
+is missing, importing the product path raises.
+
+Plain-data conventions (shared with the tests):
+  grid   dict(nx, nz, ng, pitch, x0, z0, dx, dz, geom='cyl'|'cart',
+              bc=(xlo, xhi, zlo, zhi))
+  eos    dict(kind='ideal'|'hybrid', K=[..], G=[..], rho_b=[..], Gth=..)
+  metric dict name -> device tensor (rows, pitch) float64, or float
+  c2p    dict(w_max, rho_atm[, tol, max_iter])
+Cell fields are float64 device tensors of shape (nfield, rows, pitch),
+rows = nz + 2 ng.
+"""
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgrhd.so")
+
+METRIC_NAMES = ["alp", "bx", "by", "bz", "W", "gxx", "gxy", "gxz", "gyy",
+                "gyz", "gzz", "kxx", "kxy", "kxz", "kyy", "kyz", "kzz"]
+FLAT = {"alp": 1.0, "W": 1.0, "gxx": 1.0, "gyy": 1.0, "gzz": 1.0}
+BC = {"outflow": 0, "periodic": 1, "axis": 2, "reflect": 3, "external": 4}
+GEOM = {"cyl": 0, "cart": 1}
+RECON = {"ppm": 0, "minmod": 1}
+RIEMANN = {"hllc": 0, "tvdlf": 1}
+PREC = {"fp64": 0, "mixed": 1}
+EOS_KIND = {"ideal": 0, "hybrid": 1}
+
+
+class GrhdError(RuntimeError):
+    pass
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int), ("nz", C.c_int), ("ng", C.c_int),
+                ("pitch", C.c_int64), ("x0", C.c_double), ("z0", C.c_double),
+                ("dx", C.c_double), ("dz", C.c_double), ("geom", C.c_int),
+                ("bc", C.c_int * 4)]
+
+
+class Eos(C.Structure):
+    _fields_ = [("kind", C.c_int), ("npieces", C.c_int), ("K", C.c_double * 8),
+                ("Gamma", C.c_double * 8), ("rho_b", C.c_double * 8),
+                ("Gamma_th", C.c_double)]
+
+
+class Metric(C.Structure):
+    _fields_ = [("f", C.c_void_p * 17), ("cval", C.c_double * 17)]
+
+
+class Cons(C.Structure):
+    _fields_ = [("q", C.c_void_p * 5)]
+
+
+class Prim(C.Structure):
+    _fields_ = [("p", C.c_void_p * 6)]
+
+
+class C2PParams(C.Structure):
+    _fields_ = [("w_max", C.c_double), ("rho_atm", C.c_double), ("tol", C.c_double),
+                ("max_iter", C.c_int), ("guess", C.c_int), ("mlp", C.c_void_p)]
+
+
+class Options(C.Structure):
+    _fields_ = [("recon", C.c_int), ("riemann", C.c_int), ("prec", C.c_int),
+                ("c2p", C2PParams), ("tile_x", C.c_int), ("tile_z", C.c_int)]
+
+
+class Stage(C.Structure):
+    _fields_ = [("a", C.c_double), ("b", C.c_double), ("c", C.c_double),
+                ("dt", C.c_double), ("g", C.c_double), ("d", C.c_double),
+                ("e", C.c_double)]
+
+
+class Diag(C.Structure):
+    _fields_ = [("max_courant", C.c_double), ("Mb", C.c_double), ("J", C.c_double),
+                ("n_rescale", C.c_ulonglong), ("n_cold", C.c_ulonglong),
+                ("n_atm", C.c_ulonglong), ("n_fail", C.c_ulonglong)]
+
+
+class Patch(C.Structure):
+    _fields_ = [("grid", Grid), ("metric", Metric), ("qn", Cons), ("qs", Cons),
+                ("qout", Cons), ("p", Prim), ("stage", Stage), ("eos_id", C.c_int),
+                ("flux_reg", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise GrhdError("libgrhd.so is not built (run __graft_entry__.build())")
+        _lib = C.CDLL(LIB_PATH)
+        p, i = C.c_void_p, C.c_int
+        sig = {
+            "grhd_con2prim": [p, p, p, p, p, p, p, p, p],
+            "grhd_prim2con": [p, p, p, p, p, i, p],
+            "grhd_reconstruct": [p, i, i, i, p, p, p, p],
+            "grhd_hllc_flux": [p, i, i, i, p, p, p, p, p, p, p],
+            "grhd_rk_substep": [p, p, p, p, p, p, p, p, p, p, p, p, p, p, p],
+            "grhd_plan_create": [p, i, p, i, p, C.c_char_p, p],
+            "grhd_batch_levels": [p, p, i, p, p],
+            "grhd_plan_destroy": [p],
+            "grhd_plan_tile": [p, p, p],
+        }
+        for name, args in sig.items():
+            fn = getattr(_lib, name, None)
+            if fn is None:
+                continue
+            fn.restype = C.c_int
+            fn.argtypes = args
+        _lib.grhd_last_error.restype = C.c_char_p
+        _lib.grhd_version.restype = C.c_char_p
+    return _lib
+
+
+def exported_symbols():
+    return [n for n in dir(lib()) if n.startswith("grhd_")]
+
+
+def _check(rc, what):
+    if rc != 0:
+        msg = lib().grhd_last_error().decode()
+        raise GrhdError("%s failed (%d): %s" % (what, rc, msg))
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ------------------------------------------------------------ marshalling
+
+def make_grid(g):
+    s = Grid()
+    s.nx, s.nz, s.ng, s.pitch = g["nx"], g["nz"], g["ng"], g["pitch"]
+    s.x0, s.z0, s.dx, s.dz = g["x0"], g["z0"], g["dx"], g["dz"]
+    s.geom = GEOM[g["geom"]]
+    for k in range(4):
+        s.bc[k] = BC[g["bc"][k]]
+    return s
+
+
+def make_eos(e):
+    s = Eos()
+    s.kind = EOS_KIND[e["kind"]]
+    s.npieces = len(e["K"])
+    for k, (K, G) in enumerate(zip(e["K"], e["G"])):
+        s.K[k], s.Gamma[k] = K, G
+    for k, r in enumerate(e.get("rho_b", [])):
+        s.rho_b[k] = r
+    s.Gamma_th = e["Gth"]
+    return s
+
+
+def _dptr(t):
+    assert t.is_cuda and t.dtype == torch.float64, "metric fields must be float64 device tensors"
+    assert t.is_contiguous()
+    return t.data_ptr()
+
+
+def make_metric(m):
+    s = Metric()
+    for k, name in enumerate(METRIC_NAMES):
+        v = m.get(name, FLAT.get(name, 0.0))
+        if isinstance(v, torch.Tensor):
+            s.f[k] = _dptr(v)
+            s.cval[k] = 0.0
+        else:
+            s.f[k] = None
+            s.cval[k] = float(v)
+    return s
+
+
+def _fields(t, nf, dtype=torch.float64):
+    assert t is not None and t.is_cuda and t.dtype == dtype and t.is_contiguous()
+    assert t.shape[0] == nf
+    stride = t.stride(0) * t.element_size()
+    return [t.data_ptr() + c * stride for c in range(nf)]
+
+
+def make_cons(t):
+    s = Cons()
+    for c, ptr in enumerate(_fields(t, 5)):
+        s.q[c] = ptr
+    return s
+
+
+def make_prim(t, dtype=torch.float64):
+    s = Prim()
+    for c, ptr in enumerate(_fields(t, 6, dtype)):
+        s.p[c] = ptr
+    return s
+
+
+def make_c2p(c):
+    s = C2PParams()
+    s.w_max, s.rho_atm = c["w_max"], c["rho_atm"]
+    s.tol = c.get("tol", 0.0)
+    s.max_iter = c.get("max_iter", 0)
+    s.guess = 1 if c.get("mlp") is not None else 0
+    s.mlp = c["mlp"].data_ptr() if c.get("mlp") is not None else None
+    return s
+
+
+def make_stage(st):
+    s = Stage()
+    s.a, s.b, s.c, s.dt = st["a"], st["b"], st["c"], st["dt"]
+    s.g, s.d, s.e = st.get("g", 0.0), st.get("d", 0.0), st.get("e", 0.0)
+    return s
+
+
+def make_options(o):
+    s = Options()
+    s.recon = RECON[o.get("recon", "ppm")]
+    s.riemann = RIEMANN[o.get("riemann", "hllc")]
+    s.prec = PREC[o.get("prec", "fp64")]
+    s.c2p = make_c2p(o["c2p"])
+    tile = o.get("tile", (0, 0))
+    s.tile_x, s.tile_z = tile
+    return s
+
+
+def new_diag(device="cuda"):
+    return torch.zeros(8, dtype=torch.float64, device=device)  # 64 bytes
+
+
+def read_diag(t):
+    raw = t.cpu().numpy().tobytes()
+    d = Diag.from_buffer_copy(raw[:C.sizeof(Diag)])
+    return {k: getattr(d, k) for k, _ in Diag._fields_}
+
+
+# ------------------------------------------------------------ calls
+
+def con2prim(grid, eos, metric, c2p, q, p, flags=None, diag=None):
+    """q (5,rows,pitch) in/out, p (6,rows,pitch) out."""
+    rc = lib().grhd_con2prim(
+        C.byref(make_grid(grid)), C.byref(make_eos(eos)), C.byref(make_metric(metric)),
+        C.byref(make_c2p(c2p)), C.byref(make_cons(q)), C.byref(make_prim(p)),
+        C.c_void_p(flags.data_ptr() if flags is not None else 0),
+        C.c_void_p(diag.data_ptr() if diag is not None else 0), _stream())
+    _check(rc, "grhd_con2prim")
+
+
+def prim2con(grid, eos, metric, p, q, with_ghosts=False):
+    rc = lib().grhd_prim2con(C.byref(make_grid(grid)), C.byref(make_eos(eos)),
+                             C.byref(make_metric(metric)), C.byref(make_prim(p)),
+                             C.byref(make_cons(q)), 1 if with_ghosts else 0, _stream())
+    _check(rc, "grhd_prim2con")
+
+
+def face_shape(grid, dirn):
+    nx, nz = grid["nx"], grid["nz"]
+    return (nz, nx + 1) if dirn == 0 else (nz + 1, nx)
+
+
+def reconstruct(grid, dirn, recon, p, prec="fp64"):
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    shp = face_shape(grid, dirn)
+    pL = torch.empty((6,) + shp, dtype=dt, device=p.device)
+    pR = torch.empty((6,) + shp, dtype=dt, device=p.device)
+    rc = lib().grhd_reconstruct(C.byref(make_grid(grid)), dirn, RECON[recon], PREC[prec],
+                                C.byref(make_prim(p)), C.byref(make_prim(pL, dt)),
+                                C.byref(make_prim(pR, dt)), _stream())
+    _check(rc, "grhd_reconstruct")
+    return pL, pR
+
+
+def hllc_flux(grid, dirn, riemann, eos, metric, pL, pR, prec="fp64"):
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    F = torch.empty((5,) + tuple(pL.shape[1:]), dtype=torch.float64, device=pL.device)
+    sp = torch.zeros(1, dtype=torch.float64, device=pL.device)
+    rc = lib().grhd_hllc_flux(C.byref(make_grid(grid)), dirn, RIEMANN[riemann], PREC[prec],
+                              C.byref(make_eos(eos)), C.byref(make_metric(metric)),
+                              C.byref(make_prim(pL, dt)), C.byref(make_prim(pR, dt)),
+                              C.byref(make_cons(F)), C.c_void_p(sp.data_ptr()), _stream())
+    _check(rc, "grhd_hllc_flux")
+    return F, sp
+
+
+class Substep:
+    """Pre-marshalled arguments of repeated grhd_rk_substep calls (the
+    structs are built once; only the stage and buffers change)."""
+
+    def __init__(self, grid, eos, metric, opts):
+        self.grid = make_grid(grid)
+        self.eos = make_eos(eos)
+        self.metric = make_metric(metric)
+        self.opts = make_options(opts)
+        self._keep = (grid, eos, metric, opts)
+
+    def __call__(self, stage, qn, qs, qout, p, acc_in=None, acc_out=None, flux_reg=None,
+                 flags=None, diag=None, stream=None):
+        st = make_stage(stage) if isinstance(stage, dict) else stage
+        rc = lib().grhd_rk_substep(
+            C.byref(self.grid), C.byref(self.eos), C.byref(self.metric), C.byref(self.opts),
+            C.byref(st), C.byref(make_cons(qn if qn is not None else qs)),
+            C.byref(make_cons(qs)), C.byref(make_cons(qout)), C.byref(make_prim(p)),
+            C.byref(make_cons(acc_in)) if acc_in is not None else None,
+            C.byref(make_cons(acc_out)) if acc_out is not None else None,
+            C.c_void_p(flux_reg.data_ptr() if flux_reg is not None else 0),
+            C.c_void_p(flags.data_ptr() if flags is not None else 0),
+            C.c_void_p(diag.data_ptr() if diag is not None else 0),
+            C.c_void_p(stream) if stream is not None else _stream())
+        _check(rc, "grhd_rk_substep")
+
+
+def rk_substep(grid, eos, metric, opts, stage, qn, qs, qout, p, **kw):
+    Substep(grid, eos, metric, opts)(stage, qn, qs, qout, p, **kw)
+
+
+SSPRK3 = [dict(a=0.0, b=1.0, c=1.0), dict(a=0.75, b=0.25, c=0.25),
+          dict(a=1.0 / 3.0, b=2.0 / 3.0, c=2.0 / 3.0)]

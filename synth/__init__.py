@@ -219,8 +219,10 @@ def star_grid(n, extent=20.0):
                      ("axis", "outflow", "reflect", "outflow"))
 
 
-def star_problem(grid, seed, tov=None, rho_atm=1e-10, pert=1e-4):
-    """(prims, metric dict, eos) for the perturbed TOV star on `grid`."""
+def star_problem(grid, seed, tov=None, rho_atm=1e-10, pert=1e-4, vel=0.0):
+    """(prims, metric dict, eos) for the perturbed TOV star on `grid`.
+    vel > 0 adds iid velocities u_i ~ vel U[-1, 1] inside the star (test
+    states with active limiters and non-trivial recovery)."""
     if tov is None:
         tov = tov_solve()
     K, G = tov["K"], tov["G"]
@@ -235,6 +237,10 @@ def star_problem(grid, seed, tov=None, rho_atm=1e-10, pert=1e-4):
     p[0] = rho
     p[4] = K * rho ** G
     p[5] = p[4] / ((G - 1.0) * rho)
+    if vel > 0.0:
+        inside = rho0 > 0.0
+        for c in (1, 2, 3):
+            p[c] = np.where(inside, vel * rng.uniform(-1.0, 1.0, size=rho0.shape), 0.0)
     metric = dict(alp=np.ascontiguousarray(alp), W=np.ascontiguousarray(W))
     eos = ideal_eos(G, K=K)
     return p, metric, eos
@@ -288,3 +294,55 @@ def recovery_samples(seed, n):
     out[:, 5] = eps
     out[:, 4] = rho * eps
     return out
+
+
+def general_metric(grid, seed, amp=0.1):
+    """Smooth random metric with every field active: lapse, shift, W,
+    conformal metric with det = 1 (M / det(M)^(1/3)), extrinsic curvature;
+    periodic in both directions of the grid (for Cartesian periodic tests)."""
+    rng = np.random.default_rng(seed)
+    X, Z = cell_coords(grid)
+    Lx = grid["nx"] * grid["dx"]
+    Lz = grid["nz"] * grid["dz"]
+
+    def smooth():
+        a, b, c, d = rng.uniform(0, 2 * math.pi, 4)
+        return (np.sin(2 * math.pi * X / Lx + a) * np.cos(2 * math.pi * Z / Lz + b)
+                + 0.5 * np.sin(2 * math.pi * (X / Lx + Z / Lz) + c) + 0.3 * np.cos(4 * math.pi * Z / Lz + d))
+    m = {}
+    m["alp"] = 0.8 + amp * smooth()
+    m["bx"], m["by"], m["bz"] = (amp * smooth() for _ in range(3))
+    m["W"] = 0.85 + amp * smooth()
+    M = np.zeros(X.shape + (3, 3))
+    for i in range(3):
+        for j in range(i, 3):
+            v = (1.0 if i == j else 0.0) + amp * smooth()
+            M[..., i, j] = v
+            M[..., j, i] = v
+    det = np.linalg.det(M)
+    M = M / np.cbrt(det)[..., None, None]
+    names = ["gxx", "gxy", "gxz", "gyy", "gyz", "gzz"]
+    for n, (i, j) in zip(names, [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]):
+        m[n] = np.ascontiguousarray(M[..., i, j])
+    for n in ["kxx", "kxy", "kxz", "kyy", "kyz", "kzz"]:
+        m[n] = 0.05 * smooth()
+    return {k: np.ascontiguousarray(v) for k, v in m.items()}
+
+
+def smooth_state(grid, seed, gamma=5.0 / 3.0, vamp=0.3):
+    """Smooth periodic primitive state (covariant u_i small enough for any
+    metric of general_metric)."""
+    rng = np.random.default_rng(seed)
+    X, Z = cell_coords(grid)
+    Lx = grid["nx"] * grid["dx"]
+    Lz = grid["nz"] * grid["dz"]
+    kx, kz = 2 * math.pi / Lx, 2 * math.pi / Lz
+    ph = rng.uniform(0, 2 * math.pi, 6)
+    p = empty_fields(grid, 6)
+    p[0] = 1.0 + 0.3 * np.sin(kx * X + ph[0]) * np.cos(kz * Z + ph[1])
+    p[1] = vamp * np.sin(kx * X + ph[2])
+    p[2] = 0.7 * vamp * np.cos(kz * Z + ph[3])
+    p[3] = vamp * np.sin(kx * X + kz * Z + ph[4])
+    p[4] = 0.5 + 0.2 * np.cos(kx * X - kz * Z + ph[5])
+    p[5] = p[4] / ((gamma - 1.0) * p[0])
+    return p

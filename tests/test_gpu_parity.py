@@ -1,0 +1,358 @@
+"""GPU parity: every C-ABI call of libgrhd.so against the FP64 oracle on the
+same seeded inputs (run on an MI355X).
+
+Bar (FP64 path): per field, max|gpu - oracle| <= 1e-12 max|oracle| (the
+normwise reading of "1e-12 relative"); reconstruction is bitwise (both sides
+evaluate the limiters without fused multiply-add on identical inputs);
+recovery flags are bit-exact.  Sizes span several tiles with ragged tails;
+full-size star grids (512^2, 1024^2) are compared on every cell.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2502_03223_amd import grhd  # noqa: E402
+
+DEV = torch.device("cuda:0")
+C2P_STAR = dict(w_max=100.0, rho_atm=1e-10)
+C2P_RIE = dict(w_max=100.0, rho_atm=1e-12)
+TOL = 1e-12
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def mdev(metric):
+    return {k: dev(v) if isinstance(v, np.ndarray) else v for k, v in metric.items()}
+
+
+def normwise(g, o, comps=None):
+    comps = range(g.shape[0]) if comps is None else comps
+    worst = 0.0
+    for c in comps:
+        scale = np.abs(o[c]).max()
+        if scale == 0.0:
+            err = np.abs(g[c]).max()
+        else:
+            err = np.abs(g[c] - o[c]).max() / scale
+        worst = max(worst, err)
+    return worst
+
+
+@pytest.fixture(scope="module")
+def tov():
+    return synth.tov_solve()
+
+
+def star_case(n, seed, tov, vel=0.02, extent=20.0):
+    grid = synth.star_grid(n, extent=extent)
+    p, metric, eos = synth.star_problem(grid, seed=seed, tov=tov, vel=vel)
+    return grid, p, metric, eos
+
+
+# ------------------------------------------------------------ pointwise calls
+
+@pytest.mark.parametrize("case", ["star", "general"])
+def test_prim2con(orc, tov, case):
+    if case == "star":
+        grid, p, metric, eos = star_case(70, 3, tov)
+    else:
+        grid = synth.make_grid(45, 38, 0.0, 0.0, 0.02, 0.025, "cart", ("periodic",) * 4)
+        metric = synth.general_metric(grid, 1)
+        p = synth.smooth_state(grid, 2)
+        eos = synth.ideal_eos(5.0 / 3.0)
+    q_o = orc.prim2con(grid, eos, metric, p, with_ghosts=True)
+    q_g = torch.zeros((5,) + p.shape[1:], dtype=torch.float64, device=DEV)
+    grhd.prim2con(grid, eos, mdev(metric), dev(p), q_g, with_ghosts=True)
+    assert normwise(q_g.cpu().numpy(), q_o) <= 1e-14
+
+
+@pytest.mark.parametrize("case", ["star", "general", "hybrid"])
+def test_con2prim(orc, tov, case):
+    if case == "star":
+        grid, p, metric, eos = star_case(70, 4, tov, vel=0.1)
+        c2p = C2P_STAR
+    else:
+        grid = synth.make_grid(45, 38, 0.0, 0.0, 0.02, 0.025, "cart", ("periodic",) * 4)
+        metric = synth.general_metric(grid, 3)
+        p = synth.smooth_state(grid, 4, vamp=0.8)
+        eos = synth.ideal_eos(5.0 / 3.0)
+        c2p = C2P_RIE
+        if case == "hybrid":
+            eos = dict(kind="hybrid", K=[0.3, 0.3 * 0.9 ** (1.4 - 2.2)], G=[1.4, 2.2],
+                       rho_b=[0.9], Gth=5.0 / 3.0)
+            rho = p[0]
+            ecold = np.where(rho < 0.9, 0.3 / 0.4 * rho ** 0.4,
+                             eos["K"][1] / 1.2 * rho ** 1.2 + (0.3 / 0.4 * 0.9 ** 0.4 - eos["K"][1] / 1.2 * 0.9 ** 1.2))
+            p[5] = ecold + 0.2
+            p[4] = np.array([orc.eos_press(eos, r, e) for r, e in zip(rho.ravel(), p[5].ravel())]).reshape(rho.shape)
+    q = orc.prim2con(grid, eos, metric, p, with_ghosts=True)
+    # a few pathological cells: invalid input, super-luminal momentum, cold
+    qi = synth.interior(grid, q)
+    qi[0, 1, 1] = -1.0
+    qi[4, 2, 2] = np.nan
+    qi[1, 3, 3] = 5.0 * qi[4, 3, 3]
+    qi[4, 4, 4] = qi[0, 4, 4] * 0.5
+    p_o, q_o, fl_o, d_o = orc.con2prim(grid, eos, metric, c2p, q)
+    qg = dev(q)
+    pg = torch.zeros((6,) + q.shape[1:], dtype=torch.float64, device=DEV)
+    fl = torch.zeros(q.shape[1:], dtype=torch.uint8, device=DEV)
+    dg = grhd.new_diag()
+    grhd.con2prim(grid, eos, mdev(metric), c2p, qg, pg, flags=fl, diag=dg)
+    torch.cuda.synchronize()
+    assert np.array_equal(synth.interior(grid, fl.cpu().numpy()), synth.interior(grid, fl_o))
+    pgi = synth.interior(grid, pg.cpu().numpy())
+    assert np.all(np.isfinite(pgi))
+    assert normwise(pgi, synth.interior(grid, p_o)) <= TOL
+    assert normwise(synth.interior(grid, qg.cpu().numpy()), synth.interior(grid, q_o)) <= TOL
+    d = grhd.read_diag(dg)
+    for k in ("n_rescale", "n_cold", "n_atm", "n_fail"):
+        assert d[k] == d_o[k], k
+
+
+@pytest.mark.parametrize("recon", ["ppm", "minmod"])
+@pytest.mark.parametrize("dirn", [0, 1])
+def test_reconstruct_bitwise(orc, tov, recon, dirn):
+    grid, p, metric, eos = star_case(70, 5, tov, vel=0.1)
+    pf = orc.fill_ghosts(grid, p)
+    L_o, R_o = orc.reconstruct(grid, dirn, recon, pf)
+    pi = np.zeros_like(p)
+    synth.interior(grid, pi)[...] = synth.interior(grid, p)
+    L_g, R_g = grhd.reconstruct(grid, dirn, recon, dev(pi))
+    assert np.array_equal(L_g.cpu().numpy(), L_o) and np.array_equal(R_g.cpu().numpy(), R_o)
+    # FP32 path: same limiter algebra in single precision; a limiter branch
+    # may flip on FP32 rounding, so require agreement on almost every face and
+    # boundedness everywhere
+    L_f, R_f = grhd.reconstruct(grid, dirn, recon, dev(pi), prec="mixed")
+    for a, b in ((L_f.cpu().numpy(), L_o), (R_f.cpu().numpy(), R_o)):
+        assert np.all(np.isfinite(a))
+        close = np.abs(a - b) <= 2e-6 * np.abs(b) + 1e-30
+        assert close.mean() >= 0.995
+
+
+@pytest.mark.parametrize("riemann", ["hllc", "tvdlf"])
+@pytest.mark.parametrize("dirn", [0, 1])
+@pytest.mark.parametrize("case", ["star", "general"])
+def test_flux(orc, tov, riemann, dirn, case):
+    if case == "star":
+        grid, p, metric, eos = star_case(70, 6, tov, vel=0.1)
+    else:
+        grid = synth.make_grid(45, 38, 0.0, 0.0, 0.02, 0.025, "cart", ("periodic",) * 4)
+        metric = synth.general_metric(grid, 5)
+        p = synth.smooth_state(grid, 6, vamp=0.5)
+        eos = synth.ideal_eos(5.0 / 3.0)
+    pf = orc.fill_ghosts(grid, p)
+    L, R = orc.reconstruct(grid, dirn, "ppm", pf)
+    F_o, s_o = orc.face_flux(grid, dirn, riemann, eos, metric, L, R)
+    F_g, s_g = grhd.hllc_flux(grid, dirn, riemann, eos, mdev(metric), dev(L), dev(R))
+    assert normwise(F_g.cpu().numpy(), F_o) <= 1e-13
+    assert float(s_g.cpu()[0]) == pytest.approx(s_o, rel=1e-13)
+
+
+# ------------------------------------------------------------ fused substep
+
+def run_pair(orc, grid, eos, metric, opts, stage, qn, qs, acc_in=None, want_acc=False, tile=None):
+    ref = orc.rk_substep(grid, eos, metric, opts, stage, qn, qs, acc_in=acc_in, want_acc=want_acc)
+    o = dict(opts)
+    if tile:
+        o["tile"] = tile
+    sub = grhd.Substep(grid, eos, mdev(metric), o)
+    qs_g = dev(qs)
+    qn_g = dev(qn) if qn is not None else qs_g
+    qo = torch.zeros_like(qs_g)
+    pg = torch.zeros((6,) + qs.shape[1:], dtype=torch.float64, device=DEV)
+    nb = 2 * grid["nz"] + 2 * grid["nx"]
+    freg = torch.zeros(5 * nb, dtype=torch.float64, device=DEV)
+    fl = torch.zeros(qs.shape[1:], dtype=torch.uint8, device=DEV)
+    dg = grhd.new_diag()
+    ai = dev(acc_in) if acc_in is not None else None
+    ao = torch.zeros_like(qs_g) if want_acc else None
+    sub(stage, qn_g, qs_g, qo, pg, acc_in=ai, acc_out=ao, flux_reg=freg, flags=fl, diag=dg)
+    torch.cuda.synchronize()
+    out = dict(qout=qo.cpu().numpy(), qs=qs_g.cpu().numpy(), p=pg.cpu().numpy(),
+               flux_reg=freg.cpu().numpy().reshape(5, nb), flags=fl.cpu().numpy(),
+               diag=grhd.read_diag(dg), acc=ao.cpu().numpy() if want_acc else None)
+    return ref, out
+
+
+def check_pair(grid, ref, out, tol=TOL):
+    I = lambda a: synth.interior(grid, a)  # noqa: E731
+    assert normwise(I(out["qout"]), I(ref["qout"])) <= tol
+    assert normwise(I(out["qs"]), I(ref["qs"])) <= tol
+    assert normwise(I(out["p"]), I(ref["p"])) <= tol
+    assert np.array_equal(I(out["flags"]), I(ref["flags"]))
+    # boundary fluxes: one scale for all components (the mass flux through
+    # the axis and through a static atmosphere is rounding noise)
+    fr, fo = out["flux_reg"], ref["flux_reg"]
+    assert np.abs(fr - fo).max() <= tol * np.abs(fo).max()
+    d, r = out["diag"], ref["diag"]
+    assert d["max_courant"] == pytest.approx(r["max_courant"], rel=1e-12)
+    assert d["Mb"] == pytest.approx(r["Mb"], rel=1e-12)
+    assert d["J"] == pytest.approx(r["J"], rel=1e-12, abs=1e-12 * abs(r["Mb"]))
+    for k in ("n_rescale", "n_cold", "n_atm", "n_fail"):
+        assert d[k] == r[k], k
+    if ref["acc"] is not None:
+        assert normwise(I(out["acc"]), I(ref["acc"])) <= tol
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("riemann,recon", [("hllc", "ppm"), ("tvdlf", "ppm"), ("hllc", "minmod")])
+def test_substep_riemann(orc, seed, riemann, recon):
+    """Riemann problems on 400 x 8 (Cartesian, flat, periodic z), all three
+    SSP-RK3 stages from oracle-evolved states."""
+    gam = 5.0 / 3.0
+    (L, R), = synth.riemann_states(seed, 1, gam)
+    grid = synth.riemann_grid(400, nz=8)
+    eos = synth.ideal_eos(gam)
+    p = synth.riemann_prims(grid, L, R)
+    q0 = orc.prim2con(grid, eos, {}, p, with_ghosts=True)
+    opts = dict(recon=recon, riemann=riemann, prec="fp64", c2p=C2P_RIE)
+    dt = 0.4 * grid["dx"]
+    # evolve a few steps with the oracle so every stage starts from a
+    # developed solution
+    q = q0
+    for _ in range(10):
+        qn = q
+        for st in grhd.SSPRK3:
+            r = orc.rk_substep(grid, eos, {}, opts, dict(st, dt=dt), qn, q)
+            qn = r["qs"] if st["a"] == 0.0 else qn
+            q = r["qout"]
+    qn = q
+    for st in grhd.SSPRK3:
+        ref, out = run_pair(orc, grid, eos, {}, opts, dict(st, dt=dt), qn, q)
+        check_pair(grid, ref, out)
+        q = ref["qout"]
+
+
+def test_paper_shock_tube_substeps(orc):
+    """The paper's problem (P_R = 0, cold fallback cells) at N = 800."""
+    gam = 5.0 / 3.0
+    L, R = synth.PAPER_SHOCK_TUBE
+    grid = synth.riemann_grid(800, nz=1)
+    eos = synth.ideal_eos(gam)
+    q = orc.prim2con(grid, eos, {}, synth.riemann_prims(grid, L, R), with_ghosts=True)
+    opts = dict(recon="ppm", riemann="hllc", prec="fp64", c2p=C2P_RIE)
+    dt = 0.4 * grid["dx"]
+    for i in range(6):
+        st = grhd.SSPRK3[i % 3]
+        ref, out = run_pair(orc, grid, eos, {}, opts, dict(st, dt=dt), q, q)
+        check_pair(grid, ref, out)
+        q = ref["qout"]
+
+
+@pytest.mark.parametrize("n", [64, 93])
+@pytest.mark.parametrize("stage", [0, 1, 2])
+def test_substep_star(orc, tov, n, stage):
+    grid, p, metric, eos = star_case(n, 10 + n + stage, tov, vel=0.05)
+    q = orc.prim2con(grid, eos, metric, p, with_ghosts=True)
+    qn = orc.prim2con(grid, eos, metric, star_case(n, 99, tov, vel=0.05)[1], with_ghosts=True)
+    opts = dict(recon="ppm", riemann="hllc", prec="fp64", c2p=C2P_STAR)
+    st = dict(grhd.SSPRK3[stage], dt=0.4 * grid["dx"])
+    ref, out = run_pair(orc, grid, eos, metric, opts, st, qn, q)
+    check_pair(grid, ref, out)
+
+
+@pytest.mark.parametrize("riemann", ["hllc", "tvdlf"])
+def test_substep_general_metric(orc, riemann):
+    grid = synth.make_grid(45, 38, 0.0, 0.0, 0.02, 0.025, "cart", ("periodic",) * 4)
+    metric = synth.general_metric(grid, 7)
+    p = synth.smooth_state(grid, 8, vamp=0.5)
+    eos = synth.ideal_eos(5.0 / 3.0)
+    q = orc.prim2con(grid, eos, metric, p, with_ghosts=True)
+    opts = dict(recon="ppm", riemann=riemann, prec="fp64", c2p=C2P_RIE)
+    ref, out = run_pair(orc, grid, eos, metric, opts, dict(grhd.SSPRK3[1], dt=0.005), q, q)
+    check_pair(grid, ref, out)
+
+
+def test_substep_general_metric_cylindrical(orc, tov):
+    """Cylindrical grid with every metric field active (shift, conformal
+    metric, curvature) on top of the star: exercises the tetrad legs, the
+    moving face and the full source terms with the hoop-stress term."""
+    grid, p, metric, eos = star_case(48, 21, tov, vel=0.05)
+    gm = synth.general_metric(grid, 22, amp=0.02)
+    gm["alp"] = metric["alp"] * (1.0 + 0.0 * gm["alp"])
+    gm["W"] = metric["W"]
+    q = orc.prim2con(grid, eos, gm, p, with_ghosts=True)
+    opts = dict(recon="ppm", riemann="hllc", prec="fp64", c2p=C2P_STAR)
+    ref, out = run_pair(orc, grid, eos, gm, opts, dict(grhd.SSPRK3[0], dt=0.4 * grid["dx"]), q, q)
+    check_pair(grid, ref, out)
+
+
+def test_substep_rk4_accumulator(orc, tov):
+    grid, p, metric, eos = star_case(40, 31, tov, vel=0.05)
+    q = orc.prim2con(grid, eos, metric, p, with_ghosts=True)
+    acc = orc.prim2con(grid, eos, metric, star_case(40, 32, tov, vel=0.05)[1], with_ghosts=True) * 1e-3
+    opts = dict(recon="ppm", riemann="hllc", prec="fp64", c2p=C2P_STAR)
+    st = dict(a=1.0, b=0.0, c=0.5, dt=0.4 * grid["dx"], g=0.0, d=1.0, e=1.0 / 3.0)
+    ref, out = run_pair(orc, grid, eos, metric, opts, st, q, q, acc_in=acc, want_acc=True)
+    check_pair(grid, ref, out)
+    st = dict(a=1.0, b=0.0, c=1.0 / 6.0, dt=0.4 * grid["dx"], g=1.0, d=0.0, e=0.0)
+    ref, out = run_pair(orc, grid, eos, metric, opts, st, q, q, acc_in=acc, want_acc=True)
+    check_pair(grid, ref, out)
+
+
+def test_tile_shapes_bitwise(orc, tov):
+    """The per-cell arithmetic does not depend on the tiling: every built
+    tile shape gives identical bits, including ragged tails."""
+    grid, p, metric, eos = star_case(77, 41, tov, vel=0.05)
+    q = orc.prim2con(grid, eos, metric, p, with_ghosts=True)
+    opts = dict(recon="ppm", riemann="hllc", prec="fp64", c2p=C2P_STAR)
+    st = dict(grhd.SSPRK3[1], dt=0.4 * grid["dx"])
+    outs = []
+    for tile in [(32, 8), (32, 16), (64, 8), (16, 16)]:
+        ref, out = run_pair(orc, grid, eos, metric, opts, st, q, q, tile=tile)
+        outs.append(out)
+    check_pair(grid, ref, outs[0])
+    for o in outs[1:]:
+        assert np.array_equal(synth.interior(grid, o["qout"]), synth.interior(grid, outs[0]["qout"]))
+
+
+@pytest.mark.parametrize("n", [512, 1024])
+def test_substep_full_size_star(orc, tov, n):
+    """Full star sizes in the benchmark's launch configuration, all cells."""
+    grid, p, metric, eos = star_case(n, 50, tov, vel=0.02)
+    q = orc.prim2con(grid, eos, metric, p, with_ghosts=True)
+    opts = dict(recon="ppm", riemann="hllc", prec="fp64", c2p=C2P_STAR)
+    ref, out = run_pair(orc, grid, eos, metric, opts, dict(grhd.SSPRK3[2], dt=0.4 * grid["dx"]), q, q)
+    check_pair(grid, ref, out)
+
+
+def test_invalid_cells_never_nan(orc):
+    grid = synth.riemann_grid(64, nz=4)
+    eos = synth.ideal_eos(5.0 / 3.0)
+    (L, R), = synth.riemann_states(3, 1)
+    q = orc.prim2con(grid, eos, {}, synth.riemann_prims(grid, L, R), with_ghosts=True)
+    qi = synth.interior(grid, q)
+    qi[0, 0, 5] = -1.0
+    qi[4, 1, 9] = np.nan
+    qi[2, 2, 11] = np.inf
+    opts = dict(recon="ppm", riemann="hllc", prec="fp64", c2p=C2P_RIE)
+    ref, out = run_pair(orc, grid, eos, {}, opts, dict(grhd.SSPRK3[0], dt=0.001), q, q)
+    assert np.all(np.isfinite(synth.interior(grid, out["qout"])))
+    check_pair(grid, ref, out)
+
+
+def test_mixed_single_substep_close(orc, tov):
+    """Mixed precision (FP32 reconstruction and flux) after one substep:
+    within FP32 rounding of the flux term of the oracle."""
+    grid, p, metric, eos = star_case(64, 61, tov, vel=0.02)
+    q = orc.prim2con(grid, eos, metric, p, with_ghosts=True)
+    opts = dict(recon="ppm", riemann="hllc", prec="fp64", c2p=C2P_STAR)
+    st = dict(grhd.SSPRK3[0], dt=0.4 * grid["dx"])
+    ref, _ = run_pair(orc, grid, eos, metric, opts, st, q, q)
+    _, out = run_pair(orc, grid, eos, metric, dict(opts, prec="mixed"), st, q, q)
+    I = lambda a: synth.interior(grid, a)  # noqa: E731
+    dq_o = I(ref["qout"]) - I(q)
+    dq_g = I(out["qout"]) - I(q)
+    for c in (0, 1, 3, 4):
+        assert np.abs(dq_g[c] - dq_o[c]).max() <= 1e-5 * np.abs(dq_o[c]).max() + 1e-16 * np.abs(I(q)[c]).max()
