@@ -271,10 +271,11 @@ unsigned or_con2prim_point(const or_eos *e, const double *g, double x, int geom,
         !isfinite(p[2]) || !isfinite(p[3]))
       ok = 0;
   }
-  if (!ok) flags |= OR_F_FAIL | OR_F_ATM;
+  /* a cell that ends as the atmosphere carries only the atmosphere flag
+   * (plus the failure flag for invalid input) */
   if (!ok || p[0] < cp->rho_atm) {
     atmosphere_prim(e, cp, p);
-    flags |= OR_F_ATM;
+    flags = ok ? OR_F_ATM : (OR_F_ATM | OR_F_FAIL);
     z = 0.0;
   }
   if (flags) or_prim2con_point(e, g, x, geom, p, q);
@@ -337,7 +338,7 @@ void or_recon_line(int recon, int n, const double *a, double *aL, double *aR) {
   for (int i = 1; i < n - 1; i++) dm[i] = mono_slope(a[i - 1], a[i], a[i + 1]);
   /* ai[i] = interface value a_{i+1/2} */
   for (int i = 1; i < n - 2; i++)
-    ai[i] = a[i] + 0.5 * (a[i + 1] - a[i]) - (dm[i + 1] - dm[i]) / 6.0;
+    ai[i] = a[i] + 0.5 * (a[i + 1] - a[i]) - (1.0 / 6.0) * (dm[i + 1] - dm[i]);
   for (int i = 2; i <= n - 4; i++) {
     double l0, r0, l1, r1;
     ppm_cell(a[i], ai[i - 1], ai[i], &l0, &r0);

@@ -1,6 +1,6 @@
 /*
  * or_mlp.c -- FP64 forward pass and back-propagation of the small MLP that
- * supplies the con2prim pressure guess: 3 -> 64 (tanh) -> 64 (tanh) -> 1.
+ * supplies the con2prim pressure guess: 3 -> 64 (ReLU) -> 64 (ReLU) -> 1.
  *
  * TEST INFRASTRUCTURE ONLY (part of the oracle; see oracle.h).
  *
@@ -11,7 +11,7 @@
  *
  * Parameter vector (4481 doubles): W1[64][3], b1[64], W2[64][64] (row =
  * output unit), b2[64], w3[64], b3.
- *   h1 = tanh(W1 x + b1), h2 = tanh(W2 h1 + b2), y = w3 . h2 + b3
+ *   h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), y = w3 . h2 + b3
  *   loss = (1/n) sum (y - t)^2
  */
 #include <math.h>
@@ -32,12 +32,12 @@ static double fwd_one(const double *P, const double *x, double *h1, double *h2) 
   for (int o = 0; o < H; o++) {
     double s = P[OFF_B1 + o];
     for (int i = 0; i < 3; i++) s += P[OFF_W1 + o * 3 + i] * x[i];
-    h1[o] = tanh(s);
+    h1[o] = s > 0.0 ? s : 0.0;
   }
   for (int o = 0; o < H; o++) {
     double s = P[OFF_B2 + o];
     for (int i = 0; i < H; i++) s += P[OFF_W2 + o * H + i] * h1[i];
-    h2[o] = tanh(s);
+    h2[o] = s > 0.0 ? s : 0.0;
   }
   double y = P[OFF_B3];
   for (int i = 0; i < H; i++) y += P[OFF_W3 + i] * h2[i];
@@ -63,7 +63,7 @@ double or_mlp_loss_grad(const double *params, int n, const double *X,
     grad[OFF_B3] += dy;
     for (int i = 0; i < H; i++) {
       grad[OFF_W3 + i] += dy * h2[i];
-      d2[i] = dy * params[OFF_W3 + i] * (1.0 - h2[i] * h2[i]);
+      d2[i] = (h2[i] > 0.0) ? dy * params[OFF_W3 + i] : 0.0;
     }
     for (int o = 0; o < H; o++) {
       grad[OFF_B2 + o] += d2[o];
@@ -72,7 +72,7 @@ double or_mlp_loss_grad(const double *params, int n, const double *X,
     for (int i = 0; i < H; i++) {
       double a = 0.0;
       for (int o = 0; o < H; o++) a += params[OFF_W2 + o * H + i] * d2[o];
-      d1[i] = a * (1.0 - h1[i] * h1[i]);
+      d1[i] = (h1[i] > 0.0) ? a : 0.0;
     }
     for (int o = 0; o < H; o++) {
       grad[OFF_B1 + o] += d1[o];

@@ -148,7 +148,7 @@ int or_riemann_cellavg(double gam, double rhoL, double pL, double vL,
                        int n, const double *xface, int nsub,
                        double *rho, double *p, double *v);
 
-/* MLP 3-64-64-1 with tanh hidden units, FP64 forward/backward */
+/* MLP 3-64-64-1 with ReLU hidden units, FP64 forward/backward */
 void or_mlp_forward(const double *params, int n, const double *X, double *y);
 double or_mlp_loss_grad(const double *params, int n, const double *X,
                         const double *t, double *grad);
