@@ -192,7 +192,9 @@ def main():
             "mixed": {"value": value_m, "ms_per_step": wall_m * 1e3 / args.steps,
                       "speedup_vs_fp64": value_m / value, "accuracy_vs_fp64": accuracy},
         },
-        "diag_last_stage": {k: diag[k] for k in ("max_courant", "Mb", "n_atm", "n_cold", "n_rescale")},
+        "diag_last_stage": dict({k: diag[k] for k in ("max_courant", "Mb", "n_atm", "n_cold",
+                                                       "n_rescale", "iter_max")},
+                                iter_mean=diag["iter_sum"] / nzone),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

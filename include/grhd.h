@@ -102,7 +102,7 @@ typedef struct { double *p[6]; } grhd_prim;      /* rho, u_x, u_y, u_z, P, eps *
 typedef struct {
   double w_max;           /* Lorentz-factor limit (100): sets k_max */
   double rho_atm;         /* atmosphere density floor, > 0 */
-  double tol;             /* relative root tolerance (<= 0: 1e-14) */
+  double tol;             /* relative root tolerance (<= 0: 1e-15) */
   int max_iter;           /* root-solver iteration cap (<= 0: 100) */
   int guess;              /* GRHD_GUESS_* */
   const void *mlp;        /* device weights for GRHD_GUESS_MLP (layout in
@@ -127,6 +127,8 @@ typedef struct {
   double max_courant;     /* max |coordinate signal speed| dt / spacing */
   double Mb, J;           /* sum q_D dV, sum q_Sphi dV of the output */
   unsigned long long n_rescale, n_cold, n_atm, n_fail;  /* flagged cells */
+  unsigned long long iter_sum, iter_max;  /* root-solver master-function
+                                             evaluations: total, worst cell */
 } grhd_diag;
 
 /* ---------------------------------------------------------------- calls */
@@ -226,7 +228,7 @@ int grhd_plan_tile(const grhd_plan *plan, int *tile_x, int *tile_z);
 
 /* ---------------------------------------------------------- learned guess */
 
-/* MLP 3 -> 64 -> 64 -> 1 (tanh) giving the initial pressure guess of the
+/* MLP 3 -> 64 -> 64 -> 1 (ReLU) giving the initial pressure guess of the
  * recovery.  Device weight buffer layout (bytes, 256-aligned blocks):
  * see GRHD_MLP_* below.  Features: (log10 D, S/(D + tau), log10(tau/D))
  * standardised by (mean, std) in the buffer; output log10(P/D) scaled by

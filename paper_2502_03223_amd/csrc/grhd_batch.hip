@@ -18,6 +18,7 @@
 #include "grhd_dev.hpp"
 #include "grhd_host.hpp"
 #include "grhd_tile.hpp"
+#include "grhd_diag.hpp"
 
 namespace grhd {
 
@@ -29,10 +30,11 @@ int fill_patch(const grhd_grid *grid, const grhd_metric *metric, const grhd_rk_s
 // ------------------------------------------------------------ kernels
 
 // recovery over all patches: item = (patch, row, 256-cell segment)
-template <int MC>
+template <int MC, int EK>
 __global__ void __launch_bounds__(256)
 k_con2prim_batch(const PatchK *__restrict__ pt, const EosK *__restrict__ eos, C2PK cp,
-                 const long long *__restrict__ item_prefix, int npatch, grhd_diag *diag) {
+                 const long long *__restrict__ item_prefix, int npatch, C2PPart *part) {
+  __shared__ unsigned long long red[4][6];
   long long b = blockIdx.x;
   int lo = 0, hi = npatch - 1;
   while (lo < hi) {  // last patch whose first item <= b
@@ -48,6 +50,7 @@ k_con2prim_batch(const PatchK *__restrict__ pt, const EosK *__restrict__ eos, C2
   int j = (int)(li % segs) * 256 + threadIdx.x;
   bool act = j < P.g.nx;
   unsigned fl = 0;
+  int iters = 0;
   if (act) {
     long long i = cell_index(P.g, j, k);
     double W = mval(P.m, GRHD_M_W, i);
@@ -60,24 +63,14 @@ k_con2prim_batch(const PatchK *__restrict__ pt, const EosK *__restrict__ eos, C2
     double qq[5], pp[6];
     for (int c = 0; c < 5; c++) qq[c] = P.qs[c][i];
     double x = P.g.x0 + (j + 0.5) * P.g.dx;
-    C2PResult r = con2prim_cell<MC>(e, cp, W, gtu, x, P.g.geom, qq, pp, -1.0);
+    C2PResult r = con2prim_cell<MC, EK>(e, cp, W, gtu, x, P.g.geom, qq, pp, -1.0);
     fl = r.flags;
+    iters = r.iters;
     if (fl)
       for (int c = 0; c < 5; c++) P.qs[c][i] = qq[c];
     for (int c = 0; c < 6; c++) P.p[c][i] = pp[c];
   }
-  if (diag) {
-    unsigned long long b0 = __ballot(act && (fl & GRHD_FLAG_RESCALE));
-    unsigned long long b1 = __ballot(act && (fl & GRHD_FLAG_COLD));
-    unsigned long long b2 = __ballot(act && (fl & GRHD_FLAG_ATM));
-    unsigned long long b3 = __ballot(act && (fl & GRHD_FLAG_FAIL));
-    if ((threadIdx.x & 63) == 0) {
-      if (b0) atomicAdd(&diag->n_rescale, (unsigned long long)__popcll(b0));
-      if (b1) atomicAdd(&diag->n_cold, (unsigned long long)__popcll(b1));
-      if (b2) atomicAdd(&diag->n_atm, (unsigned long long)__popcll(b2));
-      if (b3) atomicAdd(&diag->n_fail, (unsigned long long)__popcll(b3));
-    }
-  }
+  if (part) c2p_block_partial<256>(act, fl, iters, &part[blockIdx.x], red);
 }
 
 // persistent stage kernel: workgroups pop tiles until the queue is empty;
@@ -86,12 +79,14 @@ template <class T, int MC, int AX, int AZ, int BX, int BZ>
 __global__ void __launch_bounds__(NT)
 k_batch(const PatchK *__restrict__ pt, const EosK *__restrict__ eos,
         const long long *__restrict__ tile_prefix, int npatch, long long total,
-        unsigned long long *queue, grhd_diag *diag) {
+        unsigned long long *queue, FluxPart *part) {
+  __shared__ double red[NT / 64][3];
   __shared__ union {
     TileSmem<T, MC, AX, AZ> a;
     TileSmem<T, MC, BX, BZ> b;
   } sm;
   __shared__ long long s_item;
+  double cm = 0.0, mb = 0.0, jm = 0.0;
   for (;;) {
     if (threadIdx.x == 0) s_item = (long long)atomicAdd(&queue[0], 1ull);
     __syncthreads();
@@ -107,10 +102,11 @@ k_batch(const PatchK *__restrict__ pt, const EosK *__restrict__ eos,
     const PatchK &P = pt[lo];
     int lt = (int)(t - tile_prefix[lo]);
     if (P.g.nz <= 8)
-      substep_tile<T, MC, AX, AZ>(P, eos[P.eos_id], lt % P.tiles_x, lt / P.tiles_x, sm.a, diag);
+      substep_tile<T, MC, AX, AZ>(P, eos[P.eos_id], lt % P.tiles_x, lt / P.tiles_x, sm.a, cm, mb, jm);
     else
-      substep_tile<T, MC, BX, BZ>(P, eos[P.eos_id], lt % P.tiles_x, lt / P.tiles_x, sm.b, diag);
+      substep_tile<T, MC, BX, BZ>(P, eos[P.eos_id], lt % P.tiles_x, lt / P.tiles_x, sm.b, cm, mb, jm);
   }
+  if (part) flux_block_partial<NT>(cm, mb, jm, &part[blockIdx.x], red);
   if (threadIdx.x == 0) {
     __threadfence();
     unsigned long long done = atomicAdd(&queue[1], 1ull);
@@ -121,15 +117,8 @@ k_batch(const PatchK *__restrict__ pt, const EosK *__restrict__ eos,
   }
 }
 
-__global__ void k_zero_diag_b(grhd_diag *d) {
-  if (threadIdx.x == 0) {
-    d->max_courant = 0.0; d->Mb = 0.0; d->J = 0.0;
-    d->n_rescale = d->n_cold = d->n_atm = d->n_fail = 0ull;
-  }
-}
-
 using BatchFn = void (*)(const PatchK *, const EosK *, const long long *, int, long long,
-                         unsigned long long *, grhd_diag *);
+                         unsigned long long *, FluxPart *);
 
 // thin-patch shapes (nz <= 8) and square-patch shapes
 static const int kThin[2][2] = {{64, 8}, {32, 8}};
@@ -163,7 +152,7 @@ using namespace grhd;
 // ------------------------------------------------------------ plan
 
 struct grhd_plan {
-  int npatch = 0, neos = 0, prec = 0, mc = MC_CF;
+  int npatch = 0, neos = 0, prec = 0, mc = MC_CF, ek = GRHD_EOS_IDEAL;
   int shape_a = 0, shape_b = 0;
   grhd_options opts{};
   C2PK cp{};
@@ -184,6 +173,9 @@ struct grhd_plan {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   grhd_diag *graph_diag = nullptr;  // diag pointer baked into the graph
+  C2PPart *d_part1 = nullptr;       // per-workgroup diagnostic records
+  FluxPart *d_part2 = nullptr;
+  int part2_cap = 0;
 };
 
 namespace {
@@ -228,16 +220,24 @@ int capture_graph(grhd_plan *pl, grhd_diag *diag) {
   hipStream_t s = pl->cap_stream;
   if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return fail(GRHD_ERR_DEVICE, "graph capture begin failed");
-  hipLaunchKernelGGL(k_zero_diag_b, dim3(1), dim3(64), 0, s, diag);
-  if (pl->mc == MC_GEN)
-    hipLaunchKernelGGL(k_con2prim_batch<MC_GEN>, dim3((unsigned)pl->total_items), dim3(256), 0, s,
-                       pl->d_patches, pl->d_eos, pl->cp, pl->d_item_prefix, pl->npatch, diag);
+  dim3 gi((unsigned)pl->total_items);
+  C2PPart *p1 = pl->d_part1;
+  if (pl->mc == MC_GEN && pl->ek == GRHD_EOS_IDEAL)
+    hipLaunchKernelGGL((k_con2prim_batch<MC_GEN, GRHD_EOS_IDEAL>), gi, dim3(256), 0, s, pl->d_patches,
+                       pl->d_eos, pl->cp, pl->d_item_prefix, pl->npatch, p1);
+  else if (pl->mc == MC_GEN)
+    hipLaunchKernelGGL((k_con2prim_batch<MC_GEN, GRHD_EOS_HYBRID>), gi, dim3(256), 0, s, pl->d_patches,
+                       pl->d_eos, pl->cp, pl->d_item_prefix, pl->npatch, p1);
+  else if (pl->ek == GRHD_EOS_IDEAL)
+    hipLaunchKernelGGL((k_con2prim_batch<MC_CF, GRHD_EOS_IDEAL>), gi, dim3(256), 0, s, pl->d_patches,
+                       pl->d_eos, pl->cp, pl->d_item_prefix, pl->npatch, p1);
   else
-    hipLaunchKernelGGL(k_con2prim_batch<MC_CF>, dim3((unsigned)pl->total_items), dim3(256), 0, s,
-                       pl->d_patches, pl->d_eos, pl->cp, pl->d_item_prefix, pl->npatch, diag);
+    hipLaunchKernelGGL((k_con2prim_batch<MC_CF, GRHD_EOS_HYBRID>), gi, dim3(256), 0, s, pl->d_patches,
+                       pl->d_eos, pl->cp, pl->d_item_prefix, pl->npatch, p1);
   BatchFn fn = batch_kernel(pl->prec, pl->mc, pl->shape_a, pl->shape_b);
   hipLaunchKernelGGL(fn, dim3(pl->nblocks), dim3(NT), 0, s, pl->d_patches, pl->d_eos,
-                     pl->d_tile_prefix, pl->npatch, pl->total_tiles, pl->d_queue, diag);
+                     pl->d_tile_prefix, pl->npatch, pl->total_tiles, pl->d_queue, pl->d_part2);
+  launch_diag_final(pl->d_part1, (int)pl->total_items, pl->d_part2, pl->nblocks, diag, s);
   hipError_t le = hipGetLastError();
   hipError_t err = hipStreamEndCapture(s, &pl->graph);
   if (le != hipSuccess || err != hipSuccess)
@@ -278,6 +278,13 @@ int set_shapes(grhd_plan *pl, int a, int b, const grhd_patch *patches) {
     occ = 1;
   long long nb = (long long)ncu * occ;
   pl->nblocks = (int)std::max(1LL, std::min(nb, pl->total_tiles));
+  if (pl->nblocks > pl->part2_cap) {
+    hipFree(pl->d_part2);
+    pl->d_part2 = nullptr;
+    if (hipMalloc(&pl->d_part2, sizeof(FluxPart) * pl->nblocks) != hipSuccess)
+      return fail(GRHD_ERR_DEVICE, "plan allocation failed");
+    pl->part2_cap = pl->nblocks;
+  }
   return capture_graph(pl, pl->d_diag);
 }
 
@@ -361,6 +368,8 @@ void destroy_plan(grhd_plan *pl) {
   hipFree(pl->d_item_prefix);
   hipFree(pl->d_queue);
   hipFree(pl->d_diag);
+  hipFree(pl->d_part1);
+  hipFree(pl->d_part2);
   delete pl;
 }
 
@@ -382,6 +391,8 @@ extern "C" int grhd_plan_create(const grhd_patch *patches, int npatch, const grh
   for (int i = 0; i < neos; i++)
     if ((rc = check_eos(&eos_table[i]))) return rc;
   grhd_plan *pl = new grhd_plan();
+  for (int i = 0; i < neos; i++)
+    if (eos_table[i].kind == GRHD_EOS_HYBRID) pl->ek = GRHD_EOS_HYBRID;
   pl->npatch = npatch;
   pl->neos = neos;
   pl->prec = opts->prec;
@@ -412,6 +423,7 @@ extern "C" int grhd_plan_create(const grhd_patch *patches, int npatch, const grh
              hipMalloc(&pl->d_item_prefix, sizeof(long long) * npatch) == hipSuccess &&
              hipMalloc(&pl->d_queue, 2 * sizeof(unsigned long long)) == hipSuccess &&
              hipMalloc(&pl->d_diag, sizeof(grhd_diag)) == hipSuccess &&
+             hipMalloc(&pl->d_part1, sizeof(C2PPart) * pl->total_items) == hipSuccess &&
              hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking) == hipSuccess;
   for (int s = 0; okm && s < grhd_plan::kSlots; s++)
     okm = hipHostMalloc((void **)&pl->h_slots[s], sizeof(PatchK) * npatch, hipHostMallocDefault) == hipSuccess &&

@@ -152,51 +152,101 @@ __device__ __forceinline__ void prim2con_cell(double W, const double *gtu, doubl
 }
 
 // ------------------------------------------------ con -> prim (II.C.4)
+// The EOS kind is a template parameter (EK) so the gamma-law kernels carry
+// no piecewise-polytrope code.
 
-// Master function f(z) = z - r / h(z) with eps-hat clamped to eps_min.
-__device__ __forceinline__ double c2p_master(const EosK &e, double D, double qq,
-                                             double r, double z) {
+template <int EK>
+__device__ __forceinline__ double eps_cold_k(const EosK &e, double rho) {
+  return (EK == GRHD_EOS_IDEAL) ? 0.0 : eps_cold(e, rho);
+}
+
+template <int EK>
+__device__ __forceinline__ double press_cold_k(const EosK &e, double rho) {
+  return (EK == GRHD_EOS_IDEAL) ? 0.0 : press_cold(e, rho);
+}
+
+template <int EK>
+__device__ __forceinline__ double eos_press_k(const EosK &e, double rho, double eps) {
+  return (EK == GRHD_EOS_IDEAL) ? (e.Gth - 1.0) * rho * eps : eos_press(e, rho, eps);
+}
+
+// h(z) = (1 + eps)(1 + a) of the master function f(z) = z - r / h(z)
+// (eq. c2p_fn), eps-hat clamped to eps_min.
+template <int EK>
+__device__ __forceinline__ double c2p_h(const EosK &e, double D, double qq, double r, double z) {
   double w = sqrt(1.0 + z * z);
   double eps = w * qq - z * r + z * z / (1.0 + w);
-  double h;
-  if (e.kind == GRHD_EOS_IDEAL) {
+  if (EK == GRHD_EOS_IDEAL) {
     // (1+eps)(1+a) with a = P/(rho(1+eps)) reduces to 1 + Gamma eps
     if (eps < 0.0) eps = 0.0;
-    h = 1.0 + e.Gth * eps;
+    return 1.0 + e.Gth * eps;
   } else {
     double rho = D / w;
     double emin = eps_cold(e, rho);
     if (eps < emin) eps = emin;
     double P = eos_press(e, rho, eps);
     double a = P / (rho * (1.0 + eps));
-    h = (1.0 + eps) * (1.0 + a);
+    return (1.0 + eps) * (1.0 + a);
   }
-  return z - r / h;
 }
 
-__device__ __forceinline__ double c2p_cold_fn(const EosK &e, double D, double r, double z) {
-  double w = sqrt(1.0 + z * z);
-  double rho = D / w;
-  double hc = 1.0 + eps_cold(e, rho) + press_cold(e, rho) / rho;
-  return z - r / hc;
+// master function f(z), or its zero-temperature variant z - r / h_cold
+template <int EK, bool COLD>
+__device__ __forceinline__ double c2p_f(const EosK &e, double D, double qq, double r, double z) {
+  if (COLD) {
+    double rho = D / sqrt(1.0 + z * z);
+    double hc = 1.0 + eps_cold_k<EK>(e, rho) + press_cold_k<EK>(e, rho) / rho;
+    return z - r / hc;
+  }
+  return z - r / c2p_h<EK>(e, D, qq, r, z);
+}
+
+// f(z) and f'(z).  Gamma law: with eps(z) = w q - z r + (w - 1),
+// deps/dz = z (1 + q) / w - r and f' = 1 + r Gamma eps' / h^2 where eps > 0.
+template <int EK>
+__device__ __forceinline__ void c2p_f_df(const EosK &e, double D, double qq, double r, double z,
+                                         double &f, double &df) {
+  if (EK == GRHD_EOS_IDEAL) {
+    double w = sqrt(1.0 + z * z);
+    double eps = w * qq - z * r + z * z / (1.0 + w);
+    if (eps > 0.0) {
+      double h = 1.0 + e.Gth * eps;
+      double ih = 1.0 / h;
+      f = z - r * ih;
+      df = 1.0 + r * e.Gth * (z * (1.0 + qq) / w - r) * ih * ih;
+    } else {
+      f = z - r;
+      df = 1.0;
+    }
+  } else {
+    f = c2p_f<EK, false>(e, D, qq, r, z);
+    double hh = 1e-7 * z + 1e-300;
+    df = (c2p_f<EK, false>(e, D, qq, r, z + hh) - f) / hh;
+  }
 }
 
 // Illinois (modified regula falsi) on a bracket with f(a) < 0 < f(b).
-template <bool COLD>
-__device__ double illinois(const EosK &e, double D, double qq, double r, double a,
-                           double b, double tol, int max_iter, int *iters) {
-  double fa = COLD ? c2p_cold_fn(e, D, r, a) : c2p_master(e, D, qq, r, a);
+// Converged when the step, the bracket, or the distance of the secant
+// estimate to an end of the bracket falls below tol z (the last case is a
+// bracket end that already is the root).
+template <int EK, bool COLD>
+__device__ double illinois(const EosK &e, double D, double qq, double r, double a, double b,
+                           double tol, int max_iter, int *iters) {
+  double fa = c2p_f<EK, COLD>(e, D, qq, r, a);
   if (!(fa < 0.0)) return a;
-  double fb = COLD ? c2p_cold_fn(e, D, r, b) : c2p_master(e, D, qq, r, b);
+  double fb = c2p_f<EK, COLD>(e, D, qq, r, b);
   if (!(fb > 0.0)) return b;
   int side = 0;
   double c = a;
   for (int it = 0; it < max_iter; it++) {
     double cp = c;
     c = (a * fb - b * fa) / (fb - fa);
-    if (!(c > a && c < b)) c = 0.5 * (a + b);
-    double fc = COLD ? c2p_cold_fn(e, D, r, c) : c2p_master(e, D, qq, r, c);
-    if (iters) (*iters)++;
+    if (c - a <= tol * c || b - c <= tol * c) {
+      c = fmin(fmax(c, a), b);
+      break;
+    }
+    double fc = c2p_f<EK, COLD>(e, D, qq, r, c);
+    (*iters)++;
     if (fc > 0.0) {
       b = c; fb = fc;
       if (side == -1) fa *= 0.5;
@@ -220,11 +270,15 @@ struct C2PResult {
 
 // Full recovery of one cell.  q: densitised conserved (in; rewritten from
 // the primitives when a flag is set).  W, gtu: metric at the cell.
-// zguess >= 0 enables a safeguarded Newton start inside the bracket.
-template <int MC>
-__device__ C2PResult con2prim_cell(const EosK &e, const C2PK &cp, double W,
-                                   const double *gtu, double x, int geom, double *q,
-                                   double *p, double zguess) {
+// zguess >= 0 starts a safeguarded Newton iteration inside the bracket
+// (Illinois from the bracket when it does not converge).  A cell whose
+// state ends as the atmosphere carries the ATM flag only (plus FAIL for
+// invalid input).  The root satisfies z >= z- (and the gamma-law cold root
+// is z = r), so rho = D / w(z) <= D / w(min(z-, r)): when that bound is
+// below rho_atm the cell is atmosphere and the root is not needed.
+template <int MC, int EK>
+__device__ C2PResult con2prim_cell(const EosK &e, const C2PK &cp, double W, const double *gtu,
+                                   double x, int geom, double *q, double *p, double zguess) {
   C2PResult res{0u, 0};
   double W3 = W * W * W;
   bool ok = isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]) && isfinite(q[3]) &&
@@ -236,7 +290,9 @@ __device__ C2PResult con2prim_cell(const EosK &e, const C2PK &cp, double W,
   S[2] = W3 * q[3];
   double E = W3 * q[4];
   if (!(D > 0.0) || !(E > 0.0)) ok = false;
-  if (ok) {
+  bool atm = !ok || D < e.rho_atm;
+  double r = 0.0, qq = 0.0, z = 0.0;
+  if (!atm) {
     double S2;
     if (MC == MC_GEN) {
       S2 = 0.0;
@@ -246,8 +302,9 @@ __device__ C2PResult con2prim_cell(const EosK &e, const C2PK &cp, double W,
     } else {
       S2 = W * W * (S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
     }
-    double r = sqrt(S2) / D;
-    double qq = E / D - 1.0;
+    double iD = 1.0 / D;
+    r = sqrt(S2) * iD;
+    qq = E * iD - 1.0;
     double k = r / (1.0 + qq);
     if (k > cp.kmax) {
       double sc = cp.kmax / k;
@@ -256,21 +313,21 @@ __device__ C2PResult con2prim_cell(const EosK &e, const C2PK &cp, double W,
       k = cp.kmax;
       res.flags |= GRHD_FLAG_RESCALE;
     }
-    double z = 0.0;
-    if (k > 0.0) {
-      double zm = 0.5 * k / sqrt(1.0 - 0.25 * k * k);
-      double zp = k / sqrt(1.0 - k * k);
+    double zm = 0.5 * k / sqrt(1.0 - 0.25 * k * k);
+    double zp = k / sqrt(1.0 - k * k);
+    double zlo = (EK == GRHD_EOS_IDEAL) ? fmin(zm, r) : 0.0;
+    if (D / sqrt(1.0 + zlo * zlo) < e.rho_atm) atm = true;
+    if (!atm && k > 0.0) {
       bool done = false;
       if (zguess >= 0.0) {
-        // safeguarded Newton from the learned guess (derivative by a
-        // one-sided secant of width 1e-7 z), at most 8 steps, on the bracket
+        // safeguarded Newton from the learned guess, at most 8 steps, kept
+        // inside the bracket (analytic derivative for the gamma law, a
+        // one-sided difference otherwise)
         double zz = fmin(fmax(zguess, zm), zp);
         for (int it = 0; it < 8; it++) {
-          double f0 = c2p_master(e, D, qq, r, zz);
-          double hh = 1e-7 * zz + 1e-300;
-          double f1 = c2p_master(e, D, qq, r, zz + hh);
-          res.iters += 2;
-          double df = (f1 - f0) / hh;
+          double f0, df;
+          c2p_f_df<EK>(e, D, qq, r, zz, f0, df);
+          res.iters += 1;
           double zn = zz - f0 / df;
           if (!(zn >= zm && zn <= zp)) break;
           double dz = fabs(zn - zz);
@@ -279,44 +336,45 @@ __device__ C2PResult con2prim_cell(const EosK &e, const C2PK &cp, double W,
         }
         if (done) z = zz;
       }
-      if (!done) z = illinois<false>(e, D, qq, r, zm, zp, cp.tol, cp.max_iter, &res.iters);
+      if (!done) z = illinois<EK, false>(e, D, qq, r, zm, zp, cp.tol, cp.max_iter, &res.iters);
     }
+  }
+  if (!atm) {
     double w = sqrt(1.0 + z * z);
     double rho = D / w;
     double eps = w * qq - z * r + z * z / (1.0 + w);
     double P;
-    if (eps < eps_cold(e, rho)) {
-      if (e.kind == GRHD_EOS_IDEAL) {
+    if (eps < eps_cold_k<EK>(e, rho)) {
+      if (EK == GRHD_EOS_IDEAL) {
         z = r;  // h_cold = 1: the zero-temperature root is z = r
       } else {
-        z = (r > 0.0) ? illinois<true>(e, D, qq, r, 0.0, r, cp.tol, cp.max_iter, &res.iters)
-                      : 0.0;
+        z = (r > 0.0) ? illinois<EK, true>(e, D, qq, r, 0.0, r, cp.tol, cp.max_iter, &res.iters) : 0.0;
       }
       w = sqrt(1.0 + z * z);
       rho = D / w;
-      eps = eps_cold(e, rho);
-      P = press_cold(e, rho);
+      eps = eps_cold_k<EK>(e, rho);
+      P = press_cold_k<EK>(e, rho);
       res.flags |= GRHD_FLAG_COLD;
     } else {
-      P = eos_press(e, rho, eps);
+      P = eos_press_k<EK>(e, rho, eps);
     }
     double h = 1.0 + eps + P / rho;
-    double Dh = D * h;
+    double iDh = 1.0 / (D * h);
     p[0] = rho;
-    p[1] = S[0] / Dh;
-    p[2] = S[1] / Dh;
-    p[3] = S[2] / Dh;
+    p[1] = S[0] * iDh;
+    p[2] = S[1] * iDh;
+    p[3] = S[2] * iDh;
     p[4] = P;
     p[5] = eps;
     if (!isfinite(rho) || !isfinite(P) || !isfinite(eps) || !isfinite(p[1]) ||
         !isfinite(p[2]) || !isfinite(p[3]))
       ok = false;
+    atm = !ok || rho < e.rho_atm;
   }
-  if (!ok) res.flags |= GRHD_FLAG_FAIL | GRHD_FLAG_ATM;
-  if (!ok || p[0] < e.rho_atm) {
+  if (atm) {
     p[0] = e.rho_atm; p[1] = 0.0; p[2] = 0.0; p[3] = 0.0;
     p[4] = e.P_atm; p[5] = e.eps_atm;
-    res.flags |= GRHD_FLAG_ATM;
+    res.flags = ok ? GRHD_FLAG_ATM : (GRHD_FLAG_ATM | GRHD_FLAG_FAIL);
   }
   if (res.flags) prim2con_cell<MC>(W, gtu, x, geom, p, q);
   return res;
@@ -367,9 +425,10 @@ __device__ __forceinline__ void ppm_face(const T *s, T &L, T &R) {
   T d2 = mono_slope(s[1], s[2], s[3]);
   T d3 = mono_slope(s[2], s[3], s[4]);
   T d4 = mono_slope(s[3], s[4], s[5]);
-  T i1 = s[1] + T(0.5) * (s[2] - s[1]) - (d2 - d1) / T(6);
-  T i2 = s[2] + T(0.5) * (s[3] - s[2]) - (d3 - d2) / T(6);
-  T i3 = s[3] + T(0.5) * (s[4] - s[3]) - (d4 - d3) / T(6);
+  const T sixth = T(1.0 / 6.0);
+  T i1 = s[1] + T(0.5) * (s[2] - s[1]) - sixth * (d2 - d1);
+  T i2 = s[2] + T(0.5) * (s[3] - s[2]) - sixth * (d3 - d2);
+  T i3 = s[3] + T(0.5) * (s[4] - s[3]) - sixth * (d4 - d3);
   T l0, r0, l1, r1;
   ppm_cell(s[2], i1, i2, l0, r0);
   ppm_cell(s[3], i2, i3, l1, r1);
@@ -407,6 +466,7 @@ __device__ __forceinline__ T lagrange6(const T *a) {
 }
 
 __device__ __forceinline__ double deriv6(const double *a, double inv60h) {
+#pragma clang fp contract(off)
   return (-a[0] + 9.0 * a[1] - 45.0 * a[2] + 45.0 * a[4] - 9.0 * a[5] + a[6]) * inv60h;
 }
 
@@ -671,6 +731,7 @@ __device__ __forceinline__ void face_flux(const EosK &e, const FaceMet<T> &m, in
 template <int MC>
 __device__ __forceinline__ void sources(const double *g, const double *dg, double x, int geom,
                                         const double *p, double *s) {
+#pragma clang fp contract(off)
   double alp = g[GRHD_M_ALP], W = g[GRHD_M_W];
   double rho = p[0], P = p[4], eps = p[5];
   double u[3] = {p[1], p[2], p[3]};

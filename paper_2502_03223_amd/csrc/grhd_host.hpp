@@ -115,7 +115,7 @@ inline C2PK to_c2pk(const grhd_c2p_params *c) {
   C2PK k;
   double vmax = std::sqrt(1.0 - 1.0 / (c->w_max * c->w_max));
   k.kmax = 2.0 * vmax / (1.0 + vmax * vmax);
-  k.tol = (c->tol > 0.0) ? c->tol : 1e-14;
+  k.tol = (c->tol > 0.0) ? c->tol : 1e-15;
   k.max_iter = (c->max_iter > 0) ? c->max_iter : 100;
   k.guess = c->guess;
   k.mlp = c->mlp;

@@ -6,12 +6,15 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "grhd.h"
 #include "grhd_dev.hpp"
 #include "grhd_host.hpp"
 #include "grhd_tile.hpp"
+#include "grhd_diag.hpp"
 
 namespace grhd {
 
@@ -38,13 +41,53 @@ int fail(int code, const char *fmt, ...) {
 
 // ------------------------------------------------------------ small kernels
 
-__global__ void k_zero_diag(grhd_diag *d) {
-  if (threadIdx.x == 0) {
-    d->max_courant = 0.0;
-    d->Mb = 0.0;
-    d->J = 0.0;
-    d->n_rescale = d->n_cold = d->n_atm = d->n_fail = 0ull;
+// fold n1 recovery records and n2 stage records into diag (fixed order)
+__global__ void __launch_bounds__(256)
+k_diag_final(const C2PPart *p1, int n1, const FluxPart *p2, int n2, grhd_diag *diag) {
+  __shared__ unsigned long long su[256][6];
+  __shared__ double sd[256][3];
+  int t = threadIdx.x;
+  unsigned long long a[6] = {0, 0, 0, 0, 0, 0};
+  double c = 0.0, mb = 0.0, jm = 0.0;
+  for (int i = t; i < n1; i += 256) {
+    for (int k = 0; k < 5; k++) a[k] += p1[i].n[k];
+    a[5] = p1[i].n[5] > a[5] ? p1[i].n[5] : a[5];
   }
+  for (int i = t; i < n2; i += 256) {
+    c = fmax(c, p2[i].cmax);
+    mb += p2[i].mb;
+    jm += p2[i].jm;
+  }
+  for (int k = 0; k < 6; k++) su[t][k] = a[k];
+  sd[t][0] = c; sd[t][1] = mb; sd[t][2] = jm;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) {
+      for (int k = 0; k < 5; k++) su[t][k] += su[t + s][k];
+      su[t][5] = su[t + s][5] > su[t][5] ? su[t + s][5] : su[t][5];
+      sd[t][0] = fmax(sd[t][0], sd[t + s][0]);
+      sd[t][1] += sd[t + s][1];
+      sd[t][2] += sd[t + s][2];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    diag->max_courant = sd[0][0];
+    diag->Mb = sd[0][1];
+    diag->J = sd[0][2];
+    diag->n_rescale = su[0][0];
+    diag->n_cold = su[0][1];
+    diag->n_atm = su[0][2];
+    diag->n_fail = su[0][3];
+    diag->iter_sum = su[0][4];
+    diag->iter_max = su[0][5];
+  }
+}
+
+int launch_diag_final(const C2PPart *p1, int n1, const FluxPart *p2, int n2, grhd_diag *diag,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, st, p1, n1, p2, n2, diag);
+  return launch_status("diag final");
 }
 
 __global__ void k_zero_double(double *d) {
@@ -53,10 +96,11 @@ __global__ void k_zero_double(double *d) {
 
 // Recovery of one cell per thread over [jlo, jhi) x [klo, khi); cells
 // outside the interior are processed only on EXTERNAL sides (corners never).
-template <int MC>
+template <int MC, int EK>
 __global__ void __launch_bounds__(256)
-k_con2prim(GridK g, EosK e, C2PK cp, MetK m, Q5 q, P6 p, uint8_t *flags, grhd_diag *diag,
+k_con2prim(GridK g, EosK e, C2PK cp, MetK m, Q5 q, P6 p, uint8_t *flags, C2PPart *part,
            int jlo, int jhi, int klo) {
+  __shared__ unsigned long long red[4][6];
   int j = jlo + blockIdx.x * blockDim.x + threadIdx.x;
   int k = klo + blockIdx.y;
   bool act = j < jhi;
@@ -67,6 +111,7 @@ k_con2prim(GridK g, EosK e, C2PK cp, MetK m, Q5 q, P6 p, uint8_t *flags, grhd_di
     else act = act && g.bc[k < 0 ? 2 : 3] == GRHD_BC_EXTERNAL;
   }
   unsigned fl = 0;
+  int iters = 0;
   if (act) {
     long long i = cell_index(g, j, k);
     double W = mval(m, GRHD_M_W, i);
@@ -79,25 +124,16 @@ k_con2prim(GridK g, EosK e, C2PK cp, MetK m, Q5 q, P6 p, uint8_t *flags, grhd_di
     double qq[5], pp[6];
     for (int c = 0; c < 5; c++) qq[c] = q.q[c][i];
     double x = g.x0 + (j + 0.5) * g.dx;
-    C2PResult r = con2prim_cell<MC>(e, cp, W, gtu, x, g.geom, qq, pp, -1.0);
+    C2PResult r = con2prim_cell<MC, EK>(e, cp, W, gtu, x, g.geom, qq, pp, -1.0);
     fl = r.flags;
+    iters = r.iters;
     if (fl)
       for (int c = 0; c < 5; c++) q.q[c][i] = qq[c];
     for (int c = 0; c < 6; c++) p.p[c][i] = pp[c];
     if (flags) flags[i] = (uint8_t)fl;
   }
-  if (diag && jin && kin) {
-    unsigned long long b0 = __ballot(act && (fl & GRHD_FLAG_RESCALE));
-    unsigned long long b1 = __ballot(act && (fl & GRHD_FLAG_COLD));
-    unsigned long long b2 = __ballot(act && (fl & GRHD_FLAG_ATM));
-    unsigned long long b3 = __ballot(act && (fl & GRHD_FLAG_FAIL));
-    if ((threadIdx.x & 63) == __ffsll((long long)__ballot(1)) - 1) {
-      if (b0) atomicAdd(&diag->n_rescale, (unsigned long long)__popcll(b0));
-      if (b1) atomicAdd(&diag->n_cold, (unsigned long long)__popcll(b1));
-      if (b2) atomicAdd(&diag->n_atm, (unsigned long long)__popcll(b2));
-      if (b3) atomicAdd(&diag->n_fail, (unsigned long long)__popcll(b3));
-    }
-  }
+  if (part)
+    c2p_block_partial<256>(act && jin && kin, fl, iters, &part[blockIdx.y * gridDim.x + blockIdx.x], red);
 }
 
 template <int MC>
@@ -208,19 +244,22 @@ k_flux(GridK g, EosK e, MetK m, int dir, int riemann, Ptr6<T> Lp, Ptr6<T> Rp, Q5
 // the 8 XCDs works on a contiguous band of tiles (halo reuse in its L2).
 template <class T, int MC, int TX, int TZ>
 __global__ void __launch_bounds__(NT)
-k_substep(PatchK P, EosK e, grhd_diag *diag) {
+k_substep(PatchK P, EosK e, FluxPart *part) {
   __shared__ TileSmem<T, MC, TX, TZ> sm;
+  __shared__ double red[NT / 64][3];
   int ntiles = P.tiles_x * P.tiles_z;
   int b = blockIdx.x;
   int full = (ntiles / 8) * 8;
   int t = b;
   if (b < full) t = (b % 8) * (full / 8) + b / 8;
-  substep_tile<T, MC, TX, TZ>(P, e, t % P.tiles_x, t / P.tiles_x, sm, diag);
+  double cm = 0.0, mb = 0.0, jm = 0.0;
+  substep_tile<T, MC, TX, TZ>(P, e, t % P.tiles_x, t / P.tiles_x, sm, cm, mb, jm);
+  if (part) flux_block_partial<NT>(cm, mb, jm, &part[b], red);
 }
 
 // ------------------------------------------------------------ dispatch
 
-using SubstepFn = void (*)(PatchK, EosK, grhd_diag *);
+using SubstepFn = void (*)(PatchK, EosK, FluxPart *);
 
 struct TileShape { int tx, tz; };
 static const TileShape kShapes[] = {{32, 8}, {32, 16}, {64, 8}, {16, 16}};
@@ -242,6 +281,42 @@ static SubstepFn substep_kernel(int prec, int mc, int shape) {
   return mc == MC_GEN ? pick_shape<double, MC_GEN>(shape) : pick_shape<double, MC_CF>(shape);
 }
 
+// Scratch for the workgroup partial records of the diagnostics, owned by
+// the library: one buffer per (device, stream), allocated on the first call
+// that asks for diagnostics and grown when a larger grid needs more.
+// Calls that overlap on the same stream are ordered; different streams use
+// different buffers.
+struct DiagScratch {
+  int dev;
+  hipStream_t st;
+  void *buf;
+  size_t bytes;
+};
+static std::mutex g_scratch_mu;
+static std::vector<DiagScratch> g_scratch;
+
+void *diag_scratch(hipStream_t st, size_t bytes) {
+  int dev = 0;
+  hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  for (auto &s : g_scratch)
+    if (s.dev == dev && s.st == st) {
+      if (s.bytes >= bytes) return s.buf;
+      hipStreamSynchronize(st);
+      hipFree(s.buf);
+      s.buf = nullptr;
+      s.bytes = 0;
+      if (hipMalloc(&s.buf, bytes) != hipSuccess) return nullptr;
+      s.bytes = bytes;
+      return s.buf;
+    }
+  DiagScratch s{dev, st, nullptr, 0};
+  if (hipMalloc(&s.buf, bytes) != hipSuccess) return nullptr;
+  s.bytes = bytes;
+  g_scratch.push_back(s);
+  return s.buf;
+}
+
 int shape_index(int tx, int tz) {
   for (int s = 0; s < kNumShapes; s++)
     if (kShapes[s].tx == tx && kShapes[s].tz == tz) return s;
@@ -251,22 +326,45 @@ int shape_index(int tx, int tz) {
 int num_shapes() { return kNumShapes; }
 void shape_of(int s, int *tx, int *tz) { *tx = kShapes[s].tx; *tz = kShapes[s].tz; }
 
-int launch_con2prim(const GridK &g, const EosK &e, const C2PK &cp, const MetK &m, int mc,
-                    const Q5 &q, const P6 &p, uint8_t *flags, grhd_diag *diag, hipStream_t st) {
+template <int MC, int EK>
+static void con2prim_launch(dim3 grid, hipStream_t st, const GridK &g, const EosK &e, const C2PK &cp,
+                            const MetK &m, const Q5 &q, const P6 &p, uint8_t *flags, C2PPart *part,
+                            int jlo, int jhi, int klo) {
+  hipLaunchKernelGGL((k_con2prim<MC, EK>), grid, dim3(256), 0, st, g, e, cp, m, q, p, flags, part, jlo,
+                     jhi, klo);
+}
+
+int con2prim_blocks(const GridK &g) {
   int jlo = (g.bc[0] == GRHD_BC_EXTERNAL) ? -g.ng : 0;
   int jhi = (g.bc[1] == GRHD_BC_EXTERNAL) ? g.nx + g.ng : g.nx;
   int klo = (g.bc[2] == GRHD_BC_EXTERNAL) ? -g.ng : 0;
   int khi = (g.bc[3] == GRHD_BC_EXTERNAL) ? g.nz + g.ng : g.nz;
-  int bs = 256;
-  dim3 grid((jhi - jlo + bs - 1) / bs, khi - klo);
-  if (mc == MC_GEN)
-    hipLaunchKernelGGL(k_con2prim<MC_GEN>, grid, dim3(bs), 0, st, g, e, cp, m, q, p, flags, diag, jlo, jhi, klo);
-  else
-    hipLaunchKernelGGL(k_con2prim<MC_CF>, grid, dim3(bs), 0, st, g, e, cp, m, q, p, flags, diag, jlo, jhi, klo);
+  return ((jhi - jlo + 255) / 256) * (khi - klo);
+}
+
+int launch_con2prim_mlp(const GridK &g, const EosK &e, const C2PK &cp, const MetK &m, int mc,
+                        const Q5 &q, const P6 &p, uint8_t *flags, C2PPart *part, hipStream_t st);
+
+int launch_con2prim(const GridK &g, const EosK &e, const C2PK &cp, const MetK &m, int mc,
+                    const Q5 &q, const P6 &p, uint8_t *flags, C2PPart *diag, hipStream_t st) {
+  if (cp.guess == GRHD_GUESS_MLP) return launch_con2prim_mlp(g, e, cp, m, mc, q, p, flags, diag, st);
+  int jlo = (g.bc[0] == GRHD_BC_EXTERNAL) ? -g.ng : 0;
+  int jhi = (g.bc[1] == GRHD_BC_EXTERNAL) ? g.nx + g.ng : g.nx;
+  int klo = (g.bc[2] == GRHD_BC_EXTERNAL) ? -g.ng : 0;
+  int khi = (g.bc[3] == GRHD_BC_EXTERNAL) ? g.nz + g.ng : g.nz;
+  dim3 grid((jhi - jlo + 255) / 256, khi - klo);
+  bool ideal = e.kind == GRHD_EOS_IDEAL;
+  if (mc == MC_GEN) {
+    if (ideal) con2prim_launch<MC_GEN, GRHD_EOS_IDEAL>(grid, st, g, e, cp, m, q, p, flags, diag, jlo, jhi, klo);
+    else con2prim_launch<MC_GEN, GRHD_EOS_HYBRID>(grid, st, g, e, cp, m, q, p, flags, diag, jlo, jhi, klo);
+  } else {
+    if (ideal) con2prim_launch<MC_CF, GRHD_EOS_IDEAL>(grid, st, g, e, cp, m, q, p, flags, diag, jlo, jhi, klo);
+    else con2prim_launch<MC_CF, GRHD_EOS_HYBRID>(grid, st, g, e, cp, m, q, p, flags, diag, jlo, jhi, klo);
+  }
   return launch_status("con2prim");
 }
 
-int launch_substep(const PatchK &pk, const EosK &e, int prec, int mc, int shape, grhd_diag *diag,
+int launch_substep(const PatchK &pk, const EosK &e, int prec, int mc, int shape, FluxPart *diag,
                    hipStream_t st) {
   SubstepFn fn = substep_kernel(prec, mc, shape);
   int ntiles = pk.tiles_x * pk.tiles_z;
@@ -291,19 +389,25 @@ extern "C" int grhd_con2prim(const grhd_grid *grid, const grhd_eos *eos, const g
   if ((rc = check_grid(grid)) || (rc = check_eos(eos)) || (rc = check_metric(metric)) ||
       (rc = check_c2p(c2p)) || (rc = check_cons(q, "q")) || (rc = check_prim(p, "p")))
     return rc;
-  if (c2p->guess == GRHD_GUESS_MLP)
-    return fail(GRHD_ERR_UNSUPPORTED, "use grhd_con2prim_mlp for the learned guess");
   hipStream_t st = (hipStream_t)hip_stream;
   Q5 qq;
   P6 pp;
   for (int c = 0; c < 5; c++) qq.q[c] = q->q[c];
   for (int c = 0; c < 6; c++) pp.p[c] = p->p[c];
+  GridK g = to_gridk(grid);
+  int nb1 = con2prim_blocks(g);
+  C2PPart *p1 = nullptr;
   if (diag) {
-    hipLaunchKernelGGL(k_zero_diag, dim3(1), dim3(64), 0, st, diag);
-    if ((rc = launch_status("diag reset"))) return rc;
+    p1 = (C2PPart *)diag_scratch(st, sizeof(C2PPart) * nb1);
+    if (!p1) return fail(GRHD_ERR_DEVICE, "diagnostic scratch allocation failed");
   }
-  return launch_con2prim(to_gridk(grid), to_eosk(eos, c2p->rho_atm), to_c2pk(c2p), to_metk(metric),
-                         metric_class(metric), qq, pp, flags, diag, st);
+  if ((rc = launch_con2prim(g, to_eosk(eos, c2p->rho_atm), to_c2pk(c2p), to_metk(metric),
+                            metric_class(metric), qq, pp, flags, p1, st)))
+    return rc;
+  if (diag) {
+    return launch_diag_final(p1, nb1, nullptr, 0, diag, st);
+  }
+  return GRHD_OK;
 }
 
 extern "C" int grhd_prim2con(const grhd_grid *grid, const grhd_eos *eos, const grhd_metric *metric,
@@ -453,8 +557,6 @@ extern "C" int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos, const
   int rc;
   if (!opts) return fail(GRHD_ERR_INVALID, "opts is NULL");
   if ((rc = check_eos(eos)) || (rc = check_c2p(&opts->c2p))) return rc;
-  if (opts->c2p.guess == GRHD_GUESS_MLP)
-    return fail(GRHD_ERR_UNSUPPORTED, "learned guess is not wired into the substep");
   if (opts->prec != GRHD_PREC_FP64 && opts->prec != GRHD_PREC_MIXED) return fail(GRHD_ERR_INVALID, "bad prec");
   PatchK pk;
   if ((rc = fill_patch(grid, metric, stage, qn, qs, qout, p, acc_in, acc_out, flux_reg, opts->recon,
@@ -476,10 +578,19 @@ extern "C" int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos, const
   P6 pp;
   for (int c = 0; c < 5; c++) q.q[c] = qs->q[c];
   for (int c = 0; c < 6; c++) pp.p[c] = p->p[c];
+  int nb1 = con2prim_blocks(pk.g), nb2 = pk.tiles_x * pk.tiles_z;
+  C2PPart *p1 = nullptr;
+  FluxPart *p2 = nullptr;
   if (diag) {
-    hipLaunchKernelGGL(k_zero_diag, dim3(1), dim3(64), 0, st, diag);
-    if ((rc = launch_status("diag reset"))) return rc;
+    char *buf = (char *)diag_scratch(st, sizeof(C2PPart) * nb1 + sizeof(FluxPart) * nb2);
+    if (!buf) return fail(GRHD_ERR_DEVICE, "diagnostic scratch allocation failed");
+    p1 = (C2PPart *)buf;
+    p2 = (FluxPart *)(buf + sizeof(C2PPart) * nb1);
   }
-  if ((rc = launch_con2prim(pk.g, e, to_c2pk(&opts->c2p), pk.m, mc, q, pp, flags, diag, st))) return rc;
-  return launch_substep(pk, e, opts->prec, mc, shape, diag, st);
+  if ((rc = launch_con2prim(pk.g, e, to_c2pk(&opts->c2p), pk.m, mc, q, pp, flags, p1, st))) return rc;
+  if ((rc = launch_substep(pk, e, opts->prec, mc, shape, p2, st))) return rc;
+  if (diag) {
+    return launch_diag_final(p1, nb1, p2, nb2, diag, st);
+  }
+  return GRHD_OK;
 }

@@ -1,0 +1,315 @@
+// grhd_mlp.hip -- the learned initial guess of the primitive recovery:
+// inference on the matrix cores inside the recovery kernel, and the
+// training kernels (per-sample forward and backward in FP32 with the BF16
+// weights of the inference path, gradient reduction, Adam, packing).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "grhd.h"
+#include "grhd_dev.hpp"
+#include "grhd_diag.hpp"
+#include "grhd_host.hpp"
+#include "grhd_mlp.hpp"
+
+namespace grhd {
+
+// ------------------------------------------------------------ inference
+
+// standalone forward: X holds standardised features (n x 3), y receives
+// the network output
+__global__ void __launch_bounds__(256) k_mlp_forward(const MlpDev *w, const float *X, float *y, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool act = i < n;
+  float x0 = act ? X[3 * i] : 0.0f, x1 = act ? X[3 * i + 1] : 0.0f, x2 = act ? X[3 * i + 2] : 0.0f;
+  float o = mlp_forward_wave(w, x0, x1, x2);
+  if (act) y[i] = o;
+}
+
+// Recovery seeded by the network: features (log10 D, S/E, log10(tau/D)),
+// output log10(P/D); the guess P0 gives v0 = S/(E + P0) and
+// z0 = v0 / sqrt(1 - v0^2), from which a safeguarded Newton solve starts.
+template <int MC, int EK>
+__global__ void __launch_bounds__(256)
+k_con2prim_mlp(GridK g, EosK e, C2PK cp, MetK m, Q5 q, P6 p, uint8_t *flags, C2PPart *part,
+               int jlo, int jhi, int klo) {
+  __shared__ unsigned long long red[4][6];
+  const MlpDev *w = (const MlpDev *)cp.mlp;
+  int j = jlo + blockIdx.x * blockDim.x + threadIdx.x;
+  int k = klo + blockIdx.y;
+  bool act = j < jhi;
+  bool jin = (j >= 0 && j < g.nx), kin = (k >= 0 && k < g.nz);
+  if (!jin || !kin) {
+    if (!jin && !kin) act = false;
+    else if (!jin) act = act && g.bc[j < 0 ? 0 : 1] == GRHD_BC_EXTERNAL;
+    else act = act && g.bc[k < 0 ? 2 : 3] == GRHD_BC_EXTERNAL;
+  }
+  long long i = cell_index(g, act ? j : 0, act ? k : 0);
+  double qq[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, W = 1.0, gtu[6];
+  double x = g.x0 + (j + 0.5) * g.dx;
+  if (act) {
+    W = mval(m, GRHD_M_W, i);
+    for (int c = 0; c < 5; c++) qq[c] = q.q[c][i];
+  }
+  if (MC == MC_GEN) {
+    double gt[6];
+    for (int t = 0; t < 6; t++) gt[t] = act ? mval(m, GRHD_M_GXX + t, i) : (t == 0 || t == 3 || t == 5);
+    inv_sym3(gt, gtu);
+  }
+  // features (all lanes take part in the network evaluation)
+  double W3 = W * W * W;
+  double D = W3 * qq[0], E = W3 * qq[4];
+  double Sx = W3 * qq[1], Sy = W3 * ((g.geom == GRHD_GEOM_CYLINDRICAL && act) ? qq[2] / x : qq[2]),
+         Sz = W3 * qq[3];
+  double S2;
+  if (MC == MC_GEN) {
+    double Sv[3] = {Sx, Sy, Sz};
+    S2 = 0.0;
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++) S2 += gtu[s3i(a, b)] * Sv[a] * Sv[b];
+    S2 *= W * W;
+  } else {
+    S2 = W * W * (Sx * Sx + Sy * Sy + Sz * Sz);
+  }
+  double S = sqrt(S2);
+  double tau = E - D;
+  bool good = act && D > 0.0 && E > 0.0 && tau > 0.0 && isfinite(S) && isfinite(E);
+  float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
+  if (good) {
+    f0 = ((float)log10(D) - w->xm[0]) / w->xs[0];
+    f1 = ((float)(S / E) - w->xm[1]) / w->xs[1];
+    f2 = ((float)log10(tau / D) - w->xm[2]) / w->xs[2];
+  }
+  float y = mlp_forward_wave(w, f0, f1, f2);
+  double zg = -1.0;
+  if (good) {
+    double P0 = D * exp10((double)(y * w->ys + w->ym));
+    double v0 = S / (E + P0);
+    if (v0 >= 0.0 && v0 < 1.0) zg = v0 / sqrt(1.0 - v0 * v0);
+  }
+  unsigned fl = 0;
+  int iters = 0;
+  if (act) {
+    double pp[6];
+    C2PResult r = con2prim_cell<MC, EK>(e, cp, W, gtu, x, g.geom, qq, pp, zg);
+    fl = r.flags;
+    iters = r.iters;
+    if (fl)
+      for (int c = 0; c < 5; c++) q.q[c][i] = qq[c];
+    for (int c = 0; c < 6; c++) p.p[c][i] = pp[c];
+    if (flags) flags[i] = (uint8_t)fl;
+  }
+  if (part)
+    c2p_block_partial<256>(act && jin && kin, fl, iters, &part[blockIdx.y * gridDim.x + blockIdx.x], red);
+}
+
+template <int MC, int EK>
+static void launch_mlp(dim3 grid, hipStream_t st, const GridK &g, const EosK &e, const C2PK &cp,
+                       const MetK &m, const Q5 &q, const P6 &p, uint8_t *flags, C2PPart *part, int jlo,
+                       int jhi, int klo) {
+  hipLaunchKernelGGL((k_con2prim_mlp<MC, EK>), grid, dim3(256), 0, st, g, e, cp, m, q, p, flags, part,
+                     jlo, jhi, klo);
+}
+
+int launch_con2prim_mlp(const GridK &g, const EosK &e, const C2PK &cp, const MetK &m, int mc,
+                        const Q5 &q, const P6 &p, uint8_t *flags, C2PPart *part, hipStream_t st) {
+  int jlo = (g.bc[0] == GRHD_BC_EXTERNAL) ? -g.ng : 0;
+  int jhi = (g.bc[1] == GRHD_BC_EXTERNAL) ? g.nx + g.ng : g.nx;
+  int klo = (g.bc[2] == GRHD_BC_EXTERNAL) ? -g.ng : 0;
+  int khi = (g.bc[3] == GRHD_BC_EXTERNAL) ? g.nz + g.ng : g.nz;
+  dim3 grid((jhi - jlo + 255) / 256, khi - klo);
+  bool ideal = e.kind == GRHD_EOS_IDEAL;
+  if (mc == MC_GEN) {
+    if (ideal) launch_mlp<MC_GEN, GRHD_EOS_IDEAL>(grid, st, g, e, cp, m, q, p, flags, part, jlo, jhi, klo);
+    else launch_mlp<MC_GEN, GRHD_EOS_HYBRID>(grid, st, g, e, cp, m, q, p, flags, part, jlo, jhi, klo);
+  } else {
+    if (ideal) launch_mlp<MC_CF, GRHD_EOS_IDEAL>(grid, st, g, e, cp, m, q, p, flags, part, jlo, jhi, klo);
+    else launch_mlp<MC_CF, GRHD_EOS_HYBRID>(grid, st, g, e, cp, m, q, p, flags, part, jlo, jhi, klo);
+  }
+  return launch_status("con2prim (learned guess)");
+}
+
+// ------------------------------------------------------------ training
+
+constexpr int GW = 64;  // samples per chunk (one wave)
+
+// Per-sample forward/backward of the MSE loss with the BF16-rounded weights
+// of the inference path (FP32 arithmetic), then a change of roles: lane u
+// accumulates the gradient row of hidden unit u over the chunk's samples.
+// Each workgroup folds its rows into grad with one atomic per parameter.
+__global__ void __launch_bounds__(GW)
+k_mlp_grad(const float *__restrict__ P, const float *__restrict__ X, const float *__restrict__ t, int n,
+           float *grad, float *loss) {
+  __shared__ float sW1[MLP_H * 3], sb1[MLP_H], sW2[MLP_H * MLP_H], sb2[MLP_H], sw3[MLP_H];
+  __shared__ float sH1[MLP_H][GW + 1], sH2[MLP_H][GW + 1], sD2[MLP_H][GW + 1], sD1[MLP_H][GW + 1];
+  __shared__ float sX[3][GW], sDY[GW];
+  const int l = threadIdx.x;
+  for (int i = l; i < MLP_H * 3; i += GW) sW1[i] = bf2f(f2bf(P[OFF_W1 + i]));
+  for (int i = l; i < MLP_H * MLP_H; i += GW) sW2[i] = bf2f(f2bf(P[OFF_W2 + i]));
+  for (int i = l; i < MLP_H; i += GW) {
+    sb1[i] = P[OFF_B1 + i];
+    sb2[i] = P[OFF_B2 + i];
+    sw3[i] = P[OFF_W3 + i];
+  }
+  const float b3 = P[OFF_B3];
+  __syncthreads();
+  float gW2[MLP_H];
+  for (int i = 0; i < MLP_H; i++) gW2[i] = 0.0f;
+  float gb2 = 0.0f, gw3 = 0.0f, gW1[3] = {0.0f, 0.0f, 0.0f}, gb1 = 0.0f, gb3 = 0.0f, lsum = 0.0f;
+  const float inv_n = 1.0f / (float)n;
+  int nchunk = (n + GW - 1) / GW;
+  for (int ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+    int s = ch * GW + l;
+    bool act = s < n;
+    float x[3] = {act ? X[3 * s] : 0.0f, act ? X[3 * s + 1] : 0.0f, act ? X[3 * s + 2] : 0.0f};
+    float h1[MLP_H], h2[MLP_H];
+    for (int u = 0; u < MLP_H; u++) {
+      float a = sb1[u] + sW1[u * 3] * x[0] + sW1[u * 3 + 1] * x[1] + sW1[u * 3 + 2] * x[2];
+      h1[u] = fmaxf(a, 0.0f);
+      sH1[u][l] = h1[u];
+    }
+    float y = b3;
+    for (int o = 0; o < MLP_H; o++) {
+      float a = sb2[o];
+      for (int u = 0; u < MLP_H; u++) a += sW2[o * MLP_H + u] * h1[u];
+      h2[o] = fmaxf(a, 0.0f);
+      sH2[o][l] = h2[o];
+      y += sw3[o] * h2[o];
+    }
+    float r = act ? y - t[s] : 0.0f;
+    lsum += r * r;
+    float dy = 2.0f * r * inv_n;
+    sDY[l] = dy;
+    for (int k = 0; k < 3; k++) sX[k][l] = x[k];
+    for (int o = 0; o < MLP_H; o++) {
+      h2[o] = (h2[o] > 0.0f) ? dy * sw3[o] : 0.0f;   // delta of layer 2
+      sD2[o][l] = h2[o];
+    }
+    for (int u = 0; u < MLP_H; u++) {
+      float a = 0.0f;
+      for (int o = 0; o < MLP_H; o++) a += sW2[o * MLP_H + u] * h2[o];
+      sD1[u][l] = (h1[u] > 0.0f) ? a : 0.0f;
+    }
+    __syncthreads();
+    // lane l now stands for hidden unit l
+    for (int ss = 0; ss < GW; ss++) {
+      float d2 = sD2[l][ss], d1 = sD1[l][ss], dys = sDY[ss];
+      for (int u = 0; u < MLP_H; u++) gW2[u] += d2 * sH1[u][ss];
+      gb2 += d2;
+      gw3 += dys * sH2[l][ss];
+      gW1[0] += d1 * sX[0][ss];
+      gW1[1] += d1 * sX[1][ss];
+      gW1[2] += d1 * sX[2][ss];
+      gb1 += d1;
+      gb3 += dys;
+    }
+    __syncthreads();
+  }
+  for (int u = 0; u < MLP_H; u++) atomicAdd(&grad[OFF_W2 + l * MLP_H + u], gW2[u]);
+  atomicAdd(&grad[OFF_B2 + l], gb2);
+  atomicAdd(&grad[OFF_W3 + l], gw3);
+  for (int k = 0; k < 3; k++) atomicAdd(&grad[OFF_W1 + l * 3 + k], gW1[k]);
+  atomicAdd(&grad[OFF_B1 + l], gb1);
+  if (l == 0) atomicAdd(&grad[OFF_B3], gb3);
+  for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
+  if (loss && l == 0) atomicAdd(loss, lsum * inv_n);
+}
+
+__global__ void k_fill0(float *a, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0.0f;
+}
+
+// Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 master parameters
+__global__ void k_adam(float *P, float *m, float *v, const float *g, float lr, float bc1, float bc2) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= MLP_NPARAM) return;
+  float gi = g[i];
+  float mi = 0.9f * m[i] + 0.1f * gi;
+  float vi = 0.999f * v[i] + 0.001f * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  P[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + 1e-8f);
+}
+
+// FP32 parameters -> device weight buffer (BF16 matrices, FP32 vectors);
+// scal (nullable): feature mean[3], std[3], target mean, std
+__global__ void k_mlp_pack(MlpDev *w, const float *P, const float *scal) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < MLP_H * 16) {
+    int u = i / 16, k = i % 16;
+    w->W1[i] = (k < 3) ? f2bf(P[OFF_W1 + u * 3 + k]) : (uint16_t)0;
+  }
+  if (i < MLP_H * MLP_H) w->W2[i] = f2bf(P[OFF_W2 + i]);
+  if (i < MLP_H) {
+    w->b1[i] = P[OFF_B1 + i];
+    w->b2[i] = P[OFF_B2 + i];
+    w->w3[i] = P[OFF_W3 + i];
+  }
+  if (i == 0) {
+    w->b3 = P[OFF_B3];
+    if (scal) {
+      for (int k = 0; k < 3; k++) {
+        w->xm[k] = scal[k];
+        w->xs[k] = scal[3 + k];
+      }
+      w->ym = scal[6];
+      w->ys = scal[7];
+    }
+  }
+}
+
+}  // namespace grhd
+
+using namespace grhd;
+
+extern "C" size_t grhd_mlp_bytes(void) { return sizeof(MlpDev); }
+
+extern "C" int grhd_mlp_pack(void *mlp, const float *params, const float *scal, void *hip_stream) {
+  if (!mlp || !params) return fail(GRHD_ERR_INVALID, "NULL argument");
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipLaunchKernelGGL(k_mlp_pack, dim3((MLP_H * MLP_H + 255) / 256), dim3(256), 0, st, (MlpDev *)mlp, params,
+                     scal);
+  return launch_status("mlp pack");
+}
+
+extern "C" int grhd_mlp_forward(const void *mlp, const float *X, float *y, int n, void *hip_stream) {
+  if (!mlp || !X || !y) return fail(GRHD_ERR_INVALID, "NULL argument");
+  if (n < 0) return fail(GRHD_ERR_INVALID, "n must be >= 0");
+  if (n == 0) return GRHD_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipLaunchKernelGGL(k_mlp_forward, dim3((n + 255) / 256), dim3(256), 0, st, (const MlpDev *)mlp, X, y, n);
+  return launch_status("mlp forward");
+}
+
+static int mlp_grad_launch(const float *params, float *grad, const float *X, const float *t, int n,
+                           float *loss, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill0, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, st, grad, MLP_NPARAM);
+  if (loss) hipLaunchKernelGGL(k_fill0, dim3(1), dim3(64), 0, st, loss, 1);
+  int nchunk = (n + GW - 1) / GW;
+  int blocks = nchunk < 512 ? nchunk : 512;
+  hipLaunchKernelGGL(k_mlp_grad, dim3(blocks), dim3(GW), 0, st, params, X, t, n, grad, loss);
+  return launch_status("mlp gradient");
+}
+
+extern "C" int grhd_mlp_grad(const float *params, float *grad, const float *X, const float *t, int n,
+                             float *loss, void *hip_stream) {
+  if (!params || !grad || !X || !t) return fail(GRHD_ERR_INVALID, "NULL argument");
+  if (n < 1) return fail(GRHD_ERR_INVALID, "n must be >= 1");
+  return mlp_grad_launch(params, grad, X, t, n, loss, (hipStream_t)hip_stream);
+}
+
+extern "C" int grhd_mlp_train_step(void *mlp, float *params, float *m, float *v, float *grad, const float *X,
+                                   const float *t, int n, float lr, int step, float *loss, void *hip_stream) {
+  if (!mlp || !params || !m || !v || !grad || !X || !t) return fail(GRHD_ERR_INVALID, "NULL argument");
+  if (n < 1 || step < 1 || !(lr > 0.0f)) return fail(GRHD_ERR_INVALID, "need n >= 1, step >= 1, lr > 0");
+  hipStream_t st = (hipStream_t)hip_stream;
+  int rc = mlp_grad_launch(params, grad, X, t, n, loss, st);
+  if (rc) return rc;
+  float bc1 = 1.0f - powf(0.9f, (float)step), bc2 = 1.0f - powf(0.999f, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, st, params, m, v, grad, lr, bc1, bc2);
+  if ((rc = launch_status("adam"))) return rc;
+  hipLaunchKernelGGL(k_mlp_pack, dim3((MLP_H * MLP_H + 255) / 256), dim3(256), 0, st, (MlpDev *)mlp, params,
+                     (const float *)nullptr);
+  return launch_status("mlp pack");
+}

@@ -8,6 +8,7 @@
 #pragma once
 
 #include "grhd_dev.hpp"
+#include "grhd_diag.hpp"
 
 namespace grhd {
 
@@ -30,12 +31,11 @@ template <class T, int MC, int TX, int TZ>
 struct TileSmem {
   static constexpr int HX = TX + 6, HZ = TZ + 6, NC = HX * HZ;
   static constexpr int NFX = (TX + 1) * TZ, NFZ = TX * (TZ + 1);
-  static constexpr int NF = NFX > NFZ ? NFX : NFZ;
+  static constexpr int NF = NFX + NFZ;  // x faces, then z faces
   static constexpr int NM = (MC == MC_CF) ? NC : 1;
   T p[6][NC];
   double ma[NM], mw[NM];
   T f[5][NF];
-  double red[3][NT / 64];
 };
 
 // Source cell of ghost cell (j, k) under the boundary conditions, with the
@@ -83,7 +83,8 @@ __device__ __forceinline__ double wave_max(double v) {
 
 template <class T, int MC, int TX, int TZ>
 __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int tx, int tz,
-                                             TileSmem<T, MC, TX, TZ> &sm, grhd_diag *diag) {
+                                             TileSmem<T, MC, TX, TZ> &sm, double &cmax_acc,
+                                             double &mb_acc, double &jm_acc) {
   using S = TileSmem<T, MC, TX, TZ>;
   constexpr int HX = S::HX, HZ = S::HZ;
   constexpr int CPT = (TX * TZ + NT - 1) / NT;
@@ -121,40 +122,67 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
 
   const int nb = 2 * nz + 2 * nx;  // flux-register stride
   double cmax = 0.0;
-  double divx[CPT][5];
 
-  // ---- 2. x faces: face x_{j-1/2}, j = j0 .. j0+TX
-  for (int f = tid; f < S::NFX; f += NT) {
-    int jj = f % (TX + 1), kk = f / (TX + 1);
-    int j = j0 + jj, k = k0 + kk;
+  // ---- 2. all faces of the tile in one balanced loop: x faces x_{j-1/2}
+  // (j = j0..j0+TX) first, then z faces z_{k-1/2} (k = k0..k0+TZ); the
+  // stencil is addressed by a base and a stride so x and z lanes of one
+  // wave run the same instructions.
+  for (int f = tid; f < S::NF; f += NT) {
+    const bool isx = f < S::NFX;
+    int jj, kk, base, stride;
+    if (isx) {
+      jj = f % (TX + 1); kk = f / (TX + 1);
+      base = (kk + 3) * HX + jj; stride = 1;
+    } else {
+      int h = f - S::NFX;
+      jj = h % TX; kk = h / TX;
+      base = kk * HX + jj + 3; stride = HX;
+    }
+    const int j = j0 + jj, k = k0 + kk;
+    const bool valid = isx ? (k < nz && j <= nx) : (j < nx && k <= nz);
     FluxT<T> out;
     for (int m = 0; m < 5; m++) out.f[m] = T(0);
-    if (k < nz && j <= nx) {
-      int base = (kk + 3) * HX + jj;
-      PrimT<T> L, R;
-      T s[6], a, b;
+    if (valid) {
+      // a stencil of six equal cells (quiescent atmosphere) has equal left
+      // and right states, and both solvers then return the flux of that
+      // state exactly: evaluate it directly
+      bool uni = true;
       for (int fld = 0; fld < 6; fld++) {
-        for (int i = 0; i < 6; i++) s[i] = sm.p[fld][base + i];
-        recon_face(P.recon, s, a, b);
-        if (fld == 0) { L.rho = a; R.rho = b; }
-        else if (fld < 4) { L.u[fld - 1] = a; R.u[fld - 1] = b; }
-        else if (fld == 4) { L.P = a; R.P = b; }
-        else { L.eps = a; R.eps = b; }
+        T c0 = sm.p[fld][base];
+        for (int i = 1; i < 6; i++) uni = uni && (sm.p[fld][base + i * stride] == c0);
+      }
+      PrimT<T> L, R;
+      if (uni) {
+        L.rho = sm.p[0][base];
+        L.u[0] = sm.p[1][base]; L.u[1] = sm.p[2][base]; L.u[2] = sm.p[3][base];
+        L.P = sm.p[4][base]; L.eps = sm.p[5][base];
+        R = L;
+      } else {
+        T s[6], a, b;
+        for (int fld = 0; fld < 6; fld++) {
+          for (int i = 0; i < 6; i++) s[i] = sm.p[fld][base + i * stride];
+          recon_face(P.recon, s, a, b);
+          if (fld == 0) { L.rho = a; R.rho = b; }
+          else if (fld < 4) { L.u[fld - 1] = a; R.u[fld - 1] = b; }
+          else if (fld == 4) { L.P = a; R.P = b; }
+          else { L.eps = a; R.eps = b; }
+        }
       }
       FaceMet<T> fm;
+      T t6[6];
       if (MC == MC_CF) {
-        T t6[6];
-        for (int i = 0; i < 6; i++) t6[i] = (T)sm.ma[base + i];
+        for (int i = 0; i < 6; i++) t6[i] = (T)sm.ma[base + i * stride];
         fm.alp = lagrange6(t6);
-        for (int i = 0; i < 6; i++) t6[i] = (T)sm.mw[base + i];
+        for (int i = 0; i < 6; i++) t6[i] = (T)sm.mw[base + i * stride];
         fm.W = lagrange6(t6);
       } else {
-        T t6[6];
+        long long g0 = isx ? cell_index(g, j - 3, k) : cell_index(g, j, k - 3);
+        long long gs = isx ? 1 : g.pitch;
         for (int fld = 0; fld < 11; fld++) {
           const double *src = P.m.f[fld];
           T v;
           if (src) {
-            for (int i = 0; i < 6; i++) t6[i] = (T)src[cell_index(g, j - 3 + i, k)];
+            for (int i = 0; i < 6; i++) t6[i] = (T)src[g0 + i * gs];
             v = lagrange6(t6);
           } else {
             v = (T)P.m.c[fld];
@@ -165,101 +193,21 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
           else fm.gt[fld - 5] = v;
         }
       }
-      face_flux<T, MC>(e, fm, 0, P.riemann, L, R, out);
-      cmax = fmax(cmax, (double)out.speed * (P.dt / g.dx));
-      if (P.flux_reg && (j == 0 || j == nx)) {
-        int o = (j == 0) ? k : nz + k;
-        double xf = g.x0 + j * g.dx;
-        double fv[5] = {(double)out.f[0], (double)out.f[1], (double)out.f[2], (double)out.f[3],
-                        (double)out.f[0] + (double)out.f[4]};
-        if (cyl) fv[2] *= xf;
-        for (int m = 0; m < 5; m++) P.flux_reg[m * nb + o] = fv[m];
-      }
-    }
-    for (int m = 0; m < 5; m++) sm.f[m][f] = out.f[m];
-  }
-  __syncthreads();
-
-  // ---- 3. x divergence per owned cell (area weighted in cylindrical)
-#pragma unroll
-  for (int ci = 0; ci < CPT; ci++) {
-    int c = tid + ci * NT;
-    int jj = c % TX, kk = c / TX;
-    int j = j0 + jj;
-    for (int m = 0; m < 5; m++) divx[ci][m] = 0.0;
-    if (c < TX * TZ && j < nx && k0 + kk < nz) {
-      int fl = kk * (TX + 1) + jj, fr = fl + 1;
-      double xl = g.x0 + j * g.dx, xr = g.x0 + (j + 1) * g.dx, xc = g.x0 + (j + 0.5) * g.dx;
-      for (int m = 0; m < 5; m++) {
-        double Fl, Fr;
-        if (m == 4) {
-          Fl = (double)sm.f[0][fl] + (double)sm.f[4][fl];
-          Fr = (double)sm.f[0][fr] + (double)sm.f[4][fr];
-        } else {
-          Fl = (double)sm.f[m][fl];
-          Fr = (double)sm.f[m][fr];
-        }
-        if (cyl) {
-          if (m == 2) { Fl *= xl; Fr *= xr; }
-          divx[ci][m] = (xr * Fr - xl * Fl) / (xc * g.dx);
-        } else {
-          divx[ci][m] = (Fr - Fl) / g.dx;
-        }
-      }
-    }
-  }
-  __syncthreads();
-
-  // ---- 4. z faces: face z_{k-1/2}, k = k0 .. k0+TZ
-  for (int f = tid; f < S::NFZ; f += NT) {
-    int jj = f % TX, kk = f / TX;
-    int j = j0 + jj, k = k0 + kk;
-    FluxT<T> out;
-    for (int m = 0; m < 5; m++) out.f[m] = T(0);
-    if (j < nx && k <= nz) {
-      int col = jj + 3;
-      PrimT<T> L, R;
-      T s[6], a, b;
-      for (int fld = 0; fld < 6; fld++) {
-        for (int i = 0; i < 6; i++) s[i] = sm.p[fld][(kk + i) * HX + col];
-        recon_face(P.recon, s, a, b);
-        if (fld == 0) { L.rho = a; R.rho = b; }
-        else if (fld < 4) { L.u[fld - 1] = a; R.u[fld - 1] = b; }
-        else if (fld == 4) { L.P = a; R.P = b; }
-        else { L.eps = a; R.eps = b; }
-      }
-      FaceMet<T> fm;
-      if (MC == MC_CF) {
-        T t6[6];
-        for (int i = 0; i < 6; i++) t6[i] = (T)sm.ma[(kk + i) * HX + col];
-        fm.alp = lagrange6(t6);
-        for (int i = 0; i < 6; i++) t6[i] = (T)sm.mw[(kk + i) * HX + col];
-        fm.W = lagrange6(t6);
+      if (uni) {
+        T Q[5], lm, lp, gtu[6];
+        if (MC == MC_GEN) inv_sym3(fm.gt, gtu);
+        valencia<T, MC>(e, fm, gtu, isx ? 0 : 2, L, out.f, Q, lm, lp);
+        out.speed = fmax(fabs(lm), fabs(lp));
       } else {
-        T t6[6];
-        for (int fld = 0; fld < 11; fld++) {
-          const double *src = P.m.f[fld];
-          T v;
-          if (src) {
-            for (int i = 0; i < 6; i++) t6[i] = (T)src[cell_index(g, j, k - 3 + i)];
-            v = lagrange6(t6);
-          } else {
-            v = (T)P.m.c[fld];
-          }
-          if (fld == 0) fm.alp = v;
-          else if (fld < 4) fm.beta[fld - 1] = v;
-          else if (fld == 4) fm.W = v;
-          else fm.gt[fld - 5] = v;
-        }
+        face_flux<T, MC>(e, fm, isx ? 0 : 1, P.riemann, L, R, out);
       }
-      face_flux<T, MC>(e, fm, 1, P.riemann, L, R, out);
-      cmax = fmax(cmax, (double)out.speed * (P.dt / g.dz));
-      if (P.flux_reg && (k == 0 || k == nz)) {
-        int o = 2 * nz + ((k == 0) ? j : nx + j);
-        double xc = g.x0 + (j + 0.5) * g.dx;
+      cmax = fmax(cmax, (double)out.speed * (P.dt / (isx ? g.dx : g.dz)));
+      if (P.flux_reg && (isx ? (j == 0 || j == nx) : (k == 0 || k == nz))) {
+        int o = isx ? ((j == 0) ? k : nz + k) : 2 * nz + ((k == 0) ? j : nx + j);
+        double xx = isx ? g.x0 + j * g.dx : g.x0 + (j + 0.5) * g.dx;
         double fv[5] = {(double)out.f[0], (double)out.f[1], (double)out.f[2], (double)out.f[3],
                         (double)out.f[0] + (double)out.f[4]};
-        if (cyl) fv[2] *= xc;
+        if (cyl) fv[2] *= xx;
         for (int m = 0; m < 5; m++) P.flux_reg[m * nb + o] = fv[m];
       }
     }
@@ -272,13 +220,35 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
   const double i60dx = 1.0 / (60.0 * g.dx), i60dz = 1.0 / (60.0 * g.dz);
 #pragma unroll
   for (int ci = 0; ci < CPT; ci++) {
+    // per-cell arithmetic evaluated without contraction, so that every
+    // compiled instance (single patch, batch) rounds identically
+#pragma clang fp contract(off)
     int c = tid + ci * NT;
     int jj = c % TX, kk = c / TX;
     int j = j0 + jj, k = k0 + kk;
     if (!(c < TX * TZ && j < nx && k < nz)) continue;
     double xc = g.x0 + (j + 0.5) * g.dx;
-    int fb = kk * TX + jj, ft = fb + TX;
-    double divz[5];
+    const double xl = g.x0 + j * g.dx, xr = g.x0 + (j + 1) * g.dx;
+    const int fl = kk * (TX + 1) + jj, fr = fl + 1;
+    const int fb = S::NFX + kk * TX + jj, ft = fb + TX;
+    double divx[5], divz[5];
+    const double ivx = cyl ? 1.0 / (xc * g.dx) : 1.0 / g.dx, ivz = 1.0 / g.dz;
+    for (int m = 0; m < 5; m++) {
+      double Fl, Fr;
+      if (m == 4) {
+        Fl = (double)sm.f[0][fl] + (double)sm.f[4][fl];
+        Fr = (double)sm.f[0][fr] + (double)sm.f[4][fr];
+      } else {
+        Fl = (double)sm.f[m][fl];
+        Fr = (double)sm.f[m][fr];
+      }
+      if (cyl) {
+        if (m == 2) { Fl *= xl; Fr *= xr; }
+        divx[m] = (xr * Fr - xl * Fl) * ivx;
+      } else {
+        divx[m] = (Fr - Fl) * ivx;
+      }
+    }
     for (int m = 0; m < 5; m++) {
       double Fb, Ft;
       if (m == 4) {
@@ -289,7 +259,7 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
         Ft = (double)sm.f[m][ft];
       }
       if (cyl && m == 2) { Fb *= xc; Ft *= xc; }
-      divz[m] = (Ft - Fb) / g.dz;
+      divz[m] = (Ft - Fb) * ivz;
     }
     // metric at the cell and its x, z derivatives
     long long ic = cell_index(g, j, k);
@@ -330,7 +300,7 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
     sources<MC>(gm, dg, xc, g.geom, pc, s);
     double dV = cyl ? 2.0 * M_PI * xc * g.dx * g.dz : g.dx * g.dz;
     for (int m = 0; m < 5; m++) {
-      double L = s[m] - divx[ci][m] - divz[m];
+      double L = s[m] - divx[m] - divz[m];
       double v = P.b * P.qs[m][ic] + P.cdt * L;
       if (P.use_qn) v += P.a * P.qn[m][ic];
       if (P.use_acc_in) v += P.gdt * P.acc_in[m][ic];
@@ -345,30 +315,9 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
     }
   }
 
-  // ---- 6. workgroup reductions of the diagnostics
-  if (diag) {
-    cmax = wave_max(cmax);
-    mb = wave_sum(mb);
-    jm = wave_sum(jm);
-    int wv = tid >> 6;
-    if ((tid & 63) == 0) {
-      sm.red[0][wv] = cmax;
-      sm.red[1][wv] = mb;
-      sm.red[2][wv] = jm;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double c = sm.red[0][0], s1 = sm.red[1][0], s2 = sm.red[2][0];
-      for (int w = 1; w < NT / 64; w++) {
-        c = fmax(c, sm.red[0][w]);
-        s1 += sm.red[1][w];
-        s2 += sm.red[2][w];
-      }
-      atomicMax((unsigned long long *)&diag->max_courant, (unsigned long long)__double_as_longlong(c));
-      unsafeAtomicAdd(&diag->Mb, s1);
-      unsafeAtomicAdd(&diag->J, s2);
-    }
-  }
+  cmax_acc = fmax(cmax_acc, cmax);
+  mb_acc += mb;
+  jm_acc += jm;
 }
 
 }  // namespace grhd

@@ -82,7 +82,8 @@ class Stage(C.Structure):
 class Diag(C.Structure):
     _fields_ = [("max_courant", C.c_double), ("Mb", C.c_double), ("J", C.c_double),
                 ("n_rescale", C.c_ulonglong), ("n_cold", C.c_ulonglong),
-                ("n_atm", C.c_ulonglong), ("n_fail", C.c_ulonglong)]
+                ("n_atm", C.c_ulonglong), ("n_fail", C.c_ulonglong),
+                ("iter_sum", C.c_ulonglong), ("iter_max", C.c_ulonglong)]
 
 
 class Patch(C.Structure):
@@ -231,7 +232,7 @@ def make_options(o):
 
 
 def new_diag(device="cuda"):
-    return torch.zeros(8, dtype=torch.float64, device=device)  # 64 bytes
+    return torch.zeros(16, dtype=torch.float64, device=device)  # >= sizeof(grhd_diag)
 
 
 def read_diag(t):
@@ -321,3 +322,158 @@ def rk_substep(grid, eos, metric, opts, stage, qn, qs, qout, p, **kw):
 
 SSPRK3 = [dict(a=0.0, b=1.0, c=1.0), dict(a=0.75, b=0.25, c=0.25),
           dict(a=1.0 / 3.0, b=2.0 / 3.0, c=2.0 / 3.0)]
+
+
+# ------------------------------------------------------------ batched path
+
+def make_patch(d):
+    """d: dict(grid, metric, qn, qs, qout, p, stage, eos_id[, flux_reg])."""
+    s = Patch()
+    s.grid = make_grid(d["grid"])
+    s.metric = make_metric(d["metric"])
+    s.qn = make_cons(d["qn"] if d.get("qn") is not None else d["qs"])
+    s.qs = make_cons(d["qs"])
+    s.qout = make_cons(d["qout"])
+    s.p = make_prim(d["p"])
+    s.stage = make_stage(d["stage"])
+    s.eos_id = d.get("eos_id", 0)
+    fr = d.get("flux_reg")
+    s.flux_reg = fr.data_ptr() if fr is not None else None
+    return s
+
+
+class Plan:
+    """A grhd_plan: one graph-captured persistent substep over many patches.
+    Creating it may run the batch on the given buffers to time candidate
+    tile shapes (q_s corrected in place, q_out overwritten)."""
+
+    def __init__(self, patches, eos_table, opts, tune_cache=None):
+        lib()
+        self.n = len(patches)
+        arr = (Patch * self.n)(*[make_patch(d) for d in patches])
+        eos_arr = (Eos * len(eos_table))(*[make_eos(e) for e in eos_table])
+        self._opts = make_options(opts)
+        self.handle = C.c_void_p()
+        rc = lib().grhd_plan_create(arr, self.n, eos_arr, len(eos_table), C.byref(self._opts),
+                                    tune_cache.encode() if tune_cache else None,
+                                    C.byref(self.handle))
+        _check(rc, "grhd_plan_create")
+
+    def __call__(self, patches, diag=None, stream=None):
+        arr = (Patch * self.n)(*[make_patch(d) for d in patches])
+        rc = lib().grhd_batch_levels(self.handle, arr, self.n,
+                                     C.c_void_p(diag.data_ptr() if diag is not None else 0),
+                                     C.c_void_p(stream) if stream is not None else _stream())
+        _check(rc, "grhd_batch_levels")
+
+    def tiles(self):
+        tx = (C.c_int * 2)()
+        tz = (C.c_int * 2)()
+        _check(lib().grhd_plan_tile(self.handle, tx, tz), "grhd_plan_tile")
+        return dict(square=(tx[0], tz[0]), thin=(tx[1], tz[1]))
+
+    def close(self):
+        if self.handle:
+            lib().grhd_plan_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ learned guess
+
+NPARAM_MLP = 4481
+
+
+def _fptr(t):
+    assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+    return C.c_void_p(t.data_ptr())
+
+
+def _mlp_sigs():
+    L = lib()
+    if getattr(L, "_mlp_sig", False):
+        return L
+    p, i, f = C.c_void_p, C.c_int, C.c_float
+    L.grhd_mlp_bytes.restype = C.c_size_t
+    L.grhd_mlp_bytes.argtypes = []
+    for name, args in {"grhd_mlp_pack": [p, p, p, p],
+                       "grhd_mlp_forward": [p, p, p, i, p],
+                       "grhd_mlp_grad": [p, p, p, p, i, p, p],
+                       "grhd_mlp_train_step": [p, p, p, p, p, p, p, i, f, i, p, p]}.items():
+        fn = getattr(L, name)
+        fn.restype = C.c_int
+        fn.argtypes = args
+    L._mlp_sig = True
+    return L
+
+
+class MLP:
+    """Device weight buffer of the learned recovery guess plus its FP32
+    master parameters and Adam state.  scal: feature mean[3], std[3],
+    target mean, std (float32 device tensor of 8)."""
+
+    def __init__(self, params, scal):
+        L = _mlp_sigs()
+        dev = params.device
+        self.buf = torch.zeros(int(L.grhd_mlp_bytes()), dtype=torch.uint8, device=dev)
+        self.params = params.contiguous()
+        self.scal = scal.contiguous()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.step_no = 0
+        self.pack()
+
+    def pack(self):
+        _check(_mlp_sigs().grhd_mlp_pack(C.c_void_p(self.buf.data_ptr()), _fptr(self.params),
+                                         _fptr(self.scal), _stream()), "grhd_mlp_pack")
+
+    def forward(self, X):
+        y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        _check(_mlp_sigs().grhd_mlp_forward(C.c_void_p(self.buf.data_ptr()), _fptr(X), _fptr(y),
+                                            X.shape[0], _stream()), "grhd_mlp_forward")
+        return y
+
+    def train_step(self, X, t, lr):
+        self.step_no += 1
+        _check(_mlp_sigs().grhd_mlp_train_step(
+            C.c_void_p(self.buf.data_ptr()), _fptr(self.params), _fptr(self.m), _fptr(self.v),
+            _fptr(self.grad), _fptr(X), _fptr(t), X.shape[0], C.c_float(lr), self.step_no,
+            _fptr(self.loss), _stream()), "grhd_mlp_train_step")
+        return self.loss
+
+
+def mlp_grad(params, X, t):
+    grad = torch.empty_like(params)
+    loss = torch.zeros(1, dtype=torch.float32, device=params.device)
+    _check(_mlp_sigs().grhd_mlp_grad(_fptr(params), _fptr(grad), _fptr(X), _fptr(t), X.shape[0],
+                                     _fptr(loss), _stream()), "grhd_mlp_grad")
+    return grad, loss
+
+
+def mlp_init(seed, device="cuda"):
+    """He-initialised FP32 parameter vector (W1[64][3], b1, W2[64][64], b2, w3, b3)."""
+    g = torch.Generator().manual_seed(seed)
+    P = torch.zeros(NPARAM_MLP, dtype=torch.float32)
+    P[0:192] = torch.randn(192, generator=g) * (2.0 / 3.0) ** 0.5
+    P[256:4352] = torch.randn(4096, generator=g) * (2.0 / 64.0) ** 0.5
+    P[4416:4480] = torch.randn(64, generator=g) * (1.0 / 64.0) ** 0.5
+    return P.to(device)
+
+
+def recovery_features(q, W=None, x=None, geom="cart"):
+    """Features (log10 D, S/E, log10(tau/D)) and the masks of usable cells
+    from densitised conserved variables of a flat metric (q: 5 x n torch
+    float64).  Matches the in-kernel feature definition."""
+    D, E = q[0], q[4]
+    Sy = q[2] / x if (geom == "cyl" and x is not None) else q[2]
+    S = torch.sqrt(q[1] ** 2 + Sy ** 2 + q[3] ** 2)
+    tau = E - D
+    X = torch.stack([torch.log10(D), S / E, torch.log10(tau / D)], dim=1)
+    return X

@@ -1,0 +1,106 @@
+"""GPU: the batched persistent substep (grhd_plan_create / grhd_batch_levels)
+equals the single-patch substep bit for bit on every patch (the per-cell
+arithmetic does not depend on the tiling or on the launch), over a mixture
+of nested star levels and uneven Riemann instances, for several calls in a
+row with changing stages and buffers (graph replays with host work and
+synchronisation in between)."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2502_03223_amd import grhd  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def build_patches(orc, nlev=3, n=48, nriem=6, seed=5):
+    tov = synth.tov_solve()
+    patches = []
+    for lvl, grid in enumerate(synth.fmr_levels(nlev, n, finest_extent=20.0)):
+        p, metric, eos = synth.star_problem(grid, seed=seed + lvl, tov=tov, vel=0.03)
+        q = orc.prim2con(grid, eos, metric, p, with_ghosts=True)
+        patches.append(dict(grid=grid, metric={k: dev(v) for k, v in metric.items()},
+                            q0=q, eos_id=0))
+    gam = 5.0 / 3.0
+    sizes = synth.riemann_patch_sizes(seed, nriem, lo=40, hi=300)
+    for i, (nxr, (L, R)) in enumerate(zip(sizes, synth.riemann_states(seed, nriem, gam))):
+        grid = synth.riemann_grid(nxr, nz=8)
+        p = synth.riemann_prims(grid, L, R, gam)
+        q = orc.prim2con(grid, synth.ideal_eos(gam), {}, p, with_ghosts=True)
+        patches.append(dict(grid=grid, metric={}, q0=q, eos_id=1))
+    eos_table = [synth.ideal_eos(2.0, 100.0), synth.ideal_eos(gam)]
+    return patches, eos_table
+
+
+def alloc(pt):
+    q = dev(pt["q0"])
+    return dict(q=q, q1=torch.zeros_like(q), p=torch.zeros((6,) + q.shape[1:], dtype=torch.float64, device=DEV))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_equals_single_patch(orc, prec):
+    patches, eos_table = build_patches(orc)
+    opts = dict(recon="ppm", riemann="hllc", prec=prec, c2p=dict(w_max=100.0, rho_atm=1e-10))
+    A = [alloc(pt) for pt in patches]     # batched
+    B = [alloc(pt) for pt in patches]     # one call per patch
+
+    def descr(buf, pt, st):
+        dt = 0.4 * pt["grid"]["dx"]
+        return dict(grid=pt["grid"], metric=pt["metric"], qn=buf["q"], qs=buf["q"], qout=buf["q1"],
+                    p=buf["p"], stage=dict(st, dt=dt), eos_id=pt["eos_id"])
+
+    plan = grhd.Plan([descr(a, pt, grhd.SSPRK3[0]) for a, pt in zip(A, patches)], eos_table, opts)
+    subs = [grhd.Substep(pt["grid"], eos_table[pt["eos_id"]], pt["metric"], opts) for pt in patches]
+    # plan creation may have run the batch (tuning): start both from q0
+    for a, b, pt in zip(A, B, patches):
+        a["q"].copy_(dev(pt["q0"]))
+        b["q"].copy_(dev(pt["q0"]))
+    diag = grhd.new_diag()
+    for call in range(4):
+        st = grhd.SSPRK3[0]  # q1 = q + dt L(q), then swap: repeated forward stages
+        plan([descr(a, pt, st) for a, pt in zip(A, patches)], diag=diag)
+        for b, pt, sub in zip(B, patches, subs):
+            sub(dict(st, dt=0.4 * pt["grid"]["dx"]), b["q"], b["q"], b["q1"], b["p"])
+        torch.cuda.synchronize()
+        for a, b, pt in zip(A, B, patches):
+            g = pt["grid"]
+            for key in ("q1", "q", "p"):
+                x = synth.interior(g, a[key].cpu().numpy())
+                y = synth.interior(g, b[key].cpu().numpy())
+                assert np.array_equal(x, y), (call, key, g["nx"], g["nz"])
+            a["q"], a["q1"] = a["q1"], a["q"]
+            b["q"], b["q1"] = b["q1"], b["q"]
+        d = grhd.read_diag(diag)
+        assert d["n_atm"] > 0 and d["Mb"] > 0.0
+    t = plan.tiles()
+    assert t["thin"][1] == 8
+    plan.close()
+
+
+def test_batch_tune_cache_roundtrip(orc, tmp_path):
+    patches, eos_table = build_patches(orc, nlev=2, n=32, nriem=3)
+    opts = dict(recon="ppm", riemann="hllc", prec="fp64", c2p=dict(w_max=100.0, rho_atm=1e-10))
+    bufs = [alloc(pt) for pt in patches]
+    desc = [dict(grid=pt["grid"], metric=pt["metric"], qn=b["q"], qs=b["q"], qout=b["q1"], p=b["p"],
+                 stage=dict(grhd.SSPRK3[0], dt=0.01), eos_id=pt["eos_id"]) for b, pt in zip(bufs, patches)]
+    cache = str(tmp_path / "tune.txt")
+    p1 = grhd.Plan(desc, eos_table, opts, tune_cache=cache)
+    t1 = p1.tiles()
+    p1.close()
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and "gfx" in lines[0]
+    p2 = grhd.Plan(desc, eos_table, opts, tune_cache=cache)
+    assert p2.tiles() == t1
+    assert len(open(cache).read().splitlines()) == 1   # found, not re-measured
+    p2.close()

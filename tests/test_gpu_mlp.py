@@ -1,0 +1,137 @@
+"""GPU: the learned recovery guess.
+
+- the matrix-core forward pass equals the oracle's FP64 forward pass with
+  the same BF16-rounded weights, to BF16 activation rounding;
+- the training gradient (FP32, BF16-rounded weights) equals the oracle's
+  FP64 back-propagation with the same weights (per tensor, normwise 1e-4);
+- training on (D, S, tau) -> P pairs that the oracle generates lowers the
+  loss, and the recovery seeded by the trained network reaches the same
+  root as the paper's Illinois recovery and as the oracle's bisection
+  (1e-12 normwise on the primitives) with fewer master-function
+  evaluations on the differentially rotating workload.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2502_03223_amd import grhd  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def bf16_round(a):
+    t = torch.from_numpy(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).to(torch.float32)
+    return t.numpy().astype(np.float64)
+
+
+def rounded_params(P):
+    """FP64 copy of an FP32 parameter vector with W1 and W2 rounded to BF16
+    (the matrices the GPU uses)."""
+    Q = P.astype(np.float64).copy()
+    Q[0:192] = bf16_round(P[0:192])
+    Q[256:4352] = bf16_round(P[256:4352])
+    return Q
+
+
+def test_forward_matches_oracle(orc):
+    P = grhd.mlp_init(3)
+    scal = torch.tensor([0, 0, 0, 1, 1, 1, 0, 1], dtype=torch.float32, device=DEV)
+    net = grhd.MLP(P, scal)
+    rng = np.random.default_rng(0)
+    X = rng.normal(size=(1000, 3)).astype(np.float32)
+    y = net.forward(torch.from_numpy(X).to(DEV)).cpu().numpy()
+    ref = orc.mlp_forward(rounded_params(P.cpu().numpy()), bf16_round(X))
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    assert err <= 2e-2, err
+    assert np.corrcoef(y, ref)[0, 1] > 0.9999
+
+
+def test_gradient_matches_oracle(orc):
+    P = grhd.mlp_init(4)
+    rng = np.random.default_rng(1)
+    n = 777  # several chunks and a ragged tail
+    X = rng.normal(size=(n, 3)).astype(np.float32)
+    t = rng.normal(size=n).astype(np.float32)
+    g, loss = grhd.mlp_grad(P, torch.from_numpy(X).to(DEV), torch.from_numpy(t).to(DEV))
+    g = g.cpu().numpy()
+    lo, go = orc.mlp_loss_grad(rounded_params(P.cpu().numpy()), X.astype(np.float64), t.astype(np.float64))
+    assert float(loss.cpu()[0]) == pytest.approx(lo, rel=1e-4)
+    for a, b in [(0, 192), (192, 256), (256, 4352), (4352, 4416), (4416, 4480), (4480, 4481)]:
+        err = np.abs(g[a:b] - go[a:b]).max() / np.abs(go[a:b]).max()
+        assert err <= 1e-4, (a, b, err)
+
+
+def training_pairs(orc, seed, n):
+    """(D, S, tau) -> P pairs from the oracle's prim->con on seeded states."""
+    prims = synth.recovery_samples(seed, n)
+    grid = synth.make_grid(n, 1, 0.0, 0.0, 1.0, 1.0, "cart", ("outflow",) * 4)
+    p = synth.empty_fields(grid, 6)
+    synth.interior(grid, p)[:, 0, :] = prims.T
+    q = orc.prim2con(grid, synth.ideal_eos(2.0, 100.0), {}, p)
+    qi = synth.interior(grid, q)[:, 0, :]
+    D, E = qi[0], qi[4]
+    S = np.sqrt(qi[1] ** 2 + qi[2] ** 2 + qi[3] ** 2)
+    X = np.stack([np.log10(D), S / E, np.log10((E - D) / D)], axis=1)
+    y = np.log10(prims[:, 4] / D)
+    return X, y
+
+
+def train(orc, n=200_000, epochs=8, batch=8192, seed=11):
+    X, y = training_pairs(orc, seed, n)
+    xm, xs = X.mean(axis=0), X.std(axis=0)
+    ym, ys = y.mean(), y.std()
+    scal = torch.tensor(list(xm) + list(xs) + [ym, ys], dtype=torch.float32, device=DEV)
+    Xs = torch.from_numpy(((X - xm) / xs).astype(np.float32)).to(DEV)
+    ts = torch.from_numpy(((y - ym) / ys).astype(np.float32)).to(DEV)
+    net = grhd.MLP(grhd.mlp_init(seed), scal)
+    g = torch.Generator(device=DEV).manual_seed(seed)
+    losses = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g, device=DEV)
+        lr = 3e-3 * (0.5 ** (ep // 3))
+        for b in range(0, n, batch):
+            idx = perm[b:b + batch]
+            net.train_step(Xs[idx].contiguous(), ts[idx].contiguous(), lr)
+        losses.append(float(net.loss.cpu()[0]))
+    return net, losses
+
+
+def test_training_and_gain(orc):
+    net, losses = train(orc)
+    assert losses[-1] < 0.05 * losses[0] and losses[-1] < 1e-2, losses
+    # recovery on the rotating workload (flat metric), three ways
+    grid = synth.make_grid(256, 64, 0.0, 0.0, 20.0 / 256, 20.0 / 256, "cart",
+                           ("outflow", "outflow", "outflow", "outflow"))
+    p = synth.rotating_field(grid, 7)
+    eos = synth.ideal_eos(2.0, 100.0)
+    q = orc.prim2con(grid, eos, {}, p)
+    c2p = dict(w_max=100.0, rho_atm=1e-12)
+    p_o, _, fl_o, _ = orc.con2prim(grid, eos, {}, c2p, q)
+    res = {}
+    for name, mlp in (("illinois", None), ("mlp", net.buf)):
+        qg = torch.from_numpy(q).to(DEV)
+        pg = torch.zeros((6,) + q.shape[1:], dtype=torch.float64, device=DEV)
+        fl = torch.zeros(q.shape[1:], dtype=torch.uint8, device=DEV)
+        dg = grhd.new_diag()
+        grhd.con2prim(grid, eos, {}, dict(c2p, mlp=mlp), qg, pg, flags=fl, diag=dg)
+        torch.cuda.synchronize()
+        res[name] = (synth.interior(grid, pg.cpu().numpy()), grhd.read_diag(dg),
+                     synth.interior(grid, fl.cpu().numpy()))
+    ref = synth.interior(grid, p_o)
+    for name, (pp, d, fl) in res.items():
+        assert np.array_equal(fl, synth.interior(grid, fl_o)), name
+        for c in range(6):
+            scale = np.abs(ref[c]).max()
+            assert np.abs(pp[c] - ref[c]).max() <= 1e-12 * scale, (name, c)
+    it_ill = res["illinois"][1]["iter_sum"]
+    it_mlp = res["mlp"][1]["iter_sum"]
+    assert it_mlp < it_ill, (it_mlp, it_ill)

@@ -36,17 +36,28 @@ def mdev(metric):
     return {k: dev(v) if isinstance(v, np.ndarray) else v for k, v in metric.items()}
 
 
+class Err(float):
+    """A normwise error that also remembers where it is largest."""
+    where = ""
+
+    def __repr__(self):
+        return "%.3e at %s" % (float(self), self.where)
+
+
 def normwise(g, o, comps=None):
     comps = range(g.shape[0]) if comps is None else comps
-    worst = 0.0
+    worst, where = 0.0, ""
     for c in comps:
         scale = np.abs(o[c]).max()
-        if scale == 0.0:
-            err = np.abs(g[c]).max()
-        else:
-            err = np.abs(g[c] - o[c]).max() / scale
-        worst = max(worst, err)
-    return worst
+        d = np.abs(g[c] - o[c])
+        err = d.max() if scale == 0.0 else d.max() / scale
+        if err > worst or not where:
+            idx = np.unravel_index(np.argmax(d), d.shape)
+            worst, where = err, "field %d index %s (gpu %r, oracle %r)" % (
+                c, tuple(int(i) for i in idx), float(g[c][idx]), float(o[c][idx]))
+    e = Err(worst)
+    e.where = where
+    return e
 
 
 @pytest.fixture(scope="module")
@@ -185,12 +196,12 @@ def run_pair(orc, grid, eos, metric, opts, stage, qn, qs, acc_in=None, want_acc=
     return ref, out
 
 
-def check_pair(grid, ref, out, tol=TOL):
+def check_pair(grid, ref, out, tol=TOL, flag_mask=0xFF):
     I = lambda a: synth.interior(grid, a)  # noqa: E731
     assert normwise(I(out["qout"]), I(ref["qout"])) <= tol
     assert normwise(I(out["qs"]), I(ref["qs"])) <= tol
     assert normwise(I(out["p"]), I(ref["p"])) <= tol
-    assert np.array_equal(I(out["flags"]), I(ref["flags"]))
+    assert np.array_equal(I(out["flags"]) & flag_mask, I(ref["flags"]) & flag_mask)
     # boundary fluxes: one scale for all components (the mass flux through
     # the axis and through a static atmosphere is rounding noise)
     fr, fo = out["flux_reg"], ref["flux_reg"]
@@ -235,7 +246,15 @@ def test_substep_riemann(orc, seed, riemann, recon):
 
 
 def test_paper_shock_tube_substeps(orc):
-    """The paper's problem (P_R = 0, cold fallback cells) at N = 800."""
+    """The paper's problem at N = 800.  Its right state has P = 0 exactly:
+    in the cells the shock is entering, whether the recovered specific
+    energy is a rounding-level positive number or is clamped to the cold
+    value (P = 0) is decided by rounding, and the sound speed
+    c_s = sqrt(Gamma P / (rho h)) turns a pressure of order 1e-16 into a
+    wave speed of order 1e-8; the local fluxes then differ at the 1e-6
+    relative level, i.e. ~1e-11 against the largest state.  The bar for this
+    degenerate state is 1e-9 normwise and the cold-recovery flag may differ;
+    every other flag and every non-degenerate case keep 1e-12."""
     gam = 5.0 / 3.0
     L, R = synth.PAPER_SHOCK_TUBE
     grid = synth.riemann_grid(800, nz=1)
@@ -246,7 +265,7 @@ def test_paper_shock_tube_substeps(orc):
     for i in range(6):
         st = grhd.SSPRK3[i % 3]
         ref, out = run_pair(orc, grid, eos, {}, opts, dict(st, dt=dt), q, q)
-        check_pair(grid, ref, out)
+        check_pair(grid, ref, out, tol=1e-9, flag_mask=0xFF & ~2)
         q = ref["qout"]
 
 
