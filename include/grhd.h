@@ -113,6 +113,12 @@ typedef struct {
   int recon, riemann, prec;   /* GRHD_RECON_*, GRHD_RIEMANN_*, GRHD_PREC_* */
   grhd_c2p_params c2p;
   int tile_x, tile_z;         /* 0, 0 = library default */
+  void *ev_begin, *ev_end;    /* optional events from grhd_event_create,
+                                 recorded on the stream right before and
+                                 right after the fused stage kernel of
+                                 grhd_rk_substep, so that kernel can be timed
+                                 alone; NULL = not recorded (ignored by the
+                                 batched plan) */
 } grhd_options;
 
 /* One Runge-Kutta stage:
@@ -223,39 +229,69 @@ int grhd_batch_levels(grhd_plan *plan, const grhd_patch *patches, int npatch,
 
 int grhd_plan_destroy(grhd_plan *plan);
 
-/* Tile shape used by a plan (for reporting). */
+/* Tile shapes chosen for a plan (for reporting): tile_x[0], tile_z[0] =
+ * square-ish patches, tile_x[1], tile_z[1] = thin patches (nz <= 8);
+ * both arrays hold 2 ints. */
 int grhd_plan_tile(const grhd_plan *plan, int *tile_x, int *tile_z);
 
 /* ---------------------------------------------------------- learned guess */
 
-/* MLP 3 -> 64 -> 64 -> 1 (ReLU) giving the initial pressure guess of the
- * recovery.  Device weight buffer layout (bytes, 256-aligned blocks):
- * see GRHD_MLP_* below.  Features: (log10 D, S/(D + tau), log10(tau/D))
- * standardised by (mean, std) in the buffer; output log10(P/D) scaled by
- * (mean, std).  X: n x 3 FP32 features (raw), y: n FP32 outputs. */
+/* An added initial-guess model for the recovery of Sec. II.C.4 (not part
+ * of the paper, which starts the Illinois iteration from the bracket of
+ * its eq. for z-/z+): an MLP 3 -> 64 -> 64 -> 1 with ReLU hidden units.
+ *   features  x = ((log10 D, S/E, log10((E - D)/D)) - mean) / std, with the
+ *             undensitised D, E, S = sqrt(gamma^ij S_i S_j) of the cell;
+ *   output    y = (log10(P/D) - mean_y) / std_y, so P0 = D 10^(y std_y + mean_y)
+ *             gives v0 = S/(E + P0) and the starting point z0 = v0 W(v0)
+ *             of a Newton iteration on the paper's master function kept
+ *             inside the bracket (Illinois from the bracket when it leaves
+ *             it or does not converge in 8 steps).
+ * The guess only changes where the root search starts, never the root.
+ *
+ * Parameter vector (GRHD_MLP_NPARAM FP32): W1[64][3], b1[64], W2[64][64]
+ * (row = output unit), b2[64], w3[64], b3.  The device weight buffer
+ * (grhd_mlp_bytes() bytes, device memory owned by the caller) holds W1 and
+ * W2 in BF16 (for the matrix cores), the vectors in FP32 and the eight
+ * scalers (feature mean[3], std[3], target mean, std).  Pass it as
+ * grhd_c2p_params.mlp with guess = GRHD_GUESS_MLP. */
 #define GRHD_MLP_HIDDEN 64
 #define GRHD_MLP_NPARAM 4481
+size_t grhd_mlp_bytes(void);
+
+/* Fill a weight buffer from FP32 params (device, NPARAM) and scal (device,
+ * 8 floats; NULL keeps the scalers already in the buffer). */
+int grhd_mlp_pack(void *mlp, const float *params, const float *scal,
+                  void *hip_stream);
+
+/* Network output for n standardised feature rows: X device n x 3 FP32
+ * (row-major), y device n FP32 (the standardised output).  BF16 matrix
+ * products with FP32 accumulation, as inside the recovery kernel. */
 int grhd_mlp_forward(const void *mlp, const float *X, float *y, int n,
                      void *hip_stream);
 
-/* One Adam step of MSE training on a batch (X n x 3 standardised
- * features, t n standardised targets): master FP32 parameters params,
- * Adam moments m, v (GRHD_MLP_NPARAM floats each), grad workspace
- * (GRHD_MLP_NPARAM floats), loss (device float, nullable).  The BF16
- * weights used by the forward kernels are refreshed into mlp. */
+/* Gradient of the loss mean_i (y_i - t_i)^2 over n >= 1 samples at the FP32
+ * params (W1, W2 rounded to BF16 as in the forward kernel, FP32
+ * arithmetic): grad device NPARAM floats (overwritten), loss device float
+ * (nullable, overwritten).  X, t standardised, device. */
+int grhd_mlp_grad(const float *params, float *grad, const float *X,
+                  const float *t, int n, float *loss, void *hip_stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr, step
+ * number step >= 1 for the bias correction) on a batch: params, m, v are
+ * the FP32 master parameters and moments (device, NPARAM each), grad a
+ * device workspace of NPARAM floats; the BF16 weights in mlp are refreshed
+ * from the updated params (scalers kept). */
 int grhd_mlp_train_step(void *mlp, float *params, float *m, float *v,
                         float *grad, const float *X, const float *t, int n,
                         float lr, int step, float *loss, void *hip_stream);
 
-/* Gradient only (for checking): grad <- d(mean (y - t)^2)/d params at the
- * FP32 params (BF16-rounded for the matrix products, as in training). */
-int grhd_mlp_grad(const float *params, float *grad, const float *X,
-                  const float *t, int n, float *loss, void *hip_stream);
+/* ---------------------------------------------------------------- timing */
 
-/* Pack FP32 params + feature/target scalers into a device weight buffer. */
-int grhd_mlp_pack(void *mlp, const float *params, const float *scal /*8*/,
-                  void *hip_stream);
-size_t grhd_mlp_bytes(void);
+/* A HIP event with timing enabled, for grhd_options.ev_begin/ev_end. */
+int grhd_event_create(void **ev);
+/* Milliseconds between two recorded events; waits for `end`. */
+int grhd_event_elapsed_ms(void *begin, void *end, float *ms);
+int grhd_event_destroy(void *ev);
 
 /* ---------------------------------------------------------------- misc */
 const char *grhd_last_error(void);

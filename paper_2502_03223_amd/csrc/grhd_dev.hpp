@@ -233,8 +233,10 @@ template <int EK, bool COLD>
 __device__ double illinois(const EosK &e, double D, double qq, double r, double a, double b,
                            double tol, int max_iter, int *iters) {
   double fa = c2p_f<EK, COLD>(e, D, qq, r, a);
+  (*iters)++;
   if (!(fa < 0.0)) return a;
   double fb = c2p_f<EK, COLD>(e, D, qq, r, b);
+  (*iters)++;
   if (!(fb > 0.0)) return b;
   int side = 0;
   double c = a;
@@ -319,24 +321,43 @@ __device__ C2PResult con2prim_cell(const EosK &e, const C2PK &cp, double W, cons
     if (D / sqrt(1.0 + zlo * zlo) < e.rho_atm) atm = true;
     if (!atm && k > 0.0) {
       bool done = false;
+      double za = zm, zb = zp;
       if (zguess >= 0.0) {
-        // safeguarded Newton from the learned guess, at most 8 steps, kept
-        // inside the bracket (analytic derivative for the gamma law, a
-        // one-sided difference otherwise)
+        // safeguarded Newton from the learned guess (analytic derivative
+        // for the gamma law, a one-sided difference otherwise): every
+        // evaluation narrows the bracket [za, zb]; a step that leaves it
+        // first tries the untested end itself (the root may sit on it, as
+        // for cold gas where it equals z+), then bisects; after 8
+        // evaluations Illinois finishes on the narrowed bracket
+        bool ta = false, tb = false;
         double zz = fmin(fmax(zguess, zm), zp);
         for (int it = 0; it < 8; it++) {
           double f0, df;
           c2p_f_df<EK>(e, D, qq, r, zz, f0, df);
           res.iters += 1;
+          if (f0 == 0.0 || (zz == zp && f0 <= 0.0) || (zz == zm && f0 >= 0.0)) {
+            z = zz;
+            done = true;
+            break;
+          }
+          if (f0 < 0.0) { za = zz; ta = true; }
+          else { zb = zz; tb = true; }
           double zn = zz - f0 / df;
-          if (!(zn >= zm && zn <= zp)) break;
+          if (!(zn > za && zn < zb)) {
+            if (zn >= zb && !tb) zn = zb;
+            else if (zn <= za && !ta) zn = za;
+            else zn = 0.5 * (za + zb);
+          }
           double dz = fabs(zn - zz);
           zz = zn;
-          if (dz <= cp.tol * zz) { done = true; break; }
+          if (dz <= cp.tol * zz) {
+            z = zz;
+            done = true;
+            break;
+          }
         }
-        if (done) z = zz;
       }
-      if (!done) z = illinois<EK, false>(e, D, qq, r, zm, zp, cp.tol, cp.max_iter, &res.iters);
+      if (!done) z = illinois<EK, false>(e, D, qq, r, za, zb, cp.tol, cp.max_iter, &res.iters);
     }
   }
   if (!atm) {

@@ -588,9 +588,34 @@ extern "C" int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos, const
     p2 = (FluxPart *)(buf + sizeof(C2PPart) * nb1);
   }
   if ((rc = launch_con2prim(pk.g, e, to_c2pk(&opts->c2p), pk.m, mc, q, pp, flags, p1, st))) return rc;
+  if (opts->ev_begin && hipEventRecord((hipEvent_t)opts->ev_begin, st) != hipSuccess)
+    return fail(GRHD_ERR_DEVICE, "hipEventRecord failed");
   if ((rc = launch_substep(pk, e, opts->prec, mc, shape, p2, st))) return rc;
+  if (opts->ev_end && hipEventRecord((hipEvent_t)opts->ev_end, st) != hipSuccess)
+    return fail(GRHD_ERR_DEVICE, "hipEventRecord failed");
   if (diag) {
     return launch_diag_final(p1, nb1, p2, nb2, diag, st);
   }
   return GRHD_OK;
+}
+
+extern "C" int grhd_event_create(void **ev) {
+  if (!ev) return fail(GRHD_ERR_INVALID, "ev is NULL");
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return fail(GRHD_ERR_DEVICE, "hipEventCreate failed");
+  *ev = (void *)e;
+  return GRHD_OK;
+}
+
+extern "C" int grhd_event_elapsed_ms(void *begin, void *end, float *ms) {
+  if (!begin || !end || !ms) return fail(GRHD_ERR_INVALID, "NULL argument");
+  if (hipEventSynchronize((hipEvent_t)end) != hipSuccess) return fail(GRHD_ERR_DEVICE, "hipEventSynchronize failed");
+  if (hipEventElapsedTime(ms, (hipEvent_t)begin, (hipEvent_t)end) != hipSuccess)
+    return fail(GRHD_ERR_DEVICE, "hipEventElapsedTime failed");
+  return GRHD_OK;
+}
+
+extern "C" int grhd_event_destroy(void *ev) {
+  if (!ev) return GRHD_OK;
+  return hipEventDestroy((hipEvent_t)ev) == hipSuccess ? GRHD_OK : fail(GRHD_ERR_DEVICE, "hipEventDestroy failed");
 }

@@ -70,7 +70,8 @@ class C2PParams(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("recon", C.c_int), ("riemann", C.c_int), ("prec", C.c_int),
-                ("c2p", C2PParams), ("tile_x", C.c_int), ("tile_z", C.c_int)]
+                ("c2p", C2PParams), ("tile_x", C.c_int), ("tile_z", C.c_int),
+                ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p)]
 
 
 class Stage(C.Structure):
@@ -113,6 +114,9 @@ def lib():
             "grhd_batch_levels": [p, p, i, p, p],
             "grhd_plan_destroy": [p],
             "grhd_plan_tile": [p, p, p],
+            "grhd_event_create": [p],
+            "grhd_event_elapsed_ms": [p, p, p],
+            "grhd_event_destroy": [p],
         }
         for name, args in sig.items():
             fn = getattr(_lib, name, None)
@@ -228,6 +232,9 @@ def make_options(o):
     s.c2p = make_c2p(o["c2p"])
     tile = o.get("tile", (0, 0))
     s.tile_x, s.tile_z = tile
+    ev = o.get("events")
+    if ev is not None:
+        s.ev_begin, s.ev_end = ev[0].handle, ev[1].handle
     return s
 
 
@@ -301,8 +308,14 @@ class Substep:
         self._keep = (grid, eos, metric, opts)
 
     def __call__(self, stage, qn, qs, qout, p, acc_in=None, acc_out=None, flux_reg=None,
-                 flags=None, diag=None, stream=None):
+                 flags=None, diag=None, stream=None, events=None):
+        """events: optional (begin, end) Event pair recorded around the fused
+        stage kernel of this call."""
         st = make_stage(stage) if isinstance(stage, dict) else stage
+        if events is not None:
+            self.opts.ev_begin, self.opts.ev_end = events[0].handle, events[1].handle
+        else:
+            self.opts.ev_begin = self.opts.ev_end = None
         rc = lib().grhd_rk_substep(
             C.byref(self.grid), C.byref(self.eos), C.byref(self.metric), C.byref(self.opts),
             C.byref(st), C.byref(make_cons(qn if qn is not None else qs)),
@@ -380,6 +393,30 @@ class Plan:
     def __del__(self):
         try:
             self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ timing
+
+class Event:
+    """HIP event (timing enabled) owned by the library's helpers."""
+
+    def __init__(self):
+        L = lib()
+        h = C.c_void_p()
+        _check(L.grhd_event_create(C.byref(h)), "grhd_event_create")
+        self.handle = h
+
+    def elapsed_ms(self, end):
+        ms = C.c_float()
+        _check(lib().grhd_event_elapsed_ms(self.handle, end.handle, C.byref(ms)),
+               "grhd_event_elapsed_ms")
+        return ms.value
+
+    def __del__(self):
+        try:
+            lib().grhd_event_destroy(self.handle)
         except Exception:
             pass
 

@@ -10,8 +10,6 @@
   (1e-12 normwise on the primitives) with fewer master-function
   evaluations on the differentially rotating workload.
 """
-import math
-
 import numpy as np
 import pytest
 
@@ -93,8 +91,9 @@ def train(orc, n=200_000, epochs=8, batch=8192, seed=11):
     Xs = torch.from_numpy(((X - xm) / xs).astype(np.float32)).to(DEV)
     ts = torch.from_numpy(((y - ym) / ys).astype(np.float32)).to(DEV)
     net = grhd.MLP(grhd.mlp_init(seed), scal)
+    _, l0 = grhd.mlp_grad(net.params, Xs, ts)
+    losses = [float(l0.cpu()[0])]
     g = torch.Generator(device=DEV).manual_seed(seed)
-    losses = []
     for ep in range(epochs):
         perm = torch.randperm(n, generator=g, device=DEV)
         lr = 3e-3 * (0.5 ** (ep // 3))
@@ -107,7 +106,8 @@ def train(orc, n=200_000, epochs=8, batch=8192, seed=11):
 
 def test_training_and_gain(orc):
     net, losses = train(orc)
-    assert losses[-1] < 0.05 * losses[0] and losses[-1] < 1e-2, losses
+    # losses[0] is the untrained network's loss on the whole set
+    assert losses[-1] < 0.02 * losses[0] and losses[-1] < 1e-2, losses
     # recovery on the rotating workload (flat metric), three ways
     grid = synth.make_grid(256, 64, 0.0, 0.0, 20.0 / 256, 20.0 / 256, "cart",
                            ("outflow", "outflow", "outflow", "outflow"))
