@@ -73,52 +73,38 @@ k_con2prim_batch(const PatchK *__restrict__ pt, const EosK *__restrict__ eos, C2
   if (part) c2p_block_partial<256>(act, fl, iters, &part[blockIdx.x], red);
 }
 
-// persistent stage kernel: workgroups pop tiles until the queue is empty;
-// the last workgroup to leave resets the queue for the next launch.
+// Batched stage kernel: one workgroup per (patch, tile) item, item =
+// workgroup index (patches in table order, tiles row-major), so the XCDs
+// (dealt workgroups round-robin) each take every 8th item of every patch.
+// Two tile shapes share the LDS: thin patches (nz <= 8) use AX x AZ, the
+// others BX x BZ.  Each item writes one diagnostic record.
 template <class T, int MC, int AX, int AZ, int BX, int BZ>
 __global__ void __launch_bounds__(NT)
 k_batch(const PatchK *__restrict__ pt, const EosK *__restrict__ eos,
-        const long long *__restrict__ tile_prefix, int npatch, long long total,
-        unsigned long long *queue, FluxPart *part) {
+        const long long *__restrict__ tile_prefix, int npatch, FluxPart *part2) {
   __shared__ double red[NT / 64][3];
   __shared__ union {
     TileSmem<T, MC, AX, AZ> a;
     TileSmem<T, MC, BX, BZ> b;
   } sm;
-  __shared__ long long s_item;
-  double cm = 0.0, mb = 0.0, jm = 0.0;
-  for (;;) {
-    if (threadIdx.x == 0) s_item = (long long)atomicAdd(&queue[0], 1ull);
-    __syncthreads();
-    long long t = s_item;
-    __syncthreads();
-    if (t >= total) break;
-    int lo = 0, hi = npatch - 1;
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (tile_prefix[mid] <= t) lo = mid;
-      else hi = mid - 1;
-    }
-    const PatchK &P = pt[lo];
-    int lt = (int)(t - tile_prefix[lo]);
-    if (P.g.nz <= 8)
-      substep_tile<T, MC, AX, AZ>(P, eos[P.eos_id], lt % P.tiles_x, lt / P.tiles_x, sm.a, cm, mb, jm);
-    else
-      substep_tile<T, MC, BX, BZ>(P, eos[P.eos_id], lt % P.tiles_x, lt / P.tiles_x, sm.b, cm, mb, jm);
+  const long long t = blockIdx.x;
+  int lo = 0, hi = npatch - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (tile_prefix[mid] <= t) lo = mid;
+    else hi = mid - 1;
   }
-  if (part) flux_block_partial<NT>(cm, mb, jm, &part[blockIdx.x], red);
-  if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned long long done = atomicAdd(&queue[1], 1ull);
-    if (done == (unsigned long long)gridDim.x - 1) {
-      atomicExch(&queue[0], 0ull);
-      atomicExch(&queue[1], 0ull);
-    }
-  }
+  const PatchK &P = pt[lo];
+  int lt = (int)(t - tile_prefix[lo]);
+  double cm, mb, jm;
+  if (P.g.nz <= 8)
+    substep_tile<T, MC, AX, AZ>(P, eos[P.eos_id], lt % P.tiles_x, lt / P.tiles_x, sm.a, cm, mb, jm);
+  else
+    substep_tile<T, MC, BX, BZ>(P, eos[P.eos_id], lt % P.tiles_x, lt / P.tiles_x, sm.b, cm, mb, jm);
+  flux_block_partial<NT>(cm, mb, jm, &part2[t], red);
 }
 
-using BatchFn = void (*)(const PatchK *, const EosK *, const long long *, int, long long,
-                         unsigned long long *, FluxPart *);
+using BatchFn = void (*)(const PatchK *, const EosK *, const long long *, int, FluxPart *);
 
 // thin-patch shapes (nz <= 8) and square-patch shapes
 static const int kThin[2][2] = {{64, 8}, {32, 8}};
@@ -162,9 +148,7 @@ struct grhd_plan {
   PatchK *d_patches = nullptr;
   EosK *d_eos = nullptr;
   long long *d_tile_prefix = nullptr, *d_item_prefix = nullptr;
-  unsigned long long *d_queue = nullptr;
   grhd_diag *d_diag = nullptr;      // used when the caller passes no diag
-  int nblocks = 0;
   static constexpr int kSlots = 4;
   PatchK *h_slots[kSlots] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t slot_ev[kSlots] = {};
@@ -173,9 +157,9 @@ struct grhd_plan {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   grhd_diag *graph_diag = nullptr;  // diag pointer baked into the graph
-  C2PPart *d_part1 = nullptr;       // per-workgroup diagnostic records
-  FluxPart *d_part2 = nullptr;
-  int part2_cap = 0;
+  C2PPart *d_part1 = nullptr;       // diagnostic records: recovery workgroups,
+  FluxPart *d_part2 = nullptr;      // stage tiles
+  long long part2_cap = 0;
 };
 
 namespace {
@@ -193,6 +177,7 @@ int plan_tiles(grhd_plan *pl, int a, int b, std::vector<PatchK> &hp) {
     acc += (long long)hp[i].tiles_x * hp[i].tiles_z;
   }
   pl->total_tiles = acc;
+  if (acc >= (1LL << 31)) return fail(GRHD_ERR_UNSUPPORTED, "more than 2^31 - 1 tiles in one plan");
   return GRHD_OK;
 }
 
@@ -235,9 +220,9 @@ int capture_graph(grhd_plan *pl, grhd_diag *diag) {
     hipLaunchKernelGGL((k_con2prim_batch<MC_CF, GRHD_EOS_HYBRID>), gi, dim3(256), 0, s, pl->d_patches,
                        pl->d_eos, pl->cp, pl->d_item_prefix, pl->npatch, p1);
   BatchFn fn = batch_kernel(pl->prec, pl->mc, pl->shape_a, pl->shape_b);
-  hipLaunchKernelGGL(fn, dim3(pl->nblocks), dim3(NT), 0, s, pl->d_patches, pl->d_eos,
-                     pl->d_tile_prefix, pl->npatch, pl->total_tiles, pl->d_queue, pl->d_part2);
-  launch_diag_final(pl->d_part1, (int)pl->total_items, pl->d_part2, pl->nblocks, diag, s);
+  hipLaunchKernelGGL(fn, dim3((unsigned)pl->total_tiles), dim3(NT), 0, s, pl->d_patches, pl->d_eos,
+                     pl->d_tile_prefix, pl->npatch, pl->d_part2);
+  launch_diag_final(pl->d_part1, (int)pl->total_items, pl->d_part2, (int)pl->total_tiles, diag, s);
   hipError_t le = hipGetLastError();
   hipError_t err = hipStreamEndCapture(s, &pl->graph);
   if (le != hipSuccess || err != hipSuccess)
@@ -266,24 +251,16 @@ int set_shapes(grhd_plan *pl, int a, int b, const grhd_patch *patches) {
   if (rc) return rc;
   pl->shape_a = a;
   pl->shape_b = b;
-  plan_tiles(pl, a, b, hp);
+  if ((rc = plan_tiles(pl, a, b, hp))) return rc;
   if (hipMemcpy(pl->d_tile_prefix, pl->tile_prefix.data(), sizeof(long long) * pl->npatch,
                 hipMemcpyHostToDevice) != hipSuccess)
     return fail(GRHD_ERR_DEVICE, "tile table upload failed");
-  int dev = 0, ncu = 256, occ = 2;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  BatchFn fn = batch_kernel(pl->prec, pl->mc, a, b);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, NT, 0) != hipSuccess || occ < 1)
-    occ = 1;
-  long long nb = (long long)ncu * occ;
-  pl->nblocks = (int)std::max(1LL, std::min(nb, pl->total_tiles));
-  if (pl->nblocks > pl->part2_cap) {
+  if (pl->total_tiles > pl->part2_cap) {
     hipFree(pl->d_part2);
     pl->d_part2 = nullptr;
-    if (hipMalloc(&pl->d_part2, sizeof(FluxPart) * pl->nblocks) != hipSuccess)
+    if (hipMalloc(&pl->d_part2, sizeof(FluxPart) * pl->total_tiles) != hipSuccess)
       return fail(GRHD_ERR_DEVICE, "plan allocation failed");
-    pl->part2_cap = pl->nblocks;
+    pl->part2_cap = pl->total_tiles;
   }
   return capture_graph(pl, pl->d_diag);
 }
@@ -366,7 +343,6 @@ void destroy_plan(grhd_plan *pl) {
   hipFree(pl->d_eos);
   hipFree(pl->d_tile_prefix);
   hipFree(pl->d_item_prefix);
-  hipFree(pl->d_queue);
   hipFree(pl->d_diag);
   hipFree(pl->d_part1);
   hipFree(pl->d_part2);
@@ -421,7 +397,6 @@ extern "C" int grhd_plan_create(const grhd_patch *patches, int npatch, const grh
              hipMalloc(&pl->d_eos, sizeof(EosK) * neos) == hipSuccess &&
              hipMalloc(&pl->d_tile_prefix, sizeof(long long) * npatch) == hipSuccess &&
              hipMalloc(&pl->d_item_prefix, sizeof(long long) * npatch) == hipSuccess &&
-             hipMalloc(&pl->d_queue, 2 * sizeof(unsigned long long)) == hipSuccess &&
              hipMalloc(&pl->d_diag, sizeof(grhd_diag)) == hipSuccess &&
              hipMalloc(&pl->d_part1, sizeof(C2PPart) * pl->total_items) == hipSuccess &&
              hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking) == hipSuccess;
@@ -429,11 +404,9 @@ extern "C" int grhd_plan_create(const grhd_patch *patches, int npatch, const grh
     okm = hipHostMalloc((void **)&pl->h_slots[s], sizeof(PatchK) * npatch, hipHostMallocDefault) == hipSuccess &&
           hipEventCreateWithFlags(&pl->slot_ev[s], hipEventDisableTiming) == hipSuccess;
   if (!okm) { destroy_plan(pl); return fail(GRHD_ERR_DEVICE, "plan allocation failed"); }
-  unsigned long long zq[2] = {0ull, 0ull};
   okm = hipMemcpy(pl->d_eos, he.data(), sizeof(EosK) * neos, hipMemcpyHostToDevice) == hipSuccess &&
         hipMemcpy(pl->d_item_prefix, pl->item_prefix.data(), sizeof(long long) * npatch,
-                  hipMemcpyHostToDevice) == hipSuccess &&
-        hipMemcpy(pl->d_queue, zq, sizeof(zq), hipMemcpyHostToDevice) == hipSuccess;
+                  hipMemcpyHostToDevice) == hipSuccess;
   if (!okm) { destroy_plan(pl); return fail(GRHD_ERR_DEVICE, "plan upload failed"); }
 
   // tile shapes: cache, explicit option, or measured on the given patches

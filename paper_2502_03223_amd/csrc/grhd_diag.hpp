@@ -1,7 +1,8 @@
 // grhd_diag.hpp -- diagnostics without contended atomics: every workgroup
-// reduces its cells (wave shuffles, then LDS) and writes one partial record
-// to a scratch array; one single-workgroup kernel folds the records in a
-// fixed order and overwrites the caller's grhd_diag.
+// of the recovery and every tile of the stage kernel reduces its cells
+// (wave shuffles, then LDS) and writes one partial record to a scratch
+// array; one single-workgroup kernel folds the records in a fixed order and
+// overwrites the caller's grhd_diag.
 #pragma once
 
 #include "grhd_dev.hpp"
@@ -79,8 +80,90 @@ __device__ __forceinline__ void flux_block_partial(double cmax, double mb, doubl
   }
 }
 
-// fold n1 recovery records and n2 stage records into diag (fixed order);
-// defined once in grhd_kernels.hip
+// Fold n1 recovery records and n2 stage records into diag, by one whole
+// workgroup of NTHR threads (every thread must call it).  red: NTHR/64 x 9
+// words of LDS.  Each thread folds a strided subset, then the waves reduce
+// by shuffles and thread 0 combines the wave results, always in the same
+// order.
+// Fold n1 recovery records and n2 stage records into diag, by one whole
+// workgroup of NTHR threads (every thread must call it).  red: NTHR/64 x 9
+// words of LDS.  Thread t folds records t, t + NTHR, t + 2 NTHR, ... in that
+// order (four loads in flight at a time), the waves reduce by shuffles and
+// thread 0 combines the wave results in wave order: the result depends only
+// on the record counts.
+template <int NTHR>
+__device__ void diag_fold(const C2PPart *p1, int n1, const FluxPart *p2, int n2, grhd_diag *diag,
+                          unsigned long long (*red)[9]) {
+  int t = threadIdx.x;
+  unsigned long long a[6] = {0, 0, 0, 0, 0, 0};
+  double c = 0.0, mb = 0.0, jm = 0.0;
+  for (int i0 = t; i0 < n1; i0 += 4 * NTHR) {
+    C2PPart r[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+      if (i0 + u * NTHR < n1) r[u] = p1[i0 + u * NTHR];
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+      if (i0 + u * NTHR < n1) {
+        for (int k = 0; k < 5; k++) a[k] += r[u].n[k];
+        a[5] = r[u].n[5] > a[5] ? r[u].n[5] : a[5];
+      }
+  }
+  for (int i0 = t; i0 < n2; i0 += 4 * NTHR) {
+    FluxPart r[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+      if (i0 + u * NTHR < n2) r[u] = p2[i0 + u * NTHR];
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+      if (i0 + u * NTHR < n2) {
+        c = fmax(c, r[u].cmax);
+        mb += r[u].mb;
+        jm += r[u].jm;
+      }
+  }
+  for (int k = 0; k < 5; k++) a[k] = wave_sum_u64(a[k]);
+  a[5] = wave_max_u64(a[5]);
+  for (int o = 32; o > 0; o >>= 1) {
+    c = fmax(c, __shfl_xor(c, o, 64));
+    mb += __shfl_xor(mb, o, 64);
+    jm += __shfl_xor(jm, o, 64);
+  }
+  int w = t >> 6;
+  if ((t & 63) == 0) {
+    for (int k = 0; k < 6; k++) red[w][k] = a[k];
+    red[w][6] = (unsigned long long)__double_as_longlong(c);
+    red[w][7] = (unsigned long long)__double_as_longlong(mb);
+    red[w][8] = (unsigned long long)__double_as_longlong(jm);
+  }
+  __syncthreads();
+  if (t == 0) {
+    unsigned long long u[6];
+    for (int k = 0; k < 6; k++) u[k] = red[0][k];
+    double cc = __longlong_as_double((long long)red[0][6]);
+    double sb = __longlong_as_double((long long)red[0][7]);
+    double sj = __longlong_as_double((long long)red[0][8]);
+    for (int ww = 1; ww < NTHR / 64; ww++) {
+      for (int k = 0; k < 5; k++) u[k] += red[ww][k];
+      u[5] = red[ww][5] > u[5] ? red[ww][5] : u[5];
+      cc = fmax(cc, __longlong_as_double((long long)red[ww][6]));
+      sb += __longlong_as_double((long long)red[ww][7]);
+      sj += __longlong_as_double((long long)red[ww][8]);
+    }
+    diag->max_courant = cc;
+    diag->Mb = sb;
+    diag->J = sj;
+    diag->n_rescale = u[0];
+    diag->n_cold = u[1];
+    diag->n_atm = u[2];
+    diag->n_fail = u[3];
+    diag->iter_sum = u[4];
+    diag->iter_max = u[5];
+  }
+}
+
+// stand-alone fold (one workgroup of 256 threads); defined once in
+// grhd_kernels.hip
 int launch_diag_final(const C2PPart *p1, int n1, const FluxPart *p2, int n2, grhd_diag *diag,
                       hipStream_t st);
 

@@ -42,51 +42,15 @@ int fail(int code, const char *fmt, ...) {
 // ------------------------------------------------------------ small kernels
 
 // fold n1 recovery records and n2 stage records into diag (fixed order)
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 k_diag_final(const C2PPart *p1, int n1, const FluxPart *p2, int n2, grhd_diag *diag) {
-  __shared__ unsigned long long su[256][6];
-  __shared__ double sd[256][3];
-  int t = threadIdx.x;
-  unsigned long long a[6] = {0, 0, 0, 0, 0, 0};
-  double c = 0.0, mb = 0.0, jm = 0.0;
-  for (int i = t; i < n1; i += 256) {
-    for (int k = 0; k < 5; k++) a[k] += p1[i].n[k];
-    a[5] = p1[i].n[5] > a[5] ? p1[i].n[5] : a[5];
-  }
-  for (int i = t; i < n2; i += 256) {
-    c = fmax(c, p2[i].cmax);
-    mb += p2[i].mb;
-    jm += p2[i].jm;
-  }
-  for (int k = 0; k < 6; k++) su[t][k] = a[k];
-  sd[t][0] = c; sd[t][1] = mb; sd[t][2] = jm;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) {
-      for (int k = 0; k < 5; k++) su[t][k] += su[t + s][k];
-      su[t][5] = su[t + s][5] > su[t][5] ? su[t + s][5] : su[t][5];
-      sd[t][0] = fmax(sd[t][0], sd[t + s][0]);
-      sd[t][1] += sd[t + s][1];
-      sd[t][2] += sd[t + s][2];
-    }
-    __syncthreads();
-  }
-  if (t == 0) {
-    diag->max_courant = sd[0][0];
-    diag->Mb = sd[0][1];
-    diag->J = sd[0][2];
-    diag->n_rescale = su[0][0];
-    diag->n_cold = su[0][1];
-    diag->n_atm = su[0][2];
-    diag->n_fail = su[0][3];
-    diag->iter_sum = su[0][4];
-    diag->iter_max = su[0][5];
-  }
+  __shared__ unsigned long long red[16][9];
+  diag_fold<1024>(p1, n1, p2, n2, diag, red);
 }
 
 int launch_diag_final(const C2PPart *p1, int n1, const FluxPart *p2, int n2, grhd_diag *diag,
                       hipStream_t st) {
-  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, st, p1, n1, p2, n2, diag);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(1024), 0, st, p1, n1, p2, n2, diag);
   return launch_status("diag final");
 }
 
@@ -240,21 +204,25 @@ k_flux(GridK g, EosK e, MetK m, int dir, int riemann, Ptr6<T> Lp, Ptr6<T> Rp, Q5
   }
 }
 
-// Fused stage: one workgroup per tile; tile index remapped so that each of
-// the 8 XCDs works on a contiguous band of tiles (halo reuse in its L2).
+// Fused stage: one workgroup per tile, tile = workgroup index.  The
+// hardware deals workgroups to the 8 XCDs round-robin by index, so each XCD
+// takes every 8th tile of a tile row: any spatially smooth distribution of
+// heavy tiles (stellar interior, shocks) spreads evenly over the XCDs, and
+// when the tile row length is a multiple of 8 the tiles above and below a
+// tile run on the same XCD (its z halo is then shared in that XCD's L2).
+// Each tile writes one diagnostic record part2[tile]; a one-workgroup
+// kernel folds the records afterwards.  (Handing tiles out through a global
+// counter costs two same-address atomics per workgroup, which serialise
+// across the XCDs and cost more than the imbalance they remove.)
 template <class T, int MC, int TX, int TZ>
 __global__ void __launch_bounds__(NT)
-k_substep(PatchK P, EosK e, FluxPart *part) {
+k_substep(PatchK P, EosK e, FluxPart *part2) {
   __shared__ TileSmem<T, MC, TX, TZ> sm;
   __shared__ double red[NT / 64][3];
-  int ntiles = P.tiles_x * P.tiles_z;
-  int b = blockIdx.x;
-  int full = (ntiles / 8) * 8;
-  int t = b;
-  if (b < full) t = (b % 8) * (full / 8) + b / 8;
-  double cm = 0.0, mb = 0.0, jm = 0.0;
+  const int t = blockIdx.x;
+  double cm, mb, jm;
   substep_tile<T, MC, TX, TZ>(P, e, t % P.tiles_x, t / P.tiles_x, sm, cm, mb, jm);
-  if (part) flux_block_partial<NT>(cm, mb, jm, &part[b], red);
+  if (part2) flux_block_partial<NT>(cm, mb, jm, &part2[t], red);
 }
 
 // ------------------------------------------------------------ dispatch
@@ -281,11 +249,12 @@ static SubstepFn substep_kernel(int prec, int mc, int shape) {
   return mc == MC_GEN ? pick_shape<double, MC_GEN>(shape) : pick_shape<double, MC_CF>(shape);
 }
 
-// Scratch for the workgroup partial records of the diagnostics, owned by
-// the library: one buffer per (device, stream), allocated on the first call
-// that asks for diagnostics and grown when a larger grid needs more.
-// Calls that overlap on the same stream are ordered; different streams use
-// different buffers.
+// Library-owned device scratch for the partial records of the
+// diagnostics, one buffer per (device, stream), allocated on the first call
+// that asks for diagnostics and grown when a larger grid needs more.  Calls
+// that overlap on one stream are ordered by the stream; different streams
+// use different buffers.  The first such call on a stream allocates: make
+// it before capturing calls into a graph.
 struct DiagScratch {
   int dev;
   hipStream_t st;
@@ -364,11 +333,12 @@ int launch_con2prim(const GridK &g, const EosK &e, const C2PK &cp, const MetK &m
   return launch_status("con2prim");
 }
 
-int launch_substep(const PatchK &pk, const EosK &e, int prec, int mc, int shape, FluxPart *diag,
+int launch_substep(const PatchK &pk, const EosK &e, int prec, int mc, int shape, FluxPart *part2,
                    hipStream_t st) {
   SubstepFn fn = substep_kernel(prec, mc, shape);
-  int ntiles = pk.tiles_x * pk.tiles_z;
-  hipLaunchKernelGGL(fn, dim3(ntiles), dim3(NT), 0, st, pk, e, diag);
+  long long nt = (long long)pk.tiles_x * pk.tiles_z;
+  if (nt >= (1LL << 31)) return fail(GRHD_ERR_UNSUPPORTED, "more than 2^31 - 1 tiles");
+  hipLaunchKernelGGL(fn, dim3((unsigned)nt), dim3(NT), 0, st, pk, e, part2);
   return launch_status("substep");
 }
 
@@ -562,7 +532,9 @@ extern "C" int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos, const
   if ((rc = fill_patch(grid, metric, stage, qn, qs, qout, p, acc_in, acc_out, flux_reg, opts->recon,
                        opts->riemann, pk)))
     return rc;
-  int shape = 0;
+  // default 16 x 16: the smallest halo per cell of the built shapes, and
+  // the FP64 instance fits three workgroups per CU in LDS
+  int shape = 3;
   if (opts->tile_x || opts->tile_z) {
     shape = shape_index(opts->tile_x, opts->tile_z);
     if (shape < 0) return fail(GRHD_ERR_UNSUPPORTED, "tile %dx%d not built", opts->tile_x, opts->tile_z);
@@ -593,9 +565,7 @@ extern "C" int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos, const
   if ((rc = launch_substep(pk, e, opts->prec, mc, shape, p2, st))) return rc;
   if (opts->ev_end && hipEventRecord((hipEvent_t)opts->ev_end, st) != hipSuccess)
     return fail(GRHD_ERR_DEVICE, "hipEventRecord failed");
-  if (diag) {
-    return launch_diag_final(p1, nb1, p2, nb2, diag, st);
-  }
+  if (diag) return launch_diag_final(p1, nb1, p2, nb2, diag, st);
   return GRHD_OK;
 }
 

@@ -36,6 +36,7 @@ struct TileSmem {
   T p[6][NC];
   double ma[NM], mw[NM];
   T f[5][NF];
+  uint8_t atm[NC];  // 1: the cell holds exactly the atmosphere state
 };
 
 // Source cell of ghost cell (j, k) under the boundary conditions, with the
@@ -81,41 +82,73 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// One tile of one patch.  cmax, mb, jm receive this thread's share of the
+// tile's diagnostics (max Courant number, sums of q_D dV and q_Sphi dV).
 template <class T, int MC, int TX, int TZ>
 __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int tx, int tz,
-                                             TileSmem<T, MC, TX, TZ> &sm, double &cmax_acc,
-                                             double &mb_acc, double &jm_acc) {
+                                             TileSmem<T, MC, TX, TZ> &sm, double &cmax_out,
+                                             double &mb_out, double &jm_out) {
   using S = TileSmem<T, MC, TX, TZ>;
-  constexpr int HX = S::HX, HZ = S::HZ;
+  constexpr int HX = S::HX;
   constexpr int CPT = (TX * TZ + NT - 1) / NT;
+  constexpr int LPT = (S::NC + NT - 1) / NT;
   const GridK &g = P.g;
   const int tid = threadIdx.x;
   const int nx = g.nx, nz = g.nz;
   const int j0 = tx * TX, k0 = tz * TZ;
   const bool cyl = (g.geom == GRHD_GEOM_CYLINDRICAL);
+  const T ra = (T)e.rho_atm, Pa = (T)e.P_atm, ea = (T)e.eps_atm;
   __syncthreads();  // LDS of a previous tile (persistent loop) is free
 
-  // ---- 1. stage primitives and (conformally flat class) lapse, W in LDS
-  for (int c = tid; c < S::NC; c += NT) {
-    int jj = c % HX, kk = c / HX;
-    int j = j0 - 3 + jj, k = k0 - 3 + kk;
-    bool inx = (jj >= 3 && jj < 3 + TX), inz = (kk >= 3 && kk < 3 + TZ);
-    bool need = (inx && j < nx && k >= -3 && k < nz + 3) || (inz && k < nz && j >= -3 && j < nx + 3);
-    if (!need) continue;
-    int js, ks;
-    double sg[3];
-    if (!ghost_map(g, j, k, js, ks, sg)) continue;
-    long long is = cell_index(g, js, ks);
-    sm.p[0][c] = (T)P.p[0][is];
-    sm.p[1][c] = (T)(sg[0] * P.p[1][is]);
-    sm.p[2][c] = (T)(sg[1] * P.p[2][is]);
-    sm.p[3][c] = (T)(sg[2] * P.p[3][is]);
-    sm.p[4][c] = (T)P.p[4][is];
-    sm.p[5][c] = (T)P.p[5][is];
-    if (MC == MC_CF) {
-      long long im = cell_index(g, j, k);
-      sm.ma[c] = P.m.f[GRHD_M_ALP] ? P.m.f[GRHD_M_ALP][im] : P.m.c[GRHD_M_ALP];
-      sm.mw[c] = P.m.f[GRHD_M_W] ? P.m.f[GRHD_M_W][im] : P.m.c[GRHD_M_W];
+  // ---- 1. stage primitives (and, for the conformally flat class, lapse
+  // and W) of the cross-shaped halo in LDS.  All addresses first, then all
+  // loads, then all LDS stores, so each thread has every load in flight at
+  // once.  Boundary conditions are an index map with velocity parities.
+  {
+    long long src[LPT], im[LPT];
+    bool use[LPT];
+    double s0[LPT], s1[LPT], s2[LPT];
+#pragma unroll
+    for (int i = 0; i < LPT; i++) {
+      int c = tid + i * NT;
+      int jj = c % HX, kk = c / HX;
+      int j = j0 - 3 + jj, k = k0 - 3 + kk;
+      bool inx = (jj >= 3 && jj < 3 + TX), inz = (kk >= 3 && kk < 3 + TZ);
+      bool need = c < S::NC &&
+                  ((inx && j < nx && k >= -3 && k < nz + 3) || (inz && k < nz && j >= -3 && j < nx + 3));
+      int js = j, ks = k;
+      double sg[3] = {1.0, 1.0, 1.0};
+      if (need) need = ghost_map(g, j, k, js, ks, sg);
+      use[i] = need;
+      src[i] = need ? cell_index(g, js, ks) : 0;
+      im[i] = need ? cell_index(g, j, k) : 0;
+      s0[i] = sg[0]; s1[i] = sg[1]; s2[i] = sg[2];
+    }
+    double v[LPT][6], va[LPT], vw[LPT];
+#pragma unroll
+    for (int i = 0; i < LPT; i++) {
+      if (use[i]) {
+        for (int f = 0; f < 6; f++) v[i][f] = P.p[f][src[i]];
+        if (MC == MC_CF) {
+          va[i] = P.m.f[GRHD_M_ALP] ? P.m.f[GRHD_M_ALP][im[i]] : P.m.c[GRHD_M_ALP];
+          vw[i] = P.m.f[GRHD_M_W] ? P.m.f[GRHD_M_W][im[i]] : P.m.c[GRHD_M_W];
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < LPT; i++) {
+      int c = tid + i * NT;
+      if (use[i]) {
+        T r = (T)v[i][0], u0 = (T)(s0[i] * v[i][1]), u1 = (T)(s1[i] * v[i][2]),
+          u2 = (T)(s2[i] * v[i][3]), pr = (T)v[i][4], ep = (T)v[i][5];
+        sm.p[0][c] = r; sm.p[1][c] = u0; sm.p[2][c] = u1; sm.p[3][c] = u2;
+        sm.p[4][c] = pr; sm.p[5][c] = ep;
+        sm.atm[c] = (r == ra && u0 == T(0) && u1 == T(0) && u2 == T(0) && pr == Pa && ep == ea) ? 1 : 0;
+        if (MC == MC_CF) {
+          sm.ma[c] = va[i];
+          sm.mw[c] = vw[i];
+        }
+      }
     }
   }
   __syncthreads();
@@ -143,19 +176,16 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
     FluxT<T> out;
     for (int m = 0; m < 5; m++) out.f[m] = T(0);
     if (valid) {
-      // a stencil of six equal cells (quiescent atmosphere) has equal left
-      // and right states, and both solvers then return the flux of that
-      // state exactly: evaluate it directly
+      // a stencil of six atmosphere cells has equal left and right states,
+      // and both solvers then return the physical flux of that state
+      // exactly: evaluate it directly
       bool uni = true;
-      for (int fld = 0; fld < 6; fld++) {
-        T c0 = sm.p[fld][base];
-        for (int i = 1; i < 6; i++) uni = uni && (sm.p[fld][base + i * stride] == c0);
-      }
+      for (int i = 0; i < 6; i++) uni = uni && sm.atm[base + i * stride];
       PrimT<T> L, R;
       if (uni) {
-        L.rho = sm.p[0][base];
-        L.u[0] = sm.p[1][base]; L.u[1] = sm.p[2][base]; L.u[2] = sm.p[3][base];
-        L.P = sm.p[4][base]; L.eps = sm.p[5][base];
+        L.rho = ra;
+        L.u[0] = T(0); L.u[1] = T(0); L.u[2] = T(0);
+        L.P = Pa; L.eps = ea;
         R = L;
       } else {
         T s[6], a, b;
@@ -215,7 +245,7 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
   }
   __syncthreads();
 
-  // ---- 5. z divergence, sources, stage combination, diagnostics
+  // ---- 3. divergence, sources, stage combination, diagnostics
   double mb = 0.0, jm = 0.0;
   const double i60dx = 1.0 / (60.0 * g.dx), i60dz = 1.0 / (60.0 * g.dz);
 #pragma unroll
@@ -227,6 +257,21 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
     int jj = c % TX, kk = c / TX;
     int j = j0 + jj, k = k0 + kk;
     if (!(c < TX * TZ && j < nx && k < nz)) continue;
+    long long ic = cell_index(g, j, k);
+    // state loads first: their latency overlaps the flux arithmetic below
+    double qs5[5], qn5[5], ai5[5];
+    for (int m = 0; m < 5; m++) qs5[m] = P.qs[m][ic];
+    if (P.use_qn)
+      for (int m = 0; m < 5; m++) qn5[m] = P.qn[m][ic];
+    if (P.use_acc_in)
+      for (int m = 0; m < 5; m++) ai5[m] = P.acc_in[m][ic];
+    const int lc = (kk + 3) * HX + (jj + 3);
+    double pc[6];
+    if (sizeof(T) == sizeof(double)) {
+      for (int i = 0; i < 6; i++) pc[i] = (double)sm.p[i][lc];  // own cells: no parity flip
+    } else {
+      for (int i = 0; i < 6; i++) pc[i] = P.p[i][ic];
+    }
     double xc = g.x0 + (j + 0.5) * g.dx;
     const double xl = g.x0 + j * g.dx, xr = g.x0 + (j + 1) * g.dx;
     const int fl = kk * (TX + 1) + jj, fr = fl + 1;
@@ -262,10 +307,8 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
       divz[m] = (Ft - Fb) * ivz;
     }
     // metric at the cell and its x, z derivatives
-    long long ic = cell_index(g, j, k);
     double gm[GRHD_NMET], dg[2 * GRHD_NMET];
     if (MC == MC_CF) {
-      int lc = (kk + 3) * HX + (jj + 3);
       for (int i = 0; i < GRHD_NMET; i++) { gm[i] = P.m.c[i]; dg[i] = 0.0; dg[GRHD_NMET + i] = 0.0; }
       gm[GRHD_M_ALP] = sm.ma[lc];
       gm[GRHD_M_W] = sm.mw[lc];
@@ -294,20 +337,18 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
         dg[GRHD_NMET + i] = deriv6(a7, i60dz);
       }
     }
-    double pc[6];
-    for (int i = 0; i < 6; i++) pc[i] = P.p[i][ic];
     double s[5];
     sources<MC>(gm, dg, xc, g.geom, pc, s);
     double dV = cyl ? 2.0 * M_PI * xc * g.dx * g.dz : g.dx * g.dz;
     for (int m = 0; m < 5; m++) {
       double L = s[m] - divx[m] - divz[m];
-      double v = P.b * P.qs[m][ic] + P.cdt * L;
-      if (P.use_qn) v += P.a * P.qn[m][ic];
-      if (P.use_acc_in) v += P.gdt * P.acc_in[m][ic];
+      double v = P.b * qs5[m] + P.cdt * L;
+      if (P.use_qn) v += P.a * qn5[m];
+      if (P.use_acc_in) v += P.gdt * ai5[m];
       P.qo[m][ic] = v;
       if (P.use_acc_out) {
         double av = P.e * L;
-        if (P.use_acc_in) av += P.d * P.acc_in[m][ic];
+        if (P.use_acc_in) av += P.d * ai5[m];
         P.acc_out[m][ic] = av;
       }
       if (m == 0) mb += v * dV;
@@ -315,9 +356,9 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
     }
   }
 
-  cmax_acc = fmax(cmax_acc, cmax);
-  mb_acc += mb;
-  jm_acc += jm;
+  cmax_out = cmax;
+  mb_out = mb;
+  jm_out = jm;
 }
 
 }  // namespace grhd
