@@ -1,18 +1,27 @@
 """Benchmark of the GRHD Runge-Kutta substep on one MI355X.
 
-Workload (default): the perturbed TOV star (K = 100, Gamma = 2,
+Headline workload: the perturbed TOV star (K = 100, Gamma = 2,
 rho_c = 1.28e-3, Cowling metric) on a 1024 x 1024 cylindrical grid covering
 [0, 20]^2, PPM + HLLC, SSP-RK3.  A benchmark step is one full SSP-RK3 time
-step = three substeps (each: recovery + the fused reconstruction / flux /
-divergence / source / stage kernel), with the diagnostic reductions on.
-Inputs are resident in HBM before the timed region.
+step = three substeps (each: primitive recovery, the fused reconstruction /
+flux / divergence / source / stage kernel, the diagnostic fold), with the
+diagnostics on.  Inputs are resident in HBM before the timed region.
 
-Metric: zone-updates/s (interior cells x substeps / second), FP64 path.
-The JSON line also carries the mixed-precision form (FP32 reconstruction and
-flux) with its L1 error against the FP64 path after 1000 substeps, the
-roofline of the substep and the oracle timed on a bounded sample on the host.
+Metric: zone-updates/s (interior cells x substeps / second) of the plain
+FP64 path.  The JSON line also carries:
+  forms.mixed    FP32 reconstruction and flux, FP64 recovery and update, with
+                 its L1 error against the FP64 path after N substeps;
+  forms.batched  six nested 256^2 star levels plus 64 Riemann patches
+                 (N_x log-uniform in [128, 2048], 8 periodic z cells) in one
+                 graph-captured batched launch, against one call per patch;
+  forms.learned  recovery of a 2048^2 differentially rotating field, Illinois
+                 from the bracket against Newton seeded by the matrix-core MLP
+                 (trained here on GPU), same root;
+  roofline       of the fused stage kernel (HIP events recorded by the library
+                 around that kernel, algorithmic bytes per zone);
+  cpu_baseline   the oracle on a bounded sample of the headline workload.
 
-  python bench.py [--steps K] [--warmup W] [--n N] [--gpus 1]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--forms fp64,mixed,...]
 """
 import argparse
 import json
@@ -31,6 +40,7 @@ HBM_PEAK_GBS = 8000.0
 # fields read or written once: primitives (6 x 8), lapse and W (2 x 8), q_s
 # (5 x 8) read, q_out (5 x 8) written; stages 2 and 3 also read q^n (5 x 8).
 BYTES_KERNEL = [144.0, 184.0, 184.0]
+ALL_FORMS = ("fp64", "mixed", "batched", "learned")
 
 
 def parse():
@@ -39,9 +49,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--forms", default=",".join(ALL_FORMS))
     ap.add_argument("--accuracy-substeps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-rows", type=int, default=128)
+    ap.add_argument("--cpu-sample-rows", type=int, default=1024)
+    ap.add_argument("--learned-n", type=int, default=2048)
+    ap.add_argument("--train-pairs", type=int, default=1 << 20)
+    ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB three "
                          "times (calibrates HBM byte counters against a known size)")
@@ -54,6 +68,10 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    forms = [f for f in args.forms.split(",") if f]
+    for f in forms:
+        if f not in ALL_FORMS:
+            sys.exit("unknown form %r" % f)
     import torch
 
     import synth
@@ -69,6 +87,7 @@ def main():
         print("copy calibration: %d MiB read + %d MiB written per copy, 3 copies"
               % (args.copy_mib, args.copy_mib), file=sys.stderr)
         del src, dst
+
     n = args.n
     grid = synth.star_grid(n, extent=20.0)
     tov = synth.tov_solve()
@@ -107,78 +126,57 @@ def main():
                     events[s][1].record()
             self.q, self.q1 = self.q1, self.q
 
-    # ---------------------------------------------------------------- FP64
-    st = Stepper("fp64")
-    for _ in range(args.warmup):
-        st.step()
-    torch.cuda.synchronize()
-    # stage events on torch's current stream (the library launches on it) and
-    # HIP events recorded by the library around the fused stage kernel
-    evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(3)]
-           for _ in range(args.steps)]
-    kevs = [[(grhd.Event(), grhd.Event()) for _ in range(3)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        st.step(evs[k], kevs[k])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    stage_ms = np.array([[evs[k][s][0].elapsed_time(evs[k][s][1]) for s in range(3)]
-                         for k in range(args.steps)])
-    kernel_ms = np.array([[kevs[k][s][0].elapsed_ms(kevs[k][s][1]) for s in range(3)]
-                          for k in range(args.steps)])
-    ms_per_step = wall * 1e3 / args.steps
-    value = 3 * nzone * args.steps / wall
-    mean_stage_ms = stage_ms.mean(axis=0)
-    mean_kernel_ms = kernel_ms.mean(axis=0)
-    # bytes and time per launch, averaged over the three stages
-    bytes_per_launch = np.mean(BYTES_KERNEL) * nzone
-    achieved = bytes_per_launch / (mean_kernel_ms.mean() * 1e-3) / 1e9
-    diag = grhd.read_diag(st.diag)
+    def run_form(prec):
+        st = Stepper(prec)
+        for _ in range(args.warmup):
+            st.step()
+        torch.cuda.synchronize()
+        # stage events on torch's current stream (the library launches on
+        # it) and HIP events recorded by the library around the fused kernel
+        evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(3)]
+               for _ in range(args.steps)]
+        kevs = [[(grhd.Event(), grhd.Event()) for _ in range(3)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            st.step(evs[k], kevs[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        stage_ms = np.array([[evs[k][s][0].elapsed_time(evs[k][s][1]) for s in range(3)]
+                             for k in range(args.steps)])
+        kernel_ms = np.array([[kevs[k][s][0].elapsed_ms(kevs[k][s][1]) for s in range(3)]
+                              for k in range(args.steps)])
+        return dict(wall=wall, stage_ms=stage_ms.mean(axis=0), kernel_ms=kernel_ms.mean(axis=0),
+                    diag=grhd.read_diag(st.diag))
 
-    # ---------------------------------------------------------------- mixed
-    sm = Stepper("mixed")
-    for _ in range(args.warmup):
-        sm.step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        sm.step()
-    torch.cuda.synchronize()
-    wall_m = time.perf_counter() - t0
-    value_m = 3 * nzone * args.steps / wall_m
+    out_forms = {}
+    r64 = run_form("fp64")
+    value = 3 * nzone * args.steps / r64["wall"]
+    ms_per_step = r64["wall"] * 1e3 / args.steps
+    # bytes and time per launch of the fused kernel, averaged over the stages
+    bytes_per_launch = float(np.mean(BYTES_KERNEL)) * nzone
+    achieved = bytes_per_launch / (float(r64["kernel_ms"].mean()) * 1e-3) / 1e9
+    diag = r64["diag"]
+    out_forms["fp64"] = {"value": value, "ms_per_step": ms_per_step,
+                         "kernel_ms": r64["kernel_ms"].tolist(), "stage_ms": r64["stage_ms"].tolist()}
+    print("fp64 done: %.3e zone-updates/s" % value, file=sys.stderr, flush=True)
 
-    # accuracy of the mixed form against the FP64 path after S substeps
-    nsteps_acc = args.accuracy_substeps // 3
-    a64, a32 = Stepper("fp64"), Stepper("mixed")
-    for _ in range(nsteps_acc):
-        a64.step()
-        a32.step()
-    grhd.con2prim(grid, eos, metric, c2p, a64.q.clone(), a64.p)
-    grhd.con2prim(grid, eos, metric, c2p, a32.q.clone(), a32.p)
-    torch.cuda.synchronize()
-    P64 = synth.interior(grid, a64.p.cpu().numpy())
-    P32 = synth.interior(grid, a32.p.cpu().numpy())
-    X, _ = synth.cell_coords(grid)
-    x = synth.interior(grid, X)
-    Wm = synth.interior(grid, metric_np["W"])
-    alp = synth.interior(grid, metric_np["alp"])
-    wgt = alp * Wm ** -3 * x           # sqrt(-g) dV / (2 pi dx dz)
+    if "mixed" in forms:
+        rm = run_form("mixed")
+        value_m = 3 * nzone * args.steps / rm["wall"]
+        out_forms["mixed"] = {"value": value_m, "ms_per_step": rm["wall"] * 1e3 / args.steps,
+                              "speedup_vs_fp64": value_m / value,
+                              "kernel_ms": rm["kernel_ms"].tolist(),
+                              "accuracy_vs_fp64": mixed_accuracy(args, Stepper, grid, eos, metric,
+                                                                 metric_np, c2p)}
+        print("mixed done", file=sys.stderr, flush=True)
+    if "batched" in forms:
+        out_forms["batched"] = batched_form(args, tov)
+        print("batched done", file=sys.stderr, flush=True)
+    if "learned" in forms:
+        out_forms["learned"] = learned_form(args)
+        print("learned done", file=sys.stderr, flush=True)
 
-    def l1rel(a, b):
-        return float((np.abs(a - b) * wgt).sum() / (np.abs(b) * wgt).sum())
-
-    def vel(P):
-        w = np.sqrt(1.0 + Wm ** 2 * (P[1] ** 2 + P[2] ** 2 + P[3] ** 2))
-        return Wm ** 2 * P[1] / w, Wm ** 2 * P[3] / w
-    vx64, vz64 = vel(P64)
-    vx32, vz32 = vel(P32)
-    l1_v = float(((np.abs(vx32 - vx64) + np.abs(vz32 - vz64)) * x).sum() / x.sum())
-    accuracy = dict(substeps=3 * nsteps_acc, l1_rel_rho=l1rel(P32[0], P64[0]),
-                    l1_rel_eps=l1rel(P32[5], P64[5]), l1_abs_v=l1_v,
-                    max_abs_v_fp64=float(np.abs(np.stack([vx64, vz64])).max()))
-
-    # ---------------------------------------------------------------- CPU
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(grid, eos, metric_np, p_np, c2p, dt, args.cpu_sample_rows)
@@ -205,29 +203,235 @@ def main():
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
             "kernel": "k_substep<double> (fused reconstruction, flux, divergence, sources, stage)",
-            "bytes_per_zone": BYTES_KERNEL, "kernel_ms": mean_kernel_ms.tolist(),
-            "stage_ms": mean_stage_ms.tolist(),
+            "bytes_per_zone": BYTES_KERNEL, "kernel_ms": r64["kernel_ms"].tolist(),
         },
-        "forms": {
-            "fp64": {"value": value, "ms_per_step": ms_per_step},
-            "mixed": {"value": value_m, "ms_per_step": wall_m * 1e3 / args.steps,
-                      "speedup_vs_fp64": value_m / value, "accuracy_vs_fp64": accuracy},
-        },
+        "forms": out_forms,
         "diag_last_stage": dict({k: diag[k] for k in ("max_courant", "Mb", "n_atm", "n_cold",
                                                        "n_rescale", "iter_max")},
                                 iter_mean=diag["iter_sum"] / nzone),
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
+
+
+def mixed_accuracy(args, Stepper, grid, eos, metric, metric_np, c2p):
+    """L1 differences of the mixed form from the FP64 path after the same
+    number of substeps from the same initial data."""
+    import torch
+
+    import synth
+    from paper_2502_03223_amd import grhd
+    nsteps = args.accuracy_substeps // 3
+    a64, a32 = Stepper("fp64"), Stepper("mixed")
+    for _ in range(nsteps):
+        a64.step()
+        a32.step()
+    grhd.con2prim(grid, eos, metric, c2p, a64.q.clone(), a64.p)
+    grhd.con2prim(grid, eos, metric, c2p, a32.q.clone(), a32.p)
+    torch.cuda.synchronize()
+    P64 = synth.interior(grid, a64.p.cpu().numpy())
+    P32 = synth.interior(grid, a32.p.cpu().numpy())
+    X, _ = synth.cell_coords(grid)
+    x = synth.interior(grid, X)
+    Wm = synth.interior(grid, metric_np["W"])
+    alp = synth.interior(grid, metric_np["alp"])
+    wgt = alp * Wm ** -3 * x           # sqrt(-g) dV / (2 pi dx dz)
+
+    def l1rel(a, b):
+        return float((np.abs(a - b) * wgt).sum() / (np.abs(b) * wgt).sum())
+
+    def vel(P):
+        w = np.sqrt(1.0 + Wm ** 2 * (P[1] ** 2 + P[2] ** 2 + P[3] ** 2))
+        return Wm ** 2 * P[1] / w, Wm ** 2 * P[3] / w
+    vx64, vz64 = vel(P64)
+    vx32, vz32 = vel(P32)
+    l1_v = float(((np.abs(vx32 - vx64) + np.abs(vz32 - vz64)) * x).sum() / x.sum())
+    return dict(substeps=3 * nsteps, l1_rel_rho=l1rel(P32[0], P64[0]),
+                l1_rel_eps=l1rel(P32[5], P64[5]), l1_abs_v=l1_v,
+                max_abs_v_fp64=float(np.abs(np.stack([vx64, vz64])).max()))
+
+
+def batched_form(args, tov):
+    """Six nested 256^2 star levels plus 64 thin Riemann patches: one
+    batched graph launch per substep against one library call per patch."""
+    import torch
+
+    import synth
+    from paper_2502_03223_amd import grhd
+    dev = torch.device("cuda:0")
+    patches = []
+    for lvl, g in enumerate(synth.fmr_levels(6, 256, finest_extent=20.0)):
+        p, met, _ = synth.star_problem(g, seed=100 + lvl, tov=tov)
+        patches.append(dict(grid=g, metric={k: torch.from_numpy(v).to(dev) for k, v in met.items()},
+                            p0=p, eos_id=0))
+    gam = 5.0 / 3.0
+    sizes = synth.riemann_patch_sizes(7, 64, 128, 2048)
+    for nxr, (L, R) in zip(sizes, synth.riemann_states(7, 64, gam)):
+        g = synth.riemann_grid(nxr, nz=8)
+        patches.append(dict(grid=g, metric={}, p0=synth.riemann_prims(g, L, R, gam), eos_id=1))
+    eos_table = [synth.ideal_eos(tov["G"], K=tov["K"]), synth.ideal_eos(gam)]
+    zones = sum(pt["grid"]["nx"] * pt["grid"]["nz"] for pt in patches)
+    c2p = dict(w_max=100.0, rho_atm=1e-10)
+
+    def alloc():
+        bufs = []
+        for pt in patches:
+            p = torch.from_numpy(pt["p0"]).to(dev)
+            q = torch.zeros((5,) + p.shape[1:], dtype=torch.float64, device=dev)
+            grhd.prim2con(pt["grid"], eos_table[pt["eos_id"]], pt["metric"], p, q, with_ghosts=True)
+            bufs.append(dict(q=q, q1=torch.zeros_like(q), q2=torch.zeros_like(q), p=p.clone()))
+        return bufs
+
+    def descr(b, pt, s, qn, qs, qo):
+        return dict(grid=pt["grid"], metric=pt["metric"], qn=b[qn], qs=b[qs], qout=b[qo], p=b["p"],
+                    stage=dict(grhd.SSPRK3[s], dt=0.4 * pt["grid"]["dx"]), eos_id=pt["eos_id"])
+    roles = [("q", "q", "q1"), ("q", "q1", "q2"), ("q", "q2", "q1")]
+    res = {"zones": zones, "patches": len(patches),
+           "workload": "6 nested 256^2 TOV star levels (outer edges 20..640) + 64 Riemann patches "
+                       "N_x log-uniform [128, 2048] x 8 periodic z, Gamma 5/3; SSP-RK3"}
+    steps = max(args.steps // 2, 5)
+    for prec in ("mixed", "fp64"):
+        opts = dict(recon="ppm", riemann="hllc", prec=prec, c2p=c2p)
+        A = alloc()
+        plan = grhd.Plan([descr(b, pt, 0, *roles[0]) for b, pt in zip(A, patches)], eos_table, opts)
+        A = alloc()
+        diag = grhd.new_diag()
+        # marshalled once: step parity (q and q1 swap every step) x stage
+        swapped = [dict(b, q=b["q1"], q1=b["q"]) for b in A]
+        tables = [[plan.table([descr(b, pt, s, *roles[s]) for b, pt in zip(bufs, patches)])
+                   for s in range(3)] for bufs in (A, swapped)]
+        par = [0]
+
+        def step_batched():
+            for s in range(3):
+                plan(tables[par[0]][s], diag=diag)
+            par[0] ^= 1
+        B = alloc()
+        subs = [grhd.Substep(pt["grid"], eos_table[pt["eos_id"]], pt["metric"], opts) for pt in patches]
+        dg = grhd.new_diag()
+        calls = []
+        for bufs in (B, [dict(b, q=b["q1"], q1=b["q"]) for b in B]):
+            per = []
+            for s in range(3):
+                qn, qs, qo = roles[s]
+                per.append([sub.bind(dict(grhd.SSPRK3[s], dt=0.4 * pt["grid"]["dx"]), b[qn], b[qs],
+                                     b[qo], b["p"], diag=dg) for b, sub, pt in zip(bufs, subs, patches)])
+            calls.append(per)
+        parb = [0]
+
+        def step_loop():
+            for s in range(3):
+                for c in calls[parb[0]][s]:
+                    c()
+            parb[0] ^= 1
+        out = {}
+        for name, fn in (("batched", step_batched), ("per_patch_calls", step_loop)):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                fn()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            out[name] = 3 * zones * steps / wall
+        res[prec] = {"value": out["batched"], "per_patch_calls_value": out["per_patch_calls"],
+                     "speedup_vs_per_patch": out["batched"] / out["per_patch_calls"],
+                     "tiles": plan.tiles()}
+        plan.close()
+    return res
+
+
+def learned_form(args):
+    """Recovery of a 2048^2 differentially rotating field: Illinois from the
+    bracket (the paper's method) against Newton seeded by the matrix-core
+    MLP, trained here on GPU from GPU prim->con pairs of an independent
+    seed.  Both land on the same root (max relative primitive difference
+    reported); time and master-function evaluations per cell are compared."""
+    import torch
+
+    import synth
+    from paper_2502_03223_amd import grhd
+    dev = torch.device("cuda:0")
+    eos = synth.ideal_eos(2.0, 100.0)
+    c2p = dict(w_max=100.0, rho_atm=1e-12)
+    # ---- training pairs: (D, S, tau) -> P through the library's prim->con
+    npair = args.train_pairs
+    prims = synth.recovery_samples(12345, npair)
+    tg = synth.make_grid(npair, 1, 0.0, 0.0, 1.0, 1.0, "cart", ("outflow",) * 4)
+    ng = tg["ng"]
+    pt = torch.zeros((6, 1 + 2 * ng, tg["pitch"]), dtype=torch.float64, device=dev)
+    pt[:, ng, ng:ng + npair] = torch.from_numpy(prims.T.copy()).to(dev)
+    qt = torch.zeros((5,) + pt.shape[1:], dtype=torch.float64, device=dev)
+    grhd.prim2con(tg, eos, {}, pt, qt)
+    qi = qt[:, ng, ng:ng + npair]
+    X = grhd.recovery_features(qi)
+    y = torch.log10(pt[4, ng, ng:ng + npair] / qi[0])
+    xm, xs = X.mean(dim=0), X.std(dim=0)
+    ym, ys = y.mean(), y.std()
+    scal = torch.cat([xm, xs, ym.view(1), ys.view(1)]).float().contiguous()
+    Xs = ((X - xm) / xs).float().contiguous()
+    ts = ((y - ym) / ys).float().contiguous()
+    net = grhd.MLP(grhd.mlp_init(1), scal)
+    gen = torch.Generator(device=dev).manual_seed(1)
+    batch = 8192
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(args.train_steps):
+        idx = torch.randint(0, npair, (batch,), device=dev, generator=gen)
+        lr = 2e-3 * 0.5 * (1.0 + math.cos(math.pi * it / args.train_steps)) + 1e-5
+        net.train_step(Xs[idx].contiguous(), ts[idx].contiguous(), lr)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    _, full_loss = grhd.mlp_grad(net.params, Xs, ts)
+    # ---- the recovery workload
+    n = args.learned_n
+    grid = synth.make_grid(n, n, 0.0, 0.0, 20.0 / n, 20.0 / n, "cart", ("outflow",) * 4)
+    p = torch.from_numpy(synth.rotating_field(grid, 7)).to(dev)
+    q = torch.zeros((5,) + p.shape[1:], dtype=torch.float64, device=dev)
+    grhd.prim2con(grid, eos, {}, p, q)
+    res = {"zones": n * n, "train": {"pairs": npair, "steps": args.train_steps, "batch": batch,
+                                     "seconds": train_s, "mse_standardised": float(full_loss.cpu()[0])}}
+    outs = {}
+    for name, mlp in (("illinois", None), ("mlp_newton", net.buf)):
+        cp = dict(c2p, mlp=mlp)
+        pp = torch.zeros_like(p)
+        dg = grhd.new_diag()
+        qq = q.clone()
+        for _ in range(3):
+            qq.copy_(q)
+            grhd.con2prim(grid, eos, {}, cp, qq, pp, diag=dg)
+        reps = 10
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(reps)]
+        for r in range(reps):
+            qq.copy_(q)
+            evs[r][0].record()
+            grhd.con2prim(grid, eos, {}, cp, qq, pp, diag=dg)
+            evs[r][1].record()
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        d = grhd.read_diag(dg)
+        outs[name] = pp.clone()
+        res[name] = {"ms": ms, "zones_per_s": n * n / (ms * 1e-3),
+                     "evals_mean": d["iter_sum"] / (n * n), "evals_max": d["iter_max"],
+                     "n_fail": d["n_fail"], "n_atm": d["n_atm"]}
+    a = synth.interior(grid, outs["illinois"])
+    b = synth.interior(grid, outs["mlp_newton"])
+    rel = (b - a).abs() / a.abs().amax(dim=(1, 2), keepdim=True).clamp_min(1e-300)
+    res["max_rel_diff_vs_illinois"] = float(rel.max().cpu())
+    res["speedup"] = res["illinois"]["ms"] / res["mlp_newton"]["ms"]
+    return res
 
 
 def cpu_baseline(grid, eos, metric_np, p_np, c2p, dt, rows):
     """The oracle (single thread, plain C) on a horizontal band of the same
-    star grid: `rows` full rows through the stellar core, one SSP-RK3 step."""
+    star grid: its first `rows` full rows (all of it by default), one SSP-RK3
+    step."""
     import oracle
-    import synth
     oracle.build(force=False)
     ng = grid["ng"]
+    rows = min(rows, grid["nz"])
     band = dict(grid, nz=rows, z0=grid["z0"],
                 bc=(grid["bc"][0], grid["bc"][1], "reflect", "outflow"))
     sl = slice(0, rows + 2 * ng)
@@ -248,8 +452,8 @@ def cpu_baseline(grid, eos, metric_np, p_np, c2p, dt, rows):
     zones = band["nx"] * band["nz"] * 3
     return {"value": zones / el, "unit": "zone-updates/s", "cores": 1, "kind": "oracle",
             "sample": "oracle FP64 C (gcc -O2, 1 thread): one SSP-RK3 step (3 substeps) of "
-                      "the %dx%d star grid restricted to its first %d rows (%d zone-updates, %.1f s)"
-                      % (grid["nx"], grid["nz"], rows, zones, el)}
+                      "the first %d of %d rows of the %dx%d star grid (%d zone-updates, %.1f s)"
+                      % (rows, grid["nz"], grid["nx"], grid["nz"], zones, el)}
 
 
 if __name__ == "__main__":

@@ -785,14 +785,17 @@ __device__ __forceinline__ void sources(const double *g, const double *dg, doubl
     }
   }
   double vsq = vl[0] * vu[0] + vl[1] * vu[1] + vl[2] * vu[2];
-  double sg = 1.0 / (W * W * W);
+  // one division for the powers of 1/W (they differ from the quotients
+  // by a few ulp at most)
+  double iW = 1.0 / W;
+  double sg = iW * iW * iW;
   double rhw2 = rho * h * w * w;
   double sm[2];
   for (int d = 0; d < 2; d++) {
     const double *dd = dg + d * GRHD_NMET;
     double dalp = dd[GRHD_M_ALP], dW = dd[GRHD_M_W];
-    double dasg = dalp * sg + alp * (-3.0 * dW / (W * W * W * W));
-    double br = dalp + alp * vsq * dW / W;
+    double dasg = dalp * sg + alp * (-3.0 * dW * (sg * iW));
+    double br = dalp + alp * vsq * dW * iW;
     if (MC == MC_GEN) {
       double vdb = vl[0] * dd[GRHD_M_BX] + vl[1] * dd[GRHD_M_BY] + vl[2] * dd[GRHD_M_BZ];
       double vvdg = 0.0;

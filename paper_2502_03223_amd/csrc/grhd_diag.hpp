@@ -80,20 +80,21 @@ __device__ __forceinline__ void flux_block_partial(double cmax, double mb, doubl
   }
 }
 
-// Fold n1 recovery records and n2 stage records into diag, by one whole
-// workgroup of NTHR threads (every thread must call it).  red: NTHR/64 x 9
-// words of LDS.  Each thread folds a strided subset, then the waves reduce
-// by shuffles and thread 0 combines the wave results, always in the same
-// order.
-// Fold n1 recovery records and n2 stage records into diag, by one whole
-// workgroup of NTHR threads (every thread must call it).  red: NTHR/64 x 9
-// words of LDS.  Thread t folds records t, t + NTHR, t + 2 NTHR, ... in that
-// order (four loads in flight at a time), the waves reduce by shuffles and
-// thread 0 combines the wave results in wave order: the result depends only
-// on the record counts.
+// A folded set of records.
+struct FoldPart {
+  unsigned long long n[6];
+  double cmax, mb, jm;
+};
+
+// Fold records p1[0..n1) and p2[0..n2) by one whole workgroup of NTHR
+// threads (every thread must call it); the result is valid in thread 0.
+// red: NTHR/64 x 9 words of LDS.  Thread t folds records t, t + NTHR, ...
+// in that order (four loads in flight at a time), the waves reduce by
+// shuffles and thread 0 combines the wave results in wave order: the result
+// depends only on the record counts.
 template <int NTHR>
-__device__ void diag_fold(const C2PPart *p1, int n1, const FluxPart *p2, int n2, grhd_diag *diag,
-                          unsigned long long (*red)[9]) {
+__device__ FoldPart fold_records(const C2PPart *p1, int n1, const FluxPart *p2, int n2,
+                                 unsigned long long (*red)[9]) {
   int t = threadIdx.x;
   unsigned long long a[6] = {0, 0, 0, 0, 0, 0};
   double c = 0.0, mb = 0.0, jm = 0.0;
@@ -137,33 +138,24 @@ __device__ void diag_fold(const C2PPart *p1, int n1, const FluxPart *p2, int n2,
     red[w][8] = (unsigned long long)__double_as_longlong(jm);
   }
   __syncthreads();
+  FoldPart f{};
   if (t == 0) {
-    unsigned long long u[6];
-    for (int k = 0; k < 6; k++) u[k] = red[0][k];
-    double cc = __longlong_as_double((long long)red[0][6]);
-    double sb = __longlong_as_double((long long)red[0][7]);
-    double sj = __longlong_as_double((long long)red[0][8]);
+    for (int k = 0; k < 6; k++) f.n[k] = red[0][k];
+    f.cmax = __longlong_as_double((long long)red[0][6]);
+    f.mb = __longlong_as_double((long long)red[0][7]);
+    f.jm = __longlong_as_double((long long)red[0][8]);
     for (int ww = 1; ww < NTHR / 64; ww++) {
-      for (int k = 0; k < 5; k++) u[k] += red[ww][k];
-      u[5] = red[ww][5] > u[5] ? red[ww][5] : u[5];
-      cc = fmax(cc, __longlong_as_double((long long)red[ww][6]));
-      sb += __longlong_as_double((long long)red[ww][7]);
-      sj += __longlong_as_double((long long)red[ww][8]);
+      for (int k = 0; k < 5; k++) f.n[k] += red[ww][k];
+      f.n[5] = red[ww][5] > f.n[5] ? red[ww][5] : f.n[5];
+      f.cmax = fmax(f.cmax, __longlong_as_double((long long)red[ww][6]));
+      f.mb += __longlong_as_double((long long)red[ww][7]);
+      f.jm += __longlong_as_double((long long)red[ww][8]);
     }
-    diag->max_courant = cc;
-    diag->Mb = sb;
-    diag->J = sj;
-    diag->n_rescale = u[0];
-    diag->n_cold = u[1];
-    diag->n_atm = u[2];
-    diag->n_fail = u[3];
-    diag->iter_sum = u[4];
-    diag->iter_max = u[5];
   }
+  return f;
 }
 
-// stand-alone fold (one workgroup of 256 threads); defined once in
-// grhd_kernels.hip
+// fold into *diag by one workgroup; defined once in grhd_kernels.hip
 int launch_diag_final(const C2PPart *p1, int n1, const FluxPart *p2, int n2, grhd_diag *diag,
                       hipStream_t st);
 

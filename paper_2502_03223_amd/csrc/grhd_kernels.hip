@@ -41,11 +41,25 @@ int fail(int code, const char *fmt, ...) {
 
 // ------------------------------------------------------------ small kernels
 
-// fold n1 recovery records and n2 stage records into diag (fixed order)
+// Fold of the diagnostic records into *diag by one 1024-thread workgroup.
+// (Splitting the fold over several workgroups needs a device-scope release
+// by each of them, which writes back the XCD's L2 and costs more than the
+// single workgroup's serial part.)
 __global__ void __launch_bounds__(1024)
 k_diag_final(const C2PPart *p1, int n1, const FluxPart *p2, int n2, grhd_diag *diag) {
   __shared__ unsigned long long red[16][9];
-  diag_fold<1024>(p1, n1, p2, n2, diag, red);
+  FoldPart f = fold_records<1024>(p1, n1, p2, n2, red);
+  if (threadIdx.x == 0) {
+    diag->max_courant = f.cmax;
+    diag->Mb = f.mb;
+    diag->J = f.jm;
+    diag->n_rescale = f.n[0];
+    diag->n_cold = f.n[1];
+    diag->n_atm = f.n[2];
+    diag->n_fail = f.n[3];
+    diag->iter_sum = f.n[4];
+    diag->iter_max = f.n[5];
+  }
 }
 
 int launch_diag_final(const C2PPart *p1, int n1, const FluxPart *p2, int n2, grhd_diag *diag,
@@ -266,13 +280,14 @@ static std::vector<DiagScratch> g_scratch;
 
 void *diag_scratch(hipStream_t st, size_t bytes) {
   int dev = 0;
-  hipGetDevice(&dev);
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
   std::lock_guard<std::mutex> lk(g_scratch_mu);
   for (auto &s : g_scratch)
     if (s.dev == dev && s.st == st) {
       if (s.bytes >= bytes) return s.buf;
-      hipStreamSynchronize(st);
-      hipFree(s.buf);
+      // the old buffer may still be read by work queued on this stream
+      if (hipStreamSynchronize(st) != hipSuccess) return nullptr;
+      (void)hipFree(s.buf);
       s.buf = nullptr;
       s.bytes = 0;
       if (hipMalloc(&s.buf, bytes) != hipSuccess) return nullptr;

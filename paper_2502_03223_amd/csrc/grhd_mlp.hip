@@ -74,18 +74,20 @@ k_con2prim_mlp(GridK g, EosK e, C2PK cp, MetK m, Q5 q, P6 p, uint8_t *flags, C2P
   double S = sqrt(S2);
   double tau = E - D;
   bool good = act && D > 0.0 && E > 0.0 && tau > 0.0 && isfinite(S) && isfinite(E);
+  // features and guess in FP32: the guess only sets where the FP64 root
+  // search starts
   float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
   if (good) {
-    f0 = ((float)log10(D) - w->xm[0]) / w->xs[0];
+    f0 = (log10f((float)D) - w->xm[0]) / w->xs[0];
     f1 = ((float)(S / E) - w->xm[1]) / w->xs[1];
-    f2 = ((float)log10(tau / D) - w->xm[2]) / w->xs[2];
+    f2 = (log10f((float)(tau / D)) - w->xm[2]) / w->xs[2];
   }
   float y = mlp_forward_wave(w, f0, f1, f2);
   double zg = -1.0;
   if (good) {
-    double P0 = D * exp10((double)(y * w->ys + w->ym));
-    double v0 = S / (E + P0);
-    if (v0 >= 0.0 && v0 < 1.0) zg = v0 / sqrt(1.0 - v0 * v0);
+    float P0 = (float)D * exp10f(y * w->ys + w->ym);
+    float v0 = (float)S / ((float)E + P0);
+    if (v0 >= 0.0f && v0 < 1.0f) zg = (double)(v0 / sqrtf(1.0f - v0 * v0));
   }
   unsigned fl = 0;
   int iters = 0;

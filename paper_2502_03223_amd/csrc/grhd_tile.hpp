@@ -98,6 +98,7 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
   const int j0 = tx * TX, k0 = tz * TZ;
   const bool cyl = (g.geom == GRHD_GEOM_CYLINDRICAL);
   const T ra = (T)e.rho_atm, Pa = (T)e.P_atm, ea = (T)e.eps_atm;
+  const T cs_atm = tsqrt(eos_cs2<T>(e, ra, ea, Pa));
   __syncthreads();  // LDS of a previous tile (persistent loop) is free
 
   // ---- 1. stage primitives (and, for the conformally flat class, lapse
@@ -105,6 +106,9 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
   // loads, then all LDS stores, so each thread has every load in flight at
   // once.  Boundary conditions are an index map with velocity parities.
   {
+    // a tile whose halo lies inside the grid reads every cell where it is
+    // (no boundary map, no parities)
+    const bool inner = j0 >= 3 && j0 + TX + 3 <= nx && k0 >= 3 && k0 + TZ + 3 <= nz;
     long long src[LPT], im[LPT];
     bool use[LPT];
     double s0[LPT], s1[LPT], s2[LPT];
@@ -114,11 +118,16 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
       int jj = c % HX, kk = c / HX;
       int j = j0 - 3 + jj, k = k0 - 3 + kk;
       bool inx = (jj >= 3 && jj < 3 + TX), inz = (kk >= 3 && kk < 3 + TZ);
-      bool need = c < S::NC &&
-                  ((inx && j < nx && k >= -3 && k < nz + 3) || (inz && k < nz && j >= -3 && j < nx + 3));
       int js = j, ks = k;
       double sg[3] = {1.0, 1.0, 1.0};
-      if (need) need = ghost_map(g, j, k, js, ks, sg);
+      bool need;
+      if (inner) {
+        need = c < S::NC && (inx || inz);
+      } else {
+        need = c < S::NC &&
+               ((inx && j < nx && k >= -3 && k < nz + 3) || (inz && k < nz && j >= -3 && j < nx + 3));
+        if (need) need = ghost_map(g, j, k, js, ks, sg);
+      }
       use[i] = need;
       src[i] = need ? cell_index(g, js, ks) : 0;
       im[i] = need ? cell_index(g, j, k) : 0;
@@ -223,7 +232,15 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
           else fm.gt[fld - 5] = v;
         }
       }
-      if (uni) {
+      if (uni && MC == MC_CF) {
+        // the atmosphere at rest in a conformally flat metric without
+        // shift: of the physical flux only alpha W^-3 P in the normal
+        // momentum survives, and the signal speeds are -+ alpha c_s W
+        // (the physical-flux evaluation below reduces to exactly these)
+        T sg = T(1) / (fm.W * fm.W * fm.W);
+        out.f[isx ? 1 : 3] = sg * (fm.alp * Pa);
+        out.speed = fm.alp * (cs_atm * fm.W);
+      } else if (uni) {
         T Q[5], lm, lp, gtu[6];
         if (MC == MC_GEN) inv_sym3(fm.gt, gtu);
         valencia<T, MC>(e, fm, gtu, isx ? 0 : 2, L, out.f, Q, lm, lp);

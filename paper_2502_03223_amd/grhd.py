@@ -329,6 +329,25 @@ class Substep:
         _check(rc, "grhd_rk_substep")
 
 
+    def bind(self, stage, qn, qs, qout, p, diag=None, stream=None):
+        """A call of this substep with every argument marshalled once (for
+        loops that repeat the same calls)."""
+        L = lib()
+        st = make_stage(stage) if isinstance(stage, dict) else stage
+        args = (C.byref(self.grid), C.byref(self.eos), C.byref(self.metric), C.byref(self.opts),
+                C.byref(st), C.byref(make_cons(qn if qn is not None else qs)),
+                C.byref(make_cons(qs)), C.byref(make_cons(qout)), C.byref(make_prim(p)), None, None,
+                C.c_void_p(0), C.c_void_p(0),
+                C.c_void_p(diag.data_ptr() if diag is not None else 0),
+                C.c_void_p(stream) if stream is not None else _stream())
+        keep = (st, qn, qs, qout, p, diag)
+
+        def call():
+            _check(L.grhd_rk_substep(*args), "grhd_rk_substep")
+        call.keep = keep
+        return call
+
+
 def rk_substep(grid, eos, metric, opts, stage, qn, qs, qout, p, **kw):
     Substep(grid, eos, metric, opts)(stage, qn, qs, qout, p, **kw)
 
@@ -372,8 +391,13 @@ class Plan:
                                     C.byref(self.handle))
         _check(rc, "grhd_plan_create")
 
+    def table(self, patches):
+        """Marshalled patch table, reusable across calls with the same
+        buffers and stages."""
+        return (Patch * self.n)(*[make_patch(d) for d in patches])
+
     def __call__(self, patches, diag=None, stream=None):
-        arr = (Patch * self.n)(*[make_patch(d) for d in patches])
+        arr = patches if isinstance(patches, C.Array) else self.table(patches)
         rc = lib().grhd_batch_levels(self.handle, arr, self.n,
                                      C.c_void_p(diag.data_ptr() if diag is not None else 0),
                                      C.c_void_p(stream) if stream is not None else _stream())
