@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--cpu-sample-rows", type=int, default=1024)
     ap.add_argument("--learned-n", type=int, default=2048)
     ap.add_argument("--train-pairs", type=int, default=1 << 20)
-    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--train-steps", type=int, default=10000)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB three "
                          "times (calibrates HBM byte counters against a known size)")

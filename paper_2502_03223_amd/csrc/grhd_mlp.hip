@@ -19,22 +19,28 @@ namespace grhd {
 // standalone forward: X holds standardised features (n x 3), y receives
 // the network output
 __global__ void __launch_bounds__(256) k_mlp_forward(const MlpDev *w, const float *X, float *y, int n) {
+  __shared__ MlpDev sw;
+  mlp_stage<256>(w, &sw);
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   bool act = i < n;
   float x0 = act ? X[3 * i] : 0.0f, x1 = act ? X[3 * i + 1] : 0.0f, x2 = act ? X[3 * i + 2] : 0.0f;
-  float o = mlp_forward_wave(w, x0, x1, x2);
+  float o = mlp_forward_wave(&sw, x0, x1, x2);
   if (act) y[i] = o;
 }
 
 // Recovery seeded by the network: features (log10 D, S/E, log10(tau/D)),
 // output log10(P/D); the guess P0 gives v0 = S/(E + P0) and
 // z0 = v0 / sqrt(1 - v0^2), from which a safeguarded Newton solve starts.
+// The workgroup stages the weights in LDS once; its waves read their
+// operand fragments from there.
 template <int MC, int EK>
 __global__ void __launch_bounds__(256)
 k_con2prim_mlp(GridK g, EosK e, C2PK cp, MetK m, Q5 q, P6 p, uint8_t *flags, C2PPart *part,
                int jlo, int jhi, int klo) {
   __shared__ unsigned long long red[4][6];
-  const MlpDev *w = (const MlpDev *)cp.mlp;
+  __shared__ MlpDev sw;
+  mlp_stage<256>((const MlpDev *)cp.mlp, &sw);
+  const MlpDev *w = &sw;
   int j = jlo + blockIdx.x * blockDim.x + threadIdx.x;
   int k = klo + blockIdx.y;
   bool act = j < jhi;
@@ -93,9 +99,9 @@ k_con2prim_mlp(GridK g, EosK e, C2PK cp, MetK m, Q5 q, P6 p, uint8_t *flags, C2P
   int iters = 0;
   if (act) {
     double pp[6];
-    C2PResult r = con2prim_cell<MC, EK>(e, cp, W, gtu, x, g.geom, qq, pp, zg);
-    fl = r.flags;
-    iters = r.iters;
+    C2PResult res = con2prim_cell<MC, EK>(e, cp, W, gtu, x, g.geom, qq, pp, zg);
+    fl = res.flags;
+    iters = res.iters;
     if (fl)
       for (int c = 0; c < 5; c++) q.q[c][i] = qq[c];
     for (int c = 0; c < 6; c++) p.p[c][i] = pp[c];
@@ -238,11 +244,16 @@ __global__ void k_adam(float *P, float *m, float *v, const float *g, float lr, f
 // scal (nullable): feature mean[3], std[3], target mean, std
 __global__ void k_mlp_pack(MlpDev *w, const float *P, const float *scal) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < MLP_H * 16) {
-    int u = i / 16, k = i % 16;
-    w->W1[i] = (k < 3) ? f2bf(P[OFF_W1 + u * 3 + k]) : (uint16_t)0;
+  if (i < 4 * 64 * 4) {  // W1op[mb][l][e]
+    int mb = i / 256, l = (i / 4) % 64, el = i % 4;
+    int u = mb * 16 + (l & 15), k = 4 * (l >> 4) + el;
+    w->W1op[mb][l][el] = (k < 3) ? f2bf(P[OFF_W1 + u * 3 + k]) : (uint16_t)0;
   }
-  if (i < MLP_H * MLP_H) w->W2[i] = f2bf(P[OFF_W2 + i]);
+  if (i < 4 * 4 * 64 * 4) {  // W2op[mb][kb][l][e]
+    int mb = i / 1024, kb = (i / 256) % 4, l = (i / 4) % 64, el = i % 4;
+    int u = mb * 16 + (l & 15), k = 16 * kb + 4 * (l >> 4) + el;
+    w->W2op[mb][kb][l][el] = f2bf(P[OFF_W2 + u * MLP_H + k]);
+  }
   if (i < MLP_H) {
     w->b1[i] = P[OFF_B1 + i];
     w->b2[i] = P[OFF_B2 + i];

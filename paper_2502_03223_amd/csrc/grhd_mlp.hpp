@@ -15,17 +15,23 @@ namespace grhd {
 
 constexpr int MLP_H = 64;
 
-// Device weight buffer (grhd_mlp_bytes() bytes).  W1 is padded from 3 to
-// 16 inputs so layer 1 is one MFMA K-step; rows are output units.
+// Device weight buffer (grhd_mlp_bytes() bytes), matrices in matrix-core
+// operand order: the fragment that lane l (r = l % 16, g = l / 16) feeds to
+// the 16x16x16 instruction for unit block mb (and input block kb) is four
+// consecutive BF16 values, so a wave reads each operand as one contiguous
+// 512-byte run.
+//   W1op[mb][l][i] = W1[16 mb + r][4 g + i]   (inputs 3..15 are zero)
+//   W2op[mb][kb][l][i] = W2[16 mb + r][16 kb + 4 g + i]
 struct MlpDev {
-  uint16_t W1[MLP_H * 16];    // bf16 [out][16], inputs 3..15 zero
-  uint16_t W2[MLP_H * MLP_H]; // bf16 [out][in]
+  uint16_t W1op[4][64][4];
+  uint16_t W2op[4][4][64][4];
   float b1[MLP_H], b2[MLP_H], w3[MLP_H];
   float b3;
   float xm[3], xs[3];         // feature standardisation (mean, std)
   float ym, ys;               // target scaling
-  float pad[53];
+  float pad[55];
 };
+static_assert(sizeof(MlpDev) % 16 == 0, "MlpDev is copied in 16-byte words");
 
 // FP32 master parameter vector order (GRHD_MLP_NPARAM floats), same as the
 // FP64 reference: W1[64][3], b1[64], W2[64][64], b2[64], w3[64], b3
@@ -49,28 +55,28 @@ __host__ __device__ __forceinline__ float bf2f(uint16_t b) {
 }
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16v8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// four FP32 values to a BF16 operand fragment (round to nearest even,
-// hardware pack-converts)
-__device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
-  __bf16 ha = (__bf16)a, hb = (__bf16)b, hc = (__bf16)c, hd = (__bf16)d;
-  bf16x4 v;
-  v[0] = __builtin_bit_cast(short, ha);
-  v[1] = __builtin_bit_cast(short, hb);
-  v[2] = __builtin_bit_cast(short, hc);
-  v[3] = __builtin_bit_cast(short, hd);
-  return v;
+// four FP32 values to a BF16 operand fragment: two dwords, each a
+// round-to-nearest-even pack of two values
+__device__ __forceinline__ u32x2 pack4(float a, float b, float c, float d) {
+  bf16x2v lo = {(__bf16)a, (__bf16)b}, hi = {(__bf16)c, (__bf16)d};
+  return u32x2{__builtin_bit_cast(unsigned int, lo), __builtin_bit_cast(unsigned int, hi)};
 }
 
-__device__ __forceinline__ bf16v8 cat8(bf16x4 lo, bf16x4 hi) {
-  bf16v8 v;
-  for (int i = 0; i < 4; i++) {
-    v[i] = __builtin_bit_cast(__bf16, lo[i]);
-    v[4 + i] = __builtin_bit_cast(__bf16, hi[i]);
-  }
-  return v;
+__device__ __forceinline__ f32x4 mfma16(u32x2 a, u32x2 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4, a), __builtin_bit_cast(bf16x4, b),
+                                                   c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x4 mfma32(u32x2 a_lo, u32x2 a_hi, u32x2 b_lo, u32x2 b_hi, f32x4 c) {
+  u32x4 a = {a_lo.x, a_lo.y, a_hi.x, a_hi.y}, b = {b_lo.x, b_lo.y, b_hi.x, b_hi.y};
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16v8, a), __builtin_bit_cast(bf16v8, b), c,
+                                                 0, 0, 0);
 }
 
 // Forward pass for the 64 lanes of a wave: lane l holds the standardised
@@ -87,53 +93,73 @@ __device__ __forceinline__ bf16v8 cat8(bf16x4 lo, bf16x4 hi) {
 // 32 K indices of a lane group as (units 32p+4g..+3, units 32p+16+4g..+3);
 // the W2 columns are loaded in that same order, and a sum over K does not
 // depend on its order.  Biases enter as the accumulator's initial value.
-__device__ __forceinline__ float mlp_forward_wave(const MlpDev *__restrict__ w, float x0, float x1,
-                                                  float x2) {
+// Operands are assembled from whole dwords (two BF16 each).
+struct MlpRegs {
+  u32x2 a1[4], a2[4][4];
+  f32x4 c1[4], c2[4], o3[4];
+  float b3;
+};
+
+// this lane's share of the weights, from a weight buffer in global memory
+// or in LDS
+__device__ __forceinline__ MlpRegs mlp_load(const MlpDev *__restrict__ w) {
+  const int l = threadIdx.x & 63;
+  const int g = l >> 4;
+  MlpRegs R;
+  for (int mb = 0; mb < 4; mb++) {
+    R.a1[mb] = *(const u32x2 *)&w->W1op[mb][l][0];
+    for (int kb = 0; kb < 4; kb++) R.a2[mb][kb] = *(const u32x2 *)&w->W2op[mb][kb][l][0];
+    R.c1[mb] = *(const f32x4 *)&w->b1[mb * 16 + 4 * g];
+    R.c2[mb] = *(const f32x4 *)&w->b2[mb * 16 + 4 * g];
+    R.o3[mb] = *(const f32x4 *)&w->w3[mb * 16 + 4 * g];
+  }
+  R.b3 = w->b3;
+  return R;
+}
+
+// copy of the weight buffer into LDS by a whole workgroup (every thread
+// calls it; a barrier follows the copy)
+template <int NTHR>
+__device__ __forceinline__ void mlp_stage(const MlpDev *__restrict__ w, MlpDev *sw) {
+  const u32x4 *src = (const u32x4 *)w;
+  u32x4 *dst = (u32x4 *)sw;
+  constexpr int N = sizeof(MlpDev) / 16;
+  for (int i = threadIdx.x; i < N; i += NTHR) dst[i] = src[i];
+  __syncthreads();
+}
+
+__device__ __forceinline__ float mlp_forward_regs(const MlpRegs &R, float x0, float x1, float x2) {
   const int l = threadIdx.x & 63;
   const int r = l & 15, g = l >> 4;
-  bf16x4 a1[4];
-  bf16v8 a2[4][2];
-  f32x4 c1[4], c2[4], o3[4];
-  for (int mb = 0; mb < 4; mb++) {
-    const uint16_t *src = &w->W1[(mb * 16 + r) * 16 + 4 * g];
-    a1[mb] = bf16x4{(short)src[0], (short)src[1], (short)src[2], (short)src[3]};
-    for (int p = 0; p < 2; p++) {
-      const uint16_t *lo = &w->W2[(mb * 16 + r) * MLP_H + 32 * p + 4 * g];
-      const uint16_t *hi = lo + 16;
-      a2[mb][p] = cat8(bf16x4{(short)lo[0], (short)lo[1], (short)lo[2], (short)lo[3]},
-                       bf16x4{(short)hi[0], (short)hi[1], (short)hi[2], (short)hi[3]});
-    }
-    for (int i = 0; i < 4; i++) {
-      int u = mb * 16 + 4 * g + i;
-      c1[mb][i] = w->b1[u];
-      c2[mb][i] = w->b2[u];
-      o3[mb][i] = w->w3[u];
-    }
-  }
-  const float b3 = w->b3;
   float y = 0.0f;
   for (int cb = 0; cb < 4; cb++) {
     // layer-1 input tile: inputs 0..2 of cells cb*16 + r live in lanes g = 0
     int src = cb * 16 + r;
     float f0 = __shfl(x0, src, 64), f1 = __shfl(x1, src, 64), f2 = __shfl(x2, src, 64);
-    bf16x4 xb = (g == 0) ? pack4(f0, f1, f2, 0.0f) : bf16x4{0, 0, 0, 0};
-    bf16x4 h1[4];
+    u32x2 xb = (g == 0) ? pack4(f0, f1, f2, 0.0f) : u32x2{0u, 0u};
+    u32x2 h1[4];
     for (int mb = 0; mb < 4; mb++) {
-      f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[mb], xb, c1[mb], 0, 0, 0);
+      f32x4 acc = mfma16(R.a1[mb], xb, R.c1[mb]);
       h1[mb] = pack4(fmaxf(acc[0], 0.0f), fmaxf(acc[1], 0.0f), fmaxf(acc[2], 0.0f), fmaxf(acc[3], 0.0f));
     }
-    bf16v8 hb[2] = {cat8(h1[0], h1[1]), cat8(h1[2], h1[3])};
     float part = 0.0f;
     for (int mb = 0; mb < 4; mb++) {
-      f32x4 acc = c2[mb];
-      for (int p = 0; p < 2; p++) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[mb][p], hb[p], acc, 0, 0, 0);
-      for (int i = 0; i < 4; i++) part += o3[mb][i] * fmaxf(acc[i], 0.0f);
+      f32x4 acc = R.c2[mb];
+      for (int p = 0; p < 2; p++)
+        acc = mfma32(R.a2[mb][2 * p], R.a2[mb][2 * p + 1], h1[2 * p], h1[2 * p + 1], acc);
+      for (int i = 0; i < 4; i++) part += R.o3[mb][i] * fmaxf(acc[i], 0.0f);
     }
     part += __shfl_xor(part, 16, 64);
     part += __shfl_xor(part, 32, 64);
-    if (g == cb) y = part + b3;
+    if (g == cb) y = part + R.b3;
   }
   return y;
+}
+
+__device__ __forceinline__ float mlp_forward_wave(const MlpDev *__restrict__ w, float x0, float x1,
+                                                  float x2) {
+  MlpRegs R = mlp_load(w);
+  return mlp_forward_regs(R, x0, x1, x2);
 }
 
 }  // namespace grhd
