@@ -331,6 +331,38 @@ __device__ C2PResult con2prim_cell(const EosK &e, const C2PK &cp, double W, cons
         // evaluations Illinois finishes on the narrowed bracket
         bool ta = false, tb = false;
         double zz = fmin(fmax(zguess, zm), zp);
+        if (EK == GRHD_EOS_IDEAL) {
+          // the guess is first refined by Newton in FP32 (to about 1e-6
+          // relative, clamped to the bracket), which is far cheaper than
+          // FP64 evaluations; the FP64 iteration then starts next to the
+          // root
+          const float zmf = (float)zm, zpf = (float)zp, qf = (float)qq, rf = (float)r, Gf = (float)e.Gth;
+          float zf = fminf(fmaxf((float)zz, zmf), zpf);
+          for (int it = 0; it < 4; it++) {
+            float w = sqrtf(1.0f + zf * zf);
+            float eps = w * qf - zf * rf + zf * zf / (1.0f + w);
+            float f, df;
+            if (eps > 0.0f) {
+              float ih = 1.0f / (1.0f + Gf * eps);
+              f = zf - rf * ih;
+              df = 1.0f + rf * Gf * (zf * (1.0f + qf) / w - rf) * ih * ih;
+            } else {
+              f = zf - rf;
+              df = 1.0f;
+            }
+            res.iters += 1;
+            float zn = fminf(fmaxf(zf - f / df, zmf), zpf);
+            float dz = fabsf(zn - zf);
+            zf = zn;
+            if (!(dz > 1e-6f * zf)) break;
+          }
+          zz = fmin(fmax((double)zf, zm), zp);
+        }
+        // Converged when a step is below the tolerance, or when two Newton
+        // steps in a row (no bisection, no end test) were taken and the
+        // second moved z by at most 1e-9 z: in the quadratic regime the
+        // point it lands on is then within rounding of the root.
+        bool prev_newton = false;
         for (int it = 0; it < 8; it++) {
           double f0, df;
           c2p_f_df<EK>(e, D, qq, r, zz, f0, df);
@@ -343,18 +375,21 @@ __device__ C2PResult con2prim_cell(const EosK &e, const C2PK &cp, double W, cons
           if (f0 < 0.0) { za = zz; ta = true; }
           else { zb = zz; tb = true; }
           double zn = zz - f0 / df;
+          bool newton = true;
           if (!(zn > za && zn < zb)) {
+            newton = false;
             if (zn >= zb && !tb) zn = zb;
             else if (zn <= za && !ta) zn = za;
             else zn = 0.5 * (za + zb);
           }
           double dz = fabs(zn - zz);
           zz = zn;
-          if (dz <= cp.tol * zz) {
+          if (dz <= cp.tol * zz || (newton && prev_newton && dz <= 1e-9 * zz)) {
             z = zz;
             done = true;
             break;
           }
+          prev_newton = newton;
         }
       }
       if (!done) z = illinois<EK, false>(e, D, qq, r, za, zb, cp.tol, cp.max_iter, &res.iters);
