@@ -41,6 +41,38 @@ HBM_PEAK_GBS = 8000.0
 # (5 x 8) read, q_out (5 x 8) written; stages 2 and 3 also read q^n (5 x 8).
 BYTES_KERNEL = [144.0, 184.0, 184.0]
 ALL_FORMS = ("fp64", "mixed", "batched", "learned")
+# measured HBM traffic of the fused kernel (rocprofv3 FETCH_SIZE/WRITE_SIZE,
+# calibrated with a plain copy) is kept with the hash of the sources it was
+# measured on; it is reported only while the sources still hash the same
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_substep_star1024_counters.md")
+KERNEL_SOURCES = ["paper_2502_03223_amd/csrc/" + f for f in
+                  ("grhd_tile.hpp", "grhd_dev.hpp", "grhd_diag.hpp", "grhd_host.hpp", "grhd_kernels.hip")] + \
+                 ["paper_2502_03223_amd/build.py"]
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """(bytes per launch, source hash) recorded with the counter profile, or
+    None when absent or taken on other sources."""
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and line.split(":", 1)[0].strip() in ("traffic_bytes_per_launch", "source_sha256"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip().strip("`")
+        if kv.get("source_sha256") != kernel_sources_hash():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -53,6 +85,7 @@ def parse():
     ap.add_argument("--accuracy-substeps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=1024)
+    ap.add_argument("--cpu-sample-steps", type=int, default=3)
     ap.add_argument("--learned-n", type=int, default=2048)
     ap.add_argument("--train-pairs", type=int, default=1 << 20)
     ap.add_argument("--train-steps", type=int, default=10000)
@@ -157,6 +190,8 @@ def main():
     bytes_per_launch = float(np.mean(BYTES_KERNEL)) * nzone
     achieved = bytes_per_launch / (float(r64["kernel_ms"].mean()) * 1e-3) / 1e9
     diag = r64["diag"]
+    tb = measured_traffic()
+    traffic = tb / (float(r64["kernel_ms"].mean()) * 1e-3) / 1e9 if tb else None
     out_forms["fp64"] = {"value": value, "ms_per_step": ms_per_step,
                          "kernel_ms": r64["kernel_ms"].tolist(), "stage_ms": r64["stage_ms"].tolist()}
     print("fp64 done: %.3e zone-updates/s" % value, file=sys.stderr, flush=True)
@@ -179,7 +214,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(grid, eos, metric_np, p_np, c2p, dt, args.cpu_sample_rows)
+        cpu = cpu_baseline(grid, eos, metric_np, p_np, c2p, dt, args.cpu_sample_rows, args.cpu_sample_steps)
 
     out = {
         "metric": "zone-updates/s per GRHD RK substep at 1 GPU, FP64 plain vs mixed/batched",
@@ -201,9 +236,13 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "k_substep<double> (fused reconstruction, flux, divergence, sources, stage)",
             "bytes_per_zone": BYTES_KERNEL, "kernel_ms": r64["kernel_ms"].tolist(),
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "measured_bytes_per_launch": tb,
+            "traffic_note": "traffic = measured HBM bytes per launch (FETCH x2 + WRITE x1, factors "
+                            "from a 256 MiB copy) / the same mean launch time, in GB/s",
         },
         "forms": out_forms,
         "diag_last_stage": dict({k: diag[k] for k in ("max_courant", "Mb", "n_atm", "n_cold",
@@ -424,10 +463,10 @@ def learned_form(args):
     return res
 
 
-def cpu_baseline(grid, eos, metric_np, p_np, c2p, dt, rows):
+def cpu_baseline(grid, eos, metric_np, p_np, c2p, dt, rows, steps):
     """The oracle (single thread, plain C) on a horizontal band of the same
-    star grid: its first `rows` full rows (all of it by default), one SSP-RK3
-    step."""
+    star grid: its first `rows` full rows (all of it by default), `steps`
+    SSP-RK3 steps from the same initial data."""
     import oracle
     oracle.build(force=False)
     ng = grid["ng"]
@@ -440,20 +479,22 @@ def cpu_baseline(grid, eos, metric_np, p_np, c2p, dt, rows):
     q = oracle.prim2con(band, eos, met, p, with_ghosts=True)
     opts = dict(recon="ppm", riemann="hllc", c2p=c2p)
     t0 = time.perf_counter()
-    qn = q
-    qs = q
-    for s in [dict(a=0.0, b=1.0, c=1.0), dict(a=0.75, b=0.25, c=0.25),
-              dict(a=1.0 / 3.0, b=2.0 / 3.0, c=2.0 / 3.0)]:
-        r = oracle.rk_substep(band, eos, met, opts, dict(s, dt=dt), qn, qs)
-        if s["a"] == 0.0:
-            qn = r["qs"]
-        qs = r["qout"]
+    for _ in range(steps):
+        qn = q
+        qs = q
+        for s in [dict(a=0.0, b=1.0, c=1.0), dict(a=0.75, b=0.25, c=0.25),
+                  dict(a=1.0 / 3.0, b=2.0 / 3.0, c=2.0 / 3.0)]:
+            r = oracle.rk_substep(band, eos, met, opts, dict(s, dt=dt), qn, qs)
+            if s["a"] == 0.0:
+                qn = r["qs"]
+            qs = r["qout"]
+        q = qs
     el = time.perf_counter() - t0
-    zones = band["nx"] * band["nz"] * 3
+    zones = band["nx"] * band["nz"] * 3 * steps
     return {"value": zones / el, "unit": "zone-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "oracle FP64 C (gcc -O2, 1 thread): one SSP-RK3 step (3 substeps) of "
+            "sample": "oracle FP64 C (gcc -O2, 1 thread): %d SSP-RK3 steps (3 substeps each) of "
                       "the first %d of %d rows of the %dx%d star grid (%d zone-updates, %.1f s)"
-                      % (rows, grid["nz"], grid["nx"], grid["nz"], zones, el)}
+                      % (steps, rows, grid["nz"], grid["nx"], grid["nz"], zones, el)}
 
 
 if __name__ == "__main__":

@@ -171,7 +171,8 @@ int plan_tiles(grhd_plan *pl, int a, int b, std::vector<PatchK> &hp) {
     int tx, tz;
     if (hp[i].g.nz <= 8) { tx = kThin[a][0]; tz = kThin[a][1]; }
     else { tx = kSquare[b][0]; tz = kSquare[b][1]; }
-    hp[i].tiles_x = (hp[i].g.nx + tx - 1) / tx;
+    hp[i].xshift = tile_xshift(hp[i].g.ng, tx);
+    hp[i].tiles_x = (hp[i].g.nx + hp[i].xshift + tx - 1) / tx;
     hp[i].tiles_z = (hp[i].g.nz + tz - 1) / tz;
     pl->tile_prefix[i] = acc;
     acc += (long long)hp[i].tiles_x * hp[i].tiles_z;

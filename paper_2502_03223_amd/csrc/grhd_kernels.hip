@@ -235,7 +235,9 @@ k_substep(PatchK P, EosK e, FluxPart *part2) {
   __shared__ double red[NT / 64][3];
   const int t = blockIdx.x;
   double cm, mb, jm;
-  substep_tile<T, MC, TX, TZ>(P, e, t % P.tiles_x, t / P.tiles_x, sm, cm, mb, jm);
+  int tx, tz;
+  tile_of(t, P.tiles_x, P.tiles_z, tx, tz);
+  substep_tile<T, MC, TX, TZ>(P, e, tx, tz, sm, cm, mb, jm);
   if (part2) flux_block_partial<NT>(cm, mb, jm, &part2[t], red);
 }
 
@@ -556,7 +558,8 @@ extern "C" int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos, const
   }
   int tx, tz;
   shape_of(shape, &tx, &tz);
-  pk.tiles_x = (grid->nx + tx - 1) / tx;
+  pk.xshift = tile_xshift(grid->ng, tx);
+  pk.tiles_x = (grid->nx + pk.xshift + tx - 1) / tx;
   pk.tiles_z = (grid->nz + tz - 1) / tz;
   hipStream_t st = (hipStream_t)hip_stream;
   EosK e = to_eosk(eos, opts->c2p.rho_atm);

@@ -24,8 +24,29 @@ struct PatchK {
   int use_qn, use_acc_in, use_acc_out;
   int recon, riemann, eos_id;
   int tiles_x, tiles_z;
+  int xshift;  // tile tx covers cells j in [tx TX - xshift, (tx + 1) TX - xshift)
   long long tile_base;
 };
+
+// Tile layout of a patch: tiles start xshift = ng mod TX cells left of the
+// interior, so with rows aligned to 128 bytes (pitch a multiple of 16
+// doubles) every tile row segment starts on a line boundary.
+__host__ __device__ inline int tile_xshift(int ng, int TX) { return ng % TX; }
+
+// Order of the tiles of one patch over the workgroups: stripes of 8 tile
+// columns, each stripe row by row.  Workgroups are dealt to the 8 XCDs
+// round-robin, so in a full stripe each XCD owns one tile column: tiles
+// above and below one another share their z halo in one L2, and any
+// spatially compact heavy region spreads over all XCDs.
+__host__ __device__ inline void tile_of(long long t, int tiles_x, int tiles_z, int &tx, int &tz) {
+  long long per = 8LL * tiles_z;
+  int s = (int)(t / per);
+  int rem = (int)(t - per * s);
+  int w = tiles_x - 8 * s;
+  if (w > 8) w = 8;
+  tz = rem / w;
+  tx = 8 * s + rem % w;
+}
 
 template <class T, int MC, int TX, int TZ>
 struct TileSmem {
@@ -95,7 +116,7 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
   const GridK &g = P.g;
   const int tid = threadIdx.x;
   const int nx = g.nx, nz = g.nz;
-  const int j0 = tx * TX, k0 = tz * TZ;
+  const int j0 = tx * TX - P.xshift, k0 = tz * TZ;
   const bool cyl = (g.geom == GRHD_GEOM_CYLINDRICAL);
   const T ra = (T)e.rho_atm, Pa = (T)e.P_atm, ea = (T)e.eps_atm;
   const T cs_atm = tsqrt(eos_cs2<T>(e, ra, ea, Pa));
@@ -181,7 +202,7 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
       base = kk * HX + jj + 3; stride = HX;
     }
     const int j = j0 + jj, k = k0 + kk;
-    const bool valid = isx ? (k < nz && j <= nx) : (j < nx && k <= nz);
+    const bool valid = isx ? (k < nz && j >= 0 && j <= nx) : (j >= 0 && j < nx && k <= nz);
     FluxT<T> out;
     for (int m = 0; m < 5; m++) out.f[m] = T(0);
     if (valid) {
@@ -273,7 +294,7 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
     int c = tid + ci * NT;
     int jj = c % TX, kk = c / TX;
     int j = j0 + jj, k = k0 + kk;
-    if (!(c < TX * TZ && j < nx && k < nz)) continue;
+    if (!(c < TX * TZ && j >= 0 && j < nx && k < nz)) continue;
     long long ic = cell_index(g, j, k);
     // state loads first: their latency overlaps the flux arithmetic below
     double qs5[5], qn5[5], ai5[5];
