@@ -69,6 +69,7 @@ k_con2prim_batch(const PatchK *__restrict__ pt, const EosK *__restrict__ eos, C2
     if (fl)
       for (int c = 0; c < 5; c++) P.qs[c][i] = qq[c];
     for (int c = 0; c < 6; c++) P.p[c][i] = pp[c];
+    if (P.flags) P.flags[i] = (uint8_t)fl;
   }
   if (part) c2p_block_partial<256>(act, fl, iters, &part[blockIdx.x], red);
 }
@@ -160,6 +161,8 @@ struct grhd_plan {
   C2PPart *d_part1 = nullptr;       // diagnostic records: recovery workgroups,
   FluxPart *d_part2 = nullptr;      // stage tiles
   long long part2_cap = 0;
+  uint8_t *d_flags = nullptr;       // recovery flags of every patch, read by
+  std::vector<size_t> flag_off, flag_bytes;  // the stage (atmosphere tiles)
 };
 
 namespace {
@@ -196,6 +199,9 @@ int build_patch_table(grhd_plan *pl, const grhd_patch *patches, std::vector<Patc
         P.grid.bc[2] == GRHD_BC_EXTERNAL || P.grid.bc[3] == GRHD_BC_EXTERNAL)
       return fail(GRHD_ERR_UNSUPPORTED, "patch %d: EXTERNAL boundaries are not batched", i);
     hp[i].eos_id = P.eos_id;
+    size_t fb = (size_t)(P.grid.nz + 2 * P.grid.ng) * (size_t)P.grid.pitch;
+    if (fb > pl->flag_bytes[i]) return fail(GRHD_ERR_INVALID, "patch %d layout differs from the plan", i);
+    hp[i].flags = pl->d_flags ? pl->d_flags + pl->flag_off[i] : nullptr;
   }
   return GRHD_OK;
 }
@@ -347,6 +353,7 @@ void destroy_plan(grhd_plan *pl) {
   hipFree(pl->d_diag);
   hipFree(pl->d_part1);
   hipFree(pl->d_part2);
+  hipFree(pl->d_flags);
   delete pl;
 }
 
@@ -376,11 +383,16 @@ extern "C" int grhd_plan_create(const grhd_patch *patches, int npatch, const grh
   pl->opts = *opts;
   pl->cp = to_c2pk(&opts->c2p);
   pl->mc = MC_CF;
+  size_t flag_total = 0;
   for (int i = 0; i < npatch; i++) {
     if ((rc = check_metric(&patches[i].metric))) { destroy_plan(pl); return rc; }
     if (metric_class(&patches[i].metric) == MC_GEN) pl->mc = MC_GEN;
     pl->nx.push_back(patches[i].grid.nx);
     pl->nz.push_back(patches[i].grid.nz);
+    pl->flag_off.push_back(flag_total);
+    size_t fb = (size_t)(patches[i].grid.nz + 2 * patches[i].grid.ng) * (size_t)patches[i].grid.pitch;
+    pl->flag_bytes.push_back(fb);
+    flag_total += (fb + 255) & ~(size_t)255;
   }
   std::vector<PatchK> hp;
   if ((rc = build_patch_table(pl, patches, hp))) { destroy_plan(pl); return rc; }
@@ -400,6 +412,7 @@ extern "C" int grhd_plan_create(const grhd_patch *patches, int npatch, const grh
              hipMalloc(&pl->d_item_prefix, sizeof(long long) * npatch) == hipSuccess &&
              hipMalloc(&pl->d_diag, sizeof(grhd_diag)) == hipSuccess &&
              hipMalloc(&pl->d_part1, sizeof(C2PPart) * pl->total_items) == hipSuccess &&
+             hipMalloc(&pl->d_flags, flag_total) == hipSuccess &&
              hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking) == hipSuccess;
   for (int s = 0; okm && s < grhd_plan::kSlots; s++)
     okm = hipHostMalloc((void **)&pl->h_slots[s], sizeof(PatchK) * npatch, hipHostMallocDefault) == hipSuccess &&

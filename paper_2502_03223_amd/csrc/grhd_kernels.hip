@@ -265,27 +265,29 @@ static SubstepFn substep_kernel(int prec, int mc, int shape) {
   return mc == MC_GEN ? pick_shape<double, MC_GEN>(shape) : pick_shape<double, MC_CF>(shape);
 }
 
-// Library-owned device scratch for the partial records of the
-// diagnostics, one buffer per (device, stream), allocated on the first call
-// that asks for diagnostics and grown when a larger grid needs more.  Calls
-// that overlap on one stream are ordered by the stream; different streams
-// use different buffers.  The first such call on a stream allocates: make
-// it before capturing calls into a graph.
-struct DiagScratch {
+// Library-owned device scratch, one buffer per (device, stream, use):
+// use 0 holds the partial records of the diagnostics, use 1 the recovery
+// flags of a substep whose caller passes none.  A buffer is allocated on
+// first use and grown when a larger grid needs more.  Calls that overlap on
+// one stream are ordered by the stream; different streams use different
+// buffers.  The first such call on a stream allocates: make it before
+// capturing calls into a graph.
+struct StreamScratch {
   int dev;
   hipStream_t st;
+  int use;
   void *buf;
   size_t bytes;
 };
 static std::mutex g_scratch_mu;
-static std::vector<DiagScratch> g_scratch;
+static std::vector<StreamScratch> g_scratch;
 
-void *diag_scratch(hipStream_t st, size_t bytes) {
+static void *stream_scratch(hipStream_t st, int use, size_t bytes) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return nullptr;
   std::lock_guard<std::mutex> lk(g_scratch_mu);
   for (auto &s : g_scratch)
-    if (s.dev == dev && s.st == st) {
+    if (s.dev == dev && s.st == st && s.use == use) {
       if (s.bytes >= bytes) return s.buf;
       // the old buffer may still be read by work queued on this stream
       if (hipStreamSynchronize(st) != hipSuccess) return nullptr;
@@ -296,12 +298,14 @@ void *diag_scratch(hipStream_t st, size_t bytes) {
       s.bytes = bytes;
       return s.buf;
     }
-  DiagScratch s{dev, st, nullptr, 0};
+  StreamScratch s{dev, st, use, nullptr, 0};
   if (hipMalloc(&s.buf, bytes) != hipSuccess) return nullptr;
   s.bytes = bytes;
   g_scratch.push_back(s);
   return s.buf;
 }
+
+void *diag_scratch(hipStream_t st, size_t bytes) { return stream_scratch(st, 0, bytes); }
 
 int shape_index(int tx, int tz) {
   for (int s = 0; s < kNumShapes; s++)
@@ -532,6 +536,7 @@ int fill_patch(const grhd_grid *grid, const grhd_metric *metric, const grhd_rk_s
   pk.riemann = riemann;
   pk.eos_id = 0;
   pk.tile_base = 0;
+  pk.flags = nullptr;
   return GRHD_OK;
 }
 }  // namespace grhd
@@ -577,7 +582,16 @@ extern "C" int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos, const
     p1 = (C2PPart *)buf;
     p2 = (FluxPart *)(buf + sizeof(C2PPart) * nb1);
   }
-  if ((rc = launch_con2prim(pk.g, e, to_c2pk(&opts->c2p), pk.m, mc, q, pp, flags, p1, st))) return rc;
+  // the stage kernel reads the recovery flags (all-atmosphere tiles skip
+  // their primitives); without caller flags they go to library scratch
+  uint8_t *fl = flags;
+  if (!fl) {
+    size_t fb = (size_t)(grid->nz + 2 * grid->ng) * (size_t)grid->pitch;
+    fl = (uint8_t *)stream_scratch(st, 1, fb);
+    if (!fl) return fail(GRHD_ERR_DEVICE, "flag scratch allocation failed");
+  }
+  pk.flags = fl;
+  if ((rc = launch_con2prim(pk.g, e, to_c2pk(&opts->c2p), pk.m, mc, q, pp, fl, p1, st))) return rc;
   if (opts->ev_begin && hipEventRecord((hipEvent_t)opts->ev_begin, st) != hipSuccess)
     return fail(GRHD_ERR_DEVICE, "hipEventRecord failed");
   if ((rc = launch_substep(pk, e, opts->prec, mc, shape, p2, st))) return rc;

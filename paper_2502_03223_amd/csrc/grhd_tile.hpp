@@ -23,6 +23,7 @@ struct PatchK {
   double a, b, cdt, gdt, d, e, dt;
   int use_qn, use_acc_in, use_acc_out;
   int recon, riemann, eos_id;
+  uint8_t *flags;  // recovery flags of q_s (nullable)
   int tiles_x, tiles_z;
   int xshift;  // tile tx covers cells j in [tx TX - xshift, (tx + 1) TX - xshift)
   long long tile_base;
@@ -122,16 +123,22 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
   const T cs_atm = tsqrt(eos_cs2<T>(e, ra, ea, Pa));
   __syncthreads();  // LDS of a previous tile (persistent loop) is free
 
-  // ---- 1. stage primitives (and, for the conformally flat class, lapse
-  // and W) of the cross-shaped halo in LDS.  All addresses first, then all
-  // loads, then all LDS stores, so each thread has every load in flight at
-  // once.  Boundary conditions are an index map with velocity parities.
+  // ---- 1. stage the cross-shaped halo in LDS: lapse and W (conformally
+  // flat class) and the atmosphere mask first, then the primitives unless
+  // the whole halo is atmosphere.  With the recovery flags of q_s at hand
+  // the mask comes from them (ATM: the recovery reset the cell to exactly
+  // the atmosphere state) and an all-atmosphere tile needs no primitives at
+  // all; without them the mask compares the primitive values.  Within each
+  // part all addresses come first, then all loads, then all LDS stores.
+  // Boundary conditions are an index map with velocity parities.
+  bool tile_atm;
   {
     // a tile whose halo lies inside the grid reads every cell where it is
     // (no boundary map, no parities)
     const bool inner = j0 >= 3 && j0 + TX + 3 <= nx && k0 >= 3 && k0 + TZ + 3 <= nz;
+    const bool have_flags = P.flags != nullptr;
     long long src[LPT], im[LPT];
-    bool use[LPT];
+    bool use[LPT], fin[LPT];
     double s0[LPT], s1[LPT], s2[LPT];
 #pragma unroll
     for (int i = 0; i < LPT; i++) {
@@ -150,38 +157,61 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
         if (need) need = ghost_map(g, j, k, js, ks, sg);
       }
       use[i] = need;
+      // recovery flags exist for grid cells only (an EXTERNAL ghost maps
+      // to itself and counts as not atmosphere)
+      fin[i] = inner || (js >= 0 && js < nx && ks >= 0 && ks < nz);
       src[i] = need ? cell_index(g, js, ks) : 0;
       im[i] = need ? cell_index(g, j, k) : 0;
       s0[i] = sg[0]; s1[i] = sg[1]; s2[i] = sg[2];
     }
-    double v[LPT][6], va[LPT], vw[LPT];
+    double va[LPT], vw[LPT];
+    uint8_t fl[LPT];
 #pragma unroll
     for (int i = 0; i < LPT; i++) {
       if (use[i]) {
-        for (int f = 0; f < 6; f++) v[i][f] = P.p[f][src[i]];
+        fl[i] = (have_flags && fin[i]) ? P.flags[src[i]] : (uint8_t)0;
         if (MC == MC_CF) {
           va[i] = P.m.f[GRHD_M_ALP] ? P.m.f[GRHD_M_ALP][im[i]] : P.m.c[GRHD_M_ALP];
           vw[i] = P.m.f[GRHD_M_W] ? P.m.f[GRHD_M_W][im[i]] : P.m.c[GRHD_M_W];
         }
       }
     }
+    int my_atm = have_flags ? 1 : 0;
 #pragma unroll
     for (int i = 0; i < LPT; i++) {
       int c = tid + i * NT;
       if (use[i]) {
-        T r = (T)v[i][0], u0 = (T)(s0[i] * v[i][1]), u1 = (T)(s1[i] * v[i][2]),
-          u2 = (T)(s2[i] * v[i][3]), pr = (T)v[i][4], ep = (T)v[i][5];
-        sm.p[0][c] = r; sm.p[1][c] = u0; sm.p[2][c] = u1; sm.p[3][c] = u2;
-        sm.p[4][c] = pr; sm.p[5][c] = ep;
-        sm.atm[c] = (r == ra && u0 == T(0) && u1 == T(0) && u2 == T(0) && pr == Pa && ep == ea) ? 1 : 0;
+        uint8_t a = (fl[i] & GRHD_FLAG_ATM) ? 1 : 0;
+        sm.atm[c] = a;
+        my_atm &= a;
         if (MC == MC_CF) {
           sm.ma[c] = va[i];
           sm.mw[c] = vw[i];
         }
       }
     }
+    tile_atm = __syncthreads_and(my_atm) != 0;
+    if (!tile_atm) {
+      double v[LPT][6];
+#pragma unroll
+      for (int i = 0; i < LPT; i++)
+        if (use[i])
+          for (int f = 0; f < 6; f++) v[i][f] = P.p[f][src[i]];
+#pragma unroll
+      for (int i = 0; i < LPT; i++) {
+        int c = tid + i * NT;
+        if (use[i]) {
+          T r = (T)v[i][0], u0 = (T)(s0[i] * v[i][1]), u1 = (T)(s1[i] * v[i][2]),
+            u2 = (T)(s2[i] * v[i][3]), pr = (T)v[i][4], ep = (T)v[i][5];
+          sm.p[0][c] = r; sm.p[1][c] = u0; sm.p[2][c] = u1; sm.p[3][c] = u2;
+          sm.p[4][c] = pr; sm.p[5][c] = ep;
+          if (!have_flags)
+            sm.atm[c] = (r == ra && u0 == T(0) && u1 == T(0) && u2 == T(0) && pr == Pa && ep == ea) ? 1 : 0;
+        }
+      }
+      __syncthreads();
+    }
   }
-  __syncthreads();
 
   const int nb = 2 * nz + 2 * nx;  // flux-register stride
   double cmax = 0.0;
@@ -209,8 +239,11 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
       // a stencil of six atmosphere cells has equal left and right states,
       // and both solvers then return the physical flux of that state
       // exactly: evaluate it directly
-      bool uni = true;
-      for (int i = 0; i < 6; i++) uni = uni && sm.atm[base + i * stride];
+      bool uni = tile_atm;
+      if (!uni) {
+        uni = true;
+        for (int i = 0; i < 6; i++) uni = uni && sm.atm[base + i * stride];
+      }
       PrimT<T> L, R;
       if (uni) {
         L.rho = ra;
@@ -304,8 +337,11 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
     if (P.use_acc_in)
       for (int m = 0; m < 5; m++) ai5[m] = P.acc_in[m][ic];
     const int lc = (kk + 3) * HX + (jj + 3);
+    const bool catm = tile_atm || sm.atm[lc];
     double pc[6];
-    if (sizeof(T) == sizeof(double)) {
+    if (tile_atm) {
+      pc[0] = e.rho_atm; pc[1] = 0.0; pc[2] = 0.0; pc[3] = 0.0; pc[4] = e.P_atm; pc[5] = e.eps_atm;
+    } else if (sizeof(T) == sizeof(double)) {
       for (int i = 0; i < 6; i++) pc[i] = (double)sm.p[i][lc];  // own cells: no parity flip
     } else {
       for (int i = 0; i < 6; i++) pc[i] = P.p[i][ic];
@@ -376,7 +412,8 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
       }
     }
     double s[5];
-    sources<MC>(gm, dg, xc, g.geom, pc, s);
+    if (MC == MC_CF && catm) sources_atm_cf(gm, dg, xc, g.geom, pc, s);
+    else sources<MC>(gm, dg, xc, g.geom, pc, s);
     double dV = cyl ? 2.0 * M_PI * xc * g.dx * g.dz : g.dx * g.dz;
     for (int m = 0; m < 5; m++) {
       double L = s[m] - divx[m] - divz[m];
