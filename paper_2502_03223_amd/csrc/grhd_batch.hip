@@ -62,12 +62,12 @@ k_con2prim_batch(const PatchK *__restrict__ pt, const EosK *__restrict__ eos, C2
     }
     double qq[5], pp[6];
     for (int c = 0; c < 5; c++) qq[c] = P.qs[c][i];
+    double q0[5] = {qq[0], qq[1], qq[2], qq[3], qq[4]};
     double x = P.g.x0 + (j + 0.5) * P.g.dx;
     C2PResult r = con2prim_cell<MC, EK>(e, cp, W, gtu, x, P.g.geom, qq, pp, -1.0);
     fl = r.flags;
     iters = r.iters;
-    if (fl)
-      for (int c = 0; c < 5; c++) P.qs[c][i] = qq[c];
+    if (fl) store_corrected(qq, q0, P.qs, i);
     for (int c = 0; c < 6; c++) P.p[c][i] = pp[c];
     if (P.flags) P.flags[i] = (uint8_t)fl;
   }

@@ -436,6 +436,15 @@ __device__ C2PResult con2prim_cell(const EosK &e, const C2PK &cp, double W, cons
   return res;
 }
 
+// Write back the components of a corrected conserved state that differ
+// bitwise from the ones read: a cell reset to the atmosphere state it
+// already held rewrites nothing.
+__device__ __forceinline__ void store_corrected(const double *qq, const double *q0, double *const *q,
+                                                long long i) {
+  for (int c = 0; c < 5; c++)
+    if (__double_as_longlong(qq[c]) != __double_as_longlong(q0[c])) q[c][i] = qq[c];
+}
+
 // ------------------------------------------------ reconstruction (II.C.2)
 // PPM of Colella & Woodward (1984): monotonised central slopes, interface
 // values, parabola limiter; no steepening or flattening.  Contraction into
@@ -865,17 +874,15 @@ __device__ __forceinline__ void sources(const double *g, const double *dg, doubl
 }
 
 // sources<MC_CF> for a cell at rest (u = 0): the same operations with
-// every velocity term exactly zero (w = 1, v = 0), so the result equals
-// the general evaluation; no square root and two divisions fewer.
+// every velocity term exactly zero (w = 1, v = 0); P and rhw2 = rho h of
+// the cell's state come from the caller (for the atmosphere they are
+// constants of the launch), so no square root and three divisions fewer.
 __device__ __forceinline__ void sources_atm_cf(const double *g, const double *dg, double x, int geom,
-                                               const double *p, double *s) {
+                                               double P, double rhw2, double *s) {
 #pragma clang fp contract(off)
   double alp = g[GRHD_M_ALP], W = g[GRHD_M_W];
-  double rho = p[0], P = p[4], eps = p[5];
-  double h = 1.0 + eps + P / rho;
   double iW = 1.0 / W;
   double sg = iW * iW * iW;
-  double rhw2 = rho * h;
   double sm[2];
   for (int d = 0; d < 2; d++) {
     const double *dd = dg + d * GRHD_NMET;

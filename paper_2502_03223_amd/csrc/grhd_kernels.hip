@@ -101,12 +101,12 @@ k_con2prim(GridK g, EosK e, C2PK cp, MetK m, Q5 q, P6 p, uint8_t *flags, C2PPart
     }
     double qq[5], pp[6];
     for (int c = 0; c < 5; c++) qq[c] = q.q[c][i];
+    double q0[5] = {qq[0], qq[1], qq[2], qq[3], qq[4]};
     double x = g.x0 + (j + 0.5) * g.dx;
     C2PResult r = con2prim_cell<MC, EK>(e, cp, W, gtu, x, g.geom, qq, pp, -1.0);
     fl = r.flags;
     iters = r.iters;
-    if (fl)
-      for (int c = 0; c < 5; c++) q.q[c][i] = qq[c];
+    if (fl) store_corrected(qq, q0, q.q, i);
     for (int c = 0; c < 6; c++) p.p[c][i] = pp[c];
     if (flags) flags[i] = (uint8_t)fl;
   }
@@ -228,8 +228,16 @@ k_flux(GridK g, EosK e, MetK m, int dir, int riemann, Ptr6<T> Lp, Ptr6<T> Rp, Q5
 // kernel folds the records afterwards.  (Handing tiles out through a global
 // counter costs two same-address atomics per workgroup, which serialise
 // across the XCDs and cost more than the imbalance they remove.)
+// Waves per SIMD the register allocation must allow: the FP64 16 x 16
+// instance of the conformally flat class fits three workgroups per CU in
+// LDS, so its registers are held to three waves as well.
 template <class T, int MC, int TX, int TZ>
-__global__ void __launch_bounds__(NT)
+constexpr int substep_waves() {
+  return (sizeof(T) == 8 && MC == MC_CF && TX == 16 && TZ == 16) ? 3 : 1;
+}
+
+template <class T, int MC, int TX, int TZ>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(substep_waves<T, MC, TX, TZ>())))
 k_substep(PatchK P, EosK e, FluxPart *part2) {
   __shared__ TileSmem<T, MC, TX, TZ> sm;
   __shared__ double red[NT / 64][3];

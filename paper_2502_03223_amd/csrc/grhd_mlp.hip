@@ -57,6 +57,7 @@ k_con2prim_mlp(GridK g, EosK e, C2PK cp, MetK m, Q5 q, P6 p, uint8_t *flags, C2P
     W = mval(m, GRHD_M_W, i);
     for (int c = 0; c < 5; c++) qq[c] = q.q[c][i];
   }
+  const double q0[5] = {qq[0], qq[1], qq[2], qq[3], qq[4]};
   if (MC == MC_GEN) {
     double gt[6];
     for (int t = 0; t < 6; t++) gt[t] = act ? mval(m, GRHD_M_GXX + t, i) : (t == 0 || t == 3 || t == 5);
@@ -102,8 +103,7 @@ k_con2prim_mlp(GridK g, EosK e, C2PK cp, MetK m, Q5 q, P6 p, uint8_t *flags, C2P
     C2PResult res = con2prim_cell<MC, EK>(e, cp, W, gtu, x, g.geom, qq, pp, zg);
     fl = res.flags;
     iters = res.iters;
-    if (fl)
-      for (int c = 0; c < 5; c++) q.q[c][i] = qq[c];
+    if (fl) store_corrected(qq, q0, q.q, i);
     for (int c = 0; c < 6; c++) p.p[c][i] = pp[c];
     if (flags) flags[i] = (uint8_t)fl;
   }

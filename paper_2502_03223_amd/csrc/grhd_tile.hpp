@@ -215,6 +215,117 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
 
   const int nb = 2 * nz + 2 * nx;  // flux-register stride
   double cmax = 0.0;
+  // rho h of the atmosphere state
+  const double rhw2_atm = e.rho_atm * (1.0 + e.eps_atm + e.P_atm / e.rho_atm);
+  const double i60dx = 1.0 / (60.0 * g.dx), i60dz = 1.0 / (60.0 * g.dz);
+
+  if (MC == MC_CF && tile_atm) {
+    // ---- all-atmosphere tile (conformally flat metric class): at every
+    // face the atmosphere at rest has only alpha W^-3 P_atm in the normal
+    // momentum (S_x at x faces, S_z at z faces) and the signal speeds
+    // -+ alpha c_s W; D, S_phi and tau of the cells change only through
+    // the stage weights.  The same values as the general path's uniform
+    // faces and atmosphere sources, with the zero terms left out.
+    const double cx = P.dt / g.dx, cz = P.dt / g.dz;
+    for (int f = tid; f < S::NF; f += NT) {
+      const bool isx = f < S::NFX;
+      int jj, kk, base, stride;
+      if (isx) {
+        jj = f % (TX + 1); kk = f / (TX + 1);
+        base = (kk + 3) * HX + jj; stride = 1;
+      } else {
+        int h = f - S::NFX;
+        jj = h % TX; kk = h / TX;
+        base = kk * HX + jj + 3; stride = HX;
+      }
+      const int j = j0 + jj, k = k0 + kk;
+      const bool valid = isx ? (k < nz && j >= 0 && j <= nx) : (j >= 0 && j < nx && k <= nz);
+      T fn = T(0);
+      if (valid) {
+        T t6[6];
+        for (int i = 0; i < 6; i++) t6[i] = (T)sm.ma[base + i * stride];
+        const T alp = lagrange6(t6);
+        for (int i = 0; i < 6; i++) t6[i] = (T)sm.mw[base + i * stride];
+        const T W = lagrange6(t6);
+        T sg = T(1) / (W * W * W);
+        fn = sg * (alp * Pa);
+        const T sp = alp * (cs_atm * W);
+        cmax = fmax(cmax, (double)sp * (isx ? cx : cz));
+        if (P.flux_reg && (isx ? (j == 0 || j == nx) : (k == 0 || k == nz))) {
+          int o = isx ? ((j == 0) ? k : nz + k) : 2 * nz + ((k == 0) ? j : nx + j);
+          for (int m = 0; m < 5; m++) P.flux_reg[m * nb + o] = 0.0;
+          P.flux_reg[(isx ? 1 : 3) * nb + o] = (double)fn;
+        }
+      }
+      sm.f[0][f] = fn;
+    }
+    __syncthreads();
+    double mb = 0.0, jm = 0.0;
+#pragma unroll
+    for (int ci = 0; ci < CPT; ci++) {
+#pragma clang fp contract(off)
+      int c = tid + ci * NT;
+      int jj = c % TX, kk = c / TX;
+      int j = j0 + jj, k = k0 + kk;
+      if (!(c < TX * TZ && j >= 0 && j < nx && k < nz)) continue;
+      long long ic = cell_index(g, j, k);
+      double qs5[5], qn5[5], ai5[5];
+      for (int m = 0; m < 5; m++) qs5[m] = P.qs[m][ic];
+      if (P.use_qn)
+        for (int m = 0; m < 5; m++) qn5[m] = P.qn[m][ic];
+      if (P.use_acc_in)
+        for (int m = 0; m < 5; m++) ai5[m] = P.acc_in[m][ic];
+      const int lc = (kk + 3) * HX + (jj + 3);
+      double xc = g.x0 + (j + 0.5) * g.dx;
+      const double xl = g.x0 + j * g.dx, xr = g.x0 + (j + 1) * g.dx;
+      const int fl = kk * (TX + 1) + jj, fr = fl + 1;
+      const int fb = S::NFX + kk * TX + jj, ft = fb + TX;
+      const double ivx = cyl ? 1.0 / (xc * g.dx) : 1.0 / g.dx, ivz = 1.0 / g.dz;
+      double Fl = (double)sm.f[0][fl], Fr = (double)sm.f[0][fr];
+      double divx1 = cyl ? (xr * Fr - xl * Fl) * ivx : (Fr - Fl) * ivx;
+      double divz3 = ((double)sm.f[0][ft] - (double)sm.f[0][fb]) * ivz;
+      double gm[GRHD_NMET], dg[2 * GRHD_NMET];
+      for (int i = 0; i < GRHD_NMET; i++) { gm[i] = P.m.c[i]; dg[i] = 0.0; dg[GRHD_NMET + i] = 0.0; }
+      gm[GRHD_M_ALP] = sm.ma[lc];
+      gm[GRHD_M_W] = sm.mw[lc];
+      double a7[7];
+      if (P.m.f[GRHD_M_ALP]) {
+        for (int i = 0; i < 7; i++) a7[i] = sm.ma[lc - 3 + i];
+        dg[GRHD_M_ALP] = deriv6(a7, i60dx);
+        for (int i = 0; i < 7; i++) a7[i] = sm.ma[lc + (i - 3) * HX];
+        dg[GRHD_NMET + GRHD_M_ALP] = deriv6(a7, i60dz);
+      }
+      if (P.m.f[GRHD_M_W]) {
+        for (int i = 0; i < 7; i++) a7[i] = sm.mw[lc - 3 + i];
+        dg[GRHD_M_W] = deriv6(a7, i60dx);
+        for (int i = 0; i < 7; i++) a7[i] = sm.mw[lc + (i - 3) * HX];
+        dg[GRHD_NMET + GRHD_M_W] = deriv6(a7, i60dz);
+      }
+      double s[5];
+      sources_atm_cf(gm, dg, xc, g.geom, e.P_atm, rhw2_atm, s);
+      double L[5] = {0.0, s[1] - divx1, 0.0, s[3] - divz3, 0.0};
+      double dV = cyl ? 2.0 * M_PI * xc * g.dx * g.dz : g.dx * g.dz;
+      for (int m = 0; m < 5; m++) {
+        const bool moves = (m == 1 || m == 3);
+        double v = P.b * qs5[m];
+        if (moves) v += P.cdt * L[m];
+        if (P.use_qn) v += P.a * qn5[m];
+        if (P.use_acc_in) v += P.gdt * ai5[m];
+        P.qo[m][ic] = v;
+        if (P.use_acc_out) {
+          double av = moves ? P.e * L[m] : 0.0;
+          if (P.use_acc_in) av += P.d * ai5[m];
+          P.acc_out[m][ic] = av;
+        }
+        if (m == 0) mb += v * dV;
+        if (m == 2) jm += v * dV;
+      }
+    }
+    cmax_out = cmax;
+    mb_out = mb;
+    jm_out = jm;
+    return;
+  }
 
   // ---- 2. all faces of the tile in one balanced loop: x faces x_{j-1/2}
   // (j = j0..j0+TX) first, then z faces z_{k-1/2} (k = k0..k0+TZ); the
@@ -318,7 +429,6 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
 
   // ---- 3. divergence, sources, stage combination, diagnostics
   double mb = 0.0, jm = 0.0;
-  const double i60dx = 1.0 / (60.0 * g.dx), i60dz = 1.0 / (60.0 * g.dz);
 #pragma unroll
   for (int ci = 0; ci < CPT; ci++) {
     // per-cell arithmetic evaluated without contraction, so that every
@@ -412,7 +522,7 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
       }
     }
     double s[5];
-    if (MC == MC_CF && catm) sources_atm_cf(gm, dg, xc, g.geom, pc, s);
+    if (MC == MC_CF && catm) sources_atm_cf(gm, dg, xc, g.geom, e.P_atm, rhw2_atm, s);
     else sources<MC>(gm, dg, xc, g.geom, pc, s);
     double dV = cyl ? 2.0 * M_PI * xc * g.dx * g.dz : g.dx * g.dz;
     for (int m = 0; m < 5; m++) {
