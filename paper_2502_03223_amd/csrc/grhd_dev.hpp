@@ -111,8 +111,8 @@ __device__ __forceinline__ T eos_cs2(const EosK &e, T rho, T eps, T P) {
   } else {
     double rd = (double)rho;
     int i = eos_piece(e, rd);
-    T kr = T(e.K[i] * pow(rd, e.G[i] - 1.0));
-    T ec = T(e.K[i] / (e.G[i] - 1.0)) * kr + T(e.deps[i]);
+    T kr = T(e.K[i] * pow(rd, e.G[i] - 1.0));  // K rho^(Gamma - 1)
+    T ec = kr / T(e.G[i] - 1.0) + T(e.deps[i]);  // cold specific energy
     chi = T(e.G[i]) * kr + gm1 * (eps - ec) - gm1 * kr;
   }
   T h = T(1) + eps + P / rho;

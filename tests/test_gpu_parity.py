@@ -71,6 +71,21 @@ def star_case(n, seed, tov, vel=0.02, extent=20.0):
     return grid, p, metric, eos
 
 
+# two-piece hybrid EOS (K != 1 in both pieces, so a misplaced K shows)
+HYBRID = dict(kind="hybrid", K=[0.3, 0.3 * 0.9 ** (1.4 - 2.2)], G=[1.4, 2.2], rho_b=[0.9], Gth=5.0 / 3.0)
+
+
+def hybrid_state(orc, p):
+    """p with eps = eps_cold(rho) + 0.2 and P from the hybrid EOS."""
+    rho = p[0]
+    K1 = HYBRID["K"][1]
+    ecold = np.where(rho < 0.9, 0.3 / 0.4 * rho ** 0.4,
+                     K1 / 1.2 * rho ** 1.2 + (0.3 / 0.4 * 0.9 ** 0.4 - K1 / 1.2 * 0.9 ** 1.2))
+    p[5] = ecold + 0.2
+    p[4] = np.array([orc.eos_press(HYBRID, r, e) for r, e in zip(rho.ravel(), p[5].ravel())]).reshape(rho.shape)
+    return p
+
+
 # ------------------------------------------------------------ pointwise calls
 
 @pytest.mark.parametrize("case", ["star", "general"])
@@ -100,13 +115,8 @@ def test_con2prim(orc, tov, case):
         eos = synth.ideal_eos(5.0 / 3.0)
         c2p = C2P_RIE
         if case == "hybrid":
-            eos = dict(kind="hybrid", K=[0.3, 0.3 * 0.9 ** (1.4 - 2.2)], G=[1.4, 2.2],
-                       rho_b=[0.9], Gth=5.0 / 3.0)
-            rho = p[0]
-            ecold = np.where(rho < 0.9, 0.3 / 0.4 * rho ** 0.4,
-                             eos["K"][1] / 1.2 * rho ** 1.2 + (0.3 / 0.4 * 0.9 ** 0.4 - eos["K"][1] / 1.2 * 0.9 ** 1.2))
-            p[5] = ecold + 0.2
-            p[4] = np.array([orc.eos_press(eos, r, e) for r, e in zip(rho.ravel(), p[5].ravel())]).reshape(rho.shape)
+            eos = HYBRID
+            p = hybrid_state(orc, p)
     q = orc.prim2con(grid, eos, metric, p, with_ghosts=True)
     # a few pathological cells: invalid input, super-luminal momentum, cold
     qi = synth.interior(grid, q)
@@ -153,7 +163,7 @@ def test_reconstruct_bitwise(orc, tov, recon, dirn):
 
 @pytest.mark.parametrize("riemann", ["hllc", "tvdlf"])
 @pytest.mark.parametrize("dirn", [0, 1])
-@pytest.mark.parametrize("case", ["star", "general"])
+@pytest.mark.parametrize("case", ["star", "general", "hybrid"])
 def test_flux(orc, tov, riemann, dirn, case):
     if case == "star":
         grid, p, metric, eos = star_case(70, 6, tov, vel=0.1)
@@ -162,6 +172,9 @@ def test_flux(orc, tov, riemann, dirn, case):
         metric = synth.general_metric(grid, 5)
         p = synth.smooth_state(grid, 6, vamp=0.5)
         eos = synth.ideal_eos(5.0 / 3.0)
+        if case == "hybrid":
+            eos = HYBRID
+            p = hybrid_state(orc, p)
     pf = orc.fill_ghosts(grid, p)
     L, R = orc.reconstruct(grid, dirn, "ppm", pf)
     F_o, s_o = orc.face_flux(grid, dirn, riemann, eos, metric, L, R)
@@ -281,12 +294,15 @@ def test_substep_star(orc, tov, n, stage):
     check_pair(grid, ref, out)
 
 
-@pytest.mark.parametrize("riemann", ["hllc", "tvdlf"])
-def test_substep_general_metric(orc, riemann):
+@pytest.mark.parametrize("riemann,eos_kind", [("hllc", "ideal"), ("tvdlf", "ideal"), ("hllc", "hybrid")])
+def test_substep_general_metric(orc, riemann, eos_kind):
     grid = synth.make_grid(45, 38, 0.0, 0.0, 0.02, 0.025, "cart", ("periodic",) * 4)
     metric = synth.general_metric(grid, 7)
     p = synth.smooth_state(grid, 8, vamp=0.5)
     eos = synth.ideal_eos(5.0 / 3.0)
+    if eos_kind == "hybrid":
+        eos = HYBRID
+        p = hybrid_state(orc, p)
     q = orc.prim2con(grid, eos, metric, p, with_ghosts=True)
     opts = dict(recon="ppm", riemann=riemann, prec="fp64", c2p=C2P_RIE)
     ref, out = run_pair(orc, grid, eos, metric, opts, dict(grhd.SSPRK3[1], dt=0.005), q, q)
