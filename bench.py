@@ -9,8 +9,12 @@ diagnostics on.  Inputs are resident in HBM before the timed region.
 
 Metric: zone-updates/s (interior cells x substeps / second) of the plain
 FP64 path.  The JSON line also carries:
-  forms.mixed    FP32 reconstruction and flux, FP64 recovery and update, with
-                 its L1 error against the FP64 path after N substeps;
+  forms.fp64_chained  the same FP64 substep as one chained kernel per stage
+                 (grhd_rk_substep_chained: the recovery of the new state at
+                 the end of each stage; one recovery pass starts the chain);
+  forms.mixed    FP32 reconstruction and flux, FP64 recovery and update, in
+                 the chained form, with its L1 error against the FP64 path
+                 after N substeps;
   forms.batched  six nested 256^2 star levels plus 64 Riemann patches
                  (N_x log-uniform in [128, 2048], 8 periodic z cells) in one
                  graph-captured batched launch, against one call per patch;
@@ -18,7 +22,8 @@ FP64 path.  The JSON line also carries:
                  from the bracket against Newton seeded by the matrix-core MLP
                  (trained here on GPU), same root;
   roofline       of the fused stage kernel (HIP events recorded by the library
-                 around that kernel, algorithmic bytes per zone);
+                 around that kernel, algorithmic bytes per zone), with the
+                 whole substep's fraction beside it;
   cpu_baseline   the oracle on a bounded sample of the headline workload.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--forms fp64,mixed,...]
@@ -40,7 +45,10 @@ HBM_PEAK_GBS = 8000.0
 # fields read or written once: primitives (6 x 8), lapse and W (2 x 8), q_s
 # (5 x 8) read, q_out (5 x 8) written; stages 2 and 3 also read q^n (5 x 8).
 BYTES_KERNEL = [144.0, 184.0, 184.0]
-ALL_FORMS = ("fp64", "mixed", "batched", "learned")
+# algorithmic bytes per zone-update of a whole substep (recovery included):
+# q_s and the metric read, q_out written, q^n read in stages 2 and 3
+BYTES_SUBSTEP = [96.0, 136.0, 136.0]
+ALL_FORMS = ("fp64", "fp64_chained", "mixed", "batched", "learned")
 # measured HBM traffic of the fused kernel (rocprofv3 FETCH_SIZE/WRITE_SIZE,
 # calibrated with a plain copy) is kept with the hash of the sources it was
 # measured on; it is reported only while the sources still hash the same
@@ -137,30 +145,55 @@ def main():
         return q
 
     class Stepper:
-        def __init__(self, prec):
+        """SSP-RK3 steps of the star, chained (one kernel per substep, the
+        recovery at the end of each stage) or separate (recovery pass, then
+        the stage kernel)."""
+
+        def __init__(self, prec, chained=True):
             opts = dict(recon="ppm", riemann="hllc", prec=prec, c2p=c2p)
+            self.chained = chained
             self.sub = grhd.Substep(grid, eos, metric, opts)
             self.q = make_state()
             self.q1 = torch.zeros_like(self.q)
             self.q2 = torch.zeros_like(self.q)
-            self.p = torch.zeros((6,) + self.q.shape[1:], dtype=torch.float64, device=dev)
+            shp = self.q.shape[1:]
+            self.p = torch.zeros((6,) + shp, dtype=torch.float64, device=dev)
+            self.pb = torch.zeros_like(self.p)
+            self.fa = torch.zeros(shp, dtype=torch.uint8, device=dev)
+            self.fb = torch.zeros_like(self.fa)
             self.diag = grhd.new_diag()
             self.stages = [grhd.make_stage(dict(s, dt=dt)) for s in grhd.SSPRK3]
+            if chained:
+                grhd.con2prim(grid, eos, metric, c2p, self.q, self.p, flags=self.fa)
 
         def step(self, events=None, kevents=None):
             # q -> q1 -> q2 -> q (SSP-RK3, q^n = q)
             bufs = [(self.q, self.q, self.q1), (self.q, self.q1, self.q2), (self.q, self.q2, self.q1)]
+            prims = [(self.p, self.fa, self.pb, self.fb), (self.pb, self.fb, self.p, self.fa),
+                     (self.p, self.fa, self.pb, self.fb)]
             for s, (qn, qs, qo) in enumerate(bufs):
                 if events is not None:
                     events[s][0].record()
-                self.sub(self.stages[s], qn, qs, qo, self.p, diag=self.diag,
-                         events=kevents[s] if kevents is not None else None)
+                kev = kevents[s] if kevents is not None else None
+                if self.chained:
+                    self.sub.chained(self.stages[s], qn, qs, qo, *prims[s], diag=self.diag, events=kev)
+                else:
+                    self.sub(self.stages[s], qn, qs, qo, self.p, diag=self.diag, events=kev)
                 if events is not None:
                     events[s][1].record()
             self.q, self.q1 = self.q1, self.q
+            if self.chained:
+                self.p, self.pb = self.pb, self.p
+                self.fa, self.fb = self.fb, self.fa
 
-    def run_form(prec):
-        st = Stepper(prec)
+        def prims(self):
+            """Primitives of the current state."""
+            if not self.chained:
+                grhd.con2prim(grid, eos, metric, c2p, self.q.clone(), self.p)
+            return self.p
+
+    def run_form(prec, chained=True):
+        st = Stepper(prec, chained)
         for _ in range(args.warmup):
             st.step()
         torch.cuda.synchronize()
@@ -183,23 +216,33 @@ def main():
                     diag=grhd.read_diag(st.diag))
 
     out_forms = {}
-    r64 = run_form("fp64")
+    r64 = run_form("fp64", chained=False)
     value = 3 * nzone * args.steps / r64["wall"]
     ms_per_step = r64["wall"] * 1e3 / args.steps
     # bytes and time per launch of the fused kernel, averaged over the stages
+    kms = float(r64["kernel_ms"].mean())
     bytes_per_launch = float(np.mean(BYTES_KERNEL)) * nzone
-    achieved = bytes_per_launch / (float(r64["kernel_ms"].mean()) * 1e-3) / 1e9
+    achieved = bytes_per_launch / (kms * 1e-3) / 1e9
+    # the whole substep (recovery, stage kernel, fold) against its own bytes
+    substep_gbs = float(np.mean(BYTES_SUBSTEP)) * nzone / (float(r64["stage_ms"].mean()) * 1e-3) / 1e9
     diag = r64["diag"]
     tb = measured_traffic()
-    traffic = tb / (float(r64["kernel_ms"].mean()) * 1e-3) / 1e9 if tb else None
-    out_forms["fp64"] = {"value": value, "ms_per_step": ms_per_step,
+    traffic = tb / (kms * 1e-3) / 1e9 if tb else None
+    out_forms["fp64"] = {"value": value, "ms_per_step": ms_per_step, "chained": False,
                          "kernel_ms": r64["kernel_ms"].tolist(), "stage_ms": r64["stage_ms"].tolist()}
     print("fp64 done: %.3e zone-updates/s" % value, file=sys.stderr, flush=True)
+    if "fp64_chained" in forms:
+        rc_ = run_form("fp64", chained=True)
+        value_c = 3 * nzone * args.steps / rc_["wall"]
+        out_forms["fp64_chained"] = {"value": value_c, "ms_per_step": rc_["wall"] * 1e3 / args.steps,
+                                     "chained": True, "kernel_ms": rc_["kernel_ms"].tolist(),
+                                     "stage_ms": rc_["stage_ms"].tolist()}
+        print("fp64_chained done", file=sys.stderr, flush=True)
 
     if "mixed" in forms:
         rm = run_form("mixed")
         value_m = 3 * nzone * args.steps / rm["wall"]
-        out_forms["mixed"] = {"value": value_m, "ms_per_step": rm["wall"] * 1e3 / args.steps,
+        out_forms["mixed"] = {"value": value_m, "ms_per_step": rm["wall"] * 1e3 / args.steps, "chained": True,
                               "speedup_vs_fp64": value_m / value,
                               "kernel_ms": rm["kernel_ms"].tolist(),
                               "accuracy_vs_fp64": mixed_accuracy(args, Stepper, grid, eos, metric,
@@ -241,6 +284,8 @@ def main():
             "bytes_per_zone": BYTES_KERNEL, "kernel_ms": r64["kernel_ms"].tolist(),
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "measured_bytes_per_launch": tb,
+            "substep_bytes_per_zone": BYTES_SUBSTEP, "substep_gbs": substep_gbs,
+            "substep_frac": substep_gbs / HBM_PEAK_GBS,
             "traffic_note": "traffic = measured HBM bytes per launch (FETCH x2 + WRITE x1, factors "
                             "from a 256 MiB copy) / the same mean launch time, in GB/s",
         },
@@ -256,20 +301,14 @@ def main():
 def mixed_accuracy(args, Stepper, grid, eos, metric, metric_np, c2p):
     """L1 differences of the mixed form from the FP64 path after the same
     number of substeps from the same initial data."""
-    import torch
-
     import synth
-    from paper_2502_03223_amd import grhd
     nsteps = args.accuracy_substeps // 3
-    a64, a32 = Stepper("fp64"), Stepper("mixed")
+    a64, a32 = Stepper("fp64", chained=False), Stepper("mixed")
     for _ in range(nsteps):
         a64.step()
         a32.step()
-    grhd.con2prim(grid, eos, metric, c2p, a64.q.clone(), a64.p)
-    grhd.con2prim(grid, eos, metric, c2p, a32.q.clone(), a32.p)
-    torch.cuda.synchronize()
-    P64 = synth.interior(grid, a64.p.cpu().numpy())
-    P32 = synth.interior(grid, a32.p.cpu().numpy())
+    P64 = synth.interior(grid, a64.prims().cpu().numpy())
+    P32 = synth.interior(grid, a32.prims().cpu().numpy())
     X, _ = synth.cell_coords(grid)
     x = synth.interior(grid, X)
     Wm = synth.interior(grid, metric_np["W"])

@@ -196,7 +196,33 @@ int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos,
                     const grhd_cons *acc_out, double *flux_reg,
                     uint8_t *flags, grhd_diag *diag, void *hip_stream);
 
-/* ------------------------------------------------ batched persistent path */
+/* The same stage with the recovery moved to its end (Sec. II.C.1 and
+ * II.C.4 in one pass): the call takes the recovery of q_s as input and
+ * leaves the recovery of q_out as output, so a sequence of stages needs
+ * one recovery pass in total (grhd_con2prim before the first stage) and
+ * each stage is a single kernel.  The arithmetic equals grhd_rk_substep's;
+ * only where the recovery runs differs.
+ * p_in, flags_in: primitives and recovery flags of q_s, as grhd_con2prim
+ * or the previous chained stage wrote them (q_s already corrected);
+ * flags_in is nullable (the atmosphere test then compares primitives).
+ * p_out, flags_out: written with the recovery of q_out (interior cells);
+ * q_out is stored corrected, as a recovery corrects it in place.  p_out
+ * must not alias p_in, flags_out not flags_in.
+ * diag: the recovery counts refer to q_out; Mb and J are sums of the
+ * stored (corrected) q_out.  The learned guess, tile shapes other than
+ * 16 x 16 and EXTERNAL sides (whose ghosts would need a recovery of their
+ * own) return GRHD_ERR_UNSUPPORTED.  Other arguments as grhd_rk_substep;
+ * ev_begin/ev_end bracket the one kernel of the call. */
+int grhd_rk_substep_chained(const grhd_grid *grid, const grhd_eos *eos,
+                            const grhd_metric *metric, const grhd_options *opts,
+                            const grhd_rk_stage *stage, const grhd_cons *qn,
+                            const grhd_cons *qs, const grhd_cons *qout,
+                            const grhd_prim *p_in, const uint8_t *flags_in,
+                            const grhd_prim *p_out, uint8_t *flags_out,
+                            const grhd_cons *acc_in, const grhd_cons *acc_out,
+                            double *flux_reg, grhd_diag *diag, void *hip_stream);
+
+/* ------------------------------------------------------------ batched path */
 
 /* One patch of a batch: any mixture of refinement levels and independent
  * instances; each patch carries its own grid, metric, state and stage. */
@@ -221,7 +247,7 @@ int grhd_plan_create(const grhd_patch *patches, int npatch,
                      grhd_plan **out);
 
 /* One substep of every patch in one graph-captured launch sequence
- * (recovery, then one persistent kernel over all (patch, tile) items).
+ * (recovery, then one kernel over all (patch, tile) items).
  * The patch array must have the shapes given at plan creation; pointers
  * and stage coefficients may change between calls. */
 int grhd_batch_levels(grhd_plan *plan, const grhd_patch *patches, int npatch,

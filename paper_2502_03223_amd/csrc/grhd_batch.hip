@@ -98,10 +98,13 @@ k_batch(const PatchK *__restrict__ pt, const EosK *__restrict__ eos,
   const PatchK &P = pt[lo];
   int lt = (int)(t - tile_prefix[lo]);
   double cm, mb, jm;
+  C2PAcc acc{};
+  int tx, tz;
+  tile_of(lt, P.tiles_x, P.tiles_z, tx, tz);
   if (P.g.nz <= 8)
-    substep_tile<T, MC, AX, AZ>(P, eos[P.eos_id], lt % P.tiles_x, lt / P.tiles_x, sm.a, cm, mb, jm);
+    substep_tile<T, MC, AX, AZ>(P, eos[P.eos_id], tx, tz, sm.a, cm, mb, jm, acc);
   else
-    substep_tile<T, MC, BX, BZ>(P, eos[P.eos_id], lt % P.tiles_x, lt / P.tiles_x, sm.b, cm, mb, jm);
+    substep_tile<T, MC, BX, BZ>(P, eos[P.eos_id], tx, tz, sm.b, cm, mb, jm, acc);
   flux_block_partial<NT>(cm, mb, jm, &part2[t], red);
 }
 

@@ -25,18 +25,15 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
   return v;
 }
 
-// workgroup partial of the recovery statistics; all threads must call it
+// workgroup partial of per-thread recovery statistics v[6] (counts and
+// iteration sum are summed, the iteration maximum is maxed); all threads
+// must call it
 template <int NTHR>
-__device__ __forceinline__ void c2p_block_partial(bool act, unsigned fl, int iters, C2PPart *out,
-                                                  unsigned long long (*red)[6]) {
+__device__ __forceinline__ void c2p_counts_partial(const unsigned long long *v6, C2PPart *out,
+                                                   unsigned long long (*red)[6]) {
   unsigned long long v[6];
-  v[0] = __popcll(__ballot(act && (fl & GRHD_FLAG_RESCALE)));
-  v[1] = __popcll(__ballot(act && (fl & GRHD_FLAG_COLD)));
-  v[2] = __popcll(__ballot(act && (fl & GRHD_FLAG_ATM)));
-  v[3] = __popcll(__ballot(act && (fl & GRHD_FLAG_FAIL)));
-  unsigned long long it = act ? (unsigned long long)iters : 0ull;
-  v[4] = wave_sum_u64(it);
-  v[5] = wave_max_u64(it);
+  for (int i = 0; i < 5; i++) v[i] = wave_sum_u64(v6[i]);
+  v[5] = wave_max_u64(v6[5]);
   int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0)
     for (int i = 0; i < 6; i++) red[w][i] = v[i];
@@ -50,6 +47,21 @@ __device__ __forceinline__ void c2p_block_partial(bool act, unsigned fl, int ite
     }
     *out = p;
   }
+}
+
+// workgroup partial of the recovery statistics, one cell per thread; all
+// threads must call it
+template <int NTHR>
+__device__ __forceinline__ void c2p_block_partial(bool act, unsigned fl, int iters, C2PPart *out,
+                                                  unsigned long long (*red)[6]) {
+  unsigned long long v[6];
+  v[0] = (act && (fl & GRHD_FLAG_RESCALE)) ? 1ull : 0ull;
+  v[1] = (act && (fl & GRHD_FLAG_COLD)) ? 1ull : 0ull;
+  v[2] = (act && (fl & GRHD_FLAG_ATM)) ? 1ull : 0ull;
+  v[3] = (act && (fl & GRHD_FLAG_FAIL)) ? 1ull : 0ull;
+  v[4] = act ? (unsigned long long)iters : 0ull;
+  v[5] = v[4];
+  c2p_counts_partial<NTHR>(v, out, red);
 }
 
 // workgroup partial of the stage diagnostics (max Courant number, sums of

@@ -243,10 +243,32 @@ k_substep(PatchK P, EosK e, FluxPart *part2) {
   __shared__ double red[NT / 64][3];
   const int t = blockIdx.x;
   double cm, mb, jm;
+  C2PAcc acc{};
   int tx, tz;
   tile_of(t, P.tiles_x, P.tiles_z, tx, tz);
-  substep_tile<T, MC, TX, TZ>(P, e, tx, tz, sm, cm, mb, jm);
+  substep_tile<T, MC, TX, TZ>(P, e, tx, tz, sm, cm, mb, jm, acc);
   if (part2) flux_block_partial<NT>(cm, mb, jm, &part2[t], red);
+}
+
+// The chained stage: the same tile work on 16 x 16 tiles, ending with the
+// recovery of q_out for the next stage.  Records: part1[tile] (recovery of
+// q_out), part2[tile] (stage diagnostics).
+template <class T, int MC, int EK>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(substep_waves<T, MC, 16, 16>())))
+k_substep_chain(PatchK P, EosK e, C2PPart *part1, FluxPart *part2) {
+  __shared__ TileSmem<T, MC, 16, 16> sm;
+  __shared__ double red[NT / 64][3];
+  __shared__ unsigned long long red1[NT / 64][6];
+  const int t = blockIdx.x;
+  double cm, mb, jm;
+  C2PAcc acc{};
+  int tx, tz;
+  tile_of(t, P.tiles_x, P.tiles_z, tx, tz);
+  substep_tile<T, MC, 16, 16, true, EK>(P, e, tx, tz, sm, cm, mb, jm, acc);
+  if (part2) {
+    flux_block_partial<NT>(cm, mb, jm, &part2[t], red);
+    c2p_counts_partial<NT>(acc.n, &part1[t], red1);
+  }
 }
 
 // ------------------------------------------------------------ dispatch
@@ -369,6 +391,26 @@ int launch_substep(const PatchK &pk, const EosK &e, int prec, int mc, int shape,
   if (nt >= (1LL << 31)) return fail(GRHD_ERR_UNSUPPORTED, "more than 2^31 - 1 tiles");
   hipLaunchKernelGGL(fn, dim3((unsigned)nt), dim3(NT), 0, st, pk, e, part2);
   return launch_status("substep");
+}
+
+using ChainFn = void (*)(PatchK, EosK, C2PPart *, FluxPart *);
+
+template <class T>
+static ChainFn chain_kernel_t(int mc, int ek) {
+  if (mc == MC_GEN)
+    return ek == GRHD_EOS_IDEAL ? k_substep_chain<T, MC_GEN, GRHD_EOS_IDEAL>
+                                : k_substep_chain<T, MC_GEN, GRHD_EOS_HYBRID>;
+  return ek == GRHD_EOS_IDEAL ? k_substep_chain<T, MC_CF, GRHD_EOS_IDEAL>
+                              : k_substep_chain<T, MC_CF, GRHD_EOS_HYBRID>;
+}
+
+int launch_substep_chain(const PatchK &pk, const EosK &e, int prec, int mc, C2PPart *part1,
+                         FluxPart *part2, hipStream_t st) {
+  ChainFn fn = (prec == GRHD_PREC_MIXED) ? chain_kernel_t<float>(mc, e.kind) : chain_kernel_t<double>(mc, e.kind);
+  long long nt = (long long)pk.tiles_x * pk.tiles_z;
+  if (nt >= (1LL << 31)) return fail(GRHD_ERR_UNSUPPORTED, "more than 2^31 - 1 tiles");
+  hipLaunchKernelGGL(fn, dim3((unsigned)nt), dim3(NT), 0, st, pk, e, part1, part2);
+  return launch_status("chained substep");
 }
 
 }  // namespace grhd
@@ -545,6 +587,9 @@ int fill_patch(const grhd_grid *grid, const grhd_metric *metric, const grhd_rk_s
   pk.eos_id = 0;
   pk.tile_base = 0;
   pk.flags = nullptr;
+  for (int c = 0; c < 6; c++) pk.po[c] = nullptr;
+  pk.flags_out = nullptr;
+  pk.cp = C2PK{};
   return GRHD_OK;
 }
 }  // namespace grhd
@@ -606,6 +651,63 @@ extern "C" int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos, const
   if (opts->ev_end && hipEventRecord((hipEvent_t)opts->ev_end, st) != hipSuccess)
     return fail(GRHD_ERR_DEVICE, "hipEventRecord failed");
   if (diag) return launch_diag_final(p1, nb1, p2, nb2, diag, st);
+  return GRHD_OK;
+}
+
+extern "C" int grhd_rk_substep_chained(const grhd_grid *grid, const grhd_eos *eos,
+                                       const grhd_metric *metric, const grhd_options *opts,
+                                       const grhd_rk_stage *stage, const grhd_cons *qn,
+                                       const grhd_cons *qs, const grhd_cons *qout,
+                                       const grhd_prim *p_in, const uint8_t *flags_in,
+                                       const grhd_prim *p_out, uint8_t *flags_out,
+                                       const grhd_cons *acc_in, const grhd_cons *acc_out,
+                                       double *flux_reg, grhd_diag *diag, void *hip_stream) {
+  int rc;
+  if (!opts) return fail(GRHD_ERR_INVALID, "opts is NULL");
+  if ((rc = check_eos(eos)) || (rc = check_c2p(&opts->c2p))) return rc;
+  if (opts->prec != GRHD_PREC_FP64 && opts->prec != GRHD_PREC_MIXED) return fail(GRHD_ERR_INVALID, "bad prec");
+  if (opts->c2p.guess != GRHD_GUESS_NONE)
+    return fail(GRHD_ERR_UNSUPPORTED, "the chained stage recovers without a learned guess");
+  if ((opts->tile_x || opts->tile_z) && !(opts->tile_x == 16 && opts->tile_z == 16))
+    return fail(GRHD_ERR_UNSUPPORTED, "the chained stage is built for 16 x 16 tiles only");
+  PatchK pk;
+  if ((rc = fill_patch(grid, metric, stage, qn, qs, qout, p_in, acc_in, acc_out, flux_reg, opts->recon,
+                       opts->riemann, pk)))
+    return rc;
+  if ((rc = check_prim(p_out, "p_out"))) return rc;
+  if (!flags_out) return fail(GRHD_ERR_INVALID, "flags_out is NULL");
+  if (flags_in && flags_in == flags_out) return fail(GRHD_ERR_INVALID, "flags_out must not alias flags_in");
+  for (int a = 0; a < 6; a++)
+    for (int b = 0; b < 6; b++)
+      if (p_out->p[a] == p_in->p[b]) return fail(GRHD_ERR_INVALID, "p_out must not alias p_in");
+  for (int s = 0; s < 4; s++)
+    if (grid->bc[s] == GRHD_BC_EXTERNAL)
+      return fail(GRHD_ERR_UNSUPPORTED, "the chained stage recovers interior cells only (no EXTERNAL sides)");
+  pk.flags = const_cast<uint8_t *>(flags_in);
+  for (int c = 0; c < 6; c++) pk.po[c] = p_out->p[c];
+  pk.flags_out = flags_out;
+  pk.cp = to_c2pk(&opts->c2p);
+  pk.xshift = tile_xshift(grid->ng, 16);
+  pk.tiles_x = (grid->nx + pk.xshift + 15) / 16;
+  pk.tiles_z = (grid->nz + 15) / 16;
+  hipStream_t st = (hipStream_t)hip_stream;
+  EosK e = to_eosk(eos, opts->c2p.rho_atm);
+  int mc = metric_class(metric);
+  int nt = pk.tiles_x * pk.tiles_z;
+  C2PPart *p1 = nullptr;
+  FluxPart *p2 = nullptr;
+  if (diag) {
+    char *buf = (char *)diag_scratch(st, (sizeof(C2PPart) + sizeof(FluxPart)) * (size_t)nt);
+    if (!buf) return fail(GRHD_ERR_DEVICE, "diagnostic scratch allocation failed");
+    p1 = (C2PPart *)buf;
+    p2 = (FluxPart *)(buf + sizeof(C2PPart) * (size_t)nt);
+  }
+  if (opts->ev_begin && hipEventRecord((hipEvent_t)opts->ev_begin, st) != hipSuccess)
+    return fail(GRHD_ERR_DEVICE, "hipEventRecord failed");
+  if ((rc = launch_substep_chain(pk, e, opts->prec, mc, p1, p2, st))) return rc;
+  if (opts->ev_end && hipEventRecord((hipEvent_t)opts->ev_end, st) != hipSuccess)
+    return fail(GRHD_ERR_DEVICE, "hipEventRecord failed");
+  if (diag) return launch_diag_final(p1, nt, p2, nt, diag, st);
   return GRHD_OK;
 }
 

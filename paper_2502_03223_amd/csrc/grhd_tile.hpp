@@ -24,6 +24,10 @@ struct PatchK {
   int use_qn, use_acc_in, use_acc_out;
   int recon, riemann, eos_id;
   uint8_t *flags;  // recovery flags of q_s (nullable)
+  // chained stages only: recovery of q_out at the end of the stage
+  double *po[6];       // primitives of q_out
+  uint8_t *flags_out;  // recovery flags of q_out
+  C2PK cp;
   int tiles_x, tiles_z;
   int xshift;  // tile tx covers cells j in [tx TX - xshift, (tx + 1) TX - xshift)
   long long tile_base;
@@ -104,12 +108,47 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// Recovery statistics of the cells one thread finished (rescale, cold,
+// atmosphere, failed, iteration sum, iteration max).
+struct C2PAcc {
+  unsigned long long n[6];
+};
+
+// Chained stages: recovery of the stage result v of cell ic (Sec. II.C.4),
+// v corrected where a flag is set, then q_out, the primitives and flags of
+// q_out written, so that the next stage needs no recovery pass of its own.
+// W, gt: metric at the cell.  Without CHAIN the caller stores v itself.
+template <int MC, int EK, bool CHAIN>
+__device__ __forceinline__ void finish_cell(const PatchK &P, const EosK &e, long long ic, double W,
+                                            const double *gt, double xc, double dV, double *v,
+                                            double &mb, double &jm, C2PAcc &acc) {
+  if (!CHAIN) return;  // stored by the caller as they were computed
+  {
+    double gtu[6];
+    if (MC == MC_GEN) inv_sym3(gt, gtu);
+    double pp[6];
+    C2PResult r = con2prim_cell<MC, EK>(e, P.cp, W, gtu, xc, P.g.geom, v, pp, -1.0);
+    for (int c = 0; c < 6; c++) P.po[c][ic] = pp[c];
+    P.flags_out[ic] = (uint8_t)r.flags;
+    acc.n[0] += (r.flags & GRHD_FLAG_RESCALE) ? 1 : 0;
+    acc.n[1] += (r.flags & GRHD_FLAG_COLD) ? 1 : 0;
+    acc.n[2] += (r.flags & GRHD_FLAG_ATM) ? 1 : 0;
+    acc.n[3] += (r.flags & GRHD_FLAG_FAIL) ? 1 : 0;
+    acc.n[4] += (unsigned long long)r.iters;
+    if ((unsigned long long)r.iters > acc.n[5]) acc.n[5] = (unsigned long long)r.iters;
+  }
+  for (int m = 0; m < 5; m++) P.qo[m][ic] = v[m];
+  mb += v[0] * dV;
+  jm += v[2] * dV;
+}
+
 // One tile of one patch.  cmax, mb, jm receive this thread's share of the
-// tile's diagnostics (max Courant number, sums of q_D dV and q_Sphi dV).
-template <class T, int MC, int TX, int TZ>
+// tile's diagnostics (max Courant number, sums of q_D dV and q_Sphi dV of
+// the stored q_out); with CHAIN, acc its recovery statistics.
+template <class T, int MC, int TX, int TZ, bool CHAIN = false, int EK = 0>
 __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int tx, int tz,
                                              TileSmem<T, MC, TX, TZ> &sm, double &cmax_out,
-                                             double &mb_out, double &jm_out) {
+                                             double &mb_out, double &jm_out, C2PAcc &acc) {
   using S = TileSmem<T, MC, TX, TZ>;
   constexpr int HX = S::HX;
   constexpr int CPT = (TX * TZ + NT - 1) / NT;
@@ -219,7 +258,8 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
   const double rhw2_atm = e.rho_atm * (1.0 + e.eps_atm + e.P_atm / e.rho_atm);
   const double i60dx = 1.0 / (60.0 * g.dx), i60dz = 1.0 / (60.0 * g.dz);
 
-  if (MC == MC_CF && tile_atm) {
+  const bool atm_fast = (MC == MC_CF) && tile_atm;
+  if (atm_fast) {
     // ---- all-atmosphere tile (conformally flat metric class): at every
     // face the atmosphere at rest has only alpha W^-3 P_atm in the normal
     // momentum (S_x at x faces, S_z at z faces) and the signal speeds
@@ -259,171 +299,105 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
       }
       sm.f[0][f] = fn;
     }
-    __syncthreads();
-    double mb = 0.0, jm = 0.0;
-#pragma unroll
-    for (int ci = 0; ci < CPT; ci++) {
-#pragma clang fp contract(off)
-      int c = tid + ci * NT;
-      int jj = c % TX, kk = c / TX;
-      int j = j0 + jj, k = k0 + kk;
-      if (!(c < TX * TZ && j >= 0 && j < nx && k < nz)) continue;
-      long long ic = cell_index(g, j, k);
-      double qs5[5], qn5[5], ai5[5];
-      for (int m = 0; m < 5; m++) qs5[m] = P.qs[m][ic];
-      if (P.use_qn)
-        for (int m = 0; m < 5; m++) qn5[m] = P.qn[m][ic];
-      if (P.use_acc_in)
-        for (int m = 0; m < 5; m++) ai5[m] = P.acc_in[m][ic];
-      const int lc = (kk + 3) * HX + (jj + 3);
-      double xc = g.x0 + (j + 0.5) * g.dx;
-      const double xl = g.x0 + j * g.dx, xr = g.x0 + (j + 1) * g.dx;
-      const int fl = kk * (TX + 1) + jj, fr = fl + 1;
-      const int fb = S::NFX + kk * TX + jj, ft = fb + TX;
-      const double ivx = cyl ? 1.0 / (xc * g.dx) : 1.0 / g.dx, ivz = 1.0 / g.dz;
-      double Fl = (double)sm.f[0][fl], Fr = (double)sm.f[0][fr];
-      double divx1 = cyl ? (xr * Fr - xl * Fl) * ivx : (Fr - Fl) * ivx;
-      double divz3 = ((double)sm.f[0][ft] - (double)sm.f[0][fb]) * ivz;
-      double gm[GRHD_NMET], dg[2 * GRHD_NMET];
-      for (int i = 0; i < GRHD_NMET; i++) { gm[i] = P.m.c[i]; dg[i] = 0.0; dg[GRHD_NMET + i] = 0.0; }
-      gm[GRHD_M_ALP] = sm.ma[lc];
-      gm[GRHD_M_W] = sm.mw[lc];
-      double a7[7];
-      if (P.m.f[GRHD_M_ALP]) {
-        for (int i = 0; i < 7; i++) a7[i] = sm.ma[lc - 3 + i];
-        dg[GRHD_M_ALP] = deriv6(a7, i60dx);
-        for (int i = 0; i < 7; i++) a7[i] = sm.ma[lc + (i - 3) * HX];
-        dg[GRHD_NMET + GRHD_M_ALP] = deriv6(a7, i60dz);
-      }
-      if (P.m.f[GRHD_M_W]) {
-        for (int i = 0; i < 7; i++) a7[i] = sm.mw[lc - 3 + i];
-        dg[GRHD_M_W] = deriv6(a7, i60dx);
-        for (int i = 0; i < 7; i++) a7[i] = sm.mw[lc + (i - 3) * HX];
-        dg[GRHD_NMET + GRHD_M_W] = deriv6(a7, i60dz);
-      }
-      double s[5];
-      sources_atm_cf(gm, dg, xc, g.geom, e.P_atm, rhw2_atm, s);
-      double L[5] = {0.0, s[1] - divx1, 0.0, s[3] - divz3, 0.0};
-      double dV = cyl ? 2.0 * M_PI * xc * g.dx * g.dz : g.dx * g.dz;
-      for (int m = 0; m < 5; m++) {
-        const bool moves = (m == 1 || m == 3);
-        double v = P.b * qs5[m];
-        if (moves) v += P.cdt * L[m];
-        if (P.use_qn) v += P.a * qn5[m];
-        if (P.use_acc_in) v += P.gdt * ai5[m];
-        P.qo[m][ic] = v;
-        if (P.use_acc_out) {
-          double av = moves ? P.e * L[m] : 0.0;
-          if (P.use_acc_in) av += P.d * ai5[m];
-          P.acc_out[m][ic] = av;
-        }
-        if (m == 0) mb += v * dV;
-        if (m == 2) jm += v * dV;
-      }
-    }
-    cmax_out = cmax;
-    mb_out = mb;
-    jm_out = jm;
-    return;
-  }
-
-  // ---- 2. all faces of the tile in one balanced loop: x faces x_{j-1/2}
-  // (j = j0..j0+TX) first, then z faces z_{k-1/2} (k = k0..k0+TZ); the
-  // stencil is addressed by a base and a stride so x and z lanes of one
-  // wave run the same instructions.
-  for (int f = tid; f < S::NF; f += NT) {
-    const bool isx = f < S::NFX;
-    int jj, kk, base, stride;
-    if (isx) {
-      jj = f % (TX + 1); kk = f / (TX + 1);
-      base = (kk + 3) * HX + jj; stride = 1;
-    } else {
-      int h = f - S::NFX;
-      jj = h % TX; kk = h / TX;
-      base = kk * HX + jj + 3; stride = HX;
-    }
-    const int j = j0 + jj, k = k0 + kk;
-    const bool valid = isx ? (k < nz && j >= 0 && j <= nx) : (j >= 0 && j < nx && k <= nz);
-    FluxT<T> out;
-    for (int m = 0; m < 5; m++) out.f[m] = T(0);
-    if (valid) {
-      // a stencil of six atmosphere cells has equal left and right states,
-      // and both solvers then return the physical flux of that state
-      // exactly: evaluate it directly
-      bool uni = tile_atm;
-      if (!uni) {
-        uni = true;
-        for (int i = 0; i < 6; i++) uni = uni && sm.atm[base + i * stride];
-      }
-      PrimT<T> L, R;
-      if (uni) {
-        L.rho = ra;
-        L.u[0] = T(0); L.u[1] = T(0); L.u[2] = T(0);
-        L.P = Pa; L.eps = ea;
-        R = L;
+  } else {
+    // ---- 2. all faces of the tile in one balanced loop: x faces x_{j-1/2}
+    // (j = j0..j0+TX) first, then z faces z_{k-1/2} (k = k0..k0+TZ); the
+    // stencil is addressed by a base and a stride so x and z lanes of one
+    // wave run the same instructions.
+    for (int f = tid; f < S::NF; f += NT) {
+      const bool isx = f < S::NFX;
+      int jj, kk, base, stride;
+      if (isx) {
+        jj = f % (TX + 1); kk = f / (TX + 1);
+        base = (kk + 3) * HX + jj; stride = 1;
       } else {
-        T s[6], a, b;
-        for (int fld = 0; fld < 6; fld++) {
-          for (int i = 0; i < 6; i++) s[i] = sm.p[fld][base + i * stride];
-          recon_face(P.recon, s, a, b);
-          if (fld == 0) { L.rho = a; R.rho = b; }
-          else if (fld < 4) { L.u[fld - 1] = a; R.u[fld - 1] = b; }
-          else if (fld == 4) { L.P = a; R.P = b; }
-          else { L.eps = a; R.eps = b; }
-        }
+        int h = f - S::NFX;
+        jj = h % TX; kk = h / TX;
+        base = kk * HX + jj + 3; stride = HX;
       }
-      FaceMet<T> fm;
-      T t6[6];
-      if (MC == MC_CF) {
-        for (int i = 0; i < 6; i++) t6[i] = (T)sm.ma[base + i * stride];
-        fm.alp = lagrange6(t6);
-        for (int i = 0; i < 6; i++) t6[i] = (T)sm.mw[base + i * stride];
-        fm.W = lagrange6(t6);
-      } else {
-        long long g0 = isx ? cell_index(g, j - 3, k) : cell_index(g, j, k - 3);
-        long long gs = isx ? 1 : g.pitch;
-        for (int fld = 0; fld < 11; fld++) {
-          const double *src = P.m.f[fld];
-          T v;
-          if (src) {
-            for (int i = 0; i < 6; i++) t6[i] = (T)src[g0 + i * gs];
-            v = lagrange6(t6);
-          } else {
-            v = (T)P.m.c[fld];
+      const int j = j0 + jj, k = k0 + kk;
+      const bool valid = isx ? (k < nz && j >= 0 && j <= nx) : (j >= 0 && j < nx && k <= nz);
+      FluxT<T> out;
+      for (int m = 0; m < 5; m++) out.f[m] = T(0);
+      if (valid) {
+        // a stencil of six atmosphere cells has equal left and right states,
+        // and both solvers then return the physical flux of that state
+        // exactly: evaluate it directly
+        bool uni = tile_atm;
+        if (!uni) {
+          uni = true;
+          for (int i = 0; i < 6; i++) uni = uni && sm.atm[base + i * stride];
+        }
+        PrimT<T> L, R;
+        if (uni) {
+          L.rho = ra;
+          L.u[0] = T(0); L.u[1] = T(0); L.u[2] = T(0);
+          L.P = Pa; L.eps = ea;
+          R = L;
+        } else {
+          T s[6], a, b;
+          for (int fld = 0; fld < 6; fld++) {
+            for (int i = 0; i < 6; i++) s[i] = sm.p[fld][base + i * stride];
+            recon_face(P.recon, s, a, b);
+            if (fld == 0) { L.rho = a; R.rho = b; }
+            else if (fld < 4) { L.u[fld - 1] = a; R.u[fld - 1] = b; }
+            else if (fld == 4) { L.P = a; R.P = b; }
+            else { L.eps = a; R.eps = b; }
           }
-          if (fld == 0) fm.alp = v;
-          else if (fld < 4) fm.beta[fld - 1] = v;
-          else if (fld == 4) fm.W = v;
-          else fm.gt[fld - 5] = v;
+        }
+        FaceMet<T> fm;
+        T t6[6];
+        if (MC == MC_CF) {
+          for (int i = 0; i < 6; i++) t6[i] = (T)sm.ma[base + i * stride];
+          fm.alp = lagrange6(t6);
+          for (int i = 0; i < 6; i++) t6[i] = (T)sm.mw[base + i * stride];
+          fm.W = lagrange6(t6);
+        } else {
+          long long g0 = isx ? cell_index(g, j - 3, k) : cell_index(g, j, k - 3);
+          long long gs = isx ? 1 : g.pitch;
+          for (int fld = 0; fld < 11; fld++) {
+            const double *src = P.m.f[fld];
+            T v;
+            if (src) {
+              for (int i = 0; i < 6; i++) t6[i] = (T)src[g0 + i * gs];
+              v = lagrange6(t6);
+            } else {
+              v = (T)P.m.c[fld];
+            }
+            if (fld == 0) fm.alp = v;
+            else if (fld < 4) fm.beta[fld - 1] = v;
+            else if (fld == 4) fm.W = v;
+            else fm.gt[fld - 5] = v;
+          }
+        }
+        if (uni && MC == MC_CF) {
+          // the atmosphere at rest in a conformally flat metric without
+          // shift: of the physical flux only alpha W^-3 P in the normal
+          // momentum survives, and the signal speeds are -+ alpha c_s W
+          // (the physical-flux evaluation below reduces to exactly these)
+          T sg = T(1) / (fm.W * fm.W * fm.W);
+          out.f[isx ? 1 : 3] = sg * (fm.alp * Pa);
+          out.speed = fm.alp * (cs_atm * fm.W);
+        } else if (uni) {
+          T Q[5], lm, lp, gtu[6];
+          if (MC == MC_GEN) inv_sym3(fm.gt, gtu);
+          valencia<T, MC>(e, fm, gtu, isx ? 0 : 2, L, out.f, Q, lm, lp);
+          out.speed = fmax(fabs(lm), fabs(lp));
+        } else {
+          face_flux<T, MC>(e, fm, isx ? 0 : 1, P.riemann, L, R, out);
+        }
+        cmax = fmax(cmax, (double)out.speed * (P.dt / (isx ? g.dx : g.dz)));
+        if (P.flux_reg && (isx ? (j == 0 || j == nx) : (k == 0 || k == nz))) {
+          int o = isx ? ((j == 0) ? k : nz + k) : 2 * nz + ((k == 0) ? j : nx + j);
+          double xx = isx ? g.x0 + j * g.dx : g.x0 + (j + 0.5) * g.dx;
+          double fv[5] = {(double)out.f[0], (double)out.f[1], (double)out.f[2], (double)out.f[3],
+                          (double)out.f[0] + (double)out.f[4]};
+          if (cyl) fv[2] *= xx;
+          for (int m = 0; m < 5; m++) P.flux_reg[m * nb + o] = fv[m];
         }
       }
-      if (uni && MC == MC_CF) {
-        // the atmosphere at rest in a conformally flat metric without
-        // shift: of the physical flux only alpha W^-3 P in the normal
-        // momentum survives, and the signal speeds are -+ alpha c_s W
-        // (the physical-flux evaluation below reduces to exactly these)
-        T sg = T(1) / (fm.W * fm.W * fm.W);
-        out.f[isx ? 1 : 3] = sg * (fm.alp * Pa);
-        out.speed = fm.alp * (cs_atm * fm.W);
-      } else if (uni) {
-        T Q[5], lm, lp, gtu[6];
-        if (MC == MC_GEN) inv_sym3(fm.gt, gtu);
-        valencia<T, MC>(e, fm, gtu, isx ? 0 : 2, L, out.f, Q, lm, lp);
-        out.speed = fmax(fabs(lm), fabs(lp));
-      } else {
-        face_flux<T, MC>(e, fm, isx ? 0 : 1, P.riemann, L, R, out);
-      }
-      cmax = fmax(cmax, (double)out.speed * (P.dt / (isx ? g.dx : g.dz)));
-      if (P.flux_reg && (isx ? (j == 0 || j == nx) : (k == 0 || k == nz))) {
-        int o = isx ? ((j == 0) ? k : nz + k) : 2 * nz + ((k == 0) ? j : nx + j);
-        double xx = isx ? g.x0 + j * g.dx : g.x0 + (j + 0.5) * g.dx;
-        double fv[5] = {(double)out.f[0], (double)out.f[1], (double)out.f[2], (double)out.f[3],
-                        (double)out.f[0] + (double)out.f[4]};
-        if (cyl) fv[2] *= xx;
-        for (int m = 0; m < 5; m++) P.flux_reg[m * nb + o] = fv[m];
-      }
+      for (int m = 0; m < 5; m++) sm.f[m][f] = out.f[m];
     }
-    for (int m = 0; m < 5; m++) sm.f[m][f] = out.f[m];
   }
   __syncthreads();
 
@@ -447,49 +421,11 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
     if (P.use_acc_in)
       for (int m = 0; m < 5; m++) ai5[m] = P.acc_in[m][ic];
     const int lc = (kk + 3) * HX + (jj + 3);
-    const bool catm = tile_atm || sm.atm[lc];
-    double pc[6];
-    if (tile_atm) {
-      pc[0] = e.rho_atm; pc[1] = 0.0; pc[2] = 0.0; pc[3] = 0.0; pc[4] = e.P_atm; pc[5] = e.eps_atm;
-    } else if (sizeof(T) == sizeof(double)) {
-      for (int i = 0; i < 6; i++) pc[i] = (double)sm.p[i][lc];  // own cells: no parity flip
-    } else {
-      for (int i = 0; i < 6; i++) pc[i] = P.p[i][ic];
-    }
     double xc = g.x0 + (j + 0.5) * g.dx;
     const double xl = g.x0 + j * g.dx, xr = g.x0 + (j + 1) * g.dx;
     const int fl = kk * (TX + 1) + jj, fr = fl + 1;
     const int fb = S::NFX + kk * TX + jj, ft = fb + TX;
-    double divx[5], divz[5];
     const double ivx = cyl ? 1.0 / (xc * g.dx) : 1.0 / g.dx, ivz = 1.0 / g.dz;
-    for (int m = 0; m < 5; m++) {
-      double Fl, Fr;
-      if (m == 4) {
-        Fl = (double)sm.f[0][fl] + (double)sm.f[4][fl];
-        Fr = (double)sm.f[0][fr] + (double)sm.f[4][fr];
-      } else {
-        Fl = (double)sm.f[m][fl];
-        Fr = (double)sm.f[m][fr];
-      }
-      if (cyl) {
-        if (m == 2) { Fl *= xl; Fr *= xr; }
-        divx[m] = (xr * Fr - xl * Fl) * ivx;
-      } else {
-        divx[m] = (Fr - Fl) * ivx;
-      }
-    }
-    for (int m = 0; m < 5; m++) {
-      double Fb, Ft;
-      if (m == 4) {
-        Fb = (double)sm.f[0][fb] + (double)sm.f[4][fb];
-        Ft = (double)sm.f[0][ft] + (double)sm.f[4][ft];
-      } else {
-        Fb = (double)sm.f[m][fb];
-        Ft = (double)sm.f[m][ft];
-      }
-      if (cyl && m == 2) { Fb *= xc; Ft *= xc; }
-      divz[m] = (Ft - Fb) * ivz;
-    }
     // metric at the cell and its x, z derivatives
     double gm[GRHD_NMET], dg[2 * GRHD_NMET];
     if (MC == MC_CF) {
@@ -521,24 +457,78 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
         dg[GRHD_NMET + i] = deriv6(a7, i60dz);
       }
     }
-    double s[5];
-    if (MC == MC_CF && catm) sources_atm_cf(gm, dg, xc, g.geom, e.P_atm, rhw2_atm, s);
-    else sources<MC>(gm, dg, xc, g.geom, pc, s);
+    double L[5];
+    if (atm_fast) {
+      // all-atmosphere tile: only the normal momenta carry a flux, and
+      // only S_x and S_z have sources
+      const double Fl = (double)sm.f[0][fl], Fr = (double)sm.f[0][fr];
+      const double divx1 = cyl ? (xr * Fr - xl * Fl) * ivx : (Fr - Fl) * ivx;
+      const double divz3 = ((double)sm.f[0][ft] - (double)sm.f[0][fb]) * ivz;
+      double s[5];
+      sources_atm_cf(gm, dg, xc, g.geom, e.P_atm, rhw2_atm, s);
+      L[0] = 0.0; L[1] = s[1] - divx1; L[2] = 0.0; L[3] = s[3] - divz3; L[4] = 0.0;
+    } else {
+      const bool catm = tile_atm || sm.atm[lc];
+      double pc[6];
+      if (tile_atm) {
+        pc[0] = e.rho_atm; pc[1] = 0.0; pc[2] = 0.0; pc[3] = 0.0; pc[4] = e.P_atm; pc[5] = e.eps_atm;
+      } else if (sizeof(T) == sizeof(double)) {
+        for (int i = 0; i < 6; i++) pc[i] = (double)sm.p[i][lc];  // own cells: no parity flip
+      } else {
+        for (int i = 0; i < 6; i++) pc[i] = P.p[i][ic];
+      }
+      double divx[5], divz[5];
+      for (int m = 0; m < 5; m++) {
+        double Fl, Fr;
+        if (m == 4) {
+          Fl = (double)sm.f[0][fl] + (double)sm.f[4][fl];
+          Fr = (double)sm.f[0][fr] + (double)sm.f[4][fr];
+        } else {
+          Fl = (double)sm.f[m][fl];
+          Fr = (double)sm.f[m][fr];
+        }
+        if (cyl) {
+          if (m == 2) { Fl *= xl; Fr *= xr; }
+          divx[m] = (xr * Fr - xl * Fl) * ivx;
+        } else {
+          divx[m] = (Fr - Fl) * ivx;
+        }
+      }
+      for (int m = 0; m < 5; m++) {
+        double Fb, Ft;
+        if (m == 4) {
+          Fb = (double)sm.f[0][fb] + (double)sm.f[4][fb];
+          Ft = (double)sm.f[0][ft] + (double)sm.f[4][ft];
+        } else {
+          Fb = (double)sm.f[m][fb];
+          Ft = (double)sm.f[m][ft];
+        }
+        if (cyl && m == 2) { Fb *= xc; Ft *= xc; }
+        divz[m] = (Ft - Fb) * ivz;
+      }
+      double s[5];
+      if (MC == MC_CF && catm) sources_atm_cf(gm, dg, xc, g.geom, e.P_atm, rhw2_atm, s);
+      else sources<MC>(gm, dg, xc, g.geom, pc, s);
+      for (int m = 0; m < 5; m++) L[m] = s[m] - divx[m] - divz[m];
+    }
     double dV = cyl ? 2.0 * M_PI * xc * g.dx * g.dz : g.dx * g.dz;
+    double v[5];
     for (int m = 0; m < 5; m++) {
-      double L = s[m] - divx[m] - divz[m];
-      double v = P.b * qs5[m] + P.cdt * L;
-      if (P.use_qn) v += P.a * qn5[m];
-      if (P.use_acc_in) v += P.gdt * ai5[m];
-      P.qo[m][ic] = v;
+      v[m] = P.b * qs5[m] + P.cdt * L[m];
+      if (P.use_qn) v[m] += P.a * qn5[m];
+      if (P.use_acc_in) v[m] += P.gdt * ai5[m];
+      if (!CHAIN) {
+        P.qo[m][ic] = v[m];
+        if (m == 0) mb += v[m] * dV;
+        if (m == 2) jm += v[m] * dV;
+      }
       if (P.use_acc_out) {
-        double av = P.e * L;
+        double av = P.e * L[m];
         if (P.use_acc_in) av += P.d * ai5[m];
         P.acc_out[m][ic] = av;
       }
-      if (m == 0) mb += v * dV;
-      if (m == 2) jm += v * dV;
     }
+    finish_cell<MC, EK, CHAIN>(P, e, ic, gm[GRHD_M_W], gm + GRHD_M_GXX, xc, dV, v, mb, jm, acc);
   }
 
   cmax_out = cmax;

@@ -110,6 +110,7 @@ def lib():
             "grhd_reconstruct": [p, i, i, i, p, p, p, p],
             "grhd_hllc_flux": [p, i, i, i, p, p, p, p, p, p, p],
             "grhd_rk_substep": [p, p, p, p, p, p, p, p, p, p, p, p, p, p, p],
+            "grhd_rk_substep_chained": [p] * 17,
             "grhd_plan_create": [p, i, p, i, p, C.c_char_p, p],
             "grhd_batch_levels": [p, p, i, p, p],
             "grhd_plan_destroy": [p],
@@ -348,6 +349,48 @@ class Substep:
         return call
 
 
+    def _chained_args(self, stage, qn, qs, qout, p_in, flags_in, p_out, flags_out, acc_in, acc_out,
+                      flux_reg, diag, stream):
+        st = make_stage(stage) if isinstance(stage, dict) else stage
+        args = (C.byref(self.grid), C.byref(self.eos), C.byref(self.metric), C.byref(self.opts),
+                C.byref(st), C.byref(make_cons(qn if qn is not None else qs)),
+                C.byref(make_cons(qs)), C.byref(make_cons(qout)), C.byref(make_prim(p_in)),
+                C.c_void_p(flags_in.data_ptr() if flags_in is not None else 0),
+                C.byref(make_prim(p_out)), C.c_void_p(flags_out.data_ptr()),
+                C.byref(make_cons(acc_in)) if acc_in is not None else None,
+                C.byref(make_cons(acc_out)) if acc_out is not None else None,
+                C.c_void_p(flux_reg.data_ptr() if flux_reg is not None else 0),
+                C.c_void_p(diag.data_ptr() if diag is not None else 0),
+                C.c_void_p(stream) if stream is not None else _stream())
+        return st, args
+
+    def chained(self, stage, qn, qs, qout, p_in, flags_in, p_out, flags_out, acc_in=None,
+                acc_out=None, flux_reg=None, diag=None, stream=None, events=None):
+        """grhd_rk_substep_chained: the stage with the recovery of q_out at
+        its end; p_in/flags_in hold the recovery of q_s, p_out/flags_out
+        receive that of q_out."""
+        if events is not None:
+            self.opts.ev_begin, self.opts.ev_end = events[0].handle, events[1].handle
+        else:
+            self.opts.ev_begin = self.opts.ev_end = None
+        _, args = self._chained_args(stage, qn, qs, qout, p_in, flags_in, p_out, flags_out, acc_in,
+                                     acc_out, flux_reg, diag, stream)
+        _check(lib().grhd_rk_substep_chained(*args), "grhd_rk_substep_chained")
+
+    def bind_chained(self, stage, qn, qs, qout, p_in, flags_in, p_out, flags_out, diag=None,
+                     stream=None):
+        """A chained call with every argument marshalled once."""
+        L = lib()
+        st, args = self._chained_args(stage, qn, qs, qout, p_in, flags_in, p_out, flags_out, None,
+                                      None, None, diag, stream)
+        keep = (st, qn, qs, qout, p_in, flags_in, p_out, flags_out, diag)
+
+        def call():
+            _check(L.grhd_rk_substep_chained(*args), "grhd_rk_substep_chained")
+        call.keep = keep
+        return call
+
+
 def rk_substep(grid, eos, metric, opts, stage, qn, qs, qout, p, **kw):
     Substep(grid, eos, metric, opts)(stage, qn, qs, qout, p, **kw)
 
@@ -375,7 +418,7 @@ def make_patch(d):
 
 
 class Plan:
-    """A grhd_plan: one graph-captured persistent substep over many patches.
+    """A grhd_plan: one graph-captured substep over many patches.
     Creating it may run the batch on the given buffers to time candidate
     tile shapes (q_s corrected in place, q_out overwritten)."""
 

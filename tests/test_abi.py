@@ -84,3 +84,47 @@ def test_null_pointers_rejected(G):
     assert lib.grhd_con2prim(*([None] * 9)) == -1
     assert lib.grhd_reconstruct(None, 0, 0, 0, None, None, None, None) == -1
     assert lib.grhd_hllc_flux(None, 0, 0, 0, None, None, None, None, None, None, None) == -1
+
+
+class FakeBuf:
+    """Stands in for a device buffer whose address is never dereferenced."""
+
+    def data_ptr(self):
+        return 0x7000
+
+
+def call_chained(G, opts=None, grid=None, alias_p=False, alias_flags=False, null_flags_out=False):
+    import synth
+    g = G.make_grid(grid or grid_ok())
+    e = G.make_eos(synth.ideal_eos(2.0, 100.0))
+    m = G.make_metric({})
+    o = G.make_options(opts or dict(c2p=dict(w_max=100.0, rho_atm=1e-10)))
+    st = G.make_stage(dict(a=0.0, b=1.0, c=1.0, dt=0.01))
+    q, qo, pi, po = G.Cons(), G.Cons(), G.Prim(), G.Prim()
+    for c in range(5):
+        q.q[c] = 0x1000 + 8 * c   # never dereferenced: validation fails first
+        qo.q[c] = 0x2000 + 8 * c
+    for c in range(6):
+        pi.p[c] = 0x3000 + 8 * c
+        po.p[c] = (0x3000 if alias_p and c == 2 else 0x4000) + 8 * c
+    fi = C.c_void_p(0x5000)
+    fo = None if null_flags_out else C.c_void_p(0x5000 if alias_flags else 0x6000)
+    return G.lib().grhd_rk_substep_chained(C.byref(g), C.byref(e), C.byref(m), C.byref(o), C.byref(st),
+                                           C.byref(q), C.byref(q), C.byref(qo), C.byref(pi), fi,
+                                           C.byref(po), fo, None, None, None, None, None)
+
+
+@pytest.mark.parametrize("bad,rc", [
+    (dict(alias_p=True), -1),
+    (dict(alias_flags=True), -1),
+    (dict(null_flags_out=True), -1),
+    (dict(opts=dict(c2p=dict(w_max=100.0, rho_atm=1e-10, mlp=FakeBuf()))), -3),
+    (dict(opts=dict(c2p=dict(w_max=100.0, rho_atm=1e-10), tile=(32, 8))), -3),
+    (dict(grid=dict(grid_ok(), bc=("axis", "external", "reflect", "outflow"))), -3),
+])
+def test_chained_arguments_rejected(G, bad, rc):
+    """The chained stage rejects aliased outputs (invalid) and what it is
+    not built for (unsupported: learned guess, other tiles, EXTERNAL
+    sides) before touching the device."""
+    assert call_chained(G, **bad) == rc
+    assert len(G.lib().grhd_last_error()) > 0
