@@ -24,7 +24,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRCS = ["or_hydro.c", "or_riemann.c", "or_mlp.c"]
+_SRCS = ["or_hydro.c", "or_riemann.c", "or_mlp.c", "or_fmr.c"]
 
 METRIC_NAMES = ["alp", "bx", "by", "bz", "W", "gxx", "gxy", "gxz", "gyy",
                 "gyz", "gzz", "kxx", "kxy", "kxz", "kyy", "kyz", "kzz"]
@@ -117,6 +117,10 @@ def lib():
             "or_face_flux": (None, [p, i, i, p, p, p, p, p, p]),
             "or_rhs": (None, [p, p, p, p, p, p, p]),
             "or_rk_substep": (i, [p, p, p, i, i, p, p, p, p, p, p, p, p, p, p, p]),
+            "or_rk_substep_reg": (i, [p, p, p, i, i, p, p, p, p, p, p, p, p, p, p, p, p, i, i, d]),
+            "or_fmr_prolong": (None, [p, p, p, p, i, d, d, d, d, p, p, p, p, p]),
+            "or_fmr_restrict": (None, [p, p, p, p]),
+            "or_fmr_reflux": (None, [p, p, p, p, p]),
             "or_riemann_solve": (i, [d, d, d, d, d, d, d, p]),
             "or_riemann_sample": (None, [d, p, d, p, p, p]),
             "or_riemann_cellavg": (i, [d, d, d, d, d, d, d, d, d, i, p, i, p, p, p]),
@@ -352,9 +356,12 @@ SSPRK3 = [dict(a=0.0, b=1.0, c=1.0), dict(a=0.75, b=0.25, c=0.25),
           dict(a=1.0 / 3.0, b=2.0 / 3.0, c=2.0 / 3.0)]
 
 
-def rk_substep(grid, eos, metric, opts, stage, qn, qs, acc_in=None, want_acc=False):
+def rk_substep(grid, eos, metric, opts, stage, qn, qs, acc_in=None, want_acc=False, reg=None):
     """One substep.  Returns dict(qout, qs (corrected), p, flags, diag,
-    flux_reg, acc).  Inputs are not modified."""
+    flux_reg, acc).  Inputs are not modified.  reg: optional (array,
+    reg_j, reg_k, weight): the refinement-boundary register (5 x (reg_k +
+    reg_j) float64, updated in place) gets weight dt F added on the face
+    set {x faces j = reg_j, k < reg_k} + {z faces k = reg_k, j < reg_j}."""
     keep = []
     qs = qs.copy()
     qout = np.zeros_like(qs)
@@ -368,7 +375,9 @@ def rk_substep(grid, eos, metric, opts, stage, qn, qs, acc_in=None, want_acc=Fal
     st.g, st.d, st.e = stage.get("g", 0.0), stage.get("d", 0.0), stage.get("e", 0.0)
     acc_out = np.zeros_like(qs) if want_acc else None
     qn_ptr = _fieldptrs(qn, 5) if qn is not None else None
-    lib().or_rk_substep(
+    if reg is not None:
+        assert reg[0].dtype == np.float64 and reg[0].flags.c_contiguous
+    lib().or_rk_substep_reg(
         C.byref(make_grid(grid)), C.byref(make_eos(eos)),
         C.byref(make_metric(metric, keep)), RECON[opts.get("recon", "ppm")],
         RIEMANN[opts.get("riemann", "hllc")], C.byref(make_c2p(opts["c2p"])),
@@ -376,9 +385,141 @@ def rk_substep(grid, eos, metric, opts, stage, qn, qs, acc_in=None, want_acc=Fal
         _fieldptrs(qs, 5), _fieldptrs(qout, 5), _fieldptrs(p, 6),
         _fieldptrs(acc_in, 5) if acc_in is not None else None,
         _fieldptrs(acc_out, 5) if acc_out is not None else None,
-        _ptr(freg), _ptr(flags), C.byref(d))
+        _ptr(freg), _ptr(flags), C.byref(d),
+        _ptr(reg[0]) if reg is not None else None,
+        reg[1] if reg is not None else 0, reg[2] if reg is not None else 0,
+        float(reg[3]) if reg is not None else 0.0)
     return dict(qout=qout, qs=qs, p=p, flags=flags, diag=d.as_dict(),
                 flux_reg=freg.reshape(5, nb), acc=acc_out)
+
+
+# ---------------------------------------------------------------- refinement
+
+def fmr_prolong(pgrid, slices, times, t, cgrid, eos, cmetric, p_child, q_child):
+    """Fill the child's EXTERNAL ghost cells (p_child 6 and q_child 5 cell
+    arrays, updated in place) from the parent's primitive slices (a list of
+    1-3 arrays, oldest first, with their times) at time t."""
+    keep = []
+    ns = len(slices)
+    old = slices[0] if ns == 3 else None
+    cur = slices[-2] if ns >= 2 else slices[0]
+    new = slices[-1] if ns >= 2 else None
+    t_old = times[0] if ns == 3 else 0.0
+    t_cur = times[-2] if ns >= 2 else times[0]
+    t_new = times[-1] if ns >= 2 else 0.0
+    lib().or_fmr_prolong(C.byref(make_grid(pgrid)), _fieldptrs(old, 6) if old is not None else None,
+                         _fieldptrs(cur, 6), _fieldptrs(new, 6) if new is not None else None, ns,
+                         t_old, t_cur, t_new, t, C.byref(make_grid(cgrid)), C.byref(make_eos(eos)),
+                         C.byref(make_metric(cmetric, keep)), _fieldptrs(p_child, 6),
+                         _fieldptrs(q_child, 5))
+
+
+def fmr_restrict(pgrid, q_parent, cgrid, q_child):
+    """q_parent (updated in place) over the child's footprint."""
+    lib().or_fmr_restrict(C.byref(make_grid(pgrid)), _fieldptrs(q_parent, 5),
+                          C.byref(make_grid(cgrid)), _fieldptrs(q_child, 5))
+
+
+def fmr_reflux(pgrid, q_parent, preg, cgrid, creg):
+    """Flux correction of the parent cells next to the child (in place)."""
+    preg, creg = _f64(preg), _f64(creg)
+    lib().or_fmr_reflux(C.byref(make_grid(pgrid)), _fieldptrs(q_parent, 5), _ptr(preg),
+                        C.byref(make_grid(cgrid)), _ptr(creg))
+
+
+class FmrDriver:
+    """Berger-Oliger driver of the oracle (Sec. II.E): the same schedule as
+    the library's (SSP-RK3 per level, levels l <= l_fix take the parent's
+    step and finer ones half of it, a child's ghost cells prolonged from its
+    parent's slices at every stage time, restriction, flux correction and
+    recovery of the parent after its child's steps), with every operation
+    done by the oracle functions above.  levels: list of dict(grid, metric,
+    q) with numpy cell arrays (q is copied)."""
+
+    A = (0.0, 0.75, 1.0 / 3.0)
+    B = (1.0, 0.25, 2.0 / 3.0)
+    T = (0.0, 1.0, 0.5)          # stage times in units of dt
+    W = (1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0)   # weights of the stage fluxes in the step
+
+    def __init__(self, levels, eos, opts, l_fix=0, t0=0.0):
+        self.lev = [dict(grid=d["grid"], metric=d["metric"], q=np.array(d["q"], dtype=np.float64))
+                    for d in levels]
+        self.eos, self.opts, self.l_fix, self.t = eos, opts, l_fix, t0
+        n = len(self.lev)
+        self.slices = [[] for _ in range(n)]
+        for l, L in enumerate(self.lev):
+            g = L["grid"]
+            L["reg_bnd"] = np.zeros(5 * (g["nx"] + g["nz"])) if l > 0 else None
+            if l + 1 < n:
+                cg = self.lev[l + 1]["grid"]
+                L["reg_int"] = np.zeros(5 * (cg["nx"] // 2 + cg["nz"] // 2))
+                self._push(l, t0)
+            else:
+                L["reg_int"] = None
+
+    def _recover(self, l):
+        L = self.lev[l]
+        p, q, _, _ = con2prim(L["grid"], self.eos, L["metric"], self.opts["c2p"], L["q"])
+        L["q"] = q
+        return p
+
+    def _push(self, l, t):
+        self.slices[l].append((t, self._recover(l)))
+        self.slices[l] = self.slices[l][-3:]
+
+    def _step(self, l, t, dt):
+        n = len(self.lev)
+        L = self.lev[l]
+        g = L["grid"]
+        nx, nz = g["nx"], g["nz"]
+        has_child, has_parent = l + 1 < n, l > 0
+        if has_child:
+            cg = self.lev[l + 1]["grid"]
+            J, K = cg["nx"] // 2, cg["nz"] // 2
+            L["reg_int"][:] = 0.0
+        bufs = {"q": L["q"], "q1": np.zeros_like(L["q"]), "q2": np.zeros_like(L["q"])}
+        order = [("q", "q", "q1"), ("q", "q1", "q2"), ("q", "q2", "q")]
+        for s in range(3):
+            qn_name, qs_name, qo_name = order[s]
+            if has_parent:
+                P = self.lev[l - 1]
+                ts = [x[0] for x in self.slices[l - 1]]
+                sl = [x[1] for x in self.slices[l - 1]]
+                p_scratch = np.zeros((6,) + L["q"].shape[1:])
+                fmr_prolong(P["grid"], sl, ts, t + self.T[s] * dt, g, self.eos, L["metric"], p_scratch,
+                            bufs[qs_name])
+            st = dict(a=self.A[s], b=self.B[s], c=self.B[s], dt=dt)
+            reg = (L["reg_int"], J, K, self.W[s]) if has_child else None
+            r = rk_substep(g, self.eos, L["metric"], self.opts, st, bufs[qn_name], bufs[qs_name], reg=reg)
+            bufs[qs_name] = r["qs"]
+            if qs_name == "q":
+                bufs["q"] = r["qs"]
+            if has_parent:
+                fr = r["flux_reg"]
+                w = self.W[s] * dt
+                rb = L["reg_bnd"].reshape(5, nx + nz)
+                rb[:, :nz] += w * fr[:, nz:2 * nz]
+                rb[:, nz:] += w * fr[:, 2 * nz + nx:]
+            out = np.array(bufs[qo_name]) if qo_name != "q" else bufs["q"]
+            I = (slice(None), slice(g["ng"], g["ng"] + nz), slice(g["ng"], g["ng"] + nx))
+            out[I] = r["qout"][I]
+            bufs[qo_name] = out
+        L["q"] = bufs["q"]
+        if not has_child:
+            return
+        self._push(l, t + dt)
+        nsub = 1 if l + 1 <= self.l_fix else 2
+        for i in range(nsub):
+            self._step(l + 1, t + i * (dt / nsub), dt / nsub)
+        C_ = self.lev[l + 1]
+        fmr_restrict(g, L["q"], C_["grid"], C_["q"])
+        fmr_reflux(g, L["q"], L["reg_int"], C_["grid"], C_["reg_bnd"])
+        C_["reg_bnd"][:] = 0.0
+        self.slices[l][-1] = (t + dt, self._recover(l))
+
+    def step(self, dt0):
+        self._step(0, self.t, dt0)
+        self.t += dt0
 
 
 # ---------------------------------------------------------------- exact Riemann

@@ -914,6 +914,16 @@ int or_rk_substep(const or_grid *gr, const or_eos *e, const or_metric *m,
                   double *const *p_out, double *const *acc_in,
                   double *const *acc_out, double *flux_reg, uint8_t *flags,
                   or_diag *diag) {
+  return or_rk_substep_reg(gr, e, m, recon, riemann, cp, st, qn, qs, qout, p_out, acc_in,
+                           acc_out, flux_reg, flags, diag, NULL, 0, 0, 0.0);
+}
+
+int or_rk_substep_reg(const or_grid *gr, const or_eos *e, const or_metric *m,
+                      int recon, int riemann, const or_c2p *cp, const or_stage *st,
+                      double *const *qn, double *const *qs, double *const *qout,
+                      double *const *p_out, double *const *acc_in,
+                      double *const *acc_out, double *flux_reg, uint8_t *flags,
+                      or_diag *diag, double *reg, int reg_j, int reg_k, double reg_w) {
   int nx = gr->nx, nz = gr->nz;
   int64_t ncell = (int64_t)(nz + 2 * gr->ng) * gr->pitch;
   int64_t nfxa = (int64_t)nz * (nx + 1), nfza = (int64_t)(nz + 1) * nx;
@@ -971,6 +981,19 @@ int or_rk_substep(const or_grid *gr, const or_eos *e, const or_metric *m,
         flux_reg[c * nb + 2 * nz + j] = Fz[c][j];
         flux_reg[c * nb + 2 * nz + nx + j] = Fz[c][(int64_t)nz * nx + j];
       }
+    }
+  }
+  /* 7b. refinement-boundary flux register (Sec. II.E): the time integral
+   * of the flux through the L-shaped face set {x faces j = reg_j, k <
+   * reg_k} + {z faces k = reg_k, j < reg_j}, accumulated with the stage's
+   * weight in the Runge-Kutta step */
+  if (reg) {
+    int64_t nr = (int64_t)reg_k + reg_j;
+    for (int c = 0; c < 5; c++) {
+      for (int k = 0; k < reg_k; k++)
+        reg[c * nr + k] += reg_w * st->dt * Fx[c][(int64_t)k * (nx + 1) + reg_j];
+      for (int j = 0; j < reg_j; j++)
+        reg[c * nr + reg_k + j] += reg_w * st->dt * Fz[c][(int64_t)reg_k * nx + j];
     }
   }
   /* 8. diagnostics on the stage output */

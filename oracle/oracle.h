@@ -137,6 +137,38 @@ int or_rk_substep(const or_grid *gr, const or_eos *e, const or_metric *m,
                   double *const *acc_out, double *flux_reg, uint8_t *flags,
                   or_diag *diag);
 
+/* the same substep, also adding reg_w dt F on the refinement-boundary
+ * face set {x faces j = reg_j, k < reg_k} + {z faces k = reg_k, j < reg_j}
+ * into reg (5 x (reg_k + reg_j): x faces by k, then z faces by j) */
+int or_rk_substep_reg(const or_grid *gr, const or_eos *e, const or_metric *m,
+                      int recon, int riemann, const or_c2p *cp, const or_stage *st,
+                      double *const *qn, double *const *qs, double *const *qout,
+                      double *const *p_out, double *const *acc_in,
+                      double *const *acc_out, double *flux_reg, uint8_t *flags,
+                      or_diag *diag, double *reg, int reg_j, int reg_k, double reg_w);
+
+/* fixed mesh refinement between a parent level and its child, which
+ * covers the parent cells [0, nx_c/2) x [0, nz_c/2) with half the spacing
+ * (Sec. II.A, II.E).
+ * prolong: the child's ghost cells on EXTERNAL sides (the cross-shaped
+ * halo) from the parent's primitives: time interpolation of nslice parent
+ * slices (1: p_cur; 2: linear between t_cur and t_new; 3: quadratic over
+ * t_old, t_cur, t_new, linear where the slices are not monotone) at time t,
+ * then minmod-limited linear prolongation in space, then the conserved
+ * variables from the primitives with the child's metric.
+ * restrict: q_parent = sum(q_child dV_child) / dV_parent over each 2 x 2
+ * block.  reflux: the parent cells just outside the child get the
+ * difference of the child's and the parent's time-integrated fluxes through
+ * the shared faces. */
+void or_fmr_prolong(const or_grid *pg, double *const *p_old, double *const *p_cur,
+                    double *const *p_new, int nslice, double t_old, double t_cur,
+                    double t_new, double t, const or_grid *cg, const or_eos *e,
+                    const or_metric *cm, double *const *cp /*6*/, double *const *cq /*5*/);
+void or_fmr_restrict(const or_grid *pg, double *const *pq, const or_grid *cg,
+                     double *const *cq);
+void or_fmr_reflux(const or_grid *pg, double *const *pq, const double *preg,
+                   const or_grid *cg, const double *creg);
+
 /* exact special-relativistic Riemann solver (ideal gas, no tangential
  * velocity); returns 0 on success, 1 if the solution contains vacuum */
 int or_riemann_solve(double gam, double rhoL, double pL, double vL,

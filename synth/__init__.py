@@ -252,6 +252,39 @@ def fmr_levels(nlev=6, n=256, finest_extent=20.0):
     return [star_grid(n, finest_extent * 2 ** (nlev - 1 - l)) for l in range(nlev)]
 
 
+def fmr_grids(nlev, n, extent, geom="cart", outer="reflect"):
+    """Nested 2:1 levels anchored at the lower faces: level 0 covers
+    [0, extent]^2 with n x n cells, every finer level n x n cells over its
+    parent's lower-left quarter with EXTERNAL high sides; level 0's high
+    sides are `outer`; low sides: axis (cyl) or reflect (cart) in x,
+    reflect in z."""
+    lo_x = "axis" if geom == "cyl" else "reflect"
+    out = []
+    for l in range(nlev):
+        d = extent / n / 2 ** l
+        hi = outer if l == 0 else "external"
+        out.append(make_grid(n, n, 0.0, 0.0, d, d, geom, (lo_x, hi, "reflect", hi)))
+    return out
+
+
+def blast_state(grid, center, width, seed, gamma=5.0 / 3.0, vamp=0.05):
+    """Smooth over-dense, over-pressured Gaussian bump at `center` on a
+    uniform background, with a small seeded velocity field."""
+    rng = np.random.default_rng(seed)
+    X, Z = cell_coords(grid)
+    r2 = ((X - center[0]) ** 2 + (Z - center[1]) ** 2) / width ** 2
+    bump = np.exp(-r2)
+    ph = rng.uniform(0, 2 * math.pi, 3)
+    p = empty_fields(grid, 6)
+    p[0] = 1.0 + 0.5 * bump
+    p[1] = vamp * bump * np.sin(X / width + ph[0])
+    p[2] = 0.5 * vamp * bump * np.cos(Z / width + ph[1])
+    p[3] = vamp * bump * np.sin((X + Z) / width + ph[2])
+    p[4] = 0.1 + 1.0 * bump
+    p[5] = p[4] / ((gamma - 1.0) * p[0])
+    return p
+
+
 def riemann_patch_sizes(seed, npatch=64, lo=128, hi=2048):
     rng = np.random.default_rng(seed)
     return [int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
