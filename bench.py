@@ -18,6 +18,10 @@ FP64 path.  The JSON line also carries:
   forms.batched  six nested 256^2 star levels plus 64 Riemann patches
                  (N_x log-uniform in [128, 2048], 8 periodic z cells) in one
                  graph-captured batched launch, against one call per patch;
+  forms.fmr      Berger-Oliger evolution of the same six levels as one
+                 refinement hierarchy (prolongation at every stage,
+                 restriction, refluxing; l_fix = 0 and l_fix = 5), with the
+                 composite baryon-mass change over the timed steps;
   forms.learned  recovery of a 2048^2 differentially rotating field, Illinois
                  from the bracket against Newton seeded by the matrix-core MLP
                  (trained here on GPU), same root;
@@ -48,7 +52,7 @@ BYTES_KERNEL = [144.0, 184.0, 184.0]
 # algorithmic bytes per zone-update of a whole substep (recovery included):
 # q_s and the metric read, q_out written, q^n read in stages 2 and 3
 BYTES_SUBSTEP = [96.0, 136.0, 136.0]
-ALL_FORMS = ("fp64", "fp64_chained", "mixed", "batched", "learned")
+ALL_FORMS = ("fp64", "fp64_chained", "mixed", "batched", "fmr", "learned")
 # measured HBM traffic of the fused kernel (rocprofv3 FETCH_SIZE/WRITE_SIZE,
 # calibrated with a plain copy) is kept with the hash of the sources it was
 # measured on; it is reported only while the sources still hash the same
@@ -251,6 +255,9 @@ def main():
     if "batched" in forms:
         out_forms["batched"] = batched_form(args, tov)
         print("batched done", file=sys.stderr, flush=True)
+    if "fmr" in forms:
+        out_forms["fmr"] = fmr_form(args, tov)
+        print("fmr done", file=sys.stderr, flush=True)
     if "learned" in forms:
         out_forms["learned"] = learned_form(args)
         print("learned done", file=sys.stderr, flush=True)
@@ -417,6 +424,72 @@ def batched_form(args, tov):
                      "speedup_vs_per_patch": out["batched"] / out["per_patch_calls"],
                      "tiles": plan.tiles()}
         plan.close()
+    return res
+
+
+def fmr_form(args, tov):
+    """Six nested 256^2 levels of the star as one refinement hierarchy
+    (level l covers [0, 20 2^(5-l)]^2): zone-updates/s over whole coarse
+    steps, counting every level's substeps."""
+    import torch
+
+    import synth
+    from paper_2502_03223_amd import grhd
+    dev = torch.device("cuda:0")
+    grids = synth.fmr_grids(6, 256, 640.0, geom="cyl", outer="outflow")
+    eos = synth.ideal_eos(tov["G"], K=tov["K"])
+    opts = dict(recon="ppm", riemann="hllc", prec="fp64", c2p=dict(w_max=100.0, rho_atm=1e-10))
+    res = {"workload": "6 nested 256^2 TOV star levels, outer edges 20..640, cylindrical, "
+                       "Berger-Oliger with prolongation, restriction and refluxing; SSP-RK3"}
+    steps = max(args.steps // 10, 3)
+
+    def mass(levels):
+        M = 0.0
+        for l, L in enumerate(levels):
+            g = L["grid"]
+            q = synth.interior(g, L["q"].cpu().numpy())
+            X, _ = synth.cell_coords(g)
+            x = synth.interior(g, X)
+            dV = 2.0 * math.pi * x * g["dx"] * g["dz"]
+            mask = np.ones_like(x, dtype=bool)
+            if l + 1 < len(levels):
+                mask[:grids[l + 1]["nz"] // 2, :grids[l + 1]["nx"] // 2] = False
+            M += float((q[0] * dV)[mask].sum())
+        return M
+    for l_fix in (0, 5):
+        levels = []
+        for lvl, g in enumerate(grids):
+            p, met, _ = synth.star_problem(g, seed=100 + lvl, tov=tov)
+            metric = {k: torch.from_numpy(v).to(dev) for k, v in met.items()}
+            q = torch.zeros((5,) + p.shape[1:], dtype=torch.float64, device=dev)
+            grhd.prim2con(g, eos, metric, torch.from_numpy(p).to(dev), q, with_ghosts=True)
+            levels.append(dict(grid=g, metric=metric, q=q))
+        h = grhd.Hierarchy(levels, eos, opts, l_fix=l_fix)
+        # the finest level keeps a Courant factor of 0.4
+        dt0 = 0.4 * grids[0]["dx"] / 2 ** min(l_fix, len(grids) - 1)
+        level_steps = [1]
+        for l in range(1, len(grids)):
+            level_steps.append(level_steps[-1] * (1 if l <= l_fix else 2))
+        zu = 3 * sum(g["nx"] * g["nz"] * n for g, n in zip(grids, level_steps))
+        for _ in range(2):
+            h.step(dt0)
+        torch.cuda.synchronize()
+        M0 = mass(levels)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            h.step(dt0)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        M1 = mass(levels)
+        res["l_fix_%d" % l_fix] = {"value": zu * steps / wall, "unit": "zone-updates/s",
+                                   "coarse_steps": steps, "level_steps_per_coarse_step": level_steps,
+                                   "ms_per_coarse_step": wall * 1e3 / steps,
+                                   "gpu_ms_per_coarse_step": e0.elapsed_time(e1) / steps,
+                                   "mass_rel_change": (M1 - M0) / M0}
+        h.close()
     return res
 
 

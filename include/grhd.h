@@ -182,7 +182,8 @@ int grhd_hllc_flux(const grhd_grid *grid, int dir, int riemann, int prec,
  * fluxes in both directions, area-weighted divergence with the cylindrical
  * and metric source terms, stage combination.
  * qn: q^n (read only when stage->a != 0; may alias qs).  qs: in/out.
- * qout: out (interior cells; must not alias qs or qn).
+ * qout: out (interior cells; must not alias qs; may alias qn, each cell
+ * reads its own q^n before its q_out is written).
  * p: required workspace and output: primitives of q_s (interior cells).
  * acc_in / acc_out: nullable accumulator cell arrays (RK4).
  * flux_reg: nullable, 5 x (2 nz + 2 nx) doubles: the q fluxes on the
@@ -259,6 +260,77 @@ int grhd_plan_destroy(grhd_plan *plan);
  * square-ish patches, tile_x[1], tile_z[1] = thin patches (nz <= 8);
  * both arrays hold 2 ints. */
 int grhd_plan_tile(const grhd_plan *plan, int *tile_x, int *tile_z);
+
+/* ------------------------------------------------------- mesh refinement */
+
+/* Fixed mesh refinement, Sec. II.A and II.E.  Levels are the nested,
+ * mirror-symmetric boxes of Sec. II.A: a child starts at its parent's lower
+ * faces with half the spacing (child cell (jf, kf) lies in parent cell
+ * (jf/2, kf/2)), has even nx, nz, the parent's low-side boundary
+ * conditions, EXTERNAL high sides, and its parent extends at least 3 cells
+ * beyond it.  Registers hold time integrals of face fluxes (in the flux
+ * register form of grhd_rk_substep: S_phi component times x, E flux).
+ * reg_child_bnd (levels with a parent): 5 x (nx + nz): the x-high faces by
+ * k, then the z-high faces by j.  reg_parent_int (levels with a child):
+ * 5 x (K + J) with J = nx_child/2, K = nz_child/2: the x faces j = J,
+ * k < K, then the z faces k = K, j < J. */
+typedef struct {
+  grhd_grid grid;
+  grhd_metric metric;
+  grhd_cons q;               /* state (in/out) */
+  grhd_cons q1, q2;          /* Runge-Kutta stage buffers */
+  grhd_prim p;               /* recovery workspace */
+  grhd_prim slice[3];        /* primitive time slices (levels with a child) */
+  double *reg_child_bnd;     /* levels with a parent */
+  double *reg_parent_int;    /* levels with a child */
+} grhd_level;
+
+typedef struct grhd_fmr grhd_fmr;   /* opaque, library-owned */
+
+/* Prolongation into the child's EXTERNAL ghost cells (the cross-shaped
+ * halo), Sec. II.E: the parent's primitives at time t from nslice slices
+ * (oldest first, increasing times: 1 = the slice itself, 2 = linear, 3 =
+ * second-order Lagrange, first order through the last two slices where
+ * (p^{n+1} - p^n)(p^n - p^{n-1}) < 0), the parent's boundary conditions on
+ * them, minmod-limited linear prolongation in space (per field, x and z
+ * slopes over the child centre's offset), then the conserved variables
+ * from the primitives with the child's metric (no recovery).  Writes
+ * p_child and q_child ghost cells only.  rho_atm: atmosphere floor of the
+ * EOS constants. */
+int grhd_fmr_prolong(const grhd_grid *parent, const grhd_prim *slices, int nslice,
+                     const double *times, double t, const grhd_grid *child,
+                     const grhd_metric *child_metric, const grhd_eos *eos,
+                     double rho_atm, const grhd_prim *p_child,
+                     const grhd_cons *q_child, void *hip_stream);
+
+/* Conservative restriction, Sec. II.E: every parent cell under the child
+ * takes sum(q_child dV_child) / dV_parent of its 2 x 2 child cells. */
+int grhd_fmr_restrict(const grhd_grid *parent, const grhd_cons *q_parent,
+                      const grhd_grid *child, const grhd_cons *q_child,
+                      void *hip_stream);
+
+/* Flux correction, Sec. II.E: the parent cells just outside the child
+ * (x interface: cells (J, k < K); z interface: cells (j < J, K)) replace
+ * the parent's time-integrated flux through their low face by the child's
+ * (area-weighted over the two child faces). */
+int grhd_fmr_reflux(const grhd_grid *parent, const grhd_cons *q_parent,
+                    const double *reg_parent, const grhd_grid *child,
+                    const double *reg_child, void *hip_stream);
+
+/* Berger-Oliger driver (Sec. II.E) over nlev levels (level 0 coarsest):
+ * a level steps with SSP-RK3; levels l <= l_fix take the parent's step,
+ * finer levels half of it; before each stage a child's ghost cells are
+ * prolonged from its parent's slices at the stage time; after a child's
+ * steps its parent is restricted, refluxed and recovered.  create: copies
+ * the level descriptors (device buffers stay the caller's), recovers every
+ * level with a child into its first slice.  step: one step dt0 of level 0
+ * (all finer levels follow).  Single path kernels on the 16 x 16 tiles. */
+int grhd_fmr_create(const grhd_level *levels, int nlev, const grhd_eos *eos,
+                    const grhd_options *opts, int l_fix, double t0,
+                    grhd_fmr **out, void *hip_stream);
+int grhd_fmr_step(grhd_fmr *h, double dt0, void *hip_stream);
+int grhd_fmr_time(const grhd_fmr *h, double *t);
+int grhd_fmr_destroy(grhd_fmr *h);
 
 /* ---------------------------------------------------------- learned guess */
 

@@ -563,9 +563,10 @@ int fill_patch(const grhd_grid *grid, const grhd_metric *metric, const grhd_rk_s
   if (acc_out && (rc = check_cons(acc_out, "acc_out"))) return rc;
   if (recon != GRHD_RECON_PPM && recon != GRHD_RECON_MINMOD) return fail(GRHD_ERR_INVALID, "bad recon");
   if (riemann != GRHD_RIEMANN_HLLC && riemann != GRHD_RIEMANN_TVDLF) return fail(GRHD_ERR_INVALID, "bad riemann");
+  // q_out may alias q^n (each cell reads its own q^n before writing
+  // q_out), never q_s (whose halo other tiles read)
   for (int c = 0; c < 5; c++)
-    if (qout->q[c] == qs->q[c] || (stage->a != 0.0 && qout->q[c] == qn->q[c]))
-      return fail(GRHD_ERR_INVALID, "qout must not alias qs or qn");
+    if (qout->q[c] == qs->q[c]) return fail(GRHD_ERR_INVALID, "qout must not alias qs");
   pk.g = to_gridk(grid);
   pk.m = to_metk(metric);
   for (int c = 0; c < 5; c++) {
@@ -590,6 +591,12 @@ int fill_patch(const grhd_grid *grid, const grhd_metric *metric, const grhd_rk_s
   for (int c = 0; c < 6; c++) pk.po[c] = nullptr;
   pk.flags_out = nullptr;
   pk.cp = C2PK{};
+  for (int s = 0; s < 2; s++) {
+    pk.reg[s] = nullptr;
+    pk.reg_j[s] = 0;
+    pk.reg_k[s] = 0;
+  }
+  pk.reg_w = 0.0;
   return GRHD_OK;
 }
 }  // namespace grhd

@@ -28,6 +28,12 @@ struct PatchK {
   double *po[6];       // primitives of q_out
   uint8_t *flags_out;  // recovery flags of q_out
   C2PK cp;
+  // refinement-boundary flux registers (nullable): reg[s] accumulates
+  // reg_w dt F over the face set {x faces j = reg_j[s], k < reg_k[s]} +
+  // {z faces k = reg_k[s], j < reg_j[s]} (5 x (reg_k + reg_j) doubles)
+  double *reg[2];
+  int reg_j[2], reg_k[2];
+  double reg_w;
   int tiles_x, tiles_z;
   int xshift;  // tile tx covers cells j in [tx TX - xshift, (tx + 1) TX - xshift)
   long long tile_base;
@@ -106,6 +112,28 @@ __device__ __forceinline__ double wave_sum(double v) {
 __device__ __forceinline__ double wave_max(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
+}
+
+// Adds reg_w dt F of one face to the refinement-boundary registers that
+// contain it.  A face on a tile edge is computed by both tiles: the tile
+// holding the cell on its high side adds it (the last tile at the patch's
+// high edge).  fv: the face flux in register form (S_phi component times
+// x, E flux = D flux + tau flux).
+template <int TX, int TZ>
+__device__ __forceinline__ void fmr_reg_add(const PatchK &P, bool isx, int j, int k, int jj, int kk,
+                                            const double *fv) {
+  for (int s = 0; s < 2; s++) {
+    double *r = P.reg[s];
+    if (!r) continue;
+    const int rj = P.reg_j[s], rk = P.reg_k[s];
+    const bool on = isx ? (j == rj && k < rk && (jj < TX || j == P.g.nx))
+                        : (k == rk && j < rj && (kk < TZ || k == P.g.nz));
+    if (!on) continue;
+    const long long nr = (long long)rk + rj;
+    const long long o = isx ? k : rk + j;
+    const double wdt = P.reg_w * P.dt;
+    for (int m = 0; m < 5; m++) r[m * nr + o] += wdt * fv[m];
+  }
 }
 
 // Recovery statistics of the cells one thread finished (rescale, cold,
@@ -296,6 +324,10 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
           for (int m = 0; m < 5; m++) P.flux_reg[m * nb + o] = 0.0;
           P.flux_reg[(isx ? 1 : 3) * nb + o] = (double)fn;
         }
+        if (P.reg[0] || P.reg[1]) {
+          double fv[5] = {0.0, isx ? (double)fn : 0.0, 0.0, isx ? 0.0 : (double)fn, 0.0};
+          fmr_reg_add<TX, TZ>(P, isx, j, k, jj, kk, fv);
+        }
       }
       sm.f[0][f] = fn;
     }
@@ -387,13 +419,17 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
           face_flux<T, MC>(e, fm, isx ? 0 : 1, P.riemann, L, R, out);
         }
         cmax = fmax(cmax, (double)out.speed * (P.dt / (isx ? g.dx : g.dz)));
-        if (P.flux_reg && (isx ? (j == 0 || j == nx) : (k == 0 || k == nz))) {
-          int o = isx ? ((j == 0) ? k : nz + k) : 2 * nz + ((k == 0) ? j : nx + j);
+        const bool on_edge = isx ? (j == 0 || j == nx) : (k == 0 || k == nz);
+        if ((P.flux_reg && on_edge) || P.reg[0] || P.reg[1]) {
           double xx = isx ? g.x0 + j * g.dx : g.x0 + (j + 0.5) * g.dx;
           double fv[5] = {(double)out.f[0], (double)out.f[1], (double)out.f[2], (double)out.f[3],
                           (double)out.f[0] + (double)out.f[4]};
           if (cyl) fv[2] *= xx;
-          for (int m = 0; m < 5; m++) P.flux_reg[m * nb + o] = fv[m];
+          if (P.flux_reg && on_edge) {
+            int o = isx ? ((j == 0) ? k : nz + k) : 2 * nz + ((k == 0) ? j : nx + j);
+            for (int m = 0; m < 5; m++) P.flux_reg[m * nb + o] = fv[m];
+          }
+          fmr_reg_add<TX, TZ>(P, isx, j, k, jj, kk, fv);
         }
       }
       for (int m = 0; m < 5; m++) sm.f[m][f] = out.f[m];

@@ -87,6 +87,12 @@ class Diag(C.Structure):
                 ("iter_sum", C.c_ulonglong), ("iter_max", C.c_ulonglong)]
 
 
+class Level(C.Structure):
+    _fields_ = [("grid", Grid), ("metric", Metric), ("q", Cons), ("q1", Cons), ("q2", Cons),
+                ("p", Prim), ("slice", Prim * 3), ("reg_child_bnd", C.c_void_p),
+                ("reg_parent_int", C.c_void_p)]
+
+
 class Patch(C.Structure):
     _fields_ = [("grid", Grid), ("metric", Metric), ("qn", Cons), ("qs", Cons),
                 ("qout", Cons), ("p", Prim), ("stage", Stage), ("eos_id", C.c_int),
@@ -111,6 +117,13 @@ def lib():
             "grhd_hllc_flux": [p, i, i, i, p, p, p, p, p, p, p],
             "grhd_rk_substep": [p, p, p, p, p, p, p, p, p, p, p, p, p, p, p],
             "grhd_rk_substep_chained": [p] * 17,
+            "grhd_fmr_prolong": [p, p, i, p, C.c_double, p, p, p, C.c_double, p, p, p],
+            "grhd_fmr_restrict": [p, p, p, p, p],
+            "grhd_fmr_reflux": [p, p, p, p, p, p],
+            "grhd_fmr_create": [p, i, p, p, i, C.c_double, p, p],
+            "grhd_fmr_step": [p, C.c_double, p],
+            "grhd_fmr_time": [p, p],
+            "grhd_fmr_destroy": [p],
             "grhd_plan_create": [p, i, p, i, p, C.c_char_p, p],
             "grhd_batch_levels": [p, p, i, p, p],
             "grhd_plan_destroy": [p],
@@ -484,6 +497,103 @@ class Event:
     def __del__(self):
         try:
             lib().grhd_event_destroy(self.handle)
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ mesh refinement
+
+def fmr_prolong(pgrid, slices, times, t, cgrid, cmetric, eos, rho_atm, p_child, q_child):
+    """grhd_fmr_prolong: slices = list of 1-3 (6, rows, pitch) parent
+    primitive tensors, oldest first, with their times."""
+    arr = (Prim * len(slices))(*[make_prim(x) for x in slices])
+    tm = (C.c_double * len(times))(*times)
+    rc = lib().grhd_fmr_prolong(C.byref(make_grid(pgrid)), arr, len(slices), tm, float(t),
+                                C.byref(make_grid(cgrid)), C.byref(make_metric(cmetric)),
+                                C.byref(make_eos(eos)), float(rho_atm), C.byref(make_prim(p_child)),
+                                C.byref(make_cons(q_child)), _stream())
+    _check(rc, "grhd_fmr_prolong")
+
+
+def fmr_restrict(pgrid, q_parent, cgrid, q_child):
+    rc = lib().grhd_fmr_restrict(C.byref(make_grid(pgrid)), C.byref(make_cons(q_parent)),
+                                 C.byref(make_grid(cgrid)), C.byref(make_cons(q_child)), _stream())
+    _check(rc, "grhd_fmr_restrict")
+
+
+def fmr_reflux(pgrid, q_parent, reg_parent, cgrid, reg_child):
+    for r in (reg_parent, reg_child):
+        assert r.is_cuda and r.dtype == torch.float64 and r.is_contiguous()
+    rc = lib().grhd_fmr_reflux(C.byref(make_grid(pgrid)), C.byref(make_cons(q_parent)),
+                               C.c_void_p(reg_parent.data_ptr()), C.byref(make_grid(cgrid)),
+                               C.c_void_p(reg_child.data_ptr()), _stream())
+    _check(rc, "grhd_fmr_reflux")
+
+
+class Hierarchy:
+    """A grhd_fmr driver over levels given as dicts (grid, metric, q); the
+    stage buffers, recovery workspace, slices and registers are allocated
+    here as device tensors and handed to the library."""
+
+    def __init__(self, levels, eos, opts, l_fix=0, t0=0.0):
+        lib()
+        n = len(levels)
+        self.levels = levels
+        self.bufs = []
+        arr = (Level * n)()
+        for l, d in enumerate(levels):
+            q = d["q"]
+            shp = q.shape[1:]
+            b = dict(q1=torch.zeros_like(q), q2=torch.zeros_like(q),
+                     p=torch.zeros((6,) + shp, dtype=torch.float64, device=q.device))
+            b["slices"] = [torch.zeros((6,) + shp, dtype=torch.float64, device=q.device)
+                           for _ in range(3 if l + 1 < n else 0)]
+            g = d["grid"]
+            b["reg_child_bnd"] = (torch.zeros(5 * (g["nx"] + g["nz"]), dtype=torch.float64, device=q.device)
+                                  if l > 0 else None)
+            if l + 1 < n:
+                cg = levels[l + 1]["grid"]
+                b["reg_parent_int"] = torch.zeros(5 * (cg["nx"] // 2 + cg["nz"] // 2), dtype=torch.float64,
+                                                  device=q.device)
+            else:
+                b["reg_parent_int"] = None
+            L = arr[l]
+            L.grid = make_grid(g)
+            L.metric = make_metric(d["metric"])
+            L.q = make_cons(q)
+            L.q1 = make_cons(b["q1"])
+            L.q2 = make_cons(b["q2"])
+            L.p = make_prim(b["p"])
+            for s_, t_ in enumerate(b["slices"]):
+                L.slice[s_] = make_prim(t_)
+            L.reg_child_bnd = b["reg_child_bnd"].data_ptr() if b["reg_child_bnd"] is not None else None
+            L.reg_parent_int = b["reg_parent_int"].data_ptr() if b["reg_parent_int"] is not None else None
+            self.bufs.append(b)
+        self._arr = arr
+        self._opts = make_options(opts)
+        self._eos = make_eos(eos)
+        self.handle = C.c_void_p()
+        _check(lib().grhd_fmr_create(arr, n, C.byref(self._eos), C.byref(self._opts), int(l_fix), float(t0),
+                                     C.byref(self.handle), _stream()), "grhd_fmr_create")
+
+    def step(self, dt0):
+        _check(lib().grhd_fmr_step(self.handle, float(dt0), _stream()), "grhd_fmr_step")
+
+    @property
+    def time(self):
+        t = C.c_double()
+        _check(lib().grhd_fmr_time(self.handle, C.byref(t)), "grhd_fmr_time")
+        return t.value
+
+    def close(self):
+        if self.handle:
+            torch.cuda.synchronize()
+            lib().grhd_fmr_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass
 
