@@ -22,6 +22,10 @@ FP64 path.  The JSON line also carries:
                  refinement hierarchy (prolongation at every stage,
                  restriction, refluxing; l_fix = 0 and l_fix = 5), with the
                  composite baryon-mass change over the timed steps;
+  forms.bondi    Bondi accretion in the maximal trumpet slice (shift, lapse
+                 and extrinsic curvature all active) on [0, 16M]^2 to t = 20M
+                 at N = 64, 128, 256, PPM and minmod: zone-updates/s and
+                 the L1 density error of each, with the convergence orders;
   forms.learned  recovery of a 2048^2 differentially rotating field, Illinois
                  from the bracket against Newton seeded by the matrix-core MLP
                  (trained here on GPU), same root;
@@ -52,7 +56,7 @@ BYTES_KERNEL = [144.0, 184.0, 184.0]
 # algorithmic bytes per zone-update of a whole substep (recovery included):
 # q_s and the metric read, q_out written, q^n read in stages 2 and 3
 BYTES_SUBSTEP = [96.0, 136.0, 136.0]
-ALL_FORMS = ("fp64", "fp64_chained", "mixed", "batched", "fmr", "learned")
+ALL_FORMS = ("fp64", "fp64_chained", "mixed", "batched", "fmr", "bondi", "learned")
 # measured HBM traffic of the fused kernel (rocprofv3 FETCH_SIZE/WRITE_SIZE,
 # calibrated with a plain copy) is kept with the hash of the sources it was
 # measured on; it is reported only while the sources still hash the same
@@ -101,6 +105,8 @@ def parse():
     ap.add_argument("--learned-n", type=int, default=2048)
     ap.add_argument("--train-pairs", type=int, default=1 << 20)
     ap.add_argument("--train-steps", type=int, default=10000)
+    ap.add_argument("--tile", default="", help="tile shape of the single-patch forms, e.g. 16x8 "
+                    "(default: the library's)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB three "
                          "times (calibrates HBM byte counters against a known size)")
@@ -155,6 +161,8 @@ def main():
 
         def __init__(self, prec, chained=True):
             opts = dict(recon="ppm", riemann="hllc", prec=prec, c2p=c2p)
+            if args.tile and not chained:
+                opts["tile"] = tuple(int(v) for v in args.tile.split("x"))
             self.chained = chained
             self.sub = grhd.Substep(grid, eos, metric, opts)
             self.q = make_state()
@@ -258,6 +266,9 @@ def main():
     if "fmr" in forms:
         out_forms["fmr"] = fmr_form(args, tov)
         print("fmr done", file=sys.stderr, flush=True)
+    if "bondi" in forms:
+        out_forms["bondi"] = bondi_form(args)
+        print("bondi done", file=sys.stderr, flush=True)
     if "learned" in forms:
         out_forms["learned"] = learned_form(args)
         print("learned done", file=sys.stderr, flush=True)
@@ -490,6 +501,59 @@ def fmr_form(args, tov):
                                    "gpu_ms_per_coarse_step": e0.elapsed_time(e1) / steps,
                                    "mass_rel_change": (M1 - M0) / M0}
         h.close()
+    return res
+
+
+def bondi_form(args):
+    """Bondi flow on the trumpet slice (general-metric path), held within
+    r < 0.4M, exact flow in the outer ghosts; SSP-RK3 to t = 20M."""
+    import torch
+
+    import synth
+    from paper_2502_03223_amd import grhd
+    dev = torch.device("cuda:0")
+    c2p = dict(w_max=100.0, rho_atm=1e-14)
+    res = {"workload": "Bondi accretion, maximal trumpet slice of Schwarzschild, Gamma 4/3, K = 1, "
+                       "r_c = 8M, [0, 16M]^2 cylindrical, fixed for r < 0.4M, PPM+HLLC, SSP-RK3 to t = 20M"}
+    errs = {}
+    for recon, n in [("ppm", 64), ("ppm", 128), ("ppm", 256), ("minmod", 64), ("minmod", 128), ("minmod", 256)]:
+        d = 16.0 / n
+        g = synth.make_grid(n, n, 0.0, 0.0, d, d, "cyl", ("axis", "external", "reflect", "external"))
+        p, m, eos, frozen = synth.bondi_problem(g)
+        md = {k: torch.from_numpy(v).to(dev) for k, v in m.items()}
+        sub = grhd.Substep(g, eos, md, dict(recon=recon, riemann="hllc", prec="fp64", c2p=c2p))
+        pd = torch.from_numpy(p).to(dev)
+        q = torch.zeros((5,) + p.shape[1:], dtype=torch.float64, device=dev)
+        grhd.prim2con(g, eos, md, pd, q, with_ghosts=True)
+        qfix, q1, q2 = q.clone(), q.clone(), q.clone()
+        mask = torch.from_numpy(frozen.astype(np.uint8)).to(dev)
+        pw = torch.zeros_like(pd)
+        dt = 0.4 * d
+        nsteps = int(round(20.0 / dt))
+        calls = [sub.bind(dict(grhd.SSPRK3[s], dt=dt), qn, qs, qo, pw)
+                 for s, (qn, qs, qo) in enumerate([(q, q, q1), (q, q1, q2), (q, q2, q)])]
+        outs = [q1, q2, q]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            for c, qo in zip(calls, outs):
+                c()
+                grhd.fix_cells(g, mask, qfix, qo)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        grhd.con2prim(g, eos, md, c2p, q.clone(), pw)
+        rho = synth.interior(g, pw.cpu().numpy()[0])
+        rho0 = synth.interior(g, p[0])
+        X, _ = synth.cell_coords(g)
+        x = synth.interior(g, X)
+        sg = synth.interior(g, m["alp"] * m["W"] ** -3) * x
+        errs[(recon, n)] = float((np.abs(rho - rho0) * sg).sum() / (np.abs(rho0) * sg).sum())
+        res["%s_N%d" % (recon, n)] = {"value": 3 * n * n * nsteps / wall, "unit": "zone-updates/s",
+                                      "steps": nsteps, "ms_per_step": wall * 1e3 / nsteps,
+                                      "l1_rho": errs[(recon, n)]}
+    for recon in ("ppm", "minmod"):
+        res["%s_order_64_128" % recon] = math.log2(errs[(recon, 64)] / errs[(recon, 128)])
+        res["%s_order_128_256" % recon] = math.log2(errs[(recon, 128)] / errs[(recon, 256)])
     return res
 
 

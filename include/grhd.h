@@ -261,6 +261,13 @@ int grhd_plan_destroy(grhd_plan *plan);
  * both arrays hold 2 ints. */
 int grhd_plan_tile(const grhd_plan *plan, int *tile_x, int *tile_z);
 
+/* Interior boundary condition (the inner region of the Bondi test of
+ * Sec. III.B.2 keeps its initial state): q = q_fixed on every interior
+ * cell whose mask byte (cell array, same layout as q) is nonzero. */
+int grhd_fix_cells(const grhd_grid *grid, const uint8_t *mask,
+                   const grhd_cons *q_fixed, const grhd_cons *q,
+                   void *hip_stream);
+
 /* ------------------------------------------------------- mesh refinement */
 
 /* Fixed mesh refinement, Sec. II.A and II.E.  Levels are the nested,
@@ -324,7 +331,8 @@ int grhd_fmr_reflux(const grhd_grid *parent, const grhd_cons *q_parent,
  * steps its parent is restricted, refluxed and recovered.  create: copies
  * the level descriptors (device buffers stay the caller's), recovers every
  * level with a child into its first slice.  step: one step dt0 of level 0
- * (all finer levels follow).  Single path kernels on the 16 x 16 tiles. */
+ * (all finer levels follow).  Single path kernels on 16 x 16 tiles (16 x 8
+ * on grids of fewer than 1536 tiles of 16 x 16). */
 int grhd_fmr_create(const grhd_level *levels, int nlev, const grhd_eos *eos,
                     const grhd_options *opts, int l_fix, double t0,
                     grhd_fmr **out, void *hip_stream);

@@ -33,42 +33,40 @@ int launch_substep(const PatchK &pk, const EosK &e, int prec, int mc, int shape,
 int shape_index(int tx, int tz);
 void shape_of(int s, int *tx, int *tz);
 
-// parent primitive slices, oldest first
+// parent primitive slices, oldest first, with the interpolation weights
+// at the target time (computed on the host)
 struct SliceK {
   const double *p[3][6];
-  double t[3];
   int ns;
+  double wl;          // linear weight of the newest slice, (t - t_cur) / (t_new - t_cur)
+  double l[3];        // quadratic Lagrange weights of the three slices
 };
 
-// Time interpolation of one value from ns slices at time t: the current
-// slice (1), linear (2), or the quadratic Lagrange polynomial through
-// three slices, replaced by the linear one through the last two where the
+// Time interpolation of one value (slices oldest first): the current slice
+// (1 slice), linear between the last two (2 slices), or the quadratic
+// Lagrange polynomial through three, replaced by the linear one where the
 // slices are not monotone.
-__device__ __forceinline__ double slice_interp(const SliceK &S, const double *a, double t) {
+__device__ __forceinline__ double slice_interp(const SliceK &S, const double *a) {
 #pragma clang fp contract(off)
   if (S.ns == 1) return a[0];
   const int c = S.ns - 2, n = S.ns - 1;  // current, newest
-  const double lin = a[c] + (a[n] - a[c]) * ((t - S.t[c]) / (S.t[n] - S.t[c]));
+  const double lin = a[c] + (a[n] - a[c]) * S.wl;
   if (S.ns == 2) return lin;
   if ((a[2] - a[1]) * (a[1] - a[0]) < 0.0) return lin;
-  const double t0 = S.t[0], t1 = S.t[1], t2 = S.t[2];
-  const double l0 = (t - t1) * (t - t2) / ((t0 - t1) * (t0 - t2));
-  const double l1 = (t - t0) * (t - t2) / ((t1 - t0) * (t1 - t2));
-  const double l2 = (t - t0) * (t - t1) / ((t2 - t0) * (t2 - t1));
-  return l0 * a[0] + l1 * a[1] + l2 * a[2];
+  return S.l[0] * a[0] + S.l[1] * a[1] + S.l[2] * a[2];
 }
 
-// the parent's primitive field f at cell (j, k), time t, with the parent's
-// boundary conditions (index map and velocity parities)
-__device__ __forceinline__ double parent_prim(const GridK &pg, const SliceK &S, int f, int j, int k,
-                                              double t) {
+// the parent's primitive field f at cell (j, k), with the parent's boundary
+// conditions (index map and velocity parities)
+__device__ __forceinline__ double parent_prim(const GridK &pg, const SliceK &S, int f, int j, int k) {
   int js, ks;
   double sg[3];
   ghost_map(pg, j, k, js, ks, sg);
   const long long i = cell_index(pg, js, ks);
   double a[3];
-  for (int s = 0; s < S.ns; s++) a[s] = S.p[s][f][i];
-  double v = slice_interp(S, a, t);
+#pragma unroll
+  for (int s = 0; s < 3; s++) a[s] = (s < S.ns) ? S.p[s][f][i] : 0.0;
+  double v = slice_interp(S, a);
   if (f >= 1 && f <= 3) v *= sg[f - 1];
   return v;
 }
@@ -86,15 +84,10 @@ __host__ __device__ inline long long prolong_count(const GridK &cg) {
   return n;
 }
 
-template <int MC>
-__global__ void __launch_bounds__(256)
-k_fmr_prolong(GridK pg, SliceK S, double t, GridK cg, MetK cm, EosK e, P6 cp, Q5 cq) {
-#pragma clang fp contract(off)
-  long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  // locate the cell: sides in order x-low, x-high, z-low, z-high
-  int jf = 0, kf = 0;
-  bool found = false;
-  for (int s = 0; s < 4 && !found; s++) {
+// child ghost cell number id of the cross-shaped EXTERNAL halo (sides in
+// order x-low, x-high, z-low, z-high); false past the last one
+__device__ __forceinline__ bool ghost_cell(const GridK &cg, long long id, int &jf, int &kf) {
+  for (int s = 0; s < 4; s++) {
     if (cg.bc[s] != GRHD_BC_EXTERNAL) continue;
     const long long len = (s < 2) ? cg.nz : cg.nx;
     const long long n = (long long)cg.ng * len;
@@ -104,37 +97,55 @@ k_fmr_prolong(GridK pg, SliceK S, double t, GridK cg, MetK cm, EosK e, P6 cp, Q5
       else if (s == 1) { jf = cg.nx + m; kf = r; }
       else if (s == 2) { jf = r; kf = -1 - m; }
       else { jf = r; kf = cg.nz + m; }
-      found = true;
-    } else {
-      id -= n;
+      return true;
     }
+    id -= n;
   }
-  if (!found) return;
-  const int jc = (jf >= 0) ? jf / 2 : -((1 - jf) / 2);
-  const int kc = (kf >= 0) ? kf / 2 : -((1 - kf) / 2);
-  const double ox = (cg.x0 + (jf + 0.5) * cg.dx) - (pg.x0 + (jc + 0.5) * pg.dx);
-  const double oz = (cg.z0 + (kf + 0.5) * cg.dz) - (pg.z0 + (kc + 0.5) * pg.dz);
-  double pf[6];
-  for (int f = 0; f < 6; f++) {
-    const double a = parent_prim(pg, S, f, jc, kc, t);
-    const double xp = parent_prim(pg, S, f, jc + 1, kc, t), xm = parent_prim(pg, S, f, jc - 1, kc, t);
-    const double zp = parent_prim(pg, S, f, jc, kc + 1, t), zm = parent_prim(pg, S, f, jc, kc - 1, t);
+  return false;
+}
+
+// One workgroup: 32 ghost cells x 6 fields, one (field, cell) per thread;
+// the prolonged primitives meet in LDS for the conserved variables.
+constexpr int PRO_CELLS = 32;
+
+template <int MC>
+__global__ void __launch_bounds__(PRO_CELLS * 6)
+k_fmr_prolong(GridK pg, SliceK S, GridK cg, MetK cm, EosK e, P6 cp, Q5 cq) {
+#pragma clang fp contract(off)
+  __shared__ double spf[6][PRO_CELLS];
+  const int f = threadIdx.x / PRO_CELLS, cl = threadIdx.x % PRO_CELLS;
+  int jf = 0, kf = 0;
+  const bool act = ghost_cell(cg, (long long)blockIdx.x * PRO_CELLS + cl, jf, kf);
+  if (act) {
+    const int jc = (jf >= 0) ? jf / 2 : -((1 - jf) / 2);
+    const int kc = (kf >= 0) ? kf / 2 : -((1 - kf) / 2);
+    const double ox = (cg.x0 + (jf + 0.5) * cg.dx) - (pg.x0 + (jc + 0.5) * pg.dx);
+    const double oz = (cg.z0 + (kf + 0.5) * cg.dz) - (pg.z0 + (kc + 0.5) * pg.dz);
+    const double a = parent_prim(pg, S, f, jc, kc);
+    const double xp = parent_prim(pg, S, f, jc + 1, kc), xm = parent_prim(pg, S, f, jc - 1, kc);
+    const double zp = parent_prim(pg, S, f, jc, kc + 1), zm = parent_prim(pg, S, f, jc, kc - 1);
     const double sx = minmod2(xp - a, a - xm) / pg.dx;
     const double sz = minmod2(zp - a, a - zm) / pg.dz;
-    pf[f] = a + sx * ox + sz * oz;
+    const double v = a + sx * ox + sz * oz;
+    spf[f][cl] = v;
+    cp.p[f][cell_index(cg, jf, kf)] = v;
   }
-  const long long i = cell_index(cg, jf, kf);
-  const double W = mval(cm, GRHD_M_W, i);
-  double gtu[6];
-  if (MC == MC_GEN) {
-    double gt[6];
-    for (int s = 0; s < 6; s++) gt[s] = mval(cm, GRHD_M_GXX + s, i);
-    inv_sym3(gt, gtu);
+  __syncthreads();
+  if (f == 0 && act) {
+    const long long i = cell_index(cg, jf, kf);
+    double pf[6];
+    for (int c = 0; c < 6; c++) pf[c] = spf[c][cl];
+    const double W = mval(cm, GRHD_M_W, i);
+    double gtu[6];
+    if (MC == MC_GEN) {
+      double gt[6];
+      for (int s = 0; s < 6; s++) gt[s] = mval(cm, GRHD_M_GXX + s, i);
+      inv_sym3(gt, gtu);
+    }
+    double q[5];
+    prim2con_cell<MC>(W, gtu, cg.x0 + (jf + 0.5) * cg.dx, cg.geom, pf, q);
+    for (int c = 0; c < 5; c++) cq.q[c][i] = q[c];
   }
-  double q[5];
-  prim2con_cell<MC>(W, gtu, cg.x0 + (jf + 0.5) * cg.dx, cg.geom, pf, q);
-  for (int f = 0; f < 6; f++) cp.p[f][i] = pf[f];
-  for (int c = 0; c < 5; c++) cq.q[c][i] = q[c];
 }
 
 __device__ __forceinline__ double cell_volume(const GridK &g, int j) {
@@ -220,17 +231,33 @@ static int check_pair(const grhd_grid *pg, const grhd_grid *cg) {
   return GRHD_OK;
 }
 
-static SliceK make_slices(const grhd_prim *slices, int ns, const double *times) {
+// the time-interpolation weights at t for slice times ts[0..ns) (oldest
+// first): linear between the last two, quadratic Lagrange through three
+static void slice_weights(SliceK &S, const double *ts, double t) {
+  S.wl = 0.0;
+  S.l[0] = S.l[1] = S.l[2] = 0.0;
+  if (S.ns >= 2) {
+    const double tc = ts[S.ns - 2], tn = ts[S.ns - 1];
+    S.wl = (t - tc) / (tn - tc);
+  }
+  if (S.ns == 3) {
+    const double t0 = ts[0], t1 = ts[1], t2 = ts[2];
+    S.l[0] = (t - t1) * (t - t2) / ((t0 - t1) * (t0 - t2));
+    S.l[1] = (t - t0) * (t - t2) / ((t1 - t0) * (t1 - t2));
+    S.l[2] = (t - t0) * (t - t1) / ((t2 - t0) * (t2 - t1));
+  }
+}
+
+static SliceK make_slices(const grhd_prim *slices, int ns, const double *times, double t) {
   SliceK S{};
   S.ns = ns;
-  for (int s = 0; s < ns; s++) {
+  for (int s = 0; s < ns; s++)
     for (int f = 0; f < 6; f++) S.p[s][f] = slices[s].p[f];
-    S.t[s] = times[s];
-  }
+  slice_weights(S, times, t);
   return S;
 }
 
-static int prolong(const grhd_grid *pg, const SliceK &S, double t, const grhd_grid *cg,
+static int prolong(const grhd_grid *pg, const SliceK &S, const grhd_grid *cg,
                    const grhd_metric *cm, const grhd_eos *eos, double rho_atm, const grhd_prim *pc,
                    const grhd_cons *qc, hipStream_t st) {
   GridK P = to_gridk(pg), Cg = to_gridk(cg);
@@ -241,11 +268,11 @@ static int prolong(const grhd_grid *pg, const SliceK &S, double t, const grhd_gr
   for (int f = 0; f < 6; f++) pp.p[f] = pc->p[f];
   for (int c = 0; c < 5; c++) qq.q[c] = qc->q[c];
   EosK e = to_eosk(eos, rho_atm);
-  dim3 grid((unsigned)((n + 255) / 256));
+  dim3 grid((unsigned)((n + PRO_CELLS - 1) / PRO_CELLS)), block(PRO_CELLS * 6);
   if (metric_class(cm) == MC_GEN)
-    hipLaunchKernelGGL(k_fmr_prolong<MC_GEN>, grid, dim3(256), 0, st, P, S, t, Cg, to_metk(cm), e, pp, qq);
+    hipLaunchKernelGGL(k_fmr_prolong<MC_GEN>, grid, block, 0, st, P, S, Cg, to_metk(cm), e, pp, qq);
   else
-    hipLaunchKernelGGL(k_fmr_prolong<MC_CF>, grid, dim3(256), 0, st, P, S, t, Cg, to_metk(cm), e, pp, qq);
+    hipLaunchKernelGGL(k_fmr_prolong<MC_CF>, grid, block, 0, st, P, S, Cg, to_metk(cm), e, pp, qq);
   return launch_status("fmr prolong");
 }
 
@@ -293,7 +320,7 @@ extern "C" int grhd_fmr_prolong(const grhd_grid *parent, const grhd_prim *slices
   for (int s = 0; s + 1 < nslice; s++)
     if (!(times[s + 1] > times[s])) return fail(GRHD_ERR_INVALID, "slice times must increase");
   if (!(rho_atm > 0.0)) return fail(GRHD_ERR_INVALID, "rho_atm must be > 0");
-  return prolong(parent, make_slices(slices, nslice, times), t, child, child_metric, eos, rho_atm, p_child,
+  return prolong(parent, make_slices(slices, nslice, times, t), child, child_metric, eos, rho_atm, p_child,
                  q_child, (hipStream_t)hip_stream);
 }
 
@@ -378,12 +405,10 @@ int step_level(grhd_fmr *h, int l, double t, double dt, hipStream_t st) {
       const grhd_level &Pl = h->lev[l - 1];
       SliceK S{};
       S.ns = h->ns[l - 1];
-      for (int i = 0; i < S.ns; i++) {
+      for (int i = 0; i < S.ns; i++)
         for (int f = 0; f < 6; f++) S.p[i][f] = Pl.slice[h->order[l - 1][i]].p[f];
-        S.t[i] = h->ts[l - 1][i];
-      }
-      if ((rc = prolong(&Pl.grid, S, t + kT[s] * dt, &L.grid, &L.metric, &h->eos, h->opts.c2p.rho_atm, &L.p,
-                        qs_of[s], st)))
+      slice_weights(S, h->ts[l - 1].data(), t + kT[s] * dt);
+      if ((rc = prolong(&Pl.grid, S, &L.grid, &L.metric, &h->eos, h->opts.c2p.rho_atm, &L.p, qs_of[s], st)))
         return rc;
     }
     grhd_rk_stage stg{};
@@ -395,8 +420,13 @@ int step_level(grhd_fmr *h, int l, double t, double dt, hipStream_t st) {
     if (has_parent) { pk.reg[0] = L.reg_child_bnd; pk.reg_j[0] = L.grid.nx; pk.reg_k[0] = L.grid.nz; }
     if (has_child) { pk.reg[1] = L.reg_parent_int; pk.reg_j[1] = cg->nx / 2; pk.reg_k[1] = cg->nz / 2; }
     pk.reg_w = kW[s];
+    // grids of few 16 x 16 tiles (under two per workgroup slot of the
+    // chip) take 16 x 8 tiles: twice the workgroups, half the latency of
+    // the slowest (star) tile
+    const int shape = ((long long)((L.grid.nx + 15) / 16) * ((L.grid.nz + 15) / 16) < 1536)
+                          ? shape_index(16, 8) : h->shape;
     int tx, tz;
-    shape_of(h->shape, &tx, &tz);
+    shape_of(shape, &tx, &tz);
     pk.xshift = tile_xshift(L.grid.ng, tx);
     pk.tiles_x = (L.grid.nx + pk.xshift + tx - 1) / tx;
     pk.tiles_z = (L.grid.nz + tz - 1) / tz;
@@ -405,7 +435,7 @@ int step_level(grhd_fmr *h, int l, double t, double dt, hipStream_t st) {
     for (int c = 0; c < 5; c++) q.q[c] = qs_of[s]->q[c];
     for (int f = 0; f < 6; f++) p.p[f] = L.p.p[f];
     if ((rc = launch_con2prim(pk.g, e, to_c2pk(&h->opts.c2p), pk.m, mc, q, p, nullptr, nullptr, st))) return rc;
-    if ((rc = launch_substep(pk, e, h->opts.prec, mc, h->shape, nullptr, st))) return rc;
+    if ((rc = launch_substep(pk, e, h->opts.prec, mc, shape, nullptr, st))) return rc;
   }
   if (!has_child) return GRHD_OK;
   if ((rc = push_slice(h, l, t + dt, st))) return rc;

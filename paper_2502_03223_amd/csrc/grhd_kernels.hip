@@ -228,12 +228,12 @@ k_flux(GridK g, EosK e, MetK m, int dir, int riemann, Ptr6<T> Lp, Ptr6<T> Rp, Q5
 // kernel folds the records afterwards.  (Handing tiles out through a global
 // counter costs two same-address atomics per workgroup, which serialise
 // across the XCDs and cost more than the imbalance they remove.)
-// Waves per SIMD the register allocation must allow: the FP64 16 x 16
-// instance of the conformally flat class fits three workgroups per CU in
-// LDS, so its registers are held to three waves as well.
+// Waves per SIMD the register allocation must allow: the FP64 16 x 16 and
+// 16 x 8 instances of the conformally flat class fit at least three
+// workgroups per CU in LDS, so their registers are held to three waves.
 template <class T, int MC, int TX, int TZ>
 constexpr int substep_waves() {
-  return (sizeof(T) == 8 && MC == MC_CF && TX == 16 && TZ == 16) ? 3 : 1;
+  return (sizeof(T) == 8 && MC == MC_CF && TX == 16 && (TZ == 16 || TZ == 8)) ? 3 : 1;
 }
 
 template <class T, int MC, int TX, int TZ>
@@ -276,8 +276,8 @@ k_substep_chain(PatchK P, EosK e, C2PPart *part1, FluxPart *part2) {
 using SubstepFn = void (*)(PatchK, EosK, FluxPart *);
 
 struct TileShape { int tx, tz; };
-static const TileShape kShapes[] = {{32, 8}, {32, 16}, {64, 8}, {16, 16}};
-constexpr int kNumShapes = 4;
+static const TileShape kShapes[] = {{32, 8}, {32, 16}, {64, 8}, {16, 16}, {16, 8}};
+constexpr int kNumShapes = 5;
 
 template <class T, int MC>
 static SubstepFn pick_shape(int s) {
@@ -285,6 +285,7 @@ static SubstepFn pick_shape(int s) {
     case 0: return k_substep<T, MC, 32, 8>;
     case 1: return k_substep<T, MC, 32, 16>;
     case 2: return k_substep<T, MC, 64, 8>;
+    case 4: return k_substep<T, MC, 16, 8>;
     default: return k_substep<T, MC, 16, 16>;
   }
 }
@@ -716,6 +717,31 @@ extern "C" int grhd_rk_substep_chained(const grhd_grid *grid, const grhd_eos *eo
     return fail(GRHD_ERR_DEVICE, "hipEventRecord failed");
   if (diag) return launch_diag_final(p1, nt, p2, nt, diag, st);
   return GRHD_OK;
+}
+
+namespace grhd {
+// q = q_fixed on the interior cells where mask is set
+__global__ void __launch_bounds__(256) k_fix_cells(GridK g, const uint8_t *mask, Q5 qf, Q5 q) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (long long)g.nx * g.nz) return;
+  const long long i = cell_index(g, (int)(id % g.nx), (int)(id / g.nx));
+  if (!mask[i]) return;
+  for (int c = 0; c < 5; c++) q.q[c][i] = qf.q[c][i];
+}
+}  // namespace grhd
+
+extern "C" int grhd_fix_cells(const grhd_grid *grid, const uint8_t *mask, const grhd_cons *q_fixed,
+                              const grhd_cons *q, void *hip_stream) {
+  int rc;
+  if ((rc = check_grid(grid)) || (rc = check_cons(q_fixed, "q_fixed")) || (rc = check_cons(q, "q")))
+    return rc;
+  if (!mask) return fail(GRHD_ERR_INVALID, "mask is NULL");
+  Q5 a, b;
+  for (int c = 0; c < 5; c++) { a.q[c] = q_fixed->q[c]; b.q[c] = q->q[c]; }
+  long long n = (long long)grid->nx * grid->nz;
+  hipLaunchKernelGGL(k_fix_cells, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)hip_stream,
+                     to_gridk(grid), mask, a, b);
+  return launch_status("fix cells");
 }
 
 extern "C" int grhd_event_create(void **ev) {

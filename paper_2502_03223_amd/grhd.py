@@ -117,6 +117,7 @@ def lib():
             "grhd_hllc_flux": [p, i, i, i, p, p, p, p, p, p, p],
             "grhd_rk_substep": [p, p, p, p, p, p, p, p, p, p, p, p, p, p, p],
             "grhd_rk_substep_chained": [p] * 17,
+            "grhd_fix_cells": [p, p, p, p, p],
             "grhd_fmr_prolong": [p, p, i, p, C.c_double, p, p, p, C.c_double, p, p, p],
             "grhd_fmr_restrict": [p, p, p, p, p],
             "grhd_fmr_reflux": [p, p, p, p, p, p],
@@ -499,6 +500,14 @@ class Event:
             lib().grhd_event_destroy(self.handle)
         except Exception:
             pass
+
+
+def fix_cells(grid, mask, q_fixed, q):
+    """grhd_fix_cells: q = q_fixed where mask (uint8 cell tensor) is set."""
+    assert mask.is_cuda and mask.dtype == torch.uint8 and mask.is_contiguous()
+    rc = lib().grhd_fix_cells(C.byref(make_grid(grid)), C.c_void_p(mask.data_ptr()),
+                              C.byref(make_cons(q_fixed)), C.byref(make_cons(q)), _stream())
+    _check(rc, "grhd_fix_cells")
 
 
 # ------------------------------------------------------------ mesh refinement

@@ -285,6 +285,129 @@ def blast_state(grid, center, width, seed, gamma=5.0 / 3.0, vamp=0.05):
     return p
 
 
+def trumpet_r_of_R(R, M=1.0):
+    """Isotropic radius of the maximal trumpet slice of Schwarzschild as a
+    function of the areal radius R >= 3M/2 (closed form)."""
+    R = np.asarray(R, dtype=np.float64)
+    a = (2.0 * R + M + np.sqrt(4.0 * R * R + 4.0 * M * R + 3.0 * M * M)) / 4.0
+    b = ((4.0 + 3.0 * math.sqrt(2.0)) * (2.0 * R - 3.0 * M)
+         / (8.0 * R + 6.0 * M + 3.0 * np.sqrt(8.0 * R * R + 8.0 * M * R + 6.0 * M * M)))
+    return a * np.maximum(b, 0.0) ** (1.0 / math.sqrt(2.0))
+
+
+def trumpet_R_of_r(r, M=1.0):
+    """Areal radius at isotropic radius r (inverse of trumpet_r_of_R, by
+    bisection to the last bit; r(R) increases monotonically)."""
+    r = np.asarray(r, dtype=np.float64)
+    lo = np.full(r.shape, 1.5 * M)
+    hi = np.maximum(r, 0.0) + 2.0 * M + 1.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        up = trumpet_r_of_R(mid, M) < r
+        lo = np.where(up, mid, lo)
+        hi = np.where(up, hi, mid)
+    return 0.5 * (lo + hi)
+
+
+def trumpet_metric(grid, M=1.0):
+    """The maximal trumpet slice of a Schwarzschild black hole of mass M in
+    the cartoon plane y = 0: lapse, shift C x^i / R^3, W = r / R, flat
+    conformal metric, K = 0 and K_ij = W^-2 C / R^3 (delta_ij - 3 x^i x^j /
+    r^2), C = 3 sqrt(3) M^2 / 4 (every stored cell)."""
+    X, Z = cell_coords(grid)
+    r = np.sqrt(X * X + Z * Z)
+    R = trumpet_R_of_r(r, M)
+    C = 3.0 * math.sqrt(3.0) * M * M / 4.0
+    c = C / R ** 3
+    W = r / R
+    iW2 = 1.0 / (W * W)
+    out = dict(alp=np.sqrt(1.0 - 2.0 * M / R + C * C / R ** 4), bx=c * X, bz=c * Z, W=W,
+               kxx=iW2 * c * (1.0 - 3.0 * X * X / (r * r)), kxz=iW2 * c * (-3.0 * X * Z / (r * r)),
+               kyy=iW2 * c, kzz=iW2 * c * (1.0 - 3.0 * Z * Z / (r * r)))
+    return {k: np.ascontiguousarray(v) for k, v in out.items()}
+
+
+def bondi_profile(R, M=1.0, K=1.0, G=4.0 / 3.0, Rc=8.0):
+    """Transonic Bondi (Michel) accretion in Schwarzschild areal radius:
+    (rho, |u^R|) at R for the polytrope P = K rho^G with the sonic point at
+    Rc.  The flux 4 pi R^2 rho |u^R| and the Bernoulli constant
+    h^2 (1 - 2M/R + u^2) are those of the sonic point; subsonic branch
+    outside Rc, supersonic inside.  Returns (rho, u, mdot)."""
+    R = np.asarray(R, dtype=np.float64)
+    uc2 = M / (2.0 * Rc)
+    cs2c = uc2 / (1.0 - 3.0 * uc2)
+
+    def hK(rho):
+        return 1.0 + G / (G - 1.0) * K * rho ** (G - 1.0)
+    # sonic density: cs2 = G K rho^(G-1) / h solved for rho in closed form
+    x = cs2c / (G - cs2c * G / (G - 1.0))          # K rho^(G-1)
+    rhoc = (x / K) ** (1.0 / (G - 1.0))
+    uc = math.sqrt(uc2)
+    mdot = 4.0 * math.pi * Rc * Rc * rhoc * uc
+    B = hK(rhoc) ** 2 * (1.0 - 2.0 * M / Rc + uc2)
+
+    def f(u, RR):
+        rho = mdot / (4.0 * math.pi * RR * RR * u)
+        return hK(rho) ** 2 * (1.0 - 2.0 * M / RR + u * u) - B
+    # f is convex in log u with its minimum at the sonic speed of the
+    # radius: bisection on each branch, vectorised over R
+    lo_s, hi_s = np.full(R.shape, 1e-12), np.full(R.shape, 1.0)
+    # the minimum of f over u (golden section in log u)
+    a, b = np.log(lo_s), np.log(hi_s * 0.9999999)
+    g = (math.sqrt(5.0) - 1.0) / 2.0
+    for _ in range(200):
+        c1 = b - g * (b - a)
+        c2 = a + g * (b - a)
+        left = f(np.exp(c1), R) < f(np.exp(c2), R)
+        b = np.where(left, c2, b)
+        a = np.where(left, a, c1)
+    umin = np.exp(0.5 * (a + b))
+    sub = R > Rc
+    lo = np.where(sub, 1e-14, umin)
+    hi = np.where(sub, umin, 0.9999999999)
+    flo = f(lo, R)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        fm = f(mid, R)
+        same = np.sign(fm) == np.sign(flo)
+        lo = np.where(same, mid, lo)
+        flo = np.where(same, fm, flo)
+        hi = np.where(same, hi, mid)
+    u = 0.5 * (lo + hi)
+    u = np.where(np.abs(R - Rc) < 1e-12, uc, u)
+    rho = mdot / (4.0 * math.pi * R * R * u)
+    return rho, u, mdot
+
+
+def bondi_problem(grid, M=1.0, r_in=0.4):
+    """(prims, metric, eos, frozen) for the Bondi flow in the maximal trumpet
+    slice (every stored cell, so EXTERNAL ghosts carry the solution):
+    rho, P = rho^(4/3), eps, and the covariant spatial four-velocity of the
+    infalling flow on the trumpet slice; frozen marks the cells with
+    r < r_in, which keep their initial state."""
+    G, K = 4.0 / 3.0, 1.0
+    metric = trumpet_metric(grid, M)
+    X, Z = cell_coords(grid)
+    r = np.sqrt(X * X + Z * Z)
+    R = trumpet_R_of_r(r, M)
+    rho, u, _ = bondi_profile(R, M, K, G, 8.0)
+    C = 3.0 * math.sqrt(3.0) * M * M / 4.0
+    alp = metric["alp"]
+    s = np.sqrt(1.0 - 2.0 * M / R + u * u)
+    a = C / (R * R * alp)
+    # covariant radial component on the trumpet slice (T = t_S + h(R),
+    # h' = C / (R^2 (1 - 2M/R) alpha)), written without the horizon's 0/0
+    uR = (C * C / R ** 4 - u * u) / (alp * alp * (s * a + u))
+    ur = uR * alp * R / r          # dR/dr = alpha R / r
+    p = empty_fields(grid, 6)
+    p[0] = rho
+    p[1] = ur * X / r
+    p[3] = ur * Z / r
+    p[4] = K * rho ** G
+    p[5] = p[4] / ((G - 1.0) * rho)
+    return p, metric, ideal_eos(G, K=K), np.ascontiguousarray(r < r_in)
+
+
 def riemann_patch_sizes(seed, npatch=64, lo=128, hi=2048):
     rng = np.random.default_rng(seed)
     return [int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))

@@ -1,0 +1,75 @@
+"""Pins of the Bondi-in-trumpet workload (paper Sec. III.A.1 trumpet black
+hole, Sec. III.B.2 Bondi accretion) and of the oracle's general-metric
+substep on it.
+
+- the trumpet slice: r = 0 at the areal radius 3M/2 and the horizon at
+  r ~ 0.78M, as the paper states; K_ij is trace-free (maximal slicing);
+  the radial map satisfies dR/dr = alpha R / r (conformal flatness of the
+  maximal slice, checked by finite differences of the numerical inverse);
+- the Bondi flow: the accretion rate 0.0848 of the paper for r_c = 8M,
+  K = 1, Gamma = 4/3;
+- the oracle's right-hand side L(q) of the stationary flow (shift,
+  curvature, lapse all non-trivial) falls by at least 2.5x per doubling of
+  the resolution: a dropped curvature term or a flipped shift stalls it
+  (checked while writing this pin: ratio 1.0).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+def test_trumpet_paper_values():
+    t = GOLD["trumpet"]
+    assert synth.trumpet_r_of_R(t["R_at_r0"]) == 0.0
+    assert round(float(synth.trumpet_r_of_R(2.0)), t["digits"]) == t["r_horizon"]
+
+
+def test_trumpet_metric_identities():
+    g = synth.make_grid(24, 24, 0.0, 0.0, 0.25, 0.25, "cyl", ("axis", "external", "reflect", "external"))
+    m = synth.trumpet_metric(g)
+    # maximal slicing: gamma^ij K_ij = W^2 (K_xx + K_yy + K_zz) = 0
+    tr = m["W"] ** 2 * (m["kxx"] + m["kyy"] + m["kzz"])
+    assert np.abs(tr).max() <= 1e-13 * np.abs(m["kyy"] * m["W"] ** 2).max()
+    # dR/dr = alpha R / r along a ray (central differences of the inverse)
+    r = np.linspace(1.0, 10.0, 50)
+    h = 1e-5
+    dRdr = (synth.trumpet_R_of_r(r + h) - synth.trumpet_R_of_r(r - h)) / (2 * h)
+    R = synth.trumpet_R_of_r(r)
+    alp = np.sqrt(1.0 - 2.0 / R + 27.0 / (16.0 * R ** 4))
+    assert np.allclose(dRdr, alp * R / r, rtol=1e-8)
+    # the lapse vanishes at the puncture
+    assert math.sqrt(1.0 - 2.0 / 1.5 + 27.0 / (16.0 * 1.5 ** 4)) == pytest.approx(0.0, abs=1e-7)
+
+
+def test_bondi_accretion_rate():
+    b = GOLD["bondi"]
+    _, u, mdot = synth.bondi_profile(np.array([b["r_c"], 4.0, 12.0]), K=b["K"], G=b["Gamma"], Rc=b["r_c"])
+    assert round(mdot, b["mdot_digits"] + 1) == pytest.approx(b["mdot"], abs=0.5 * 10 ** -(b["mdot_digits"] + 1))
+    assert u[0] == pytest.approx(math.sqrt(1.0 / (2.0 * b["r_c"])), rel=1e-12)
+
+
+@pytest.mark.parametrize("riemann", ["hllc", "tvdlf"])
+def test_bondi_residual_converges(orc, riemann):
+    opts = dict(recon="ppm", riemann=riemann, c2p=dict(w_max=100.0, rho_atm=1e-14))
+    errs = []
+    for n in (32, 64, 128):
+        d = 16.0 / n
+        g = synth.make_grid(n, n, 0.0, 0.0, d, d, "cyl", ("axis", "external", "reflect", "external"))
+        p, m, eos, _ = synth.bondi_problem(g)
+        q = orc.prim2con(g, eos, m, p, with_ghosts=True)
+        r = orc.rk_substep(g, eos, m, opts, dict(a=0.0, b=0.0, c=1.0, dt=1.0), q, q)
+        L, qi = synth.interior(g, r["qout"]), synth.interior(g, q)
+        X, Z = synth.cell_coords(g)
+        rr = synth.interior(g, np.sqrt(X * X + Z * Z))
+        x = synth.interior(g, X)
+        sel = (rr > 1.0) & (rr < 12.0)
+        errs.append(max(np.abs(L[c][sel] * x[sel]).sum() / np.abs(qi[c][sel] * x[sel]).sum()
+                        for c in (0, 1, 3, 4)))
+    assert errs[0] / errs[1] >= 2.5 and errs[1] / errs[2] >= 2.5, errs
