@@ -107,6 +107,11 @@ typedef struct {
   int guess;              /* GRHD_GUESS_* */
   const void *mlp;        /* device weights for GRHD_GUESS_MLP (layout in
                              grhd_mlp_forward) */
+  int adiabatic;          /* nonzero: the zero-temperature mode of
+                             Sec. III.C.2 -- the energy equation is
+                             discarded: every cell takes the cold root from
+                             (D, S_i), its E is reset from the cold state
+                             and it carries GRHD_FLAG_COLD */
 } grhd_c2p_params;
 
 typedef struct {

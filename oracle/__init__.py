@@ -67,7 +67,7 @@ class Metric(C.Structure):
 
 
 class C2P(C.Structure):
-    _fields_ = [("w_max", C.c_double), ("rho_atm", C.c_double)]
+    _fields_ = [("w_max", C.c_double), ("rho_atm", C.c_double), ("adiabatic", C.c_int)]
 
 
 class Stage(C.Structure):
@@ -192,6 +192,7 @@ def metric_point(m):
 def make_c2p(c):
     s = C2P()
     s.w_max, s.rho_atm = c["w_max"], c["rho_atm"]
+    s.adiabatic = 1 if c.get("adiabatic") else 0
     return s
 
 

@@ -244,12 +244,14 @@ unsigned or_con2prim_point(const or_eos *e, const double *g, double x, int geom,
     }
     double zm = 0.5 * k / sqrt(1.0 - 0.25 * k * k);
     double zp = k / sqrt(1.0 - k * k);
-    z = (k > 0.0) ? bisect_root(e, D, qq, r, zm, zp, 0) : 0.0;
+    /* the adiabatic mode (Sec. III.C.2) never uses the energy: only the
+     * cold root below */
+    z = (k > 0.0 && !cp->adiabatic) ? bisect_root(e, D, qq, r, zm, zp, 0) : 0.0;
     double w = sqrt(1.0 + z * z);
     double rho = D / w;
     double eps = w * qq - z * r + z * z / (1.0 + w);
     double P, h;
-    if (eps < or_eos_eps_cold(e, rho)) {
+    if (cp->adiabatic || eps < or_eos_eps_cold(e, rho)) {
       /* zero-temperature recovery from (D, S_i) on [0, r] */
       z = (r > 0.0) ? bisect_root(e, D, qq, r, 0.0, r, 1) : 0.0;
       w = sqrt(1.0 + z * z);

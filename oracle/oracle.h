@@ -67,6 +67,8 @@ typedef struct {
 
 typedef struct {
   double w_max, rho_atm;
+  int adiabatic;           /* 1: zero temperature, the energy equation is
+                              discarded (the cold root from D and S) */
 } or_c2p;
 
 typedef struct {

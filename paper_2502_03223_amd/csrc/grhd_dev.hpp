@@ -40,6 +40,7 @@ struct C2PK {
   double kmax, tol;
   int max_iter, guess;
   const void *mlp;
+  int adiabatic;  // zero-temperature mode: the cold root only
 };
 
 enum MetricClass { MC_CF = 0, MC_GEN = 1 };  // conformally flat static / general
@@ -319,7 +320,9 @@ __device__ C2PResult con2prim_cell(const EosK &e, const C2PK &cp, double W, cons
     double zp = k / sqrt(1.0 - k * k);
     double zlo = (EK == GRHD_EOS_IDEAL) ? fmin(zm, r) : 0.0;
     if (D / sqrt(1.0 + zlo * zlo) < e.rho_atm) atm = true;
-    if (!atm && k > 0.0) {
+    // the adiabatic mode never solves the energy equation: the cold root
+    // below is its only root
+    if (!atm && k > 0.0 && !cp.adiabatic) {
       bool done = false;
       double za = zm, zb = zp;
       if (zguess >= 0.0) {
@@ -400,7 +403,7 @@ __device__ C2PResult con2prim_cell(const EosK &e, const C2PK &cp, double W, cons
     double rho = D / w;
     double eps = w * qq - z * r + z * z / (1.0 + w);
     double P;
-    if (eps < eps_cold_k<EK>(e, rho)) {
+    if (cp.adiabatic || eps < eps_cold_k<EK>(e, rho)) {
       if (EK == GRHD_EOS_IDEAL) {
         z = r;  // h_cold = 1: the zero-temperature root is z = r
       } else {

@@ -119,6 +119,7 @@ inline C2PK to_c2pk(const grhd_c2p_params *c) {
   k.max_iter = (c->max_iter > 0) ? c->max_iter : 100;
   k.guess = c->guess;
   k.mlp = c->mlp;
+  k.adiabatic = c->adiabatic ? 1 : 0;
   return k;
 }
 

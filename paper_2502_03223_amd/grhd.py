@@ -65,7 +65,8 @@ class Prim(C.Structure):
 
 class C2PParams(C.Structure):
     _fields_ = [("w_max", C.c_double), ("rho_atm", C.c_double), ("tol", C.c_double),
-                ("max_iter", C.c_int), ("guess", C.c_int), ("mlp", C.c_void_p)]
+                ("max_iter", C.c_int), ("guess", C.c_int), ("mlp", C.c_void_p),
+                ("adiabatic", C.c_int)]
 
 
 class Options(C.Structure):
@@ -229,6 +230,7 @@ def make_c2p(c):
     s.max_iter = c.get("max_iter", 0)
     s.guess = 1 if c.get("mlp") is not None else 0
     s.mlp = c["mlp"].data_ptr() if c.get("mlp") is not None else None
+    s.adiabatic = 1 if c.get("adiabatic") else 0
     return s
 
 

@@ -391,3 +391,52 @@ def test_mixed_single_substep_close(orc, tov):
     dq_g = I(out["qout"]) - I(q)
     for c in (0, 1, 3, 4):
         assert np.abs(dq_g[c] - dq_o[c]).max() <= 1e-5 * np.abs(dq_o[c]).max() + 1e-16 * np.abs(I(q)[c]).max()
+
+
+# ------------------------------------------------------------ zero temperature
+
+THREE_PIECE = dict(kind="hybrid", K=[8.95e-2, 8.95e-2 * 1.5e-4 ** (1.35692 - 3.005),
+                                     8.95e-2 * 1.5e-4 ** (1.35692 - 3.005) * 8.1e-4 ** (3.005 - 2.988)],
+                   G=[1.35692, 3.005, 2.988], rho_b=[1.5e-4, 8.1e-4], Gth=1.75)
+
+
+def test_con2prim_adiabatic_three_piece(orc):
+    """The adiabatic recovery (cold root from D, S; E reset) on a general
+    metric with a three-piece polytrope, hot and cold cells mixed."""
+    grid = synth.make_grid(45, 38, 0.0, 0.0, 0.02, 0.025, "cart", ("periodic",) * 4)
+    metric = synth.general_metric(grid, 13)
+    rng = np.random.default_rng(14)
+    p = synth.smooth_state(grid, 15, vamp=0.3)
+    p[0] = 10.0 ** rng.uniform(-5, -2.5, size=p[0].shape)
+    ec = np.array([orc.eos_eps_cold(THREE_PIECE, r) for r in p[0].ravel()]).reshape(p[0].shape)
+    p[5] = ec + np.where(rng.uniform(size=ec.shape) < 0.5, 0.0, 0.02)
+    p[4] = np.array([orc.eos_press(THREE_PIECE, r, e) for r, e in zip(p[0].ravel(), p[5].ravel())]).reshape(ec.shape)
+    q = orc.prim2con(grid, THREE_PIECE, metric, p, with_ghosts=True)
+    c2p = dict(w_max=100.0, rho_atm=1e-12, adiabatic=True)
+    p_o, q_o, fl_o, d_o = orc.con2prim(grid, THREE_PIECE, metric, c2p, q)
+    qg = dev(q)
+    pg = torch.zeros((6,) + q.shape[1:], dtype=torch.float64, device=DEV)
+    fl = torch.zeros(q.shape[1:], dtype=torch.uint8, device=DEV)
+    grhd.con2prim(grid, THREE_PIECE, mdev(metric), c2p, qg, pg, flags=fl)
+    torch.cuda.synchronize()
+    I = lambda a: synth.interior(grid, a)  # noqa: E731
+    assert np.array_equal(I(fl.cpu().numpy()), I(fl_o))
+    assert normwise(I(pg.cpu().numpy()), I(p_o)) <= TOL
+    assert normwise(I(qg.cpu().numpy()), I(q_o)) <= TOL
+
+
+def test_substep_star_adiabatic(orc, tov):
+    """The star with the zero-temperature law P = K rho^Gamma (one-piece
+    hybrid EOS, energy equation discarded), every stage."""
+    grid, p, metric, _ = star_case(64, 71, tov, vel=0.05)
+    eos = dict(kind="hybrid", K=[tov["K"]], G=[tov["G"]], rho_b=[], Gth=2.0)
+    q = orc.prim2con(grid, eos, metric, p, with_ghosts=True)
+    opts = dict(recon="ppm", riemann="hllc", prec="fp64", c2p=dict(C2P_STAR, adiabatic=True))
+    qn = q
+    for s in range(3):
+        st = dict(grhd.SSPRK3[s], dt=0.4 * grid["dx"])
+        ref, out = run_pair(orc, grid, eos, metric, opts, st, qn, q)
+        check_pair(grid, ref, out)
+        if s == 0:
+            qn = ref["qs"]
+        q = ref["qout"]
