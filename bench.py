@@ -26,6 +26,9 @@ FP64 path.  The JSON line also carries:
                  and extrinsic curvature all active) on [0, 16M]^2 to t = 20M
                  at N = 64, 128, 256, PPM and minmod: zone-updates/s and
                  the L1 density error of each, with the convergence orders;
+  forms.bondi_rt the hot bubble in the Bondi flow (N = 512, t = 25M), HLLC
+                 against TVDLF: total variation of the density (sharper
+                 fingers give more) and zone-updates/s;
   forms.learned  recovery of a 2048^2 differentially rotating field, Illinois
                  from the bracket against Newton seeded by the matrix-core MLP
                  (trained here on GPU), same root;
@@ -56,7 +59,7 @@ BYTES_KERNEL = [144.0, 184.0, 184.0]
 # algorithmic bytes per zone-update of a whole substep (recovery included):
 # q_s and the metric read, q_out written, q^n read in stages 2 and 3
 BYTES_SUBSTEP = [96.0, 136.0, 136.0]
-ALL_FORMS = ("fp64", "fp64_chained", "mixed", "batched", "fmr", "bondi", "learned")
+ALL_FORMS = ("fp64", "fp64_chained", "mixed", "batched", "fmr", "bondi", "bondi_rt", "learned")
 # measured HBM traffic of the fused kernel (rocprofv3 FETCH_SIZE/WRITE_SIZE,
 # calibrated with a plain copy) is kept with the hash of the sources it was
 # measured on; it is reported only while the sources still hash the same
@@ -269,6 +272,9 @@ def main():
     if "bondi" in forms:
         out_forms["bondi"] = bondi_form(args)
         print("bondi done", file=sys.stderr, flush=True)
+    if "bondi_rt" in forms:
+        out_forms["bondi_rt"] = bondi_rt_form(args)
+        print("bondi_rt done", file=sys.stderr, flush=True)
     if "learned" in forms:
         out_forms["learned"] = learned_form(args)
         print("learned done", file=sys.stderr, flush=True)
@@ -554,6 +560,68 @@ def bondi_form(args):
     for recon in ("ppm", "minmod"):
         res["%s_order_64_128" % recon] = math.log2(errs[(recon, 64)] / errs[(recon, 128)])
         res["%s_order_128_256" % recon] = math.log2(errs[(recon, 128)] / errs[(recon, 256)])
+    return res
+
+
+def density_tv(grid, rho):
+    """Area-weighted total variation of rho over the interior (cylindrical
+    faces: x-faces weighted by their x, z-faces by the cell x)."""
+    x = grid["x0"] + (np.arange(grid["nx"]) + 0.5) * grid["dx"]
+    xf = grid["x0"] + np.arange(1, grid["nx"]) * grid["dx"]
+    tvx = (np.abs(np.diff(rho, axis=1)) * xf[None, :]).sum() * grid["dz"]
+    tvz = (np.abs(np.diff(rho, axis=0)) * x[None, :]).sum() * grid["dx"]
+    return float(tvx + tvz)
+
+
+def run_bondi(grid, p, m, eos, frozen, opts, t_end):
+    """SSP-RK3 of a Bondi-type state with the inner region held; returns
+    (final primitives, zone-updates/s)."""
+    import torch
+
+    from paper_2502_03223_amd import grhd
+    dev = torch.device("cuda:0")
+    md = {k: torch.from_numpy(v).to(dev) for k, v in m.items()}
+    sub = grhd.Substep(grid, eos, md, opts)
+    pd = torch.from_numpy(p).to(dev)
+    q = torch.zeros((5,) + p.shape[1:], dtype=torch.float64, device=dev)
+    grhd.prim2con(grid, eos, md, pd, q, with_ghosts=True)
+    qfix, q1, q2 = q.clone(), q.clone(), q.clone()
+    mask = torch.from_numpy(frozen.astype(np.uint8)).to(dev)
+    pw = torch.zeros_like(pd)
+    dt = 0.4 * grid["dx"]
+    nsteps = int(round(t_end / dt))
+    calls = [sub.bind(dict(grhd.SSPRK3[s], dt=dt), qn, qs, qo, pw)
+             for s, (qn, qs, qo) in enumerate([(q, q, q1), (q, q1, q2), (q, q2, q)])]
+    outs = [q1, q2, q]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        for c, qo in zip(calls, outs):
+            c()
+            grhd.fix_cells(grid, mask, qfix, qo)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    grhd.con2prim(grid, eos, md, opts["c2p"], q.clone(), pw)
+    return pw.cpu().numpy(), 3 * grid["nx"] * grid["nz"] * nsteps / wall
+
+
+def bondi_rt_form(args):
+    """The paper's hot-bubble test on the Bondi flow: HLLC against TVDLF."""
+    import synth
+    n = 512
+    d = 16.0 / n
+    g = synth.make_grid(n, n, 0.0, 0.0, d, d, "cyl", ("axis", "external", "reflect", "external"))
+    p, m, eos, frozen = synth.modified_bondi_problem(g)
+    res = {"workload": "Bondi flow with a hot bubble (rho x 0.1, P x 50, u = 0 inside r < 3M [1 + 0.05 "
+                       "(cos 80 theta + 1)]), 512^2 on [0, 16M]^2, PPM, SSP-RK3 to t = 25M"}
+    tv0 = density_tv(g, synth.interior(g, p[0]))
+    for riemann in ("hllc", "tvdlf"):
+        opts = dict(recon="ppm", riemann=riemann, prec="fp64", c2p=dict(w_max=100.0, rho_atm=1e-14))
+        pf, rate = run_bondi(g, p, m, eos, frozen, opts, 25.0)
+        res[riemann] = {"value": rate, "unit": "zone-updates/s",
+                        "density_tv_over_initial": density_tv(g, synth.interior(g, pf[0])) / tv0}
+    res["tv_ratio_hllc_over_tvdlf"] = (res["hllc"]["density_tv_over_initial"]
+                                       / res["tvdlf"]["density_tv_over_initial"])
     return res
 
 

@@ -408,6 +408,24 @@ def bondi_problem(grid, M=1.0, r_in=0.4):
     return p, metric, ideal_eos(G, K=K), np.ascontiguousarray(r < r_in)
 
 
+def modified_bondi_problem(grid, M=1.0, r_in=0.4):
+    """The Bondi flow with a hot, light bubble (Sec. III.B.3): inside
+    r < 3M [1 + 0.05 (cos(80 theta) + 1)] (theta the polar angle from the
+    z axis) rho = 0.1 rho_bondi, P = 50 P_bondi, u = 0."""
+    p, metric, eos, frozen = bondi_problem(grid, M, r_in)
+    X, Z = cell_coords(grid)
+    r = np.sqrt(X * X + Z * Z)
+    theta = np.arctan2(np.abs(X), Z)
+    inside = r < 3.0 * M * (1.0 + 0.05 * (np.cos(80.0 * theta) + 1.0))
+    G = 4.0 / 3.0
+    p[0] = np.where(inside, 0.1 * p[0], p[0])
+    p[4] = np.where(inside, 50.0 * p[4], p[4])
+    for c in (1, 2, 3):
+        p[c] = np.where(inside, 0.0, p[c])
+    p[5] = p[4] / ((G - 1.0) * p[0])
+    return p, metric, eos, frozen
+
+
 def riemann_patch_sizes(seed, npatch=64, lo=128, hi=2048):
     rng = np.random.default_rng(seed)
     return [int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
