@@ -101,39 +101,37 @@ struct FoldPart {
 // Fold records p1[0..n1) and p2[0..n2) by one whole workgroup of NTHR
 // threads (every thread must call it); the result is valid in thread 0.
 // red: NTHR/64 x 9 words of LDS.  Thread t folds records t, t + NTHR, ...
-// in that order (four loads in flight at a time), the waves reduce by
-// shuffles and thread 0 combines the wave results in wave order: the result
-// depends only on the record counts.
+// of both arrays; the loads of up to four records of each array are
+// issued together before any is used, so a small fold is one memory round
+// trip.  The waves reduce by shuffles and thread 0 combines the wave
+// results in wave order: the result depends only on the record counts.
 template <int NTHR>
 __device__ FoldPart fold_records(const C2PPart *p1, int n1, const FluxPart *p2, int n2,
                                  unsigned long long (*red)[9]) {
   int t = threadIdx.x;
   unsigned long long a[6] = {0, 0, 0, 0, 0, 0};
   double c = 0.0, mb = 0.0, jm = 0.0;
-  for (int i0 = t; i0 < n1; i0 += 4 * NTHR) {
-    C2PPart r[4];
+  const int nmax = n1 > n2 ? n1 : n2;
+  for (int i0 = t; i0 < nmax; i0 += 4 * NTHR) {
+    C2PPart r1[4];
+    FluxPart r2[4];
 #pragma unroll
-    for (int u = 0; u < 4; u++)
-      if (i0 + u * NTHR < n1) r[u] = p1[i0 + u * NTHR];
+    for (int u = 0; u < 4; u++) {
+      if (i0 + u * NTHR < n1) r1[u] = p1[i0 + u * NTHR];
+      if (i0 + u * NTHR < n2) r2[u] = p2[i0 + u * NTHR];
+    }
 #pragma unroll
-    for (int u = 0; u < 4; u++)
+    for (int u = 0; u < 4; u++) {
       if (i0 + u * NTHR < n1) {
-        for (int k = 0; k < 5; k++) a[k] += r[u].n[k];
-        a[5] = r[u].n[5] > a[5] ? r[u].n[5] : a[5];
+        for (int k = 0; k < 5; k++) a[k] += r1[u].n[k];
+        a[5] = r1[u].n[5] > a[5] ? r1[u].n[5] : a[5];
       }
-  }
-  for (int i0 = t; i0 < n2; i0 += 4 * NTHR) {
-    FluxPart r[4];
-#pragma unroll
-    for (int u = 0; u < 4; u++)
-      if (i0 + u * NTHR < n2) r[u] = p2[i0 + u * NTHR];
-#pragma unroll
-    for (int u = 0; u < 4; u++)
       if (i0 + u * NTHR < n2) {
-        c = fmax(c, r[u].cmax);
-        mb += r[u].mb;
-        jm += r[u].jm;
+        c = fmax(c, r2[u].cmax);
+        mb += r2[u].mb;
+        jm += r2[u].jm;
       }
+    }
   }
   for (int k = 0; k < 5; k++) a[k] = wave_sum_u64(a[k]);
   a[5] = wave_max_u64(a[5]);
