@@ -103,6 +103,8 @@ def parse():
     ap.add_argument("--forms", default=",".join(ALL_FORMS))
     ap.add_argument("--accuracy-substeps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-reuse-atm", action="store_true",
+                    help="the star forms' recoveries rewrite the primitives of every cell")
     ap.add_argument("--cpu-sample-rows", type=int, default=1024)
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
     ap.add_argument("--learned-n", type=int, default=2048)
@@ -147,7 +149,9 @@ def main():
     tov = synth.tov_solve()
     p_np, metric_np, eos = synth.star_problem(grid, seed=2025, tov=tov)
     metric = {k: torch.from_numpy(v).to(dev) for k, v in metric_np.items()}
-    c2p = dict(w_max=100.0, rho_atm=1e-10)
+    # cells that stay atmosphere keep the primitives of the previous
+    # recovery into the same buffer (bit for bit the same p)
+    c2p = dict(w_max=100.0, rho_atm=1e-10, reuse_atm=not args.no_reuse_atm)
     dt = 0.4 * grid["dx"]
     nzone = grid["nx"] * grid["nz"]
 
@@ -193,7 +197,7 @@ def main():
                 if self.chained:
                     self.sub.chained(self.stages[s], qn, qs, qo, *prims[s], diag=self.diag, events=kev)
                 else:
-                    self.sub(self.stages[s], qn, qs, qo, self.p, diag=self.diag, events=kev)
+                    self.sub(self.stages[s], qn, qs, qo, self.p, flags=self.fa, diag=self.diag, events=kev)
                 if events is not None:
                     events[s][1].record()
             self.q, self.q1 = self.q1, self.q
@@ -310,6 +314,7 @@ def main():
             "workload": "TOV star K=100 Gamma=2 rho_c=1.28e-3, %dx%d cylindrical [0,20]^2, "
                         "Cowling metric, PPM+HLLC, SSP-RK3 (3 substeps per step)" % (n, n),
             "zones": nzone, "substeps_per_step": 3, "seed": 2025,
+            "recovery_reuse_atm": not args.no_reuse_atm,
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

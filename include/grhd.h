@@ -112,6 +112,17 @@ typedef struct {
                              discarded: every cell takes the cold root from
                              (D, S_i), its E is reset from the cold state
                              and it carries GRHD_FLAG_COLD */
+  int reuse_atm;          /* nonzero: a cell whose entry in the caller's
+                             flags array already carries GRHD_FLAG_ATM and
+                             that is reset to the atmosphere again does not
+                             rewrite its primitives.  Precondition: p holds
+                             what the last recovery with this flags array
+                             wrote (for such cells the atmosphere state of
+                             the same rho_atm and EOS), or the flags are
+                             zero.  p then ends exactly as with 0.  Taken by
+                             grhd_con2prim and grhd_rk_substep with caller
+                             flags and by grhd_rk_substep_chained (pair
+                             p_out, flags_out); ignored elsewhere */
 } grhd_c2p_params;
 
 typedef struct {
@@ -246,7 +257,7 @@ typedef struct grhd_plan grhd_plan;   /* opaque, library-owned */
 
 /* Build a plan for a fixed set of patch shapes: tile shape (from tune_cache
  * if given and present, else measured and stored there), device patch and
- * work tables, persistent-launch configuration and the captured graph. */
+ * work tables, launch configuration and the captured graph. */
 int grhd_plan_create(const grhd_patch *patches, int npatch,
                      const grhd_eos *eos_table, int neos,
                      const grhd_options *opts, const char *tune_cache,

@@ -1,10 +1,10 @@
 // grhd_batch.hip -- batched substep of many patches (fixed-mesh-refinement
 // levels and independent instances of uneven sizes) in one graph-captured
-// sequence: diag reset, one recovery launch over all patches, one
-// persistent launch whose workgroups pop (patch, tile) items from a
-// device-wide counter.  Two tile shapes are compiled into the persistent
-// kernel (thin patches with nz <= 8 and the rest); an autotuner measures the
-// candidate shapes on the actual patches and caches the choice.
+// sequence: one recovery launch over all patches, one stage launch with a
+// workgroup per (patch, tile) item, the diagnostic fold.  Two tile shapes
+// are compiled into the stage kernel (thin patches with nz <= 8 and the
+// rest); an autotuner measures the candidate shapes on the actual patches
+// and caches the choice.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -163,6 +163,7 @@ struct grhd_plan {
   grhd_diag *graph_diag = nullptr;  // diag pointer baked into the graph
   C2PPart *d_part1 = nullptr;       // diagnostic records: recovery workgroups,
   FluxPart *d_part2 = nullptr;      // stage tiles
+  FoldPart *d_lvl = nullptr;        // the fold's chunk results
   long long part2_cap = 0;
   uint8_t *d_flags = nullptr;       // recovery flags of every patch, read by
   std::vector<size_t> flag_off, flag_bytes;  // the stage (atmosphere tiles)
@@ -232,7 +233,7 @@ int capture_graph(grhd_plan *pl, grhd_diag *diag) {
   BatchFn fn = batch_kernel(pl->prec, pl->mc, pl->shape_a, pl->shape_b);
   hipLaunchKernelGGL(fn, dim3((unsigned)pl->total_tiles), dim3(NT), 0, s, pl->d_patches, pl->d_eos,
                      pl->d_tile_prefix, pl->npatch, pl->d_part2);
-  launch_diag_final(pl->d_part1, (int)pl->total_items, pl->d_part2, (int)pl->total_tiles, diag, s);
+  launch_diag_final(pl->d_part1, (int)pl->total_items, pl->d_part2, (int)pl->total_tiles, pl->d_lvl, diag, s);
   hipError_t le = hipGetLastError();
   hipError_t err = hipStreamEndCapture(s, &pl->graph);
   if (le != hipSuccess || err != hipSuccess)
@@ -356,6 +357,7 @@ void destroy_plan(grhd_plan *pl) {
   hipFree(pl->d_diag);
   hipFree(pl->d_part1);
   hipFree(pl->d_part2);
+  hipFree(pl->d_lvl);
   hipFree(pl->d_flags);
   delete pl;
 }
@@ -415,6 +417,7 @@ extern "C" int grhd_plan_create(const grhd_patch *patches, int npatch, const grh
              hipMalloc(&pl->d_item_prefix, sizeof(long long) * npatch) == hipSuccess &&
              hipMalloc(&pl->d_diag, sizeof(grhd_diag)) == hipSuccess &&
              hipMalloc(&pl->d_part1, sizeof(C2PPart) * pl->total_items) == hipSuccess &&
+             hipMalloc(&pl->d_lvl, sizeof(FoldPart) * kFoldMax) == hipSuccess &&
              hipMalloc(&pl->d_flags, flag_total) == hipSuccess &&
              hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking) == hipSuccess;
   for (int s = 0; okm && s < grhd_plan::kSlots; s++)

@@ -41,6 +41,7 @@ struct C2PK {
   int max_iter, guess;
   const void *mlp;
   int adiabatic;  // zero-temperature mode: the cold root only
+  int reuse_atm;  // skip the primitives of cells that stay atmosphere
 };
 
 enum MetricClass { MC_CF = 0, MC_GEN = 1 };  // conformally flat static / general

@@ -1,8 +1,9 @@
-// grhd_diag.hpp -- diagnostics without contended atomics: every workgroup
-// of the recovery and every tile of the stage kernel reduces its cells
-// (wave shuffles, then LDS) and writes one partial record to a scratch
-// array; one single-workgroup kernel folds the records in a fixed order and
-// overwrites the caller's grhd_diag.
+// grhd_diag.hpp -- diagnostics without atomics: every workgroup of the
+// recovery and every tile of the stage kernel reduces its cells (wave
+// shuffles, then LDS) and writes one partial record to a scratch array; a
+// first kernel folds contiguous chunks of the records in parallel, a
+// second one wave folds the chunks in a fixed order and overwrites the
+// caller's grhd_diag.
 #pragma once
 
 #include "grhd_dev.hpp"
@@ -165,8 +166,27 @@ __device__ FoldPart fold_records(const C2PPart *p1, int n1, const FluxPart *p2, 
   return f;
 }
 
-// fold into *diag by one workgroup; defined once in grhd_kernels.hip
-int launch_diag_final(const C2PPart *p1, int n1, const FluxPart *p2, int n2, grhd_diag *diag,
-                      hipStream_t st);
+// Fold of the folded sets f[0..n) (n <= 64) by one wave in a fixed
+// butterfly order; the result is valid in lane 0 and depends only on n.
+__device__ __forceinline__ FoldPart fold_wave(const FoldPart *f, int n) {
+  const int t = threadIdx.x;
+  FoldPart a{};
+  if (t < n) a = f[t];
+  for (int k = 0; k < 5; k++) a.n[k] = wave_sum_u64(a.n[k]);
+  a.n[5] = wave_max_u64(a.n[5]);
+  for (int o = 32; o > 0; o >>= 1) {
+    a.cmax = fmax(a.cmax, __shfl_xor(a.cmax, o, 64));
+    a.mb += __shfl_xor(a.mb, o, 64);
+    a.jm += __shfl_xor(a.jm, o, 64);
+  }
+  return a;
+}
+
+// fold into *diag (two small launches: chunks of the records in parallel,
+// then the chunks in order); defined once in grhd_kernels.hip
+// lvl: kFoldMax folded sets of device scratch owned by the caller.
+constexpr int kFoldMax = 64;
+int launch_diag_final(const C2PPart *p1, int n1, const FluxPart *p2, int n2, FoldPart *lvl,
+                      grhd_diag *diag, hipStream_t st);
 
 }  // namespace grhd

@@ -120,6 +120,7 @@ inline C2PK to_c2pk(const grhd_c2p_params *c) {
   k.guess = c->guess;
   k.mlp = c->mlp;
   k.adiabatic = c->adiabatic ? 1 : 0;
+  k.reuse_atm = 0;  // set by the entry points that take it
   return k;
 }
 

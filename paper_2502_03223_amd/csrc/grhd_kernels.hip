@@ -41,14 +41,29 @@ int fail(int code, const char *fmt, ...) {
 
 // ------------------------------------------------------------ small kernels
 
-// Fold of the diagnostic records into *diag by one 1024-thread workgroup.
-// (Splitting the fold over several workgroups needs a device-scope release
-// by each of them, which writes back the XCD's L2 and costs more than the
-// single workgroup's serial part.)
-__global__ void __launch_bounds__(1024)
-k_diag_final(const C2PPart *p1, int n1, const FluxPart *p2, int n2, grhd_diag *diag) {
-  __shared__ unsigned long long red[16][9];
-  FoldPart f = fold_records<1024>(p1, n1, p2, n2, red);
+// Fold of the diagnostic records into *diag.  Workgroup b of the first
+// kernel folds the b-th contiguous chunk of each record array; one wave of
+// the second folds the chunk results in a fixed order.  The chunk count
+// is a function of the record counts, so the result depends on nothing
+// else.
+__device__ __forceinline__ void fold_chunk(int n, int nchunk, int b, int &lo, int &m) {
+  const int c = (n + nchunk - 1) / nchunk;
+  lo = b * c < n ? b * c : n;
+  m = n - lo < c ? n - lo : c;
+}
+
+__global__ void __launch_bounds__(256)
+k_diag_chunks(const C2PPart *p1, int n1, const FluxPart *p2, int n2, FoldPart *lvl) {
+  __shared__ unsigned long long red[4][9];
+  int lo1, m1, lo2, m2;
+  fold_chunk(n1, gridDim.x, blockIdx.x, lo1, m1);
+  fold_chunk(n2, gridDim.x, blockIdx.x, lo2, m2);
+  FoldPart f = fold_records<256>(p1 + lo1, m1, p2 + lo2, m2, red);
+  if (threadIdx.x == 0) lvl[blockIdx.x] = f;
+}
+
+__global__ void __launch_bounds__(64) k_diag_final(const FoldPart *lvl, int nchunk, grhd_diag *diag) {
+  FoldPart f = fold_wave(lvl, nchunk);
   if (threadIdx.x == 0) {
     diag->max_courant = f.cmax;
     diag->Mb = f.mb;
@@ -62,9 +77,14 @@ k_diag_final(const C2PPart *p1, int n1, const FluxPart *p2, int n2, grhd_diag *d
   }
 }
 
-int launch_diag_final(const C2PPart *p1, int n1, const FluxPart *p2, int n2, grhd_diag *diag,
-                      hipStream_t st) {
-  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(1024), 0, st, p1, n1, p2, n2, diag);
+int launch_diag_final(const C2PPart *p1, int n1, const FluxPart *p2, int n2, FoldPart *lvl,
+                      grhd_diag *diag, hipStream_t st) {
+  // about one record of each array per thread, at most kFoldMax chunks
+  const int n = n1 > n2 ? n1 : n2;
+  int nchunk = (n + 255) / 256;
+  nchunk = nchunk < 1 ? 1 : (nchunk > kFoldMax ? kFoldMax : nchunk);
+  hipLaunchKernelGGL(k_diag_chunks, dim3(nchunk), dim3(256), 0, st, p1, n1, p2, n2, lvl);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, st, lvl, nchunk, diag);
   return launch_status("diag final");
 }
 
@@ -101,13 +121,17 @@ k_con2prim(GridK g, EosK e, C2PK cp, MetK m, Q5 q, P6 p, uint8_t *flags, C2PPart
     }
     double qq[5], pp[6];
     for (int c = 0; c < 5; c++) qq[c] = q.q[c][i];
+    // flag of the last recovery into p (reuse_atm implies caller flags)
+    const unsigned old = cp.reuse_atm ? flags[i] : 0u;
     double q0[5] = {qq[0], qq[1], qq[2], qq[3], qq[4]};
     double x = g.x0 + (j + 0.5) * g.dx;
     C2PResult r = con2prim_cell<MC, EK>(e, cp, W, gtu, x, g.geom, qq, pp, -1.0);
     fl = r.flags;
     iters = r.iters;
     if (fl) store_corrected(qq, q0, q.q, i);
-    for (int c = 0; c < 6; c++) p.p[c][i] = pp[c];
+    // a cell that was and stays atmosphere already holds its primitives
+    if (!(old & fl & GRHD_FLAG_ATM))
+      for (int c = 0; c < 6; c++) p.p[c][i] = pp[c];
     if (flags) flags[i] = (uint8_t)fl;
   }
   if (part)
@@ -338,6 +362,23 @@ static void *stream_scratch(hipStream_t st, int use, size_t bytes) {
 
 void *diag_scratch(hipStream_t st, size_t bytes) { return stream_scratch(st, 0, bytes); }
 
+// the fold's chunk results, then n1 recovery and n2 stage records, in the
+// diagnostic scratch of the stream
+struct DiagBufs {
+  FoldPart *lvl;
+  C2PPart *p1;
+  FluxPart *p2;
+};
+static bool diag_bufs(hipStream_t st, size_t n1, size_t n2, DiagBufs &b) {
+  const size_t l = sizeof(FoldPart) * kFoldMax;
+  char *buf = (char *)diag_scratch(st, l + sizeof(C2PPart) * n1 + sizeof(FluxPart) * n2);
+  if (!buf) return false;
+  b.lvl = (FoldPart *)buf;
+  b.p1 = (C2PPart *)(buf + l);
+  b.p2 = (FluxPart *)(buf + l + sizeof(C2PPart) * n1);
+  return true;
+}
+
 int shape_index(int tx, int tz) {
   for (int s = 0; s < kNumShapes; s++)
     if (kShapes[s].tx == tx && kShapes[s].tz == tz) return s;
@@ -438,16 +479,16 @@ extern "C" int grhd_con2prim(const grhd_grid *grid, const grhd_eos *eos, const g
   for (int c = 0; c < 6; c++) pp.p[c] = p->p[c];
   GridK g = to_gridk(grid);
   int nb1 = con2prim_blocks(g);
-  C2PPart *p1 = nullptr;
-  if (diag) {
-    p1 = (C2PPart *)diag_scratch(st, sizeof(C2PPart) * nb1);
-    if (!p1) return fail(GRHD_ERR_DEVICE, "diagnostic scratch allocation failed");
-  }
-  if ((rc = launch_con2prim(g, to_eosk(eos, c2p->rho_atm), to_c2pk(c2p), to_metk(metric),
+  DiagBufs db{nullptr, nullptr, nullptr};
+  if (diag && !diag_bufs(st, nb1, 0, db)) return fail(GRHD_ERR_DEVICE, "diagnostic scratch allocation failed");
+  C2PPart *p1 = db.p1;
+  C2PK cp = to_c2pk(c2p);
+  cp.reuse_atm = (c2p->reuse_atm && flags) ? 1 : 0;
+  if ((rc = launch_con2prim(g, to_eosk(eos, c2p->rho_atm), cp, to_metk(metric),
                             metric_class(metric), qq, pp, flags, p1, st)))
     return rc;
   if (diag) {
-    return launch_diag_final(p1, nb1, nullptr, 0, diag, st);
+    return launch_diag_final(p1, nb1, nullptr, 0, db.lvl, diag, st);
   }
   return GRHD_OK;
 }
@@ -635,14 +676,10 @@ extern "C" int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos, const
   for (int c = 0; c < 5; c++) q.q[c] = qs->q[c];
   for (int c = 0; c < 6; c++) pp.p[c] = p->p[c];
   int nb1 = con2prim_blocks(pk.g), nb2 = pk.tiles_x * pk.tiles_z;
-  C2PPart *p1 = nullptr;
-  FluxPart *p2 = nullptr;
-  if (diag) {
-    char *buf = (char *)diag_scratch(st, sizeof(C2PPart) * nb1 + sizeof(FluxPart) * nb2);
-    if (!buf) return fail(GRHD_ERR_DEVICE, "diagnostic scratch allocation failed");
-    p1 = (C2PPart *)buf;
-    p2 = (FluxPart *)(buf + sizeof(C2PPart) * nb1);
-  }
+  DiagBufs db{nullptr, nullptr, nullptr};
+  if (diag && !diag_bufs(st, nb1, nb2, db)) return fail(GRHD_ERR_DEVICE, "diagnostic scratch allocation failed");
+  C2PPart *p1 = db.p1;
+  FluxPart *p2 = db.p2;
   // the stage kernel reads the recovery flags (all-atmosphere tiles skip
   // their primitives); without caller flags they go to library scratch
   uint8_t *fl = flags;
@@ -652,13 +689,15 @@ extern "C" int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos, const
     if (!fl) return fail(GRHD_ERR_DEVICE, "flag scratch allocation failed");
   }
   pk.flags = fl;
-  if ((rc = launch_con2prim(pk.g, e, to_c2pk(&opts->c2p), pk.m, mc, q, pp, fl, p1, st))) return rc;
+  C2PK cp = to_c2pk(&opts->c2p);
+  cp.reuse_atm = (opts->c2p.reuse_atm && flags) ? 1 : 0;  // never with the scratch flags
+  if ((rc = launch_con2prim(pk.g, e, cp, pk.m, mc, q, pp, fl, p1, st))) return rc;
   if (opts->ev_begin && hipEventRecord((hipEvent_t)opts->ev_begin, st) != hipSuccess)
     return fail(GRHD_ERR_DEVICE, "hipEventRecord failed");
   if ((rc = launch_substep(pk, e, opts->prec, mc, shape, p2, st))) return rc;
   if (opts->ev_end && hipEventRecord((hipEvent_t)opts->ev_end, st) != hipSuccess)
     return fail(GRHD_ERR_DEVICE, "hipEventRecord failed");
-  if (diag) return launch_diag_final(p1, nb1, p2, nb2, diag, st);
+  if (diag) return launch_diag_final(p1, nb1, p2, nb2, db.lvl, diag, st);
   return GRHD_OK;
 }
 
@@ -695,6 +734,7 @@ extern "C" int grhd_rk_substep_chained(const grhd_grid *grid, const grhd_eos *eo
   for (int c = 0; c < 6; c++) pk.po[c] = p_out->p[c];
   pk.flags_out = flags_out;
   pk.cp = to_c2pk(&opts->c2p);
+  pk.cp.reuse_atm = opts->c2p.reuse_atm ? 1 : 0;
   pk.xshift = tile_xshift(grid->ng, 16);
   pk.tiles_x = (grid->nx + pk.xshift + 15) / 16;
   pk.tiles_z = (grid->nz + 15) / 16;
@@ -702,20 +742,16 @@ extern "C" int grhd_rk_substep_chained(const grhd_grid *grid, const grhd_eos *eo
   EosK e = to_eosk(eos, opts->c2p.rho_atm);
   int mc = metric_class(metric);
   int nt = pk.tiles_x * pk.tiles_z;
-  C2PPart *p1 = nullptr;
-  FluxPart *p2 = nullptr;
-  if (diag) {
-    char *buf = (char *)diag_scratch(st, (sizeof(C2PPart) + sizeof(FluxPart)) * (size_t)nt);
-    if (!buf) return fail(GRHD_ERR_DEVICE, "diagnostic scratch allocation failed");
-    p1 = (C2PPart *)buf;
-    p2 = (FluxPart *)(buf + sizeof(C2PPart) * (size_t)nt);
-  }
+  DiagBufs db{nullptr, nullptr, nullptr};
+  if (diag && !diag_bufs(st, nt, nt, db)) return fail(GRHD_ERR_DEVICE, "diagnostic scratch allocation failed");
+  C2PPart *p1 = db.p1;
+  FluxPart *p2 = db.p2;
   if (opts->ev_begin && hipEventRecord((hipEvent_t)opts->ev_begin, st) != hipSuccess)
     return fail(GRHD_ERR_DEVICE, "hipEventRecord failed");
   if ((rc = launch_substep_chain(pk, e, opts->prec, mc, p1, p2, st))) return rc;
   if (opts->ev_end && hipEventRecord((hipEvent_t)opts->ev_end, st) != hipSuccess)
     return fail(GRHD_ERR_DEVICE, "hipEventRecord failed");
-  if (diag) return launch_diag_final(p1, nt, p2, nt, diag, st);
+  if (diag) return launch_diag_final(p1, nt, p2, nt, db.lvl, diag, st);
   return GRHD_OK;
 }
 

@@ -4,7 +4,7 @@
 // of the tile in x then z (fluxes staged in LDS, one buffer reused for both
 // directions), area-weighted divergence, cylindrical and metric sources,
 // and the stage combination, all for one TX x TZ tile of one patch.
-// Used by the single-patch kernel and by the persistent batched kernel.
+// Used by the single-patch kernels and by the batched kernel.
 #pragma once
 
 #include "grhd_dev.hpp"
@@ -156,7 +156,10 @@ __device__ __forceinline__ void finish_cell(const PatchK &P, const EosK &e, long
     if (MC == MC_GEN) inv_sym3(gt, gtu);
     double pp[6];
     C2PResult r = con2prim_cell<MC, EK>(e, P.cp, W, gtu, xc, P.g.geom, v, pp, -1.0);
-    for (int c = 0; c < 6; c++) P.po[c][ic] = pp[c];
+    // a cell that was and stays atmosphere already holds its primitives
+    const bool keep = P.cp.reuse_atm && (r.flags & GRHD_FLAG_ATM) && (P.flags_out[ic] & GRHD_FLAG_ATM);
+    if (!keep)
+      for (int c = 0; c < 6; c++) P.po[c][ic] = pp[c];
     P.flags_out[ic] = (uint8_t)r.flags;
     acc.n[0] += (r.flags & GRHD_FLAG_RESCALE) ? 1 : 0;
     acc.n[1] += (r.flags & GRHD_FLAG_COLD) ? 1 : 0;
@@ -188,7 +191,7 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
   const bool cyl = (g.geom == GRHD_GEOM_CYLINDRICAL);
   const T ra = (T)e.rho_atm, Pa = (T)e.P_atm, ea = (T)e.eps_atm;
   const T cs_atm = tsqrt(eos_cs2<T>(e, ra, ea, Pa));
-  __syncthreads();  // LDS of a previous tile (persistent loop) is free
+  __syncthreads();  // LDS of a previous use in this workgroup is free
 
   // ---- 1. stage the cross-shaped halo in LDS: lapse and W (conformally
   // flat class) and the atmosphere mask first, then the primitives unless

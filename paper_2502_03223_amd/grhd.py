@@ -66,7 +66,7 @@ class Prim(C.Structure):
 class C2PParams(C.Structure):
     _fields_ = [("w_max", C.c_double), ("rho_atm", C.c_double), ("tol", C.c_double),
                 ("max_iter", C.c_int), ("guess", C.c_int), ("mlp", C.c_void_p),
-                ("adiabatic", C.c_int)]
+                ("adiabatic", C.c_int), ("reuse_atm", C.c_int)]
 
 
 class Options(C.Structure):
@@ -231,6 +231,7 @@ def make_c2p(c):
     s.guess = 1 if c.get("mlp") is not None else 0
     s.mlp = c["mlp"].data_ptr() if c.get("mlp") is not None else None
     s.adiabatic = 1 if c.get("adiabatic") else 0
+    s.reuse_atm = 1 if c.get("reuse_atm") else 0
     return s
 
 
@@ -346,7 +347,7 @@ class Substep:
         _check(rc, "grhd_rk_substep")
 
 
-    def bind(self, stage, qn, qs, qout, p, diag=None, stream=None):
+    def bind(self, stage, qn, qs, qout, p, diag=None, stream=None, flags=None):
         """A call of this substep with every argument marshalled once (for
         loops that repeat the same calls)."""
         L = lib()
@@ -354,10 +355,10 @@ class Substep:
         args = (C.byref(self.grid), C.byref(self.eos), C.byref(self.metric), C.byref(self.opts),
                 C.byref(st), C.byref(make_cons(qn if qn is not None else qs)),
                 C.byref(make_cons(qs)), C.byref(make_cons(qout)), C.byref(make_prim(p)), None, None,
-                C.c_void_p(0), C.c_void_p(0),
+                C.c_void_p(0), C.c_void_p(flags.data_ptr() if flags is not None else 0),
                 C.c_void_p(diag.data_ptr() if diag is not None else 0),
                 C.c_void_p(stream) if stream is not None else _stream())
-        keep = (st, qn, qs, qout, p, diag)
+        keep = (st, qn, qs, qout, p, diag, flags)
 
         def call():
             _check(L.grhd_rk_substep(*args), "grhd_rk_substep")
