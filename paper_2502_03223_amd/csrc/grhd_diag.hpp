@@ -26,6 +26,73 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
   return v;
 }
 
+// A double moved across lanes by one DPP pattern (both 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ __forceinline__ double lane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Wave sum and maximum of doubles in a fixed order, without LDS: within
+// each row of 16 lanes by DPP (swap neighbours, swap pairs, mirror half
+// rows, mirror rows: each step combines two equal-sized groups, so every
+// lane of a row ends with the same bits), then the four row results in
+// order.  All 64 lanes must be active; the result is uniform.
+constexpr int kDppQuad1032 = 0xB1, kDppQuad2301 = 0x4E, kDppRowHalfMirror = 0x141, kDppRowMirror = 0x140;
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  v += dpp_f64<kDppQuad1032>(v);
+  v += dpp_f64<kDppQuad2301>(v);
+  v += dpp_f64<kDppRowHalfMirror>(v);
+  v += dpp_f64<kDppRowMirror>(v);
+  return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+}
+
+__device__ __forceinline__ double wave_max_f64(double v) {
+  v = fmax(v, dpp_f64<kDppQuad1032>(v));
+  v = fmax(v, dpp_f64<kDppQuad2301>(v));
+  v = fmax(v, dpp_f64<kDppRowHalfMirror>(v));
+  v = fmax(v, dpp_f64<kDppRowMirror>(v));
+  return fmax(fmax(lane_f64(v, 0), lane_f64(v, 16)), fmax(lane_f64(v, 32), lane_f64(v, 48)));
+}
+
+// Sum and maximum over the wave of small non-negative integers, exact, by
+// bit planes: plane b contributes 2^b times the number of lanes with bit b
+// set (a ballot and a bit count, no LDS traffic); the planes run while any
+// lane has bits left, a loop that is uniform over the wave.
+__device__ __forceinline__ unsigned long long wave_sum_small(unsigned long long v) {
+  unsigned long long s = 0;
+  for (int b = 0; b < 64 && __ballot((v >> b) != 0); b++)
+    s += (unsigned long long)__popcll(__ballot((v >> b) & 1)) << b;
+  return s;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_small(unsigned long long v) {
+  int top = 0;  // planes in use
+  while (top < 64 && __ballot((v >> top) != 0)) top++;
+  // from the highest plane down, keep the lanes that agree with the
+  // maximum found so far
+  bool alive = true;
+  unsigned long long m = 0;
+  for (int b = top - 1; b >= 0; b--) {
+    const bool bit = ((v >> b) & 1) != 0;
+    if (__ballot(alive && bit)) {
+      m |= 1ull << b;
+      alive = alive && bit;
+    }
+  }
+  return m;
+}
+
 // workgroup partial of per-thread recovery statistics v[6] (counts and
 // iteration sum are summed, the iteration maximum is maxed); all threads
 // must call it
@@ -33,8 +100,8 @@ template <int NTHR>
 __device__ __forceinline__ void c2p_counts_partial(const unsigned long long *v6, C2PPart *out,
                                                    unsigned long long (*red)[6]) {
   unsigned long long v[6];
-  for (int i = 0; i < 5; i++) v[i] = wave_sum_u64(v6[i]);
-  v[5] = wave_max_u64(v6[5]);
+  for (int i = 0; i < 5; i++) v[i] = wave_sum_small(v6[i]);
+  v[5] = wave_max_small(v6[5]);
   int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0)
     for (int i = 0; i < 6; i++) red[w][i] = v[i];
@@ -70,11 +137,9 @@ __device__ __forceinline__ void c2p_block_partial(bool act, unsigned fl, int ite
 template <int NTHR>
 __device__ __forceinline__ void flux_block_partial(double cmax, double mb, double jm, FluxPart *out,
                                                    double (*red)[3]) {
-  for (int o = 32; o > 0; o >>= 1) {
-    cmax = fmax(cmax, __shfl_xor(cmax, o, 64));
-    mb += __shfl_xor(mb, o, 64);
-    jm += __shfl_xor(jm, o, 64);
-  }
+  cmax = wave_max_f64(cmax);
+  mb = wave_sum_f64(mb);
+  jm = wave_sum_f64(jm);
   int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
     red[w][0] = cmax;
@@ -136,11 +201,9 @@ __device__ FoldPart fold_records(const C2PPart *p1, int n1, const FluxPart *p2, 
   }
   for (int k = 0; k < 5; k++) a[k] = wave_sum_u64(a[k]);
   a[5] = wave_max_u64(a[5]);
-  for (int o = 32; o > 0; o >>= 1) {
-    c = fmax(c, __shfl_xor(c, o, 64));
-    mb += __shfl_xor(mb, o, 64);
-    jm += __shfl_xor(jm, o, 64);
-  }
+  c = wave_max_f64(c);
+  mb = wave_sum_f64(mb);
+  jm = wave_sum_f64(jm);
   int w = t >> 6;
   if ((t & 63) == 0) {
     for (int k = 0; k < 6; k++) red[w][k] = a[k];
@@ -166,19 +229,17 @@ __device__ FoldPart fold_records(const C2PPart *p1, int n1, const FluxPart *p2, 
   return f;
 }
 
-// Fold of the folded sets f[0..n) (n <= 64) by one wave in a fixed
-// butterfly order; the result is valid in lane 0 and depends only on n.
+// Fold of the folded sets f[0..n) (n <= 64) by one wave in a fixed order;
+// the result is valid in lane 0 and depends only on n.
 __device__ __forceinline__ FoldPart fold_wave(const FoldPart *f, int n) {
   const int t = threadIdx.x;
   FoldPart a{};
   if (t < n) a = f[t];
   for (int k = 0; k < 5; k++) a.n[k] = wave_sum_u64(a.n[k]);
   a.n[5] = wave_max_u64(a.n[5]);
-  for (int o = 32; o > 0; o >>= 1) {
-    a.cmax = fmax(a.cmax, __shfl_xor(a.cmax, o, 64));
-    a.mb += __shfl_xor(a.mb, o, 64);
-    a.jm += __shfl_xor(a.jm, o, 64);
-  }
+  a.cmax = wave_max_f64(a.cmax);
+  a.mb = wave_sum_f64(a.mb);
+  a.jm = wave_sum_f64(a.jm);
   return a;
 }
 
