@@ -13,17 +13,44 @@ namespace grhd {
 struct C2PPart { unsigned long long n[6]; };   // rescale, cold, atm, fail, iter sum, iter max
 struct FluxPart { double cmax, mb, jm, pad; };
 
+// A 64-bit integer moved across lanes by one DPP pattern (both halves).
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, 0xF, 0xF, true);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+__device__ __forceinline__ unsigned long long lane_u64(unsigned long long v, int lane) {
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)v, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+constexpr int kDppQuad1032 = 0xB1, kDppQuad2301 = 0x4E, kDppRowHalfMirror = 0x141, kDppRowMirror = 0x140;
+
+// Wave sum and maximum of 64-bit integers without LDS: within each row of
+// 16 lanes by DPP (swap neighbours, swap pairs, mirror half rows, mirror
+// rows), then the four row results.  All 64 lanes must be active; the
+// result is uniform.
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_u64<kDppQuad1032>(v);
+  v += dpp_u64<kDppQuad2301>(v);
+  v += dpp_u64<kDppRowHalfMirror>(v);
+  v += dpp_u64<kDppRowMirror>(v);
+  return lane_u64(v, 0) + lane_u64(v, 16) + lane_u64(v, 32) + lane_u64(v, 48);
+}
+
+__device__ __forceinline__ unsigned long long u64max(unsigned long long a, unsigned long long b) {
+  return a > b ? a : b;
 }
 
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-  for (int o = 32; o > 0; o >>= 1) {
-    unsigned long long w = __shfl_xor(v, o, 64);
-    v = w > v ? w : v;
-  }
-  return v;
+  v = u64max(v, dpp_u64<kDppQuad1032>(v));
+  v = u64max(v, dpp_u64<kDppQuad2301>(v));
+  v = u64max(v, dpp_u64<kDppRowHalfMirror>(v));
+  v = u64max(v, dpp_u64<kDppRowMirror>(v));
+  return u64max(u64max(lane_u64(v, 0), lane_u64(v, 16)), u64max(lane_u64(v, 32), lane_u64(v, 48)));
 }
 
 // A double moved across lanes by one DPP pattern (both 32-bit halves).
@@ -47,8 +74,6 @@ __device__ __forceinline__ double lane_f64(double v, int lane) {
 // rows, mirror rows: each step combines two equal-sized groups, so every
 // lane of a row ends with the same bits), then the four row results in
 // order.  All 64 lanes must be active; the result is uniform.
-constexpr int kDppQuad1032 = 0xB1, kDppQuad2301 = 0x4E, kDppRowHalfMirror = 0x141, kDppRowMirror = 0x140;
-
 __device__ __forceinline__ double wave_sum_f64(double v) {
   v += dpp_f64<kDppQuad1032>(v);
   v += dpp_f64<kDppQuad2301>(v);
