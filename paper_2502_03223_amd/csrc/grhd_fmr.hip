@@ -354,6 +354,13 @@ struct grhd_fmr {
   std::vector<int> ns;
   std::vector<std::array<double, 3>> ts;
   int shape = 3;
+  // per level: recovery flags of the stage recoveries (library-owned), so
+  // the stage kernel takes its all-atmosphere tile path
+  std::vector<uint8_t *> flags;
+  ~grhd_fmr() {
+    for (uint8_t *f : flags)
+      if (f) (void)hipFree(f);
+  }
 };
 
 namespace {
@@ -417,6 +424,7 @@ int step_level(grhd_fmr *h, int l, double t, double dt, hipStream_t st) {
     if ((rc = fill_patch(&L.grid, &L.metric, &stg, &L.q, qs_of[s], qo_of[s], &L.p, nullptr, nullptr, nullptr,
                          h->opts.recon, h->opts.riemann, pk)))
       return rc;
+    pk.flags = h->flags[l];
     if (has_parent) { pk.reg[0] = L.reg_child_bnd; pk.reg_j[0] = L.grid.nx; pk.reg_k[0] = L.grid.nz; }
     if (has_child) { pk.reg[1] = L.reg_parent_int; pk.reg_j[1] = cg->nx / 2; pk.reg_k[1] = cg->nz / 2; }
     pk.reg_w = kW[s];
@@ -434,7 +442,8 @@ int step_level(grhd_fmr *h, int l, double t, double dt, hipStream_t st) {
     P6 p;
     for (int c = 0; c < 5; c++) q.q[c] = qs_of[s]->q[c];
     for (int f = 0; f < 6; f++) p.p[f] = L.p.p[f];
-    if ((rc = launch_con2prim(pk.g, e, to_c2pk(&h->opts.c2p), pk.m, mc, q, p, nullptr, nullptr, st))) return rc;
+    if ((rc = launch_con2prim(pk.g, e, to_c2pk(&h->opts.c2p), pk.m, mc, q, p, h->flags[l], nullptr, st)))
+      return rc;
     if ((rc = launch_substep(pk, e, h->opts.prec, mc, shape, nullptr, st))) return rc;
   }
   if (!has_child) return GRHD_OK;
@@ -488,6 +497,14 @@ extern "C" int grhd_fmr_create(const grhd_level *levels, int nlev, const grhd_eo
   h->ns.assign(nlev, 0);
   h->ts.assign(nlev, {0.0, 0.0, 0.0});
   h->shape = shape_index(16, 16);
+  h->flags.assign(nlev, nullptr);
+  for (int l = 0; l < nlev; l++) {
+    const size_t fb = (size_t)(levels[l].grid.nz + 2 * levels[l].grid.ng) * (size_t)levels[l].grid.pitch;
+    if (hipMalloc(&h->flags[l], fb) != hipSuccess || hipMemset(h->flags[l], 0, fb) != hipSuccess) {
+      delete h;
+      return fail(GRHD_ERR_DEVICE, "flag allocation failed");
+    }
+  }
   hipStream_t st = (hipStream_t)hip_stream;
   for (int l = 0; l < nlev; l++) {
     if (l + 1 < nlev && (rc = push_slice(h, l, t0, st))) { delete h; return rc; }
@@ -517,6 +534,8 @@ extern "C" int grhd_fmr_time(const grhd_fmr *h, double *t) {
 
 extern "C" int grhd_fmr_destroy(grhd_fmr *h) {
   if (!h) return fail(GRHD_ERR_INVALID, "hierarchy is NULL");
+  // queued steps may still read the level flags
+  if (hipDeviceSynchronize() != hipSuccess) return fail(GRHD_ERR_DEVICE, "hipDeviceSynchronize failed");
   delete h;
   return GRHD_OK;
 }
