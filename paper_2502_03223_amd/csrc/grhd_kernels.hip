@@ -92,10 +92,18 @@ __global__ void k_zero_double(double *d) {
   if (threadIdx.x == 0) *d = 0.0;
 }
 
+// The gamma-law, conformally flat recovery fits six waves per SIMD in
+// registers without spilling (one more than unconstrained); the other
+// instances would spill there.
+template <int MC, int EK>
+constexpr int con2prim_waves() {
+  return (MC == MC_CF && EK == GRHD_EOS_IDEAL) ? 6 : 1;
+}
+
 // Recovery of one cell per thread over [jlo, jhi) x [klo, khi); cells
 // outside the interior are processed only on EXTERNAL sides (corners never).
 template <int MC, int EK>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(con2prim_waves<MC, EK>())))
 k_con2prim(GridK g, EosK e, C2PK cp, MetK m, Q5 q, P6 p, uint8_t *flags, C2PPart *part,
            int jlo, int jhi, int klo) {
   __shared__ unsigned long long red[4][6];
