@@ -277,6 +277,16 @@ int grhd_plan_destroy(grhd_plan *plan);
  * both arrays hold 2 ints. */
 int grhd_plan_tile(const grhd_plan *plan, int *tile_x, int *tile_z);
 
+/* The batched autotuner on its own: the tile shapes a plan for these
+ * patches would use -- taken from tune_cache when it holds this GPU,
+ * option set and patch-shape set, else measured by timing the candidate
+ * shapes on the patches (their q_s is corrected in place and q_out
+ * overwritten, as by grhd_plan_create) and stored there.  tile_x, tile_z:
+ * 2 ints each, laid out as for grhd_plan_tile.  Explicit tile_x/tile_z in
+ * opts are returned as they are.  Synchronous (library streams). */
+int grhd_autotune(const grhd_patch *patches, int npatch, const grhd_eos *eos_table, int neos,
+                  const grhd_options *opts, const char *tune_cache, int *tile_x, int *tile_z);
+
 /* Interior boundary condition (the inner region of the Bondi test of
  * Sec. III.B.2 keeps its initial state): q = q_fixed on every interior
  * cell whose mask byte (cell array, same layout as q) is nonzero. */

@@ -488,6 +488,17 @@ extern "C" int grhd_plan_destroy(grhd_plan *pl) {
   return GRHD_OK;
 }
 
+extern "C" int grhd_autotune(const grhd_patch *patches, int npatch, const grhd_eos *eos_table, int neos,
+                             const grhd_options *opts, const char *tune_cache, int *tile_x, int *tile_z) {
+  if (!tile_x || !tile_z) return fail(GRHD_ERR_INVALID, "NULL argument");
+  grhd_plan *pl = nullptr;
+  int rc = grhd_plan_create(patches, npatch, eos_table, neos, opts, tune_cache, &pl);
+  if (rc) return rc;
+  rc = grhd_plan_tile(pl, tile_x, tile_z);
+  grhd_plan_destroy(pl);
+  return rc;
+}
+
 extern "C" int grhd_plan_tile(const grhd_plan *pl, int *tile_x, int *tile_z) {
   if (!pl || !tile_x || !tile_z) return fail(GRHD_ERR_INVALID, "NULL argument");
   tile_x[0] = kSquare[pl->shape_b][0];

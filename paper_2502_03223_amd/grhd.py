@@ -130,6 +130,7 @@ def lib():
             "grhd_batch_levels": [p, p, i, p, p],
             "grhd_plan_destroy": [p],
             "grhd_plan_tile": [p, p, p],
+            "grhd_autotune": [p, i, p, i, p, C.c_char_p, p, p],
             "grhd_event_create": [p],
             "grhd_event_elapsed_ms": [p, p, p],
             "grhd_event_destroy": [p],
@@ -432,6 +433,20 @@ def make_patch(d):
     fr = d.get("flux_reg")
     s.flux_reg = fr.data_ptr() if fr is not None else None
     return s
+
+
+def autotune(patches, eos_table, opts, tune_cache=None):
+    """grhd_autotune: the tile shapes a plan for these patches would use
+    (may time the candidates on the patches' buffers)."""
+    n = len(patches)
+    arr = (Patch * n)(*[make_patch(d) for d in patches])
+    eos_arr = (Eos * len(eos_table))(*[make_eos(e) for e in eos_table])
+    o = make_options(opts)
+    tx = (C.c_int * 2)()
+    tz = (C.c_int * 2)()
+    _check(lib().grhd_autotune(arr, n, eos_arr, len(eos_table), C.byref(o),
+                               tune_cache.encode() if tune_cache else None, tx, tz), "grhd_autotune")
+    return dict(square=(tx[0], tz[0]), thin=(tx[1], tz[1]))
 
 
 class Plan:

@@ -104,3 +104,12 @@ def test_batch_tune_cache_roundtrip(orc, tmp_path):
     assert p2.tiles() == t1
     assert len(open(cache).read().splitlines()) == 1   # found, not re-measured
     p2.close()
+    # the tuner on its own reads the same entry, and measures a fresh cache
+    assert grhd.autotune(desc, eos_table, opts, tune_cache=cache) == t1
+    assert len(open(cache).read().splitlines()) == 1
+    fresh = str(tmp_path / "fresh.txt")
+    t3 = grhd.autotune(desc, eos_table, opts, tune_cache=fresh)
+    assert len(open(fresh).read().splitlines()) == 1
+    assert t3["thin"][1] == 8 and t3["square"] in [(32, 8), (32, 16), (64, 8), (16, 16)]
+    # explicit shapes pass through
+    assert grhd.autotune(desc, eos_table, dict(opts, tile=(32, 16)))["square"] == (32, 16)
