@@ -262,10 +262,21 @@ k_flux(GridK g, EosK e, MetK m, int dir, int riemann, Ptr6<T> Lp, Ptr6<T> Rp, Q5
 // across the XCDs and cost more than the imbalance they remove.)
 // Waves per SIMD the register allocation must allow: the FP64 16 x 16 and
 // 16 x 8 instances of the conformally flat class fit at least three
-// workgroups per CU in LDS, so their registers are held to three waves.
+// workgroups per CU in LDS, so their registers are held to three waves;
+// the FP32 16 x 16 instance fits four (31 KB of LDS) and is held to four
+// (113 registers, no spilling).
 template <class T, int MC, int TX, int TZ>
 constexpr int substep_waves() {
-  return (sizeof(T) == 8 && MC == MC_CF && TX == 16 && (TZ == 16 || TZ == 8)) ? 3 : 1;
+  return (sizeof(T) == 8 && MC == MC_CF && TX == 16 && (TZ == 16 || TZ == 8)) ? 3
+         : (sizeof(T) == 4 && MC == MC_CF && TX == 16 && TZ == 16)             ? 4
+                                                                               : 1;
+}
+
+// The chained instances: as above, except that the FP32 hybrid-EOS
+// recovery would spill at four waves and stays unconstrained.
+template <class T, int MC, int EK>
+constexpr int chain_waves() {
+  return (sizeof(T) == 4 && EK != GRHD_EOS_IDEAL) ? 1 : substep_waves<T, MC, 16, 16>();
 }
 
 template <class T, int MC, int TX, int TZ>
@@ -286,7 +297,7 @@ k_substep(PatchK P, EosK e, FluxPart *part2) {
 // recovery of q_out for the next stage.  Records: part1[tile] (recovery of
 // q_out), part2[tile] (stage diagnostics).
 template <class T, int MC, int EK>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(substep_waves<T, MC, 16, 16>())))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(chain_waves<T, MC, EK>())))
 k_substep_chain(PatchK P, EosK e, C2PPart *part1, FluxPart *part2) {
   __shared__ TileSmem<T, MC, 16, 16> sm;
   __shared__ double red[NT / 64][3];
