@@ -29,6 +29,9 @@ struct EosK {
   double K[8], G[8], rho_b[8], deps[8];
   double Gth;
   double P_atm, eps_atm, rho_atm;
+  // of the atmosphere state, set on the host: sound speed (c_s^2 clamped
+  // to [0, 0.999999] as eos_cs2 does) and rho h
+  double cs_atm, rhw2_atm;
 };
 
 struct MetK {

@@ -98,6 +98,24 @@ inline EosK to_eosk(const grhd_eos *e, double rho_atm) {
     k.P_atm = e->K[i] * std::pow(rho_atm, e->Gamma[i]);
     k.eps_atm = e->K[i] / (e->Gamma[i] - 1.0) * std::pow(rho_atm, e->Gamma[i] - 1.0) + k.deps[i];
   }
+  // c_s^2 of the atmosphere state, the same expression as the device EOS
+  const double gm1 = k.Gth - 1.0;
+  double chi;
+  if (k.kind == GRHD_EOS_IDEAL) {
+    chi = gm1 * k.eps_atm;
+  } else {
+    int i = 0;
+    while (i < k.n - 1 && rho_atm >= k.rho_b[i]) i++;
+    const double kr = k.K[i] * std::pow(rho_atm, k.G[i] - 1.0);
+    const double ec = kr / (k.G[i] - 1.0) + k.deps[i];
+    chi = k.G[i] * kr + gm1 * (k.eps_atm - ec) - gm1 * kr;
+  }
+  const double h = 1.0 + k.eps_atm + k.P_atm / rho_atm;
+  double cs2 = (chi + k.P_atm / rho_atm * gm1) / h;
+  if (!(cs2 > 0.0)) cs2 = 0.0;
+  if (cs2 > 0.999999) cs2 = 0.999999;
+  k.cs_atm = std::sqrt(cs2);
+  k.rhw2_atm = rho_atm * h;
   return k;
 }
 

@@ -641,6 +641,9 @@ int fill_patch(const grhd_grid *grid, const grhd_metric *metric, const grhd_rk_s
   pk.flux_reg = flux_reg;
   pk.a = stage->a; pk.b = stage->b; pk.cdt = stage->c * stage->dt;
   pk.gdt = stage->g * stage->dt; pk.d = stage->d; pk.e = stage->e; pk.dt = stage->dt;
+  pk.cx = stage->dt / grid->dx; pk.cz = stage->dt / grid->dz;
+  pk.idx = 1.0 / grid->dx; pk.idz = 1.0 / grid->dz;
+  pk.i60dx = 1.0 / (60.0 * grid->dx); pk.i60dz = 1.0 / (60.0 * grid->dz);
   pk.use_qn = stage->a != 0.0;
   pk.use_acc_in = acc_in != nullptr && (stage->g != 0.0 || stage->d != 0.0);
   pk.use_acc_out = acc_out != nullptr;

@@ -21,6 +21,9 @@ struct PatchK {
   double *acc_in[5], *acc_out[5];
   double *flux_reg;
   double a, b, cdt, gdt, d, e, dt;
+  // grid and step constants, set on the host: dt/dx, dt/dz, 1/dx, 1/dz,
+  // 1/(60 dx), 1/(60 dz)
+  double cx, cz, idx, idz, i60dx, i60dz;
   int use_qn, use_acc_in, use_acc_out;
   int recon, riemann, eos_id;
   uint8_t *flags;  // recovery flags of q_s (nullable)
@@ -190,7 +193,7 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
   const int j0 = tx * TX - P.xshift, k0 = tz * TZ;
   const bool cyl = (g.geom == GRHD_GEOM_CYLINDRICAL);
   const T ra = (T)e.rho_atm, Pa = (T)e.P_atm, ea = (T)e.eps_atm;
-  const T cs_atm = tsqrt(eos_cs2<T>(e, ra, ea, Pa));
+  const T cs_atm = (T)e.cs_atm;
   __syncthreads();  // LDS of a previous use in this workgroup is free
 
   // ---- 1. stage the cross-shaped halo in LDS: lapse and W (conformally
@@ -286,8 +289,8 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
   const int nb = 2 * nz + 2 * nx;  // flux-register stride
   double cmax = 0.0;
   // rho h of the atmosphere state
-  const double rhw2_atm = e.rho_atm * (1.0 + e.eps_atm + e.P_atm / e.rho_atm);
-  const double i60dx = 1.0 / (60.0 * g.dx), i60dz = 1.0 / (60.0 * g.dz);
+  const double rhw2_atm = e.rhw2_atm;
+  const double i60dx = P.i60dx, i60dz = P.i60dz;
 
   const bool atm_fast = (MC == MC_CF) && tile_atm;
   if (atm_fast) {
@@ -297,7 +300,7 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
     // -+ alpha c_s W; D, S_phi and tau of the cells change only through
     // the stage weights.  The same values as the general path's uniform
     // faces and atmosphere sources, with the zero terms left out.
-    const double cx = P.dt / g.dx, cz = P.dt / g.dz;
+    const double cx = P.cx, cz = P.cz;
     for (int f = tid; f < S::NF; f += NT) {
       const bool isx = f < S::NFX;
       int jj, kk, base, stride;
@@ -421,7 +424,7 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
         } else {
           face_flux<T, MC>(e, fm, isx ? 0 : 1, P.riemann, L, R, out);
         }
-        cmax = fmax(cmax, (double)out.speed * (P.dt / (isx ? g.dx : g.dz)));
+        cmax = fmax(cmax, (double)out.speed * (isx ? P.cx : P.cz));
         const bool on_edge = isx ? (j == 0 || j == nx) : (k == 0 || k == nz);
         if ((P.flux_reg && on_edge) || P.reg[0] || P.reg[1]) {
           double xx = isx ? g.x0 + j * g.dx : g.x0 + (j + 0.5) * g.dx;
@@ -464,7 +467,7 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
     const double xl = g.x0 + j * g.dx, xr = g.x0 + (j + 1) * g.dx;
     const int fl = kk * (TX + 1) + jj, fr = fl + 1;
     const int fb = S::NFX + kk * TX + jj, ft = fb + TX;
-    const double ivx = cyl ? 1.0 / (xc * g.dx) : 1.0 / g.dx, ivz = 1.0 / g.dz;
+    const double ivx = cyl ? 1.0 / (xc * g.dx) : P.idx, ivz = P.idz;
     // metric at the cell and its x, z derivatives
     double gm[GRHD_NMET], dg[2 * GRHD_NMET];
     if (MC == MC_CF) {
