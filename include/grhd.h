@@ -69,7 +69,9 @@ enum { GRHD_M_ALP = 0, GRHD_M_BX, GRHD_M_BY, GRHD_M_BZ, GRHD_M_W,
 /* Cell-centred grid of one patch (Sec. II.A). */
 typedef struct {
   int nx, nz, ng;         /* interior cells; ghosts (must be 3) */
-  int64_t pitch;          /* row pitch in elements, >= nx + 2 ng */
+  int64_t pitch;          /* row pitch in elements, >= nx + 2 ng; a field
+                             holds at most 2^29 cells:
+                             (nz + 2 ng) pitch <= 2^29 */
   double x0, z0, dx, dz;  /* lower faces of cell (0,0); spacings > 0 */
   int geom;               /* GRHD_GEOM_*; cylindrical needs x0 >= 0 */
   int bc[4];              /* x-low, x-high, z-low, z-high: GRHD_BC_* */

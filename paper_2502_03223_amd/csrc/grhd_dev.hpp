@@ -57,6 +57,28 @@ __device__ __forceinline__ double mval(const MetK &m, int f, long long i) {
   return m.f[f] ? m.f[f][i] : m.c[f];
 }
 
+// Cell arrays addressed by a 32-bit element index through a 32-bit byte
+// offset from the base pointer (a field holds at most 2^29 cells, checked
+// on the host): with a uniform base the compiler uses the scalar-base
+// form, one offset register for every field of a cell.
+__device__ __forceinline__ unsigned cell_idx32(const GridK &g, int j, int k) {
+  return (unsigned)((k + g.ng) * (int)g.pitch + (j + g.ng));
+}
+
+template <class X>
+__device__ __forceinline__ X ld32(const X *base, unsigned i) {
+  return *reinterpret_cast<const X *>(reinterpret_cast<const char *>(base) + i * (unsigned)sizeof(X));
+}
+
+template <class X>
+__device__ __forceinline__ void st32(X *base, unsigned i, X v) {
+  *reinterpret_cast<X *>(reinterpret_cast<char *>(base) + i * (unsigned)sizeof(X)) = v;
+}
+
+__device__ __forceinline__ double mval32(const MetK &m, int f, unsigned i) {
+  return m.f[f] ? ld32(m.f[f], i) : m.c[f];
+}
+
 template <class T> __device__ __forceinline__ T tsqrt(T x) { return sqrt(x); }
 template <> __device__ __forceinline__ float tsqrt<float>(float x) { return sqrtf(x); }
 
@@ -450,6 +472,12 @@ __device__ __forceinline__ void store_corrected(const double *qq, const double *
                                                 long long i) {
   for (int c = 0; c < 5; c++)
     if (__double_as_longlong(qq[c]) != __double_as_longlong(q0[c])) q[c][i] = qq[c];
+}
+
+__device__ __forceinline__ void store_corrected(const double *qq, const double *q0, double *const *q,
+                                                unsigned i) {
+  for (int c = 0; c < 5; c++)
+    if (__double_as_longlong(qq[c]) != __double_as_longlong(q0[c])) st32(q[c], i, qq[c]);
 }
 
 // ------------------------------------------------ reconstruction (II.C.2)

@@ -29,6 +29,9 @@ inline int check_grid(const grhd_grid *g) {
   if (g->ng != 3) return fail(GRHD_ERR_INVALID, "ng must be 3 (got %d)", g->ng);
   if (g->pitch < (int64_t)g->nx + 2 * g->ng)
     return fail(GRHD_ERR_INVALID, "pitch %lld < nx + 2 ng", (long long)g->pitch);
+  if ((int64_t)(g->nz + 2 * g->ng) * g->pitch > ((int64_t)1 << 29))
+    return fail(GRHD_ERR_INVALID, "a field holds at most 2^29 cells ((nz + 2 ng) pitch = %lld)",
+                (long long)((int64_t)(g->nz + 2 * g->ng) * g->pitch));
   if (!(g->dx > 0.0) || !(g->dz > 0.0) || !std::isfinite(g->dx) || !std::isfinite(g->dz))
     return fail(GRHD_ERR_INVALID, "dx, dz must be finite and > 0");
   if (g->geom != GRHD_GEOM_CYLINDRICAL && g->geom != GRHD_GEOM_CARTESIAN)

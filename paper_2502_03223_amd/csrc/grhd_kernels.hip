@@ -119,18 +119,18 @@ k_con2prim(GridK g, EosK e, C2PK cp, MetK m, Q5 q, P6 p, uint8_t *flags, C2PPart
   unsigned fl = 0;
   int iters = 0;
   if (act) {
-    long long i = cell_index(g, j, k);
-    double W = mval(m, GRHD_M_W, i);
+    const unsigned i = cell_idx32(g, j, k);
+    double W = mval32(m, GRHD_M_W, i);
     double gtu[6];
     if (MC == MC_GEN) {
       double gt[6];
-      for (int t = 0; t < 6; t++) gt[t] = mval(m, GRHD_M_GXX + t, i);
+      for (int t = 0; t < 6; t++) gt[t] = mval32(m, GRHD_M_GXX + t, i);
       inv_sym3(gt, gtu);
     }
     double qq[5], pp[6];
-    for (int c = 0; c < 5; c++) qq[c] = q.q[c][i];
+    for (int c = 0; c < 5; c++) qq[c] = ld32(q.q[c], i);
     // flag of the last recovery into p (reuse_atm implies caller flags)
-    const unsigned old = cp.reuse_atm ? flags[i] : 0u;
+    const unsigned old = cp.reuse_atm ? (unsigned)ld32(flags, i) : 0u;
     double q0[5] = {qq[0], qq[1], qq[2], qq[3], qq[4]};
     double x = g.x0 + (j + 0.5) * g.dx;
     C2PResult r = con2prim_cell<MC, EK>(e, cp, W, gtu, x, g.geom, qq, pp, -1.0);
@@ -139,8 +139,8 @@ k_con2prim(GridK g, EosK e, C2PK cp, MetK m, Q5 q, P6 p, uint8_t *flags, C2PPart
     if (fl) store_corrected(qq, q0, q.q, i);
     // a cell that was and stays atmosphere already holds its primitives
     if (!(old & fl & GRHD_FLAG_ATM))
-      for (int c = 0; c < 6; c++) p.p[c][i] = pp[c];
-    if (flags) flags[i] = (uint8_t)fl;
+      for (int c = 0; c < 6; c++) st32(p.p[c], i, pp[c]);
+    if (flags) st32(flags, i, (uint8_t)fl);
   }
   if (part)
     c2p_block_partial<256>(act && jin && kin, fl, iters, &part[blockIdx.y * gridDim.x + blockIdx.x], red);

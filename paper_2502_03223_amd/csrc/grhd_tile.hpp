@@ -150,7 +150,7 @@ struct C2PAcc {
 // q_out written, so that the next stage needs no recovery pass of its own.
 // W, gt: metric at the cell.  Without CHAIN the caller stores v itself.
 template <int MC, int EK, bool CHAIN>
-__device__ __forceinline__ void finish_cell(const PatchK &P, const EosK &e, long long ic, double W,
+__device__ __forceinline__ void finish_cell(const PatchK &P, const EosK &e, unsigned ic, double W,
                                             const double *gt, double xc, double dV, double *v,
                                             double &mb, double &jm, C2PAcc &acc) {
   if (!CHAIN) return;  // stored by the caller as they were computed
@@ -160,10 +160,10 @@ __device__ __forceinline__ void finish_cell(const PatchK &P, const EosK &e, long
     double pp[6];
     C2PResult r = con2prim_cell<MC, EK>(e, P.cp, W, gtu, xc, P.g.geom, v, pp, -1.0);
     // a cell that was and stays atmosphere already holds its primitives
-    const bool keep = P.cp.reuse_atm && (r.flags & GRHD_FLAG_ATM) && (P.flags_out[ic] & GRHD_FLAG_ATM);
+    const bool keep = P.cp.reuse_atm && (r.flags & GRHD_FLAG_ATM) && (ld32(P.flags_out, ic) & GRHD_FLAG_ATM);
     if (!keep)
-      for (int c = 0; c < 6; c++) P.po[c][ic] = pp[c];
-    P.flags_out[ic] = (uint8_t)r.flags;
+      for (int c = 0; c < 6; c++) st32(P.po[c], ic, pp[c]);
+    st32(P.flags_out, ic, (uint8_t)r.flags);
     acc.n[0] += (r.flags & GRHD_FLAG_RESCALE) ? 1 : 0;
     acc.n[1] += (r.flags & GRHD_FLAG_COLD) ? 1 : 0;
     acc.n[2] += (r.flags & GRHD_FLAG_ATM) ? 1 : 0;
@@ -171,7 +171,7 @@ __device__ __forceinline__ void finish_cell(const PatchK &P, const EosK &e, long
     acc.n[4] += (unsigned long long)r.iters;
     if ((unsigned long long)r.iters > acc.n[5]) acc.n[5] = (unsigned long long)r.iters;
   }
-  for (int m = 0; m < 5; m++) P.qo[m][ic] = v[m];
+  for (int m = 0; m < 5; m++) st32(P.qo[m], ic, v[m]);
   mb += v[0] * dV;
   jm += v[2] * dV;
 }
@@ -210,7 +210,7 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
     // (no boundary map, no parities)
     const bool inner = j0 >= 3 && j0 + TX + 3 <= nx && k0 >= 3 && k0 + TZ + 3 <= nz;
     const bool have_flags = P.flags != nullptr;
-    long long src[LPT], im[LPT];
+    unsigned src[LPT], im[LPT];
     bool use[LPT], fin[LPT];
     double s0[LPT], s1[LPT], s2[LPT];
 #pragma unroll
@@ -233,8 +233,8 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
       // recovery flags exist for grid cells only (an EXTERNAL ghost maps
       // to itself and counts as not atmosphere)
       fin[i] = inner || (js >= 0 && js < nx && ks >= 0 && ks < nz);
-      src[i] = need ? cell_index(g, js, ks) : 0;
-      im[i] = need ? cell_index(g, j, k) : 0;
+      src[i] = need ? cell_idx32(g, js, ks) : 0u;
+      im[i] = need ? cell_idx32(g, j, k) : 0u;
       s0[i] = sg[0]; s1[i] = sg[1]; s2[i] = sg[2];
     }
     double va[LPT], vw[LPT];
@@ -242,10 +242,10 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
 #pragma unroll
     for (int i = 0; i < LPT; i++) {
       if (use[i]) {
-        fl[i] = (have_flags && fin[i]) ? P.flags[src[i]] : (uint8_t)0;
+        fl[i] = (have_flags && fin[i]) ? ld32(P.flags, src[i]) : (uint8_t)0;
         if (MC == MC_CF) {
-          va[i] = P.m.f[GRHD_M_ALP] ? P.m.f[GRHD_M_ALP][im[i]] : P.m.c[GRHD_M_ALP];
-          vw[i] = P.m.f[GRHD_M_W] ? P.m.f[GRHD_M_W][im[i]] : P.m.c[GRHD_M_W];
+          va[i] = mval32(P.m, GRHD_M_ALP, im[i]);
+          vw[i] = mval32(P.m, GRHD_M_W, im[i]);
         }
       }
     }
@@ -269,7 +269,7 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
 #pragma unroll
       for (int i = 0; i < LPT; i++)
         if (use[i])
-          for (int f = 0; f < 6; f++) v[i][f] = P.p[f][src[i]];
+          for (int f = 0; f < 6; f++) v[i][f] = ld32(P.p[f], src[i]);
 #pragma unroll
       for (int i = 0; i < LPT; i++) {
         int c = tid + i * NT;
@@ -454,14 +454,14 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
     int jj = c % TX, kk = c / TX;
     int j = j0 + jj, k = k0 + kk;
     if (!(c < TX * TZ && j >= 0 && j < nx && k < nz)) continue;
-    long long ic = cell_index(g, j, k);
+    const unsigned ic = cell_idx32(g, j, k);
     // state loads first: their latency overlaps the flux arithmetic below
     double qs5[5], qn5[5], ai5[5];
-    for (int m = 0; m < 5; m++) qs5[m] = P.qs[m][ic];
+    for (int m = 0; m < 5; m++) qs5[m] = ld32(P.qs[m], ic);
     if (P.use_qn)
-      for (int m = 0; m < 5; m++) qn5[m] = P.qn[m][ic];
+      for (int m = 0; m < 5; m++) qn5[m] = ld32(P.qn[m], ic);
     if (P.use_acc_in)
-      for (int m = 0; m < 5; m++) ai5[m] = P.acc_in[m][ic];
+      for (int m = 0; m < 5; m++) ai5[m] = ld32(P.acc_in[m], ic);
     const int lc = (kk + 3) * HX + (jj + 3);
     double xc = g.x0 + (j + 0.5) * g.dx;
     const double xl = g.x0 + j * g.dx, xr = g.x0 + (j + 1) * g.dx;
@@ -491,11 +491,11 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
       for (int i = 0; i < GRHD_NMET; i++) {
         const double *src = P.m.f[i];
         if (!src) { gm[i] = P.m.c[i]; dg[i] = 0.0; dg[GRHD_NMET + i] = 0.0; continue; }
-        gm[i] = src[ic];
+        gm[i] = ld32(src, ic);
         double a7[7];
-        for (int t = 0; t < 7; t++) a7[t] = src[ic - 3 + t];
+        for (int t = 0; t < 7; t++) a7[t] = ld32(src, ic - 3u + (unsigned)t);
         dg[i] = deriv6(a7, i60dx);
-        for (int t = 0; t < 7; t++) a7[t] = src[ic + (t - 3) * g.pitch];
+        for (int t = 0; t < 7; t++) a7[t] = ld32(src, ic + (unsigned)((t - 3) * (int)g.pitch));
         dg[GRHD_NMET + i] = deriv6(a7, i60dz);
       }
     }
@@ -517,7 +517,7 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
       } else if (sizeof(T) == sizeof(double)) {
         for (int i = 0; i < 6; i++) pc[i] = (double)sm.p[i][lc];  // own cells: no parity flip
       } else {
-        for (int i = 0; i < 6; i++) pc[i] = P.p[i][ic];
+        for (int i = 0; i < 6; i++) pc[i] = ld32(P.p[i], ic);
       }
       double divx[5], divz[5];
       for (int m = 0; m < 5; m++) {
@@ -560,14 +560,14 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
       if (P.use_qn) v[m] += P.a * qn5[m];
       if (P.use_acc_in) v[m] += P.gdt * ai5[m];
       if (!CHAIN) {
-        P.qo[m][ic] = v[m];
+        st32(P.qo[m], ic, v[m]);
         if (m == 0) mb += v[m] * dV;
         if (m == 2) jm += v[m] * dV;
       }
       if (P.use_acc_out) {
         double av = P.e * L[m];
         if (P.use_acc_in) av += P.d * ai5[m];
-        P.acc_out[m][ic] = av;
+        st32(P.acc_out[m], ic, av);
       }
     }
     finish_cell<MC, EK, CHAIN>(P, e, ic, gm[GRHD_M_W], gm + GRHD_M_GXX, xc, dV, v, mb, jm, acc);
