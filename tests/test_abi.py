@@ -63,6 +63,7 @@ def call_substep(G, grid=None, eos=None, opts=None, stage=None, null_q=False):
     dict(grid=dict(grid_ok(), ng=2)),
     dict(grid=dict(grid_ok(), dx=-1.0)),
     dict(grid=dict(grid_ok(), pitch=10)),
+    dict(grid=dict(grid_ok(), nz=8192, pitch=65536)),     # more than 2^29 cells per field
     dict(grid=dict(grid_ok(), bc=("outflow", "axis", "reflect", "outflow"))),
     dict(grid=dict(grid_ok(), bc=("periodic", "outflow", "reflect", "outflow"))),
     dict(grid=dict(grid_ok(), x0=-1.0)),
