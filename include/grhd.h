@@ -130,7 +130,9 @@ typedef struct {
 typedef struct {
   int recon, riemann, prec;   /* GRHD_RECON_*, GRHD_RIEMANN_*, GRHD_PREC_* */
   grhd_c2p_params c2p;
-  int tile_x, tile_z;         /* 0, 0 = library default */
+  int tile_x, tile_z;         /* 0, 0 = library default (16 x 16; 16 x 8
+                                 on grids of fewer than 1536 such tiles,
+                                 128 for the general metric class) */
   void *ev_begin, *ev_end;    /* optional events from grhd_event_create,
                                  recorded on the stream right before and
                                  right after the fused stage kernel of

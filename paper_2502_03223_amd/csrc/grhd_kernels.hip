@@ -679,11 +679,17 @@ extern "C" int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos, const
                        opts->riemann, pk)))
     return rc;
   // default 16 x 16: the smallest halo per cell of the built shapes, and
-  // the FP64 instance fits three workgroups per CU in LDS
+  // the FP64 instance fits three workgroups per CU in LDS; grids of few
+  // such tiles take 16 x 8 (twice the workgroups, half the length of the
+  // slowest tile): under 1536 tiles for the conformally flat class, under
+  // 128 for the general one, whose 16 x 8 instance holds fewer waves
   int shape = 3;
   if (opts->tile_x || opts->tile_z) {
     shape = shape_index(opts->tile_x, opts->tile_z);
     if (shape < 0) return fail(GRHD_ERR_UNSUPPORTED, "tile %dx%d not built", opts->tile_x, opts->tile_z);
+  } else {
+    const long long t16 = (long long)((grid->nx + 15) / 16) * ((grid->nz + 15) / 16);
+    if (t16 < (metric_class(metric) == MC_CF ? 1536 : 128)) shape = shape_index(16, 8);
   }
   int tx, tz;
   shape_of(shape, &tx, &tz);
