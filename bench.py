@@ -545,24 +545,24 @@ def bondi_form(args):
         g = synth.make_grid(n, n, 0.0, 0.0, d, d, "cyl", ("axis", "external", "reflect", "external"))
         p, m, eos, frozen = synth.bondi_problem(g)
         md = {k: torch.from_numpy(v).to(dev) for k, v in m.items()}
-        sub = grhd.Substep(g, eos, md, dict(recon=recon, riemann="hllc", prec="fp64", c2p=c2p))
         pd = torch.from_numpy(p).to(dev)
         q = torch.zeros((5,) + p.shape[1:], dtype=torch.float64, device=dev)
         grhd.prim2con(g, eos, md, pd, q, with_ghosts=True)
         qfix, q1, q2 = q.clone(), q.clone(), q.clone()
         mask = torch.from_numpy(frozen.astype(np.uint8)).to(dev)
+        # the inner region is held inside each stage (no separate pass)
+        sub = grhd.Substep(g, eos, md, dict(recon=recon, riemann="hllc", prec="fp64", c2p=c2p,
+                                            fix=(mask, qfix)))
         pw = torch.zeros_like(pd)
         dt = 0.4 * d
         nsteps = int(round(20.0 / dt))
         calls = [sub.bind(dict(grhd.SSPRK3[s], dt=dt), qn, qs, qo, pw)
                  for s, (qn, qs, qo) in enumerate([(q, q, q1), (q, q1, q2), (q, q2, q)])]
-        outs = [q1, q2, q]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(nsteps):
-            for c, qo in zip(calls, outs):
+            for c in calls:
                 c()
-                grhd.fix_cells(g, mask, qfix, qo)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         grhd.con2prim(g, eos, md, c2p, q.clone(), pw)
@@ -599,24 +599,22 @@ def run_bondi(grid, p, m, eos, frozen, opts, t_end):
     from paper_2502_03223_amd import grhd
     dev = torch.device("cuda:0")
     md = {k: torch.from_numpy(v).to(dev) for k, v in m.items()}
-    sub = grhd.Substep(grid, eos, md, opts)
     pd = torch.from_numpy(p).to(dev)
     q = torch.zeros((5,) + p.shape[1:], dtype=torch.float64, device=dev)
     grhd.prim2con(grid, eos, md, pd, q, with_ghosts=True)
     qfix, q1, q2 = q.clone(), q.clone(), q.clone()
     mask = torch.from_numpy(frozen.astype(np.uint8)).to(dev)
+    sub = grhd.Substep(grid, eos, md, dict(opts, fix=(mask, qfix)))
     pw = torch.zeros_like(pd)
     dt = 0.4 * grid["dx"]
     nsteps = int(round(t_end / dt))
     calls = [sub.bind(dict(grhd.SSPRK3[s], dt=dt), qn, qs, qo, pw)
              for s, (qn, qs, qo) in enumerate([(q, q, q1), (q, q1, q2), (q, q2, q)])]
-    outs = [q1, q2, q]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(nsteps):
-        for c, qo in zip(calls, outs):
+        for c in calls:
             c()
-            grhd.fix_cells(grid, mask, qfix, qo)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     grhd.con2prim(grid, eos, md, opts["c2p"], q.clone(), pw)

@@ -133,6 +133,14 @@ typedef struct {
   int tile_x, tile_z;         /* 0, 0 = library default (16 x 16; 16 x 8
                                  on grids of fewer than 1536 such tiles,
                                  128 for the general metric class) */
+  const uint8_t *fix_mask;    /* optional interior boundary condition
+                                 (nullable; grhd_rk_substep and
+                                 grhd_rk_substep_chained): on interior
+                                 cells whose mask byte (cell array, layout
+                                 of q) is nonzero the stage stores
+                                 fix_q instead of its update, as
+                                 grhd_fix_cells after the stage would */
+  grhd_cons fix_q;
   void *ev_begin, *ev_end;    /* optional events from grhd_event_create,
                                  recorded on the stream right before and
                                  right after the fused stage kernel of

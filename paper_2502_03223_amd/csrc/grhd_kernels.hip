@@ -639,6 +639,8 @@ int fill_patch(const grhd_grid *grid, const grhd_metric *metric, const grhd_rk_s
   }
   for (int c = 0; c < 6; c++) pk.p[c] = p->p[c];
   pk.flux_reg = flux_reg;
+  pk.fix_mask = nullptr;
+  for (int c = 0; c < 5; c++) pk.fix_q[c] = nullptr;
   pk.a = stage->a; pk.b = stage->b; pk.cdt = stage->c * stage->dt;
   pk.gdt = stage->g * stage->dt; pk.d = stage->d; pk.e = stage->e; pk.dt = stage->dt;
   pk.cx = stage->dt / grid->dx; pk.cz = stage->dt / grid->dz;
@@ -665,6 +667,16 @@ int fill_patch(const grhd_grid *grid, const grhd_metric *metric, const grhd_rk_s
 }
 }  // namespace grhd
 
+// the optional interior boundary condition of grhd_options
+static int set_fixed(const grhd_options *opts, PatchK &pk) {
+  if (!opts->fix_mask) return GRHD_OK;
+  int rc;
+  if ((rc = check_cons(&opts->fix_q, "fix_q"))) return rc;
+  pk.fix_mask = opts->fix_mask;
+  for (int c = 0; c < 5; c++) pk.fix_q[c] = opts->fix_q.q[c];
+  return GRHD_OK;
+}
+
 extern "C" int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos, const grhd_metric *metric,
                                const grhd_options *opts, const grhd_rk_stage *stage,
                                const grhd_cons *qn, const grhd_cons *qs, const grhd_cons *qout,
@@ -678,6 +690,7 @@ extern "C" int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos, const
   if ((rc = fill_patch(grid, metric, stage, qn, qs, qout, p, acc_in, acc_out, flux_reg, opts->recon,
                        opts->riemann, pk)))
     return rc;
+  if ((rc = set_fixed(opts, pk))) return rc;
   // default 16 x 16: the smallest halo per cell of the built shapes, and
   // the FP64 instance fits three workgroups per CU in LDS; grids of few
   // such tiles take 16 x 8 (twice the workgroups, half the length of the
@@ -749,6 +762,7 @@ extern "C" int grhd_rk_substep_chained(const grhd_grid *grid, const grhd_eos *eo
   if ((rc = fill_patch(grid, metric, stage, qn, qs, qout, p_in, acc_in, acc_out, flux_reg, opts->recon,
                        opts->riemann, pk)))
     return rc;
+  if ((rc = set_fixed(opts, pk))) return rc;
   if ((rc = check_prim(p_out, "p_out"))) return rc;
   if (!flags_out) return fail(GRHD_ERR_INVALID, "flags_out is NULL");
   if (flags_in && flags_in == flags_out) return fail(GRHD_ERR_INVALID, "flags_out must not alias flags_in");

@@ -37,6 +37,10 @@ struct PatchK {
   double *reg[2];
   int reg_j[2], reg_k[2];
   double reg_w;
+  // interior boundary condition (nullable): cells with a nonzero mask
+  // byte store fix_q instead of their update
+  const uint8_t *fix_mask;
+  const double *fix_q[5];
   int tiles_x, tiles_z;
   int xshift;  // tile tx covers cells j in [tx TX - xshift, (tx + 1) TX - xshift)
   long long tile_base;
@@ -554,11 +558,13 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
       for (int m = 0; m < 5; m++) L[m] = s[m] - divx[m] - divz[m];
     }
     double dV = cyl ? 2.0 * M_PI * xc * g.dx * g.dz : g.dx * g.dz;
+    const bool fixed = P.fix_mask && ld32(P.fix_mask, ic);
     double v[5];
     for (int m = 0; m < 5; m++) {
       v[m] = P.b * qs5[m] + P.cdt * L[m];
       if (P.use_qn) v[m] += P.a * qn5[m];
       if (P.use_acc_in) v[m] += P.gdt * ai5[m];
+      if (fixed) v[m] = ld32(P.fix_q[m], ic);
       if (!CHAIN) {
         st32(P.qo[m], ic, v[m]);
         if (m == 0) mb += v[m] * dV;

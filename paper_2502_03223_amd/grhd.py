@@ -72,6 +72,7 @@ class C2PParams(C.Structure):
 class Options(C.Structure):
     _fields_ = [("recon", C.c_int), ("riemann", C.c_int), ("prec", C.c_int),
                 ("c2p", C2PParams), ("tile_x", C.c_int), ("tile_z", C.c_int),
+                ("fix_mask", C.c_void_p), ("fix_q", Cons),
                 ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p)]
 
 
@@ -251,6 +252,10 @@ def make_options(o):
     s.c2p = make_c2p(o["c2p"])
     tile = o.get("tile", (0, 0))
     s.tile_x, s.tile_z = tile
+    fix = o.get("fix")
+    if fix is not None:   # (mask uint8 cell tensor, q_fixed)
+        s.fix_mask = fix[0].data_ptr()
+        s.fix_q = make_cons(fix[1])
     ev = o.get("events")
     if ev is not None:
         s.ev_begin, s.ev_end = ev[0].handle, ev[1].handle
