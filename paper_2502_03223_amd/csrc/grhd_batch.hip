@@ -79,8 +79,17 @@ k_con2prim_batch(const PatchK *__restrict__ pt, const EosK *__restrict__ eos, C2
 // (dealt workgroups round-robin) each take every 8th item of every patch.
 // Two tile shapes share the LDS: thin patches (nz <= 8) use AX x AZ, the
 // others BX x BZ.  Each item writes one diagnostic record.
+// Waves per SIMD the registers must allow: with both shapes 16 cells wide
+// (16 x 16 or 16 x 8) the LDS of the conformally flat class fits three
+// workgroups per CU in FP64 and four in FP32, as in the single-patch kernel.
 template <class T, int MC, int AX, int AZ, int BX, int BZ>
-__global__ void __launch_bounds__(NT)
+constexpr int batch_waves() {
+  constexpr bool narrow = AX == 16 && BX == 16 && (AZ == 8 || AZ == 16) && (BZ == 8 || BZ == 16);
+  return (MC == MC_CF && narrow) ? (sizeof(T) == 8 ? 3 : 4) : 1;
+}
+
+template <class T, int MC, int AX, int AZ, int BX, int BZ>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(batch_waves<T, MC, AX, AZ, BX, BZ>())))
 k_batch(const PatchK *__restrict__ pt, const EosK *__restrict__ eos,
         const long long *__restrict__ tile_prefix, int npatch, FluxPart *part2) {
   __shared__ double red[NT / 64][3];
@@ -110,9 +119,11 @@ k_batch(const PatchK *__restrict__ pt, const EosK *__restrict__ eos,
 
 using BatchFn = void (*)(const PatchK *, const EosK *, const long long *, int, FluxPart *);
 
-// thin-patch shapes (nz <= 8) and square-patch shapes
-static const int kThin[2][2] = {{64, 8}, {32, 8}};
-static const int kSquare[4][2] = {{32, 8}, {32, 16}, {64, 8}, {16, 16}};
+// thin-patch shapes (nz <= 8) and square-patch shapes (indices are kept
+// in tune caches: new shapes go at the end)
+static const int kThin[3][2] = {{64, 8}, {32, 8}, {16, 8}};
+static const int kSquare[5][2] = {{32, 8}, {32, 16}, {64, 8}, {16, 16}, {16, 8}};
+static const int kNumThin = 3, kNumSquare = 5;
 
 template <class T, int MC, int AX, int AZ>
 static BatchFn pick_b(int b) {
@@ -120,13 +131,14 @@ static BatchFn pick_b(int b) {
     case 0: return k_batch<T, MC, AX, AZ, 32, 8>;
     case 1: return k_batch<T, MC, AX, AZ, 32, 16>;
     case 2: return k_batch<T, MC, AX, AZ, 64, 8>;
-    default: return k_batch<T, MC, AX, AZ, 16, 16>;
+    case 3: return k_batch<T, MC, AX, AZ, 16, 16>;
+    default: return k_batch<T, MC, AX, AZ, 16, 8>;
   }
 }
 
 template <class T, int MC>
 static BatchFn pick_ab(int a, int b) {
-  return a == 0 ? pick_b<T, MC, 64, 8>(b) : pick_b<T, MC, 32, 8>(b);
+  return a == 0 ? pick_b<T, MC, 64, 8>(b) : a == 1 ? pick_b<T, MC, 32, 8>(b) : pick_b<T, MC, 16, 8>(b);
 }
 
 static BatchFn batch_kernel(int prec, int mc, int a, int b) {
@@ -322,8 +334,8 @@ bool cache_lookup(const char *path, const std::string &key, int *a, int *b) {
   while (fgets(line, sizeof(line), f)) {
     char k[400];
     int ia, ib;
-    if (sscanf(line, "%399s %d %d", k, &ia, &ib) == 3 && key == k && ia >= 0 && ia < 2 && ib >= 0 &&
-        ib < 4) {
+    if (sscanf(line, "%399s %d %d", k, &ia, &ib) == 3 && key == k && ia >= 0 && ia < kNumThin && ib >= 0 &&
+        ib < kNumSquare) {
       *a = ia;
       *b = ib;
       found = true;
@@ -435,23 +447,21 @@ extern "C" int grhd_plan_create(const grhd_patch *patches, int npatch, const grh
   bool have_thin = false, have_sq = false;
   for (int i = 0; i < npatch; i++) (pl->nz[i] <= 8 ? have_thin : have_sq) = true;
   if (opts->tile_x || opts->tile_z) {
-    for (int i = 0; i < 4; i++)
+    for (int i = 0; i < kNumSquare; i++)
       if (kSquare[i][0] == opts->tile_x && kSquare[i][1] == opts->tile_z) b = i;
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < kNumThin; i++)
       if (kThin[i][0] == opts->tile_x && kThin[i][1] == opts->tile_z) a = i;
   } else if (!cache_lookup(tune_cache, key, &a, &b)) {
+    // every (thin, square) pair: the kernel's LDS and registers are those
+    // of both shapes together, so one shape's best depends on the other
     double best = 1e30;
     int ba = 0, bb = 0;
-    for (int ib = 0; ib < (have_sq ? 4 : 1); ib++) {
-      if ((rc = set_shapes(pl, 0, ib, patches))) { destroy_plan(pl); return rc; }
-      double ms = time_plan(pl, patches, 5);
-      if (ms < best) { best = ms; bb = ib; }
-    }
-    for (int ia = 1; ia < (have_thin ? 2 : 1); ia++) {
-      if ((rc = set_shapes(pl, ia, bb, patches))) { destroy_plan(pl); return rc; }
-      double ms = time_plan(pl, patches, 5);
-      if (ms < best) { best = ms; ba = ia; }
-    }
+    for (int ia = 0; ia < (have_thin ? kNumThin : 1); ia++)
+      for (int ib = 0; ib < (have_sq ? kNumSquare : 1); ib++) {
+        if ((rc = set_shapes(pl, ia, ib, patches))) { destroy_plan(pl); return rc; }
+        double ms = time_plan(pl, patches, 5);
+        if (ms < best) { best = ms; ba = ia; bb = ib; }
+      }
     a = ba;
     b = bb;
     cache_store(tune_cache, key, a, b, best);

@@ -110,6 +110,7 @@ def test_batch_tune_cache_roundtrip(orc, tmp_path):
     fresh = str(tmp_path / "fresh.txt")
     t3 = grhd.autotune(desc, eos_table, opts, tune_cache=fresh)
     assert len(open(fresh).read().splitlines()) == 1
-    assert t3["thin"][1] == 8 and t3["square"] in [(32, 8), (32, 16), (64, 8), (16, 16)]
+    assert t3["thin"] in [(64, 8), (32, 8), (16, 8)]
+    assert t3["square"] in [(32, 8), (32, 16), (64, 8), (16, 16), (16, 8)]
     # explicit shapes pass through
     assert grhd.autotune(desc, eos_table, dict(opts, tile=(32, 16)))["square"] == (32, 16)
