@@ -48,10 +48,15 @@ def alloc(pt):
     return dict(q=q, q1=torch.zeros_like(q), p=torch.zeros((6,) + q.shape[1:], dtype=torch.float64, device=DEV))
 
 
+@pytest.mark.parametrize("tile", [None, (16, 8)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_batch_equals_single_patch(orc, prec):
+def test_batch_equals_single_patch(orc, prec, tile):
+    """tile None: the tuner's choice; (16, 8): that shape for thin and
+    square patches alike (and for the single-patch calls)."""
     patches, eos_table = build_patches(orc)
     opts = dict(recon="ppm", riemann="hllc", prec=prec, c2p=dict(w_max=100.0, rho_atm=1e-10))
+    if tile is not None:
+        opts["tile"] = tile
     A = [alloc(pt) for pt in patches]     # batched
     B = [alloc(pt) for pt in patches]     # one call per patch
 
@@ -85,6 +90,8 @@ def test_batch_equals_single_patch(orc, prec):
         assert d["n_atm"] > 0 and d["Mb"] > 0.0
     t = plan.tiles()
     assert t["thin"][1] == 8
+    if tile is not None:
+        assert t["thin"] == tile and t["square"] == tile
     plan.close()
 
 
