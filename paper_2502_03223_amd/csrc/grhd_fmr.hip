@@ -148,6 +148,81 @@ k_fmr_prolong(GridK pg, SliceK S, GridK cg, MetK cm, EosK e, P6 cp, Q5 cq) {
   }
 }
 
+// A level stage's recovery with the prolongation of the level's EXTERNAL
+// ghost cells in one launch.  Workgroups [0, nrec) recover the interior
+// rows (256 cells each, row k = b / segs); the others take 32 ghost cells
+// each (8 x 32 threads, fields 0-5 on the first six groups), prolong them
+// as k_fmr_prolong does, form the conserved values and recover them in
+// registers as the recovery launch would from memory: the same results as
+// the two launches, without the second one.
+constexpr int PREP_THREADS = 256;
+
+template <int MC, int EK>
+__global__ void __launch_bounds__(PREP_THREADS)
+k_fmr_prep(GridK pg, SliceK S, GridK cg, MetK cm, EosK e, C2PK cp, P6 pp, Q5 qq, uint8_t *flags, int segs,
+           int nrec) {
+#pragma clang fp contract(off)
+  __shared__ double spf[6][PRO_CELLS];
+  const int b = blockIdx.x;
+  if (b < nrec) {
+    const int k = b / segs;
+    const int j = (b % segs) * PREP_THREADS + threadIdx.x;
+    if (j >= cg.nx) return;
+    const long long i = cell_index(cg, j, k);
+    const double W = mval(cm, GRHD_M_W, i);
+    double gtu[6];
+    if (MC == MC_GEN) {
+      double gt[6];
+      for (int t = 0; t < 6; t++) gt[t] = mval(cm, GRHD_M_GXX + t, i);
+      inv_sym3(gt, gtu);
+    }
+    double q[5], p[6];
+    for (int c = 0; c < 5; c++) q[c] = qq.q[c][i];
+    const double q0[5] = {q[0], q[1], q[2], q[3], q[4]};
+    const C2PResult r = con2prim_cell<MC, EK>(e, cp, W, gtu, cg.x0 + (j + 0.5) * cg.dx, cg.geom, q, p, -1.0);
+    if (r.flags) store_corrected(q, q0, qq.q, i);
+    for (int c = 0; c < 6; c++) pp.p[c][i] = p[c];
+    if (flags) flags[i] = (uint8_t)r.flags;
+    return;
+  }
+  const int f = threadIdx.x / PRO_CELLS, cl = threadIdx.x % PRO_CELLS;
+  int jf = 0, kf = 0;
+  const bool act = ghost_cell(cg, (long long)(b - nrec) * PRO_CELLS + cl, jf, kf);
+  if (act && f < 6) {
+    const int jc = (jf >= 0) ? jf / 2 : -((1 - jf) / 2);
+    const int kc = (kf >= 0) ? kf / 2 : -((1 - kf) / 2);
+    const double ox = (cg.x0 + (jf + 0.5) * cg.dx) - (pg.x0 + (jc + 0.5) * pg.dx);
+    const double oz = (cg.z0 + (kf + 0.5) * cg.dz) - (pg.z0 + (kc + 0.5) * pg.dz);
+    const double a = parent_prim(pg, S, f, jc, kc);
+    const double xp = parent_prim(pg, S, f, jc + 1, kc), xm = parent_prim(pg, S, f, jc - 1, kc);
+    const double zp = parent_prim(pg, S, f, jc, kc + 1), zm = parent_prim(pg, S, f, jc, kc - 1);
+    const double sx = minmod2(xp - a, a - xm) / pg.dx;
+    const double sz = minmod2(zp - a, a - zm) / pg.dz;
+    spf[f][cl] = a + sx * ox + sz * oz;
+  }
+  __syncthreads();
+  if (f == 0 && act) {
+    const long long i = cell_index(cg, jf, kf);
+    double pf[6];
+    for (int c = 0; c < 6; c++) pf[c] = spf[c][cl];
+    const double W = mval(cm, GRHD_M_W, i);
+    double gtu[6];
+    if (MC == MC_GEN) {
+      double gt[6];
+      for (int t = 0; t < 6; t++) gt[t] = mval(cm, GRHD_M_GXX + t, i);
+      inv_sym3(gt, gtu);
+    }
+    const double x = cg.x0 + (jf + 0.5) * cg.dx;
+    double q[5], p[6];
+    prim2con_cell<MC>(W, gtu, x, cg.geom, pf, q);
+    // q is now what the prolongation stores; the recovery corrects it
+    const C2PResult r = con2prim_cell<MC, EK>(e, cp, W, gtu, x, cg.geom, q, p, -1.0);
+    for (int c = 0; c < 5; c++) qq.q[c][i] = q[c];
+    for (int c = 0; c < 6; c++) pp.p[c][i] = p[c];
+    if (flags) flags[i] = (uint8_t)r.flags;
+  }
+}
+
 __device__ __forceinline__ double cell_volume(const GridK &g, int j) {
   return (g.geom == GRHD_GEOM_CYLINDRICAL) ? 2.0 * M_PI * (g.x0 + (j + 0.5) * g.dx) * g.dx * g.dz
                                            : g.dx * g.dz;
@@ -274,6 +349,36 @@ static int prolong(const grhd_grid *pg, const SliceK &S, const grhd_grid *cg,
   else
     hipLaunchKernelGGL(k_fmr_prolong<MC_CF>, grid, block, 0, st, P, S, Cg, to_metk(cm), e, pp, qq);
   return launch_status("fmr prolong");
+}
+
+// recovery of a child level's q_s with its ghost cells prolonged from the
+// parent slices S (k_fmr_prep)
+static int prep(const grhd_grid *pg, const SliceK &S, const grhd_level &L, const EosK &e, const C2PK &cp,
+                const Q5 &q, const P6 &p, uint8_t *flags, int mc, hipStream_t st) {
+  const GridK P = to_gridk(pg), Cg = to_gridk(&L.grid);
+  const int segs = (Cg.nx + PREP_THREADS - 1) / PREP_THREADS;
+  const long long nrec = (long long)segs * Cg.nz;
+  const long long npro = (prolong_count(Cg) + PRO_CELLS - 1) / PRO_CELLS;
+  if (nrec + npro >= (1LL << 31)) return fail(GRHD_ERR_UNSUPPORTED, "level too large");
+  const dim3 grid((unsigned)(nrec + npro)), block(PREP_THREADS);
+  const MetK m = to_metk(&L.metric);
+  const bool ideal = e.kind == GRHD_EOS_IDEAL;
+  if (mc == MC_GEN) {
+    if (ideal)
+      hipLaunchKernelGGL((k_fmr_prep<MC_GEN, GRHD_EOS_IDEAL>), grid, block, 0, st, P, S, Cg, m, e, cp, p, q, flags,
+                         segs, (int)nrec);
+    else
+      hipLaunchKernelGGL((k_fmr_prep<MC_GEN, GRHD_EOS_HYBRID>), grid, block, 0, st, P, S, Cg, m, e, cp, p, q,
+                         flags, segs, (int)nrec);
+  } else {
+    if (ideal)
+      hipLaunchKernelGGL((k_fmr_prep<MC_CF, GRHD_EOS_IDEAL>), grid, block, 0, st, P, S, Cg, m, e, cp, p, q, flags,
+                         segs, (int)nrec);
+    else
+      hipLaunchKernelGGL((k_fmr_prep<MC_CF, GRHD_EOS_HYBRID>), grid, block, 0, st, P, S, Cg, m, e, cp, p, q,
+                         flags, segs, (int)nrec);
+  }
+  return launch_status("fmr stage recovery and prolongation");
 }
 
 static int restrict_(const grhd_grid *pg, const grhd_cons *qp, const grhd_grid *cg, const grhd_cons *qc,
@@ -408,15 +513,14 @@ int step_level(grhd_fmr *h, int l, double t, double dt, hipStream_t st) {
   EosK e = to_eosk(&h->eos, h->opts.c2p.rho_atm);
   const int mc = metric_class(&L.metric);
   for (int s = 0; s < 3; s++) {
+    // the parent's slices at the stage time (ghost cells of this level)
+    SliceK S{};
     if (has_parent) {
       const grhd_level &Pl = h->lev[l - 1];
-      SliceK S{};
       S.ns = h->ns[l - 1];
       for (int i = 0; i < S.ns; i++)
         for (int f = 0; f < 6; f++) S.p[i][f] = Pl.slice[h->order[l - 1][i]].p[f];
       slice_weights(S, h->ts[l - 1].data(), t + kT[s] * dt);
-      if ((rc = prolong(&Pl.grid, S, &L.grid, &L.metric, &h->eos, h->opts.c2p.rho_atm, &L.p, qs_of[s], st)))
-        return rc;
     }
     grhd_rk_stage stg{};
     stg.a = kA[s]; stg.b = kB[s]; stg.c = kC[s]; stg.dt = dt;
@@ -442,8 +546,11 @@ int step_level(grhd_fmr *h, int l, double t, double dt, hipStream_t st) {
     P6 p;
     for (int c = 0; c < 5; c++) q.q[c] = qs_of[s]->q[c];
     for (int f = 0; f < 6; f++) p.p[f] = L.p.p[f];
-    if ((rc = launch_con2prim(pk.g, e, to_c2pk(&h->opts.c2p), pk.m, mc, q, p, h->flags[l], nullptr, st)))
-      return rc;
+    // recovery of q_s; a child level's ghost cells are prolonged in the
+    // same launch
+    rc = has_parent ? prep(&h->lev[l - 1].grid, S, L, e, to_c2pk(&h->opts.c2p), q, p, h->flags[l], mc, st)
+                    : launch_con2prim(pk.g, e, to_c2pk(&h->opts.c2p), pk.m, mc, q, p, h->flags[l], nullptr, st);
+    if (rc) return rc;
     if ((rc = launch_substep(pk, e, h->opts.prec, mc, shape, nullptr, st))) return rc;
   }
   if (!has_child) return GRHD_OK;
