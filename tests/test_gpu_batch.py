@@ -1,4 +1,4 @@
-"""GPU: the batched persistent substep (grhd_plan_create / grhd_batch_levels)
+"""GPU: the batched substep (grhd_plan_create / grhd_batch_levels)
 equals the single-patch substep bit for bit on every patch (the per-cell
 arithmetic does not depend on the tiling or on the launch), over a mixture
 of nested star levels and uneven Riemann instances, for several calls in a
