@@ -10,8 +10,7 @@ general-metric path (shift, lapse, extrinsic curvature, cylindrical).
   least 2.5x per doubling at t = 2M (measured 3.0x, 3.4x); with minmod by
   at least 3x per doubling at t = 20M (measured 3.4x, 3.7x: second order).
   PPM's error at t = 20M falls only about 2x per doubling (measured: first
-  order); most of it sits in the strong-field region r < 4M next to the
-  held inner cells (62% at N = 256), little around the sonic point.
+  order, also restricted to r > 2M); the cause is not identified.
 - the inner-region hold inside the stage (grhd_options.fix_mask) equals
   the separate grhd_fix_cells pass bit for bit.
 """
