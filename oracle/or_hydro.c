@@ -97,6 +97,15 @@ double or_eos_press(const or_eos *e, double rho, double eps) {
   return pc + (e->Gth - 1.0) * rho * (eps - ec);
 }
 
+/* the inverse of or_eos_press in eps: the specific internal energy at
+ * which the EOS gives pressure P at density rho */
+double or_eos_eps(const or_eos *e, double rho, double P) {
+  if (e->kind == OR_EOS_IDEAL) return P / ((e->Gth - 1.0) * rho);
+  double pc = or_eos_press_cold(e, rho);
+  double ec = or_eos_eps_cold(e, rho);
+  return ec + (P - pc) / ((e->Gth - 1.0) * rho);
+}
+
 /* sound speed squared: c_s^2 h = dP/drho|_eps + (P/rho^2) dP/deps|_rho,
  * derivatives at (rho, eps), P as given (reconstructed states carry an
  * independent P); clamped to [0, 1). */
@@ -910,6 +919,18 @@ static void free_fields(double **a, int nf) {
   free(a);
 }
 
+/* Face states on the EOS (reading of Sec. II.C.2, which names rho, u_i,
+ * P and eps as the primitives): rho, u_i and P come from the
+ * reconstruction, eps from the EOS at the reconstructed (rho, P).  An
+ * independently reconstructed eps leaves the face state off the EOS, and
+ * at a contact of uniform pressure that mismatch feeds pressure noise. */
+static void faces_on_eos(const or_eos *e, int64_t n, double *const *L, double *const *R) {
+  for (int64_t o = 0; o < n; o++) {
+    L[5][o] = or_eos_eps(e, L[0][o], L[4][o]);
+    R[5][o] = or_eos_eps(e, R[0][o], R[4][o]);
+  }
+}
+
 int or_rk_substep(const or_grid *gr, const or_eos *e, const or_metric *m,
                   int recon, int riemann, const or_c2p *cp, const or_stage *st,
                   double *const *qn, double *const *qs, double *const *qout,
@@ -941,11 +962,13 @@ int or_rk_substep_reg(const or_grid *gr, const or_eos *e, const or_metric *m,
   or_con2prim(gr, e, m, cp, qs, p, flags, &dloc);
   /* 2. ghost cells on primitives */
   or_fill_ghosts(gr, p);
-  /* 3. reconstruction, 4. Riemann fluxes, in x then z */
+  /* 3. reconstruction (face eps from the EOS), 4. Riemann fluxes, in x then z */
   double sx, sz;
   or_reconstruct(gr, 0, recon, p, xL, xR);
+  faces_on_eos(e, nfxa, xL, xR);
   or_face_flux(gr, 0, riemann, e, m, xL, xR, Fx, &sx);
   or_reconstruct(gr, 1, recon, p, zL, zR);
+  faces_on_eos(e, nfza, zL, zR);
   or_face_flux(gr, 1, riemann, e, m, zL, zR, Fz, &sz);
   /* 5. divergence and sources */
   or_rhs(gr, e, m, p, Fx, Fz, L);

@@ -87,6 +87,7 @@ extern "C" {
 
 /* pointwise EOS */
 double or_eos_press(const or_eos *e, double rho, double eps);
+double or_eos_eps(const or_eos *e, double rho, double P);
 double or_eos_eps_cold(const or_eos *e, double rho);
 double or_eos_press_cold(const or_eos *e, double rho);
 double or_eos_cs2(const or_eos *e, double rho, double eps, double P);
