@@ -149,6 +149,21 @@ __device__ __forceinline__ T eos_cs2(const EosK &e, T rho, T eps, T P) {
   return cs2;
 }
 
+// specific internal energy at which the EOS gives pressure P at density
+// rho (the inverse of eos_press in eps); the face states of the flux take
+// rho, u_i and P from the reconstruction and eps from here, so that they
+// lie on the EOS
+template <class T>
+__device__ __forceinline__ T eos_eps(const EosK &e, T rho, T P) {
+  T gm1 = T(e.Gth - 1.0);
+  if (e.kind == GRHD_EOS_IDEAL) return P / (gm1 * rho);
+  double rd = (double)rho;
+  int i = eos_piece(e, rd);
+  T kr = T(e.K[i] * pow(rd, e.G[i] - 1.0));  // K rho^(Gamma - 1)
+  T ec = kr / T(e.G[i] - 1.0) + T(e.deps[i]);  // cold specific energy
+  return ec + (P - kr * rho) / (gm1 * rho);
+}
+
 // ------------------------------------------------ prim -> con (cons_var)
 
 // conserved vector (densitised, Cartesian S components, E total) of a

@@ -377,15 +377,18 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
           L.P = Pa; L.eps = ea;
           R = L;
         } else {
+          // rho, u_i and P reconstructed; eps from the EOS at the face's
+          // (rho, P), which keeps the face states on the EOS
           T s[6], a, b;
-          for (int fld = 0; fld < 6; fld++) {
+          for (int fld = 0; fld < 5; fld++) {
             for (int i = 0; i < 6; i++) s[i] = sm.p[fld][base + i * stride];
             recon_face(P.recon, s, a, b);
             if (fld == 0) { L.rho = a; R.rho = b; }
             else if (fld < 4) { L.u[fld - 1] = a; R.u[fld - 1] = b; }
-            else if (fld == 4) { L.P = a; R.P = b; }
-            else { L.eps = a; R.eps = b; }
+            else { L.P = a; R.P = b; }
           }
+          L.eps = eos_eps(e, L.rho, L.P);
+          R.eps = eos_eps(e, R.rho, R.P);
         }
         FaceMet<T> fm;
         T t6[6];
