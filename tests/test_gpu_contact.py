@@ -1,0 +1,62 @@
+"""GPU: an oblique contact (density wave of uniform pressure and velocity,
+flat metric, gamma-law, periodic in x and z) keeps P and u uniform through
+SSP-RK3 steps of grhd_rk_substep, on a grid of many 16x16 tiles with ragged
+tails.  The face states lie on the EOS (eps from the reconstructed rho and
+P), and the conserved vector of such states is affine in rho, so the
+family is kept to rounding: FP64 to 1e-12, mixed precision (FP32 face
+work) to 1e-5.  The same property pins the oracle; here it checks the
+kernels at a size the oracle does not run."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2502_03223_amd import grhd  # noqa: E402
+
+DEV = torch.device("cuda:0")
+GAM = 5.0 / 3.0
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+@pytest.mark.parametrize("recon", ["ppm", "minmod"])
+def test_contact_keeps_pressure_and_velocity(prec, tol, recon):
+    nx, nz = 1000, 360
+    g = synth.make_grid(nx, nz, 0.0, 0.0, 1.0 / nx, 1.0 / nz, "cart", ("periodic",) * 4)
+    eos = synth.ideal_eos(GAM)
+    X, Z = synth.cell_coords(g)
+    p = synth.empty_fields(g, 6)
+    vx, vz = 0.3, -0.4
+    w = 1.0 / math.sqrt(1.0 - vx * vx - vz * vz)
+    p[0] = 1.0 + 0.2 * np.sin(2.0 * math.pi * (X + 2.0 * Z))
+    p[1], p[3] = w * vx, w * vz
+    p[4] = 1.0
+    p[5] = p[4] / ((GAM - 1.0) * p[0])
+    pd = torch.from_numpy(np.ascontiguousarray(p)).to(DEV)
+    q = torch.zeros((5,) + pd.shape[1:], dtype=torch.float64, device=DEV)
+    grhd.prim2con(g, eos, {}, pd, q, with_ghosts=True)
+    c2p = dict(w_max=100.0, rho_atm=1e-12)
+    sub = grhd.Substep(g, eos, {}, dict(recon=recon, riemann="hllc", prec=prec, c2p=c2p))
+    q1, q2 = torch.zeros_like(q), torch.zeros_like(q)
+    pw = torch.zeros_like(pd)
+    dt = 0.4 / nx
+    for _ in range(4):
+        for s, (qn, qs, qo) in enumerate([(q, q, q1), (q, q1, q2), (q, q2, q)]):
+            sub(dict(grhd.SSPRK3[s], dt=dt), qn, qs, qo, pw)
+    grhd.con2prim(g, eos, {}, c2p, q, pw)
+    torch.cuda.synchronize()
+    out = pw.cpu().numpy()
+    P = synth.interior(g, out[4])
+    rho = synth.interior(g, out[0])
+    assert np.abs(P - 1.0).max() < tol
+    assert np.abs(synth.interior(g, out[1]) - w * vx).max() < tol
+    assert np.abs(synth.interior(g, out[3]) - w * vz).max() < tol
+    assert np.abs(synth.interior(g, out[2])).max() < tol
+    assert np.abs(rho - synth.interior(g, p[0])).max() > 1e-5   # the wave moved
