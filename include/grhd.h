@@ -188,7 +188,9 @@ int grhd_prim2con(const grhd_grid *grid, const grhd_eos *eos,
  * (0 = varpi/x, 1 = z), Sec. II.C.2: third-order PPM or minmod.  p holds
  * interior primitives; ghost values come from the boundary conditions
  * (EXTERNAL: from p's ghost cells).  pL, pR: face arrays of 6 fields, FP64
- * (prec = FP64) or FP32 (prec = MIXED; pointers then address float). */
+ * (prec = FP64) or FP32 (prec = MIXED; pointers then address float).
+ * Every field is reconstructed, eps included; the stage
+ * (grhd_rk_substep) replaces the face eps by the EOS value. */
 int grhd_reconstruct(const grhd_grid *grid, int dir, int recon, int prec,
                      const grhd_prim *p, const grhd_prim *pL,
                      const grhd_prim *pR, void *hip_stream);
@@ -206,7 +208,8 @@ int grhd_hllc_flux(const grhd_grid *grid, int dir, int riemann, int prec,
                    const grhd_cons *F, double *max_speed, void *hip_stream);
 
 /* One Runge-Kutta stage of the whole hot path, Sec. II.C.1: recovery of
- * q_s (corrected in place), ghost handling, reconstruction and Riemann
+ * q_s (corrected in place), ghost handling, reconstruction of rho, u_i
+ * and P with eps at each face from the EOS at the face's (rho, P), Riemann
  * fluxes in both directions, area-weighted divergence with the cylindrical
  * and metric source terms, stage combination.
  * qn: q^n (read only when stage->a != 0; may alias qs).  qs: in/out.
