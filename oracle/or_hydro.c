@@ -14,7 +14,8 @@
  * Parity pins live in tests/ (exact Riemann solution, uniform-state
  * preservation, conservation, con2prim round trip, polynomial exactness,
  * flux consistency against the stress-energy tensor, covariant source
- * identity).  Build: gcc -O2 -ffp-contract=off (no fused multiply-add, no
+ * identity, a uniform-pressure contact kept to round-off, smooth-wave
+ * convergence).  Build: gcc -O2 -ffp-contract=off (no fused multiply-add, no
  * fast-math).
  */
 #include <math.h>
