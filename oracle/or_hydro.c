@@ -766,7 +766,9 @@ void or_con2prim(const or_grid *gr, const or_eos *e, const or_metric *m,
 }
 
 /* boundary conditions on primitives: axis parity (u_x, u_y odd),
- * mirror (normal velocity odd), periodic, outflow copy, external (kept) */
+ * mirror (normal velocity odd), periodic (the ghost at index j takes the
+ * cell j mod n, so a direction of fewer than 3 cells wraps onto itself),
+ * outflow copy, external (kept) */
 void or_fill_ghosts(const or_grid *gr, double *const *p) {
   int ng = gr->ng, nx = gr->nx, nz = gr->nz;
   for (int k = 0; k < nz; k++)
@@ -776,7 +778,7 @@ void or_fill_ghosts(const or_grid *gr, double *const *p) {
       for (int mm = 0; mm < ng; mm++) {
         int jg = side == 0 ? -1 - mm : nx + mm;
         int js;
-        if (bc == OR_BC_PERIODIC) js = side == 0 ? nx - 1 - mm : mm;
+        if (bc == OR_BC_PERIODIC) js = ((jg % nx) + nx) % nx;
         else if (bc == OR_BC_OUTFLOW) js = side == 0 ? 0 : nx - 1;
         else js = side == 0 ? mm : nx - 1 - mm;
         int64_t ig = cidx(gr, jg, k), is = cidx(gr, js, k);
@@ -792,7 +794,7 @@ void or_fill_ghosts(const or_grid *gr, double *const *p) {
       for (int mm = 0; mm < ng; mm++) {
         int kg = side == 0 ? -1 - mm : nz + mm;
         int ks;
-        if (bc == OR_BC_PERIODIC) ks = side == 0 ? nz - 1 - mm : mm;
+        if (bc == OR_BC_PERIODIC) ks = ((kg % nz) + nz) % nz;
         else if (bc == OR_BC_OUTFLOW) ks = side == 0 ? 0 : nz - 1;
         else ks = side == 0 ? mm : nz - 1 - mm;
         int64_t ig = cidx(gr, j, kg), is = cidx(gr, j, ks);
