@@ -440,3 +440,26 @@ def test_substep_star_adiabatic(orc, tov):
         if s == 0:
             qn = ref["qs"]
         q = ref["qout"]
+
+
+@pytest.mark.parametrize("nx,nz,bc", [(1, 1, "periodic"), (2, 1, "periodic"), (1, 2, "periodic"),
+                                      (2, 2, "periodic"), (1, 21, "periodic"), (19, 1, "periodic"),
+                                      (2, 37, "periodic"), (1, 1, "outflow"), (2, 3, "outflow"),
+                                      (3, 1, "outflow")])
+@pytest.mark.parametrize("recon,riemann", [("ppm", "hllc"), ("minmod", "tvdlf")])
+def test_substep_tiny_grids(orc, nx, nz, bc, recon, riemann):
+    """Degenerate grids: directions of 1 to 3 cells (periodic ones shorter
+    than the 3-cell halo wrap onto themselves), one partial tile."""
+    eos = synth.ideal_eos(5.0 / 3.0)
+    grid = synth.make_grid(nx, nz, 0.0, 0.0, 0.1, 0.1, "cart", (bc,) * 4)
+    rng = np.random.default_rng(100 * nx + nz)
+    p = synth.empty_fields(grid, 6)
+    b = rng.uniform(size=p.shape)              # ghosts too: the BCs overwrite them
+    p[0] = 1.0 + 0.3 * b[0]
+    p[1], p[2], p[3] = 0.3 * (b[1] - 0.5), 0.2 * (b[2] - 0.5), 0.3 * (b[3] - 0.5)
+    p[4] = 0.5 + 0.3 * b[4]
+    p[5] = p[4] / ((5.0 / 3.0 - 1.0) * p[0])
+    q = orc.prim2con(grid, eos, {}, p, with_ghosts=True)
+    opts = dict(recon=recon, riemann=riemann, c2p=C2P_RIE)
+    ref, out = run_pair(orc, grid, eos, {}, opts, dict(grhd.SSPRK3[0], dt=0.01), q, q)
+    check_pair(grid, ref, out)
