@@ -463,3 +463,63 @@ def test_substep_tiny_grids(orc, nx, nz, bc, recon, riemann):
     opts = dict(recon=recon, riemann=riemann, c2p=C2P_RIE)
     ref, out = run_pair(orc, grid, eos, {}, opts, dict(grhd.SSPRK3[0], dt=0.01), q, q)
     check_pair(grid, ref, out)
+
+
+def test_substep_at_the_size_limit(orc):
+    """A field of exactly 2^29 cells (the 32-bit offset limit): 16378 x
+    32762 interior cells, row pitch 16384, periodic, the state repeating
+    with period 2 in z.  Every pair of rows must equal, bit for bit, the
+    result on a 2-row periodic grid, which is itself checked against the
+    oracle; a read or write at a wrong offset anywhere in the 4 GiB fields
+    breaks the equality.  About 65 GiB of device arrays."""
+    eos = synth.ideal_eos(5.0 / 3.0)
+    nx, nz = 16378, 32762
+    gs = synth.make_grid(nx, 2, 0.0, 0.0, 0.1, 0.1, "cart", ("periodic",) * 4)
+    gb = synth.make_grid(nx, nz, 0.0, 0.0, 0.1, 0.1, "cart", ("periodic",) * 4)
+    pitch, ng = gb["pitch"], gb["ng"]
+    assert pitch == gs["pitch"] == 16384 and (nz + 2 * ng) * pitch == 1 << 29
+    rng = np.random.default_rng(29)
+    p = synth.empty_fields(gs, 6)
+    b = rng.uniform(size=p.shape)
+    p[0] = 1.0 + 0.3 * b[0]
+    p[1], p[2], p[3] = 0.3 * (b[1] - 0.5), 0.2 * (b[2] - 0.5), 0.3 * (b[3] - 0.5)
+    p[4] = 0.5 + 0.3 * b[4]
+    p[5] = p[4] / ((5.0 / 3.0 - 1.0) * p[0])
+    q = orc.prim2con(gs, eos, {}, p, with_ghosts=True)
+    opts = dict(recon="ppm", riemann="hllc", prec="fp64", c2p=C2P_RIE, tile=(16, 16))
+    st = dict(grhd.SSPRK3[0], dt=0.01)
+    ref, small = run_pair(orc, gs, eos, {}, opts, st, q, q, tile=(16, 16))
+    check_pair(gs, ref, small)
+
+    rows = nz + 2 * ng
+    qb = torch.zeros((5, rows, pitch), dtype=torch.float64, device=DEV)
+    qs_small = dev(q)[:, ng:ng + 2, :]
+    qb[:, ng:ng + nz].view(5, nz // 2, 2, pitch).copy_(qs_small[:, None].expand(5, nz // 2, 2, pitch))
+    qo = torch.zeros_like(qb)
+    pb = torch.zeros((6, rows, pitch), dtype=torch.float64, device=DEV)
+    fb = torch.zeros((rows, pitch), dtype=torch.uint8, device=DEV)
+    dg = grhd.new_diag()
+    sub = grhd.Substep(gb, eos, {}, opts)
+    sub(st, qb, qb, qo, pb, flags=fb, diag=dg)
+    torch.cuda.synchronize()
+
+    def rows_equal(big, small_np, nf):
+        s = torch.from_numpy(np.ascontiguousarray(small_np[..., ng:ng + 2, ng:ng + nx])).to(DEV)
+        bv = big[..., ng:ng + nz, :].view(*big.shape[:-2], nz // 2, 2, pitch)[..., ng:ng + nx]
+        if big.dtype == torch.float64:
+            bv, s = bv.view(torch.int64), s.view(torch.int64)
+        return bool((bv == s.unsqueeze(-3)).all())
+
+    try:
+        assert rows_equal(qo, small["qout"], 5)
+        assert rows_equal(qb, small["qs"], 5)
+        assert rows_equal(pb, small["p"], 6)
+        assert rows_equal(fb, small["flags"], 1)
+        d, r = grhd.read_diag(dg), small["diag"]
+        assert d["max_courant"] == r["max_courant"]
+        assert d["Mb"] == pytest.approx(r["Mb"] * (nz // 2), rel=1e-12)
+        for k in ("n_rescale", "n_cold", "n_atm", "n_fail"):
+            assert d[k] == r[k] * (nz // 2), k
+    finally:
+        del qb, qo, pb, fb
+        torch.cuda.empty_cache()
