@@ -121,3 +121,53 @@ def test_batch_tune_cache_roundtrip(orc, tmp_path):
     assert t3["square"] in [(32, 8), (32, 16), (64, 8), (16, 16), (16, 8)]
     # explicit shapes pass through
     assert grhd.autotune(desc, eos_table, dict(opts, tile=(32, 16)))["square"] == (32, 16)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_tiny_patches(orc, prec):
+    """Degenerate patches (1 to 3 cells in a direction, periodic and
+    outflow) batched together with ordinary ones equal the single-patch
+    calls bit for bit."""
+    gam = 5.0 / 3.0
+    eos_table = [synth.ideal_eos(gam)]
+    shapes = [(1, 1, "periodic"), (2, 1, "periodic"), (1, 17, "periodic"), (3, 2, "outflow"),
+              (19, 1, "periodic"), (2, 37, "outflow"), (40, 24, "periodic")]
+    patches = []
+    for i, (nx, nz, bc) in enumerate(shapes):
+        grid = synth.make_grid(nx, nz, 0.0, 0.0, 0.1, 0.1, "cart", (bc,) * 4)
+        b = np.random.default_rng(300 + i).uniform(size=(6,) + synth.empty_fields(grid, 1).shape[1:])
+        p = np.empty_like(b)
+        p[0] = 1.0 + 0.3 * b[0]
+        p[1], p[2], p[3] = 0.3 * (b[1] - 0.5), 0.2 * (b[2] - 0.5), 0.3 * (b[3] - 0.5)
+        p[4] = 0.5 + 0.3 * b[4]
+        p[5] = p[4] / ((gam - 1.0) * p[0])
+        q = orc.prim2con(grid, eos_table[0], {}, p, with_ghosts=True)
+        patches.append(dict(grid=grid, metric={}, q0=q, eos_id=0))
+    opts = dict(recon="ppm", riemann="hllc", prec=prec, c2p=dict(w_max=100.0, rho_atm=1e-12))
+    A = [alloc(pt) for pt in patches]
+    B = [alloc(pt) for pt in patches]
+
+    def descr(buf, pt, st):
+        return dict(grid=pt["grid"], metric={}, qn=buf["q"], qs=buf["q"], qout=buf["q1"],
+                    p=buf["p"], stage=dict(st, dt=0.01), eos_id=0)
+
+    plan = grhd.Plan([descr(a, pt, grhd.SSPRK3[0]) for a, pt in zip(A, patches)], eos_table, opts)
+    subs = [grhd.Substep(pt["grid"], eos_table[0], {}, opts) for pt in patches]
+    for a, b, pt in zip(A, B, patches):
+        a["q"].copy_(dev(pt["q0"]))
+        b["q"].copy_(dev(pt["q0"]))
+    for call in range(2):
+        st = grhd.SSPRK3[0]
+        plan([descr(a, pt, st) for a, pt in zip(A, patches)])
+        for b, pt, sub in zip(B, patches, subs):
+            sub(dict(st, dt=0.01), b["q"], b["q"], b["q1"], b["p"])
+        torch.cuda.synchronize()
+        for a, b, pt in zip(A, B, patches):
+            g = pt["grid"]
+            for key in ("q1", "q", "p"):
+                x = synth.interior(g, a[key].cpu().numpy())
+                y = synth.interior(g, b[key].cpu().numpy())
+                assert np.array_equal(x, y), (call, key, g["nx"], g["nz"])
+            a["q"], a["q1"] = a["q1"], a["q"]
+            b["q"], b["q1"] = b["q1"], b["q"]
+    plan.close()
