@@ -78,16 +78,17 @@ def kernel_sources_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """(bytes per launch, source hash) recorded with the counter profile, or
-    None when absent or taken on other sources."""
+def measured_traffic(nzone):
+    """Bytes per launch recorded with the counter profile, or None when
+    absent, taken on other sources or on a launch of another size."""
     try:
         kv = {}
         for line in open(TRAFFIC_FILE):
-            if ":" in line and line.split(":", 1)[0].strip() in ("traffic_bytes_per_launch", "source_sha256"):
+            if ":" in line and line.split(":", 1)[0].strip() in ("traffic_bytes_per_launch", "source_sha256",
+                                                                 "zones_per_launch"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip().strip("`")
-        if kv.get("source_sha256") != kernel_sources_hash():
+        if kv.get("source_sha256") != kernel_sources_hash() or int(kv["zones_per_launch"]) != nzone:
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -254,7 +255,7 @@ def main():
     # pass) against its own bytes
     substep_gbs = float(np.mean(BYTES_SUBSTEP)) * nzone / (ms_per_step / 3.0 * 1e-3) / 1e9
     diag = r64["diag"]
-    tb = measured_traffic()
+    tb = measured_traffic(nzone)
     traffic = tb / (kms * 1e-3) / 1e9 if tb else None
     out_forms["fp64"] = {"value": value, "ms_per_step": ms_per_step, "chained": False,
                          "ms_per_step_with_events": r64["wall_with_events"] * 1e3 / args.steps,
