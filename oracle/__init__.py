@@ -32,6 +32,9 @@ FLAT = {"alp": 1.0, "W": 1.0, "gxx": 1.0, "gyy": 1.0, "gzz": 1.0}
 BC_NAMES = {"outflow": 0, "periodic": 1, "axis": 2, "reflect": 3, "external": 4}
 RECON = {"ppm": 0, "minmod": 1}
 RIEMANN = {"hllc": 0, "tvdlf": 1}
+# face states of the stage: "recon" reconstructs every primitive (Sec.
+# II.C.2); "eos" takes eps from the EOS at the reconstructed (rho, P)
+FACE_EPS = {"recon": 0, "eos": 1}
 NPARAM_MLP = 4481
 
 
@@ -98,6 +101,7 @@ def lib():
         d, p, i = C.c_double, C.c_void_p, C.c_int
         sig = {
             "or_eos_press": (d, [p, d, d]),
+            "or_eos_eps": (d, [p, d, d]),
             "or_eos_eps_cold": (d, [p, d]),
             "or_eos_press_cold": (d, [p, d]),
             "or_eos_cs2": (d, [p, d, d, d]),
@@ -106,6 +110,8 @@ def lib():
             "or_c2p_master": (d, [p, d, d, d, d]),
             "or_valencia_flux_point": (None, [p, p, i, p, p]),
             "or_face_flux_point": (None, [p, p, i, i, p, p, p, p]),
+            "or_coord_speeds": (None, [p, p, i, p, p, p]),
+            "or_tetrad_speeds": (None, [p, p, i, p, p, p]),
             "or_source_point": (None, [p, p, p, d, i, p, p]),
             "or_recon_line": (None, [i, i, p, p, p]),
             "or_lagrange6": (d, [p]),
@@ -116,8 +122,8 @@ def lib():
             "or_reconstruct": (None, [p, i, i, p, p, p]),
             "or_face_flux": (None, [p, i, i, p, p, p, p, p, p]),
             "or_rhs": (None, [p, p, p, p, p, p, p]),
-            "or_rk_substep": (i, [p, p, p, i, i, p, p, p, p, p, p, p, p, p, p, p]),
-            "or_rk_substep_reg": (i, [p, p, p, i, i, p, p, p, p, p, p, p, p, p, p, p, p, i, i, d]),
+            "or_rk_substep": (i, [p, p, p, i, i, i, p, p, p, p, p, p, p, p, p, p, p]),
+            "or_rk_substep_reg": (i, [p, p, p, i, i, i, p, p, p, p, p, p, p, p, p, p, p, p, i, i, d]),
             "or_fmr_prolong": (None, [p, p, p, p, i, d, d, d, d, p, p, p, p, p]),
             "or_fmr_restrict": (None, [p, p, p, p]),
             "or_fmr_reflux": (None, [p, p, p, p, p]),
@@ -211,6 +217,10 @@ def eos_press(eos, rho, eps):
     return lib().or_eos_press(C.byref(make_eos(eos)), rho, eps)
 
 
+def eos_eps(eos, rho, P):
+    return lib().or_eos_eps(C.byref(make_eos(eos)), rho, P)
+
+
 def eos_cs2(eos, rho, eps, P):
     return lib().or_eos_cs2(C.byref(make_eos(eos)), rho, eps, P)
 
@@ -260,6 +270,17 @@ def face_flux_point(eos, g, dirn, riemann, pL, pR):
     lib().or_face_flux_point(C.byref(make_eos(eos)), _ptr(g), dirn, RIEMANN[riemann],
                              _ptr(pL), _ptr(pR), _ptr(F), _ptr(sp))
     return F, float(sp[0])
+
+
+def signal_speeds(eos, g, dirn, p, frame="coord"):
+    """(lambda-, lambda+) of state p at a face of direction dirn as
+    coordinate speeds: frame "coord" from the 3+1 characteristic formula
+    (TVDLF), "tetrad" from the face tetrad frame (HLLC)."""
+    g, p = _f64(g), _f64(p)
+    lm, lp = C.c_double(), C.c_double()
+    fn = lib().or_coord_speeds if frame == "coord" else lib().or_tetrad_speeds
+    fn(C.byref(make_eos(eos)), _ptr(g), dirn, _ptr(p), C.byref(lm), C.byref(lp))
+    return lm.value, lp.value
 
 
 def source_point(eos, g, dg, x, geom, p):
@@ -381,7 +402,8 @@ def rk_substep(grid, eos, metric, opts, stage, qn, qs, acc_in=None, want_acc=Fal
     lib().or_rk_substep_reg(
         C.byref(make_grid(grid)), C.byref(make_eos(eos)),
         C.byref(make_metric(metric, keep)), RECON[opts.get("recon", "ppm")],
-        RIEMANN[opts.get("riemann", "hllc")], C.byref(make_c2p(opts["c2p"])),
+        RIEMANN[opts.get("riemann", "hllc")], FACE_EPS[opts.get("face_eps", "recon")],
+        C.byref(make_c2p(opts["c2p"])),
         C.byref(st), qn_ptr if qn is not None else _fieldptrs(qs, 5),
         _fieldptrs(qs, 5), _fieldptrs(qout, 5), _fieldptrs(p, 6),
         _fieldptrs(acc_in, 5) if acc_in is not None else None,

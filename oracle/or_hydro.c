@@ -350,7 +350,7 @@ void or_recon_line(int recon, int n, const double *a, double *aL, double *aR) {
   for (int i = 1; i < n - 1; i++) dm[i] = mono_slope(a[i - 1], a[i], a[i + 1]);
   /* ai[i] = interface value a_{i+1/2} */
   for (int i = 1; i < n - 2; i++)
-    ai[i] = a[i] + 0.5 * (a[i + 1] - a[i]) - (1.0 / 6.0) * (dm[i + 1] - dm[i]);
+    ai[i] = a[i] + 0.5 * (a[i + 1] - a[i]) - (dm[i + 1] - dm[i]) / 6.0;
   for (int i = 2; i <= n - 4; i++) {
     double l0, r0, l1, r1;
     ppm_cell(a[i], ai[i - 1], ai[i], &l0, &r0);
@@ -433,8 +433,8 @@ static void cons_cart(const double *g, const double *p, double *q) {
 }
 
 /* coordinate characteristic speeds (Banyuls et al. 1997) for TVDLF */
-static void coord_speeds(const or_eos *e, const double *g, int dir,
-                         const double *p, double *lm, double *lp) {
+void or_coord_speeds(const or_eos *e, const double *g, int dir,
+                     const double *p, double *lm, double *lp) {
   int n = (dir == 0) ? 0 : 2;
   double alp = g[OR_ALP], W = g[OR_W];
   double beta[3] = {g[OR_BX], g[OR_BY], g[OR_BZ]};
@@ -509,36 +509,17 @@ static void hllc_star(const struct tstate *s, double lam, double lc, double Pc,
   qc[4] = (s->q[4] * dl + Pc * lc - s->P * s->vn) / den;
 }
 
-void or_face_flux_point(const or_eos *e, const double *g, int dir, int riemann,
-                        const double *pL, const double *pR, double *F,
-                        double *speed) {
-  double alp = g[OR_ALP], W = g[OR_W];
-  double sg = 1.0 / (W * W * W);
-  if (riemann == OR_RIEMANN_TVDLF) {
-    /* local Lax-Friedrichs in the coordinate frame (reading of TVDLF) */
-    double fL[5], fR[5], qL[5], qR[5], l1, l2, l3, l4;
-    or_valencia_flux_point(e, g, dir, pL, fL);
-    or_valencia_flux_point(e, g, dir, pR, fR);
-    cons_cart(g, pL, qL);
-    cons_cart(g, pR, qR);
-    coord_speeds(e, g, dir, pL, &l1, &l2);
-    coord_speeds(e, g, dir, pR, &l3, &l4);
-    double c = fabs(l1);
-    if (fabs(l2) > c) c = fabs(l2);
-    if (fabs(l3) > c) c = fabs(l3);
-    if (fabs(l4) > c) c = fabs(l4);
-    for (int m = 0; m < 5; m++) F[m] = 0.5 * (fL[m] + fR[m] - c * (qR[m] - qL[m]));
-    if (speed) *speed = c;
-    return;
-  }
-  /* HLLC in the tetrad frame of the face */
+/* Tetrad of a face (Sec. II.C.2): contravariant spatial legs El (normal,
+ * tangent 1, tangent 2; x/y/z components), covariant legs Ec, the normal
+ * factor sqrt(gamma^nn) and the face speed v_int in the tetrad frame. */
+static void face_tetrad(const double *g, int dir, double El[3][3], double Ec[3][3],
+                        double *sqgnn_out, double *vint_out) {
   int n = (dir == 0) ? 0 : 2;
+  double alp = g[OR_ALP], W = g[OR_W];
   double beta[3] = {g[OR_BX], g[OR_BY], g[OR_BZ]};
   double gt[6] = {g[OR_GXX], g[OR_GXY], g[OR_GXZ], g[OR_GYY], g[OR_GYZ], g[OR_GZZ]};
   double gtu[6];
   inv_sym3(gt, gtu);
-  /* contravariant spatial legs: normal, tangent 1, tangent 2 */
-  double El[3][3];
   if (dir == 0) {
     double B = 1.0 / sqrt(gtu[0]);
     double C = 1.0 / sqrt(gt[5]);
@@ -556,7 +537,6 @@ void or_face_flux_point(const or_eos *e, const double *g, int dir, int riemann,
     El[2][0] = 0.0; El[2][1] = W * C; El[2][2] = 0.0;
   }
   /* covariant legs e_(a)_j = gamma_ji e_(a)^i, gamma_ij = W^-2 gt_ij */
-  double Ec[3][3];
   for (int a = 0; a < 3; a++)
     for (int j = 0; j < 3; j++) {
       double s = 0.0;
@@ -564,7 +544,48 @@ void or_face_flux_point(const or_eos *e, const double *g, int dir, int riemann,
       Ec[a][j] = s / (W * W);
     }
   double sqgnn = W * sqrt(s3(gtu, n, n));
-  double vint = beta[n] / (alp * sqgnn);
+  *sqgnn_out = sqgnn;
+  *vint_out = beta[n] / (alp * sqgnn);
+}
+
+/* the signal speeds lambda-, lambda+ of one state in the face tetrad
+ * frame, mapped to coordinate speeds alpha sqrt(gamma^nn) lambda - beta^n */
+void or_tetrad_speeds(const or_eos *e, const double *g, int dir, const double *p,
+                      double *lm, double *lp) {
+  double El[3][3], Ec[3][3], sqgnn, vint;
+  face_tetrad(g, dir, El, Ec, &sqgnn, &vint);
+  struct tstate s;
+  tetrad_state(e, p, El, &s);
+  double f = g[OR_ALP] * sqgnn;
+  *lm = f * (s.lm - vint);
+  *lp = f * (s.lp - vint);
+}
+
+void or_face_flux_point(const or_eos *e, const double *g, int dir, int riemann,
+                        const double *pL, const double *pR, double *F,
+                        double *speed) {
+  double alp = g[OR_ALP], W = g[OR_W];
+  double sg = 1.0 / (W * W * W);
+  if (riemann == OR_RIEMANN_TVDLF) {
+    /* local Lax-Friedrichs in the coordinate frame (reading of TVDLF) */
+    double fL[5], fR[5], qL[5], qR[5], l1, l2, l3, l4;
+    or_valencia_flux_point(e, g, dir, pL, fL);
+    or_valencia_flux_point(e, g, dir, pR, fR);
+    cons_cart(g, pL, qL);
+    cons_cart(g, pR, qR);
+    or_coord_speeds(e, g, dir, pL, &l1, &l2);
+    or_coord_speeds(e, g, dir, pR, &l3, &l4);
+    double c = fabs(l1);
+    if (fabs(l2) > c) c = fabs(l2);
+    if (fabs(l3) > c) c = fabs(l3);
+    if (fabs(l4) > c) c = fabs(l4);
+    for (int m = 0; m < 5; m++) F[m] = 0.5 * (fL[m] + fR[m] - c * (qR[m] - qL[m]));
+    if (speed) *speed = c;
+    return;
+  }
+  /* HLLC in the tetrad frame of the face */
+  double El[3][3], Ec[3][3], sqgnn, vint;
+  face_tetrad(g, dir, El, Ec, &sqgnn, &vint);
 
   struct tstate L, R;
   tetrad_state(e, pL, El, &L);
@@ -922,11 +943,10 @@ static void free_fields(double **a, int nf) {
   free(a);
 }
 
-/* Face states on the EOS (reading of Sec. II.C.2, which names rho, u_i,
- * P and eps as the primitives): rho, u_i and P come from the
- * reconstruction, eps from the EOS at the reconstructed (rho, P).  An
- * independently reconstructed eps leaves the face state off the EOS, and
- * at a contact of uniform pressure that mismatch feeds pressure noise. */
+/* Face states on the EOS: a variant of Sec. II.C.2, which names rho, u_i,
+ * P and eps as the primitives taken to the faces.  In the variant rho, u_i
+ * and P come from the reconstruction and eps from the EOS at the
+ * reconstructed (rho, P), so the face states lie on the EOS. */
 static void faces_on_eos(const or_eos *e, int64_t n, double *const *L, double *const *R) {
   for (int64_t o = 0; o < n; o++) {
     L[5][o] = or_eos_eps(e, L[0][o], L[4][o]);
@@ -935,17 +955,18 @@ static void faces_on_eos(const or_eos *e, int64_t n, double *const *L, double *c
 }
 
 int or_rk_substep(const or_grid *gr, const or_eos *e, const or_metric *m,
-                  int recon, int riemann, const or_c2p *cp, const or_stage *st,
-                  double *const *qn, double *const *qs, double *const *qout,
-                  double *const *p_out, double *const *acc_in,
+                  int recon, int riemann, int face_eps, const or_c2p *cp,
+                  const or_stage *st, double *const *qn, double *const *qs,
+                  double *const *qout, double *const *p_out, double *const *acc_in,
                   double *const *acc_out, double *flux_reg, uint8_t *flags,
                   or_diag *diag) {
-  return or_rk_substep_reg(gr, e, m, recon, riemann, cp, st, qn, qs, qout, p_out, acc_in,
-                           acc_out, flux_reg, flags, diag, NULL, 0, 0, 0.0);
+  return or_rk_substep_reg(gr, e, m, recon, riemann, face_eps, cp, st, qn, qs, qout, p_out,
+                           acc_in, acc_out, flux_reg, flags, diag, NULL, 0, 0, 0.0);
 }
 
 int or_rk_substep_reg(const or_grid *gr, const or_eos *e, const or_metric *m,
-                      int recon, int riemann, const or_c2p *cp, const or_stage *st,
+                      int recon, int riemann, int face_eps, const or_c2p *cp,
+                      const or_stage *st,
                       double *const *qn, double *const *qs, double *const *qout,
                       double *const *p_out, double *const *acc_in,
                       double *const *acc_out, double *flux_reg, uint8_t *flags,
@@ -965,13 +986,13 @@ int or_rk_substep_reg(const or_grid *gr, const or_eos *e, const or_metric *m,
   or_con2prim(gr, e, m, cp, qs, p, flags, &dloc);
   /* 2. ghost cells on primitives */
   or_fill_ghosts(gr, p);
-  /* 3. reconstruction (face eps from the EOS), 4. Riemann fluxes, in x then z */
+  /* 3. reconstruction of (rho, u_i, P, eps), 4. Riemann fluxes, in x then z */
   double sx, sz;
   or_reconstruct(gr, 0, recon, p, xL, xR);
-  faces_on_eos(e, nfxa, xL, xR);
+  if (face_eps == OR_FACE_EPS_EOS) faces_on_eos(e, nfxa, xL, xR);
   or_face_flux(gr, 0, riemann, e, m, xL, xR, Fx, &sx);
   or_reconstruct(gr, 1, recon, p, zL, zR);
-  faces_on_eos(e, nfza, zL, zR);
+  if (face_eps == OR_FACE_EPS_EOS) faces_on_eos(e, nfza, zL, zR);
   or_face_flux(gr, 1, riemann, e, m, zL, zR, Fz, &sz);
   /* 5. divergence and sources */
   or_rhs(gr, e, m, p, Fx, Fz, L);

@@ -36,6 +36,10 @@ enum { OR_BC_OUTFLOW = 0, OR_BC_PERIODIC = 1, OR_BC_AXIS = 2,
        OR_BC_REFLECT = 3, OR_BC_EXTERNAL = 4 };
 enum { OR_RECON_PPM = 0, OR_RECON_MINMOD = 1 };
 enum { OR_RIEMANN_HLLC = 0, OR_RIEMANN_TVDLF = 1 };
+/* face states of the stage: every primitive reconstructed (Sec. II.C.2,
+ * the default), or eps taken from the EOS at the reconstructed (rho, P)
+ * (a variant, not the paper's) */
+enum { OR_FACE_EPS_RECON = 0, OR_FACE_EPS_EOS = 1 };
 enum { OR_EOS_IDEAL = 0, OR_EOS_HYBRID = 1 };
 
 /* con2prim flag bits */
@@ -106,6 +110,13 @@ void or_valencia_flux_point(const or_eos *e, const double *g, int dir,
 void or_face_flux_point(const or_eos *e, const double *g, int dir, int riemann,
                         const double *pL, const double *pR, double *F /*5*/,
                         double *speed /* max |coordinate speed| or NULL */);
+/* signal speeds of one state in direction dir, as coordinate speeds
+ * dx^n/dt: from the 3+1 characteristic formula (used by TVDLF), and from
+ * the face tetrad frame (used by HLLC) mapped back to coordinates */
+void or_coord_speeds(const or_eos *e, const double *g, int dir,
+                     const double *p, double *lm, double *lp);
+void or_tetrad_speeds(const or_eos *e, const double *g, int dir,
+                      const double *p, double *lm, double *lp);
 /* pointwise source: metric values g[], first derivatives dg[2][OR_NMET]
  * (d/dx, d/dz) at the cell; geometric term added when geom is cylindrical */
 void or_source_point(const or_eos *e, const double *g, const double *dg,
@@ -134,7 +145,8 @@ void or_rhs(const or_grid *gr, const or_eos *e, const or_metric *m,
             double *const *p, double *const *Fx, double *const *Fz,
             double *const *L);
 int or_rk_substep(const or_grid *gr, const or_eos *e, const or_metric *m,
-                  int recon, int riemann, const or_c2p *cp, const or_stage *st,
+                  int recon, int riemann, int face_eps, const or_c2p *cp,
+                  const or_stage *st,
                   double *const *qn, double *const *qs, double *const *qout,
                   double *const *p_out, double *const *acc_in,
                   double *const *acc_out, double *flux_reg, uint8_t *flags,
@@ -144,7 +156,8 @@ int or_rk_substep(const or_grid *gr, const or_eos *e, const or_metric *m,
  * face set {x faces j = reg_j, k < reg_k} + {z faces k = reg_k, j < reg_j}
  * into reg (5 x (reg_k + reg_j): x faces by k, then z faces by j) */
 int or_rk_substep_reg(const or_grid *gr, const or_eos *e, const or_metric *m,
-                      int recon, int riemann, const or_c2p *cp, const or_stage *st,
+                      int recon, int riemann, int face_eps, const or_c2p *cp,
+                      const or_stage *st,
                       double *const *qn, double *const *qs, double *const *qout,
                       double *const *p_out, double *const *acc_in,
                       double *const *acc_out, double *flux_reg, uint8_t *flags,

@@ -175,3 +175,23 @@ def christoffel_first_index_up(G, D):
     low = 0.5 * (np.einsum("adb->dab", D) + np.einsum("bda->dab", D) - D)
     # low[d,a,b] = 1/2 (d_a g_db + d_b g_da - d_d g_ab)
     return np.einsum("cd,dab->cab", Gi, low)
+
+
+def acoustic_speeds(g, prim, n, cs2):
+    """Coordinate speeds lambda = dx^n/dt of the two sound fronts moving
+    along spatial direction n, from the covariant characteristic condition
+    of a perfect fluid, (u^a xi_a)^2 = c_s^2 h^ab xi_a xi_b with
+    h^ab = g^ab + u^a u^b and the front covector xi = (-lambda, delta^n_i).
+    Returns (lambda-, lambda+)."""
+    G = four_metric(g)
+    Gi = np.linalg.inv(G)
+    ua = four_velocity_up(g, np.asarray(prim[1:4], dtype=float))
+    c2 = cs2
+    ut, un = ua[0], ua[1 + n]
+    gtt, gtn, gnn = Gi[0, 0], Gi[0, 1 + n], Gi[1 + n, 1 + n]
+    # (1 - c2)(u^n - lambda u^t)^2 - c2 (g^nn - 2 lambda g^tn + lambda^2 g^tt) = 0
+    A = (1.0 - c2) * ut * ut - c2 * gtt
+    B = -2.0 * ((1.0 - c2) * un * ut - c2 * gtn)
+    C = (1.0 - c2) * un * un - c2 * gnn
+    r = np.sqrt(B * B - 4.0 * A * C)
+    return (-B - r) / (2.0 * A), (-B + r) / (2.0 * A)

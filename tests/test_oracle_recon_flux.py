@@ -10,6 +10,11 @@ Riemann fluxes and source terms (paper Sec. II.C.1-2).
   random curved metrics with shift (this pins the tetrad, its back-transform
   and the densitisation); supersonic states are upwinded exactly; a
   stationary contact is kept exactly by HLLC and diffused by TVDLF.
+- The signal speeds of both solvers (the coordinate characteristic speeds
+  of TVDLF and the face-tetrad speeds of HLLC, mapped back to coordinates)
+  equal the sound-front speeds of the covariant characteristic condition
+  on random curved metrics with lapse, shift and conformal metric, in both
+  directions; so do the speeds both fluxes report.
 - Momentum sources equal (1/2) sqrt(-g) T^ab d_j g_ab and the energy source
   equals alpha sqrt(gamma) (T^{0b} d_b alpha - alpha T^ab Gamma^0_ab) on
   random metrics with consistent time derivatives.
@@ -199,3 +204,34 @@ def test_geometric_source_balances_pressure(orc):
     Fz, _ = orc.face_flux(grid, 1, "hllc", EOS, {}, *orc.reconstruct(grid, 1, "ppm", p))
     L = orc.rhs(grid, EOS, {}, p, Fx, Fz)
     assert np.abs(synth.interior(grid, L)).max() <= 1e-14
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_signal_speeds_match_covariant_characteristics(orc, seed):
+    """lambda-+ from the 3+1 formula (TVDLF, Courant number) and from the
+    tetrad frame (HLLC) against the roots of (u.xi)^2 = c_s^2 h^ab xi_a xi_b
+    with the front covector xi = (-lambda, delta^n_i) built from the
+    4-metric; c_s^2 = Gamma P / (rho h) for the gamma-law gas.  States up
+    to w ~ 3 in every direction; metrics with alpha in [0.6, 1.2], shift of
+    order 0.3 and a non-flat conformal metric (det 1).  A dropped alpha,
+    beta^n or gamma^nn factor fails by O(0.1)."""
+    rng = np.random.default_rng(300 + seed)
+    gam = EOS["Gth"]
+    for _ in range(20):
+        g = stt.random_point_metric(rng, scale=0.3, shift=0.3)
+        rho = rng.uniform(0.1, 2.0)
+        P = rng.uniform(0.01, 3.0)
+        eps = P / ((gam - 1.0) * rho)
+        prim = np.array([rho, *rng.normal(size=3) * 1.2, P, eps])
+        cs2 = gam * P / (rho * (1.0 + eps + P / rho))
+        for d, n in ((0, 0), (1, 2)):
+            ex = stt.acoustic_speeds(g, prim, n, cs2)
+            scale = max(1.0, abs(ex[0]), abs(ex[1]))
+            for frame in ("coord", "tetrad"):
+                lm, lp = orc.signal_speeds(EOS, g, d, prim, frame)
+                assert abs(lm - ex[0]) <= 1e-12 * scale, (frame, d, lm, ex)
+                assert abs(lp - ex[1]) <= 1e-12 * scale, (frame, d, lp, ex)
+            vmax = max(abs(ex[0]), abs(ex[1]))
+            for riemann in ("hllc", "tvdlf"):
+                _, sp = orc.face_flux_point(EOS, g, d, riemann, prim, prim)
+                assert abs(sp - vmax) <= 1e-12 * scale, (riemann, d, sp, vmax)
