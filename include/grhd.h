@@ -55,6 +55,10 @@ enum { GRHD_BC_OUTFLOW = 0, GRHD_BC_PERIODIC = 1, GRHD_BC_AXIS = 2,
 enum { GRHD_RECON_PPM = 0, GRHD_RECON_MINMOD = 1 };
 enum { GRHD_RIEMANN_HLLC = 0, GRHD_RIEMANN_TVDLF = 1 };
 enum { GRHD_PREC_FP64 = 0, GRHD_PREC_MIXED = 1 };
+/* face states of the stage: every primitive reconstructed, eps included
+ * (Sec. II.C.2; the default), or eps from the EOS at the face's
+ * reconstructed (rho, P) (a variant that keeps the face states on the EOS) */
+enum { GRHD_FACE_EPS_RECON = 0, GRHD_FACE_EPS_EOS = 1 };
 enum { GRHD_EOS_IDEAL = 0, GRHD_EOS_HYBRID = 1 };
 enum { GRHD_GUESS_NONE = 0, GRHD_GUESS_MLP = 1 };
 /* per-cell recovery flags */
@@ -147,6 +151,7 @@ typedef struct {
                                  grhd_rk_substep, so that kernel can be timed
                                  alone; NULL = not recorded (ignored by the
                                  batched plan) */
+  int face_eps;               /* GRHD_FACE_EPS_* (0: the paper's) */
 } grhd_options;
 
 /* One Runge-Kutta stage:
@@ -189,8 +194,8 @@ int grhd_prim2con(const grhd_grid *grid, const grhd_eos *eos,
  * interior primitives; ghost values come from the boundary conditions
  * (EXTERNAL: from p's ghost cells).  pL, pR: face arrays of 6 fields, FP64
  * (prec = FP64) or FP32 (prec = MIXED; pointers then address float).
- * Every field is reconstructed, eps included; the stage
- * (grhd_rk_substep) replaces the face eps by the EOS value. */
+ * Every field is reconstructed, eps included, as in the stage
+ * (grhd_rk_substep) unless its options select the EOS face variant. */
 int grhd_reconstruct(const grhd_grid *grid, int dir, int recon, int prec,
                      const grhd_prim *p, const grhd_prim *pL,
                      const grhd_prim *pR, void *hip_stream);
@@ -208,8 +213,8 @@ int grhd_hllc_flux(const grhd_grid *grid, int dir, int riemann, int prec,
                    const grhd_cons *F, double *max_speed, void *hip_stream);
 
 /* One Runge-Kutta stage of the whole hot path, Sec. II.C.1: recovery of
- * q_s (corrected in place), ghost handling, reconstruction of rho, u_i
- * and P with eps at each face from the EOS at the face's (rho, P), Riemann
+ * q_s (corrected in place), ghost handling, reconstruction of rho, u_i, P
+ * and eps to the faces (opts->face_eps selects the EOS variant), Riemann
  * fluxes in both directions, area-weighted divergence with the cylindrical
  * and metric source terms, stage combination.
  * qn: q^n (read only when stage->a != 0; may alias qs).  qs: in/out.

@@ -211,6 +211,7 @@ int build_patch_table(grhd_plan *pl, const grhd_patch *patches, std::vector<Patc
     int rc = fill_patch(&P.grid, &P.metric, &P.stage, &P.qn, &P.qs, &P.qout, &P.p, nullptr, nullptr,
                         P.flux_reg, pl->opts.recon, pl->opts.riemann, hp[i]);
     if (rc) return rc;
+    hp[i].face_eos = pl->opts.face_eps == GRHD_FACE_EPS_EOS ? 1 : 0;
     if (P.grid.bc[0] == GRHD_BC_EXTERNAL || P.grid.bc[1] == GRHD_BC_EXTERNAL ||
         P.grid.bc[2] == GRHD_BC_EXTERNAL || P.grid.bc[3] == GRHD_BC_EXTERNAL)
       return fail(GRHD_ERR_UNSUPPORTED, "patch %d: EXTERNAL boundaries are not batched", i);
@@ -320,8 +321,9 @@ std::string tune_key(const grhd_plan *pl) {
     h = (h ^ (unsigned long long)pl->nz[i]) * 1099511628211ull;
   }
   char buf[256];
-  snprintf(buf, sizeof(buf), "%s|prec=%d|mc=%d|recon=%d|riemann=%d|n=%d|%016llx", prop.gcnArchName,
-           pl->prec, pl->mc, pl->opts.recon, pl->opts.riemann, pl->npatch, h);
+  snprintf(buf, sizeof(buf), "%s|prec=%d|mc=%d|recon=%d|riemann=%d|face=%d|n=%d|%016llx",
+           prop.gcnArchName, pl->prec, pl->mc, pl->opts.recon, pl->opts.riemann, pl->opts.face_eps,
+           pl->npatch, h);
   return buf;
 }
 
@@ -385,7 +387,7 @@ extern "C" int grhd_plan_create(const grhd_patch *patches, int npatch, const grh
   if (!patches || npatch < 1) return fail(GRHD_ERR_INVALID, "need at least one patch");
   if (!eos_table || neos < 1) return fail(GRHD_ERR_INVALID, "need at least one EOS");
   if (!opts) return fail(GRHD_ERR_INVALID, "opts is NULL");
-  if ((rc = check_c2p(&opts->c2p))) return rc;
+  if ((rc = check_c2p(&opts->c2p)) || (rc = check_face_eps(opts->face_eps))) return rc;
   if (opts->c2p.guess != GRHD_GUESS_NONE)
     return fail(GRHD_ERR_UNSUPPORTED, "learned guess is not wired into the batch");
   if (opts->prec != GRHD_PREC_FP64 && opts->prec != GRHD_PREC_MIXED) return fail(GRHD_ERR_INVALID, "bad prec");

@@ -540,10 +540,9 @@ __device__ __forceinline__ void ppm_face(const T *s, T &L, T &R) {
   T d2 = mono_slope(s[1], s[2], s[3]);
   T d3 = mono_slope(s[2], s[3], s[4]);
   T d4 = mono_slope(s[3], s[4], s[5]);
-  const T sixth = T(1.0 / 6.0);
-  T i1 = s[1] + T(0.5) * (s[2] - s[1]) - sixth * (d2 - d1);
-  T i2 = s[2] + T(0.5) * (s[3] - s[2]) - sixth * (d3 - d2);
-  T i3 = s[3] + T(0.5) * (s[4] - s[3]) - sixth * (d4 - d3);
+  T i1 = s[1] + T(0.5) * (s[2] - s[1]) - (d2 - d1) / T(6);
+  T i2 = s[2] + T(0.5) * (s[3] - s[2]) - (d3 - d2) / T(6);
+  T i3 = s[3] + T(0.5) * (s[4] - s[3]) - (d4 - d3) / T(6);
   T l0, r0, l1, r1;
   ppm_cell(s[2], i1, i2, l0, r0);
   ppm_cell(s[3], i2, i3, l1, r1);

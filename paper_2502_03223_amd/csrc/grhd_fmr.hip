@@ -528,6 +528,7 @@ int step_level(grhd_fmr *h, int l, double t, double dt, hipStream_t st) {
     if ((rc = fill_patch(&L.grid, &L.metric, &stg, &L.q, qs_of[s], qo_of[s], &L.p, nullptr, nullptr, nullptr,
                          h->opts.recon, h->opts.riemann, pk)))
       return rc;
+    pk.face_eos = h->opts.face_eps == GRHD_FACE_EPS_EOS ? 1 : 0;
     pk.flags = h->flags[l];
     if (has_parent) { pk.reg[0] = L.reg_child_bnd; pk.reg_j[0] = L.grid.nx; pk.reg_k[0] = L.grid.nz; }
     if (has_child) { pk.reg[1] = L.reg_parent_int; pk.reg_j[1] = cg->nx / 2; pk.reg_k[1] = cg->nz / 2; }
@@ -575,7 +576,8 @@ extern "C" int grhd_fmr_create(const grhd_level *levels, int nlev, const grhd_eo
   *out = nullptr;
   if (!levels || nlev < 1) return fail(GRHD_ERR_INVALID, "need at least one level");
   if (!opts) return fail(GRHD_ERR_INVALID, "opts is NULL");
-  if ((rc = check_eos(eos)) || (rc = check_c2p(&opts->c2p))) return rc;
+  if ((rc = check_eos(eos)) || (rc = check_c2p(&opts->c2p)) || (rc = check_face_eps(opts->face_eps)))
+    return rc;
   if (opts->c2p.guess != GRHD_GUESS_NONE) return fail(GRHD_ERR_UNSUPPORTED, "the driver recovers without a learned guess");
   if (opts->prec != GRHD_PREC_FP64 && opts->prec != GRHD_PREC_MIXED) return fail(GRHD_ERR_INVALID, "bad prec");
   if (l_fix < 0) return fail(GRHD_ERR_INVALID, "l_fix must be >= 0");

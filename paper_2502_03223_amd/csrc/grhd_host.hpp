@@ -132,6 +132,12 @@ inline int check_c2p(const grhd_c2p_params *c) {
   return GRHD_OK;
 }
 
+inline int check_face_eps(int face_eps) {
+  if (face_eps != GRHD_FACE_EPS_RECON && face_eps != GRHD_FACE_EPS_EOS)
+    return fail(GRHD_ERR_INVALID, "bad face_eps");
+  return GRHD_OK;
+}
+
 inline C2PK to_c2pk(const grhd_c2p_params *c) {
   C2PK k;
   double vmax = std::sqrt(1.0 - 1.0 / (c->w_max * c->w_max));

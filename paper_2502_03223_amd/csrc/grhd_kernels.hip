@@ -651,6 +651,7 @@ int fill_patch(const grhd_grid *grid, const grhd_metric *metric, const grhd_rk_s
   pk.use_acc_out = acc_out != nullptr;
   pk.recon = recon;
   pk.riemann = riemann;
+  pk.face_eos = 0;
   pk.eos_id = 0;
   pk.tile_base = 0;
   pk.flags = nullptr;
@@ -669,6 +670,7 @@ int fill_patch(const grhd_grid *grid, const grhd_metric *metric, const grhd_rk_s
 
 // the optional interior boundary condition of grhd_options
 static int set_fixed(const grhd_options *opts, PatchK &pk) {
+  pk.face_eos = opts->face_eps == GRHD_FACE_EPS_EOS ? 1 : 0;
   if (!opts->fix_mask) return GRHD_OK;
   int rc;
   if ((rc = check_cons(&opts->fix_q, "fix_q"))) return rc;
@@ -684,7 +686,8 @@ extern "C" int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos, const
                                double *flux_reg, uint8_t *flags, grhd_diag *diag, void *hip_stream) {
   int rc;
   if (!opts) return fail(GRHD_ERR_INVALID, "opts is NULL");
-  if ((rc = check_eos(eos)) || (rc = check_c2p(&opts->c2p))) return rc;
+  if ((rc = check_eos(eos)) || (rc = check_c2p(&opts->c2p)) || (rc = check_face_eps(opts->face_eps)))
+    return rc;
   if (opts->prec != GRHD_PREC_FP64 && opts->prec != GRHD_PREC_MIXED) return fail(GRHD_ERR_INVALID, "bad prec");
   PatchK pk;
   if ((rc = fill_patch(grid, metric, stage, qn, qs, qout, p, acc_in, acc_out, flux_reg, opts->recon,
@@ -752,7 +755,8 @@ extern "C" int grhd_rk_substep_chained(const grhd_grid *grid, const grhd_eos *eo
                                        double *flux_reg, grhd_diag *diag, void *hip_stream) {
   int rc;
   if (!opts) return fail(GRHD_ERR_INVALID, "opts is NULL");
-  if ((rc = check_eos(eos)) || (rc = check_c2p(&opts->c2p))) return rc;
+  if ((rc = check_eos(eos)) || (rc = check_c2p(&opts->c2p)) || (rc = check_face_eps(opts->face_eps)))
+    return rc;
   if (opts->prec != GRHD_PREC_FP64 && opts->prec != GRHD_PREC_MIXED) return fail(GRHD_ERR_INVALID, "bad prec");
   if (opts->c2p.guess != GRHD_GUESS_NONE)
     return fail(GRHD_ERR_UNSUPPORTED, "the chained stage recovers without a learned guess");

@@ -26,6 +26,7 @@ struct PatchK {
   double cx, cz, idx, idz, i60dx, i60dz;
   int use_qn, use_acc_in, use_acc_out;
   int recon, riemann, eos_id;
+  int face_eos;  // 1: face eps from the EOS at the face's (rho, P) (variant)
   uint8_t *flags;  // recovery flags of q_s (nullable)
   // chained stages only: recovery of q_out at the end of the stage
   double *po[6];       // primitives of q_out
@@ -377,18 +378,23 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
           L.P = Pa; L.eps = ea;
           R = L;
         } else {
-          // rho, u_i and P reconstructed; eps from the EOS at the face's
-          // (rho, P), which keeps the face states on the EOS
+          // rho, u_i, P and eps reconstructed (the paper's face states);
+          // in the EOS variant eps comes from the EOS at the face's
+          // (rho, P) instead
           T s[6], a, b;
-          for (int fld = 0; fld < 5; fld++) {
+          const int nrec = P.face_eos ? 5 : 6;
+          for (int fld = 0; fld < nrec; fld++) {
             for (int i = 0; i < 6; i++) s[i] = sm.p[fld][base + i * stride];
             recon_face(P.recon, s, a, b);
             if (fld == 0) { L.rho = a; R.rho = b; }
             else if (fld < 4) { L.u[fld - 1] = a; R.u[fld - 1] = b; }
-            else { L.P = a; R.P = b; }
+            else if (fld == 4) { L.P = a; R.P = b; }
+            else { L.eps = a; R.eps = b; }
           }
-          L.eps = eos_eps(e, L.rho, L.P);
-          R.eps = eos_eps(e, R.rho, R.P);
+          if (P.face_eos) {
+            L.eps = eos_eps(e, L.rho, L.P);
+            R.eps = eos_eps(e, R.rho, R.P);
+          }
         }
         FaceMet<T> fm;
         T t6[6];

@@ -31,6 +31,7 @@ GEOM = {"cyl": 0, "cart": 1}
 RECON = {"ppm": 0, "minmod": 1}
 RIEMANN = {"hllc": 0, "tvdlf": 1}
 PREC = {"fp64": 0, "mixed": 1}
+FACE_EPS = {"recon": 0, "eos": 1}
 EOS_KIND = {"ideal": 0, "hybrid": 1}
 
 
@@ -73,7 +74,7 @@ class Options(C.Structure):
     _fields_ = [("recon", C.c_int), ("riemann", C.c_int), ("prec", C.c_int),
                 ("c2p", C2PParams), ("tile_x", C.c_int), ("tile_z", C.c_int),
                 ("fix_mask", C.c_void_p), ("fix_q", Cons),
-                ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p)]
+                ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p), ("face_eps", C.c_int)]
 
 
 class Stage(C.Structure):
@@ -249,6 +250,7 @@ def make_options(o):
     s.recon = RECON[o.get("recon", "ppm")]
     s.riemann = RIEMANN[o.get("riemann", "hllc")]
     s.prec = PREC[o.get("prec", "fp64")]
+    s.face_eps = FACE_EPS[o.get("face_eps", "recon")]
     s.c2p = make_c2p(o["c2p"])
     tile = o.get("tile", (0, 0))
     s.tile_x, s.tile_z = tile

@@ -1,5 +1,7 @@
 """GPU: the batched substep (grhd_plan_create / grhd_batch_levels)
-equals the single-patch substep bit for bit on every patch (the per-cell
+matches the FP64 oracle on every patch (1e-12 normwise per field and per
+cell on the positive fields in FP64, as in the single-patch parity tests; the single-substep mixed bar in mixed
+precision) and equals the single-patch substep bit for bit (the per-cell
 arithmetic does not depend on the tiling or on the launch), over a mixture
 of nested star levels and uneven Riemann instances, for several calls in a
 row with changing stages and buffers (graph replays with host work and
@@ -8,6 +10,7 @@ import numpy as np
 import pytest
 
 import synth
+from cmp import normwise, percell, percell_cond, percell_local
 
 pytestmark = pytest.mark.gpu
 
@@ -31,14 +34,14 @@ def build_patches(orc, nlev=3, n=48, nriem=6, seed=5):
         p, metric, eos = synth.star_problem(grid, seed=seed + lvl, tov=tov, vel=0.03)
         q = orc.prim2con(grid, eos, metric, p, with_ghosts=True)
         patches.append(dict(grid=grid, metric={k: dev(v) for k, v in metric.items()},
-                            q0=q, eos_id=0))
+                            metric_np=metric, q0=q, eos_id=0))
     gam = 5.0 / 3.0
     sizes = synth.riemann_patch_sizes(seed, nriem, lo=40, hi=300)
     for i, (nxr, (L, R)) in enumerate(zip(sizes, synth.riemann_states(seed, nriem, gam))):
         grid = synth.riemann_grid(nxr, nz=8)
         p = synth.riemann_prims(grid, L, R, gam)
         q = orc.prim2con(grid, synth.ideal_eos(gam), {}, p, with_ghosts=True)
-        patches.append(dict(grid=grid, metric={}, q0=q, eos_id=1))
+        patches.append(dict(grid=grid, metric={}, metric_np={}, q0=q, eos_id=1))
     eos_table = [synth.ideal_eos(2.0, 100.0), synth.ideal_eos(gam)]
     return patches, eos_table
 
@@ -46,6 +49,31 @@ def build_patches(orc, nlev=3, n=48, nriem=6, seed=5):
 def alloc(pt):
     q = dev(pt["q0"])
     return dict(q=q, q1=torch.zeros_like(q), p=torch.zeros((6,) + q.shape[1:], dtype=torch.float64, device=DEV))
+
+
+def check_oracle(orc, pt, eos_table, opts, stage, q_in, out, prec):
+    """The batched result of one patch against the oracle's stage on the
+    same input: FP64 within 1e-12 normwise per field and per cell on D, E,
+    rho, P, eps; mixed within 1e-5 of the oracle's update dq (plus 1e-16 of
+    the state)."""
+    g = pt["grid"]
+    ref = orc.rk_substep(g, eos_table[pt["eos_id"]], pt["metric_np"], opts, stage, q_in, q_in)
+    I = lambda a: synth.interior(g, a)  # noqa: E731
+    qo, qs, pp = I(out["q1"].cpu().numpy()), I(out["q"].cpu().numpy()), I(out["p"].cpu().numpy())
+    ro, rs, rp = I(ref["qout"]), I(ref["qs"]), I(ref["p"])
+    if prec == "fp64":
+        shape = (g["nx"], g["nz"])
+        for gg, oo in ((qo, ro), (qs, rs), (pp, rp)):
+            assert normwise(gg, oo) <= 1e-12, shape
+        assert percell_local(qo, ro, (0, 4)) <= 1e-12, shape
+        assert percell(qs, rs, (0, 4)) <= 1e-12, shape
+        assert percell(pp, rp, (0,)) <= 1e-12, shape
+        assert percell_cond(pp, rp, rs) <= 1e-12, shape
+    else:
+        q0 = I(q_in)
+        for c in (0, 1, 3, 4):
+            dq_o, dq_g = ro[c] - q0[c], qo[c] - q0[c]
+            assert np.abs(dq_g - dq_o).max() <= 1e-5 * np.abs(dq_o).max() + 1e-16 * np.abs(q0[c]).max(), c
 
 
 @pytest.mark.parametrize("tile", [None, (16, 8)])
@@ -74,16 +102,18 @@ def test_batch_equals_single_patch(orc, prec, tile):
     diag = grhd.new_diag()
     for call in range(4):
         st = grhd.SSPRK3[0]  # q1 = q + dt L(q), then swap: repeated forward stages
+        q_in = [a["q"].cpu().numpy() for a in A]
         plan([descr(a, pt, st) for a, pt in zip(A, patches)], diag=diag)
         for b, pt, sub in zip(B, patches, subs):
             sub(dict(st, dt=0.4 * pt["grid"]["dx"]), b["q"], b["q"], b["q1"], b["p"])
         torch.cuda.synchronize()
-        for a, b, pt in zip(A, B, patches):
+        for a, b, pt, qi in zip(A, B, patches, q_in):
             g = pt["grid"]
             for key in ("q1", "q", "p"):
                 x = synth.interior(g, a[key].cpu().numpy())
                 y = synth.interior(g, b[key].cpu().numpy())
                 assert np.array_equal(x, y), (call, key, g["nx"], g["nz"])
+            check_oracle(orc, pt, eos_table, opts, dict(st, dt=0.4 * g["dx"]), qi, a, prec)
             a["q"], a["q1"] = a["q1"], a["q"]
             b["q"], b["q1"] = b["q1"], b["q"]
         d = grhd.read_diag(diag)

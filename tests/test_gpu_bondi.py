@@ -125,6 +125,17 @@ def test_bondi_stationary_ppm_early():
     assert errs[0] / errs[1] >= 2.5 and errs[1] / errs[2] >= 2.5, errs
 
 
+@pytest.mark.skip(reason="PPM converges at first order at t = 20M (L1 ratios about 2 per doubling "
+                         "with HLLC); the cause is not found yet, the paper states second order")
+@pytest.mark.parametrize("riemann", ["hllc", "tvdlf"])
+def test_bondi_stationary_ppm_second_order(riemann):
+    """The paper's statement (Sec. III.B.2): the L1 density error of the
+    stationary flow converges at second order with both Riemann solvers.
+    Bar: at least 3x per doubling at t = 20M, N = 64, 128, 256."""
+    errs = [evolve_l1(n, 20.0, riemann=riemann)[0] for n in (64, 128, 256)]
+    assert errs[0] / errs[1] >= 3.0 and errs[1] / errs[2] >= 3.0, errs
+
+
 def test_bondi_stationary_minmod_second_order():
     errs = [evolve_l1(n, 20.0, recon="minmod")[0] for n in (64, 128, 256)]
     assert errs[0] / errs[1] >= 3.0 and errs[1] / errs[2] >= 3.0, errs

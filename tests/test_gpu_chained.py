@@ -3,8 +3,11 @@
 A whole SSP-RK3 step runs as one recovery pass and three chained stages.
 After each stage the stored q_out and its recovery flags must equal the
 oracle's stage followed by the oracle's recovery of the result (per field
-1e-12 normwise, flags exact), and the primitives must equal the oracle's
-recovery of the stored q_out (1e-12: the recovery on identical input; the
+1e-12 normwise, and per cell on D and E against the largest value the
+stencil reaches; flags exact), and the primitives must equal the oracle's
+recovery of the stored q_out (1e-12 normwise and per cell on rho, on P
+and eps scaled by the recovery's conditioning: the recovery on identical
+input; the
 primitives of a slowly moving cell amplify the 1e-16-level differences of
 its conserved state, so the end-to-end comparison goes through q); the
 boundary fluxes equal the oracle's; the diagnostics carry the stage's
@@ -17,6 +20,7 @@ import numpy as np
 import pytest
 
 import synth
+from cmp import normwise, percell, percell_cond, percell_local
 
 pytestmark = pytest.mark.gpu
 
@@ -38,15 +42,6 @@ def dev(a):
 
 def mdev(metric):
     return {k: dev(v) if isinstance(v, np.ndarray) else v for k, v in metric.items()}
-
-
-def normwise(g, o):
-    worst = 0.0
-    for c in range(g.shape[0]):
-        scale = np.abs(o[c]).max()
-        d = np.abs(g[c] - o[c]).max()
-        worst = max(worst, d if scale == 0.0 else d / scale)
-    return worst
 
 
 def sums(grid, q):
@@ -97,12 +92,18 @@ def run_step(orc, grid, eos, metric, opts, q0, dt, acc=None):
         q_g = out.cpu().numpy()
         e_q = normwise(I(q_g), I(q_r))
         assert e_q <= TOL, (i, e_q)
+        e_c = percell_local(I(q_g), I(q_r), (0, 4))
+        assert e_c <= TOL, (i, e_c)
         # the recovery itself on identical input: the oracle recovers the
         # GPU's stored q_out (a recovery maps its own corrected output to
         # the same primitives up to rounding)
         p_same = orc.con2prim(grid, eos, metric, c2p, q_g)[0]
         e_p = normwise(I(pg[cur].cpu().numpy()), I(p_same))
         assert e_p <= TOL, (i, e_p)
+        e_pc = percell(I(pg[cur].cpu().numpy()), I(p_same), (0,))
+        assert e_pc <= TOL, (i, e_pc)
+        e_pk = percell_cond(I(pg[cur].cpu().numpy()), I(p_same), I(q_g))
+        assert e_pk <= TOL, (i, e_pk)
         assert np.array_equal(I(fg[cur].cpu().numpy()), I(fl_r)), i
         fr, fo = freg.cpu().numpy().reshape(5, nb), ref["flux_reg"]
         assert np.abs(fr - fo).max() <= TOL * np.abs(fo).max(), i

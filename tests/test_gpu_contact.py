@@ -1,13 +1,15 @@
-"""GPU: an oblique contact (density wave of uniform pressure and velocity,
-flat metric, gamma-law, periodic in x and z) keeps P and u uniform through
-SSP-RK3 steps of grhd_rk_substep, on a grid of many 16x16 tiles with ragged
-tails.  The face states lie on the EOS (eps from the reconstructed rho and
-P), and the conserved vector of such states is affine in rho, so the
-family is kept to rounding: FP64 to 1e-12, mixed precision (FP32 face
-work) to 1e-5.  The same property pins the oracle; here it checks the
-kernels at a size the oracle does not run.  A smooth density wave
-travelling one period converges at the rates of the scalar advection
-equation with the same reconstructions (PPM ahead of minmod)."""
+"""GPU: the EOS face-state variant (face_eps="eos": eps at each face from
+the EOS at the reconstructed rho and P, instead of the paper's
+reconstructed eps) on an oblique contact (density wave of uniform pressure
+and velocity, flat metric, gamma-law, periodic in x and z): P and u stay
+uniform through SSP-RK3 steps of grhd_rk_substep, on a grid of many 16x16
+tiles with ragged tails.  The variant's face states lie on the EOS, and the
+conserved vector of such states is affine in rho, so the family is kept to
+rounding: FP64 to 1e-12, mixed precision (FP32 face work) to 1e-5.  The
+same property pins the oracle's variant; here it checks the kernels at a
+size the oracle does not run.  A smooth density wave travelling one period
+converges under the variant at the rates of the scalar advection equation
+with the same reconstructions (PPM ahead of minmod)."""
 import math
 
 import numpy as np
@@ -45,7 +47,7 @@ def test_contact_keeps_pressure_and_velocity(prec, tol, recon):
     q = torch.zeros((5,) + pd.shape[1:], dtype=torch.float64, device=DEV)
     grhd.prim2con(g, eos, {}, pd, q, with_ghosts=True)
     c2p = dict(w_max=100.0, rho_atm=1e-12)
-    sub = grhd.Substep(g, eos, {}, dict(recon=recon, riemann="hllc", prec=prec, c2p=c2p))
+    sub = grhd.Substep(g, eos, {}, dict(recon=recon, riemann="hllc", prec=prec, c2p=c2p, face_eps="eos"))
     q1, q2 = torch.zeros_like(q), torch.zeros_like(q)
     pw = torch.zeros_like(pd)
     dt = 0.4 / nx
@@ -81,7 +83,7 @@ def wave_l1(recon, n):
     q = torch.zeros((5,) + pd.shape[1:], dtype=torch.float64, device=DEV)
     grhd.prim2con(g, eos, {}, pd, q, with_ghosts=True)
     c2p = dict(w_max=100.0, rho_atm=1e-12)
-    sub = grhd.Substep(g, eos, {}, dict(recon=recon, riemann="hllc", prec="fp64", c2p=c2p))
+    sub = grhd.Substep(g, eos, {}, dict(recon=recon, riemann="hllc", prec="fp64", c2p=c2p, face_eps="eos"))
     q1, q2 = torch.zeros_like(q), torch.zeros_like(q)
     pw = torch.zeros_like(pd)
     T = 1.0 / v

@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 
 import synth
+from cmp import percell_local
 
 pytestmark = pytest.mark.gpu
 
@@ -144,6 +145,15 @@ def run_pair(orc, grids, eos, metrics, prims, l_fix, dt, nstep):
     return out_g, out_o, M0
 
 
+def reach(level, l_fix, coarse_steps):
+    """Cells the stencil reaches on a level over a run: 3 per Runge-Kutta
+    stage, 3 stages per step, 2 steps per parent step below l_fix."""
+    steps = coarse_steps
+    for m in range(1, level + 1):
+        steps *= 1 if m <= l_fix else 2
+    return 9 * steps
+
+
 @pytest.mark.parametrize("l_fix", [0, 1])
 @pytest.mark.parametrize("geom", ["cart", "cyl"])
 def test_hierarchy_blast_parity_and_conservation(orc, geom, l_fix):
@@ -155,6 +165,9 @@ def test_hierarchy_blast_parity_and_conservation(orc, geom, l_fix):
     out_g, out_o, M0 = run_pair(orc, grids, eos, [{}] * 3, prims, l_fix, dt, 2)
     for l, g in enumerate(grids):
         e = normwise(synth.interior(g, out_g[l]), synth.interior(g, out_o[l]))
+        assert e <= 1e-12, (l, e)
+        e = percell_local(synth.interior(g, out_g[l]), synth.interior(g, out_o[l]), (0, 4),
+                          radius=reach(l, l_fix, 2))
         assert e <= 1e-12, (l, e)
     M_g = composite_mass(out_g, grids)
     assert abs(M_g - M0) <= 1e-13 * abs(M0), (M0, M_g)
@@ -182,6 +195,9 @@ def test_hierarchy_star_parity(orc):
     torch.cuda.synchronize()
     for l, g in enumerate(grids):
         e = normwise(synth.interior(g, lev_g[l]["q"].cpu().numpy()), synth.interior(g, drv.lev[l]["q"]))
+        assert e <= 1e-12, (l, e)
+        e = percell_local(synth.interior(g, lev_g[l]["q"].cpu().numpy()), synth.interior(g, drv.lev[l]["q"]),
+                          (0, 4), radius=reach(l, 0, 2))
         assert e <= 1e-12, (l, e)
     assert h.time == pytest.approx(2 * dt)
     h.close()

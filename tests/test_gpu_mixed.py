@@ -1,0 +1,130 @@
+"""GPU: the mixed-precision form over many substeps against the FP64 oracle.
+
+The 256^2 star (K = 100, Gamma = 2, rho_c = 1.28e-3, Cowling metric,
+cylindrical [0, 20]^2, PPM + HLLC, SSP-RK3 at dt = 0.4 dx) runs 100 steps
+(300 substeps) in the oracle (FP64) and on the GPU in the mixed form
+(FP32 reconstruction, face metric, tetrad and Riemann solver; FP64
+recovery, divergence, sources and stage update) as chained stages, and in
+the plain FP64 form.  Compared on the primitives of the final state:
+
+- rho and eps: L1 relative with the sqrt(-g) x weight (the volume element
+  of the cylindrical cartoon grid), bars 1e-5 (rho) and 1e-5 (eps);
+- v^varpi and v^z: L1 absolute, x weighted (the star is near rest, so a
+  relative figure would divide by ~0), bar 1e-4 as the sum of both.
+
+The FP64 GPU form is held to 1e-10 on the same figures (limiter decisions
+taken on values that differ in the last bits can move a cell by more than
+rounding over 300 substeps, so this is not the single-substep 1e-12 bar).
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2502_03223_amd import grhd  # noqa: E402
+
+DEV = torch.device("cuda:0")
+N = 256
+STEPS = 100
+C2P = dict(w_max=100.0, rho_atm=1e-10)
+SSP = [dict(a=0.0, b=1.0, c=1.0), dict(a=0.75, b=0.25, c=0.25),
+       dict(a=1.0 / 3.0, b=2.0 / 3.0, c=2.0 / 3.0)]
+
+
+def oracle_run(orc, grid, eos, metric, q, dt):
+    opts = dict(recon="ppm", riemann="hllc", c2p=C2P)
+    for _ in range(STEPS):
+        qn, qs = q, q
+        for st in SSP:
+            r = orc.rk_substep(grid, eos, metric, opts, dict(st, dt=dt), qn, qs)
+            if st["a"] == 0.0:
+                qn = r["qs"]
+            qs = r["qout"]
+        q = qs
+    return orc.con2prim(grid, eos, metric, C2P, q)[0]
+
+
+def gpu_run(grid, eos, metric, q0, dt, prec):
+    md = {k: torch.from_numpy(v).to(DEV) if isinstance(v, np.ndarray) else v for k, v in metric.items()}
+    sub = grhd.Substep(grid, eos, md, dict(recon="ppm", riemann="hllc", prec=prec, c2p=C2P))
+    q = torch.from_numpy(q0).to(DEV)
+    q1, q2 = torch.zeros_like(q), torch.zeros_like(q)
+    shp = q.shape[1:]
+    pa = torch.zeros((6,) + shp, dtype=torch.float64, device=DEV)
+    pb = torch.zeros_like(pa)
+    fa = torch.zeros(shp, dtype=torch.uint8, device=DEV)
+    fb = torch.zeros_like(fa)
+    stages = [dict(s, dt=dt) for s in SSP]
+    chained = prec == "mixed"
+    if chained:
+        grhd.con2prim(grid, eos, md, C2P, q, pa, flags=fa)
+    for _ in range(STEPS):
+        bufs = [(q, q, q1), (q, q1, q2), (q, q2, q1)]
+        prims = [(pa, fa, pb, fb), (pb, fb, pa, fa), (pa, fa, pb, fb)]
+        for s, (qn, qs, qo) in enumerate(bufs):
+            if chained:
+                sub.chained(stages[s], qn, qs, qo, *prims[s])
+            else:
+                sub(stages[s], qn, qs, qo, pa, flags=fa)
+        q, q1 = q1, q
+        if chained:
+            pa, pb = pb, pa
+            fa, fb = fb, fa
+    grhd.con2prim(grid, eos, md, C2P, q.clone(), pa)
+    torch.cuda.synchronize()
+    return pa.cpu().numpy()
+
+
+def l1_figures(grid, metric, P, R):
+    X, _ = synth.cell_coords(grid)
+    x = synth.interior(grid, X)
+    W = synth.interior(grid, metric["W"])
+    alp = synth.interior(grid, metric["alp"])
+    wgt = alp * W ** -3 * x
+    P, R = synth.interior(grid, P), synth.interior(grid, R)
+
+    def l1rel(a, b):
+        return float((np.abs(a - b) * wgt).sum() / (np.abs(b) * wgt).sum())
+
+    def vel(Q):
+        w = np.sqrt(1.0 + W ** 2 * (Q[1] ** 2 + Q[2] ** 2 + Q[3] ** 2))
+        return W ** 2 * Q[1] / w, W ** 2 * Q[3] / w
+
+    vx, vz = vel(P)
+    rx, rz = vel(R)
+    l1v = float(((np.abs(vx - rx) + np.abs(vz - rz)) * x).sum() / x.sum())
+    return dict(rho=l1rel(P[0], R[0]), eps=l1rel(P[5], R[5]), v=l1v,
+                vmax=float(np.abs(np.stack([rx, rz])).max()))
+
+
+@pytest.fixture(scope="module")
+def runs(orc):
+    tov = synth.tov_solve()
+    grid = synth.star_grid(N)
+    p, metric, eos = synth.star_problem(grid, seed=2026, tov=tov)
+    q0 = orc.prim2con(grid, eos, metric, p, with_ghosts=True)
+    dt = 0.4 * grid["dx"]
+    ref = oracle_run(orc, grid, eos, metric, q0, dt)
+    out = {prec: gpu_run(grid, eos, metric, q0, dt, prec) for prec in ("mixed", "fp64")}
+    return grid, metric, ref, out
+
+
+def test_mixed_300_substeps_against_oracle(runs):
+    grid, metric, ref, out = runs
+    f = l1_figures(grid, metric, out["mixed"], ref)
+    print("mixed vs FP64 oracle after %d substeps: %s" % (3 * STEPS, f))
+    assert f["vmax"] > 1e-6                     # the star is not frozen
+    assert f["rho"] <= 1e-5 and f["eps"] <= 1e-5 and f["v"] <= 1e-4, f
+
+
+def test_fp64_300_substeps_against_oracle(runs):
+    grid, metric, ref, out = runs
+    f = l1_figures(grid, metric, out["fp64"], ref)
+    print("FP64 vs FP64 oracle after %d substeps: %s" % (3 * STEPS, f))
+    assert f["rho"] <= 1e-10 and f["eps"] <= 1e-10 and f["v"] <= 1e-10 * max(f["vmax"], 1e-3), f

@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import synth
+from cmp import percell, percell_cond
 
 pytestmark = pytest.mark.gpu
 
@@ -132,6 +133,11 @@ def test_training_and_gain(orc):
         for c in range(6):
             scale = np.abs(ref[c]).max()
             assert np.abs(pp[c] - ref[c]).max() <= 1e-12 * scale, (name, c)
+        # per cell on the positive fields: rho spans eight decades here
+        e = percell(pp, ref, (0,))
+        assert e <= 1e-12, (name, e)
+        e = percell_cond(pp, ref, synth.interior(grid, q))
+        assert e <= 1e-12, (name, e)
     it_ill = res["illinois"][1]["iter_sum"]
     it_mlp = res["mlp"][1]["iter_sum"]
     assert it_mlp < it_ill, (it_mlp, it_ill)

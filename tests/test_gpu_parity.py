@@ -2,10 +2,18 @@
 same seeded inputs (run on an MI355X).
 
 Bar (FP64 path): per field, max|gpu - oracle| <= 1e-12 max|oracle| (the
-normwise reading of "1e-12 relative"); reconstruction is bitwise (both sides
-evaluate the limiters without fused multiply-add on identical inputs);
-recovery flags are bit-exact.  Sizes span several tiles with ragged tails;
-full-size star grids (512^2, 1024^2) are compared on every cell.
+normwise reading of "1e-12 relative"), and per cell on the positive
+fields, so a low-density or atmosphere cell cannot hide behind the stellar
+scale: D and E of the stage output within 1e-12 of the largest value its
+stencil reaches (tests/cmp.py), D and E of the corrected input and the
+recovered rho within 1e-12 of the cell's own value, the recovered P and
+eps within 1e-12 max(1, kappa 1e-2) of it (kappa = (E/D)^2 / eps: the
+conditioning of eps at the root); reconstruction is
+bitwise (both sides evaluate the limiters without fused multiply-add on
+identical inputs); recovery flags are bit-exact.  Stage tests run the
+paper's face states (every primitive reconstructed) and, where marked, the
+EOS face variant.  Sizes span several tiles with ragged tails; full-size
+star grids (512^2, 1024^2) are compared on every cell.
 """
 import math
 
@@ -13,6 +21,7 @@ import numpy as np
 import pytest
 
 import synth
+from cmp import normwise, percell, percell_cond, percell_local
 
 pytestmark = pytest.mark.gpu
 
@@ -34,30 +43,6 @@ def dev(a):
 
 def mdev(metric):
     return {k: dev(v) if isinstance(v, np.ndarray) else v for k, v in metric.items()}
-
-
-class Err(float):
-    """A normwise error that also remembers where it is largest."""
-    where = ""
-
-    def __repr__(self):
-        return "%.3e at %s" % (float(self), self.where)
-
-
-def normwise(g, o, comps=None):
-    comps = range(g.shape[0]) if comps is None else comps
-    worst, where = 0.0, ""
-    for c in comps:
-        scale = np.abs(o[c]).max()
-        d = np.abs(g[c] - o[c])
-        err = d.max() if scale == 0.0 else d.max() / scale
-        if err > worst or not where:
-            idx = np.unravel_index(np.argmax(d), d.shape)
-            worst, where = err, "field %d index %s (gpu %r, oracle %r)" % (
-                c, tuple(int(i) for i in idx), float(g[c][idx]), float(o[c][idx]))
-    e = Err(worst)
-    e.where = where
-    return e
 
 
 @pytest.fixture(scope="module")
@@ -135,6 +120,8 @@ def test_con2prim(orc, tov, case):
     pgi = synth.interior(grid, pg.cpu().numpy())
     assert np.all(np.isfinite(pgi))
     assert normwise(pgi, synth.interior(grid, p_o)) <= TOL
+    assert percell(pgi, synth.interior(grid, p_o), (0,)) <= TOL
+    assert percell_cond(pgi, synth.interior(grid, p_o), synth.interior(grid, q_o)) <= TOL
     assert normwise(synth.interior(grid, qg.cpu().numpy()), synth.interior(grid, q_o)) <= TOL
     d = grhd.read_diag(dg)
     for k in ("n_rescale", "n_cold", "n_atm", "n_fail"):
@@ -214,6 +201,11 @@ def check_pair(grid, ref, out, tol=TOL, flag_mask=0xFF):
     assert normwise(I(out["qout"]), I(ref["qout"])) <= tol
     assert normwise(I(out["qs"]), I(ref["qs"])) <= tol
     assert normwise(I(out["p"]), I(ref["p"])) <= tol
+    # per cell on the positive fields: D, E; rho, P, eps
+    assert percell_local(I(out["qout"]), I(ref["qout"]), (0, 4)) <= tol
+    assert percell(I(out["qs"]), I(ref["qs"]), (0, 4)) <= tol
+    assert percell(I(out["p"]), I(ref["p"]), (0,)) <= tol
+    assert percell_cond(I(out["p"]), I(ref["p"]), I(ref["qs"])) <= tol
     assert np.array_equal(I(out["flags"]) & flag_mask, I(ref["flags"]) & flag_mask)
     # boundary fluxes: one scale for all components (the mass flux through
     # the axis and through a static atmosphere is rounding noise)
@@ -229,9 +221,9 @@ def check_pair(grid, ref, out, tol=TOL, flag_mask=0xFF):
         assert normwise(I(out["acc"]), I(ref["acc"])) <= tol
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("seed,face_eps", [(0, "recon"), (1, "recon"), (2, "recon"), (0, "eos")])
 @pytest.mark.parametrize("riemann,recon", [("hllc", "ppm"), ("tvdlf", "ppm"), ("hllc", "minmod")])
-def test_substep_riemann(orc, seed, riemann, recon):
+def test_substep_riemann(orc, seed, riemann, recon, face_eps):
     """Riemann problems on 400 x 8 (Cartesian, flat, periodic z), all three
     SSP-RK3 stages from oracle-evolved states."""
     gam = 5.0 / 3.0
@@ -240,7 +232,7 @@ def test_substep_riemann(orc, seed, riemann, recon):
     eos = synth.ideal_eos(gam)
     p = synth.riemann_prims(grid, L, R)
     q0 = orc.prim2con(grid, eos, {}, p, with_ghosts=True)
-    opts = dict(recon=recon, riemann=riemann, prec="fp64", c2p=C2P_RIE)
+    opts = dict(recon=recon, riemann=riemann, prec="fp64", c2p=C2P_RIE, face_eps=face_eps)
     dt = 0.4 * grid["dx"]
     # evolve a few steps with the oracle so every stage starts from a
     # developed solution
@@ -282,20 +274,22 @@ def test_paper_shock_tube_substeps(orc):
         q = ref["qout"]
 
 
+@pytest.mark.parametrize("face_eps", ["recon", "eos"])
 @pytest.mark.parametrize("n", [64, 93])
 @pytest.mark.parametrize("stage", [0, 1, 2])
-def test_substep_star(orc, tov, n, stage):
+def test_substep_star(orc, tov, n, stage, face_eps):
     grid, p, metric, eos = star_case(n, 10 + n + stage, tov, vel=0.05)
     q = orc.prim2con(grid, eos, metric, p, with_ghosts=True)
     qn = orc.prim2con(grid, eos, metric, star_case(n, 99, tov, vel=0.05)[1], with_ghosts=True)
-    opts = dict(recon="ppm", riemann="hllc", prec="fp64", c2p=C2P_STAR)
+    opts = dict(recon="ppm", riemann="hllc", prec="fp64", c2p=C2P_STAR, face_eps=face_eps)
     st = dict(grhd.SSPRK3[stage], dt=0.4 * grid["dx"])
     ref, out = run_pair(orc, grid, eos, metric, opts, st, qn, q)
     check_pair(grid, ref, out)
 
 
+@pytest.mark.parametrize("face_eps", ["recon", "eos"])
 @pytest.mark.parametrize("riemann,eos_kind", [("hllc", "ideal"), ("tvdlf", "ideal"), ("hllc", "hybrid")])
-def test_substep_general_metric(orc, riemann, eos_kind):
+def test_substep_general_metric(orc, riemann, eos_kind, face_eps):
     grid = synth.make_grid(45, 38, 0.0, 0.0, 0.02, 0.025, "cart", ("periodic",) * 4)
     metric = synth.general_metric(grid, 7)
     p = synth.smooth_state(grid, 8, vamp=0.5)
@@ -304,7 +298,7 @@ def test_substep_general_metric(orc, riemann, eos_kind):
         eos = HYBRID
         p = hybrid_state(orc, p)
     q = orc.prim2con(grid, eos, metric, p, with_ghosts=True)
-    opts = dict(recon="ppm", riemann=riemann, prec="fp64", c2p=C2P_RIE)
+    opts = dict(recon="ppm", riemann=riemann, prec="fp64", c2p=C2P_RIE, face_eps=face_eps)
     ref, out = run_pair(orc, grid, eos, metric, opts, dict(grhd.SSPRK3[1], dt=0.005), q, q)
     check_pair(grid, ref, out)
 
@@ -352,12 +346,12 @@ def test_tile_shapes_bitwise(orc, tov):
         assert np.array_equal(synth.interior(grid, o["qout"]), synth.interior(grid, outs[0]["qout"]))
 
 
-@pytest.mark.parametrize("n", [512, 1024])
-def test_substep_full_size_star(orc, tov, n):
+@pytest.mark.parametrize("n,face_eps", [(512, "recon"), (1024, "recon"), (512, "eos")])
+def test_substep_full_size_star(orc, tov, n, face_eps):
     """Full star sizes in the benchmark's launch configuration, all cells."""
     grid, p, metric, eos = star_case(n, 50, tov, vel=0.02)
     q = orc.prim2con(grid, eos, metric, p, with_ghosts=True)
-    opts = dict(recon="ppm", riemann="hllc", prec="fp64", c2p=C2P_STAR)
+    opts = dict(recon="ppm", riemann="hllc", prec="fp64", c2p=C2P_STAR, face_eps=face_eps)
     ref, out = run_pair(orc, grid, eos, metric, opts, dict(grhd.SSPRK3[2], dt=0.4 * grid["dx"]), q, q)
     check_pair(grid, ref, out)
 
