@@ -29,10 +29,16 @@
  *    last failure of the calling thread.
  *  - Trouble in a single cell during primitive recovery is not a call
  *    error: it is reported through per-cell flags and the diag counters.
+ *  - The single-patch calls never allocate: device scratch (the partial
+ *    records of the diagnostics, and the recovery flags of a stage whose
+ *    caller passes no flags array) lives in a caller-owned workspace, sized
+ *    by grhd_workspace_bytes.  Calls that may run at the same time need
+ *    separate workspaces.
  */
 #ifndef GRHD_H
 #define GRHD_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -43,7 +49,9 @@ typedef enum {
   GRHD_OK = 0,
   GRHD_ERR_INVALID = -1,     /* bad argument: nothing was launched */
   GRHD_ERR_DEVICE = -2,      /* a HIP call or launch failed */
-  GRHD_ERR_UNSUPPORTED = -3  /* valid but not implemented combination */
+  GRHD_ERR_UNSUPPORTED = -3, /* valid but not implemented combination */
+  GRHD_ERR_WORKSPACE = -4    /* the caller's workspace is missing or too
+                                small for this call: nothing was launched */
 } grhd_status;
 
 enum { GRHD_GEOM_CYLINDRICAL = 0, GRHD_GEOM_CARTESIAN = 1 };
@@ -172,6 +180,15 @@ typedef struct {
 
 /* ---------------------------------------------------------------- calls */
 
+/* Device workspace (bytes) that grhd_con2prim, grhd_rk_substep and
+ * grhd_rk_substep_chained need on this grid with every option (diagnostics
+ * on, no caller flags).  The workspace must be 256-byte aligned device
+ * memory owned by the caller; each call uses the parts it needs and
+ * returns GRHD_ERR_WORKSPACE, launching nothing, when they do not fit.  A
+ * call without diag (and, for grhd_rk_substep, with caller flags) needs
+ * none and takes NULL, 0. */
+int grhd_workspace_bytes(const grhd_grid *grid, size_t *bytes);
+
 /* Conservative-to-primitive recovery, Sec. II.C.4 (Galeazzi master
  * function f(z) = z - r / h(z) on [z-, z+], Illinois bracketed root, k
  * rescaling for w_max, zero-temperature recovery when eps < eps_min,
@@ -181,7 +198,8 @@ typedef struct {
 int grhd_con2prim(const grhd_grid *grid, const grhd_eos *eos,
                   const grhd_metric *metric, const grhd_c2p_params *c2p,
                   const grhd_cons *q, const grhd_prim *p, uint8_t *flags,
-                  grhd_diag *diag, void *hip_stream);
+                  grhd_diag *diag, void *workspace, size_t workspace_bytes,
+                  void *hip_stream);
 
 /* Primitive-to-conservative map, eq. (cons_var).  with_ghosts != 0 also
  * converts every ghost cell. */
@@ -224,14 +242,17 @@ int grhd_hllc_flux(const grhd_grid *grid, int dir, int riemann, int prec,
  * acc_in / acc_out: nullable accumulator cell arrays (RK4).
  * flux_reg: nullable, 5 x (2 nz + 2 nx) doubles: the q fluxes on the
  * x-low, x-high, z-low, z-high boundary faces (refluxing hook).
- * flags: nullable uint8 cell array.  diag: nullable. */
+ * flags: nullable uint8 cell array (the recovery flags of q_s; without it
+ * they go to the workspace).  diag: nullable.  workspace: see
+ * grhd_workspace_bytes. */
 int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos,
                     const grhd_metric *metric, const grhd_options *opts,
                     const grhd_rk_stage *stage, const grhd_cons *qn,
                     const grhd_cons *qs, const grhd_cons *qout,
                     const grhd_prim *p, const grhd_cons *acc_in,
                     const grhd_cons *acc_out, double *flux_reg,
-                    uint8_t *flags, grhd_diag *diag, void *hip_stream);
+                    uint8_t *flags, grhd_diag *diag, void *workspace,
+                    size_t workspace_bytes, void *hip_stream);
 
 /* The same stage with the recovery moved to its end (Sec. II.C.1 and
  * II.C.4 in one pass): the call takes the recovery of q_s as input and
@@ -257,7 +278,8 @@ int grhd_rk_substep_chained(const grhd_grid *grid, const grhd_eos *eos,
                             const grhd_prim *p_in, const uint8_t *flags_in,
                             const grhd_prim *p_out, uint8_t *flags_out,
                             const grhd_cons *acc_in, const grhd_cons *acc_out,
-                            double *flux_reg, grhd_diag *diag, void *hip_stream);
+                            double *flux_reg, grhd_diag *diag, void *workspace,
+                            size_t workspace_bytes, void *hip_stream);
 
 /* ------------------------------------------------------------ batched path */
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <mutex>
 #include <string>
@@ -339,63 +340,53 @@ static SubstepFn substep_kernel(int prec, int mc, int shape) {
   return mc == MC_GEN ? pick_shape<double, MC_GEN>(shape) : pick_shape<double, MC_CF>(shape);
 }
 
-// Library-owned device scratch, one buffer per (device, stream, use):
-// use 0 holds the partial records of the diagnostics, use 1 the recovery
-// flags of a substep whose caller passes none.  A buffer is allocated on
-// first use and grown when a larger grid needs more.  Calls that overlap on
-// one stream are ordered by the stream; different streams use different
-// buffers.  The first such call on a stream allocates: make it before
-// capturing calls into a graph.
-struct StreamScratch {
-  int dev;
-  hipStream_t st;
-  int use;
-  void *buf;
-  size_t bytes;
-};
-static std::mutex g_scratch_mu;
-static std::vector<StreamScratch> g_scratch;
-
-static void *stream_scratch(hipStream_t st, int use, size_t bytes) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-  std::lock_guard<std::mutex> lk(g_scratch_mu);
-  for (auto &s : g_scratch)
-    if (s.dev == dev && s.st == st && s.use == use) {
-      if (s.bytes >= bytes) return s.buf;
-      // the old buffer may still be read by work queued on this stream
-      if (hipStreamSynchronize(st) != hipSuccess) return nullptr;
-      (void)hipFree(s.buf);
-      s.buf = nullptr;
-      s.bytes = 0;
-      if (hipMalloc(&s.buf, bytes) != hipSuccess) return nullptr;
-      s.bytes = bytes;
-      return s.buf;
-    }
-  StreamScratch s{dev, st, use, nullptr, 0};
-  if (hipMalloc(&s.buf, bytes) != hipSuccess) return nullptr;
-  s.bytes = bytes;
-  g_scratch.push_back(s);
-  return s.buf;
-}
-
-void *diag_scratch(hipStream_t st, size_t bytes) { return stream_scratch(st, 0, bytes); }
-
-// the fold's chunk results, then n1 recovery and n2 stage records, in the
-// diagnostic scratch of the stream
-struct DiagBufs {
+// The caller's device workspace of the single-patch calls, in 256-byte
+// aligned parts: the fold's chunk results, the recovery records, the stage
+// records and, for a stage whose caller passes no flags array, the recovery
+// flags of q_s.  The library never allocates on these paths; a call whose
+// parts do not fit the workspace it is given launches nothing and returns
+// GRHD_ERR_WORKSPACE.
+struct Workspace {
   FoldPart *lvl;
   C2PPart *p1;
   FluxPart *p2;
+  uint8_t *flags;
 };
-static bool diag_bufs(hipStream_t st, size_t n1, size_t n2, DiagBufs &b) {
-  const size_t l = sizeof(FoldPart) * kFoldMax;
-  char *buf = (char *)diag_scratch(st, l + sizeof(C2PPart) * n1 + sizeof(FluxPart) * n2);
-  if (!buf) return false;
-  b.lvl = (FoldPart *)buf;
-  b.p1 = (C2PPart *)(buf + l);
-  b.p2 = (FluxPart *)(buf + l + sizeof(C2PPart) * n1);
-  return true;
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Bytes of the parts: n1 recovery records, n2 stage records (both with the
+// fold's chunk results when either is nonzero), nflag flag bytes.
+static size_t ws_need(size_t n1, size_t n2, size_t nflag) {
+  size_t o = 0;
+  if (n1 || n2) {
+    o += align256(sizeof(FoldPart) * kFoldMax);
+    o += align256(sizeof(C2PPart) * n1);
+    o += align256(sizeof(FluxPart) * n2);
+  }
+  o += align256(nflag);
+  return o;
+}
+
+int ws_carve(void *ws, size_t bytes, size_t n1, size_t n2, size_t nflag, Workspace &w) {
+  w = Workspace{nullptr, nullptr, nullptr, nullptr};
+  const size_t need = ws_need(n1, n2, nflag);
+  if (need == 0) return GRHD_OK;
+  if (!ws) return fail(GRHD_ERR_WORKSPACE, "this call needs a workspace of %zu bytes (workspace is NULL)", need);
+  if ((uintptr_t)ws % 256) return fail(GRHD_ERR_INVALID, "workspace must be 256-byte aligned");
+  if (bytes < need)
+    return fail(GRHD_ERR_WORKSPACE, "workspace of %zu bytes is too small: this call needs %zu", bytes, need);
+  char *c = (char *)ws;
+  if (n1 || n2) {
+    w.lvl = (FoldPart *)c;
+    c += align256(sizeof(FoldPart) * kFoldMax);
+    w.p1 = (C2PPart *)c;
+    c += align256(sizeof(C2PPart) * n1);
+    w.p2 = (FluxPart *)c;
+    c += align256(sizeof(FluxPart) * n2);
+  }
+  if (nflag) w.flags = (uint8_t *)c;
+  return GRHD_OK;
 }
 
 int shape_index(int tx, int tz) {
@@ -413,6 +404,25 @@ static void con2prim_launch(dim3 grid, hipStream_t st, const GridK &g, const Eos
                             int jlo, int jhi, int klo) {
   hipLaunchKernelGGL((k_con2prim<MC, EK>), grid, dim3(256), 0, st, g, e, cp, m, q, p, flags, part, jlo,
                      jhi, klo);
+}
+
+static int con2prim_blocks_of(const grhd_grid *g) {
+  int jlo = (g->bc[0] == GRHD_BC_EXTERNAL) ? -g->ng : 0;
+  int jhi = (g->bc[1] == GRHD_BC_EXTERNAL) ? g->nx + g->ng : g->nx;
+  int klo = (g->bc[2] == GRHD_BC_EXTERNAL) ? -g->ng : 0;
+  int khi = (g->bc[3] == GRHD_BC_EXTERNAL) ? g->nz + g->ng : g->nz;
+  return ((jhi - jlo + 255) / 256) * (khi - klo);
+}
+
+// the most stage tiles any built shape makes of a grid
+static long long max_stage_tiles(const grhd_grid *g) {
+  long long m = 0;
+  for (int s = 0; s < kNumShapes; s++) {
+    const int tx = kShapes[s].tx, tz = kShapes[s].tz;
+    const long long t = (long long)((g->nx + tile_xshift(g->ng, tx) + tx - 1) / tx) * ((g->nz + tz - 1) / tz);
+    if (t > m) m = t;
+  }
+  return m;
 }
 
 int con2prim_blocks(const GridK &g) {
@@ -484,9 +494,21 @@ extern "C" const char *grhd_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" const char *grhd_version(void) { return "grhd-mi355x 0.1 (gfx950)"; }
 
+extern "C" int grhd_workspace_bytes(const grhd_grid *grid, size_t *bytes) {
+  int rc;
+  if ((rc = check_grid(grid))) return rc;
+  if (!bytes) return fail(GRHD_ERR_INVALID, "bytes is NULL");
+  const size_t n1 = (size_t)con2prim_blocks_of(grid);
+  const size_t n2 = (size_t)max_stage_tiles(grid);
+  const size_t nflag = (size_t)(grid->nz + 2 * grid->ng) * (size_t)grid->pitch;
+  *bytes = ws_need(n1, n2, nflag);
+  return GRHD_OK;
+}
+
 extern "C" int grhd_con2prim(const grhd_grid *grid, const grhd_eos *eos, const grhd_metric *metric,
                              const grhd_c2p_params *c2p, const grhd_cons *q, const grhd_prim *p,
-                             uint8_t *flags, grhd_diag *diag, void *hip_stream) {
+                             uint8_t *flags, grhd_diag *diag, void *workspace, size_t workspace_bytes,
+                             void *hip_stream) {
   int rc;
   if ((rc = check_grid(grid)) || (rc = check_eos(eos)) || (rc = check_metric(metric)) ||
       (rc = check_c2p(c2p)) || (rc = check_cons(q, "q")) || (rc = check_prim(p, "p")))
@@ -498,8 +520,8 @@ extern "C" int grhd_con2prim(const grhd_grid *grid, const grhd_eos *eos, const g
   for (int c = 0; c < 6; c++) pp.p[c] = p->p[c];
   GridK g = to_gridk(grid);
   int nb1 = con2prim_blocks(g);
-  DiagBufs db{nullptr, nullptr, nullptr};
-  if (diag && !diag_bufs(st, nb1, 0, db)) return fail(GRHD_ERR_DEVICE, "diagnostic scratch allocation failed");
+  Workspace db;
+  if ((rc = ws_carve(workspace, workspace_bytes, diag ? nb1 : 0, 0, 0, db))) return rc;
   C2PPart *p1 = db.p1;
   C2PK cp = to_c2pk(c2p);
   cp.reuse_atm = (c2p->reuse_atm && flags) ? 1 : 0;
@@ -679,11 +701,14 @@ static int set_fixed(const grhd_options *opts, PatchK &pk) {
   return GRHD_OK;
 }
 
-extern "C" int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos, const grhd_metric *metric,
-                               const grhd_options *opts, const grhd_rk_stage *stage,
-                               const grhd_cons *qn, const grhd_cons *qs, const grhd_cons *qout,
-                               const grhd_prim *p, const grhd_cons *acc_in, const grhd_cons *acc_out,
-                               double *flux_reg, uint8_t *flags, grhd_diag *diag, void *hip_stream) {
+namespace grhd {
+// The whole stage on a given workspace (the caller's, or the static one of
+// the variant that allocates nothing).
+int rk_substep_ws(const grhd_grid *grid, const grhd_eos *eos, const grhd_metric *metric,
+                  const grhd_options *opts, const grhd_rk_stage *stage, const grhd_cons *qn,
+                  const grhd_cons *qs, const grhd_cons *qout, const grhd_prim *p,
+                  const grhd_cons *acc_in, const grhd_cons *acc_out, double *flux_reg, uint8_t *flags,
+                  grhd_diag *diag, void *workspace, size_t workspace_bytes, void *hip_stream) {
   int rc;
   if (!opts) return fail(GRHD_ERR_INVALID, "opts is NULL");
   if ((rc = check_eos(eos)) || (rc = check_c2p(&opts->c2p)) || (rc = check_face_eps(opts->face_eps)))
@@ -720,21 +745,17 @@ extern "C" int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos, const
   for (int c = 0; c < 5; c++) q.q[c] = qs->q[c];
   for (int c = 0; c < 6; c++) pp.p[c] = p->p[c];
   int nb1 = con2prim_blocks(pk.g), nb2 = pk.tiles_x * pk.tiles_z;
-  DiagBufs db{nullptr, nullptr, nullptr};
-  if (diag && !diag_bufs(st, nb1, nb2, db)) return fail(GRHD_ERR_DEVICE, "diagnostic scratch allocation failed");
+  // the stage kernel reads the recovery flags (all-atmosphere tiles skip
+  // their primitives); without caller flags they go to the workspace
+  const size_t nflag = flags ? 0 : (size_t)(grid->nz + 2 * grid->ng) * (size_t)grid->pitch;
+  Workspace db;
+  if ((rc = ws_carve(workspace, workspace_bytes, diag ? nb1 : 0, diag ? nb2 : 0, nflag, db))) return rc;
   C2PPart *p1 = db.p1;
   FluxPart *p2 = db.p2;
-  // the stage kernel reads the recovery flags (all-atmosphere tiles skip
-  // their primitives); without caller flags they go to library scratch
-  uint8_t *fl = flags;
-  if (!fl) {
-    size_t fb = (size_t)(grid->nz + 2 * grid->ng) * (size_t)grid->pitch;
-    fl = (uint8_t *)stream_scratch(st, 1, fb);
-    if (!fl) return fail(GRHD_ERR_DEVICE, "flag scratch allocation failed");
-  }
+  uint8_t *fl = flags ? flags : db.flags;
   pk.flags = fl;
   C2PK cp = to_c2pk(&opts->c2p);
-  cp.reuse_atm = (opts->c2p.reuse_atm && flags) ? 1 : 0;  // never with the scratch flags
+  cp.reuse_atm = (opts->c2p.reuse_atm && flags) ? 1 : 0;  // never with workspace flags
   if ((rc = launch_con2prim(pk.g, e, cp, pk.m, mc, q, pp, fl, p1, st))) return rc;
   if (opts->ev_begin && hipEventRecord((hipEvent_t)opts->ev_begin, st) != hipSuccess)
     return fail(GRHD_ERR_DEVICE, "hipEventRecord failed");
@@ -744,6 +765,17 @@ extern "C" int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos, const
   if (diag) return launch_diag_final(p1, nb1, p2, nb2, db.lvl, diag, st);
   return GRHD_OK;
 }
+}  // namespace grhd
+
+extern "C" int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos, const grhd_metric *metric,
+                               const grhd_options *opts, const grhd_rk_stage *stage,
+                               const grhd_cons *qn, const grhd_cons *qs, const grhd_cons *qout,
+                               const grhd_prim *p, const grhd_cons *acc_in, const grhd_cons *acc_out,
+                               double *flux_reg, uint8_t *flags, grhd_diag *diag, void *workspace,
+                               size_t workspace_bytes, void *hip_stream) {
+  return rk_substep_ws(grid, eos, metric, opts, stage, qn, qs, qout, p, acc_in, acc_out, flux_reg, flags,
+                       diag, workspace, workspace_bytes, hip_stream);
+}
 
 extern "C" int grhd_rk_substep_chained(const grhd_grid *grid, const grhd_eos *eos,
                                        const grhd_metric *metric, const grhd_options *opts,
@@ -752,7 +784,8 @@ extern "C" int grhd_rk_substep_chained(const grhd_grid *grid, const grhd_eos *eo
                                        const grhd_prim *p_in, const uint8_t *flags_in,
                                        const grhd_prim *p_out, uint8_t *flags_out,
                                        const grhd_cons *acc_in, const grhd_cons *acc_out,
-                                       double *flux_reg, grhd_diag *diag, void *hip_stream) {
+                                       double *flux_reg, grhd_diag *diag, void *workspace,
+                                       size_t workspace_bytes, void *hip_stream) {
   int rc;
   if (!opts) return fail(GRHD_ERR_INVALID, "opts is NULL");
   if ((rc = check_eos(eos)) || (rc = check_c2p(&opts->c2p)) || (rc = check_face_eps(opts->face_eps)))
@@ -788,8 +821,8 @@ extern "C" int grhd_rk_substep_chained(const grhd_grid *grid, const grhd_eos *eo
   EosK e = to_eosk(eos, opts->c2p.rho_atm);
   int mc = metric_class(metric);
   int nt = pk.tiles_x * pk.tiles_z;
-  DiagBufs db{nullptr, nullptr, nullptr};
-  if (diag && !diag_bufs(st, nt, nt, db)) return fail(GRHD_ERR_DEVICE, "diagnostic scratch allocation failed");
+  Workspace db;
+  if ((rc = ws_carve(workspace, workspace_bytes, diag ? nt : 0, diag ? nt : 0, 0, db))) return rc;
   C2PPart *p1 = db.p1;
   FluxPart *p2 = db.p2;
   if (opts->ev_begin && hipEventRecord((hipEvent_t)opts->ev_begin, st) != hipSuccess)

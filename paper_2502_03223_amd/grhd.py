@@ -114,12 +114,13 @@ def lib():
         _lib = C.CDLL(LIB_PATH)
         p, i = C.c_void_p, C.c_int
         sig = {
-            "grhd_con2prim": [p, p, p, p, p, p, p, p, p],
+            "grhd_con2prim": [p, p, p, p, p, p, p, p, p, C.c_size_t, p],
+            "grhd_workspace_bytes": [p, p],
             "grhd_prim2con": [p, p, p, p, p, i, p],
             "grhd_reconstruct": [p, i, i, i, p, p, p, p],
             "grhd_hllc_flux": [p, i, i, i, p, p, p, p, p, p, p],
-            "grhd_rk_substep": [p, p, p, p, p, p, p, p, p, p, p, p, p, p, p],
-            "grhd_rk_substep_chained": [p] * 17,
+            "grhd_rk_substep": [p] * 14 + [p, C.c_size_t, p],
+            "grhd_rk_substep_chained": [p] * 16 + [p, C.c_size_t, p],
             "grhd_fix_cells": [p, p, p, p, p],
             "grhd_fmr_prolong": [p, p, i, p, C.c_double, p, p, p, C.c_double, p, p, p],
             "grhd_fmr_restrict": [p, p, p, p, p],
@@ -276,13 +277,37 @@ def read_diag(t):
 
 # ------------------------------------------------------------ calls
 
-def con2prim(grid, eos, metric, c2p, q, p, flags=None, diag=None):
-    """q (5,rows,pitch) in/out, p (6,rows,pitch) out."""
+def workspace_bytes(grid):
+    """Bytes of device workspace the single-patch calls need on this grid."""
+    n = C.c_size_t(0)
+    g = grid if isinstance(grid, Grid) else make_grid(grid)
+    _check(lib().grhd_workspace_bytes(C.byref(g), C.byref(n)), "grhd_workspace_bytes")
+    return n.value
+
+
+def new_workspace(grid, device="cuda"):
+    """A device workspace for the single-patch calls on this grid (torch
+    allocations are 512-byte aligned)."""
+    return torch.empty(max(workspace_bytes(grid), 256), dtype=torch.uint8, device=device)
+
+
+def _ws_args(ws):
+    if ws is None:
+        return C.c_void_p(0), C.c_size_t(0)
+    return C.c_void_p(ws.data_ptr()), C.c_size_t(ws.numel() * ws.element_size())
+
+
+def con2prim(grid, eos, metric, c2p, q, p, flags=None, diag=None, workspace=None):
+    """q (5,rows,pitch) in/out, p (6,rows,pitch) out.  With diag and no
+    workspace, one is allocated for the call."""
+    if diag is not None and workspace is None:
+        workspace = new_workspace(grid, q.device)
+    wp, wb = _ws_args(workspace)
     rc = lib().grhd_con2prim(
         C.byref(make_grid(grid)), C.byref(make_eos(eos)), C.byref(make_metric(metric)),
         C.byref(make_c2p(c2p)), C.byref(make_cons(q)), C.byref(make_prim(p)),
         C.c_void_p(flags.data_ptr() if flags is not None else 0),
-        C.c_void_p(diag.data_ptr() if diag is not None else 0), _stream())
+        C.c_void_p(diag.data_ptr() if diag is not None else 0), wp, wb, _stream())
     _check(rc, "grhd_con2prim")
 
 
@@ -326,12 +351,17 @@ class Substep:
     """Pre-marshalled arguments of repeated grhd_rk_substep calls (the
     structs are built once; only the stage and buffers change)."""
 
-    def __init__(self, grid, eos, metric, opts):
+    def __init__(self, grid, eos, metric, opts, workspace=None):
+        """workspace: device workspace of grhd_workspace_bytes(grid) bytes
+        (allocated here when not given; calls through one Substep share it,
+        so they must not run at the same time)."""
         self.grid = make_grid(grid)
         self.eos = make_eos(eos)
         self.metric = make_metric(metric)
         self.opts = make_options(opts)
         self._keep = (grid, eos, metric, opts)
+        self.ws = workspace if workspace is not None else new_workspace(self.grid)
+        self._wsa = _ws_args(self.ws)
 
     def __call__(self, stage, qn, qs, qout, p, acc_in=None, acc_out=None, flux_reg=None,
                  flags=None, diag=None, stream=None, events=None):
@@ -350,7 +380,7 @@ class Substep:
             C.byref(make_cons(acc_out)) if acc_out is not None else None,
             C.c_void_p(flux_reg.data_ptr() if flux_reg is not None else 0),
             C.c_void_p(flags.data_ptr() if flags is not None else 0),
-            C.c_void_p(diag.data_ptr() if diag is not None else 0),
+            C.c_void_p(diag.data_ptr() if diag is not None else 0), *self._wsa,
             C.c_void_p(stream) if stream is not None else _stream())
         _check(rc, "grhd_rk_substep")
 
@@ -364,9 +394,9 @@ class Substep:
                 C.byref(st), C.byref(make_cons(qn if qn is not None else qs)),
                 C.byref(make_cons(qs)), C.byref(make_cons(qout)), C.byref(make_prim(p)), None, None,
                 C.c_void_p(0), C.c_void_p(flags.data_ptr() if flags is not None else 0),
-                C.c_void_p(diag.data_ptr() if diag is not None else 0),
+                C.c_void_p(diag.data_ptr() if diag is not None else 0), *self._wsa,
                 C.c_void_p(stream) if stream is not None else _stream())
-        keep = (st, qn, qs, qout, p, diag, flags)
+        keep = (st, qn, qs, qout, p, diag, flags, self.ws)
 
         def call():
             _check(L.grhd_rk_substep(*args), "grhd_rk_substep")
@@ -385,7 +415,7 @@ class Substep:
                 C.byref(make_cons(acc_in)) if acc_in is not None else None,
                 C.byref(make_cons(acc_out)) if acc_out is not None else None,
                 C.c_void_p(flux_reg.data_ptr() if flux_reg is not None else 0),
-                C.c_void_p(diag.data_ptr() if diag is not None else 0),
+                C.c_void_p(diag.data_ptr() if diag is not None else 0), *self._wsa,
                 C.c_void_p(stream) if stream is not None else _stream())
         return st, args
 
@@ -408,7 +438,7 @@ class Substep:
         L = lib()
         st, args = self._chained_args(stage, qn, qs, qout, p_in, flags_in, p_out, flags_out, None,
                                       None, None, diag, stream)
-        keep = (st, qn, qs, qout, p_in, flags_in, p_out, flags_out, diag)
+        keep = (st, qn, qs, qout, p_in, flags_in, p_out, flags_out, diag, self.ws)
 
         def call():
             _check(L.grhd_rk_substep_chained(*args), "grhd_rk_substep_chained")

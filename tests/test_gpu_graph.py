@@ -1,8 +1,11 @@
 """GPU: an SSP-RK3 step of grhd_rk_substep calls captured into a HIP graph
 (torch.cuda.CUDAGraph on a side stream) replays bit for bit as the same
 calls made eagerly, state and diagnostics, on every replay, with eager work
-and synchronisations between the replays.  The first call on the capture
-stream runs before the capture (it allocates the library's scratch)."""
+and synchronisations between the replays.  The library allocates nothing
+on these calls: their scratch is the workspace the caller passes (here the
+Substep's), so the captured graph holds the caller's addresses; an eager
+call on a larger grid between the replays (its own workspace) changes
+nothing."""
 import numpy as np
 import pytest
 
@@ -55,8 +58,20 @@ def test_captured_step_replays_as_eager(prec):
     step(A)
     torch.cuda.synchronize()
     assert same(A["q"], B["q"])
+    # a larger grid with its own Substep (and workspace), run eagerly
+    # between the replays
+    big = synth.star_grid(256)
+    pb, mb_np, _ = synth.star_problem(big, seed=132, tov=synth.tov_solve(), vel=0.02)
+    mb = {k: torch.from_numpy(v).to(DEV) for k, v in mb_np.items()}
+    sub_big = grhd.Substep(big, eos, mb, dict(recon="ppm", riemann="hllc", prec=prec,
+                                              c2p=dict(w_max=100.0, rho_atm=1e-10)))
+    pbd = torch.from_numpy(np.ascontiguousarray(pb)).to(DEV)
+    qb = torch.zeros((5,) + pbd.shape[1:], dtype=torch.float64, device=DEV)
+    grhd.prim2con(big, eos, mb, pbd, qb, with_ghosts=True)
+    qb1 = torch.zeros_like(qb)
     for _ in range(4):
         step(A)
+        sub_big(st[0], qb, qb, qb1, torch.zeros_like(pbd), diag=grhd.new_diag())
         g.replay()
         torch.cuda.synchronize()
         x = A["q"].sum()              # eager work between the replays
