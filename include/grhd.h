@@ -254,6 +254,26 @@ int grhd_rk_substep(const grhd_grid *grid, const grhd_eos *eos,
                     uint8_t *flags, grhd_diag *diag, void *workspace,
                     size_t workspace_bytes, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * stage of grhd_rk_substep, same arguments and results, without a
+ * workspace.  Its scratch (the diagnostic records, and the recovery flags
+ * of q_s when flags is NULL) is a fixed device array of
+ * GRHD_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held until
+ * the process ends; the call allocates nothing.  A grid whose scratch
+ * needs more (grhd_workspace_bytes is an upper bound) returns
+ * GRHD_ERR_WORKSPACE before launching anything.  Every call on one GPU
+ * shares that array: calls that overlap on one GPU (other streams, other
+ * host threads) race and must be ordered by the caller. */
+#define GRHD_NOALLOC_SCRATCH_BYTES (8 << 20)
+int grhd_rk_substep_noalloc(const grhd_grid *grid, const grhd_eos *eos,
+                            const grhd_metric *metric, const grhd_options *opts,
+                            const grhd_rk_stage *stage, const grhd_cons *qn,
+                            const grhd_cons *qs, const grhd_cons *qout,
+                            const grhd_prim *p, const grhd_cons *acc_in,
+                            const grhd_cons *acc_out, double *flux_reg,
+                            uint8_t *flags, grhd_diag *diag, void *hip_stream);
+
 /* The same stage with the recovery moved to its end (Sec. II.C.1 and
  * II.C.4 in one pass): the call takes the recovery of q_s as input and
  * leaves the recovery of q_out as output, so a sequence of stages needs

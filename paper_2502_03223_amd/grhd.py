@@ -120,6 +120,7 @@ def lib():
             "grhd_reconstruct": [p, i, i, i, p, p, p, p],
             "grhd_hllc_flux": [p, i, i, i, p, p, p, p, p, p, p],
             "grhd_rk_substep": [p] * 14 + [p, C.c_size_t, p],
+            "grhd_rk_substep_noalloc": [p] * 15,
             "grhd_rk_substep_chained": [p] * 16 + [p, C.c_size_t, p],
             "grhd_fix_cells": [p, p, p, p, p],
             "grhd_fmr_prolong": [p, p, i, p, C.c_double, p, p, p, C.c_double, p, p, p],
