@@ -142,9 +142,11 @@ typedef struct {
 typedef struct {
   int recon, riemann, prec;   /* GRHD_RECON_*, GRHD_RIEMANN_*, GRHD_PREC_* */
   grhd_c2p_params c2p;
-  int tile_x, tile_z;         /* 0, 0 = library default (16 x 16; 16 x 8
-                                 on grids of fewer than 1536 such tiles,
-                                 128 for the general metric class) */
+  int tile_x, tile_z;         /* 0, 0 = library default (16 x 15; 16 x 7
+                                 on grids of fewer than 1536 tiles of
+                                 16 x 16, 128 for the general metric
+                                 class).  Built: 16 x 15, 16 x 7, 16 x 16,
+                                 16 x 8, 32 x 8, 32 x 16, 64 x 8 */
   const uint8_t *fix_mask;    /* optional interior boundary condition
                                  (nullable; grhd_rk_substep and
                                  grhd_rk_substep_chained): on interior
@@ -288,7 +290,7 @@ int grhd_rk_substep_noalloc(const grhd_grid *grid, const grhd_eos *eos,
  * must not alias p_in, flags_out not flags_in.
  * diag: the recovery counts refer to q_out; Mb and J are sums of the
  * stored (corrected) q_out.  The learned guess, tile shapes other than
- * 16 x 16 and EXTERNAL sides (whose ghosts would need a recovery of their
+ * 16 x 15 and EXTERNAL sides (whose ghosts would need a recovery of their
  * own) return GRHD_ERR_UNSUPPORTED.  Other arguments as grhd_rk_substep;
  * ev_begin/ev_end bracket the one kernel of the call. */
 int grhd_rk_substep_chained(const grhd_grid *grid, const grhd_eos *eos,
@@ -419,7 +421,7 @@ int grhd_fmr_reflux(const grhd_grid *parent, const grhd_cons *q_parent,
  * steps its parent is restricted, refluxed and recovered.  create: copies
  * the level descriptors (device buffers stay the caller's), recovers every
  * level with a child into its first slice.  step: one step dt0 of level 0
- * (all finer levels follow).  Single path kernels on 16 x 16 tiles (16 x 8
+ * (all finer levels follow).  Single path kernels on 16 x 15 tiles (16 x 7
  * on grids of fewer than 1536 tiles of 16 x 16).  The driver owns one
  * recovery flag array per level (device memory, freed by destroy, which
  * first waits for the device to finish queued work). */

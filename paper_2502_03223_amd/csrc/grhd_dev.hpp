@@ -572,9 +572,12 @@ __device__ __forceinline__ void recon_face(int recon, const T *s, T &L, T &R) {
 }
 
 // 6-point centred interpolation to the face (metric is smooth) and the
-// sixth-order centred first derivative.
+// sixth-order centred first derivative, both without contraction into FMA:
+// every caller (the face loops, the per-cell atmosphere faces) rounds them
+// identically.
 template <class T>
 __device__ __forceinline__ T lagrange6(const T *a) {
+#pragma clang fp contract(off)
   return (T(3) * a[0] - T(25) * a[1] + T(150) * a[2] + T(150) * a[3] - T(25) * a[4] +
           T(3) * a[5]) * T(1.0 / 256.0);
 }

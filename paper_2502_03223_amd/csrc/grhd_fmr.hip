@@ -534,10 +534,10 @@ int step_level(grhd_fmr *h, int l, double t, double dt, hipStream_t st) {
     if (has_child) { pk.reg[1] = L.reg_parent_int; pk.reg_j[1] = cg->nx / 2; pk.reg_k[1] = cg->nz / 2; }
     pk.reg_w = kW[s];
     // grids of few 16 x 16 tiles (under two per workgroup slot of the
-    // chip) take 16 x 8 tiles: twice the workgroups, half the latency of
-    // the slowest (star) tile
+    // chip) take 16 x 7 tiles: twice the workgroups, half the latency of
+    // the slowest (star) tile; larger ones 16 x 15
     const int shape = ((long long)((L.grid.nx + 15) / 16) * ((L.grid.nz + 15) / 16) < 1536)
-                          ? shape_index(16, 8) : h->shape;
+                          ? shape_index(16, 7) : h->shape;
     int tx, tz;
     shape_of(shape, &tx, &tz);
     pk.xshift = tile_xshift(L.grid.ng, tx);
@@ -605,7 +605,7 @@ extern "C" int grhd_fmr_create(const grhd_level *levels, int nlev, const grhd_eo
   h->order.assign(nlev, {0, 1, 2});
   h->ns.assign(nlev, 0);
   h->ts.assign(nlev, {0.0, 0.0, 0.0});
-  h->shape = shape_index(16, 16);
+  h->shape = shape_index(16, 15);
   h->flags.assign(nlev, nullptr);
   for (int l = 0; l < nlev; l++) {
     const size_t fb = (size_t)(levels[l].grid.nz + 2 * levels[l].grid.ng) * (size_t)levels[l].grid.pitch;

@@ -261,23 +261,24 @@ k_flux(GridK g, EosK e, MetK m, int dir, int riemann, Ptr6<T> Lp, Ptr6<T> Rp, Q5
 // kernel folds the records afterwards.  (Handing tiles out through a global
 // counter costs two same-address atomics per workgroup, which serialise
 // across the XCDs and cost more than the imbalance they remove.)
-// Waves per SIMD the register allocation must allow: the FP64 16 x 16 and
-// 16 x 8 instances of the conformally flat class fit at least three
-// workgroups per CU in LDS, so their registers are held to three waves;
-// the FP32 16 x 16 instance fits four (31 KB of LDS) and is held to four
-// (113 registers, no spilling).
+// Waves per SIMD the register allocation must allow: the FP64 16-wide
+// instances of the conformally flat class fit at least three workgroups per
+// CU in LDS, so their registers are held to three waves; the FP32 16 x 16
+// and 16 x 15 instances fit four (31 KB of LDS) and are held to four.
 template <class T, int MC, int TX, int TZ>
 constexpr int substep_waves() {
-  return (sizeof(T) == 8 && MC == MC_CF && TX == 16 && (TZ == 16 || TZ == 8)) ? 3
-         : (sizeof(T) == 4 && MC == MC_CF && TX == 16 && TZ == 16)             ? 4
-                                                                               : 1;
+  return (sizeof(T) == 8 && MC == MC_CF && TX == 16 && TZ >= 7) ? 3
+         : (sizeof(T) == 4 && MC == MC_CF && TX == 16 && TZ >= 15) ? 4
+                                                                   : 1;
 }
+
+constexpr int CHAIN_TZ = 15;  // tiles of the chained stage: 16 x 15
 
 // The chained instances: as above, except that the FP32 hybrid-EOS
 // recovery would spill at four waves and stays unconstrained.
 template <class T, int MC, int EK>
 constexpr int chain_waves() {
-  return (sizeof(T) == 4 && EK != GRHD_EOS_IDEAL) ? 1 : substep_waves<T, MC, 16, 16>();
+  return (sizeof(T) == 4 && EK != GRHD_EOS_IDEAL) ? 1 : substep_waves<T, MC, 16, CHAIN_TZ>();
 }
 
 template <class T, int MC, int TX, int TZ>
@@ -294,13 +295,13 @@ k_substep(PatchK P, EosK e, FluxPart *part2) {
   if (part2) flux_block_partial<NT>(cm, mb, jm, &part2[t], red);
 }
 
-// The chained stage: the same tile work on 16 x 16 tiles, ending with the
+// The chained stage: the same tile work on 16 x CHAIN_TZ tiles, ending with the
 // recovery of q_out for the next stage.  Records: part1[tile] (recovery of
 // q_out), part2[tile] (stage diagnostics).
 template <class T, int MC, int EK>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(chain_waves<T, MC, EK>())))
 k_substep_chain(PatchK P, EosK e, C2PPart *part1, FluxPart *part2) {
-  __shared__ TileSmem<T, MC, 16, 16> sm;
+  __shared__ TileSmem<T, MC, 16, CHAIN_TZ> sm;
   __shared__ double red[NT / 64][3];
   __shared__ unsigned long long red1[NT / 64][6];
   const int t = blockIdx.x;
@@ -308,7 +309,7 @@ k_substep_chain(PatchK P, EosK e, C2PPart *part1, FluxPart *part2) {
   C2PAcc acc{};
   int tx, tz;
   tile_of(t, P.tiles_x, P.tiles_z, tx, tz);
-  substep_tile<T, MC, 16, 16, true, EK>(P, e, tx, tz, sm, cm, mb, jm, acc);
+  substep_tile<T, MC, 16, CHAIN_TZ, true, EK>(P, e, tx, tz, sm, cm, mb, jm, acc);
   if (part2) {
     flux_block_partial<NT>(cm, mb, jm, &part2[t], red);
     c2p_counts_partial<NT>(acc.n, &part1[t], red1);
@@ -320,8 +321,11 @@ k_substep_chain(PatchK P, EosK e, C2PPart *part1, FluxPart *part2) {
 using SubstepFn = void (*)(PatchK, EosK, FluxPart *);
 
 struct TileShape { int tx, tz; };
-static const TileShape kShapes[] = {{32, 8}, {32, 16}, {64, 8}, {16, 16}, {16, 8}};
-constexpr int kNumShapes = 5;
+// 16 x 15 and 16 x 7 tiles have 511 and 247 faces: two (one) full passes of
+// the 256 threads over the faces, where 16 x 16 (544) and 16 x 8 (280) leave
+// a third (second) pass for a few faces
+static const TileShape kShapes[] = {{32, 8}, {32, 16}, {64, 8}, {16, 16}, {16, 8}, {16, 15}, {16, 7}};
+constexpr int kNumShapes = 7;
 
 template <class T, int MC>
 static SubstepFn pick_shape(int s) {
@@ -330,6 +334,8 @@ static SubstepFn pick_shape(int s) {
     case 1: return k_substep<T, MC, 32, 16>;
     case 2: return k_substep<T, MC, 64, 8>;
     case 4: return k_substep<T, MC, 16, 8>;
+    case 5: return k_substep<T, MC, 16, 15>;
+    case 6: return k_substep<T, MC, 16, 7>;
     default: return k_substep<T, MC, 16, 16>;
   }
 }
@@ -719,18 +725,18 @@ int rk_substep_ws(const grhd_grid *grid, const grhd_eos *eos, const grhd_metric 
                        opts->riemann, pk)))
     return rc;
   if ((rc = set_fixed(opts, pk))) return rc;
-  // default 16 x 16: the smallest halo per cell of the built shapes, and
-  // the FP64 instance fits three workgroups per CU in LDS; grids of few
-  // such tiles take 16 x 8 (twice the workgroups, half the length of the
-  // slowest tile): under 1536 tiles for the conformally flat class, under
-  // 128 for the general one, whose 16 x 8 instance holds fewer waves
-  int shape = 3;
+  // default 16 x 15: two full passes of the workgroup over the faces, a
+  // small halo per cell, and the FP64 instance fits three workgroups per CU
+  // in LDS; grids of few such tiles take 16 x 7 (twice the workgroups, half
+  // the length of the slowest tile): under 1536 tiles of 16 x 16 for the
+  // conformally flat class, under 128 for the general one
+  int shape = shape_index(16, 15);
   if (opts->tile_x || opts->tile_z) {
     shape = shape_index(opts->tile_x, opts->tile_z);
     if (shape < 0) return fail(GRHD_ERR_UNSUPPORTED, "tile %dx%d not built", opts->tile_x, opts->tile_z);
   } else {
     const long long t16 = (long long)((grid->nx + 15) / 16) * ((grid->nz + 15) / 16);
-    if (t16 < (metric_class(metric) == MC_CF ? 1536 : 128)) shape = shape_index(16, 8);
+    if (t16 < (metric_class(metric) == MC_CF ? 1536 : 128)) shape = shape_index(16, 7);
   }
   int tx, tz;
   shape_of(shape, &tx, &tz);
@@ -793,8 +799,8 @@ extern "C" int grhd_rk_substep_chained(const grhd_grid *grid, const grhd_eos *eo
   if (opts->prec != GRHD_PREC_FP64 && opts->prec != GRHD_PREC_MIXED) return fail(GRHD_ERR_INVALID, "bad prec");
   if (opts->c2p.guess != GRHD_GUESS_NONE)
     return fail(GRHD_ERR_UNSUPPORTED, "the chained stage recovers without a learned guess");
-  if ((opts->tile_x || opts->tile_z) && !(opts->tile_x == 16 && opts->tile_z == 16))
-    return fail(GRHD_ERR_UNSUPPORTED, "the chained stage is built for 16 x 16 tiles only");
+  if ((opts->tile_x || opts->tile_z) && !(opts->tile_x == 16 && opts->tile_z == CHAIN_TZ))
+    return fail(GRHD_ERR_UNSUPPORTED, "the chained stage is built for 16 x %d tiles only", CHAIN_TZ);
   PatchK pk;
   if ((rc = fill_patch(grid, metric, stage, qn, qs, qout, p_in, acc_in, acc_out, flux_reg, opts->recon,
                        opts->riemann, pk)))
@@ -816,7 +822,7 @@ extern "C" int grhd_rk_substep_chained(const grhd_grid *grid, const grhd_eos *eo
   pk.cp.reuse_atm = opts->c2p.reuse_atm ? 1 : 0;
   pk.xshift = tile_xshift(grid->ng, 16);
   pk.tiles_x = (grid->nx + pk.xshift + 15) / 16;
-  pk.tiles_z = (grid->nz + 15) / 16;
+  pk.tiles_z = (grid->nz + CHAIN_TZ - 1) / CHAIN_TZ;
   hipStream_t st = (hipStream_t)hip_stream;
   EosK e = to_eosk(eos, opts->c2p.rho_atm);
   int mc = metric_class(metric);

@@ -181,6 +181,197 @@ __device__ __forceinline__ void finish_cell(const PatchK &P, const EosK &e, unsi
   jm += v[2] * dV;
 }
 
+// Classification of an inner 16-wide tile (its halo inside the grid, rows
+// 16-byte aligned in the flag array) from the recovery flags with wide
+// loads: 16 flag bytes per tile row (one 16-byte load), the three bytes on
+// each side of the row (one aligned 4-byte load each), and the six halo
+// rows above and below.  Returns this thread's share: false when one of the
+// bytes it loaded lacks GRHD_FLAG_ATM.  e0(k) = element of cell (j0, k).
+template <int TZ>
+__device__ __forceinline__ bool atm_flags16(const PatchK &P, int j0, int k0) {
+  const int tid = threadIdx.x;
+  constexpr int NL = 3 * TZ + 6;
+  if (tid >= NL) return true;
+  const GridK &g = P.g;
+  const unsigned A = 0x04040404u;  // GRHD_FLAG_ATM in every byte
+  int row, kind;                   // kind 0: 16 bytes, 1: left side, 2: right side
+  if (tid < TZ) { row = tid; kind = 0; }
+  else if (tid < 2 * TZ) { row = tid - TZ; kind = 1; }
+  else if (tid < 3 * TZ) { row = tid - 2 * TZ; kind = 2; }
+  else { const int h = tid - 3 * TZ; row = h < 3 ? h - 3 : TZ + h - 3; kind = 0; }
+  const unsigned e0 = cell_idx32(g, j0, k0 + row);
+  const uint8_t *f = P.flags;
+  if (kind == 0) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(f + e0);
+    return ((v.x & v.y & v.z & v.w) & A) == A;
+  }
+  if (kind == 1) {
+    const unsigned v = *reinterpret_cast<const unsigned *>(f + e0 - 4);
+    return ((v | 0xFFu) & A) == A;          // bytes 1..3: cells j0-3 .. j0-1
+  }
+  const unsigned v = *reinterpret_cast<const unsigned *>(f + e0 + 16);
+  return ((v | 0xFF000000u) & A) == A;      // bytes 0..2: cells j0+16 .. j0+18
+}
+
+// The global loads of an inner tile that the all-atmosphere stage needs,
+// one cell per thread: the cell's own states (q_s, q^n, accumulator) and
+// lapse and W on its cross-shaped 7-point stencils (x: ax, wx at j-3..j+3;
+// z: az, wz at k-3..k+3; the centre value is in both).  They are issued
+// together with the classification's flag loads, so an all-atmosphere tile
+// makes one memory round trip before its arithmetic.
+template <int TX, int TZ>
+struct LeanLoads {
+  static constexpr int CPT = (TX * TZ + NT - 1) / NT;
+  unsigned ic[CPT];
+  double qs5[CPT][5], qn5[CPT][5], ai5[CPT][5];
+  double ax[CPT][7], wx[CPT][7], az[CPT][7], wz[CPT][7];
+};
+
+template <int TX, int TZ>
+__device__ __forceinline__ void lean_issue(const PatchK &P, int j0, int k0, LeanLoads<TX, TZ> &L) {
+  using LL = LeanLoads<TX, TZ>;
+  const GridK &g = P.g;
+  const int tid = threadIdx.x;
+  const unsigned pitch = (unsigned)g.pitch;
+#pragma unroll
+  for (int ci = 0; ci < LL::CPT; ci++) {
+    const int c = tid + ci * NT;
+    const int jj = c % TX, kk = c / TX;
+    const unsigned ic = cell_idx32(g, j0 + jj, k0 + kk);
+    L.ic[ci] = ic;
+    if (c < TX * TZ) {
+      for (int m = 0; m < 5; m++) L.qs5[ci][m] = ld32(P.qs[m], ic);
+      if (P.use_qn)
+        for (int m = 0; m < 5; m++) L.qn5[ci][m] = ld32(P.qn[m], ic);
+      if (P.use_acc_in)
+        for (int m = 0; m < 5; m++) L.ai5[ci][m] = ld32(P.acc_in[m], ic);
+      for (int i = 0; i < 7; i++) {
+        const unsigned ix = ic - 3u + (unsigned)i, iz = ic + (unsigned)(i - 3) * pitch;
+        L.ax[ci][i] = mval32(P.m, GRHD_M_ALP, ix);
+        L.wx[ci][i] = mval32(P.m, GRHD_M_W, ix);
+        L.az[ci][i] = mval32(P.m, GRHD_M_ALP, iz);
+        L.wz[ci][i] = mval32(P.m, GRHD_M_W, iz);
+      }
+    }
+  }
+}
+
+// Atmosphere face flux (conformally flat class): the normal-momentum flux
+// alpha W^-3 P_atm and the signal speed alpha c_s W at the face whose
+// 6-point stencil starts at a[0], w[0].  The expressions of the general
+// path's atmosphere faces.
+template <class T>
+__device__ __forceinline__ T atm_face(const double *a, const double *w, T Pa, T cs_atm, T &sp) {
+  T t6[6];
+  for (int i = 0; i < 6; i++) t6[i] = (T)a[i];
+  const T alp = lagrange6(t6);
+  for (int i = 0; i < 6; i++) t6[i] = (T)w[i];
+  const T W = lagrange6(t6);
+  T sg = T(1) / (W * W * W);
+  sp = alp * (cs_atm * W);
+  return sg * (alp * Pa);
+}
+
+// The whole stage of an inner all-atmosphere tile of the conformally flat
+// class (halo inside the grid, every cell of the halo flagged ATM by the
+// recovery), one cell per thread and no shared memory: each thread
+// evaluates the four faces of its cell from the stencils in registers (a
+// face between two cells is evaluated by both, with the same operations on
+// the same values, hence the same bits), the lapse and W derivatives, the
+// divergence, sources and stage update.  Every value is computed with the
+// same expressions in the same order as the atmosphere branch of the
+// general tile code below, so a cell's result does not depend on the path
+// its tile takes.  Inner tiles have no grid-boundary faces (no flux
+// register entries); a refinement-register face is added by the cell on its
+// high side, as in the general code.
+template <class T, int TX, int TZ, bool CHAIN, int EK>
+__device__ __forceinline__ void lean_atm_tile(const PatchK &P, const EosK &e, int j0, int k0,
+                                              const LeanLoads<TX, TZ> &ld, double &cmax_out,
+                                              double &mb_out, double &jm_out, C2PAcc &acc) {
+  constexpr int CPT = LeanLoads<TX, TZ>::CPT;
+  const GridK &g = P.g;
+  const int tid = threadIdx.x;
+  const bool cyl = (g.geom == GRHD_GEOM_CYLINDRICAL);
+  const T Pa = (T)e.P_atm, cs_atm = (T)e.cs_atm;
+  const double cx = P.cx, cz = P.cz;
+  const bool regs = P.reg[0] || P.reg[1];
+  const double rhw2_atm = e.rhw2_atm;
+  const double i60dx = P.i60dx, i60dz = P.i60dz;
+  double cmax = 0.0, mb = 0.0, jm = 0.0;
+#pragma unroll
+  for (int ci = 0; ci < CPT; ci++) {
+#pragma clang fp contract(off)
+    const int c = tid + ci * NT;
+    if (!(c < TX * TZ)) continue;
+    const int jj = c % TX, kk = c / TX;
+    const int j = j0 + jj, k = k0 + kk;
+    const unsigned ic = ld.ic[ci];
+    // the four faces: left and right x faces, bottom and top z faces
+    T sp;
+    const T fxl = atm_face<T>(ld.ax[ci], ld.wx[ci], Pa, cs_atm, sp);
+    cmax = fmax(cmax, (double)sp * cx);
+    const T fxr = atm_face<T>(ld.ax[ci] + 1, ld.wx[ci] + 1, Pa, cs_atm, sp);
+    cmax = fmax(cmax, (double)sp * cx);
+    const T fzb = atm_face<T>(ld.az[ci], ld.wz[ci], Pa, cs_atm, sp);
+    cmax = fmax(cmax, (double)sp * cz);
+    const T fzt = atm_face<T>(ld.az[ci] + 1, ld.wz[ci] + 1, Pa, cs_atm, sp);
+    cmax = fmax(cmax, (double)sp * cz);
+    if (regs) {
+      double fv[5] = {0.0, (double)fxl, 0.0, 0.0, 0.0};
+      fmr_reg_add<TX, TZ>(P, true, j, k, jj, kk, fv);
+      double fw[5] = {0.0, 0.0, 0.0, (double)fzb, 0.0};
+      fmr_reg_add<TX, TZ>(P, false, j, k, jj, kk, fw);
+    }
+    double xc = g.x0 + (j + 0.5) * g.dx;
+    const double xl = g.x0 + j * g.dx, xr = g.x0 + (j + 1) * g.dx;
+    const double ivx = cyl ? 1.0 / (xc * g.dx) : P.idx, ivz = P.idz;
+    double gm[GRHD_NMET], dg[2 * GRHD_NMET];
+    for (int i = 0; i < GRHD_NMET; i++) { gm[i] = P.m.c[i]; dg[i] = 0.0; dg[GRHD_NMET + i] = 0.0; }
+    gm[GRHD_M_ALP] = ld.ax[ci][3];
+    gm[GRHD_M_W] = ld.wx[ci][3];
+    if (P.m.f[GRHD_M_ALP]) {
+      dg[GRHD_M_ALP] = deriv6(ld.ax[ci], i60dx);
+      dg[GRHD_NMET + GRHD_M_ALP] = deriv6(ld.az[ci], i60dz);
+    }
+    if (P.m.f[GRHD_M_W]) {
+      dg[GRHD_M_W] = deriv6(ld.wx[ci], i60dx);
+      dg[GRHD_NMET + GRHD_M_W] = deriv6(ld.wz[ci], i60dz);
+    }
+    double L[5];
+    {
+      const double Fl = (double)fxl, Fr = (double)fxr;
+      const double divx1 = cyl ? (xr * Fr - xl * Fl) * ivx : (Fr - Fl) * ivx;
+      const double divz3 = ((double)fzt - (double)fzb) * ivz;
+      double s[5];
+      sources_atm_cf(gm, dg, xc, g.geom, e.P_atm, rhw2_atm, s);
+      L[0] = 0.0; L[1] = s[1] - divx1; L[2] = 0.0; L[3] = s[3] - divz3; L[4] = 0.0;
+    }
+    double dV = cyl ? 2.0 * M_PI * xc * g.dx * g.dz : g.dx * g.dz;
+    const bool fixed = P.fix_mask && ld32(P.fix_mask, ic);
+    double v[5];
+    for (int m = 0; m < 5; m++) {
+      v[m] = P.b * ld.qs5[ci][m] + P.cdt * L[m];
+      if (P.use_qn) v[m] += P.a * ld.qn5[ci][m];
+      if (P.use_acc_in) v[m] += P.gdt * ld.ai5[ci][m];
+      if (fixed) v[m] = ld32(P.fix_q[m], ic);
+      if (!CHAIN) {
+        st32(P.qo[m], ic, v[m]);
+        if (m == 0) mb += v[m] * dV;
+        if (m == 2) jm += v[m] * dV;
+      }
+      if (P.use_acc_out) {
+        double av = P.e * L[m];
+        if (P.use_acc_in) av += P.d * ld.ai5[ci][m];
+        st32(P.acc_out[m], ic, av);
+      }
+    }
+    finish_cell<MC_CF, EK, CHAIN>(P, e, ic, gm[GRHD_M_W], gm + GRHD_M_GXX, xc, dV, v, mb, jm, acc);
+  }
+  cmax_out = cmax;
+  mb_out = mb;
+  jm_out = jm;
+}
+
 // One tile of one patch.  cmax, mb, jm receive this thread's share of the
 // tile's diagnostics (max Courant number, sums of q_D dV and q_Sphi dV of
 // the stored q_out); with CHAIN, acc its recovery statistics.
@@ -210,10 +401,26 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
   // part all addresses come first, then all loads, then all LDS stores.
   // Boundary conditions are an index map with velocity parities.
   bool tile_atm;
+  // a tile whose halo lies inside the grid reads every cell where it is
+  // (no boundary map, no parities)
+  const bool inner = j0 >= 3 && j0 + TX + 3 <= nx && k0 >= 3 && k0 + TZ + 3 <= nz;
+  // inner 16-wide tiles with 16-byte aligned flag rows are classified from
+  // wide flag loads first; an all-atmosphere one of the conformally flat
+  // class then stages only its lapse and W
+  if constexpr (MC == MC_CF) {
+    const bool fast_class = TX == 16 && inner && P.flags != nullptr && (g.pitch & 15) == 0 &&
+                            ((uintptr_t)P.flags & 15) == 0;
+    if (fast_class) {
+      LeanLoads<TX, TZ> ld;
+      lean_issue<TX, TZ>(P, j0, k0, ld);
+      const bool mine = atm_flags16<TZ>(P, j0, k0);
+      if (__syncthreads_and(mine) != 0) {
+        lean_atm_tile<T, TX, TZ, CHAIN, EK>(P, e, j0, k0, ld, cmax_out, mb_out, jm_out, acc);
+        return;
+      }
+    }
+  }
   {
-    // a tile whose halo lies inside the grid reads every cell where it is
-    // (no boundary map, no parities)
-    const bool inner = j0 >= 3 && j0 + TX + 3 <= nx && k0 >= 3 && k0 + TZ + 3 <= nz;
     const bool have_flags = P.flags != nullptr;
     unsigned src[LPT], im[LPT];
     bool use[LPT], fin[LPT];

@@ -338,7 +338,7 @@ def test_tile_shapes_bitwise(orc, tov):
     opts = dict(recon="ppm", riemann="hllc", prec="fp64", c2p=C2P_STAR)
     st = dict(grhd.SSPRK3[1], dt=0.4 * grid["dx"])
     outs = []
-    for tile in [(32, 8), (32, 16), (64, 8), (16, 16), (16, 8)]:
+    for tile in [(16, 15), (32, 8), (32, 16), (64, 8), (16, 16), (16, 8), (16, 7)]:
         ref, out = run_pair(orc, grid, eos, metric, opts, st, q, q, tile=tile)
         outs.append(out)
     check_pair(grid, ref, outs[0])
