@@ -2,19 +2,29 @@
 
 Headline workload: the perturbed TOV star (K = 100, Gamma = 2,
 rho_c = 1.28e-3, Cowling metric) on a 1024 x 1024 cylindrical grid covering
-[0, 20]^2, PPM + HLLC, SSP-RK3.  A benchmark step is one full SSP-RK3 time
-step = three substeps (each: primitive recovery, the fused reconstruction /
-flux / divergence / source / stage kernel, the diagnostic fold), with the
-diagnostics on.  Inputs are resident in HBM before the timed region.
+[0, 20]^2, PPM + HLLC, SSP-RK3, the paper's face states.  A benchmark step
+is one full SSP-RK3 time step = three substeps, with the diagnostics on.
+Inputs are resident in HBM before the timed region.
 
 Metric: zone-updates/s (interior cells x substeps / second) of the plain
-FP64 path.  The JSON line also carries:
-  forms.fp64_chained  the same FP64 substep as one chained kernel per stage
-                 (grhd_rk_substep_chained: the recovery of the new state at
-                 the end of each stage; one recovery pass starts the chain);
+FP64 path, in the faster of its two forms (config.form):
+  forms.fp64     each substep a recovery pass, the fused reconstruction /
+                 flux / divergence / source / stage kernel and the
+                 diagnostic fold (grhd_rk_substep);
+  forms.fp64_chained  each substep one chained kernel (grhd_rk_substep_chained:
+                 the stage, then the recovery of the new state) and the fold;
+                 one recovery pass starts the chain.
+The JSON line also carries:
   forms.mixed    FP32 reconstruction and flux, FP64 recovery and update, in
                  the chained form, with its L1 error against the FP64 path
                  after N substeps;
+  forms.combined the headline star through the form the three patterns
+                 combine into: mixed precision, the batched plan (one
+                 graph-captured launch sequence per substep) and the learned
+                 recovery guess (the matrix-core MLP trained here on GPU on
+                 star-like states), with and without the guess, against the
+                 plain FP64 headline: zone-updates/s, speedup, and the L1
+                 difference from the FP64 path after N substeps;
   forms.batched  six nested 256^2 star levels plus 64 Riemann patches
                  (N_x log-uniform in [128, 2048], 8 periodic z cells) in one
                  graph-captured batched launch, against one call per patch;
@@ -32,10 +42,12 @@ FP64 path.  The JSON line also carries:
   forms.learned  recovery of a 2048^2 differentially rotating field, Illinois
                  from the bracket against Newton seeded by the matrix-core MLP
                  (trained here on GPU), same root;
-  roofline       of the fused stage kernel (HIP events recorded by the library
-                 around that kernel, algorithmic bytes per zone), with the
-                 whole substep's fraction beside it;
-  cpu_baseline   the oracle on a bounded sample of the headline workload.
+  roofline       of the headline's stage kernel (HIP events recorded by the
+                 library around that kernel): the algorithmic bytes of one
+                 fused pass (96, 136, 136 B per zone over the stages) per
+                 mean launch time, with the whole substep's fraction beside it;
+  cpu_baseline   the oracle on the host cores (one band of rows per core)
+                 and on one core, bounded samples of the headline workload.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--forms fp64,mixed,...]
 """
@@ -52,18 +64,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic HBM bytes per zone of the fused stage kernel (k_substep), FP64
-# fields read or written once: primitives (6 x 8), lapse and W (2 x 8), q_s
-# (5 x 8) read, q_out (5 x 8) written; stages 2 and 3 also read q^n (5 x 8).
+# bytes per zone that the separate-recovery stage kernel (k_substep) reads
+# and writes by design, FP64 fields once: primitives (6 x 8), lapse and W
+# (2 x 8), q_s (5 x 8) read, q_out (5 x 8) written; stages 2 and 3 also read
+# q^n (5 x 8)
 BYTES_KERNEL = [144.0, 184.0, 184.0]
+# the same for the chained stage kernel (k_substep_chain): primitives and
+# flags of q_s read (49), lapse and W (16), q_s (40) [+ q^n 40]; q_out (40),
+# its primitives and flags (49) written
+BYTES_CHAINED = [194.0, 234.0, 234.0]
 # algorithmic bytes per zone-update of a whole substep (recovery included):
 # q_s and the metric read, q_out written, q^n read in stages 2 and 3
 BYTES_SUBSTEP = [96.0, 136.0, 136.0]
-ALL_FORMS = ("fp64", "fp64_chained", "mixed", "batched", "fmr", "bondi", "bondi_rt", "learned")
+ALL_FORMS = ("fp64", "fp64_chained", "mixed", "combined", "batched", "fmr", "bondi", "bondi_rt", "learned")
 # measured HBM traffic of the fused kernel (rocprofv3 FETCH_SIZE/WRITE_SIZE,
 # calibrated with a plain copy) is kept with the hash of the sources it was
 # measured on; it is reported only while the sources still hash the same
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_substep_star1024_counters.md")
+TRAFFIC_FILES = {False: os.path.join(ROOT, "profiles", "k_substep_star1024_counters.md"),
+                 True: os.path.join(ROOT, "profiles", "k_substep_chain_star1024_counters.md")}
 KERNEL_SOURCES = ["paper_2502_03223_amd/csrc/" + f for f in
                   ("grhd_tile.hpp", "grhd_dev.hpp", "grhd_diag.hpp", "grhd_host.hpp", "grhd_kernels.hip")] + \
                  ["paper_2502_03223_amd/build.py"]
@@ -78,12 +96,13 @@ def kernel_sources_hash():
     return h.hexdigest()
 
 
-def measured_traffic(nzone):
-    """Bytes per launch recorded with the counter profile, or None when
-    absent, taken on other sources or on a launch of another size."""
+def measured_traffic(nzone, chained):
+    """Bytes per launch recorded with the counter profile of that stage
+    kernel, or None when absent, taken on other sources or on a launch of
+    another size."""
     try:
         kv = {}
-        for line in open(TRAFFIC_FILE):
+        for line in open(TRAFFIC_FILES[chained]):
             if ":" in line and line.split(":", 1)[0].strip() in ("traffic_bytes_per_launch", "source_sha256",
                                                                  "zones_per_launch"):
                 k, v = line.split(":", 1)
@@ -106,7 +125,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reuse-atm", action="store_true",
                     help="the star forms' recoveries rewrite the primitives of every cell")
-    ap.add_argument("--cpu-sample-rows", type=int, default=1024)
+    ap.add_argument("--cpu-sample-rows", type=int, default=128,
+                    help="rows of the single-core oracle sample")
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
     ap.add_argument("--learned-n", type=int, default=2048)
     ap.add_argument("--train-pairs", type=int, default=1 << 20)
@@ -244,31 +264,35 @@ def main():
                     kernel_ms=kernel_ms.mean(axis=0), diag=grhd.read_diag(st.diag))
 
     out_forms = {}
-    r64 = run_form("fp64", chained=False)
+    # the plain FP64 path in its two forms: separate recovery pass + stage
+    # kernel, and the chained stage (recovery of the new state at the end of
+    # each stage kernel); the headline is the faster of the two
+    res64 = {}
+    for chained in (False, True):
+        r = run_form("fp64", chained=chained)
+        res64[chained] = r
+        key = "fp64_chained" if chained else "fp64"
+        v = 3 * nzone * args.steps / r["wall"]
+        out_forms[key] = {"value": v, "ms_per_step": r["wall"] * 1e3 / args.steps, "chained": chained,
+                          "ms_per_step_with_events": r["wall_with_events"] * 1e3 / args.steps,
+                          "kernel_ms": r["kernel_ms"].tolist(), "stage_ms": r["stage_ms"].tolist()}
+        print("%s done: %.3e zone-updates/s" % (key, v), file=sys.stderr, flush=True)
+    head_chained = res64[True]["wall"] < res64[False]["wall"]
+    r64 = res64[head_chained]
     value = 3 * nzone * args.steps / r64["wall"]
     ms_per_step = r64["wall"] * 1e3 / args.steps
-    # bytes and time per launch of the fused kernel, averaged over the stages
+    # roofline of the headline's stage kernel: the algorithmic bytes of one
+    # fused pass over a zone (q_s and lapse, W read, q_out written, q^n read
+    # in stages 2 and 3: 96, 136, 136 B) over that kernel's mean duration
     kms = float(r64["kernel_ms"].mean())
-    bytes_per_launch = float(np.mean(BYTES_KERNEL)) * nzone
+    bytes_per_launch = float(np.mean(BYTES_SUBSTEP)) * nzone
     achieved = bytes_per_launch / (kms * 1e-3) / 1e9
-    # the whole substep (recovery, stage kernel, fold; time from the clean
-    # pass) against its own bytes
+    # the same bytes over the whole substep's wall time (every kernel of it,
+    # fold included, from the clean pass)
     substep_gbs = float(np.mean(BYTES_SUBSTEP)) * nzone / (ms_per_step / 3.0 * 1e-3) / 1e9
     diag = r64["diag"]
-    tb = measured_traffic(nzone)
+    tb = measured_traffic(nzone, head_chained)
     traffic = tb / (kms * 1e-3) / 1e9 if tb else None
-    out_forms["fp64"] = {"value": value, "ms_per_step": ms_per_step, "chained": False,
-                         "ms_per_step_with_events": r64["wall_with_events"] * 1e3 / args.steps,
-                         "kernel_ms": r64["kernel_ms"].tolist(), "stage_ms": r64["stage_ms"].tolist()}
-    print("fp64 done: %.3e zone-updates/s" % value, file=sys.stderr, flush=True)
-    if "fp64_chained" in forms:
-        rc_ = run_form("fp64", chained=True)
-        value_c = 3 * nzone * args.steps / rc_["wall"]
-        out_forms["fp64_chained"] = {"value": value_c, "ms_per_step": rc_["wall"] * 1e3 / args.steps,
-                                     "chained": True, "kernel_ms": rc_["kernel_ms"].tolist(),
-                                     "stage_ms": rc_["stage_ms"].tolist()}
-        print("fp64_chained done", file=sys.stderr, flush=True)
-
     if "mixed" in forms:
         rm = run_form("mixed")
         value_m = 3 * nzone * args.steps / rm["wall"]
@@ -278,6 +302,9 @@ def main():
                               "accuracy_vs_fp64": mixed_accuracy(args, Stepper, grid, eos, metric,
                                                                  metric_np, c2p)}
         print("mixed done", file=sys.stderr, flush=True)
+    if "combined" in forms:
+        out_forms["combined"] = combined_form(args, grid, eos, metric, metric_np, make_state, value, Stepper)
+        print("combined done", file=sys.stderr, flush=True)
     if "batched" in forms:
         out_forms["batched"] = batched_form(args, tov)
         print("batched done", file=sys.stderr, flush=True)
@@ -296,7 +323,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(grid, eos, metric_np, p_np, c2p, dt, args.cpu_sample_rows, args.cpu_sample_steps)
+        cpu = cpu_baseline(grid, eos, metric_np, p_np, c2p, dt, args.cpu_sample_steps, args.cpu_sample_rows)
 
     out = {
         "metric": "zone-updates/s per GRHD RK substep at 1 GPU, FP64 plain vs mixed/batched",
@@ -315,19 +342,32 @@ def main():
             "workload": "TOV star K=100 Gamma=2 rho_c=1.28e-3, %dx%d cylindrical [0,20]^2, "
                         "Cowling metric, PPM+HLLC, SSP-RK3 (3 substeps per step)" % (n, n),
             "zones": nzone, "substeps_per_step": 3, "seed": 2025,
+            "form": "chained" if head_chained else "separate recovery",
+            "face_states": "reconstructed rho, u_i, P, eps",
             "recovery_reuse_atm": not args.no_reuse_atm,
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "k_substep<double> (fused reconstruction, flux, divergence, sources, stage)",
-            "bytes_per_zone": BYTES_KERNEL, "kernel_ms": r64["kernel_ms"].tolist(),
+            "kernel": ("k_substep_chain<double> (reconstruction, flux, divergence, sources, stage, "
+                       "then the recovery of the new state)" if head_chained else
+                       "k_substep<double> (reconstruction, flux, divergence, sources, stage)"),
+            "form": "chained" if head_chained else "separate recovery",
+            "bytes_per_zone": BYTES_SUBSTEP, "kernel_ms": r64["kernel_ms"].tolist(),
             "algorithmic_bytes_per_launch": bytes_per_launch,
+            "kernel_design_bytes_per_zone": BYTES_CHAINED if head_chained else BYTES_KERNEL,
+            "kernel_design_gbs": float(np.mean(BYTES_CHAINED if head_chained else BYTES_KERNEL)) * nzone
+                                 / (kms * 1e-3) / 1e9,
             "measured_bytes_per_launch": tb,
-            "substep_bytes_per_zone": BYTES_SUBSTEP, "substep_gbs": substep_gbs,
-            "substep_frac": substep_gbs / HBM_PEAK_GBS,
+            "substep_gbs": substep_gbs, "substep_frac": substep_gbs / HBM_PEAK_GBS,
+            "bytes_note": "achieved = the algorithmic bytes of one fused pass (96, 136, 136 B per zone "
+                          "over the three SSP-RK3 stages) x zones / mean kernel time; "
+                          "kernel_design_gbs counts what this kernel reads and writes by design "
+                          "(primitives and flags of the chained form, or the primitive re-read of "
+                          "the separate-recovery form) over the same time",
             "traffic_note": "traffic = measured HBM bytes per launch (FETCH x2 + WRITE x1, factors "
-                            "from a 256 MiB copy) / the same mean launch time, in GB/s",
+                            "from a 256 MiB copy) / the same mean launch time, in GB/s; null when the "
+                            "kernel sources changed since the counters were taken",
             "timing_note": "value and ms_per_step come from K steps with nothing recorded on the stream; "
                            "kernel_ms and stage_ms from the same K steps repeated right after with HIP "
                            "events around every fused kernel and every substep",
@@ -370,6 +410,145 @@ def mixed_accuracy(args, Stepper, grid, eos, metric, metric_np, c2p):
     return dict(substeps=3 * nsteps, l1_rel_rho=l1rel(P32[0], P64[0]),
                 l1_rel_eps=l1rel(P32[5], P64[5]), l1_abs_v=l1_v,
                 max_abs_v_fp64=float(np.abs(np.stack([vx64, vz64])).max()))
+
+
+def train_guess(samples, eos, seed, train_steps, dev):
+    """The learned recovery guess trained on GPU with the library's kernels:
+    (D, S, tau) -> P pairs through the library's prim->con of the sampled
+    states.  Returns (network, training record)."""
+    import torch
+
+    import synth
+    from paper_2502_03223_amd import grhd
+    npair = samples.shape[0]
+    tg = synth.make_grid(npair, 1, 0.0, 0.0, 1.0, 1.0, "cart", ("outflow",) * 4)
+    ng = tg["ng"]
+    pt = torch.zeros((6, 1 + 2 * ng, tg["pitch"]), dtype=torch.float64, device=dev)
+    pt[:, ng, ng:ng + npair] = torch.from_numpy(samples.T.copy()).to(dev)
+    qt = torch.zeros((5,) + pt.shape[1:], dtype=torch.float64, device=dev)
+    grhd.prim2con(tg, eos, {}, pt, qt)
+    qi = qt[:, ng, ng:ng + npair]
+    X = grhd.recovery_features(qi)
+    y = torch.log10(pt[4, ng, ng:ng + npair] / qi[0])
+    xm, xs = X.mean(dim=0), X.std(dim=0)
+    ym, ys = y.mean(), y.std()
+    scal = torch.cat([xm, xs, ym.view(1), ys.view(1)]).float().contiguous()
+    Xs = ((X - xm) / xs).float().contiguous()
+    ts = ((y - ym) / ys).float().contiguous()
+    net = grhd.MLP(grhd.mlp_init(seed), scal)
+    gen = torch.Generator(device=dev).manual_seed(seed)
+    batch = 8192
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(train_steps):
+        idx = torch.randint(0, npair, (batch,), device=dev, generator=gen)
+        lr = 2e-3 * 0.5 * (1.0 + math.cos(math.pi * it / train_steps)) + 1e-5
+        net.train_step(Xs[idx].contiguous(), ts[idx].contiguous(), lr)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    _, full_loss = grhd.mlp_grad(net.params, Xs, ts)
+    return net, {"pairs": npair, "steps": train_steps, "batch": batch, "seconds": train_s,
+                 "mse_standardised": float(full_loss.cpu()[0])}
+
+
+def combined_form(args, grid, eos, metric, metric_np, make_state, value_fp64, Stepper):
+    """The headline star through a one-patch batched plan (the whole
+    substep -- recovery, stage kernel, fold -- one graph launch), mixed
+    precision, with and without the learned recovery guess."""
+    import torch
+
+    import synth
+    from paper_2502_03223_amd import grhd
+    dev = torch.device("cuda:0")
+    nzone = grid["nx"] * grid["nz"]
+    dt = 0.4 * grid["dx"]
+    c2p = dict(w_max=100.0, rho_atm=1e-10)
+    net, train_rec = train_guess(synth.star_recovery_samples(4321, args.train_pairs), eos, 2,
+                                 max(args.train_steps // 4, 100), dev)
+    roles = [("q", "q", "q1"), ("q", "q1", "q2"), ("q", "q2", "q1")]
+    res = {"workload": "the headline star, one-patch plan, SSP-RK3", "train": train_rec}
+
+    def descr(b, s):
+        qn, qs, qo = roles[s]
+        return [dict(grid=grid, metric=metric, qn=b[qn], qs=b[qs], qout=b[qo], p=b["p"],
+                     stage=dict(grhd.SSPRK3[s], dt=dt), eos_id=0)]
+
+    def make(mlp):
+        q = make_state()
+        b = dict(q=q, q1=torch.zeros_like(q), q2=torch.zeros_like(q),
+                 p=torch.zeros((6,) + q.shape[1:], dtype=torch.float64, device=dev))
+        opts = dict(recon="ppm", riemann="hllc", prec="mixed", c2p=dict(c2p, mlp=mlp))
+        plan = grhd.Plan(descr(b, 0), [eos], opts)
+        b["q"].copy_(make_state())
+        swapped = dict(b, q=b["q1"], q1=b["q"])
+        tables = [[plan.table(descr(bb, s)) for s in range(3)] for bb in (b, swapped)]
+        return plan, b, tables
+
+    for name, mlp in (("mixed_batched", None), ("mixed_batched_learned", net.buf)):
+        plan, b, tables = make(mlp)
+        diag = grhd.new_diag()
+        par = [0]
+
+        def step():
+            for s in range(3):
+                plan(tables[par[0]][s], diag=diag)
+            par[0] ^= 1
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        d = grhd.read_diag(diag)
+        v = 3 * nzone * args.steps / wall
+        res[name] = {"value": v, "ms_per_step": wall * 1e3 / args.steps, "speedup_vs_fp64": v / value_fp64,
+                     "evals_last_stage": d["iter_sum"], "evals_max_last_stage": d["iter_max"]}
+        # accuracy: the same number of substeps from the same initial data as
+        # the FP64 path (chained FP64 stepper), L1 of the primitives
+        if name == "mixed_batched_learned":
+            plan.close()
+            plan, b, tables = make(mlp)
+            par[0] = 0
+            nsteps = args.accuracy_substeps // 3
+            ref = Stepper("fp64")
+            for _ in range(nsteps):
+                step()
+                ref.step()
+            cur = b["q"] if nsteps % 2 == 0 else b["q1"]
+            pc = torch.zeros_like(b["p"])
+            grhd.con2prim(grid, eos, metric, c2p, cur.clone(), pc)
+            res[name]["accuracy_vs_fp64"] = l1_diffs(grid, metric_np, pc, ref.prims())
+            res[name]["accuracy_vs_fp64"]["substeps"] = 3 * nsteps
+        plan.close()
+    res["guess_speedup"] = res["mixed_batched_learned"]["value"] / res["mixed_batched"]["value"]
+    return res
+
+
+def l1_diffs(grid, metric_np, pa, pb):
+    """L1 differences of two primitive states: rho and eps relative with the
+    sqrt(-g) x weight, v^varpi + v^z absolute and x weighted."""
+    import synth
+    P = synth.interior(grid, pa.cpu().numpy())
+    R = synth.interior(grid, pb.cpu().numpy())
+    X, _ = synth.cell_coords(grid)
+    x = synth.interior(grid, X)
+    Wm = synth.interior(grid, metric_np["W"])
+    alp = synth.interior(grid, metric_np["alp"])
+    wgt = alp * Wm ** -3 * x
+
+    def l1rel(a, b):
+        return float((np.abs(a - b) * wgt).sum() / (np.abs(b) * wgt).sum())
+
+    def vel(Q):
+        w = np.sqrt(1.0 + Wm ** 2 * (Q[1] ** 2 + Q[2] ** 2 + Q[3] ** 2))
+        return Wm ** 2 * Q[1] / w, Wm ** 2 * Q[3] / w
+    vx, vz = vel(P)
+    rx, rz = vel(R)
+    return dict(l1_rel_rho=l1rel(P[0], R[0]), l1_rel_eps=l1rel(P[5], R[5]),
+                l1_abs_v=float(((np.abs(vx - rx) + np.abs(vz - rz)) * x).sum() / x.sum()),
+                max_abs_v_fp64=float(np.abs(np.stack([rx, rz])).max()))
 
 
 def batched_form(args, tov):
@@ -724,17 +903,16 @@ def learned_form(args):
     return res
 
 
-def cpu_baseline(grid, eos, metric_np, p_np, c2p, dt, rows, steps):
-    """The oracle (single thread, plain C) on a horizontal band of the same
-    star grid: its first `rows` full rows (all of it by default), `steps`
-    SSP-RK3 steps from the same initial data."""
+def _oracle_band(args):
+    """Worker: the oracle (FP64 C) on rows [r0, r1) of the star grid as a
+    grid of its own, `steps` SSP-RK3 steps; returns (zone-updates, seconds
+    of the substep loop)."""
+    grid, eos, metric_np, p_np, c2p, dt, r0, r1, steps = args
     import oracle
-    oracle.build(force=False)
     ng = grid["ng"]
-    rows = min(rows, grid["nz"])
-    band = dict(grid, nz=rows, z0=grid["z0"],
-                bc=(grid["bc"][0], grid["bc"][1], "reflect", "outflow"))
-    sl = slice(0, rows + 2 * ng)
+    band = dict(grid, nz=r1 - r0, z0=grid["z0"] + r0 * grid["dz"],
+                bc=(grid["bc"][0], grid["bc"][1], "reflect" if r0 == 0 else "outflow", "outflow"))
+    sl = slice(r0, r1 + 2 * ng)
     p = np.ascontiguousarray(p_np[:, sl])
     met = {k: np.ascontiguousarray(v[sl]) for k, v in metric_np.items()}
     q = oracle.prim2con(band, eos, met, p, with_ghosts=True)
@@ -751,11 +929,66 @@ def cpu_baseline(grid, eos, metric_np, p_np, c2p, dt, rows, steps):
             qs = r["qout"]
         q = qs
     el = time.perf_counter() - t0
-    zones = band["nx"] * band["nz"] * 3 * steps
-    return {"value": zones / el, "unit": "zone-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "oracle FP64 C (gcc -O2, 1 thread): %d SSP-RK3 steps (3 substeps each) of "
-                      "the first %d of %d rows of the %dx%d star grid (%d zone-updates, %.1f s)"
-                      % (steps, rows, grid["nz"], grid["nx"], grid["nz"], zones, el)}
+    return band["nx"] * band["nz"] * 3 * steps, el
+
+
+def cpu_baseline(grid, eos, metric_np, p_np, c2p, dt, steps, rows_single, reps=3):
+    """The oracle as it is (plain C, one thread per process, gcc -O3
+    without fast-math), timed on the host two ways, each the median of
+    `reps` runs: (a) the whole star grid cut into one band of rows per core,
+    every core running the oracle on its band at the same time (bands are
+    independent samples of the workload; the rate is total zone-updates
+    over the wall time of the slowest band); (b) one core on the first
+    `rows_single` rows.  Cores: the host's, capped at 16 (a GPU machine's
+    share).  Substep loops only; set-up excluded."""
+    import multiprocessing as mp
+    import platform
+    import oracle
+    oracle.build(force=False)
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    cores = max(1, min(avail, 16))
+    model = platform.processor() or ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    nz = grid["nz"]
+    edges = [round(i * nz / cores) for i in range(cores + 1)]
+    bands = [(grid, eos, metric_np, p_np, c2p, dt, edges[i], edges[i + 1], steps)
+             for i in range(cores) if edges[i + 1] > edges[i]]
+    ctx = mp.get_context("spawn")
+    multi = []
+    with ctx.Pool(len(bands)) as pool:
+        pool.map(_oracle_band, [b[:-1] + (1,) for b in bands[:len(bands)]])   # import and page in
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            res = pool.map(_oracle_band, bands)
+            wall = time.perf_counter() - t0
+            zones = sum(r[0] for r in res)
+            multi.append((zones / max(r[1] for r in res), zones, wall))
+        single = []
+        rs = min(rows_single, nz)
+        for _ in range(reps):
+            z, el = pool.apply(_oracle_band, ((grid, eos, metric_np, p_np, c2p, dt, 0, rs, steps),))
+            single.append((z / el, z, el))
+    multi.sort()
+    single.sort()
+    m, s1 = multi[len(multi) // 2], single[len(single) // 2]
+    return {"value": m[0], "unit": "zone-updates/s", "cores": len(bands), "kind": "oracle",
+            "cpu_model": model,
+            "sample": "oracle FP64 C (gcc -O3, no fast-math, one process per core): the %dx%d star grid "
+                      "cut into %d bands of rows, each band run as its own grid by one core for %d SSP-RK3 "
+                      "steps (3 substeps each), all at once; %d zone-updates per run, median of %d runs "
+                      "(%.1f s of wall time)" % (grid["nx"], nz, len(bands), steps, m[1], reps, m[2]),
+            "single_core": {"value": s1[0], "unit": "zone-updates/s", "cores": 1,
+                            "sample": "the first %d rows, %d SSP-RK3 steps, %d zone-updates, median of %d "
+                                      "runs (%.1f s)" % (rs, steps, s1[1], reps, s1[2])}}
 
 
 if __name__ == "__main__":

@@ -321,7 +321,10 @@ typedef struct grhd_plan grhd_plan;   /* opaque, library-owned */
 
 /* Build a plan for a fixed set of patch shapes: tile shape (from tune_cache
  * if given and present, else measured and stored there), device patch and
- * work tables, launch configuration and the captured graph. */
+ * work tables, launch configuration and the captured graph.  The options'
+ * recovery may take the learned guess (GRHD_GUESS_MLP): the batched
+ * recovery then evaluates the network on the matrix cores, as
+ * grhd_con2prim does. */
 int grhd_plan_create(const grhd_patch *patches, int npatch,
                      const grhd_eos *eos_table, int neos,
                      const grhd_options *opts, const char *tune_cache,

@@ -15,7 +15,7 @@
  * preservation, conservation, con2prim round trip, polynomial exactness,
  * flux consistency against the stress-energy tensor, covariant source
  * identity, a uniform-pressure contact kept to round-off, smooth-wave
- * convergence).  Build: gcc -O2 -ffp-contract=off (no fused multiply-add, no
+ * convergence).  Build: gcc -O3 -ffp-contract=off (no fused multiply-add, no
  * fast-math).
  */
 #include <math.h>

@@ -22,6 +22,9 @@
 
 namespace grhd {
 
+int launch_con2prim_batch_mlp(int mc, int ek, const PatchK *pt, const EosK *eos, const C2PK &cp,
+                              const long long *item_prefix, int npatch, long long items, C2PPart *part,
+                              hipStream_t st);
 int fill_patch(const grhd_grid *grid, const grhd_metric *metric, const grhd_rk_stage *stage,
                const grhd_cons *qn, const grhd_cons *qs, const grhd_cons *qout, const grhd_prim *p,
                const grhd_cons *acc_in, const grhd_cons *acc_out, double *flux_reg, int recon,
@@ -231,7 +234,10 @@ int capture_graph(grhd_plan *pl, grhd_diag *diag) {
     return fail(GRHD_ERR_DEVICE, "graph capture begin failed");
   dim3 gi((unsigned)pl->total_items);
   C2PPart *p1 = pl->d_part1;
-  if (pl->mc == MC_GEN && pl->ek == GRHD_EOS_IDEAL)
+  if (pl->cp.guess == GRHD_GUESS_MLP)
+    launch_con2prim_batch_mlp(pl->mc, pl->ek, pl->d_patches, pl->d_eos, pl->cp, pl->d_item_prefix, pl->npatch,
+                              pl->total_items, p1, s);
+  else if (pl->mc == MC_GEN && pl->ek == GRHD_EOS_IDEAL)
     hipLaunchKernelGGL((k_con2prim_batch<MC_GEN, GRHD_EOS_IDEAL>), gi, dim3(256), 0, s, pl->d_patches,
                        pl->d_eos, pl->cp, pl->d_item_prefix, pl->npatch, p1);
   else if (pl->mc == MC_GEN)
@@ -388,8 +394,6 @@ extern "C" int grhd_plan_create(const grhd_patch *patches, int npatch, const grh
   if (!eos_table || neos < 1) return fail(GRHD_ERR_INVALID, "need at least one EOS");
   if (!opts) return fail(GRHD_ERR_INVALID, "opts is NULL");
   if ((rc = check_c2p(&opts->c2p)) || (rc = check_face_eps(opts->face_eps))) return rc;
-  if (opts->c2p.guess != GRHD_GUESS_NONE)
-    return fail(GRHD_ERR_UNSUPPORTED, "learned guess is not wired into the batch");
   if (opts->prec != GRHD_PREC_FP64 && opts->prec != GRHD_PREC_MIXED) return fail(GRHD_ERR_INVALID, "bad prec");
   for (int i = 0; i < neos; i++)
     if ((rc = check_eos(&eos_table[i]))) return rc;

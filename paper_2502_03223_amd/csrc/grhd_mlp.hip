@@ -11,6 +11,7 @@
 #include "grhd_diag.hpp"
 #include "grhd_host.hpp"
 #include "grhd_mlp.hpp"
+#include "grhd_tile.hpp"
 
 namespace grhd {
 
@@ -28,34 +29,23 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const MlpDev *w, const floa
   if (act) y[i] = o;
 }
 
-// Recovery seeded by the network: features (log10 D, S/E, log10(tau/D)),
-// output log10(P/D); the guess P0 gives v0 = S/(E + P0) and
+// Recovery of cell (j, k) seeded by the network: features (log10 D, S/E,
+// log10(tau/D)), output log10(P/D); the guess P0 gives v0 = S/(E + P0) and
 // z0 = v0 / sqrt(1 - v0^2), from which a safeguarded Newton solve starts.
-// The workgroup stages the weights in LDS once; its waves read their
-// operand fragments from there.
+// Every lane of the wave calls it (the network spans the wave); act marks
+// the lanes that hold a cell.  q: the conserved fields (in; corrected where
+// a flag is set), p: the primitives (out), flags: nullable.
 template <int MC, int EK>
-__global__ void __launch_bounds__(256)
-k_con2prim_mlp(GridK g, EosK e, C2PK cp, MetK m, Q5 q, P6 p, uint8_t *flags, C2PPart *part,
-               int jlo, int jhi, int klo) {
-  __shared__ unsigned long long red[4][6];
-  __shared__ MlpDev sw;
-  mlp_stage<256>((const MlpDev *)cp.mlp, &sw);
-  const MlpDev *w = &sw;
-  int j = jlo + blockIdx.x * blockDim.x + threadIdx.x;
-  int k = klo + blockIdx.y;
-  bool act = j < jhi;
-  bool jin = (j >= 0 && j < g.nx), kin = (k >= 0 && k < g.nz);
-  if (!jin || !kin) {
-    if (!jin && !kin) act = false;
-    else if (!jin) act = act && g.bc[j < 0 ? 0 : 1] == GRHD_BC_EXTERNAL;
-    else act = act && g.bc[k < 0 ? 2 : 3] == GRHD_BC_EXTERNAL;
-  }
+__device__ __forceinline__ void mlp_recover_cell(const EosK &e, const C2PK &cp, const MlpDev *w,
+                                                 const GridK &g, const MetK &m, double *const *q,
+                                                 double *const *p, uint8_t *flags, bool act, int j,
+                                                 int k, unsigned &fl, int &iters) {
   long long i = cell_index(g, act ? j : 0, act ? k : 0);
   double qq[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, W = 1.0, gtu[6];
   double x = g.x0 + (j + 0.5) * g.dx;
   if (act) {
     W = mval(m, GRHD_M_W, i);
-    for (int c = 0; c < 5; c++) qq[c] = q.q[c][i];
+    for (int c = 0; c < 5; c++) qq[c] = q[c][i];
   }
   const double q0[5] = {qq[0], qq[1], qq[2], qq[3], qq[4]};
   if (MC == MC_GEN) {
@@ -96,19 +86,90 @@ k_con2prim_mlp(GridK g, EosK e, C2PK cp, MetK m, Q5 q, P6 p, uint8_t *flags, C2P
     float v0 = (float)S / ((float)E + P0);
     if (v0 >= 0.0f && v0 < 1.0f) zg = (double)(v0 / sqrtf(1.0f - v0 * v0));
   }
-  unsigned fl = 0;
-  int iters = 0;
+  fl = 0;
+  iters = 0;
   if (act) {
     double pp[6];
     C2PResult res = con2prim_cell<MC, EK>(e, cp, W, gtu, x, g.geom, qq, pp, zg);
     fl = res.flags;
     iters = res.iters;
-    if (fl) store_corrected(qq, q0, q.q, i);
-    for (int c = 0; c < 6; c++) p.p[c][i] = pp[c];
+    if (fl) store_corrected(qq, q0, q, i);
+    for (int c = 0; c < 6; c++) p[c][i] = pp[c];
     if (flags) flags[i] = (uint8_t)fl;
   }
+}
+
+// The single-patch recovery with the learned guess.  The workgroup stages
+// the weights in LDS once; its waves read their operand fragments from
+// there.
+template <int MC, int EK>
+__global__ void __launch_bounds__(256)
+k_con2prim_mlp(GridK g, EosK e, C2PK cp, MetK m, Q5 q, P6 p, uint8_t *flags, C2PPart *part,
+               int jlo, int jhi, int klo) {
+  __shared__ unsigned long long red[4][6];
+  __shared__ MlpDev sw;
+  mlp_stage<256>((const MlpDev *)cp.mlp, &sw);
+  int j = jlo + blockIdx.x * blockDim.x + threadIdx.x;
+  int k = klo + blockIdx.y;
+  bool act = j < jhi;
+  bool jin = (j >= 0 && j < g.nx), kin = (k >= 0 && k < g.nz);
+  if (!jin || !kin) {
+    if (!jin && !kin) act = false;
+    else if (!jin) act = act && g.bc[j < 0 ? 0 : 1] == GRHD_BC_EXTERNAL;
+    else act = act && g.bc[k < 0 ? 2 : 3] == GRHD_BC_EXTERNAL;
+  }
+  unsigned fl;
+  int iters;
+  mlp_recover_cell<MC, EK>(e, cp, &sw, g, m, q.q, p.p, flags, act, j, k, fl, iters);
   if (part)
     c2p_block_partial<256>(act && jin && kin, fl, iters, &part[blockIdx.y * gridDim.x + blockIdx.x], red);
+}
+
+// The batched recovery with the learned guess: item = (patch, row,
+// 256-cell segment) of a patch table, as the batch's plain recovery.
+template <int MC, int EK>
+__global__ void __launch_bounds__(256)
+k_con2prim_batch_mlp(const PatchK *__restrict__ pt, const EosK *__restrict__ eos, C2PK cp,
+                     const long long *__restrict__ item_prefix, int npatch, C2PPart *part) {
+  __shared__ unsigned long long red[4][6];
+  __shared__ MlpDev sw;
+  mlp_stage<256>((const MlpDev *)cp.mlp, &sw);
+  long long b = blockIdx.x;
+  int lo = 0, hi = npatch - 1;
+  while (lo < hi) {  // last patch whose first item <= b
+    int mid = (lo + hi + 1) >> 1;
+    if (item_prefix[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const PatchK &P = pt[lo];
+  long long li = b - item_prefix[lo];
+  int segs = (P.g.nx + 255) / 256;
+  int k = (int)(li / segs);
+  int j = (int)(li % segs) * 256 + threadIdx.x;
+  bool act = j < P.g.nx;
+  unsigned fl;
+  int iters;
+  mlp_recover_cell<MC, EK>(eos[P.eos_id], cp, &sw, P.g, P.m, P.qs, P.p, P.flags, act, j, k, fl, iters);
+  if (part) c2p_block_partial<256>(act, fl, iters, &part[blockIdx.x], red);
+}
+
+int launch_con2prim_batch_mlp(int mc, int ek, const PatchK *pt, const EosK *eos, const C2PK &cp,
+                              const long long *item_prefix, int npatch, long long items, C2PPart *part,
+                              hipStream_t st) {
+  dim3 gi((unsigned)items);
+  if (mc == MC_GEN && ek == GRHD_EOS_IDEAL)
+    hipLaunchKernelGGL((k_con2prim_batch_mlp<MC_GEN, GRHD_EOS_IDEAL>), gi, dim3(256), 0, st, pt, eos, cp,
+                       item_prefix, npatch, part);
+  else if (mc == MC_GEN)
+    hipLaunchKernelGGL((k_con2prim_batch_mlp<MC_GEN, GRHD_EOS_HYBRID>), gi, dim3(256), 0, st, pt, eos, cp,
+                       item_prefix, npatch, part);
+  else if (ek == GRHD_EOS_IDEAL)
+    hipLaunchKernelGGL((k_con2prim_batch_mlp<MC_CF, GRHD_EOS_IDEAL>), gi, dim3(256), 0, st, pt, eos, cp,
+                       item_prefix, npatch, part);
+  else
+    hipLaunchKernelGGL((k_con2prim_batch_mlp<MC_CF, GRHD_EOS_HYBRID>), gi, dim3(256), 0, st, pt, eos, cp,
+                       item_prefix, npatch, part);
+  return GRHD_OK;
 }
 
 template <int MC, int EK>

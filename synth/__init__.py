@@ -470,6 +470,24 @@ def recovery_samples(seed, n):
     return out
 
 
+def star_recovery_samples(seed, n, K=100.0, rho_max=1.5e-3):
+    """n primitive states (rho, u_x, u_y, u_z, P, eps) of the kind the star
+    holds, flat metric (training inputs of the learned guess for the star):
+    rho log-uniform in [1e-10, rho_max], eps = K rho (1 + 0.1 theta) with
+    theta ~ U[0, 1] (the Gamma = 2 polytrope plus a small thermal part),
+    u_x, u_z ~ N(0, 0.03), u_y = 0."""
+    rng = np.random.default_rng(seed)
+    rho = np.exp(rng.uniform(math.log(1e-10), math.log(rho_max), n))
+    eps = K * rho * (1.0 + 0.1 * rng.uniform(0.0, 1.0, n))
+    out = np.zeros((n, 6))
+    out[:, 0] = rho
+    out[:, 1] = rng.normal(0.0, 0.03, n)
+    out[:, 3] = rng.normal(0.0, 0.03, n)
+    out[:, 5] = eps
+    out[:, 4] = rho * eps
+    return out
+
+
 def general_metric(grid, seed, amp=0.1):
     """Smooth random metric with every field active: lapse, shift, W,
     conformal metric with det = 1 (M / det(M)^(1/3)), extrinsic curvature;

@@ -15,6 +15,11 @@ the plain FP64 form.  Compared on the primitives of the final state:
 The FP64 GPU form is held to 1e-10 on the same figures (limiter decisions
 taken on values that differ in the last bits can move a cell by more than
 rounding over 300 substeps, so this is not the single-substep 1e-12 bar).
+
+The combined form -- mixed precision, the batched plan (one graph-captured
+launch sequence per substep) and the learned recovery guess (a network
+trained on GPU on (D, S, tau) -> P pairs of star-like states from the
+oracle's prim->con) -- is held to the mixed form's bars.
 """
 import numpy as np
 import pytest
@@ -103,6 +108,63 @@ def l1_figures(grid, metric, P, R):
                 vmax=float(np.abs(np.stack([rx, rz])).max()))
 
 
+def train_star_guess(orc):
+    """The learned guess trained on star-like states (oracle prim->con
+    pairs), the library's training kernels."""
+    n = 100_000
+    prims = synth.star_recovery_samples(21, n)
+    grid = synth.make_grid(n, 1, 0.0, 0.0, 1.0, 1.0, "cart", ("outflow",) * 4)
+    p = synth.empty_fields(grid, 6)
+    synth.interior(grid, p)[:, 0, :] = prims.T
+    q = orc.prim2con(grid, synth.ideal_eos(2.0, 100.0), {}, p)
+    qi = synth.interior(grid, q)[:, 0, :]
+    D, E = qi[0], qi[4]
+    S = np.sqrt(qi[1] ** 2 + qi[2] ** 2 + qi[3] ** 2)
+    X = np.stack([np.log10(D), S / E, np.log10((E - D) / D)], axis=1)
+    y = np.log10(prims[:, 4] / D)
+    xm, xs, ym, ys = X.mean(axis=0), X.std(axis=0), y.mean(), y.std()
+    scal = torch.tensor(list(xm) + list(xs) + [ym, ys], dtype=torch.float32, device=DEV)
+    Xs = torch.from_numpy(((X - xm) / xs).astype(np.float32)).to(DEV)
+    ts = torch.from_numpy(((y - ym) / ys).astype(np.float32)).to(DEV)
+    net = grhd.MLP(grhd.mlp_init(5), scal)
+    g = torch.Generator(device=DEV).manual_seed(5)
+    for ep in range(4):
+        perm = torch.randperm(n, generator=g, device=DEV)
+        for b in range(0, n, 8192):
+            idx = perm[b:b + 8192]
+            net.train_step(Xs[idx].contiguous(), ts[idx].contiguous(), 3e-3 * 0.5 ** (ep // 2))
+    return net
+
+
+def combined_run(grid, eos, metric, q0, dt, mlp):
+    """SSP-RK3 steps through a one-patch batched plan, mixed precision,
+    recovery seeded by the network."""
+    md = {k: torch.from_numpy(v).to(DEV) if isinstance(v, np.ndarray) else v for k, v in metric.items()}
+    opts = dict(recon="ppm", riemann="hllc", prec="mixed", c2p=dict(C2P, mlp=mlp))
+    q = torch.from_numpy(q0).to(DEV)
+    bufs = dict(q=q, q1=torch.zeros_like(q), q2=torch.zeros_like(q),
+                p=torch.zeros((6,) + q.shape[1:], dtype=torch.float64, device=DEV))
+    roles = [("q", "q", "q1"), ("q", "q1", "q2"), ("q", "q2", "q1")]
+
+    def descr(b, s):
+        qn, qs, qo = roles[s]
+        return [dict(grid=grid, metric=md, qn=b[qn], qs=b[qs], qout=b[qo], p=b["p"],
+                     stage=dict(SSP[s], dt=dt), eos_id=0)]
+    plan = grhd.Plan(descr(bufs, 0), [eos], opts)
+    bufs["q"].copy_(torch.from_numpy(q0))
+    diag = grhd.new_diag()
+    iters = 0
+    for _ in range(STEPS):
+        for s in range(3):
+            plan(descr(bufs, s), diag=diag)
+            iters += grhd.read_diag(diag)["iter_sum"] if s == 0 else 0
+        bufs["q"], bufs["q1"] = bufs["q1"], bufs["q"]
+    grhd.con2prim(grid, eos, md, C2P, bufs["q"].clone(), bufs["p"])
+    torch.cuda.synchronize()
+    plan.close()
+    return bufs["p"].cpu().numpy(), iters
+
+
 @pytest.fixture(scope="module")
 def runs(orc):
     tov = synth.tov_solve()
@@ -112,6 +174,8 @@ def runs(orc):
     dt = 0.4 * grid["dx"]
     ref = oracle_run(orc, grid, eos, metric, q0, dt)
     out = {prec: gpu_run(grid, eos, metric, q0, dt, prec) for prec in ("mixed", "fp64")}
+    net = train_star_guess(orc)
+    out["combined"], out["combined_iters"] = combined_run(grid, eos, metric, q0, dt, net.buf)
     return grid, metric, ref, out
 
 
@@ -128,3 +192,13 @@ def test_fp64_300_substeps_against_oracle(runs):
     f = l1_figures(grid, metric, out["fp64"], ref)
     print("FP64 vs FP64 oracle after %d substeps: %s" % (3 * STEPS, f))
     assert f["rho"] <= 1e-10 and f["eps"] <= 1e-10 and f["v"] <= 1e-10 * max(f["vmax"], 1e-3), f
+
+
+def test_combined_form_300_substeps_against_oracle(runs):
+    """Mixed precision + batched plan + learned guess, same bars as the
+    mixed form."""
+    grid, metric, ref, out = runs
+    f = l1_figures(grid, metric, out["combined"], ref)
+    print("combined vs FP64 oracle after %d substeps: %s (first-stage master-function evaluations "
+          "summed over the run: %d)" % (3 * STEPS, f, out["combined_iters"]))
+    assert f["rho"] <= 1e-5 and f["eps"] <= 1e-5 and f["v"] <= 1e-4, f

@@ -8,13 +8,17 @@
   loss, and the recovery seeded by the trained network reaches the same
   root as the paper's Illinois recovery and as the oracle's bisection
   (1e-12 normwise on the primitives) with fewer master-function
-  evaluations on the differentially rotating workload.
+  evaluations on the differentially rotating workload;
+- the batched plan with the learned guess (star levels, a rotating-field
+  patch and Riemann patches in one graph) lands every patch on the same
+  state as the plan without it (1e-12 normwise, per cell on the positive
+  fields) and as the oracle's stage.
 """
 import numpy as np
 import pytest
 
 import synth
-from cmp import percell, percell_cond
+from cmp import normwise, percell, percell_cond
 
 pytestmark = pytest.mark.gpu
 
@@ -69,9 +73,9 @@ def test_gradient_matches_oracle(orc):
         assert err <= 1e-4, (a, b, err)
 
 
-def training_pairs(orc, seed, n):
+def training_pairs(orc, seed, n, sampler=None):
     """(D, S, tau) -> P pairs from the oracle's prim->con on seeded states."""
-    prims = synth.recovery_samples(seed, n)
+    prims = (sampler or synth.recovery_samples)(seed, n)
     grid = synth.make_grid(n, 1, 0.0, 0.0, 1.0, 1.0, "cart", ("outflow",) * 4)
     p = synth.empty_fields(grid, 6)
     synth.interior(grid, p)[:, 0, :] = prims.T
@@ -84,8 +88,8 @@ def training_pairs(orc, seed, n):
     return X, y
 
 
-def train(orc, n=200_000, epochs=8, batch=8192, seed=11):
-    X, y = training_pairs(orc, seed, n)
+def train(orc, n=200_000, epochs=8, batch=8192, seed=11, sampler=None):
+    X, y = training_pairs(orc, seed, n, sampler)
     xm, xs = X.mean(axis=0), X.std(axis=0)
     ym, ys = y.mean(), y.std()
     scal = torch.tensor(list(xm) + list(xs) + [ym, ys], dtype=torch.float32, device=DEV)
@@ -141,3 +145,63 @@ def test_training_and_gain(orc):
     it_ill = res["illinois"][1]["iter_sum"]
     it_mlp = res["mlp"][1]["iter_sum"]
     assert it_mlp < it_ill, (it_mlp, it_ill)
+
+
+def test_batch_with_learned_guess(orc):
+    """The batched recovery seeded by the network (star levels, a
+    rotating-field patch, Riemann patches, FP64) against the same plan with
+    the paper's Illinois recovery and against the oracle's stage."""
+    def both(seed, n):
+        a = synth.recovery_samples(seed, n // 2)
+        b = synth.star_recovery_samples(seed + 1, n - n // 2)
+        return np.concatenate([a, b])
+    net, _ = train(orc, n=100_000, epochs=4, sampler=both)
+    tov = synth.tov_solve()
+    patches = []
+    for lvl, grid in enumerate(synth.fmr_levels(2, 48, finest_extent=20.0)):
+        p, metric, eos = synth.star_problem(grid, seed=40 + lvl, tov=tov, vel=0.05)
+        patches.append(dict(grid=grid, metric=metric, p=p, eos_id=0))
+    rg = synth.make_grid(96, 24, 0.0, 0.0, 20.0 / 96, 20.0 / 96, "cart", ("outflow",) * 4)
+    patches.append(dict(grid=rg, metric={}, p=synth.rotating_field(rg, 8), eos_id=0))
+    gam = 5.0 / 3.0
+    for nxr, (L, R) in zip((77, 130), synth.riemann_states(9, 2, gam)):
+        g = synth.riemann_grid(nxr, nz=8)
+        patches.append(dict(grid=g, metric={}, p=synth.riemann_prims(g, L, R, gam), eos_id=1))
+    eos_table = [synth.ideal_eos(2.0, 100.0), synth.ideal_eos(gam)]
+    c2p = dict(w_max=100.0, rho_atm=1e-10)
+    out = {}
+    for name, mlp in (("illinois", None), ("mlp", net.buf)):
+        opts = dict(recon="ppm", riemann="hllc", prec="fp64", c2p=dict(c2p, mlp=mlp))
+        bufs, descs = [], []
+        for pt in patches:
+            q0 = orc.prim2con(pt["grid"], eos_table[pt["eos_id"]], pt["metric"], pt["p"], with_ghosts=True)
+            q = torch.from_numpy(q0).to(DEV)
+            b = dict(q0=q0, q=q, q1=torch.zeros_like(q),
+                     p=torch.zeros((6,) + q.shape[1:], dtype=torch.float64, device=DEV))
+            bufs.append(b)
+            descs.append(dict(grid=pt["grid"], metric={k: torch.from_numpy(v).to(DEV) for k, v in pt["metric"].items()},
+                              qn=b["q"], qs=b["q"], qout=b["q1"], p=b["p"],
+                              stage=dict(grhd.SSPRK3[0], dt=0.4 * pt["grid"]["dx"]), eos_id=pt["eos_id"]))
+        plan = grhd.Plan(descs, eos_table, opts)
+        for b in bufs:   # plan creation may have timed the batch on the buffers
+            b["q"].copy_(torch.from_numpy(b["q0"]))
+        dg = grhd.new_diag()
+        plan(descs, diag=dg)
+        torch.cuda.synchronize()
+        out[name] = [dict(q1=b["q1"].cpu().numpy(), q=b["q"].cpu().numpy(), p=b["p"].cpu().numpy())
+                     for b in bufs]
+        out[name + "_diag"] = grhd.read_diag(dg)
+        plan.close()
+    for i, pt in enumerate(patches):
+        g = pt["grid"]
+        I = lambda a: synth.interior(g, a)  # noqa: E731
+        ref = orc.rk_substep(g, eos_table[pt["eos_id"]], pt["metric"], dict(recon="ppm", riemann="hllc", c2p=c2p),
+                             dict(grhd.SSPRK3[0], dt=0.4 * g["dx"]), bufs[i]["q0"], bufs[i]["q0"])
+        for name in ("illinois", "mlp"):
+            o = out[name][i]
+            assert normwise(I(o["q1"]), I(ref["qout"])) <= 1e-12, (name, i)
+            assert normwise(I(o["p"]), I(ref["p"])) <= 1e-12, (name, i)
+            assert percell(I(o["p"]), I(ref["p"]), (0,)) <= 1e-12, (name, i)
+            assert percell_cond(I(o["p"]), I(ref["p"]), I(ref["qs"])) <= 1e-12, (name, i)
+        assert normwise(I(out["mlp"][i]["q1"]), I(out["illinois"][i]["q1"])) <= 1e-12, i
+    assert out["mlp_diag"]["n_fail"] == out["illinois_diag"]["n_fail"] == 0
