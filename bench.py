@@ -34,8 +34,10 @@ The JSON line also carries:
                  composite baryon-mass change over the timed steps;
   forms.bondi    Bondi accretion in the maximal trumpet slice (shift, lapse
                  and extrinsic curvature all active) on [0, 16M]^2 to t = 20M
-                 at N = 64, 128, 256, PPM and minmod: zone-updates/s and
-                 the L1 density error of each, with the convergence orders;
+                 at N = 64, 128, 256: PPM (CW84) and minmod with HLLC, the
+                 per-cell third-order parabola (PPM3) with HLLC and TVDLF;
+                 zone-updates/s and the L1 density error of each, with the
+                 convergence orders;
   forms.bondi_rt the hot bubble in the Bondi flow (N = 512, t = 25M), HLLC
                  against TVDLF: total variation of the density (sharper
                  fingers give more) and zone-updates/s;
@@ -718,9 +720,11 @@ def bondi_form(args):
     dev = torch.device("cuda:0")
     c2p = dict(w_max=100.0, rho_atm=1e-14)
     res = {"workload": "Bondi accretion, maximal trumpet slice of Schwarzschild, Gamma 4/3, K = 1, "
-                       "r_c = 8M, [0, 16M]^2 cylindrical, fixed for r < 0.4M, PPM+HLLC, SSP-RK3 to t = 20M"}
+                       "r_c = 8M, [0, 16M]^2 cylindrical, fixed for r < 0.4M, SSP-RK3 to t = 20M; "
+                       "keys recon[_riemann]_N"}
     errs = {}
-    for recon, n in [("ppm", 64), ("ppm", 128), ("ppm", 256), ("minmod", 64), ("minmod", 128), ("minmod", 256)]:
+    cases = [("ppm", "hllc"), ("ppm3", "hllc"), ("ppm3", "tvdlf"), ("minmod", "hllc")]
+    for (recon, riemann), n in [(c, n) for c in cases for n in (64, 128, 256)]:
         d = 16.0 / n
         g = synth.make_grid(n, n, 0.0, 0.0, d, d, "cyl", ("axis", "external", "reflect", "external"))
         p, m, eos, frozen = synth.bondi_problem(g)
@@ -731,7 +735,7 @@ def bondi_form(args):
         qfix, q1, q2 = q.clone(), q.clone(), q.clone()
         mask = torch.from_numpy(frozen.astype(np.uint8)).to(dev)
         # the inner region is held inside each stage (no separate pass)
-        sub = grhd.Substep(g, eos, md, dict(recon=recon, riemann="hllc", prec="fp64", c2p=c2p,
+        sub = grhd.Substep(g, eos, md, dict(recon=recon, riemann=riemann, prec="fp64", c2p=c2p,
                                             fix=(mask, qfix)))
         pw = torch.zeros_like(pd)
         dt = 0.4 * d
@@ -751,13 +755,15 @@ def bondi_form(args):
         X, _ = synth.cell_coords(g)
         x = synth.interior(g, X)
         sg = synth.interior(g, m["alp"] * m["W"] ** -3) * x
-        errs[(recon, n)] = float((np.abs(rho - rho0) * sg).sum() / (np.abs(rho0) * sg).sum())
-        res["%s_N%d" % (recon, n)] = {"value": 3 * n * n * nsteps / wall, "unit": "zone-updates/s",
-                                      "steps": nsteps, "ms_per_step": wall * 1e3 / nsteps,
-                                      "l1_rho": errs[(recon, n)]}
-    for recon in ("ppm", "minmod"):
-        res["%s_order_64_128" % recon] = math.log2(errs[(recon, 64)] / errs[(recon, 128)])
-        res["%s_order_128_256" % recon] = math.log2(errs[(recon, 128)] / errs[(recon, 256)])
+        key = recon if riemann == "hllc" else recon + "_" + riemann
+        errs[(key, n)] = float((np.abs(rho - rho0) * sg).sum() / (np.abs(rho0) * sg).sum())
+        res["%s_N%d" % (key, n)] = {"value": 3 * n * n * nsteps / wall, "unit": "zone-updates/s",
+                                    "steps": nsteps, "ms_per_step": wall * 1e3 / nsteps,
+                                    "l1_rho": errs[(key, n)]}
+    for recon, riemann in cases:
+        key = recon if riemann == "hllc" else recon + "_" + riemann
+        res["%s_order_64_128" % key] = math.log2(errs[(key, 64)] / errs[(key, 128)])
+        res["%s_order_128_256" % key] = math.log2(errs[(key, 128)] / errs[(key, 256)])
     return res
 
 

@@ -60,7 +60,19 @@ enum { GRHD_GEOM_CYLINDRICAL = 0, GRHD_GEOM_CARTESIAN = 1 };
  * supplied by the caller and recovered like interior cells) */
 enum { GRHD_BC_OUTFLOW = 0, GRHD_BC_PERIODIC = 1, GRHD_BC_AXIS = 2,
        GRHD_BC_REFLECT = 3, GRHD_BC_EXTERNAL = 4 };
-enum { GRHD_RECON_PPM = 0, GRHD_RECON_MINMOD = 1 };
+/* reconstruction of the face states (Sec. II.C.2, third-order PPM):
+ * PPM    Colella & Woodward (1984): interface values from monotonised
+ *        slopes, then the parabola limiter; no steepening or flattening.
+ *        Where no limiter acts both sides of a face take the same value.
+ * MINMOD linear slopes limited by minmod (the paper's prolongation limiter)
+ * PPM3   each cell's parabola through its own and its two neighbours'
+ *        averages (third order), edge values clipped to the range of the
+ *        two averages meeting there, then the same parabola limiter; the
+ *        two face states differ by a sixth of the third difference across
+ *        the face, the upwind dissipation that PPM's shared interface
+ *        value lacks on smooth flows (Sec. III.B.2's second-order Bondi
+ *        convergence holds with PPM3, not with PPM) */
+enum { GRHD_RECON_PPM = 0, GRHD_RECON_MINMOD = 1, GRHD_RECON_PPM3 = 2 };
 enum { GRHD_RIEMANN_HLLC = 0, GRHD_RIEMANN_TVDLF = 1 };
 enum { GRHD_PREC_FP64 = 0, GRHD_PREC_MIXED = 1 };
 /* face states of the stage: every primitive reconstructed, eps included

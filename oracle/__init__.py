@@ -30,7 +30,7 @@ METRIC_NAMES = ["alp", "bx", "by", "bz", "W", "gxx", "gxy", "gxz", "gyy",
                 "gyz", "gzz", "kxx", "kxy", "kxz", "kyy", "kyz", "kzz"]
 FLAT = {"alp": 1.0, "W": 1.0, "gxx": 1.0, "gyy": 1.0, "gzz": 1.0}
 BC_NAMES = {"outflow": 0, "periodic": 1, "axis": 2, "reflect": 3, "external": 4}
-RECON = {"ppm": 0, "minmod": 1}
+RECON = {"ppm": 0, "minmod": 1, "ppm3": 2}
 RIEMANN = {"hllc": 0, "tvdlf": 1}
 # face states of the stage: "recon" reconstructs every primitive (Sec.
 # II.C.2); "eos" takes eps from the EOS at the reconstructed (rho, P)

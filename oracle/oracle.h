@@ -34,7 +34,8 @@ enum {
 enum { OR_GEOM_CYL = 0, OR_GEOM_CART = 1 };
 enum { OR_BC_OUTFLOW = 0, OR_BC_PERIODIC = 1, OR_BC_AXIS = 2,
        OR_BC_REFLECT = 3, OR_BC_EXTERNAL = 4 };
-enum { OR_RECON_PPM = 0, OR_RECON_MINMOD = 1 };
+/* PPM: CW84's interface form; PPM3: per-cell three-average parabola */
+enum { OR_RECON_PPM = 0, OR_RECON_MINMOD = 1, OR_RECON_PPM3 = 2 };
 enum { OR_RIEMANN_HLLC = 0, OR_RIEMANN_TVDLF = 1 };
 /* face states of the stage: every primitive reconstructed (Sec. II.C.2,
  * the default), or eps taken from the EOS at the reconstructed (rho, P)

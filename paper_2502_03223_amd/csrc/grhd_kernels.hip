@@ -572,7 +572,8 @@ extern "C" int grhd_reconstruct(const grhd_grid *grid, int dir, int recon, int p
       (rc = check_prim(pR, "pR")))
     return rc;
   if (dir != 0 && dir != 1) return fail(GRHD_ERR_INVALID, "dir must be 0 or 1");
-  if (recon != GRHD_RECON_PPM && recon != GRHD_RECON_MINMOD) return fail(GRHD_ERR_INVALID, "bad recon");
+  if (recon != GRHD_RECON_PPM && recon != GRHD_RECON_MINMOD && recon != GRHD_RECON_PPM3)
+    return fail(GRHD_ERR_INVALID, "bad recon");
   if (prec != GRHD_PREC_FP64 && prec != GRHD_PREC_MIXED) return fail(GRHD_ERR_INVALID, "bad prec");
   hipStream_t st = (hipStream_t)hip_stream;
   GridK g = to_gridk(grid);
@@ -650,7 +651,8 @@ int fill_patch(const grhd_grid *grid, const grhd_metric *metric, const grhd_rk_s
   if (stage->a != 0.0 && (rc = check_cons(qn, "qn"))) return rc;
   if (acc_in && (rc = check_cons(acc_in, "acc_in"))) return rc;
   if (acc_out && (rc = check_cons(acc_out, "acc_out"))) return rc;
-  if (recon != GRHD_RECON_PPM && recon != GRHD_RECON_MINMOD) return fail(GRHD_ERR_INVALID, "bad recon");
+  if (recon != GRHD_RECON_PPM && recon != GRHD_RECON_MINMOD && recon != GRHD_RECON_PPM3)
+    return fail(GRHD_ERR_INVALID, "bad recon");
   if (riemann != GRHD_RIEMANN_HLLC && riemann != GRHD_RIEMANN_TVDLF) return fail(GRHD_ERR_INVALID, "bad riemann");
   // q_out may alias q^n (each cell reads its own q^n before writing
   // q_out), never q_s (whose halo other tiles read)

@@ -28,7 +28,7 @@ METRIC_NAMES = ["alp", "bx", "by", "bz", "W", "gxx", "gxy", "gxz", "gyy",
 FLAT = {"alp": 1.0, "W": 1.0, "gxx": 1.0, "gyy": 1.0, "gzz": 1.0}
 BC = {"outflow": 0, "periodic": 1, "axis": 2, "reflect": 3, "external": 4}
 GEOM = {"cyl": 0, "cart": 1}
-RECON = {"ppm": 0, "minmod": 1}
+RECON = {"ppm": 0, "minmod": 1, "ppm3": 2}
 RIEMANN = {"hllc": 0, "tvdlf": 1}
 PREC = {"fp64": 0, "mixed": 1}
 FACE_EPS = {"recon": 0, "eos": 1}

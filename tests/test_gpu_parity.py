@@ -128,7 +128,7 @@ def test_con2prim(orc, tov, case):
         assert d[k] == d_o[k], k
 
 
-@pytest.mark.parametrize("recon", ["ppm", "minmod"])
+@pytest.mark.parametrize("recon", ["ppm", "minmod", "ppm3"])
 @pytest.mark.parametrize("dirn", [0, 1])
 def test_reconstruct_bitwise(orc, tov, recon, dirn):
     grid, p, metric, eos = star_case(70, 5, tov, vel=0.1)
@@ -222,7 +222,8 @@ def check_pair(grid, ref, out, tol=TOL, flag_mask=0xFF):
 
 
 @pytest.mark.parametrize("seed,face_eps", [(0, "recon"), (1, "recon"), (2, "recon"), (0, "eos")])
-@pytest.mark.parametrize("riemann,recon", [("hllc", "ppm"), ("tvdlf", "ppm"), ("hllc", "minmod")])
+@pytest.mark.parametrize("riemann,recon", [("hllc", "ppm"), ("tvdlf", "ppm"), ("hllc", "minmod"),
+                                           ("hllc", "ppm3")])
 def test_substep_riemann(orc, seed, riemann, recon, face_eps):
     """Riemann problems on 400 x 8 (Cartesian, flat, periodic z), all three
     SSP-RK3 stages from oracle-evolved states."""
@@ -274,14 +275,14 @@ def test_paper_shock_tube_substeps(orc):
         q = ref["qout"]
 
 
-@pytest.mark.parametrize("face_eps", ["recon", "eos"])
+@pytest.mark.parametrize("recon,face_eps", [("ppm", "recon"), ("ppm", "eos"), ("ppm3", "recon")])
 @pytest.mark.parametrize("n", [64, 93])
 @pytest.mark.parametrize("stage", [0, 1, 2])
-def test_substep_star(orc, tov, n, stage, face_eps):
+def test_substep_star(orc, tov, n, stage, recon, face_eps):
     grid, p, metric, eos = star_case(n, 10 + n + stage, tov, vel=0.05)
     q = orc.prim2con(grid, eos, metric, p, with_ghosts=True)
     qn = orc.prim2con(grid, eos, metric, star_case(n, 99, tov, vel=0.05)[1], with_ghosts=True)
-    opts = dict(recon="ppm", riemann="hllc", prec="fp64", c2p=C2P_STAR, face_eps=face_eps)
+    opts = dict(recon=recon, riemann="hllc", prec="fp64", c2p=C2P_STAR, face_eps=face_eps)
     st = dict(grhd.SSPRK3[stage], dt=0.4 * grid["dx"])
     ref, out = run_pair(orc, grid, eos, metric, opts, st, qn, q)
     check_pair(grid, ref, out)

@@ -2,7 +2,9 @@
 Riemann fluxes and source terms (paper Sec. II.C.1-2).
 
 - PPM (CW84) reproduces cell averages of cubics where the limiters are
-  inactive; minmod reproduces linear profiles; a monotone step stays
+  inactive; the per-cell parabola (PPM3) reproduces quadratics and leaves
+  a face jump of -c3 h^3 on a cubic (CW84's form none); minmod reproduces
+  linear profiles; a monotone step stays
   monotone; 6-point interpolation is exact for quintics; the 6th-order
   derivative is exact for polynomials of degree 6.
 - Valencia flux equals the covariant densitised flux sqrt(-g) T^n_j etc.
@@ -47,6 +49,38 @@ def test_ppm_exact_for_cubic(orc):
     assert np.allclose(aR, exact, rtol=0, atol=1e-13)
 
 
+def test_ppm3_exact_for_quadratic(orc):
+    """The per-cell parabola reproduces a quadratic from its cell averages
+    on both sides of every face (limiters inactive on a monotone, gently
+    curved profile)."""
+    c = [0.3, 1.0, 0.2]
+    n = 40
+    xf = np.linspace(0.0, 1.0, n + 1)
+    a = cell_avg_poly(c, xf[:-1], xf[1:])
+    aL, aR = orc.recon_line("ppm3", a)
+    exact = np.polynomial.polynomial.polyval(xf[3:n - 2], c)
+    assert np.allclose(aL, exact, rtol=0, atol=1e-13)
+    assert np.allclose(aR, exact, rtol=0, atol=1e-13)
+
+
+def test_ppm3_face_jump_of_a_cubic(orc):
+    """On cell averages of a cubic c3 x^3 + ..., the per-cell parabolas of
+    the two cells at a face miss the cubic by opposite amounts: the right
+    state minus the left state is -c3 h^3 at every face.  CW84's form gives
+    both sides the same interface value there (jump 0, no dissipation from
+    the Riemann solver)."""
+    c3 = 0.05
+    c = [0.3, 1.0, 0.2, c3]
+    n = 40
+    h = 1.0 / n
+    xf = np.linspace(0.0, 1.0, n + 1)
+    a = cell_avg_poly(c, xf[:-1], xf[1:])
+    aL, aR = orc.recon_line("ppm3", a)
+    assert np.allclose(aR - aL, -c3 * h ** 3, rtol=1e-6, atol=1e-15)
+    bL, bR = orc.recon_line("ppm", a)
+    assert np.abs(bR - bL).max() <= 1e-15
+
+
 def test_minmod_exact_for_linear(orc):
     xf = np.linspace(0.0, 1.0, 31)
     a = 2.0 - 3.0 * 0.5 * (xf[:-1] + xf[1:])
@@ -55,7 +89,7 @@ def test_minmod_exact_for_linear(orc):
     assert np.allclose(aL, exact, atol=1e-14) and np.allclose(aR, exact, atol=1e-14)
 
 
-@pytest.mark.parametrize("recon", ["ppm", "minmod"])
+@pytest.mark.parametrize("recon", ["ppm", "minmod", "ppm3"])
 def test_monotone_step_stays_monotone(orc, recon):
     a = np.array([1.0] * 10 + [0.7, 0.3] + [0.1] * 10)
     aL, aR = orc.recon_line(recon, a)
