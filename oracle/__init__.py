@@ -124,8 +124,9 @@ def lib():
             "or_face_flux": (None, [p, i, i, p, p, p, p, p, p]),
             "or_rhs": (None, [p, p, p, p, p, p, p]),
             "or_rk_substep": (i, [p, p, p, i, i, i, p, p, p, p, p, p, p, p, p, p, p]),
-            "or_rk_substep_reg": (i, [p, p, p, i, i, i, p, p, p, p, p, p, p, p, p, p, p, p, i, i, d]),
-            "or_fmr_prolong": (None, [p, p, p, p, i, d, d, d, d, p, p, p, p, p]),
+            "or_rk_substep_reg": (i, [p, p, p, i, i, i, p, p, p, p, p, p, p, p, p, p, p, p, i, i, d,
+                                      p, p]),
+            "or_fmr_prolong": (None, [p, p, p, p, i, d, d, d, d, p, p, p, i, p, p]),
             "or_fmr_restrict": (None, [p, p, p, p]),
             "or_fmr_reflux": (None, [p, p, p, p, p]),
             "or_riemann_solve": (i, [d, d, d, d, d, d, d, p]),
@@ -379,12 +380,14 @@ SSPRK3 = [dict(a=0.0, b=1.0, c=1.0), dict(a=0.75, b=0.25, c=0.25),
           dict(a=1.0 / 3.0, b=2.0 / 3.0, c=2.0 / 3.0)]
 
 
-def rk_substep(grid, eos, metric, opts, stage, qn, qs, acc_in=None, want_acc=False, reg=None):
+def rk_substep(grid, eos, metric, opts, stage, qn, qs, acc_in=None, want_acc=False, reg=None,
+               want_faces=False):
     """One substep.  Returns dict(qout, qs (corrected), p, flags, diag,
-    flux_reg, acc).  Inputs are not modified.  reg: optional (array,
+    flux_reg, acc, Fx, Fz).  Inputs are not modified.  reg: optional (array,
     reg_j, reg_k, weight): the refinement-boundary register (5 x (reg_k +
     reg_j) float64, updated in place) gets weight dt F added on the face
-    set {x faces j = reg_j, k < reg_k} + {z faces k = reg_k, j < reg_j}."""
+    set {x faces j = reg_j, k < reg_k} + {z faces k = reg_k, j < reg_j}.
+    want_faces: Fx (5, nz, nx + 1) and Fz (5, nz + 1, nx), every face flux."""
     keep = []
     qs = qs.copy()
     qout = np.zeros_like(qs)
@@ -400,6 +403,9 @@ def rk_substep(grid, eos, metric, opts, stage, qn, qs, acc_in=None, want_acc=Fal
     qn_ptr = _fieldptrs(qn, 5) if qn is not None else None
     if reg is not None:
         assert reg[0].dtype == np.float64 and reg[0].flags.c_contiguous
+    nx, nz = grid["nx"], grid["nz"]
+    fx = np.zeros((5, nz, nx + 1)) if want_faces else None
+    fz = np.zeros((5, nz + 1, nx)) if want_faces else None
     lib().or_rk_substep_reg(
         C.byref(make_grid(grid)), C.byref(make_eos(eos)),
         C.byref(make_metric(metric, keep)), RECON[opts.get("recon", "ppm")],
@@ -412,17 +418,19 @@ def rk_substep(grid, eos, metric, opts, stage, qn, qs, acc_in=None, want_acc=Fal
         _ptr(freg), _ptr(flags), C.byref(d),
         _ptr(reg[0]) if reg is not None else None,
         reg[1] if reg is not None else 0, reg[2] if reg is not None else 0,
-        float(reg[3]) if reg is not None else 0.0)
+        float(reg[3]) if reg is not None else 0.0,
+        _fieldptrs(fx, 5) if want_faces else None, _fieldptrs(fz, 5) if want_faces else None)
     return dict(qout=qout, qs=qs, p=p, flags=flags, diag=d.as_dict(),
-                flux_reg=freg.reshape(5, nb), acc=acc_out)
+                flux_reg=freg.reshape(5, nb), acc=acc_out, Fx=fx, Fz=fz)
 
 
 # ---------------------------------------------------------------- refinement
 
-def fmr_prolong(pgrid, slices, times, t, cgrid, eos, cmetric, p_child, q_child):
+def fmr_prolong(pgrid, slices, times, t, cgrid, eos, cmetric, p_child, q_child, nbuf=0):
     """Fill the child's EXTERNAL ghost cells (p_child 6 and q_child 5 cell
     arrays, updated in place) from the parent's primitive slices (a list of
-    1-3 arrays, oldest first, with their times) at time t."""
+    1-3 arrays, oldest first, with their times) at time t; with nbuf > 0
+    also the nbuf interior rows/columns next to each EXTERNAL side."""
     keep = []
     ns = len(slices)
     old = slices[0] if ns == 3 else None
@@ -434,7 +442,7 @@ def fmr_prolong(pgrid, slices, times, t, cgrid, eos, cmetric, p_child, q_child):
     lib().or_fmr_prolong(C.byref(make_grid(pgrid)), _fieldptrs(old, 6) if old is not None else None,
                          _fieldptrs(cur, 6), _fieldptrs(new, 6) if new is not None else None, ns,
                          t_old, t_cur, t_new, t, C.byref(make_grid(cgrid)), C.byref(make_eos(eos)),
-                         C.byref(make_metric(cmetric, keep)), _fieldptrs(p_child, 6),
+                         C.byref(make_metric(cmetric, keep)), int(nbuf), _fieldptrs(p_child, 6),
                          _fieldptrs(q_child, 5))
 
 
@@ -454,11 +462,26 @@ def fmr_reflux(pgrid, q_parent, preg, cgrid, creg):
 class FmrDriver:
     """Berger-Oliger driver of the oracle (Sec. II.E): the same schedule as
     the library's (SSP-RK3 per level, levels l <= l_fix take the parent's
-    step and finer ones half of it, a child's ghost cells prolonged from its
-    parent's slices at every stage time, restriction, flux correction and
+    step and finer ones half of it, restriction, flux correction and
     recovery of the parent after its child's steps), with every operation
     done by the oracle functions above.  levels: list of dict(grid, metric,
-    q) with numpy cell arrays (q is copied)."""
+    q, nbuf=0) with numpy cell arrays (q is copied).
+
+    Two schedules for a child's boundary, per level (nbuf):
+    - nbuf = 0, the halo schedule: the 3 ghost cells beyond each EXTERNAL
+      side are prolonged from the parent's slices before every stage, at
+      the time of the stage's input state;
+    - nbuf > 0, the buffer schedule of Sec. II.E (the paper's (4+4) with
+      nbuf = 4): the level's grid holds nbuf cells beyond its own cells on
+      each EXTERNAL side.  Before the first stage the buffer and the ghost
+      cells beyond it are prolonged at t; the first two stages evolve own
+      cells and buffer alike, the second after the ghost cells are
+      prolonged at t + dt; the last stage updates the own cells only,
+      reading the buffer as the second stage left it (the paper's RK4
+      mapping, all stages but the last on the wider domain, taken to
+      SSP-RK3 as a reading).  Restriction, registers and flux correction
+      concern the own cells.
+    """
 
     A = (0.0, 0.75, 1.0 / 3.0)
     B = (1.0, 0.25, 2.0 / 3.0)
@@ -466,20 +489,26 @@ class FmrDriver:
     W = (1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0)   # weights of the stage fluxes in the step
 
     def __init__(self, levels, eos, opts, l_fix=0, t0=0.0):
-        self.lev = [dict(grid=d["grid"], metric=d["metric"], q=np.array(d["q"], dtype=np.float64))
-                    for d in levels]
+        self.lev = [dict(grid=d["grid"], metric=d["metric"], q=np.array(d["q"], dtype=np.float64),
+                         nbuf=int(d.get("nbuf", 0))) for d in levels]
+        assert self.lev[0]["nbuf"] == 0
         self.eos, self.opts, self.l_fix, self.t = eos, opts, l_fix, t0
         n = len(self.lev)
         self.slices = [[] for _ in range(n)]
         for l, L in enumerate(self.lev):
-            g = L["grid"]
-            L["reg_bnd"] = np.zeros(5 * (g["nx"] + g["nz"])) if l > 0 else None
+            own = self.own(l)
+            L["reg_bnd"] = np.zeros(5 * (own["nx"] + own["nz"])) if l > 0 else None
             if l + 1 < n:
-                cg = self.lev[l + 1]["grid"]
-                L["reg_int"] = np.zeros(5 * (cg["nx"] // 2 + cg["nz"] // 2))
+                co = self.own(l + 1)
+                L["reg_int"] = np.zeros(5 * (co["nx"] // 2 + co["nz"] // 2))
                 self._push(l, t0)
             else:
                 L["reg_int"] = None
+
+    def own(self, l):
+        """Level l's grid without its buffer (same arrays and pitch)."""
+        g, b = self.lev[l]["grid"], self.lev[l]["nbuf"]
+        return dict(g, nx=g["nx"] - b, nz=g["nz"] - b)
 
     def _recover(self, l):
         L = self.lev[l]
@@ -495,37 +524,46 @@ class FmrDriver:
         n = len(self.lev)
         L = self.lev[l]
         g = L["grid"]
-        nx, nz = g["nx"], g["nz"]
+        own = self.own(l)
+        nb = L["nbuf"]
         has_child, has_parent = l + 1 < n, l > 0
         if has_child:
-            cg = self.lev[l + 1]["grid"]
-            J, K = cg["nx"] // 2, cg["nz"] // 2
+            co = self.own(l + 1)
+            J, K = co["nx"] // 2, co["nz"] // 2
             L["reg_int"][:] = 0.0
         bufs = {"q": L["q"], "q1": np.zeros_like(L["q"]), "q2": np.zeros_like(L["q"])}
         order = [("q", "q", "q1"), ("q", "q1", "q2"), ("q", "q2", "q")]
         for s in range(3):
             qn_name, qs_name, qo_name = order[s]
-            if has_parent:
+            last_on_own = nb > 0 and s == 2
+            gs = own if last_on_own else g
+            if has_parent and not last_on_own:
                 P = self.lev[l - 1]
                 ts = [x[0] for x in self.slices[l - 1]]
                 sl = [x[1] for x in self.slices[l - 1]]
                 p_scratch = np.zeros((6,) + L["q"].shape[1:])
                 fmr_prolong(P["grid"], sl, ts, t + self.T[s] * dt, g, self.eos, L["metric"], p_scratch,
-                            bufs[qs_name])
+                            bufs[qs_name], nbuf=nb if s == 0 else 0)
             st = dict(a=self.A[s], b=self.B[s], c=self.B[s], dt=dt)
             reg = (L["reg_int"], J, K, self.W[s]) if has_child else None
-            r = rk_substep(g, self.eos, L["metric"], self.opts, st, bufs[qn_name], bufs[qs_name], reg=reg)
+            r = rk_substep(gs, self.eos, L["metric"], self.opts, st, bufs[qn_name], bufs[qs_name], reg=reg,
+                           want_faces=has_parent and nb > 0)
             bufs[qs_name] = r["qs"]
             if qs_name == "q":
                 bufs["q"] = r["qs"]
             if has_parent:
-                fr = r["flux_reg"]
                 w = self.W[s] * dt
-                rb = L["reg_bnd"].reshape(5, nx + nz)
-                rb[:, :nz] += w * fr[:, nz:2 * nz]
-                rb[:, nz:] += w * fr[:, 2 * nz + nx:]
+                onx, onz = own["nx"], own["nz"]
+                rb = L["reg_bnd"].reshape(5, onx + onz)
+                if nb == 0:
+                    fr = r["flux_reg"]
+                    rb[:, :onz] += w * fr[:, onz:2 * onz]
+                    rb[:, onz:] += w * fr[:, 2 * onz + onx:]
+                else:
+                    rb[:, :onz] += w * r["Fx"][:, :onz, onx]
+                    rb[:, onz:] += w * r["Fz"][:, onz, :onx]
             out = np.array(bufs[qo_name]) if qo_name != "q" else bufs["q"]
-            I = (slice(None), slice(g["ng"], g["ng"] + nz), slice(g["ng"], g["ng"] + nx))
+            I = (slice(None), slice(gs["ng"], gs["ng"] + gs["nz"]), slice(gs["ng"], gs["ng"] + gs["nx"]))
             out[I] = r["qout"][I]
             bufs[qo_name] = out
         L["q"] = bufs["q"]
@@ -536,8 +574,8 @@ class FmrDriver:
         for i in range(nsub):
             self._step(l + 1, t + i * (dt / nsub), dt / nsub)
         C_ = self.lev[l + 1]
-        fmr_restrict(g, L["q"], C_["grid"], C_["q"])
-        fmr_reflux(g, L["q"], L["reg_int"], C_["grid"], C_["reg_bnd"])
+        fmr_restrict(g, L["q"], co, C_["q"])
+        fmr_reflux(g, L["q"], L["reg_int"], co, C_["reg_bnd"])
         C_["reg_bnd"][:] = 0.0
         self.slices[l][-1] = (t + dt, self._recover(l))
 

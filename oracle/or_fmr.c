@@ -27,7 +27,11 @@
  *  - flux correction: the registers hold the time integral of each face
  *    flux over the level's step (sum over Runge-Kutta stages of the stage
  *    weight times dt times the flux); the parent cell next to the interface
- *    takes the area-weighted child integral in place of its own.
+ *    takes the area-weighted child integral in place of its own;
+ *  - the (4+4) buffer schedule: the band of nbuf interior cells next to
+ *    the child's EXTERNAL sides is prolonged together with the halo (at
+ *    the start of a child step) and then evolved by the child's own
+ *    stages; the schedule itself lives in the driver.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -67,7 +71,7 @@ static double time_interp(int nslice, double a_old, double a_cur, double a_new, 
 void or_fmr_prolong(const or_grid *pg, double *const *p_old, double *const *p_cur,
                     double *const *p_new, int nslice, double t_old, double t_cur,
                     double t_new, double t, const or_grid *cg, const or_eos *e,
-                    const or_metric *cm, double *const *cp, double *const *cq) {
+                    const or_metric *cm, int nbuf, double *const *cp, double *const *cq) {
   int64_t n = (int64_t)(pg->nz + 2 * pg->ng) * pg->pitch;
   /* 1. the parent's primitives at time t, every stored cell */
   double *pt[6];
@@ -79,14 +83,23 @@ void or_fmr_prolong(const or_grid *pg, double *const *p_old, double *const *p_cu
   }
   /* 2. the parent's boundary conditions on those primitives */
   or_fill_ghosts(pg, pt);
-  /* 3. every child ghost cell of the cross-shaped halo on an EXTERNAL side */
+  /* 3. every child ghost cell of the cross-shaped halo on an EXTERNAL
+   * side, and every interior cell within nbuf cells of an EXTERNAL side */
   int ng = cg->ng;
   for (int kf = -ng; kf < cg->nz + ng; kf++)
     for (int jf = -ng; jf < cg->nx + ng; jf++) {
       int jin = jf >= 0 && jf < cg->nx, kin = kf >= 0 && kf < cg->nz;
-      if (jin == kin) continue; /* interior or corner */
-      int side = !jin ? (jf < 0 ? 0 : 1) : (kf < 0 ? 2 : 3);
-      if (cg->bc[side] != OR_BC_EXTERNAL) continue;
+      if (!jin && !kin) continue; /* corner */
+      if (jin && kin) {
+        int band = (cg->bc[0] == OR_BC_EXTERNAL && jf < nbuf) ||
+                   (cg->bc[1] == OR_BC_EXTERNAL && jf >= cg->nx - nbuf) ||
+                   (cg->bc[2] == OR_BC_EXTERNAL && kf < nbuf) ||
+                   (cg->bc[3] == OR_BC_EXTERNAL && kf >= cg->nz - nbuf);
+        if (!band) continue;
+      } else {
+        int side = !jin ? (jf < 0 ? 0 : 1) : (kf < 0 ? 2 : 3);
+        if (cg->bc[side] != OR_BC_EXTERNAL) continue;
+      }
       int jc = (jf >= 0) ? jf / 2 : -((1 - jf) / 2);
       int kc = (kf >= 0) ? kf / 2 : -((1 - kf) / 2);
       double ox = cx(cg, jf) - cx(pg, jc), oz = cz(cg, kf) - cz(pg, kc);

@@ -992,7 +992,7 @@ int or_rk_substep(const or_grid *gr, const or_eos *e, const or_metric *m,
                   double *const *acc_out, double *flux_reg, uint8_t *flags,
                   or_diag *diag) {
   return or_rk_substep_reg(gr, e, m, recon, riemann, face_eps, cp, st, qn, qs, qout, p_out,
-                           acc_in, acc_out, flux_reg, flags, diag, NULL, 0, 0, 0.0);
+                           acc_in, acc_out, flux_reg, flags, diag, NULL, 0, 0, 0.0, NULL, NULL);
 }
 
 int or_rk_substep_reg(const or_grid *gr, const or_eos *e, const or_metric *m,
@@ -1001,7 +1001,8 @@ int or_rk_substep_reg(const or_grid *gr, const or_eos *e, const or_metric *m,
                       double *const *qn, double *const *qs, double *const *qout,
                       double *const *p_out, double *const *acc_in,
                       double *const *acc_out, double *flux_reg, uint8_t *flags,
-                      or_diag *diag, double *reg, int reg_j, int reg_k, double reg_w) {
+                      or_diag *diag, double *reg, int reg_j, int reg_k, double reg_w,
+                      double *const *fx_out, double *const *fz_out) {
   int nx = gr->nx, nz = gr->nz;
   int64_t ncell = (int64_t)(nz + 2 * gr->ng) * gr->pitch;
   int64_t nfxa = (int64_t)nz * (nx + 1), nfza = (int64_t)(nz + 1) * nx;
@@ -1076,6 +1077,11 @@ int or_rk_substep_reg(const or_grid *gr, const or_eos *e, const or_metric *m,
         reg[c * nr + reg_k + j] += reg_w * st->dt * Fz[c][(int64_t)reg_k * nx + j];
     }
   }
+  /* 7c. every face flux, for registers on other face sets */
+  if (fx_out)
+    for (int c = 0; c < 5; c++) memcpy(fx_out[c], Fx[c], sizeof(double) * (size_t)nfxa);
+  if (fz_out)
+    for (int c = 0; c < 5; c++) memcpy(fz_out[c], Fz[c], sizeof(double) * (size_t)nfza);
   /* 8. diagnostics on the stage output */
   if (diag) {
     double cx = sx * st->dt / gr->dx, cz = sz * st->dt / gr->dz;

@@ -162,13 +162,17 @@ int or_rk_substep_reg(const or_grid *gr, const or_eos *e, const or_metric *m,
                       double *const *qn, double *const *qs, double *const *qout,
                       double *const *p_out, double *const *acc_in,
                       double *const *acc_out, double *flux_reg, uint8_t *flags,
-                      or_diag *diag, double *reg, int reg_j, int reg_k, double reg_w);
+                      or_diag *diag, double *reg, int reg_j, int reg_k, double reg_w,
+                      double *const *fx_out /* 5 x nz x (nx+1), nullable */,
+                      double *const *fz_out /* 5 x (nz+1) x nx, nullable */);
 
 /* fixed mesh refinement between a parent level and its child, which
  * covers the parent cells [0, nx_c/2) x [0, nz_c/2) with half the spacing
  * (Sec. II.A, II.E).
  * prolong: the child's ghost cells on EXTERNAL sides (the cross-shaped
- * halo) from the parent's primitives: time interpolation of nslice parent
+ * halo) and, with nbuf > 0, the child's last nbuf rows/columns of interior
+ * cells next to each EXTERNAL side (the inner buffer of the (4+4) buffer
+ * schedule) from the parent's primitives: time interpolation of nslice parent
  * slices (1: p_cur; 2: linear between t_cur and t_new; 3: quadratic over
  * t_old, t_cur, t_new, linear where the slices are not monotone) at time t,
  * then minmod-limited linear prolongation in space, then the conserved
@@ -180,7 +184,8 @@ int or_rk_substep_reg(const or_grid *gr, const or_eos *e, const or_metric *m,
 void or_fmr_prolong(const or_grid *pg, double *const *p_old, double *const *p_cur,
                     double *const *p_new, int nslice, double t_old, double t_cur,
                     double t_new, double t, const or_grid *cg, const or_eos *e,
-                    const or_metric *cm, double *const *cp /*6*/, double *const *cq /*5*/);
+                    const or_metric *cm, int nbuf, double *const *cp /*6*/,
+                    double *const *cq /*5*/);
 void or_fmr_restrict(const or_grid *pg, double *const *pq, const or_grid *cg,
                      double *const *cq);
 void or_fmr_reflux(const or_grid *pg, double *const *pq, const double *preg,

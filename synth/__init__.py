@@ -246,24 +246,32 @@ def star_problem(grid, seed, tov=None, rho_atm=1e-10, pert=1e-4, vel=0.0):
     return p, metric, eos
 
 
-def fmr_levels(nlev=6, n=256, finest_extent=20.0):
+def fmr_levels(nlev=6, n=256, finest_extent=20.0, nbuf=0):
     """Nested levels anchored at the origin, 2:1 refinement; level l covers
-    [0, finest_extent * 2^(nlev-1-l)]^2."""
-    return [star_grid(n, finest_extent * 2 ** (nlev - 1 - l)) for l in range(nlev)]
+    [0, finest_extent * 2^(nlev-1-l)]^2 with its own n x n cells; levels
+    with a parent hold nbuf buffer cells beyond them on the high sides."""
+    out = []
+    for l in range(nlev):
+        g = star_grid(n, finest_extent * 2 ** (nlev - 1 - l))
+        if l > 0 and nbuf:
+            g = make_grid(n + nbuf, n + nbuf, g["x0"], g["z0"], g["dx"], g["dz"], g["geom"], g["bc"])
+        out.append(g)
+    return out
 
 
-def fmr_grids(nlev, n, extent, geom="cart", outer="reflect"):
+def fmr_grids(nlev, n, extent, geom="cart", outer="reflect", nbuf=0):
     """Nested 2:1 levels anchored at the lower faces: level 0 covers
-    [0, extent]^2 with n x n cells, every finer level n x n cells over its
-    parent's lower-left quarter with EXTERNAL high sides; level 0's high
-    sides are `outer`; low sides: axis (cyl) or reflect (cart) in x,
-    reflect in z."""
+    [0, extent]^2 with n x n cells, every finer level n x n own cells over
+    its parent's lower-left quarter (plus nbuf buffer cells beyond them on
+    the high sides) with EXTERNAL high sides; level 0's high sides are
+    `outer`; low sides: axis (cyl) or reflect (cart) in x, reflect in z."""
     lo_x = "axis" if geom == "cyl" else "reflect"
     out = []
     for l in range(nlev):
         d = extent / n / 2 ** l
         hi = outer if l == 0 else "external"
-        out.append(make_grid(n, n, 0.0, 0.0, d, d, geom, (lo_x, hi, "reflect", hi)))
+        m = n if l == 0 else n + nbuf
+        out.append(make_grid(m, m, 0.0, 0.0, d, d, geom, (lo_x, hi, "reflect", hi)))
     return out
 
 

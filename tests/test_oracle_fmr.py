@@ -15,7 +15,16 @@ grid structure, Sec. II.E FMR setting).
   III.D); without the flux correction they are not kept, so the pin sees a
   dropped or sign-flipped correction;
 - with l_fix the levels up to l_fix take the parent's step, finer ones half
-  of it.
+  of it;
+- the (4+4) buffer schedule (Sec. II.E): its prolongation fills the inner
+  buffer with the same exactness (linear in space, quadratic in time); the
+  Berger-Oliger step keeps mass and angular momentum to round-off with it
+  too and loses them without the flux correction; the stage mapping (the
+  buffer and ghosts prolonged at t before stage 1, the ghosts at t + dt
+  before stage 2, nothing before stage 3, which updates the own cells
+  only) is what the driver does; a uniform state at rest stays uniform to
+  round-off across the refinement boundaries under both schedules (the
+  restriction's volume-weighted sum rounds).
 """
 import math
 
@@ -67,22 +76,22 @@ def test_restrict_conserves_and_keeps_constants(orc, geom):
     assert np.allclose(synth.interior(pg, qp)[:, :8, :8], 0.7, rtol=1e-15, atol=0)
 
 
-def child_ghosts(cg):
+def child_ghosts(cg, nbuf=0):
     """Index arrays of the child's cross-shaped EXTERNAL halo (x-high,
-    z-high sides)."""
+    z-high sides) and of its nbuf interior rows/columns next to them."""
     ng, nx, nz = cg["ng"], cg["nx"], cg["nz"]
     ks, js = [], []
-    for m in range(ng):
+    for m in range(-nbuf, ng):
         for k in range(nz):
             ks.append(ng + k); js.append(ng + nx + m)
-        for j in range(nx):
+        for j in range(nx - nbuf if m < 0 else nx):
             ks.append(ng + nz + m); js.append(ng + j)
     return np.array(ks), np.array(js)
 
 
-@pytest.mark.parametrize("geom", ["cyl", "cart"])
-def test_prolong_linear_exact_and_quadratic_in_time(orc, geom):
-    pg, cg = synth.fmr_grids(2, 16, 1.0, geom=geom, outer="outflow")
+@pytest.mark.parametrize("geom,nbuf", [("cyl", 0), ("cart", 0), ("cyl", 4), ("cart", 4)])
+def test_prolong_linear_exact_and_quadratic_in_time(orc, geom, nbuf):
+    pg, cg = synth.fmr_grids(2, 16, 1.0, geom=geom, outer="outflow", nbuf=nbuf)
     eos = synth.ideal_eos(GAM)
     Xp, Zp = synth.cell_coords(pg)
     Xc, Zc = synth.cell_coords(cg)
@@ -100,8 +109,12 @@ def test_prolong_linear_exact_and_quadratic_in_time(orc, geom):
     t = 1.37
     pc = synth.empty_fields(cg, 6)
     qc = synth.empty_fields(cg, 5)
-    orc.fmr_prolong(pg, slices, times, t, cg, eos, {}, pc, qc)
-    ks, js = child_ghosts(cg)
+    orc.fmr_prolong(pg, slices, times, t, cg, eos, {}, pc, qc, nbuf=nbuf)
+    ks, js = child_ghosts(cg, nbuf)
+    # nothing else is written
+    touched = np.zeros(pc.shape[1:], dtype=bool)
+    touched[ks, js] = True
+    assert not np.any(pc[:, ~touched])
     # the parent's own ghosts across its low sides are mirror images, not
     # the linear continuation: keep child ghosts whose parent stencil stays
     # inside the parent (parent cell j, k >= 1, i.e. child j, k >= 2)
@@ -150,39 +163,39 @@ def test_prolong_time_limiter_and_extremum(orc):
 
 
 def composite_totals(orc, drv):
-    """sum(q_D dV) and sum(q_Sphi dV) over the composite grid: each level
-    without the lower-left quarter its child covers."""
+    """sum(q_D dV) and sum(q_Sphi dV) over the composite grid: each level's
+    own cells without the lower-left quarter its child covers."""
     M = J = 0.0
     n = len(drv.lev)
     for l, L in enumerate(drv.lev):
-        g = L["grid"]
+        g = drv.own(l)
         q = synth.interior(g, L["q"])
         X, _ = synth.cell_coords(g)
         x = synth.interior(g, X)
         dV = (2.0 * math.pi * x if g["geom"] == "cyl" else np.ones_like(x)) * g["dx"] * g["dz"]
         mask = np.ones_like(x, dtype=bool)
         if l + 1 < n:
-            cg = drv.lev[l + 1]["grid"]
+            cg = drv.own(l + 1)
             mask[:cg["nz"] // 2, :cg["nx"] // 2] = False
         M += float((q[0] * dV)[mask].sum())
         J += float((q[2] * dV)[mask].sum())
     return M, J
 
 
-def make_driver(orc, geom, nlev, l_fix=0, n=16):
-    grids = synth.fmr_grids(nlev, n, 1.0, geom=geom, outer="reflect")
+def make_driver(orc, geom, nlev, l_fix=0, n=16, nbuf=0):
+    grids = synth.fmr_grids(nlev, n, 1.0, geom=geom, outer="reflect", nbuf=nbuf)
     eos = synth.ideal_eos(GAM)
     levels = []
     for l, g in enumerate(grids):
         p = synth.blast_state(g, (0.3, 0.2), 0.15, 7)
         q = orc.prim2con(g, eos, {}, p, with_ghosts=True)
-        levels.append(dict(grid=g, metric={}, q=q))
+        levels.append(dict(grid=g, metric={}, q=q, nbuf=nbuf if l > 0 else 0))
     return orc.FmrDriver(levels, eos, OPTS, l_fix=l_fix), grids
 
 
-@pytest.mark.parametrize("geom", ["cart", "cyl"])
-def test_bo_step_conserves_mass_and_angular_momentum(orc, geom):
-    drv, grids = make_driver(orc, geom, 3)
+@pytest.mark.parametrize("geom,nbuf", [("cart", 0), ("cyl", 0), ("cart", 4), ("cyl", 4)])
+def test_bo_step_conserves_mass_and_angular_momentum(orc, geom, nbuf):
+    drv, grids = make_driver(orc, geom, 3, nbuf=nbuf)
     M0, J0 = composite_totals(orc, drv)
     dt = 0.4 * grids[-1]["dx"] * 2 ** (len(grids) - 1)
     for _ in range(2):
@@ -195,8 +208,9 @@ def test_bo_step_conserves_mass_and_angular_momentum(orc, geom):
     assert np.abs(q2[1]).max() > 1e-3
 
 
-def test_bo_step_without_flux_correction_loses_mass(orc, monkeypatch):
-    drv, grids = make_driver(orc, "cart", 2)
+@pytest.mark.parametrize("nbuf", [0, 4])
+def test_bo_step_without_flux_correction_loses_mass(orc, monkeypatch, nbuf):
+    drv, grids = make_driver(orc, "cart", 2, nbuf=nbuf)
     M0, _ = composite_totals(orc, drv)
     monkeypatch.setattr(orc, "fmr_reflux", lambda *a, **k: None)
     dt = 0.4 * grids[-1]["dx"] * 2
@@ -222,3 +236,51 @@ def test_bo_schedule(orc, monkeypatch, l_fix, want):
         assert len(mine) == count, (l, mine)
         assert all(c[2] == pytest.approx(0.01 / count) for c in mine)
         assert [c[1] for c in mine] == pytest.approx([i * 0.01 / count for i in range(count)])
+
+
+def test_buffer_schedule_stage_mapping(orc, monkeypatch):
+    """One coarse step of two levels under the buffer schedule: the child's
+    two steps each prolong (buffer + ghosts at t, then ghosts at t + dt)
+    and run two stages on the grid with its buffer and the last on its own
+    cells; the parent's three stages run on its whole grid."""
+    drv, grids = make_driver(orc, "cart", 2, n=8, nbuf=4)
+    pro, sub = [], []
+    real_pro, real_sub = orc.fmr_prolong, orc.rk_substep
+
+    def spy_pro(pgrid, slices, times, t, cgrid, *a, nbuf=0):
+        pro.append((round(t, 12), nbuf))
+        return real_pro(pgrid, slices, times, t, cgrid, *a, nbuf=nbuf)
+
+    def spy_sub(grid, *a, **k):
+        sub.append((grid["nx"], grid["nz"]))
+        return real_sub(grid, *a, **k)
+    monkeypatch.setattr(orc, "fmr_prolong", spy_pro)
+    monkeypatch.setattr(orc, "rk_substep", spy_sub)
+    dt = 0.02
+    drv.step(dt)
+    h = dt / 2
+    assert pro == [(0.0, 4), (round(h, 12), 0), (round(h, 12), 4), (round(2 * h, 12), 0)]
+    assert sub == [(8, 8)] * 3 + [(12, 12), (12, 12), (8, 8)] * 2
+
+
+@pytest.mark.parametrize("nbuf", [0, 4])
+def test_uniform_state_stays_uniform(orc, nbuf):
+    grids = synth.fmr_grids(3, 16, 1.0, geom="cart", outer="reflect", nbuf=nbuf)
+    eos = synth.ideal_eos(GAM)
+    levels = []
+    for l, g in enumerate(grids):
+        p = synth.empty_fields(g, 6)
+        p[0], p[4] = 1.3, 0.7
+        p[5] = p[4] / ((GAM - 1.0) * p[0])
+        levels.append(dict(grid=g, metric={}, q=orc.prim2con(g, eos, {}, p, with_ghosts=True),
+                           nbuf=nbuf if l > 0 else 0))
+    drv = orc.FmrDriver(levels, eos, OPTS)
+    q0 = [synth.interior(drv.own(l), L["q"]).copy() for l, L in enumerate(drv.lev)]
+    for _ in range(2):
+        drv.step(0.4 * grids[0]["dx"])
+    for l, L in enumerate(drv.lev):
+        q = synth.interior(drv.own(l), L["q"])
+        for c in (0, 4):
+            assert np.abs(q[c] - q0[l][c]).max() <= 1e-14 * q0[l][c].max(), (l, c)
+        for c in (1, 2, 3):
+            assert np.abs(q[c]).max() <= 1e-14, (l, c)
