@@ -395,6 +395,9 @@ typedef struct {
   grhd_prim slice[3];        /* primitive time slices (levels with a child) */
   double *reg_child_bnd;     /* levels with a parent */
   double *reg_parent_int;    /* levels with a child */
+  int nbuf;                  /* levels with a parent: 0 = halo schedule;
+                                3..8 = buffer schedule with this inner
+                                buffer width (the paper's (4+4): 4) */
 } grhd_level;
 
 typedef struct grhd_fmr grhd_fmr;   /* opaque, library-owned */
@@ -431,9 +434,26 @@ int grhd_fmr_reflux(const grhd_grid *parent, const grhd_cons *q_parent,
 
 /* Berger-Oliger driver (Sec. II.E) over nlev levels (level 0 coarsest):
  * a level steps with SSP-RK3; levels l <= l_fix take the parent's step,
- * finer levels half of it; before each stage a child's ghost cells are
- * prolonged from its parent's slices at the stage time; after a child's
- * steps its parent is restricted, refluxed and recovered.  create: copies
+ * finer levels half of it; after a child's steps its parent is
+ * restricted, refluxed and recovered.  A child's boundary follows one of
+ * two schedules, per level:
+ *  - halo (nbuf = 0): before each stage the child's ghost cells are
+ *    prolonged from its parent's slices at the time of the stage's input
+ *    state (t, t + dt, t + dt/2);
+ *  - buffer (nbuf > 0; the paper's (4+4) structure with nbuf = 4): the
+ *    level's grid holds nbuf cells beyond its own nx - nbuf by nz - nbuf
+ *    cells on the high sides.  Before the first stage the buffer and the
+ *    ghost cells beyond it are prolonged at t; the first two stages evolve
+ *    own cells and buffer, the second after the ghost cells are prolonged
+ *    at t + dt; the last stage updates the own cells only and reads the
+ *    buffer as the second stage left it (the paper's RK4 mapping, every
+ *    stage but the last on the wider domain, taken to SSP-RK3).  The
+ *    3 ghost cells are the outer buffer the hydro stencils read.  The
+ *    level's low sides must not be EXTERNAL.
+ * Restriction, registers (reg_child_bnd: 5 x (own nx + own nz);
+ * reg_parent_int: from the child's own cells) and flux correction concern
+ * own cells; the parent's own cells must reach (child nx + 3)/2 + 2 cells
+ * (nx of the child's grid, buffer included).  create: copies
  * the level descriptors (device buffers stay the caller's), recovers every
  * level with a child into its first slice.  step: one step dt0 of level 0
  * (all finer levels follow).  Single path kernels on 16 x 15 tiles (16 x 7

@@ -491,7 +491,10 @@ class FmrDriver:
     def __init__(self, levels, eos, opts, l_fix=0, t0=0.0):
         self.lev = [dict(grid=d["grid"], metric=d["metric"], q=np.array(d["q"], dtype=np.float64),
                          nbuf=int(d.get("nbuf", 0))) for d in levels]
+        # the last stage reads the buffer as ghost cells: it must be at least
+        # as wide as the ghost layers
         assert self.lev[0]["nbuf"] == 0
+        assert all(L["nbuf"] == 0 or L["nbuf"] >= L["grid"]["ng"] for L in self.lev)
         self.eos, self.opts, self.l_fix, self.t = eos, opts, l_fix, t0
         n = len(self.lev)
         self.slices = [[] for _ in range(n)]

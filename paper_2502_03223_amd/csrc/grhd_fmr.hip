@@ -104,6 +104,50 @@ __device__ __forceinline__ bool ghost_cell(const GridK &cg, long long id, int &j
   return false;
 }
 
+// Number of the child's interior cells within nbuf of its EXTERNAL high
+// sides (the inner buffer of the buffer schedule).
+__host__ __device__ inline long long band_count(const GridK &cg, int nbuf) {
+  if (nbuf <= 0) return 0;
+  const bool xh = cg.bc[1] == GRHD_BC_EXTERNAL, zh = cg.bc[3] == GRHD_BC_EXTERNAL;
+  return (xh ? (long long)nbuf * cg.nz : 0) + (zh ? (long long)nbuf * (xh ? cg.nx - nbuf : cg.nx) : 0);
+}
+
+// buffer cell number id: the nbuf columns next to the x-high side (every
+// row), then the nbuf rows next to the z-high side (left of those columns)
+__device__ __forceinline__ bool band_cell(const GridK &cg, int nbuf, long long id, int &jf, int &kf) {
+  const bool xh = cg.bc[1] == GRHD_BC_EXTERNAL, zh = cg.bc[3] == GRHD_BC_EXTERNAL;
+  if (xh) {
+    const long long n = (long long)nbuf * cg.nz;
+    if (id < n) {
+      jf = cg.nx - nbuf + (int)(id % nbuf);
+      kf = (int)(id / nbuf);
+      return true;
+    }
+    id -= n;
+  }
+  if (zh) {
+    const int w = xh ? cg.nx - nbuf : cg.nx;
+    if (id < (long long)nbuf * w) {
+      jf = (int)(id % w);
+      kf = cg.nz - nbuf + (int)(id / w);
+      return true;
+    }
+  }
+  return false;
+}
+
+// cell number id of the prolonged frame: the EXTERNAL halo (if halo), then
+// the buffer band (nbuf > 0)
+__device__ __forceinline__ bool frame_cell(const GridK &cg, int halo, int nbuf, long long id, int &jf,
+                                           int &kf) {
+  if (halo) {
+    const long long n = prolong_count(cg);
+    if (id < n) return ghost_cell(cg, id, jf, kf);
+    id -= n;
+  }
+  return nbuf > 0 && band_cell(cg, nbuf, id, jf, kf);
+}
+
 // One workgroup: 32 ghost cells x 6 fields, one (field, cell) per thread;
 // the prolonged primitives meet in LDS for the conserved variables.
 constexpr int PRO_CELLS = 32;
@@ -148,26 +192,27 @@ k_fmr_prolong(GridK pg, SliceK S, GridK cg, MetK cm, EosK e, P6 cp, Q5 cq) {
   }
 }
 
-// A level stage's recovery with the prolongation of the level's EXTERNAL
-// ghost cells in one launch.  Workgroups [0, nrec) recover the interior
-// rows (256 cells each, row k = b / segs); the others take 32 ghost cells
-// each (8 x 32 threads, fields 0-5 on the first six groups), prolong them
-// as k_fmr_prolong does, form the conserved values and recover them in
+// A level stage's recovery with the prolongation of the level's frame in
+// one launch.  Workgroups [0, nrec) recover the interior cells j < rnx,
+// k < rnz (rows of 256 cells, row k = b / segs); the others take 32 frame
+// cells each (the EXTERNAL halo if halo, then the nbuf-wide buffer band;
+// 8 x 32 threads, fields 0-5 on the first six groups), prolong them as
+// k_fmr_prolong does, form the conserved values and recover them in
 // registers as the recovery launch would from memory: the same results as
-// the two launches, without the second one.
+// the two launches, without the second one.  The two sets are disjoint.
 constexpr int PREP_THREADS = 256;
 
 template <int MC, int EK>
 __global__ void __launch_bounds__(PREP_THREADS)
 k_fmr_prep(GridK pg, SliceK S, GridK cg, MetK cm, EosK e, C2PK cp, P6 pp, Q5 qq, uint8_t *flags, int segs,
-           int nrec) {
+           int nrec, int rnx, int halo, int nbuf) {
 #pragma clang fp contract(off)
   __shared__ double spf[6][PRO_CELLS];
   const int b = blockIdx.x;
   if (b < nrec) {
     const int k = b / segs;
     const int j = (b % segs) * PREP_THREADS + threadIdx.x;
-    if (j >= cg.nx) return;
+    if (j >= rnx) return;
     const long long i = cell_index(cg, j, k);
     const double W = mval(cm, GRHD_M_W, i);
     double gtu[6];
@@ -187,7 +232,7 @@ k_fmr_prep(GridK pg, SliceK S, GridK cg, MetK cm, EosK e, C2PK cp, P6 pp, Q5 qq,
   }
   const int f = threadIdx.x / PRO_CELLS, cl = threadIdx.x % PRO_CELLS;
   int jf = 0, kf = 0;
-  const bool act = ghost_cell(cg, (long long)(b - nrec) * PRO_CELLS + cl, jf, kf);
+  const bool act = frame_cell(cg, halo, nbuf, (long long)(b - nrec) * PRO_CELLS + cl, jf, kf);
   if (act && f < 6) {
     const int jc = (jf >= 0) ? jf / 2 : -((1 - jf) / 2);
     const int kc = (kf >= 0) ? kf / 2 : -((1 - kf) / 2);
@@ -351,14 +396,17 @@ static int prolong(const grhd_grid *pg, const SliceK &S, const grhd_grid *cg,
   return launch_status("fmr prolong");
 }
 
-// recovery of a child level's q_s with its ghost cells prolonged from the
-// parent slices S (k_fmr_prep)
+// recovery of a child level's q_s (cells j < rnx, k < rnz) with its frame
+// prolonged from the parent slices S (the EXTERNAL halo if halo, the
+// nbuf-wide buffer band if nbuf > 0) in one launch (k_fmr_prep)
 static int prep(const grhd_grid *pg, const SliceK &S, const grhd_level &L, const EosK &e, const C2PK &cp,
-                const Q5 &q, const P6 &p, uint8_t *flags, int mc, hipStream_t st) {
+                const Q5 &q, const P6 &p, uint8_t *flags, int mc, int rnx, int rnz, int halo, int nbuf,
+                hipStream_t st) {
   const GridK P = to_gridk(pg), Cg = to_gridk(&L.grid);
-  const int segs = (Cg.nx + PREP_THREADS - 1) / PREP_THREADS;
-  const long long nrec = (long long)segs * Cg.nz;
-  const long long npro = (prolong_count(Cg) + PRO_CELLS - 1) / PRO_CELLS;
+  const int segs = (rnx + PREP_THREADS - 1) / PREP_THREADS;
+  const long long nrec = (long long)segs * rnz;
+  const long long nframe = (halo ? prolong_count(Cg) : 0) + band_count(Cg, nbuf);
+  const long long npro = (nframe + PRO_CELLS - 1) / PRO_CELLS;
   if (nrec + npro >= (1LL << 31)) return fail(GRHD_ERR_UNSUPPORTED, "level too large");
   const dim3 grid((unsigned)(nrec + npro)), block(PREP_THREADS);
   const MetK m = to_metk(&L.metric);
@@ -366,17 +414,17 @@ static int prep(const grhd_grid *pg, const SliceK &S, const grhd_level &L, const
   if (mc == MC_GEN) {
     if (ideal)
       hipLaunchKernelGGL((k_fmr_prep<MC_GEN, GRHD_EOS_IDEAL>), grid, block, 0, st, P, S, Cg, m, e, cp, p, q, flags,
-                         segs, (int)nrec);
+                         segs, (int)nrec, rnx, halo, nbuf);
     else
       hipLaunchKernelGGL((k_fmr_prep<MC_GEN, GRHD_EOS_HYBRID>), grid, block, 0, st, P, S, Cg, m, e, cp, p, q,
-                         flags, segs, (int)nrec);
+                         flags, segs, (int)nrec, rnx, halo, nbuf);
   } else {
     if (ideal)
       hipLaunchKernelGGL((k_fmr_prep<MC_CF, GRHD_EOS_IDEAL>), grid, block, 0, st, P, S, Cg, m, e, cp, p, q, flags,
-                         segs, (int)nrec);
+                         segs, (int)nrec, rnx, halo, nbuf);
     else
       hipLaunchKernelGGL((k_fmr_prep<MC_CF, GRHD_EOS_HYBRID>), grid, block, 0, st, P, S, Cg, m, e, cp, p, q,
-                         flags, segs, (int)nrec);
+                         flags, segs, (int)nrec, rnx, halo, nbuf);
   }
   return launch_status("fmr stage recovery and prolongation");
 }
@@ -498,13 +546,23 @@ int push_slice(grhd_fmr *h, int l, double t, hipStream_t st) {
   return recover(h, l, &h->lev[l].slice[buf], st);
 }
 
+// level l without its buffer (same arrays and pitch)
+grhd_grid own_grid(const grhd_level &L) {
+  grhd_grid g = L.grid;
+  g.nx -= L.nbuf;
+  g.nz -= L.nbuf;
+  return g;
+}
+
 int step_level(grhd_fmr *h, int l, double t, double dt, hipStream_t st) {
   int rc;
   const int nlev = (int)h->lev.size();
   grhd_level &L = h->lev[l];
   const bool has_child = l + 1 < nlev, has_parent = l > 0;
-  const grhd_grid *cg = has_child ? &h->lev[l + 1].grid : nullptr;
-  if (has_child && (rc = zero(L.reg_parent_int, 5LL * (cg->nx / 2 + cg->nz / 2), st))) return rc;
+  const int nb = L.nbuf;
+  const grhd_grid own = own_grid(L);
+  const grhd_grid cown = has_child ? own_grid(h->lev[l + 1]) : own;
+  if (has_child && (rc = zero(L.reg_parent_int, 5LL * (cown.nx / 2 + cown.nz / 2), st))) return rc;
   // SSP-RK3: (q^n, q_s, q_out) = (q, q, q1), (q, q1, q2), (q, q2, q)
   static const double kA[3] = {0.0, 0.75, 1.0 / 3.0}, kB[3] = {1.0, 0.25, 2.0 / 3.0},
                       kC[3] = {1.0, 0.25, 2.0 / 3.0}, kT[3] = {0.0, 1.0, 0.5},
@@ -513,7 +571,10 @@ int step_level(grhd_fmr *h, int l, double t, double dt, hipStream_t st) {
   EosK e = to_eosk(&h->eos, h->opts.c2p.rho_atm);
   const int mc = metric_class(&L.metric);
   for (int s = 0; s < 3; s++) {
-    // the parent's slices at the stage time (ghost cells of this level)
+    // buffer schedule: the last stage updates the own cells only
+    const bool last_on_own = nb > 0 && s == 2;
+    const grhd_grid &gs = last_on_own ? own : L.grid;
+    // the parent's slices at the stage time (frame of this level)
     SliceK S{};
     if (has_parent) {
       const grhd_level &Pl = h->lev[l - 1];
@@ -525,32 +586,43 @@ int step_level(grhd_fmr *h, int l, double t, double dt, hipStream_t st) {
     grhd_rk_stage stg{};
     stg.a = kA[s]; stg.b = kB[s]; stg.c = kC[s]; stg.dt = dt;
     PatchK pk;
-    if ((rc = fill_patch(&L.grid, &L.metric, &stg, &L.q, qs_of[s], qo_of[s], &L.p, nullptr, nullptr, nullptr,
+    if ((rc = fill_patch(&gs, &L.metric, &stg, &L.q, qs_of[s], qo_of[s], &L.p, nullptr, nullptr, nullptr,
                          h->opts.recon, h->opts.riemann, pk)))
       return rc;
     pk.face_eos = h->opts.face_eps == GRHD_FACE_EPS_EOS ? 1 : 0;
     pk.flags = h->flags[l];
-    if (has_parent) { pk.reg[0] = L.reg_child_bnd; pk.reg_j[0] = L.grid.nx; pk.reg_k[0] = L.grid.nz; }
-    if (has_child) { pk.reg[1] = L.reg_parent_int; pk.reg_j[1] = cg->nx / 2; pk.reg_k[1] = cg->nz / 2; }
+    if (has_parent) { pk.reg[0] = L.reg_child_bnd; pk.reg_j[0] = own.nx; pk.reg_k[0] = own.nz; }
+    if (has_child) { pk.reg[1] = L.reg_parent_int; pk.reg_j[1] = cown.nx / 2; pk.reg_k[1] = cown.nz / 2; }
     pk.reg_w = kW[s];
     // grids of few 16 x 16 tiles (under two per workgroup slot of the
     // chip) take 16 x 7 tiles: twice the workgroups, half the latency of
     // the slowest (star) tile; larger ones 16 x 15
-    const int shape = ((long long)((L.grid.nx + 15) / 16) * ((L.grid.nz + 15) / 16) < 1536)
+    const int shape = ((long long)((gs.nx + 15) / 16) * ((gs.nz + 15) / 16) < 1536)
                           ? shape_index(16, 7) : h->shape;
     int tx, tz;
     shape_of(shape, &tx, &tz);
-    pk.xshift = tile_xshift(L.grid.ng, tx);
-    pk.tiles_x = (L.grid.nx + pk.xshift + tx - 1) / tx;
-    pk.tiles_z = (L.grid.nz + tz - 1) / tz;
+    pk.xshift = tile_xshift(gs.ng, tx);
+    pk.tiles_x = (gs.nx + pk.xshift + tx - 1) / tx;
+    pk.tiles_z = (gs.nz + tz - 1) / tz;
     Q5 q;
     P6 p;
     for (int c = 0; c < 5; c++) q.q[c] = qs_of[s]->q[c];
     for (int f = 0; f < 6; f++) p.p[f] = L.p.p[f];
-    // recovery of q_s; a child level's ghost cells are prolonged in the
-    // same launch
-    rc = has_parent ? prep(&h->lev[l - 1].grid, S, L, e, to_c2pk(&h->opts.c2p), q, p, h->flags[l], mc, st)
-                    : launch_con2prim(pk.g, e, to_c2pk(&h->opts.c2p), pk.m, mc, q, p, h->flags[l], nullptr, st);
+    // recovery of q_s; a child level's frame is prolonged in the same
+    // launch: halo schedule, the ghost cells before every stage; buffer
+    // schedule, buffer and ghost cells before the first stage (the own
+    // cells recovered), the ghost cells before the second, nothing before
+    // the last (the whole grid recovered: the own cells' stage reads the
+    // buffer as its ghost cells)
+    const int nx = L.grid.nx, nz = L.grid.nz;
+    if (!has_parent)
+      rc = launch_con2prim(pk.g, e, to_c2pk(&h->opts.c2p), pk.m, mc, q, p, h->flags[l], nullptr, st);
+    else if (nb > 0 && s == 0)
+      rc = prep(&h->lev[l - 1].grid, S, L, e, to_c2pk(&h->opts.c2p), q, p, h->flags[l], mc, own.nx, own.nz,
+                1, nb, st);
+    else
+      rc = prep(&h->lev[l - 1].grid, S, L, e, to_c2pk(&h->opts.c2p), q, p, h->flags[l], mc, nx, nz,
+                last_on_own ? 0 : 1, 0, st);
     if (rc) return rc;
     if ((rc = launch_substep(pk, e, h->opts.prec, mc, shape, nullptr, st))) return rc;
   }
@@ -560,9 +632,9 @@ int step_level(grhd_fmr *h, int l, double t, double dt, hipStream_t st) {
   for (int i = 0; i < nsub; i++)
     if ((rc = step_level(h, l + 1, t + i * (dt / nsub), dt / nsub, st))) return rc;
   grhd_level &C = h->lev[l + 1];
-  if ((rc = restrict_(&L.grid, &L.q, &C.grid, &C.q, st))) return rc;
-  if ((rc = reflux(&L.grid, &L.q, L.reg_parent_int, &C.grid, C.reg_child_bnd, st))) return rc;
-  if ((rc = zero(C.reg_child_bnd, 5LL * (C.grid.nx + C.grid.nz), st))) return rc;
+  if ((rc = restrict_(&L.grid, &L.q, &cown, &C.q, st))) return rc;
+  if ((rc = reflux(&L.grid, &L.q, L.reg_parent_int, &cown, C.reg_child_bnd, st))) return rc;
+  if ((rc = zero(C.reg_child_bnd, 5LL * (cown.nx + cown.nz), st))) return rc;
   // the newest slice is the corrected state at t + dt
   return recover(h, l, &L.slice[h->order[l][h->ns[l] - 1]], st);
 }
@@ -586,8 +658,19 @@ extern "C" int grhd_fmr_create(const grhd_level *levels, int nlev, const grhd_eo
     if ((rc = check_grid(&L.grid)) || (rc = check_metric(&L.metric)) || (rc = check_cons(&L.q, "q")) ||
         (rc = check_cons(&L.q1, "q1")) || (rc = check_cons(&L.q2, "q2")) || (rc = check_prim(&L.p, "p")))
       return rc;
+    if (l == 0 && L.nbuf != 0) return fail(GRHD_ERR_INVALID, "level 0 has no buffer (nbuf must be 0)");
     if (l > 0) {
-      if ((rc = check_pair(&levels[l - 1].grid, &L.grid))) return rc;
+      if (L.nbuf != 0 && (L.nbuf < L.grid.ng || L.nbuf > 8))
+        return fail(GRHD_ERR_INVALID, "level %d: nbuf must be 0 or in [ng, 8]", l);
+      if (L.nbuf != 0 && (L.grid.bc[0] == GRHD_BC_EXTERNAL || L.grid.bc[2] == GRHD_BC_EXTERNAL))
+        return fail(GRHD_ERR_INVALID, "level %d: the buffer schedule needs non-EXTERNAL low sides", l);
+      const grhd_grid po = own_grid(levels[l - 1]), co = own_grid(L);
+      if (co.nx < 2 || co.nz < 2) return fail(GRHD_ERR_INVALID, "level %d: no own cells", l);
+      // the own cells pair with the parent as a halo-schedule child; the
+      // parent's own cells also cover the buffer's and ghosts' stencils
+      if ((rc = check_pair(&po, &co))) return rc;
+      if (po.nx < (L.grid.nx + L.grid.ng) / 2 + 2 || po.nz < (L.grid.nz + L.grid.ng) / 2 + 2)
+        return fail(GRHD_ERR_INVALID, "level %d: the parent's own cells must cover the child's buffer", l);
       if (!L.reg_child_bnd) return fail(GRHD_ERR_INVALID, "level %d needs reg_child_bnd", l);
     }
     if (l + 1 < nlev) {
@@ -617,7 +700,8 @@ extern "C" int grhd_fmr_create(const grhd_level *levels, int nlev, const grhd_eo
   hipStream_t st = (hipStream_t)hip_stream;
   for (int l = 0; l < nlev; l++) {
     if (l + 1 < nlev && (rc = push_slice(h, l, t0, st))) { delete h; return rc; }
-    if (l > 0 && (rc = zero(levels[l].reg_child_bnd, 5LL * (levels[l].grid.nx + levels[l].grid.nz), st))) {
+    if (l > 0 && (rc = zero(levels[l].reg_child_bnd,
+                            5LL * (levels[l].grid.nx + levels[l].grid.nz - 2 * levels[l].nbuf), st))) {
       delete h;
       return rc;
     }

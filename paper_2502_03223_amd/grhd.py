@@ -93,7 +93,7 @@ class Diag(C.Structure):
 class Level(C.Structure):
     _fields_ = [("grid", Grid), ("metric", Metric), ("q", Cons), ("q1", Cons), ("q2", Cons),
                 ("p", Prim), ("slice", Prim * 3), ("reg_child_bnd", C.c_void_p),
-                ("reg_parent_int", C.c_void_p)]
+                ("reg_parent_int", C.c_void_p), ("nbuf", C.c_int)]
 
 
 class Patch(C.Structure):
@@ -596,9 +596,10 @@ def fmr_reflux(pgrid, q_parent, reg_parent, cgrid, reg_child):
 
 
 class Hierarchy:
-    """A grhd_fmr driver over levels given as dicts (grid, metric, q); the
-    stage buffers, recovery workspace, slices and registers are allocated
-    here as device tensors and handed to the library."""
+    """A grhd_fmr driver over levels given as dicts (grid, metric, q, and
+    nbuf: 0 for the halo schedule, the buffer width for the buffer
+    schedule); the stage buffers, recovery workspace, slices and registers
+    are allocated here as device tensors and handed to the library."""
 
     def __init__(self, levels, eos, opts, l_fix=0, t0=0.0):
         lib()
@@ -614,12 +615,13 @@ class Hierarchy:
             b["slices"] = [torch.zeros((6,) + shp, dtype=torch.float64, device=q.device)
                            for _ in range(3 if l + 1 < n else 0)]
             g = d["grid"]
-            b["reg_child_bnd"] = (torch.zeros(5 * (g["nx"] + g["nz"]), dtype=torch.float64, device=q.device)
-                                  if l > 0 else None)
+            nb = int(d.get("nbuf", 0))
+            b["reg_child_bnd"] = (torch.zeros(5 * (g["nx"] + g["nz"] - 2 * nb), dtype=torch.float64,
+                                              device=q.device) if l > 0 else None)
             if l + 1 < n:
-                cg = levels[l + 1]["grid"]
-                b["reg_parent_int"] = torch.zeros(5 * (cg["nx"] // 2 + cg["nz"] // 2), dtype=torch.float64,
-                                                  device=q.device)
+                cg, cb = levels[l + 1]["grid"], int(levels[l + 1].get("nbuf", 0))
+                b["reg_parent_int"] = torch.zeros(5 * ((cg["nx"] - cb) // 2 + (cg["nz"] - cb) // 2),
+                                                  dtype=torch.float64, device=q.device)
             else:
                 b["reg_parent_int"] = None
             L = arr[l]
@@ -633,6 +635,7 @@ class Hierarchy:
                 L.slice[s_] = make_prim(t_)
             L.reg_child_bnd = b["reg_child_bnd"].data_ptr() if b["reg_child_bnd"] is not None else None
             L.reg_parent_int = b["reg_parent_int"].data_ptr() if b["reg_parent_int"] is not None else None
+            L.nbuf = nb
             self.bufs.append(b)
         self._arr = arr
         self._opts = make_options(opts)

@@ -8,7 +8,8 @@
   1e-12 of the oracle's driver (per field, normwise), with and without
   l_fix, on a blast crossing two refinement boundaries and on a star whose
   surface the finest boundary cuts; composite mass conserved to round-off
-  in a closed box.
+  in a closed box.  Both boundary schedules: the halo (ghost cells
+  prolonged before every stage) and the paper's (4+4) buffer (nbuf = 4).
 """
 import math
 
@@ -114,8 +115,13 @@ def test_restrict_and_reflux_parity(orc, geom):
     assert np.array_equal(qp_g.cpu().numpy(), qp_o)
 
 
-def composite_mass(levels_q, grids):
+def own(g, nbuf):
+    return dict(g, nx=g["nx"] - nbuf, nz=g["nz"] - nbuf)
+
+
+def composite_mass(levels_q, grids, nbuf=0):
     M = 0.0
+    grids = [own(g, nbuf if l > 0 else 0) for l, g in enumerate(grids)]
     for l, (g, q) in enumerate(zip(grids, levels_q)):
         qi = synth.interior(g, q)
         X, _ = synth.cell_coords(g)
@@ -128,13 +134,14 @@ def composite_mass(levels_q, grids):
     return M
 
 
-def run_pair(orc, grids, eos, metrics, prims, l_fix, dt, nstep):
+def run_pair(orc, grids, eos, metrics, prims, l_fix, dt, nstep, nbuf=0):
     qs = [orc.prim2con(g, eos, m, p, with_ghosts=True) for g, m, p in zip(grids, metrics, prims)]
-    drv = orc.FmrDriver([dict(grid=g, metric=m, q=q) for g, m, q in zip(grids, metrics, qs)], eos, OPTS,
-                        l_fix=l_fix)
-    lev_g = [dict(grid=g, metric=mdev(m), q=dev(q)) for g, m, q in zip(grids, metrics, qs)]
+    nb = [nbuf if l > 0 else 0 for l in range(len(grids))]
+    drv = orc.FmrDriver([dict(grid=g, metric=m, q=q, nbuf=b) for g, m, q, b in zip(grids, metrics, qs, nb)],
+                        eos, OPTS, l_fix=l_fix)
+    lev_g = [dict(grid=g, metric=mdev(m), q=dev(q), nbuf=b) for g, m, q, b in zip(grids, metrics, qs, nb)]
     h = grhd.Hierarchy(lev_g, eos, OPTS, l_fix=l_fix)
-    M0 = composite_mass([L["q"] for L in drv.lev], grids)
+    M0 = composite_mass([L["q"] for L in drv.lev], grids, nbuf)
     for _ in range(nstep):
         drv.step(dt)
         h.step(dt)
@@ -154,29 +161,31 @@ def reach(level, l_fix, coarse_steps):
     return 9 * steps
 
 
+@pytest.mark.parametrize("nbuf", [0, 4])
 @pytest.mark.parametrize("l_fix", [0, 1])
 @pytest.mark.parametrize("geom", ["cart", "cyl"])
-def test_hierarchy_blast_parity_and_conservation(orc, geom, l_fix):
-    grids = synth.fmr_grids(3, 32, 1.0, geom=geom, outer="reflect")
+def test_hierarchy_blast_parity_and_conservation(orc, geom, l_fix, nbuf):
+    grids = synth.fmr_grids(3, 32, 1.0, geom=geom, outer="reflect", nbuf=nbuf)
     eos = synth.ideal_eos(GAM)
     prims = [synth.blast_state(g, (0.3, 0.2), 0.15, 7) for g in grids]
     # the finest level keeps a Courant factor of 0.4
     dt = 0.4 * grids[0]["dx"] / 2 ** min(l_fix, 2)
-    out_g, out_o, M0 = run_pair(orc, grids, eos, [{}] * 3, prims, l_fix, dt, 2)
+    out_g, out_o, M0 = run_pair(orc, grids, eos, [{}] * 3, prims, l_fix, dt, 2, nbuf)
     for l, g in enumerate(grids):
         e = normwise(synth.interior(g, out_g[l]), synth.interior(g, out_o[l]))
         assert e <= 1e-12, (l, e)
         e = percell_local(synth.interior(g, out_g[l]), synth.interior(g, out_o[l]), (0, 4),
                           radius=reach(l, l_fix, 2))
         assert e <= 1e-12, (l, e)
-    M_g = composite_mass(out_g, grids)
+    M_g = composite_mass(out_g, grids, nbuf)
     assert abs(M_g - M0) <= 1e-13 * abs(M0), (M0, M_g)
 
 
-def test_hierarchy_star_parity(orc):
+@pytest.mark.parametrize("nbuf", [0, 4])
+def test_hierarchy_star_parity(orc, nbuf):
     """The TOV star on three levels whose finest boundary cuts the star."""
     tov = synth.tov_solve()
-    grids = synth.fmr_grids(3, 32, 40.0, geom="cyl", outer="outflow")
+    grids = synth.fmr_grids(3, 32, 40.0, geom="cyl", outer="outflow", nbuf=nbuf)
     prims, metrics = [], []
     eos = None
     for l, g in enumerate(grids):
@@ -185,8 +194,10 @@ def test_hierarchy_star_parity(orc):
         metrics.append(m)
     opts_star = dict(OPTS, c2p=dict(w_max=100.0, rho_atm=1e-10))
     qs = [orc.prim2con(g, eos, m, p, with_ghosts=True) for g, m, p in zip(grids, metrics, prims)]
-    drv = orc.FmrDriver([dict(grid=g, metric=m, q=q) for g, m, q in zip(grids, metrics, qs)], eos, opts_star)
-    lev_g = [dict(grid=g, metric=mdev(m), q=dev(q)) for g, m, q in zip(grids, metrics, qs)]
+    nb = [nbuf if l > 0 else 0 for l in range(3)]
+    drv = orc.FmrDriver([dict(grid=g, metric=m, q=q, nbuf=b) for g, m, q, b in zip(grids, metrics, qs, nb)],
+                        eos, opts_star)
+    lev_g = [dict(grid=g, metric=mdev(m), q=dev(q), nbuf=b) for g, m, q, b in zip(grids, metrics, qs, nb)]
     h = grhd.Hierarchy(lev_g, eos, opts_star)
     dt = 0.4 * grids[0]["dx"]
     for _ in range(2):
