@@ -22,7 +22,8 @@ The JSON line also carries:
                  combine into: mixed precision, the batched plan (one
                  graph-captured launch sequence per substep) and the learned
                  recovery guess (the matrix-core MLP trained here on GPU on
-                 star-like states), with and without the guess, against the
+                 star-like states), with and without the guess, and the
+                 chained mixed stage with and without the guess, against the
                  plain FP64 headline: zone-updates/s, speedup, and the L1
                  difference from the FP64 path after N substeps;
   forms.batched  six nested 256^2 star levels plus 64 Riemann patches
@@ -35,9 +36,10 @@ The JSON line also carries:
   forms.bondi    Bondi accretion in the maximal trumpet slice (shift, lapse
                  and extrinsic curvature all active) on [0, 16M]^2 to t = 20M
                  at N = 64, 128, 256: PPM (CW84) and minmod with HLLC, the
-                 per-cell third-order parabola (PPM3) with HLLC and TVDLF;
-                 zone-updates/s and the L1 density error of each, with the
-                 convergence orders;
+                 per-cell third-order parabola (PPM3) with HLLC and TVDLF,
+                 PPM and PPM3 with the face eps from the EOS; zone-updates/s
+                 and the L1 density error of each, with the convergence
+                 orders;
   forms.bondi_rt the hot bubble in the Bondi flow (N = 512, t = 25M), HLLC
                  against TVDLF: total variation of the density (sharper
                  fingers give more) and zone-updates/s;
@@ -189,8 +191,9 @@ def main():
         recovery at the end of each stage) or separate (recovery pass, then
         the stage kernel)."""
 
-        def __init__(self, prec, chained=True):
-            opts = dict(recon="ppm", riemann="hllc", prec=prec, c2p=c2p)
+        def __init__(self, prec, chained=True, mlp=None):
+            cp = dict(c2p, mlp=mlp)
+            opts = dict(recon="ppm", riemann="hllc", prec=prec, c2p=cp)
             if args.tile and not chained:
                 opts["tile"] = tuple(int(v) for v in args.tile.split("x"))
             self.chained = chained
@@ -206,7 +209,7 @@ def main():
             self.diag = grhd.new_diag()
             self.stages = [grhd.make_stage(dict(s, dt=dt)) for s in grhd.SSPRK3]
             if chained:
-                grhd.con2prim(grid, eos, metric, c2p, self.q, self.p, flags=self.fa)
+                grhd.con2prim(grid, eos, metric, cp, self.q, self.p, flags=self.fa)
 
         def step(self, events=None, kevents=None):
             # q -> q1 -> q2 -> q (SSP-RK3, q^n = q)
@@ -454,9 +457,10 @@ def train_guess(samples, eos, seed, train_steps, dev):
 
 
 def combined_form(args, grid, eos, metric, metric_np, make_state, value_fp64, Stepper):
-    """The headline star through a one-patch batched plan (the whole
-    substep -- recovery, stage kernel, fold -- one graph launch), mixed
-    precision, with and without the learned recovery guess."""
+    """The headline star in mixed precision with and without the learned
+    recovery guess: through a one-patch batched plan (the whole substep --
+    recovery, stage kernel, fold -- one graph launch) and through the
+    chained stage (one kernel per substep)."""
     import torch
 
     import synth
@@ -525,6 +529,32 @@ def combined_form(args, grid, eos, metric, metric_np, make_state, value_fp64, St
             res[name]["accuracy_vs_fp64"]["substeps"] = 3 * nsteps
         plan.close()
     res["guess_speedup"] = res["mixed_batched_learned"]["value"] / res["mixed_batched"]["value"]
+    # the same with the chained mixed stage (one kernel per substep, the
+    # recovery of q_out at its end, seeded by the network or not)
+    for name, mlp in (("mixed_chained", None), ("mixed_chained_learned", net.buf)):
+        st = Stepper("mixed", True, mlp)
+        for _ in range(args.warmup):
+            st.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            st.step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        d = grhd.read_diag(st.diag)
+        v = 3 * nzone * args.steps / wall
+        res[name] = {"value": v, "ms_per_step": wall * 1e3 / args.steps, "speedup_vs_fp64": v / value_fp64,
+                     "evals_last_stage": d["iter_sum"], "evals_max_last_stage": d["iter_max"]}
+        if mlp is not None:
+            st = Stepper("mixed", True, mlp)
+            ref = Stepper("fp64")
+            nsteps = args.accuracy_substeps // 3
+            for _ in range(nsteps):
+                st.step()
+                ref.step()
+            res[name]["accuracy_vs_fp64"] = l1_diffs(grid, metric_np, st.prims(), ref.prims())
+            res[name]["accuracy_vs_fp64"]["substeps"] = 3 * nsteps
+    res["guess_speedup_chained"] = res["mixed_chained_learned"]["value"] / res["mixed_chained"]["value"]
     return res
 
 
@@ -728,10 +758,14 @@ def bondi_form(args):
     c2p = dict(w_max=100.0, rho_atm=1e-14)
     res = {"workload": "Bondi accretion, maximal trumpet slice of Schwarzschild, Gamma 4/3, K = 1, "
                        "r_c = 8M, [0, 16M]^2 cylindrical, fixed for r < 0.4M, SSP-RK3 to t = 20M; "
-                       "keys recon[_riemann]_N"}
+                       "keys recon[_riemann][_eos]_N (_eos: face eps from the EOS)"}
     errs = {}
-    cases = [("ppm", "hllc"), ("ppm3", "hllc"), ("ppm3", "tvdlf"), ("minmod", "hllc")]
-    for (recon, riemann), n in [(c, n) for c in cases for n in (64, 128, 256)]:
+    cases = [("ppm", "hllc", "recon"), ("ppm3", "hllc", "recon"), ("ppm3", "tvdlf", "recon"),
+             ("minmod", "hllc", "recon"), ("ppm", "hllc", "eos"), ("ppm3", "hllc", "eos")]
+
+    def key_of(recon, riemann, face):
+        return recon + ("" if riemann == "hllc" else "_" + riemann) + ("" if face == "recon" else "_eos")
+    for (recon, riemann, face), n in [(c, n) for c in cases for n in (64, 128, 256)]:
         d = 16.0 / n
         g = synth.make_grid(n, n, 0.0, 0.0, d, d, "cyl", ("axis", "external", "reflect", "external"))
         p, m, eos, frozen = synth.bondi_problem(g)
@@ -743,7 +777,7 @@ def bondi_form(args):
         mask = torch.from_numpy(frozen.astype(np.uint8)).to(dev)
         # the inner region is held inside each stage (no separate pass)
         sub = grhd.Substep(g, eos, md, dict(recon=recon, riemann=riemann, prec="fp64", c2p=c2p,
-                                            fix=(mask, qfix)))
+                                            face_eps=face, fix=(mask, qfix)))
         pw = torch.zeros_like(pd)
         dt = 0.4 * d
         nsteps = int(round(20.0 / dt))
@@ -762,13 +796,13 @@ def bondi_form(args):
         X, _ = synth.cell_coords(g)
         x = synth.interior(g, X)
         sg = synth.interior(g, m["alp"] * m["W"] ** -3) * x
-        key = recon if riemann == "hllc" else recon + "_" + riemann
+        key = key_of(recon, riemann, face)
         errs[(key, n)] = float((np.abs(rho - rho0) * sg).sum() / (np.abs(rho0) * sg).sum())
         res["%s_N%d" % (key, n)] = {"value": 3 * n * n * nsteps / wall, "unit": "zone-updates/s",
                                     "steps": nsteps, "ms_per_step": wall * 1e3 / nsteps,
                                     "l1_rho": errs[(key, n)]}
-    for recon, riemann in cases:
-        key = recon if riemann == "hllc" else recon + "_" + riemann
+    for recon, riemann, face in cases:
+        key = key_of(recon, riemann, face)
         res["%s_order_64_128" % key] = math.log2(errs[(key, 64)] / errs[(key, 128)])
         res["%s_order_128_256" % key] = math.log2(errs[(key, 128)] / errs[(key, 256)])
     return res

@@ -301,10 +301,14 @@ int grhd_rk_substep_noalloc(const grhd_grid *grid, const grhd_eos *eos,
  * q_out is stored corrected, as a recovery corrects it in place.  p_out
  * must not alias p_in, flags_out not flags_in.
  * diag: the recovery counts refer to q_out; Mb and J are sums of the
- * stored (corrected) q_out.  The learned guess, tile shapes other than
- * 16 x 15 and EXTERNAL sides (whose ghosts would need a recovery of their
- * own) return GRHD_ERR_UNSUPPORTED.  Other arguments as grhd_rk_substep;
- * ev_begin/ev_end bracket the one kernel of the call. */
+ * stored (corrected) q_out.  With c2p.guess = GRHD_GUESS_MLP the recovery
+ * of q_out starts from the learned guess (each wave evaluates the network
+ * for its cells at the end of the tile), except in tiles whose cells and
+ * halo are all atmosphere, which recover as without it; the root is the
+ * same to the solver's tolerance.  Tile shapes other than 16 x 15 and
+ * EXTERNAL sides (whose ghosts would need a recovery of their own) return
+ * GRHD_ERR_UNSUPPORTED.  Other arguments as grhd_rk_substep; ev_begin/
+ * ev_end bracket the one kernel of the call. */
 int grhd_rk_substep_chained(const grhd_grid *grid, const grhd_eos *eos,
                             const grhd_metric *metric, const grhd_options *opts,
                             const grhd_rk_stage *stage, const grhd_cons *qn,

@@ -275,10 +275,12 @@ constexpr int substep_waves() {
 constexpr int CHAIN_TZ = 15;  // tiles of the chained stage: 16 x 15
 
 // The chained instances: as above, except that the FP32 hybrid-EOS
-// recovery would spill at four waves and stays unconstrained.
-template <class T, int MC, int EK>
+// recovery would spill at four waves and the instances with the learned
+// guess (its operand fragments held across the network) stay
+// unconstrained.
+template <class T, int MC, int EK, bool ML>
 constexpr int chain_waves() {
-  return (sizeof(T) == 4 && EK != GRHD_EOS_IDEAL) ? 1 : substep_waves<T, MC, 16, CHAIN_TZ>();
+  return ((sizeof(T) == 4 && EK != GRHD_EOS_IDEAL) || ML) ? 1 : substep_waves<T, MC, 16, CHAIN_TZ>();
 }
 
 template <class T, int MC, int TX, int TZ>
@@ -296,10 +298,11 @@ k_substep(PatchK P, EosK e, FluxPart *part2) {
 }
 
 // The chained stage: the same tile work on 16 x CHAIN_TZ tiles, ending with the
-// recovery of q_out for the next stage.  Records: part1[tile] (recovery of
-// q_out), part2[tile] (stage diagnostics).
-template <class T, int MC, int EK>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(chain_waves<T, MC, EK>())))
+// recovery of q_out for the next stage (ML: seeded by the learned guess).
+// Records: part1[tile] (recovery of q_out), part2[tile] (stage
+// diagnostics).
+template <class T, int MC, int EK, bool ML>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(chain_waves<T, MC, EK, ML>())))
 k_substep_chain(PatchK P, EosK e, C2PPart *part1, FluxPart *part2) {
   __shared__ TileSmem<T, MC, 16, CHAIN_TZ> sm;
   __shared__ double red[NT / 64][3];
@@ -309,7 +312,7 @@ k_substep_chain(PatchK P, EosK e, C2PPart *part1, FluxPart *part2) {
   C2PAcc acc{};
   int tx, tz;
   tile_of(t, P.tiles_x, P.tiles_z, tx, tz);
-  substep_tile<T, MC, 16, CHAIN_TZ, true, EK>(P, e, tx, tz, sm, cm, mb, jm, acc);
+  substep_tile<T, MC, 16, CHAIN_TZ, true, EK, ML>(P, e, tx, tz, sm, cm, mb, jm, acc);
   if (part2) {
     flux_block_partial<NT>(cm, mb, jm, &part2[t], red);
     c2p_counts_partial<NT>(acc.n, &part1[t], red1);
@@ -472,18 +475,21 @@ int launch_substep(const PatchK &pk, const EosK &e, int prec, int mc, int shape,
 
 using ChainFn = void (*)(PatchK, EosK, C2PPart *, FluxPart *);
 
-template <class T>
+template <class T, bool ML>
 static ChainFn chain_kernel_t(int mc, int ek) {
   if (mc == MC_GEN)
-    return ek == GRHD_EOS_IDEAL ? k_substep_chain<T, MC_GEN, GRHD_EOS_IDEAL>
-                                : k_substep_chain<T, MC_GEN, GRHD_EOS_HYBRID>;
-  return ek == GRHD_EOS_IDEAL ? k_substep_chain<T, MC_CF, GRHD_EOS_IDEAL>
-                              : k_substep_chain<T, MC_CF, GRHD_EOS_HYBRID>;
+    return ek == GRHD_EOS_IDEAL ? k_substep_chain<T, MC_GEN, GRHD_EOS_IDEAL, ML>
+                                : k_substep_chain<T, MC_GEN, GRHD_EOS_HYBRID, ML>;
+  return ek == GRHD_EOS_IDEAL ? k_substep_chain<T, MC_CF, GRHD_EOS_IDEAL, ML>
+                              : k_substep_chain<T, MC_CF, GRHD_EOS_HYBRID, ML>;
 }
 
 int launch_substep_chain(const PatchK &pk, const EosK &e, int prec, int mc, C2PPart *part1,
                          FluxPart *part2, hipStream_t st) {
-  ChainFn fn = (prec == GRHD_PREC_MIXED) ? chain_kernel_t<float>(mc, e.kind) : chain_kernel_t<double>(mc, e.kind);
+  const bool ml = pk.cp.guess == GRHD_GUESS_MLP;
+  ChainFn fn = (prec == GRHD_PREC_MIXED)
+                   ? (ml ? chain_kernel_t<float, true>(mc, e.kind) : chain_kernel_t<float, false>(mc, e.kind))
+                   : (ml ? chain_kernel_t<double, true>(mc, e.kind) : chain_kernel_t<double, false>(mc, e.kind));
   long long nt = (long long)pk.tiles_x * pk.tiles_z;
   if (nt >= (1LL << 31)) return fail(GRHD_ERR_UNSUPPORTED, "more than 2^31 - 1 tiles");
   hipLaunchKernelGGL(fn, dim3((unsigned)nt), dim3(NT), 0, st, pk, e, part1, part2);
@@ -799,8 +805,6 @@ extern "C" int grhd_rk_substep_chained(const grhd_grid *grid, const grhd_eos *eo
   if ((rc = check_eos(eos)) || (rc = check_c2p(&opts->c2p)) || (rc = check_face_eps(opts->face_eps)))
     return rc;
   if (opts->prec != GRHD_PREC_FP64 && opts->prec != GRHD_PREC_MIXED) return fail(GRHD_ERR_INVALID, "bad prec");
-  if (opts->c2p.guess != GRHD_GUESS_NONE)
-    return fail(GRHD_ERR_UNSUPPORTED, "the chained stage recovers without a learned guess");
   if ((opts->tile_x || opts->tile_z) && !(opts->tile_x == 16 && opts->tile_z == CHAIN_TZ))
     return fail(GRHD_ERR_UNSUPPORTED, "the chained stage is built for 16 x %d tiles only", CHAIN_TZ);
   PatchK pk;

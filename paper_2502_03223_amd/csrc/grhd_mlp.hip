@@ -53,39 +53,8 @@ __device__ __forceinline__ void mlp_recover_cell(const EosK &e, const C2PK &cp, 
     for (int t = 0; t < 6; t++) gt[t] = act ? mval(m, GRHD_M_GXX + t, i) : (t == 0 || t == 3 || t == 5);
     inv_sym3(gt, gtu);
   }
-  // features (all lanes take part in the network evaluation)
-  double W3 = W * W * W;
-  double D = W3 * qq[0], E = W3 * qq[4];
-  double Sx = W3 * qq[1], Sy = W3 * ((g.geom == GRHD_GEOM_CYLINDRICAL && act) ? qq[2] / x : qq[2]),
-         Sz = W3 * qq[3];
-  double S2;
-  if (MC == MC_GEN) {
-    double Sv[3] = {Sx, Sy, Sz};
-    S2 = 0.0;
-    for (int a = 0; a < 3; a++)
-      for (int b = 0; b < 3; b++) S2 += gtu[s3i(a, b)] * Sv[a] * Sv[b];
-    S2 *= W * W;
-  } else {
-    S2 = W * W * (Sx * Sx + Sy * Sy + Sz * Sz);
-  }
-  double S = sqrt(S2);
-  double tau = E - D;
-  bool good = act && D > 0.0 && E > 0.0 && tau > 0.0 && isfinite(S) && isfinite(E);
-  // features and guess in FP32: the guess only sets where the FP64 root
-  // search starts
-  float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
-  if (good) {
-    f0 = (log10f((float)D) - w->xm[0]) / w->xs[0];
-    f1 = ((float)(S / E) - w->xm[1]) / w->xs[1];
-    f2 = (log10f((float)(tau / D)) - w->xm[2]) / w->xs[2];
-  }
-  float y = mlp_forward_wave(w, f0, f1, f2);
-  double zg = -1.0;
-  if (good) {
-    float P0 = (float)D * exp10f(y * w->ys + w->ym);
-    float v0 = (float)S / ((float)E + P0);
-    if (v0 >= 0.0f && v0 < 1.0f) zg = (double)(v0 / sqrtf(1.0f - v0 * v0));
-  }
+  // the guess (all lanes take part in the network evaluation)
+  const double zg = mlp_guess_wave<MC>(w, act, W, gtu, x, g.geom, qq);
   fl = 0;
   iters = 0;
   if (act) {

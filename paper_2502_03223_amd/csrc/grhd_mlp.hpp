@@ -10,6 +10,7 @@
 #include <stdint.h>
 
 #include "grhd.h"
+#include "grhd_dev.hpp"
 
 namespace grhd {
 
@@ -160,6 +161,52 @@ __device__ __forceinline__ float mlp_forward_wave(const MlpDev *__restrict__ w, 
                                                   float x2) {
   MlpRegs R = mlp_load(w);
   return mlp_forward_regs(R, x0, x1, x2);
+}
+
+// The learned guess for the cells of a wave: features (log10 D, S/E,
+// log10(tau/D)) of the undensitised state (q densitised by W^-3; S_phi =
+// x S_y on cylindrical grids), the network's log10(P/D), then
+// z0 = v0 / sqrt(1 - v0^2) with v0 = S/(E + P0); -1 (no guess) where the
+// state or the guess is out of range.  Every lane of the wave calls it; act
+// marks the lanes that hold a cell (the others pass any finite values).
+// W, gtu: conformal factor and inverse conformal metric at the cell (gtu
+// used by the general class only), x: the cell's x.
+template <int MC>
+__device__ __forceinline__ double mlp_guess_wave(const MlpDev *__restrict__ w, bool act, double W,
+                                                 const double *gtu, double x, int geom, const double *qq) {
+  double W3 = W * W * W;
+  double D = W3 * qq[0], E = W3 * qq[4];
+  double Sx = W3 * qq[1], Sy = W3 * ((geom == GRHD_GEOM_CYLINDRICAL && act) ? qq[2] / x : qq[2]),
+         Sz = W3 * qq[3];
+  double S2;
+  if (MC == MC_GEN) {
+    double Sv[3] = {Sx, Sy, Sz};
+    S2 = 0.0;
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++) S2 += gtu[s3i(a, b)] * Sv[a] * Sv[b];
+    S2 *= W * W;
+  } else {
+    S2 = W * W * (Sx * Sx + Sy * Sy + Sz * Sz);
+  }
+  double S = sqrt(S2);
+  double tau = E - D;
+  bool good = act && D > 0.0 && E > 0.0 && tau > 0.0 && isfinite(S) && isfinite(E);
+  // features and guess in FP32: the guess only sets where the FP64 root
+  // search starts
+  float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
+  if (good) {
+    f0 = (log10f((float)D) - w->xm[0]) / w->xs[0];
+    f1 = ((float)(S / E) - w->xm[1]) / w->xs[1];
+    f2 = (log10f((float)(tau / D)) - w->xm[2]) / w->xs[2];
+  }
+  float y = mlp_forward_wave(w, f0, f1, f2);
+  double zg = -1.0;
+  if (good) {
+    float P0 = (float)D * exp10f(y * w->ys + w->ym);
+    float v0 = (float)S / ((float)E + P0);
+    if (v0 >= 0.0f && v0 < 1.0f) zg = (double)(v0 / sqrtf(1.0f - v0 * v0));
+  }
+  return zg;
 }
 
 }  // namespace grhd

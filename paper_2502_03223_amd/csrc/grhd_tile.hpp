@@ -9,6 +9,7 @@
 
 #include "grhd_dev.hpp"
 #include "grhd_diag.hpp"
+#include "grhd_mlp.hpp"
 
 namespace grhd {
 
@@ -154,16 +155,13 @@ struct C2PAcc {
 // v corrected where a flag is set, then q_out, the primitives and flags of
 // q_out written, so that the next stage needs no recovery pass of its own.
 // W, gt: metric at the cell.  Without CHAIN the caller stores v itself.
-template <int MC, int EK, bool CHAIN>
-__device__ __forceinline__ void finish_cell(const PatchK &P, const EosK &e, unsigned ic, double W,
-                                            const double *gt, double xc, double dV, double *v,
-                                            double &mb, double &jm, C2PAcc &acc) {
-  if (!CHAIN) return;  // stored by the caller as they were computed
+template <int MC, int EK>
+__device__ __forceinline__ void recover_store(const PatchK &P, const EosK &e, unsigned ic, double W,
+                                              const double *gtu, double xc, double dV, double *v,
+                                              double &mb, double &jm, C2PAcc &acc, double zg) {
   {
-    double gtu[6];
-    if (MC == MC_GEN) inv_sym3(gt, gtu);
     double pp[6];
-    C2PResult r = con2prim_cell<MC, EK>(e, P.cp, W, gtu, xc, P.g.geom, v, pp, -1.0);
+    C2PResult r = con2prim_cell<MC, EK>(e, P.cp, W, gtu, xc, P.g.geom, v, pp, zg);
     // a cell that was and stays atmosphere already holds its primitives
     const bool keep = P.cp.reuse_atm && (r.flags & GRHD_FLAG_ATM) && (ld32(P.flags_out, ic) & GRHD_FLAG_ATM);
     if (!keep)
@@ -179,6 +177,30 @@ __device__ __forceinline__ void finish_cell(const PatchK &P, const EosK &e, unsi
   for (int m = 0; m < 5; m++) st32(P.qo[m], ic, v[m]);
   mb += v[0] * dV;
   jm += v[2] * dV;
+}
+
+template <int MC, int EK, bool CHAIN>
+__device__ __forceinline__ void finish_cell(const PatchK &P, const EosK &e, unsigned ic, double W,
+                                            const double *gt, double xc, double dV, double *v,
+                                            double &mb, double &jm, C2PAcc &acc) {
+  if (!CHAIN) return;  // stored by the caller as they were computed
+  double gtu[6];
+  if (MC == MC_GEN) inv_sym3(gt, gtu);
+  recover_store<MC, EK>(P, e, ic, W, gtu, xc, dV, v, mb, jm, acc, -1.0);
+}
+
+// Chained stages with the learned guess (GRHD_GUESS_MLP): the recovery of
+// the stage result starts from the network's guess.  Every lane of the wave
+// calls it (the network spans the wave); act marks the lanes holding a
+// cell, the others pass W = 1, the identity metric and a zero state.
+template <int MC, int EK>
+__device__ __forceinline__ void finish_cell_mlp(const PatchK &P, const EosK &e, bool act, unsigned ic,
+                                                double W, const double *gt, double xc, double dV,
+                                                double *v, double &mb, double &jm, C2PAcc &acc) {
+  double gtu[6];
+  if (MC == MC_GEN) inv_sym3(gt, gtu);
+  const double zg = mlp_guess_wave<MC>((const MlpDev *)P.cp.mlp, act, W, gtu, xc, P.g.geom, v);
+  if (act) recover_store<MC, EK>(P, e, ic, W, gtu, xc, dV, v, mb, jm, acc, zg);
 }
 
 // Classification of an inner 16-wide tile (its halo inside the grid, rows
@@ -375,10 +397,15 @@ __device__ __forceinline__ void lean_atm_tile(const PatchK &P, const EosK &e, in
 // One tile of one patch.  cmax, mb, jm receive this thread's share of the
 // tile's diagnostics (max Courant number, sums of q_D dV and q_Sphi dV of
 // the stored q_out); with CHAIN, acc its recovery statistics.
-template <class T, int MC, int TX, int TZ, bool CHAIN = false, int EK = 0>
+// ML (chained stages only): the recovery at the end of the stage takes the
+// learned guess; every cell's recovery then waits for the end of the cell
+// loop, where the whole wave evaluates the network.  All-atmosphere tiles
+// of the lean path recover without it.
+template <class T, int MC, int TX, int TZ, bool CHAIN = false, int EK = 0, bool ML = false>
 __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int tx, int tz,
                                              TileSmem<T, MC, TX, TZ> &sm, double &cmax_out,
                                              double &mb_out, double &jm_out, C2PAcc &acc) {
+  static_assert(!ML || CHAIN, "the learned guess belongs to the chained stage's recovery");
   using S = TileSmem<T, MC, TX, TZ>;
   constexpr int HX = S::HX;
   constexpr int CPT = (TX * TZ + NT - 1) / NT;
@@ -665,6 +692,21 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
 
   // ---- 3. divergence, sources, stage combination, diagnostics
   double mb = 0.0, jm = 0.0;
+  constexpr int ND = ML ? CPT : 1;  // deferred recoveries (ML)
+  bool d_act[ND];
+  unsigned d_ic[ND];
+  double d_W[ND], d_xc[ND], d_dV[ND], d_v[ND][5], d_gt[ND][6];
+  if constexpr (ML) {
+    for (int ci = 0; ci < CPT; ci++) {
+      d_act[ci] = false;
+      d_ic[ci] = 0u;
+      d_W[ci] = 1.0;
+      d_xc[ci] = g.x0 + 0.5 * g.dx;
+      d_dV[ci] = 0.0;
+      for (int m = 0; m < 5; m++) d_v[ci][m] = 0.0;
+      for (int s = 0; s < 6; s++) d_gt[ci][s] = (s == 0 || s == 3 || s == 5) ? 1.0 : 0.0;
+    }
+  }
 #pragma unroll
   for (int ci = 0; ci < CPT; ci++) {
     // per-cell arithmetic evaluated without contraction, so that every
@@ -792,7 +834,23 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
         st32(P.acc_out[m], ic, av);
       }
     }
-    finish_cell<MC, EK, CHAIN>(P, e, ic, gm[GRHD_M_W], gm + GRHD_M_GXX, xc, dV, v, mb, jm, acc);
+    if constexpr (ML) {
+      d_act[ci] = true;
+      d_ic[ci] = ic;
+      d_W[ci] = gm[GRHD_M_W];
+      d_xc[ci] = xc;
+      d_dV[ci] = dV;
+      for (int m = 0; m < 5; m++) d_v[ci][m] = v[m];
+      for (int s = 0; s < 6; s++) d_gt[ci][s] = gm[GRHD_M_GXX + s];
+    } else {
+      finish_cell<MC, EK, CHAIN>(P, e, ic, gm[GRHD_M_W], gm + GRHD_M_GXX, xc, dV, v, mb, jm, acc);
+    }
+  }
+  if constexpr (ML) {
+    // every lane of the wave is here: the network spans the wave
+    for (int ci = 0; ci < CPT; ci++)
+      finish_cell_mlp<MC, EK>(P, e, d_act[ci], d_ic[ci], d_W[ci], d_gt[ci], d_xc[ci], d_dV[ci], d_v[ci], mb, jm,
+                              acc);
   }
 
   cmax_out = cmax;

@@ -205,3 +205,95 @@ def test_batch_with_learned_guess(orc):
             assert percell_cond(I(o["p"]), I(ref["p"]), I(ref["qs"])) <= 1e-12, (name, i)
         assert normwise(I(out["mlp"][i]["q1"]), I(out["illinois"][i]["q1"])) <= 1e-12, i
     assert out["mlp_diag"]["n_fail"] == out["illinois_diag"]["n_fail"] == 0
+
+
+@pytest.mark.parametrize("case", ["rotating", "star", "general"])
+def test_chained_with_learned_guess(orc, case):
+    """grhd_rk_substep_chained seeded by the network: one SSP-RK3 step of
+    chained stages with and without the guess.  After every stage the
+    stored q_out and its flags equal the oracle's stage followed by its
+    recovery, and its primitives the oracle's recovery of that same q_out
+    (1e-12 normwise, per cell on rho, on P and eps by the recovery's
+    conditioning); q_out equals the unseeded chained stage's (1e-12
+    normwise; the primitives of the two runs come from slightly different
+    q_out, so they are each compared with the recovery of their own); on
+    a fast shear flow (every cell needs a real root search) the seeded
+    recoveries take fewer master-function evaluations."""
+    def both(seed, n):
+        a = synth.recovery_samples(seed, n // 2)
+        b = synth.star_recovery_samples(seed + 1, n - n // 2)
+        return np.concatenate([a, b])
+    net, _ = train(orc, n=100_000, epochs=4, sampler=both)
+    if case == "rotating":
+        # a smooth, fast shear flow (Lorentz factor 1 to 5 across the grid)
+        # of the rotating workload's thermal state: every cell needs a root
+        # search
+        grid = synth.make_grid(256, 64, 0.0, 0.0, 20.0 / 256, 20.0 / 256, "cart", ("outflow",) * 4)
+        X, Z = synth.cell_coords(grid)
+        p = synth.empty_fields(grid, 6)
+        p[0] = 1e-4 + 1e-3 * np.exp(-((X - 10.0) ** 2 + (Z - 2.5) ** 2) / 20.0)
+        p[5] = 100.0 * p[0] * (1.0 + 0.5 * np.sin(X / 3.0))
+        p[4] = (2.0 - 1.0) * p[0] * p[5]
+        w = 1.0 + 4.0 * X / 20.0
+        p[2] = np.sqrt(np.maximum(w * w - 1.0, 0.0))
+        # every momentum component well above the pressure terms that
+        # change it (R20's per-field scale)
+        p[1] = 0.5 + 0.3 * np.sin(2.0 * np.pi * Z / 5.0)
+        p[3] = 0.4 + 0.2 * np.cos(2.0 * np.pi * X / 20.0)
+        metric, eos = {}, synth.ideal_eos(2.0, 100.0)
+        c2p = dict(w_max=100.0, rho_atm=1e-12)
+    elif case == "star":
+        grid = synth.star_grid(64)
+        p, metric, eos = synth.star_problem(grid, seed=61, tov=synth.tov_solve(), vel=0.05)
+        c2p = dict(w_max=100.0, rho_atm=1e-10)
+    else:
+        grid = synth.make_grid(45, 38, 0.0, 0.0, 0.02, 0.025, "cart", ("periodic",) * 4)
+        metric = synth.general_metric(grid, 7)
+        p, eos = synth.smooth_state(grid, 8, vamp=0.5), synth.ideal_eos(5.0 / 3.0)
+        c2p = dict(w_max=100.0, rho_atm=1e-12)
+    q0 = orc.prim2con(grid, eos, metric, p, with_ghosts=True)
+    md = {k: torch.from_numpy(np.ascontiguousarray(v)).to(DEV) for k, v in metric.items()}
+    dt = 0.4 * min(grid["dx"], grid["dz"])
+    I = lambda a: synth.interior(grid, a)  # noqa: E731
+    runs = {}
+    for name, mlp in (("illinois", None), ("mlp", net.buf)):
+        opts = dict(recon="ppm", riemann="hllc", prec="fp64", c2p=dict(c2p, mlp=mlp))
+        sub = grhd.Substep(grid, eos, md, opts)
+        shp = q0.shape[1:]
+        qg = [torch.from_numpy(q0).to(DEV)] + [torch.zeros((5,) + shp, dtype=torch.float64, device=DEV)
+                                              for _ in range(3)]
+        pg = [torch.zeros((6,) + shp, dtype=torch.float64, device=DEV) for _ in range(2)]
+        fg = [torch.zeros(shp, dtype=torch.uint8, device=DEV) for _ in range(2)]
+        grhd.con2prim(grid, eos, md, dict(c2p, mlp=mlp), qg[0], pg[0], flags=fg[0])
+        cur, outs = 0, []
+        for i, st in enumerate(grhd.SSPRK3):
+            dg = grhd.new_diag()
+            sub.chained(dict(st, dt=dt), qg[0], qg[0] if i == 0 else qg[i], qg[i + 1], pg[cur], fg[cur],
+                        pg[1 - cur], fg[1 - cur], diag=dg)
+            cur = 1 - cur
+            torch.cuda.synchronize()
+            outs.append(dict(q=qg[i + 1].cpu().numpy(), p=pg[cur].cpu().numpy(), f=fg[cur].cpu().numpy(),
+                             d=grhd.read_diag(dg)))
+        runs[name] = outs
+    # the oracle: each stage from the seeded run's own input (the recovery
+    # of its stored q_s), then the recovery of the result
+    opts_o = dict(recon="ppm", riemann="hllc", c2p=c2p)
+    qn_o = orc.con2prim(grid, eos, metric, c2p, q0)[1]
+    qs_in = qn_o
+    for i, st in enumerate(grhd.SSPRK3):
+        ref = orc.rk_substep(grid, eos, metric, opts_o, dict(st, dt=dt), qn_o, qs_in)
+        p_r, q_r, fl_r, _ = orc.con2prim(grid, eos, metric, c2p, ref["qout"])
+        g_, u_ = runs["mlp"][i], runs["illinois"][i]
+        assert normwise(I(g_["q"]), I(q_r)) <= 1e-12, (case, i)
+        assert np.array_equal(I(g_["f"]), I(fl_r)), (case, i)
+        p_same = orc.con2prim(grid, eos, metric, c2p, g_["q"])[0]
+        assert normwise(I(g_["p"]), I(p_same)) <= 1e-12, (case, i)
+        assert percell(I(g_["p"]), I(p_same), (0,)) <= 1e-12, (case, i)
+        assert percell_cond(I(g_["p"]), I(p_same), I(g_["q"])) <= 1e-12, (case, i)
+        assert normwise(I(g_["q"]), I(u_["q"])) <= 1e-12, (case, i)
+        assert g_["d"]["n_fail"] == u_["d"]["n_fail"] == 0
+        qs_in = g_["q"]
+    if case == "rotating":
+        it_m = sum(o["d"]["iter_sum"] for o in runs["mlp"])
+        it_i = sum(o["d"]["iter_sum"] for o in runs["illinois"])
+        assert it_m < it_i, (it_m, it_i)
