@@ -43,6 +43,10 @@ The JSON line also carries:
   forms.bondi_rt the hot bubble in the Bondi flow (N = 512, t = 25M), HLLC
                  against TVDLF: total variation of the density (sharper
                  fingers give more) and zone-updates/s;
+  forms.general  the general-metric stage at 1024^2: Bondi on the trumpet
+                 slice (8 metric arrays) and a 17-array metric; throughput,
+                 stage-kernel time and its roofline against the bytes of the
+                 metric arrays actually read;
   forms.learned  recovery of a 2048^2 differentially rotating field, Illinois
                  from the bracket against Newton seeded by the matrix-core MLP
                  (trained here on GPU), same root;
@@ -80,7 +84,8 @@ BYTES_CHAINED = [194.0, 234.0, 234.0]
 # algorithmic bytes per zone-update of a whole substep (recovery included):
 # q_s and the metric read, q_out written, q^n read in stages 2 and 3
 BYTES_SUBSTEP = [96.0, 136.0, 136.0]
-ALL_FORMS = ("fp64", "fp64_chained", "mixed", "combined", "batched", "fmr", "bondi", "bondi_rt", "learned")
+ALL_FORMS = ("fp64", "fp64_chained", "mixed", "combined", "batched", "fmr", "bondi", "bondi_rt", "general",
+             "learned")
 # measured HBM traffic of the fused kernel (rocprofv3 FETCH_SIZE/WRITE_SIZE,
 # calibrated with a plain copy) is kept with the hash of the sources it was
 # measured on; it is reported only while the sources still hash the same
@@ -322,6 +327,9 @@ def main():
     if "bondi_rt" in forms:
         out_forms["bondi_rt"] = bondi_rt_form(args)
         print("bondi_rt done", file=sys.stderr, flush=True)
+    if "general" in forms:
+        out_forms["general"] = general_form(args)
+        print("general done", file=sys.stderr, flush=True)
     if "learned" in forms:
         out_forms["learned"] = learned_form(args)
         print("learned done", file=sys.stderr, flush=True)
@@ -805,6 +813,78 @@ def bondi_form(args):
         key = key_of(recon, riemann, face)
         res["%s_order_64_128" % key] = math.log2(errs[(key, 64)] / errs[(key, 128)])
         res["%s_order_128_256" % key] = math.log2(errs[(key, 128)] / errs[(key, 256)])
+    return res
+
+
+def general_form(args):
+    """The general-metric stage at 1024^2 (FP64, recovery pass + stage
+    kernel): the Bondi flow on the trumpet slice (lapse, two shift
+    components, W and four curvature components as arrays; inner region
+    held inside the stage) and a smooth state on a metric with all 17
+    fields as arrays (Cartesian, periodic).  Throughput over SSP-RK3 steps
+    and the stage kernel's duration (HIP events); the roofline counts the
+    bytes one fused pass must move: q_s read and q_out written (40 B each),
+    q^n read in stages 2 and 3 (40 B), 8 B per metric array."""
+    import torch
+
+    import synth
+    from paper_2502_03223_amd import grhd
+    dev = torch.device("cuda:0")
+    n = 1024
+    res = {"workload": "general-metric stage at 1024^2, FP64, SSP-RK3: Bondi on the trumpet slice "
+                       "[0, 16M]^2 (8 metric arrays) and a smooth state on a 17-array metric"}
+    cases = {}
+    d = 16.0 / n
+    g = synth.make_grid(n, n, 0.0, 0.0, d, d, "cyl", ("axis", "external", "reflect", "external"))
+    p, m, eos, frozen = synth.bondi_problem(g)
+    cases["bondi"] = (g, p, m, eos, frozen, dict(w_max=100.0, rho_atm=1e-14))
+    g2 = synth.make_grid(n, n, 0.0, 0.0, 1.0 / n, 1.0 / n, "cart", ("periodic",) * 4)
+    m2 = synth.general_metric(g2, 7, amp=0.05)
+    cases["metric17"] = (g2, synth.smooth_state(g2, 8, vamp=0.3), m2, synth.ideal_eos(5.0 / 3.0), None,
+                         dict(w_max=100.0, rho_atm=1e-12))
+    steps = max(args.steps, 5)
+    for name, (g, p, m, eos, frozen, c2p) in cases.items():
+        md = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in m.items()}
+        pd = torch.from_numpy(np.ascontiguousarray(p)).to(dev)
+        q = torch.zeros((5,) + p.shape[1:], dtype=torch.float64, device=dev)
+        grhd.prim2con(g, eos, md, pd, q, with_ghosts=True)
+        qfix, q1, q2 = q.clone(), q.clone(), q.clone()
+        opts = dict(recon="ppm", riemann="hllc", prec="fp64", c2p=c2p)
+        if frozen is not None:
+            opts["fix"] = (torch.from_numpy(frozen.astype(np.uint8)).to(dev), qfix)
+        sub = grhd.Substep(g, eos, md, opts)
+        pw = torch.zeros_like(pd)
+        fl = torch.zeros(p.shape[1:], dtype=torch.uint8, device=dev)
+        dt = 0.4 * min(g["dx"], g["dz"])
+        bufs = [(q, q, q1), (q, q1, q2), (q, q2, q)]
+        stages = [grhd.make_stage(dict(s, dt=dt)) for s in grhd.SSPRK3]
+
+        def step(kev=None):
+            for s, (qn, qs, qo) in enumerate(bufs):
+                sub(stages[s], qn, qs, qo, pw, flags=fl, events=kev[s] if kev else None)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kevs = [[(grhd.Event(), grhd.Event()) for _ in range(3)] for _ in range(steps)]
+        for k in range(steps):
+            step(kevs[k])
+        torch.cuda.synchronize()
+        kms = np.array([[kevs[k][s][0].elapsed_ms(kevs[k][s][1]) for s in range(3)] for k in range(steps)])
+        kms = kms.mean(axis=0)
+        nzone = g["nx"] * g["nz"]
+        narr = len(m)
+        per_stage = [8.0 * (10 + narr), 8.0 * (15 + narr), 8.0 * (15 + narr)]
+        achieved = float(np.mean(per_stage)) * nzone / (float(kms.mean()) * 1e-3) / 1e9
+        res[name] = {"value": 3 * nzone * steps / wall, "unit": "zone-updates/s",
+                     "ms_per_step": wall * 1e3 / steps, "kernel_ms": kms.tolist(), "metric_arrays": narr,
+                     "bytes_per_zone": per_stage,
+                     "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": achieved / HBM_PEAK_GBS}}
     return res
 
 

@@ -157,8 +157,13 @@ typedef struct {
   int tile_x, tile_z;         /* 0, 0 = library default (16 x 15; 16 x 7
                                  on grids of fewer than 1536 tiles of
                                  16 x 16, 128 for the general metric
-                                 class).  Built: 16 x 15, 16 x 7, 16 x 16,
-                                 16 x 8, 32 x 8, 32 x 16, 64 x 8 */
+                                 class, and for general metrics with at
+                                 least 8 of the 11 lapse, shift, W and
+                                 conformal-metric fields as arrays: the
+                                 16 x 7 and 16 x 8 general instances stage
+                                 those fields in LDS).  Built: 16 x 15,
+                                 16 x 7, 16 x 16, 16 x 8, 32 x 8, 32 x 16,
+                                 64 x 8 */
   const uint8_t *fix_mask;    /* optional interior boundary condition
                                  (nullable; grhd_rk_substep and
                                  grhd_rk_substep_chained): on interior

@@ -735,16 +735,22 @@ int rk_substep_ws(const grhd_grid *grid, const grhd_eos *eos, const grhd_metric 
   if ((rc = set_fixed(opts, pk))) return rc;
   // default 16 x 15: two full passes of the workgroup over the faces, a
   // small halo per cell, and the FP64 instance fits three workgroups per CU
-  // in LDS; grids of few such tiles take 16 x 7 (twice the workgroups, half
-  // the length of the slowest tile): under 1536 tiles of 16 x 16 for the
-  // conformally flat class, under 128 for the general one
+  // in LDS; grids of few such tiles take 16 x 7 (twice the workgroups,
+  // half the length of the slowest tile): under 1536 tiles of 16 x 16 for
+  // the conformally flat class, under 128 for the general one
   int shape = shape_index(16, 15);
   if (opts->tile_x || opts->tile_z) {
     shape = shape_index(opts->tile_x, opts->tile_z);
     if (shape < 0) return fail(GRHD_ERR_UNSUPPORTED, "tile %dx%d not built", opts->tile_x, opts->tile_z);
   } else {
     const long long t16 = (long long)((grid->nx + 15) / 16) * ((grid->nz + 15) / 16);
-    if (t16 < (metric_class(metric) == MC_CF ? 1536 : 128)) shape = shape_index(16, 7);
+    // a general metric with most geometry fields as arrays reads them from
+    // LDS on 16 x 7 tiles (measured at 1024^2: 11 arrays, 316 against
+    // 331 us per stage on 16 x 15; 4 arrays, 284 against 249 us)
+    int geo = 0;
+    if (metric)
+      for (int f = 0; f < 11; f++) geo += metric->f[f] != nullptr;
+    if (t16 < (metric_class(metric) == MC_CF ? 1536 : 128) || geo >= 8) shape = shape_index(16, 7);
   }
   int tx, tz;
   shape_of(shape, &tx, &tz);

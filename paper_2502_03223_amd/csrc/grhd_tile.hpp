@@ -74,8 +74,15 @@ struct TileSmem {
   static constexpr int NFX = (TX + 1) * TZ, NFZ = TX * (TZ + 1);
   static constexpr int NF = NFX + NFZ;  // x faces, then z faces
   static constexpr int NM = (MC == MC_CF) ? NC : 1;
+  // general class on tiles of at most 128 cells: the 11 geometry fields
+  // (lapse, shift, W, conformal metric; the fields whose face values and
+  // derivatives the stage takes) staged in LDS as well
+  static constexpr bool MG = (MC == MC_GEN) && TX * TZ <= 128;
+  static constexpr int NGM = 11;
+  static constexpr int NGC = MG ? NC : 1;
   T p[6][NC];
   double ma[NM], mw[NM];
+  double mg[NGM][NGC];
   T f[5][NF];
   uint8_t atm[NC];  // 1: the cell holds exactly the atmosphere state
 };
@@ -488,6 +495,21 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
         }
       }
     }
+    if constexpr (S::MG) {
+      // the geometry fields at every cell a face or derivative stencil
+      // reads (metric ghost cells are the caller's, as in the face loop)
+      double vg[LPT][S::NGM];
+#pragma unroll
+      for (int i = 0; i < LPT; i++)
+        if (use[i])
+          for (int fld = 0; fld < S::NGM; fld++) vg[i][fld] = mval32(P.m, fld, im[i]);
+#pragma unroll
+      for (int i = 0; i < LPT; i++) {
+        const int c = tid + i * NT;
+        if (use[i])
+          for (int fld = 0; fld < S::NGM; fld++) sm.mg[fld][c] = vg[i][fld];
+      }
+    }
     int my_atm = have_flags ? 1 : 0;
 #pragma unroll
     for (int i = 0; i < LPT; i++) {
@@ -644,7 +666,11 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
             const double *src = P.m.f[fld];
             T v;
             if (src) {
-              for (int i = 0; i < 6; i++) t6[i] = (T)src[g0 + i * gs];
+              if constexpr (S::MG) {
+                for (int i = 0; i < 6; i++) t6[i] = (T)sm.mg[fld][base + i * stride];
+              } else {
+                for (int i = 0; i < 6; i++) t6[i] = (T)src[g0 + i * gs];
+              }
               v = lagrange6(t6);
             } else {
               v = (T)P.m.c[fld];
@@ -753,6 +779,17 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
       for (int i = 0; i < GRHD_NMET; i++) {
         const double *src = P.m.f[i];
         if (!src) { gm[i] = P.m.c[i]; dg[i] = 0.0; dg[GRHD_NMET + i] = 0.0; continue; }
+        if constexpr (S::MG) {
+          if (i < S::NGM) {
+            double a7[7];
+            gm[i] = sm.mg[i][lc];
+            for (int t = 0; t < 7; t++) a7[t] = sm.mg[i][lc - 3 + t];
+            dg[i] = deriv6(a7, i60dx);
+            for (int t = 0; t < 7; t++) a7[t] = sm.mg[i][lc + (t - 3) * HX];
+            dg[GRHD_NMET + i] = deriv6(a7, i60dz);
+            continue;
+          }
+        }
         gm[i] = ld32(src, ic);
         double a7[7];
         for (int t = 0; t < 7; t++) a7[t] = ld32(src, ic - 3u + (unsigned)t);

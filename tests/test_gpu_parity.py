@@ -347,6 +347,29 @@ def test_tile_shapes_bitwise(orc, tov):
         assert np.array_equal(synth.interior(grid, o["qout"]), synth.interior(grid, outs[0]["qout"]))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_general_metric_tile_shapes_bitwise(orc, prec):
+    """The general class reads its geometry fields from LDS on 16 x 7 and
+    16 x 8 tiles and from memory on larger ones: the same bits either way
+    (cylindrical star with every metric field active, ragged tails)."""
+    tov = synth.tov_solve()
+    grid, p, metric, eos = star_case(77, 43, tov, vel=0.05)
+    gm = synth.general_metric(grid, 44, amp=0.02)
+    gm["alp"] = metric["alp"] * (1.0 + 0.0 * gm["alp"])
+    gm["W"] = metric["W"]
+    q = orc.prim2con(grid, eos, gm, p, with_ghosts=True)
+    opts = dict(recon="ppm", riemann="hllc", prec=prec, c2p=C2P_STAR)
+    st = dict(grhd.SSPRK3[1], dt=0.4 * grid["dx"])
+    outs = []
+    for tile in [(16, 7), (16, 8), (16, 15), (32, 8)]:
+        ref, out = run_pair(orc, grid, eos, gm, opts, st, q, q, tile=tile)
+        outs.append(out)
+    if prec == "fp64":
+        check_pair(grid, ref, outs[0])
+    for o in outs[1:]:
+        assert np.array_equal(synth.interior(grid, o["qout"]), synth.interior(grid, outs[0]["qout"]))
+
+
 @pytest.mark.parametrize("n,face_eps", [(512, "recon"), (1024, "recon"), (512, "eos")])
 def test_substep_full_size_star(orc, tov, n, face_eps):
     """Full star sizes in the benchmark's launch configuration, all cells."""
