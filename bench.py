@@ -106,21 +106,21 @@ def kernel_sources_hash():
 
 
 def measured_traffic(nzone, chained):
-    """Bytes per launch recorded with the counter profile of that stage
-    kernel, or None when absent, taken on other sources or on a launch of
-    another size."""
+    """(bytes per launch of that stage kernel, bytes per substep of every
+    kernel) recorded with its counter profile, or (None, None) when absent,
+    taken on other sources or on a launch of another size."""
     try:
         kv = {}
+        keys = ("traffic_bytes_per_launch", "traffic_bytes_per_substep", "source_sha256", "zones_per_launch")
         for line in open(TRAFFIC_FILES[chained]):
-            if ":" in line and line.split(":", 1)[0].strip() in ("traffic_bytes_per_launch", "source_sha256",
-                                                                 "zones_per_launch"):
+            if ":" in line and line.split(":", 1)[0].strip() in keys:
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip().strip("`")
         if kv.get("source_sha256") != kernel_sources_hash() or int(kv["zones_per_launch"]) != nzone:
-            return None
-        return float(kv["traffic_bytes_per_launch"])
+            return None, None
+        return float(kv["traffic_bytes_per_launch"]), float(kv["traffic_bytes_per_substep"])
     except (OSError, KeyError, ValueError):
-        return None
+        return None, None
 
 
 def parse():
@@ -301,8 +301,10 @@ def main():
     # fold included, from the clean pass)
     substep_gbs = float(np.mean(BYTES_SUBSTEP)) * nzone / (ms_per_step / 3.0 * 1e-3) / 1e9
     diag = r64["diag"]
-    tb = measured_traffic(nzone, head_chained)
+    tb, tsub = measured_traffic(nzone, head_chained)
     traffic = tb / (kms * 1e-3) / 1e9 if tb else None
+    # every kernel of a substep (recovery, stage, fold) over its wall time
+    traffic_substep = tsub / (ms_per_step / 3.0 * 1e-3) / 1e9 if tsub else None
     if "mixed" in forms:
         rm = run_form("mixed")
         value_m = 3 * nzone * args.steps / rm["wall"]
@@ -372,6 +374,7 @@ def main():
             "kernel_design_gbs": float(np.mean(BYTES_CHAINED if head_chained else BYTES_KERNEL)) * nzone
                                  / (kms * 1e-3) / 1e9,
             "measured_bytes_per_launch": tb,
+            "measured_bytes_per_substep": tsub, "traffic_substep": traffic_substep,
             "substep_gbs": substep_gbs, "substep_frac": substep_gbs / HBM_PEAK_GBS,
             "bytes_note": "achieved = the algorithmic bytes of one fused pass (96, 136, 136 B per zone "
                           "over the three SSP-RK3 stages) x zones / mean kernel time; "
@@ -379,8 +382,10 @@ def main():
                           "(primitives and flags of the chained form, or the primitive re-read of "
                           "the separate-recovery form) over the same time",
             "traffic_note": "traffic = measured HBM bytes per launch (FETCH x2 + WRITE x1, factors "
-                            "from a 256 MiB copy) / the same mean launch time, in GB/s; null when the "
-                            "kernel sources changed since the counters were taken",
+                            "from a 256 MiB copy) / the same mean launch time, in GB/s; traffic_substep = "
+                            "the measured bytes of every kernel of a substep (recovery, stage, fold) / the "
+                            "substep's wall time; null when the kernel sources changed since the counters "
+                            "were taken",
             "timing_note": "value and ms_per_step come from K steps with nothing recorded on the stream; "
                            "kernel_ms and stage_ms from the same K steps repeated right after with HIP "
                            "events around every fused kernel and every substep",
