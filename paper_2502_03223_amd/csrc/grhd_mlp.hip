@@ -169,88 +169,146 @@ int launch_con2prim_mlp(const GridK &g, const EosK &e, const C2PK &cp, const Met
 
 // ------------------------------------------------------------ training
 
-constexpr int GW = 64;  // samples per chunk (one wave)
+// FP32 matrix-core instruction v_mfma_f32_16x16x4_f32 (wave64; r = l % 16,
+// g = l / 16): A lane l = A[r][g], B lane l = B[g][r], result lane l =
+// D[4g + v][r], v < 4 (the layout of the BF16 16x16x16 instruction with one
+// K value per lane).
+__device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
 
-// Per-sample forward/backward of the MSE loss with the BF16-rounded weights
-// of the inference path (FP32 arithmetic), then a change of roles: lane u
-// accumulates the gradient row of hidden unit u over the chunk's samples.
-// Each workgroup folds its rows into grad with one atomic per parameter.
-__global__ void __launch_bounds__(GW)
+constexpr int GC = 16;      // samples per chunk: one matrix-core column block
+constexpr int GWAVES = 4;   // waves per workgroup
+constexpr int W2P = MLP_H + 1;
+
+// Gradient of the MSE loss with the BF16-rounded weights of the inference
+// path, FP32 arithmetic on the FP32 matrix cores.  A wave takes chunks of
+// 16 samples (the columns of a 16x16 block); the hidden layers are 4 blocks
+// of 16 units (the rows):
+//   layer 1   H1 = ReLU(W1 X + b1)           4 instructions (K = 3, padded)
+//   layer 2   H2 = ReLU(W2 H1 + b2)          64 (K = 64 units)
+//   output    y = w3 . H2 + b3, dy = 2 (y - t) / n
+//   backward  dH2 = dy w3 [H2 > 0]; dH1 = (W2^T dH2) [H1 > 0]     64
+//             dW2 += dH2 H1^T over the chunk's samples           64 (K = 16)
+// A result block holds units 4g + v of lane l's group for sample r, which
+// is the B operand of the next product if its K indices are taken as
+// (units 4g + v, g = 0..3) for fixed v: a sum over K does not depend on its
+// order, and the weights are read in that order.  dW2 sums over samples,
+// so H1 and dH2 go through LDS once per chunk to put units in the rows.
+// The vector gradients (b1, b2, w3, b3, W1) are accumulated per lane and
+// summed at the end; each workgroup folds its gradient in LDS and adds it
+// to grad with one atomic per parameter.
+__global__ void __launch_bounds__(64 * GWAVES)
 k_mlp_grad(const float *__restrict__ P, const float *__restrict__ X, const float *__restrict__ t, int n,
            float *grad, float *loss) {
-  __shared__ float sW1[MLP_H * 3], sb1[MLP_H], sW2[MLP_H * MLP_H], sb2[MLP_H], sw3[MLP_H];
-  __shared__ float sH1[MLP_H][GW + 1], sH2[MLP_H][GW + 1], sD2[MLP_H][GW + 1], sD1[MLP_H][GW + 1];
-  __shared__ float sX[3][GW], sDY[GW];
-  const int l = threadIdx.x;
-  for (int i = l; i < MLP_H * 3; i += GW) sW1[i] = bf2f(f2bf(P[OFF_W1 + i]));
-  for (int i = l; i < MLP_H * MLP_H; i += GW) sW2[i] = bf2f(f2bf(P[OFF_W2 + i]));
-  for (int i = l; i < MLP_H; i += GW) {
+  __shared__ float sW2[MLP_H][W2P];
+  __shared__ float sW1[MLP_H][4];
+  __shared__ float sb1[MLP_H], sb2[MLP_H], sw3[MLP_H];
+  __shared__ float sT[GWAVES][2][MLP_H][GC + 1];  // per wave: H1, dH2 as [unit][sample]
+  __shared__ float sG[MLP_NPARAM];
+  const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63, r = l & 15, g = l >> 4;
+  for (int i = tid; i < MLP_H * MLP_H; i += blockDim.x) sW2[i / MLP_H][i % MLP_H] = bf2f(f2bf(P[OFF_W2 + i]));
+  for (int i = tid; i < MLP_H * 4; i += blockDim.x) {
+    const int u = i / 4, k = i % 4;
+    sW1[u][k] = (k < 3) ? bf2f(f2bf(P[OFF_W1 + u * 3 + k])) : 0.0f;
+  }
+  for (int i = tid; i < MLP_H; i += blockDim.x) {
     sb1[i] = P[OFF_B1 + i];
     sb2[i] = P[OFF_B2 + i];
     sw3[i] = P[OFF_W3 + i];
   }
+  for (int i = tid; i < MLP_NPARAM; i += blockDim.x) sG[i] = 0.0f;
   const float b3 = P[OFF_B3];
   __syncthreads();
-  float gW2[MLP_H];
-  for (int i = 0; i < MLP_H; i++) gW2[i] = 0.0f;
-  float gb2 = 0.0f, gw3 = 0.0f, gW1[3] = {0.0f, 0.0f, 0.0f}, gb1 = 0.0f, gb3 = 0.0f, lsum = 0.0f;
+  f32x4 gW2[4][4];  // [mo][mb]: lane holds dW2[16 mo + 4g + v][16 mb + r]
+  float gw3[4][4], gb2[4][4], gb1[4][4], gW1[4][4][3];
+  for (int a = 0; a < 4; a++)
+    for (int v = 0; v < 4; v++) {
+      for (int b = 0; b < 4; b++) gW2[a][b][v] = 0.0f;
+      gw3[a][v] = gb2[a][v] = gb1[a][v] = 0.0f;
+      for (int k = 0; k < 3; k++) gW1[a][v][k] = 0.0f;
+    }
+  float gb3 = 0.0f, lsum = 0.0f;
   const float inv_n = 1.0f / (float)n;
-  int nchunk = (n + GW - 1) / GW;
-  for (int ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
-    int s = ch * GW + l;
-    bool act = s < n;
-    float x[3] = {act ? X[3 * s] : 0.0f, act ? X[3 * s + 1] : 0.0f, act ? X[3 * s + 2] : 0.0f};
-    float h1[MLP_H], h2[MLP_H];
-    for (int u = 0; u < MLP_H; u++) {
-      float a = sb1[u] + sW1[u * 3] * x[0] + sW1[u * 3 + 1] * x[1] + sW1[u * 3 + 2] * x[2];
-      h1[u] = fmaxf(a, 0.0f);
-      sH1[u][l] = h1[u];
+  const int nchunk = (n + GC - 1) / GC;
+  float(*TH)[GC + 1] = sT[wv][0];
+  float(*TD)[GC + 1] = sT[wv][1];
+  for (int ch = blockIdx.x * GWAVES + wv; ch < nchunk; ch += gridDim.x * GWAVES) {
+    const int s = ch * GC + r;
+    const bool act = s < n;
+    float x[3];
+    for (int k = 0; k < 3; k++) x[k] = act ? X[3 * s + k] : 0.0f;
+    const float xb = (g == 0) ? x[0] : (g == 1) ? x[1] : (g == 2) ? x[2] : 0.0f;
+    float h1[4][4], h2[4][4], d2[4][4];
+    for (int mb = 0; mb < 4; mb++) {
+      f32x4 c = {sb1[16 * mb + 4 * g], sb1[16 * mb + 4 * g + 1], sb1[16 * mb + 4 * g + 2], sb1[16 * mb + 4 * g + 3]};
+      c = mfma4(sW1[16 * mb + r][g], xb, c);
+      for (int v = 0; v < 4; v++) h1[mb][v] = fmaxf(c[v], 0.0f);
     }
-    float y = b3;
-    for (int o = 0; o < MLP_H; o++) {
-      float a = sb2[o];
-      for (int u = 0; u < MLP_H; u++) a += sW2[o * MLP_H + u] * h1[u];
-      h2[o] = fmaxf(a, 0.0f);
-      sH2[o][l] = h2[o];
-      y += sw3[o] * h2[o];
+    for (int mo = 0; mo < 4; mo++) {
+      f32x4 c = {sb2[16 * mo + 4 * g], sb2[16 * mo + 4 * g + 1], sb2[16 * mo + 4 * g + 2], sb2[16 * mo + 4 * g + 3]};
+      for (int mb = 0; mb < 4; mb++)
+        for (int v = 0; v < 4; v++) c = mfma4(sW2[16 * mo + r][16 * mb + 4 * g + v], h1[mb][v], c);
+      for (int v = 0; v < 4; v++) h2[mo][v] = fmaxf(c[v], 0.0f);
     }
-    float r = act ? y - t[s] : 0.0f;
-    lsum += r * r;
-    float dy = 2.0f * r * inv_n;
-    sDY[l] = dy;
-    for (int k = 0; k < 3; k++) sX[k][l] = x[k];
-    for (int o = 0; o < MLP_H; o++) {
-      h2[o] = (h2[o] > 0.0f) ? dy * sw3[o] : 0.0f;   // delta of layer 2
-      sD2[o][l] = h2[o];
+    float part = 0.0f;
+    for (int mo = 0; mo < 4; mo++)
+      for (int v = 0; v < 4; v++) part += sw3[16 * mo + 4 * g + v] * h2[mo][v];
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    const float res = act ? part + b3 - t[s] : 0.0f;
+    const float dy = 2.0f * res * inv_n;
+    if (g == 0) {
+      lsum += res * res;
+      gb3 += dy;
     }
-    for (int u = 0; u < MLP_H; u++) {
-      float a = 0.0f;
-      for (int o = 0; o < MLP_H; o++) a += sW2[o * MLP_H + u] * h2[o];
-      sD1[u][l] = (h1[u] > 0.0f) ? a : 0.0f;
+    for (int mo = 0; mo < 4; mo++)
+      for (int v = 0; v < 4; v++) {
+        gw3[mo][v] += dy * h2[mo][v];
+        d2[mo][v] = (h2[mo][v] > 0.0f) ? dy * sw3[16 * mo + 4 * g + v] : 0.0f;
+        gb2[mo][v] += d2[mo][v];
+      }
+    for (int mb = 0; mb < 4; mb++) {
+      f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+      for (int mo = 0; mo < 4; mo++)
+        for (int v = 0; v < 4; v++) c = mfma4(sW2[16 * mo + 4 * g + v][16 * mb + r], d2[mo][v], c);
+      for (int v = 0; v < 4; v++) {
+        const float d1 = (h1[mb][v] > 0.0f) ? c[v] : 0.0f;
+        gb1[mb][v] += d1;
+        for (int k = 0; k < 3; k++) gW1[mb][v][k] += d1 * x[k];
+      }
     }
-    __syncthreads();
-    // lane l now stands for hidden unit l
-    for (int ss = 0; ss < GW; ss++) {
-      float d2 = sD2[l][ss], d1 = sD1[l][ss], dys = sDY[ss];
-      for (int u = 0; u < MLP_H; u++) gW2[u] += d2 * sH1[u][ss];
-      gb2 += d2;
-      gw3 += dys * sH2[l][ss];
-      gW1[0] += d1 * sX[0][ss];
-      gW1[1] += d1 * sX[1][ss];
-      gW1[2] += d1 * sX[2][ss];
-      gb1 += d1;
-      gb3 += dys;
-    }
-    __syncthreads();
+    // this wave's LDS block: the previous chunk's reads are done before
+    // these writes, and these writes before the reads below
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int mb = 0; mb < 4; mb++)
+      for (int v = 0; v < 4; v++) {
+        TH[16 * mb + 4 * g + v][r] = h1[mb][v];
+        TD[16 * mb + 4 * g + v][r] = d2[mb][v];
+      }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int j = 0; j < GC / 4; j++)
+      for (int mo = 0; mo < 4; mo++) {
+        const float a = TD[16 * mo + r][4 * j + g];
+        for (int mb = 0; mb < 4; mb++) gW2[mo][mb] = mfma4(a, TH[16 * mb + r][4 * j + g], gW2[mo][mb]);
+      }
   }
-  for (int u = 0; u < MLP_H; u++) atomicAdd(&grad[OFF_W2 + l * MLP_H + u], gW2[u]);
-  atomicAdd(&grad[OFF_B2 + l], gb2);
-  atomicAdd(&grad[OFF_W3 + l], gw3);
-  for (int k = 0; k < 3; k++) atomicAdd(&grad[OFF_W1 + l * 3 + k], gW1[k]);
-  atomicAdd(&grad[OFF_B1 + l], gb1);
-  if (l == 0) atomicAdd(&grad[OFF_B3], gb3);
+  for (int mo = 0; mo < 4; mo++)
+    for (int v = 0; v < 4; v++) {
+      const int u = 16 * mo + 4 * g + v;
+      for (int mb = 0; mb < 4; mb++) atomicAdd(&sG[OFF_W2 + u * MLP_H + 16 * mb + r], gW2[mo][mb][v]);
+      atomicAdd(&sG[OFF_W3 + u], gw3[mo][v]);
+      atomicAdd(&sG[OFF_B2 + u], gb2[mo][v]);
+      atomicAdd(&sG[OFF_B1 + u], gb1[mo][v]);
+      for (int k = 0; k < 3; k++) atomicAdd(&sG[OFF_W1 + u * 3 + k], gW1[mo][v][k]);
+    }
+  if (g == 0) atomicAdd(&sG[OFF_B3], gb3);
   for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
   if (loss && l == 0) atomicAdd(loss, lsum * inv_n);
+  __syncthreads();
+  for (int i = tid; i < MLP_NPARAM; i += blockDim.x) atomicAdd(&grad[i], sG[i]);
 }
 
 __global__ void k_fill0(float *a, int n) {
@@ -329,9 +387,11 @@ static int mlp_grad_launch(const float *params, float *grad, const float *X, con
                            float *loss, hipStream_t st) {
   hipLaunchKernelGGL(k_fill0, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, st, grad, MLP_NPARAM);
   if (loss) hipLaunchKernelGGL(k_fill0, dim3(1), dim3(64), 0, st, loss, 1);
-  int nchunk = (n + GW - 1) / GW;
-  int blocks = nchunk < 512 ? nchunk : 512;
-  hipLaunchKernelGGL(k_mlp_grad, dim3(blocks), dim3(GW), 0, st, params, X, t, n, grad, loss);
+  // about four chunks of 16 samples per wave, at most 256 workgroups
+  const long long nchunk = ((long long)n + GC - 1) / GC;
+  const long long want = (nchunk + 4 * GWAVES - 1) / (4 * GWAVES);
+  const int blocks = (int)(want < 256 ? want : 256);
+  hipLaunchKernelGGL(k_mlp_grad, dim3(blocks), dim3(64 * GWAVES), 0, st, params, X, t, n, grad, loss);
   return launch_status("mlp gradient");
 }
 
