@@ -295,16 +295,33 @@ k_mlp_grad(const float *__restrict__ P, const float *__restrict__ X, const float
         for (int mb = 0; mb < 4; mb++) gW2[mo][mb] = mfma4(a, TH[16 * mb + r][4 * j + g], gW2[mo][mb]);
       }
   }
+  // the vector gradients are summed over the 16 sample lanes of each lane
+  // group first: LDS atomics on one address from many lanes serialise
+  auto rsum16 = [](float x) {
+    x += __shfl_xor(x, 1, 64);
+    x += __shfl_xor(x, 2, 64);
+    x += __shfl_xor(x, 4, 64);
+    x += __shfl_xor(x, 8, 64);
+    return x;
+  };
   for (int mo = 0; mo < 4; mo++)
     for (int v = 0; v < 4; v++) {
       const int u = 16 * mo + 4 * g + v;
       for (int mb = 0; mb < 4; mb++) atomicAdd(&sG[OFF_W2 + u * MLP_H + 16 * mb + r], gW2[mo][mb][v]);
-      atomicAdd(&sG[OFF_W3 + u], gw3[mo][v]);
-      atomicAdd(&sG[OFF_B2 + u], gb2[mo][v]);
-      atomicAdd(&sG[OFF_B1 + u], gb1[mo][v]);
-      for (int k = 0; k < 3; k++) atomicAdd(&sG[OFF_W1 + u * 3 + k], gW1[mo][v][k]);
+      const float a = rsum16(gw3[mo][v]), b = rsum16(gb2[mo][v]), c = rsum16(gb1[mo][v]);
+      float w[3];
+      for (int k = 0; k < 3; k++) w[k] = rsum16(gW1[mo][v][k]);
+      if (r == 0) {
+        atomicAdd(&sG[OFF_W3 + u], a);
+        atomicAdd(&sG[OFF_B2 + u], b);
+        atomicAdd(&sG[OFF_B1 + u], c);
+        for (int k = 0; k < 3; k++) atomicAdd(&sG[OFF_W1 + u * 3 + k], w[k]);
+      }
     }
-  if (g == 0) atomicAdd(&sG[OFF_B3], gb3);
+  {
+    const float b = rsum16(gb3);
+    if (l == 0) atomicAdd(&sG[OFF_B3], b);
+  }
   for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
   if (loss && l == 0) atomicAdd(loss, lsum * inv_n);
   __syncthreads();
