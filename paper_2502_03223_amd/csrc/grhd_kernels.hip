@@ -277,10 +277,14 @@ constexpr int CHAIN_TZ = 15;  // tiles of the chained stage: 16 x 15
 // The chained instances: as above, except that the FP32 hybrid-EOS
 // recovery would spill at four waves and the instances with the learned
 // guess (its operand fragments held across the network) stay
-// unconstrained.
+// unconstrained, and the FP32 ideal-gas instance takes three waves (at four
+// it spills 56 B per lane; measured on the 1024^2 star 67.1 against 69.2 us
+// per stage).
 template <class T, int MC, int EK, bool ML>
 constexpr int chain_waves() {
-  return ((sizeof(T) == 4 && EK != GRHD_EOS_IDEAL) || ML) ? 1 : substep_waves<T, MC, 16, CHAIN_TZ>();
+  return ((sizeof(T) == 4 && EK != GRHD_EOS_IDEAL) || ML) ? 1
+         : (sizeof(T) == 4 && MC == MC_CF)                 ? 3
+                                                           : substep_waves<T, MC, 16, CHAIN_TZ>();
 }
 
 template <class T, int MC, int TX, int TZ>

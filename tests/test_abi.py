@@ -87,13 +87,6 @@ def test_null_pointers_rejected(G):
     assert lib.grhd_hllc_flux(None, 0, 0, 0, None, None, None, None, None, None, None) == -1
 
 
-class FakeBuf:
-    """Stands in for a device buffer whose address is never dereferenced."""
-
-    def data_ptr(self):
-        return 0x7000
-
-
 def call_chained(G, opts=None, grid=None, alias_p=False, alias_flags=False, null_flags_out=False):
     import synth
     g = G.make_grid(grid or grid_ok())
@@ -119,14 +112,13 @@ def call_chained(G, opts=None, grid=None, alias_p=False, alias_flags=False, null
     (dict(alias_p=True), -1),
     (dict(alias_flags=True), -1),
     (dict(null_flags_out=True), -1),
-    (dict(opts=dict(c2p=dict(w_max=100.0, rho_atm=1e-10, mlp=FakeBuf()))), -3),
     (dict(opts=dict(c2p=dict(w_max=100.0, rho_atm=1e-10), tile=(32, 8))), -3),
     (dict(grid=dict(grid_ok(), bc=("axis", "external", "reflect", "outflow"))), -3),
 ])
 def test_chained_arguments_rejected(G, bad, rc):
     """The chained stage rejects aliased outputs (invalid) and what it is
-    not built for (unsupported: learned guess, other tiles, EXTERNAL
-    sides) before touching the device."""
+    not built for (unsupported: other tiles, EXTERNAL sides) before
+    touching the device."""
     assert call_chained(G, **bad) == rc
     assert len(G.lib().grhd_last_error()) > 0
 
