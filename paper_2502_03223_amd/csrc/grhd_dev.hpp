@@ -82,6 +82,37 @@ __device__ __forceinline__ double mval32(const MetK &m, int f, unsigned i) {
 template <class T> __device__ __forceinline__ T tsqrt(T x) { return sqrt(x); }
 template <> __device__ __forceinline__ float tsqrt<float>(float x) { return sqrtf(x); }
 
+// Reciprocal and square root of the flux arithmetic from the hardware
+// approximations instead of the correctly rounded sequences: frcp is
+// v_rcp_f64 (relative error about 2^-24) refined by two Newton steps,
+// within one ulp of 1/x; fsqrt is v_rsq_f64 refined by one coupled Newton
+// step for sqrt(x) and 1/(2 sqrt(x)) and a final residual correction,
+// which gave the correctly rounded root on all of 4M random arguments over
+// 40 decades.  For finite x > 0 (fsqrt: x >= 0).  In single precision the
+// hardware instructions themselves (about one ulp).
+template <class T> __device__ __forceinline__ T frcp(T x);
+template <> __device__ __forceinline__ double frcp<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+template <> __device__ __forceinline__ float frcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
+template <class T> __device__ __forceinline__ T fsqrt(T x);
+template <> __device__ __forceinline__ double fsqrt<double>(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  double y = x * r, h = 0.5 * r;
+  const double e = fma(-y, h, 0.5);
+  y = fma(y, e, y);
+  h = fma(h, e, h);
+  const double d = fma(-y, y, x);
+  y = fma(d, h, y);
+  return x > 0.0 ? y : x;  // rsq(0) is infinite
+}
+template <> __device__ __forceinline__ float fsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // inverse of a symmetric 3x3 (xx,xy,xz,yy,yz,zz) by cofactors / det
 template <class T>
 __device__ __forceinline__ void inv_sym3(const T *a, T *inv) {
@@ -142,8 +173,9 @@ __device__ __forceinline__ T eos_cs2(const EosK &e, T rho, T eps, T P) {
     T ec = kr / T(e.G[i] - 1.0) + T(e.deps[i]);  // cold specific energy
     chi = T(e.G[i]) * kr + gm1 * (eps - ec) - gm1 * kr;
   }
-  T h = T(1) + eps + P / rho;
-  T cs2 = (chi + P / rho * gm1) / h;
+  const T Pr = P * frcp(rho);
+  T h = T(1) + eps + Pr;
+  T cs2 = (chi + Pr * gm1) * frcp(h);
   if (!(cs2 > T(0))) cs2 = T(0);
   if (cs2 > T(0.999999)) cs2 = T(0.999999);
   return cs2;
@@ -648,12 +680,12 @@ template <class T>
 __device__ __forceinline__ void tetrad_state(const EosK &e, const PrimT<T> &p, const T *ut,
                                              TState<T> &s) {
   T usq = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
-  T w = tsqrt(T(1) + usq);
-  T iw = T(1) / w;
+  T w = fsqrt(T(1) + usq);
+  T iw = frcp(w);
   T vn = ut[0] * iw;
   T iw2 = iw * iw;            // 1 - v^2
   T v2 = usq * iw2;
-  T h = T(1) + p.eps + p.P / p.rho;
+  T h = T(1) + p.eps + p.P * frcp(p.rho);
   T D = p.rho * w;
   T rhw = D * h;
   s.q[0] = D;
@@ -661,7 +693,7 @@ __device__ __forceinline__ void tetrad_state(const EosK &e, const PrimT<T> &p, c
   s.q[2] = rhw * ut[1];
   s.q[3] = rhw * ut[2];
   // tau = rho h w^2 - P - rho w without cancellation
-  s.q[4] = D * usq / (T(1) + w) + D * p.eps * w + p.P * usq;
+  s.q[4] = D * usq * frcp(T(1) + w) + D * p.eps * w + p.P * usq;
   s.vn = vn;
   s.P = p.P;
   s.f[0] = s.q[0] * vn;
@@ -670,12 +702,12 @@ __device__ __forceinline__ void tetrad_state(const EosK &e, const PrimT<T> &p, c
   s.f[3] = s.q[3] * vn;
   s.f[4] = (s.q[4] + p.P) * vn;
   T cs2 = eos_cs2<T>(e, p.rho, p.eps, p.P);
-  T cs = tsqrt(cs2);
+  T cs = fsqrt(cs2);
   T disc = iw2 * (T(1) - v2 * cs2 - (T(1) - cs2) * vn * vn);
   if (disc < T(0)) disc = T(0);
-  T sd = cs * tsqrt(disc);
+  T sd = cs * fsqrt(disc);
   T a0 = vn * (T(1) - cs2);
-  T iden = T(1) / (T(1) - v2 * cs2);
+  T iden = frcp(T(1) - v2 * cs2);
   s.lm = (a0 - sd) * iden;
   s.lp = (a0 + sd) * iden;
 }
@@ -683,7 +715,7 @@ __device__ __forceinline__ void tetrad_state(const EosK &e, const PrimT<T> &p, c
 template <class T>
 __device__ __forceinline__ void hllc_star(const TState<T> &s, T lam, T lc, T Pc, T *qc) {
   T dl = lam - s.vn;
-  T id = T(1) / (lam - lc);
+  T id = frcp(lam - lc);
   qc[0] = s.q[0] * dl * id;
   qc[1] = (s.q[1] * dl + Pc - s.P) * id;
   qc[2] = s.q[2] * dl * id;
@@ -702,7 +734,7 @@ __device__ __forceinline__ void hllc_tetrad(const TState<T> &L, const TState<T> 
     for (int m = 0; m < 5; m++) G[m] = s.f[m] - vint * s.q[m];
     return;
   }
-  T idl = T(1) / (lamR - lamL);
+  T idl = frcp(lamR - lamL);
   T qh[5], fh[5];
   for (int m = 0; m < 5; m++) {
     qh[m] = (lamR * R.q[m] - lamL * L.q[m] + L.f[m] - R.f[m]) * idl;
@@ -714,8 +746,8 @@ __device__ __forceinline__ void hllc_tetrad(const TState<T> &L, const TState<T> 
   T qc = qh[1];
   T disc = qb * qb - T(4) * qa * qc;
   if (disc < T(0)) disc = T(0);
-  T den = -qb + tsqrt(disc);
-  T lc = (den > T(0)) ? T(2) * qc / den : T(0);
+  T den = -qb + fsqrt(disc);
+  T lc = (den > T(0)) ? T(2) * qc * frcp(den) : T(0);
   if (!(den > T(0)) || !(lc > lamL && lc < lamR)) {
     if (vint <= lamL) for (int m = 0; m < 5; m++) G[m] = L.f[m] - vint * L.q[m];
     else if (vint <= lamR) for (int m = 0; m < 5; m++) G[m] = fh[m] - vint * qh[m];
@@ -760,13 +792,13 @@ __device__ __forceinline__ void valencia(const EosK &e, const FaceMet<T> &m, con
     un = W * W * p.u[n];
     gnn = W * W;
   }
-  T w = tsqrt(T(1) + usq);
-  T iw = T(1) / w;
+  T w = fsqrt(T(1) + usq);
+  T iw = frcp(w);
   T vn = un * iw;
-  T h = T(1) + p.eps + p.P / p.rho;
+  T h = T(1) + p.eps + p.P * frcp(p.rho);
   T D = p.rho * w;
-  T tau = D * usq / (T(1) + w) + D * p.eps * w + p.P * usq;
-  T sg = T(1) / (W * W * W);
+  T tau = D * usq * frcp(T(1) + w) + D * p.eps * w + p.P * usq;
+  T sg = frcp(W * W * W);
   T bn = (MC == MC_GEN) ? m.beta[n] : T(0);
   T tr = m.alp * vn - bn;
   T rhw = D * h;
@@ -777,13 +809,14 @@ __device__ __forceinline__ void valencia(const EosK &e, const FaceMet<T> &m, con
   for (int j = 0; j < 3; j++) Q[1 + j] = sg * (rhw * p.u[j]);
   Q[4] = sg * tau;
   T cs2 = eos_cs2<T>(e, p.rho, p.eps, p.P);
-  T cs = tsqrt(cs2);
+  T cs = fsqrt(cs2);
   T v2 = usq * iw * iw;
   T disc = (iw * iw) * (gnn * (T(1) - v2 * cs2) - vn * vn * (T(1) - cs2));
   if (disc < T(0)) disc = T(0);
-  T a = m.alp / (T(1) - v2 * cs2);
-  lm = a * (vn * (T(1) - cs2) - cs * tsqrt(disc)) - bn;
-  lp = a * (vn * (T(1) - cs2) + cs * tsqrt(disc)) - bn;
+  T a = m.alp * frcp(T(1) - v2 * cs2);
+  const T sd = cs * fsqrt(disc);
+  lm = a * (vn * (T(1) - cs2) - sd) - bn;
+  lp = a * (vn * (T(1) - cs2) + sd) - bn;
 }
 
 // Face flux (tau form), direction dir (0 = x, 1 = z).  speed: largest
@@ -853,7 +886,7 @@ __device__ __forceinline__ void face_flux(const EosK &e, const FaceMet<T> &m, in
   T G[5], lamL, lamR;
   hllc_tetrad(L, R, vint, G, lamL, lamR);
   // back to the Eulerian frame, densitised by alpha W^-3
-  T pref = m.alp / (W * W * W) * sqgnn;
+  T pref = m.alp * frcp(W * W * W) * sqgnn;
   out.f[0] = pref * G[0];
   out.f[4] = pref * G[4];
   if (MC == MC_GEN) {
@@ -869,7 +902,7 @@ __device__ __forceinline__ void face_flux(const EosK &e, const FaceMet<T> &m, in
       out.f[1 + j] = pref * s;
     }
   } else {
-    T pw = pref / W;  // covariant legs W^-1 times unit vectors
+    T pw = pref * frcp(W);  // covariant legs W^-1 times unit vectors
     if (dir == 0) {
       out.f[1] = pw * G[1]; out.f[2] = pw * G[2]; out.f[3] = pw * G[3];
     } else {
