@@ -162,15 +162,19 @@ struct C2PAcc {
 // v corrected where a flag is set, then q_out, the primitives and flags of
 // q_out written, so that the next stage needs no recovery pass of its own.
 // W, gt: metric at the cell.  Without CHAIN the caller stores v itself.
+// fprev: the cell's flag byte in P.flags_out when the caller loaded it
+// already, else -1.
 template <int MC, int EK>
 __device__ __forceinline__ void recover_store(const PatchK &P, const EosK &e, unsigned ic, double W,
                                               const double *gtu, double xc, double dV, double *v,
-                                              double &mb, double &jm, C2PAcc &acc, double zg) {
+                                              double &mb, double &jm, C2PAcc &acc, double zg,
+                                              int fprev = -1) {
   {
     double pp[6];
     C2PResult r = con2prim_cell<MC, EK>(e, P.cp, W, gtu, xc, P.g.geom, v, pp, zg);
     // a cell that was and stays atmosphere already holds its primitives
-    const bool keep = P.cp.reuse_atm && (r.flags & GRHD_FLAG_ATM) && (ld32(P.flags_out, ic) & GRHD_FLAG_ATM);
+    const bool keep = P.cp.reuse_atm && (r.flags & GRHD_FLAG_ATM) &&
+                      ((fprev >= 0 ? (uint8_t)fprev : ld32(P.flags_out, ic)) & GRHD_FLAG_ATM);
     if (!keep)
       for (int c = 0; c < 6; c++) st32(P.po[c], ic, pp[c]);
     st32(P.flags_out, ic, (uint8_t)r.flags);
@@ -189,11 +193,11 @@ __device__ __forceinline__ void recover_store(const PatchK &P, const EosK &e, un
 template <int MC, int EK, bool CHAIN>
 __device__ __forceinline__ void finish_cell(const PatchK &P, const EosK &e, unsigned ic, double W,
                                             const double *gt, double xc, double dV, double *v,
-                                            double &mb, double &jm, C2PAcc &acc) {
+                                            double &mb, double &jm, C2PAcc &acc, int fprev = -1) {
   if (!CHAIN) return;  // stored by the caller as they were computed
   double gtu[6];
   if (MC == MC_GEN) inv_sym3(gt, gtu);
-  recover_store<MC, EK>(P, e, ic, W, gtu, xc, dV, v, mb, jm, acc, -1.0);
+  recover_store<MC, EK>(P, e, ic, W, gtu, xc, dV, v, mb, jm, acc, -1.0, fprev);
 }
 
 // Chained stages with the learned guess (GRHD_GUESS_MLP): the recovery of
@@ -254,9 +258,13 @@ struct LeanLoads {
   unsigned ic[CPT];
   double qs5[CPT][5], qn5[CPT][5], ai5[CPT][5];
   double ax[CPT][7], wx[CPT][7], az[CPT][7], wz[CPT][7];
+  int fo[CPT];  // chained stages: the cell's byte in flags_out, or -1
 };
 
-template <int TX, int TZ>
+// CHAIN: the byte of flags_out that the recovery at the end of a chained
+// stage consults (reuse_atm) is loaded here too, so that no load waits
+// behind the arithmetic.
+template <int TX, int TZ, bool CHAIN>
 __device__ __forceinline__ void lean_issue(const PatchK &P, int j0, int k0, LeanLoads<TX, TZ> &L) {
   using LL = LeanLoads<TX, TZ>;
   const GridK &g = P.g;
@@ -274,6 +282,7 @@ __device__ __forceinline__ void lean_issue(const PatchK &P, int j0, int k0, Lean
         for (int m = 0; m < 5; m++) L.qn5[ci][m] = ld32(P.qn[m], ic);
       if (P.use_acc_in)
         for (int m = 0; m < 5; m++) L.ai5[ci][m] = ld32(P.acc_in[m], ic);
+      L.fo[ci] = (CHAIN && P.cp.reuse_atm) ? (int)ld32(P.flags_out, ic) : -1;
       for (int i = 0; i < 7; i++) {
         const unsigned ix = ic - 3u + (unsigned)i, iz = ic + (unsigned)(i - 3) * pitch;
         L.ax[ci][i] = mval32(P.m, GRHD_M_ALP, ix);
@@ -394,7 +403,8 @@ __device__ __forceinline__ void lean_atm_tile(const PatchK &P, const EosK &e, in
         st32(P.acc_out[m], ic, av);
       }
     }
-    finish_cell<MC_CF, EK, CHAIN>(P, e, ic, gm[GRHD_M_W], gm + GRHD_M_GXX, xc, dV, v, mb, jm, acc);
+    finish_cell<MC_CF, EK, CHAIN>(P, e, ic, gm[GRHD_M_W], gm + GRHD_M_GXX, xc, dV, v, mb, jm, acc,
+                                  ld.fo[ci]);
   }
   cmax_out = cmax;
   mb_out = mb;
@@ -446,7 +456,7 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
                             ((uintptr_t)P.flags & 15) == 0;
     if (fast_class) {
       LeanLoads<TX, TZ> ld;
-      lean_issue<TX, TZ>(P, j0, k0, ld);
+      lean_issue<TX, TZ, CHAIN>(P, j0, k0, ld);
       const bool mine = atm_flags16<TZ>(P, j0, k0);
       if (__syncthreads_and(mine) != 0) {
         lean_atm_tile<T, TX, TZ, CHAIN, EK>(P, e, j0, k0, ld, cmax_out, mb_out, jm_out, acc);
