@@ -268,9 +268,8 @@ __device__ __forceinline__ FoldPart fold_wave(const FoldPart *f, int n) {
   return a;
 }
 
-// fold into *diag (one workgroup for up to 8192 records per array, else
-// two small launches: chunks of the records in parallel, then the chunks
-// in order); defined once in grhd_kernels.hip
+// fold into *diag (two small launches: chunks of the records in parallel,
+// then the chunks in order); defined once in grhd_kernels.hip
 // lvl: kFoldMax folded sets of device scratch owned by the caller.
 constexpr int kFoldMax = 64;
 int launch_diag_final(const C2PPart *p1, int n1, const FluxPart *p2, int n2, FoldPart *lvl,

@@ -42,37 +42,15 @@ int fail(int code, const char *fmt, ...) {
 
 // ------------------------------------------------------------ small kernels
 
-// Fold of the diagnostic records into *diag.  Up to kFoldOne records per
-// array, one workgroup of 1024 threads folds everything (two rounds of
-// loads at most).  Beyond that, workgroup b of a first kernel folds the
-// b-th contiguous chunk of each record array and one wave of a second
-// folds the chunk results in a fixed order.  Either way the order of the
-// additions is a function of the record counts alone.
-constexpr int kFoldOne = 8192;
-
+// Fold of the diagnostic records into *diag.  Workgroup b of the first
+// kernel folds the b-th contiguous chunk of each record array; one wave of
+// the second folds the chunk results in a fixed order.  The chunk count
+// is a function of the record counts, so the result depends on nothing
+// else.
 __device__ __forceinline__ void fold_chunk(int n, int nchunk, int b, int &lo, int &m) {
   const int c = (n + nchunk - 1) / nchunk;
   lo = b * c < n ? b * c : n;
   m = n - lo < c ? n - lo : c;
-}
-
-__device__ __forceinline__ void store_diag(const FoldPart &f, grhd_diag *diag) {
-  diag->max_courant = f.cmax;
-  diag->Mb = f.mb;
-  diag->J = f.jm;
-  diag->n_rescale = f.n[0];
-  diag->n_cold = f.n[1];
-  diag->n_atm = f.n[2];
-  diag->n_fail = f.n[3];
-  diag->iter_sum = f.n[4];
-  diag->iter_max = f.n[5];
-}
-
-__global__ void __launch_bounds__(1024)
-k_diag_one(const C2PPart *p1, int n1, const FluxPart *p2, int n2, grhd_diag *diag) {
-  __shared__ unsigned long long red[16][9];
-  FoldPart f = fold_records<1024>(p1, n1, p2, n2, red);
-  if (threadIdx.x == 0) store_diag(f, diag);
 }
 
 __global__ void __launch_bounds__(256)
@@ -87,19 +65,25 @@ k_diag_chunks(const C2PPart *p1, int n1, const FluxPart *p2, int n2, FoldPart *l
 
 __global__ void __launch_bounds__(64) k_diag_final(const FoldPart *lvl, int nchunk, grhd_diag *diag) {
   FoldPart f = fold_wave(lvl, nchunk);
-  if (threadIdx.x == 0) store_diag(f, diag);
+  if (threadIdx.x == 0) {
+    diag->max_courant = f.cmax;
+    diag->Mb = f.mb;
+    diag->J = f.jm;
+    diag->n_rescale = f.n[0];
+    diag->n_cold = f.n[1];
+    diag->n_atm = f.n[2];
+    diag->n_fail = f.n[3];
+    diag->iter_sum = f.n[4];
+    diag->iter_max = f.n[5];
+  }
 }
 
 int launch_diag_final(const C2PPart *p1, int n1, const FluxPart *p2, int n2, FoldPart *lvl,
                       grhd_diag *diag, hipStream_t st) {
-  const int n = n1 > n2 ? n1 : n2;
-  if (n <= kFoldOne) {
-    hipLaunchKernelGGL(k_diag_one, dim3(1), dim3(1024), 0, st, p1, n1, p2, n2, diag);
-    return launch_status("diag final");
-  }
   // about one record of each array per thread, at most kFoldMax chunks
+  const int n = n1 > n2 ? n1 : n2;
   int nchunk = (n + 255) / 256;
-  nchunk = nchunk > kFoldMax ? kFoldMax : nchunk;
+  nchunk = nchunk < 1 ? 1 : (nchunk > kFoldMax ? kFoldMax : nchunk);
   hipLaunchKernelGGL(k_diag_chunks, dim3(nchunk), dim3(256), 0, st, p1, n1, p2, n2, lvl);
   hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, st, lvl, nchunk, diag);
   return launch_status("diag final");
