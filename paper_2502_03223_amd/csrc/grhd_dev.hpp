@@ -79,9 +79,6 @@ __device__ __forceinline__ double mval32(const MetK &m, int f, unsigned i) {
   return m.f[f] ? ld32(m.f[f], i) : m.c[f];
 }
 
-template <class T> __device__ __forceinline__ T tsqrt(T x) { return sqrt(x); }
-template <> __device__ __forceinline__ float tsqrt<float>(float x) { return sqrtf(x); }
-
 // Reciprocal and square root of the flux arithmetic from the hardware
 // approximations instead of the correctly rounded sequences: frcp is
 // v_rcp_f64 (relative error about 2^-24) refined by two Newton steps,
@@ -114,7 +111,9 @@ template <> __device__ __forceinline__ double fsqrt<double>(double x) {
 template <> __device__ __forceinline__ float fsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // inverse of a symmetric 3x3 (xx,xy,xz,yy,yz,zz) by cofactors / det
-template <class T>
+// FAST: the reciprocal of the determinant from frcp (the face metric of the
+// flux); the recovery and the sources keep the correctly rounded division.
+template <class T, bool FAST = false>
 __device__ __forceinline__ void inv_sym3(const T *a, T *inv) {
   T cxx = a[3] * a[5] - a[4] * a[4];
   T cxy = a[2] * a[4] - a[1] * a[5];
@@ -123,7 +122,7 @@ __device__ __forceinline__ void inv_sym3(const T *a, T *inv) {
   T cyz = a[1] * a[2] - a[0] * a[4];
   T czz = a[0] * a[3] - a[1] * a[1];
   T det = a[0] * cxx + a[1] * cxy + a[2] * cxz;
-  T id = T(1) / det;
+  T id = FAST ? frcp(det) : T(1) / det;
   inv[0] = cxx * id; inv[1] = cxy * id; inv[2] = cxz * id;
   inv[3] = cyy * id; inv[4] = cyz * id; inv[5] = czz * id;
 }
@@ -826,7 +825,7 @@ __device__ __forceinline__ void face_flux(const EosK &e, const FaceMet<T> &m, in
                                           const PrimT<T> &pL, const PrimT<T> &pR, FluxT<T> &out) {
   const int n = (dir == 0) ? 0 : 2;
   T gtu[6];
-  if (MC == MC_GEN) inv_sym3(m.gt, gtu);
+  if (MC == MC_GEN) inv_sym3<T, true>(m.gt, gtu);
   if (riemann == GRHD_RIEMANN_TVDLF) {
     T fL[5], fR[5], qL[5], qR[5], l1, l2, l3, l4;
     valencia<T, MC>(e, m, gtu, n, pL, fL, qL, l1, l2);
@@ -842,23 +841,23 @@ __device__ __forceinline__ void face_flux(const EosK &e, const FaceMet<T> &m, in
   if (MC == MC_GEN) {
     const T *gt = m.gt;
     if (dir == 0) {
-      T B = T(1) / tsqrt(gtu[0]);
-      T C = T(1) / tsqrt(gt[5]);
+      T B = frcp(fsqrt(gtu[0]));
+      T C = frcp(fsqrt(gt[5]));
       T Dh = B * C;
       El[0][0] = W * B * gtu[0]; El[0][1] = W * B * gtu[1]; El[0][2] = W * B * gtu[2];
       El[1][0] = T(0); El[1][1] = W * Dh * gt[5]; El[1][2] = -(W * Dh * gt[4]);
       El[2][0] = T(0); El[2][1] = T(0); El[2][2] = W * C;
     } else {
       // z faces: cyclic relabelling (n, t1, t2) = (z, x, y)
-      T B = T(1) / tsqrt(gtu[5]);
-      T C = T(1) / tsqrt(gt[3]);
+      T B = frcp(fsqrt(gtu[5]));
+      T C = frcp(fsqrt(gt[3]));
       T Dh = B * C;
       El[0][0] = W * B * gtu[2]; El[0][1] = W * B * gtu[4]; El[0][2] = W * B * gtu[5];
       El[1][0] = W * Dh * gt[3]; El[1][1] = -(W * Dh * gt[1]); El[1][2] = T(0);
       El[2][0] = T(0); El[2][1] = W * C; El[2][2] = T(0);
     }
-    sqgnn = W * tsqrt(gtu[s3i(n, n)]);
-    vint = m.beta[n] / (m.alp * sqgnn);
+    sqgnn = W * fsqrt(gtu[s3i(n, n)]);
+    vint = m.beta[n] * frcp(m.alp * sqgnn);
   } else {
     sqgnn = W;
     vint = T(0);
@@ -891,7 +890,7 @@ __device__ __forceinline__ void face_flux(const EosK &e, const FaceMet<T> &m, in
   out.f[4] = pref * G[4];
   if (MC == MC_GEN) {
     // covariant legs e_(a)_j = gamma_ji e_(a)^i, gamma_ij = W^-2 gt_ij
-    T iW2 = T(1) / (W * W);
+    T iW2 = frcp(W * W);
     for (int j = 0; j < 3; j++) {
       T s = T(0);
       for (int a = 0; a < 3; a++) {

@@ -701,7 +701,7 @@ __device__ __forceinline__ void substep_tile(const PatchK &P, const EosK &e, int
           out.speed = fm.alp * (cs_atm * fm.W);
         } else if (uni) {
           T Q[5], lm, lp, gtu[6];
-          if (MC == MC_GEN) inv_sym3(fm.gt, gtu);
+          if (MC == MC_GEN) inv_sym3<T, true>(fm.gt, gtu);
           valencia<T, MC>(e, fm, gtu, isx ? 0 : 2, L, out.f, Q, lm, lp);
           out.speed = fmax(fabs(lm), fabs(lp));
         } else {
