@@ -466,9 +466,12 @@ int grhd_fmr_reflux(const grhd_grid *parent, const grhd_cons *q_parent,
  * the level descriptors (device buffers stay the caller's), recovers every
  * level with a child into its first slice.  step: one step dt0 of level 0
  * (all finer levels follow).  Single path kernels on 16 x 15 tiles (16 x 7
- * on grids of fewer than 1536 tiles of 16 x 16).  The driver owns one
- * recovery flag array per level (device memory, freed by destroy, which
- * first waits for the device to finish queued work). */
+ * on grids of fewer than 1536 tiles of 16 x 16).  With opts->c2p.guess =
+ * GRHD_GUESS_MLP every level's recovery of its evolved cells starts from
+ * the learned guess (the prolonged frame of a child is recovered without
+ * it).
+ * The driver owns one recovery flag array per level (device memory, freed
+ * by destroy, which first waits for the device to finish queued work). */
 int grhd_fmr_create(const grhd_level *levels, int nlev, const grhd_eos *eos,
                     const grhd_options *opts, int l_fix, double t0,
                     grhd_fmr **out, void *hip_stream);

@@ -26,6 +26,9 @@ int fill_patch(const grhd_grid *grid, const grhd_metric *metric, const grhd_rk_s
                const grhd_cons *qn, const grhd_cons *qs, const grhd_cons *qout, const grhd_prim *p,
                const grhd_cons *acc_in, const grhd_cons *acc_out, double *flux_reg, int recon,
                int riemann, PatchK &pk);
+int launch_con2prim_mlp_rect(const GridK &g, const EosK &e, const C2PK &cp, const MetK &m, int mc,
+                             const Q5 &q, const P6 &p, uint8_t *flags, C2PPart *part, int jlo, int jhi,
+                             int klo, int khi, hipStream_t st);
 int launch_con2prim(const GridK &g, const EosK &e, const C2PK &cp, const MetK &m, int mc,
                     const Q5 &q, const P6 &p, uint8_t *flags, C2PPart *diag, hipStream_t st);
 int launch_substep(const PatchK &pk, const EosK &e, int prec, int mc, int shape, FluxPart *part2,
@@ -398,18 +401,27 @@ static int prolong(const grhd_grid *pg, const SliceK &S, const grhd_grid *cg,
 
 // recovery of a child level's q_s (cells j < rnx, k < rnz) with its frame
 // prolonged from the parent slices S (the EXTERNAL halo if halo, the
-// nbuf-wide buffer band if nbuf > 0) in one launch (k_fmr_prep)
+// nbuf-wide buffer band if nbuf > 0) in one launch (k_fmr_prep).  With the
+// learned guess the cells j < rnx, k < rnz are recovered by the seeded
+// recovery kernel first and k_fmr_prep prolongs and recovers the frame only
+// (the two sets of cells are disjoint).
 static int prep(const grhd_grid *pg, const SliceK &S, const grhd_level &L, const EosK &e, const C2PK &cp,
                 const Q5 &q, const P6 &p, uint8_t *flags, int mc, int rnx, int rnz, int halo, int nbuf,
                 hipStream_t st) {
   const GridK P = to_gridk(pg), Cg = to_gridk(&L.grid);
+  const MetK m = to_metk(&L.metric);
+  const bool seeded = cp.guess == GRHD_GUESS_MLP;
+  if (seeded) {
+    const int rc = launch_con2prim_mlp_rect(Cg, e, cp, m, mc, q, p, flags, nullptr, 0, rnx, 0, rnz, st);
+    if (rc) return rc;
+  }
   const int segs = (rnx + PREP_THREADS - 1) / PREP_THREADS;
-  const long long nrec = (long long)segs * rnz;
+  const long long nrec = seeded ? 0 : (long long)segs * rnz;
   const long long nframe = (halo ? prolong_count(Cg) : 0) + band_count(Cg, nbuf);
   const long long npro = (nframe + PRO_CELLS - 1) / PRO_CELLS;
   if (nrec + npro >= (1LL << 31)) return fail(GRHD_ERR_UNSUPPORTED, "level too large");
+  if (nrec + npro == 0) return GRHD_OK;
   const dim3 grid((unsigned)(nrec + npro)), block(PREP_THREADS);
-  const MetK m = to_metk(&L.metric);
   const bool ideal = e.kind == GRHD_EOS_IDEAL;
   if (mc == MC_GEN) {
     if (ideal)
@@ -650,7 +662,6 @@ extern "C" int grhd_fmr_create(const grhd_level *levels, int nlev, const grhd_eo
   if (!opts) return fail(GRHD_ERR_INVALID, "opts is NULL");
   if ((rc = check_eos(eos)) || (rc = check_c2p(&opts->c2p)) || (rc = check_face_eps(opts->face_eps)))
     return rc;
-  if (opts->c2p.guess != GRHD_GUESS_NONE) return fail(GRHD_ERR_UNSUPPORTED, "the driver recovers without a learned guess");
   if (opts->prec != GRHD_PREC_FP64 && opts->prec != GRHD_PREC_MIXED) return fail(GRHD_ERR_INVALID, "bad prec");
   if (l_fix < 0) return fail(GRHD_ERR_INVALID, "l_fix must be >= 0");
   for (int l = 0; l < nlev; l++) {

@@ -149,12 +149,26 @@ static void launch_mlp(dim3 grid, hipStream_t st, const GridK &g, const EosK &e,
                      jlo, jhi, klo);
 }
 
+int launch_con2prim_mlp_rect(const GridK &g, const EosK &e, const C2PK &cp, const MetK &m, int mc,
+                             const Q5 &q, const P6 &p, uint8_t *flags, C2PPart *part, int jlo, int jhi,
+                             int klo, int khi, hipStream_t st);
+
 int launch_con2prim_mlp(const GridK &g, const EosK &e, const C2PK &cp, const MetK &m, int mc,
                         const Q5 &q, const P6 &p, uint8_t *flags, C2PPart *part, hipStream_t st) {
   int jlo = (g.bc[0] == GRHD_BC_EXTERNAL) ? -g.ng : 0;
   int jhi = (g.bc[1] == GRHD_BC_EXTERNAL) ? g.nx + g.ng : g.nx;
   int klo = (g.bc[2] == GRHD_BC_EXTERNAL) ? -g.ng : 0;
   int khi = (g.bc[3] == GRHD_BC_EXTERNAL) ? g.nz + g.ng : g.nz;
+  return launch_con2prim_mlp_rect(g, e, cp, m, mc, q, p, flags, part, jlo, jhi, klo, khi, st);
+}
+
+// The same recovery over the cells [jlo, jhi) x [klo, khi) of the grid
+// (cells outside the interior only on EXTERNAL sides); part: one record
+// per workgroup, nullable.
+int launch_con2prim_mlp_rect(const GridK &g, const EosK &e, const C2PK &cp, const MetK &m, int mc,
+                             const Q5 &q, const P6 &p, uint8_t *flags, C2PPart *part, int jlo, int jhi,
+                             int klo, int khi, hipStream_t st) {
+  if (jhi <= jlo || khi <= klo) return GRHD_OK;
   dim3 grid((jhi - jlo + 255) / 256, khi - klo);
   bool ideal = e.kind == GRHD_EOS_IDEAL;
   if (mc == MC_GEN) {

@@ -134,13 +134,13 @@ def composite_mass(levels_q, grids, nbuf=0):
     return M
 
 
-def run_pair(orc, grids, eos, metrics, prims, l_fix, dt, nstep, nbuf=0):
+def run_pair(orc, grids, eos, metrics, prims, l_fix, dt, nstep, nbuf=0, gpu_opts=None):
     qs = [orc.prim2con(g, eos, m, p, with_ghosts=True) for g, m, p in zip(grids, metrics, prims)]
     nb = [nbuf if l > 0 else 0 for l in range(len(grids))]
     drv = orc.FmrDriver([dict(grid=g, metric=m, q=q, nbuf=b) for g, m, q, b in zip(grids, metrics, qs, nb)],
                         eos, OPTS, l_fix=l_fix)
     lev_g = [dict(grid=g, metric=mdev(m), q=dev(q), nbuf=b) for g, m, q, b in zip(grids, metrics, qs, nb)]
-    h = grhd.Hierarchy(lev_g, eos, OPTS, l_fix=l_fix)
+    h = grhd.Hierarchy(lev_g, eos, gpu_opts or OPTS, l_fix=l_fix)
     M0 = composite_mass([L["q"] for L in drv.lev], grids, nbuf)
     for _ in range(nstep):
         drv.step(dt)
@@ -212,3 +212,28 @@ def test_hierarchy_star_parity(orc, nbuf):
         assert e <= 1e-12, (l, e)
     assert h.time == pytest.approx(2 * dt)
     h.close()
+
+
+@pytest.mark.parametrize("nbuf", [0, 4])
+def test_hierarchy_with_learned_guess(orc, nbuf):
+    """The blast on three cylindrical levels with every level's recovery
+    seeded by the learned guess: the levels after two coarse steps equal the
+    oracle's driver (which recovers from the bracket alone) to the bars of
+    the unseeded driver, and composite mass is conserved to round-off (the
+    guess moves only where each root search starts)."""
+    from test_gpu_mlp import train
+    net, _ = train(orc, n=100_000, epochs=4)
+    grids = synth.fmr_grids(3, 32, 1.0, geom="cyl", outer="reflect", nbuf=nbuf)
+    eos = synth.ideal_eos(GAM)
+    prims = [synth.blast_state(g, (0.3, 0.2), 0.15, 7) for g in grids]
+    dt = 0.4 * grids[0]["dx"]
+    seeded = dict(OPTS, c2p=dict(OPTS["c2p"], mlp=net.buf))
+    out_g, out_o, M0 = run_pair(orc, grids, eos, [{}] * 3, prims, 0, dt, 2, nbuf, gpu_opts=seeded)
+    for l, g in enumerate(grids):
+        e = normwise(synth.interior(g, out_g[l]), synth.interior(g, out_o[l]))
+        assert e <= 1e-12, (l, e)
+        e = percell_local(synth.interior(g, out_g[l]), synth.interior(g, out_o[l]), (0, 4),
+                          radius=reach(l, 0, 2))
+        assert e <= 1e-12, (l, e)
+    M_g = composite_mass(out_g, grids, nbuf)
+    assert abs(M_g - M0) <= 1e-13 * abs(M0), (M0, M_g)
