@@ -275,16 +275,21 @@ constexpr int substep_waves() {
 constexpr int CHAIN_TZ = 15;  // tiles of the chained stage: 16 x 15
 
 // The chained instances: as above, except that the FP32 hybrid-EOS
-// recovery would spill at four waves and the instances with the learned
-// guess (its operand fragments held across the network) stay
-// unconstrained, and the FP32 ideal-gas instance takes three waves (at four
-// it spills 56 B per lane; measured on the 1024^2 star 67.1 against 69.2 us
-// per stage).
+// recovery would spill at four waves and stays unconstrained, the FP32
+// ideal-gas instance takes three waves (at four it spills 56 B per lane;
+// measured on the 1024^2 star 67.1 against 69.2 us per stage), and the
+// instances with the learned guess take three waves (conformally flat) or
+// two (general metric): unbounded, the compiler kept the network's operand
+// fragments in 36-48 AGPRs on top of the VGPRs, a wave per SIMD less;
+// bounded, the same work fits without spilling (the mixed chained form with
+// the guess on the 1024^2 star: 1.25e10 against 1.0e10 zone-updates/s).
 template <class T, int MC, int EK, bool ML>
 constexpr int chain_waves() {
-  return ((sizeof(T) == 4 && EK != GRHD_EOS_IDEAL) || ML) ? 1
-         : (sizeof(T) == 4 && MC == MC_CF)                 ? 3
-                                                           : substep_waves<T, MC, 16, CHAIN_TZ>();
+  return (sizeof(T) == 4 && EK != GRHD_EOS_IDEAL) ? 1
+         : (ML && MC == MC_CF)                     ? 3
+         : ML                                      ? 2
+         : (sizeof(T) == 4 && MC == MC_CF)         ? 3
+                                                   : substep_waves<T, MC, 16, CHAIN_TZ>();
 }
 
 template <class T, int MC, int TX, int TZ>
