@@ -151,7 +151,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     forms = [f for f in args.forms.split(",") if f]
@@ -1071,8 +1071,8 @@ def cpu_baseline(grid, eos, metric_np, p_np, c2p, dt, steps, rows_single, reps=3
     every core running the oracle on its band at the same time (bands are
     independent samples of the workload; the rate is total zone-updates
     over the wall time of the slowest band); (b) one core on the first
-    `rows_single` rows.  Cores: the host's, capped at 16 (a GPU machine's
-    share).  Substep loops only; set-up excluded."""
+    `rows_single` rows.  Cores: the host's, capped at 16 (the host share
+    of one GPU).  Substep loops only; set-up excluded."""
     import multiprocessing as mp
     import platform
     import oracle
