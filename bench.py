@@ -446,8 +446,7 @@ def train_guess(samples, eos, seed, train_steps, dev):
     qt = torch.zeros((5,) + pt.shape[1:], dtype=torch.float64, device=dev)
     grhd.prim2con(tg, eos, {}, pt, qt)
     qi = qt[:, ng, ng:ng + npair]
-    X = grhd.recovery_features(qi)
-    y = torch.log10(pt[4, ng, ng:ng + npair] / qi[0])
+    X, y = grhd.recovery_features(qi, pt[4, ng, ng:ng + npair])
     xm, xs = X.mean(dim=0), X.std(dim=0)
     ym, ys = y.mean(), y.std()
     scal = torch.cat([xm, xs, ym.view(1), ys.view(1)]).float().contiguous()
@@ -976,8 +975,7 @@ def learned_form(args):
     qt = torch.zeros((5,) + pt.shape[1:], dtype=torch.float64, device=dev)
     grhd.prim2con(tg, eos, {}, pt, qt)
     qi = qt[:, ng, ng:ng + npair]
-    X = grhd.recovery_features(qi)
-    y = torch.log10(pt[4, ng, ng:ng + npair] / qi[0])
+    X, y = grhd.recovery_features(qi, pt[4, ng, ng:ng + npair])
     xm, xs = X.mean(dim=0), X.std(dim=0)
     ym, ys = y.mean(), y.std()
     scal = torch.cat([xm, xs, ym.view(1), ys.view(1)]).float().contiguous()

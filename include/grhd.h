@@ -514,6 +514,15 @@ int grhd_mlp_pack(void *mlp, const float *params, const float *scal,
 int grhd_mlp_forward(const void *mlp, const float *X, float *y, int n,
                      void *hip_stream);
 
+/* Training data of the network: for n samples of densitised conserved
+ * values of a flat Cartesian metric (q: five device arrays of n doubles),
+ * X (device n x 3 doubles, row-major) receives the unscaled features
+ * (log10 D, S/E, log10((E - D)/D)), S = |S_i|, and, when P (device n
+ * doubles, the samples' pressures) and y are given, y the unscaled target
+ * log10(P/D).  n >= 0; errors: GRHD_ERR_INVALID for NULL q fields or X. */
+int grhd_mlp_features(const grhd_cons *q, long long n, const double *P,
+                      double *X, double *y, void *hip_stream);
+
 /* Gradient of the loss mean_i (y_i - t_i)^2 over n >= 1 samples at the FP32
  * params (W1, W2 rounded to BF16 as in the forward kernel, FP32
  * arithmetic): grad device NPARAM floats (overwritten), loss device float

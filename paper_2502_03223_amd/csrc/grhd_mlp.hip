@@ -405,6 +405,37 @@ extern "C" int grhd_mlp_pack(void *mlp, const float *params, const float *scal, 
   return launch_status("mlp pack");
 }
 
+// Training data: the unscaled features of the network (the definition the
+// recovery kernels standardise) and the target log10(P/D) of one sample
+// per thread, in FP64.
+__global__ void __launch_bounds__(256)
+k_mlp_features(Q5 q, long long n, const double *P, double *X, double *y) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double D = q.q[0][i], E = q.q[4][i];
+  const double S = sqrt(q.q[1][i] * q.q[1][i] + q.q[2][i] * q.q[2][i] + q.q[3][i] * q.q[3][i]);
+  X[3 * i] = log10(D);
+  X[3 * i + 1] = S / E;
+  X[3 * i + 2] = log10((E - D) / D);
+  if (y) y[i] = log10(P[i] / D);
+}
+
+extern "C" int grhd_mlp_features(const grhd_cons *q, long long n, const double *P, double *X, double *y,
+                                 void *hip_stream) {
+  if (!q || !X) return fail(GRHD_ERR_INVALID, "NULL argument");
+  for (int c = 0; c < 5; c++)
+    if (!q->q[c]) return fail(GRHD_ERR_INVALID, "q field %d is NULL", c);
+  if (n < 0) return fail(GRHD_ERR_INVALID, "n must be >= 0");
+  if ((P == nullptr) != (y == nullptr)) return fail(GRHD_ERR_INVALID, "P and y go together");
+  if (n == 0) return GRHD_OK;
+  if (n > (1LL << 40)) return fail(GRHD_ERR_UNSUPPORTED, "too many samples");
+  Q5 qq;
+  for (int c = 0; c < 5; c++) qq.q[c] = q->q[c];
+  hipLaunchKernelGGL(k_mlp_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)hip_stream,
+                     qq, n, P, X, y);
+  return launch_status("mlp features");
+}
+
 extern "C" int grhd_mlp_forward(const void *mlp, const float *X, float *y, int n, void *hip_stream) {
   if (!mlp || !X || !y) return fail(GRHD_ERR_INVALID, "NULL argument");
   if (n < 0) return fail(GRHD_ERR_INVALID, "n must be >= 0");

@@ -683,6 +683,8 @@ def _mlp_sigs():
     p, i, f = C.c_void_p, C.c_int, C.c_float
     L.grhd_mlp_bytes.restype = C.c_size_t
     L.grhd_mlp_bytes.argtypes = []
+    L.grhd_mlp_features.restype = C.c_int
+    L.grhd_mlp_features.argtypes = [C.POINTER(Cons), C.c_longlong, p, p, p, p]
     for name, args in {"grhd_mlp_pack": [p, p, p, p],
                        "grhd_mlp_forward": [p, p, p, i, p],
                        "grhd_mlp_grad": [p, p, p, p, i, p, p],
@@ -749,13 +751,24 @@ def mlp_init(seed, device="cuda"):
     return P.to(device)
 
 
-def recovery_features(q, W=None, x=None, geom="cart"):
-    """Features (log10 D, S/E, log10(tau/D)) and the masks of usable cells
-    from densitised conserved variables of a flat metric (q: 5 x n torch
-    float64).  Matches the in-kernel feature definition."""
-    D, E = q[0], q[4]
-    Sy = q[2] / x if (geom == "cyl" and x is not None) else q[2]
-    S = torch.sqrt(q[1] ** 2 + Sy ** 2 + q[3] ** 2)
-    tau = E - D
-    X = torch.stack([torch.log10(D), S / E, torch.log10(tau / D)], dim=1)
-    return X
+def recovery_features(q, P=None):
+    """Unscaled training features (log10 D, S/E, log10(tau/D)) of n samples
+    of densitised conserved variables of a flat Cartesian metric (q: 5 x n
+    float64 device tensor, each row contiguous), computed by
+    grhd_mlp_features; with P (n float64, the samples' pressures) also the
+    target log10(P/D).  Returns X (n x 3), or (X, y)."""
+    assert q.is_cuda and q.dtype == torch.float64 and q.shape[0] == 5
+    n = q.shape[1]
+    s = Cons()
+    for c in range(5):
+        assert q[c].is_contiguous()
+        s.q[c] = q[c].data_ptr()
+    X = torch.empty((n, 3), dtype=torch.float64, device=q.device)
+    y = None
+    if P is not None:
+        assert P.is_cuda and P.dtype == torch.float64 and P.is_contiguous() and P.shape[0] == n
+        y = torch.empty(n, dtype=torch.float64, device=q.device)
+    vp = lambda t: C.c_void_p(t.data_ptr() if t is not None else 0)  # noqa: E731
+    _check(_mlp_sigs().grhd_mlp_features(C.byref(s), n, vp(P), vp(X), vp(y), _stream()),
+           "grhd_mlp_features")
+    return X if P is None else (X, y)

@@ -85,6 +85,7 @@ def test_null_pointers_rejected(G):
     assert lib.grhd_con2prim(*([None] * 9 + [0, None])) == -1
     assert lib.grhd_reconstruct(None, 0, 0, 0, None, None, None, None) == -1
     assert lib.grhd_hllc_flux(None, 0, 0, 0, None, None, None, None, None, None, None) == -1
+    assert lib.grhd_mlp_features(None, 0, None, None, None, None) == -1
 
 
 def call_chained(G, opts=None, grid=None, alias_p=False, alias_flags=False, null_flags_out=False):

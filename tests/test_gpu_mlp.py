@@ -73,6 +73,29 @@ def test_gradient_matches_oracle(orc):
         assert err <= 1e-4, (a, b, err)
 
 
+def test_features_match_definition():
+    """grhd_mlp_features against the features written out in numpy:
+    (log10 D, |S|/E, log10((E - D)/D)) and the target log10(P/D), on
+    conserved values spanning the recovery samples' range."""
+    rng = np.random.default_rng(5)
+    n = 5000
+    D = 10.0 ** rng.uniform(-10, -2, n)
+    S = rng.normal(size=(3, n)) * D * rng.uniform(0, 3, n)
+    E = D * (1.0 + 10.0 ** rng.uniform(-8, 1, n)) + np.sqrt((S ** 2).sum(0))
+    P = D * 10.0 ** rng.uniform(-9, 0, n)
+    q = torch.from_numpy(np.stack([D, S[0], S[1], S[2], E])).to(DEV)
+    X, y = grhd.recovery_features(q, torch.from_numpy(P).to(DEV))
+    X, y = X.cpu().numpy(), y.cpu().numpy()
+    ref = np.stack([np.log10(D), np.sqrt((S ** 2).sum(0)) / E, np.log10((E - D) / D)], axis=1)
+    # per element, relative to max(1, |value|): the logarithms cross zero
+    for c in range(3):
+        assert np.max(np.abs(X[:, c] - ref[:, c]) / np.maximum(np.abs(ref[:, c]), 1.0)) <= 1e-14, c
+    t = np.log10(P / D)
+    assert np.max(np.abs(y - t) / np.maximum(np.abs(t), 1.0)) <= 1e-14
+    X0 = grhd.recovery_features(q)
+    assert torch.equal(X0.cpu(), torch.from_numpy(X))
+
+
 def training_pairs(orc, seed, n, sampler=None):
     """(D, S, tau) -> P pairs from the oracle's prim->con on seeded states."""
     prims = (sampler or synth.recovery_samples)(seed, n)
