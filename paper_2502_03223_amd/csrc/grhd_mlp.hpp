@@ -188,23 +188,27 @@ __device__ __forceinline__ double mlp_guess_wave(const MlpDev *__restrict__ w, b
   } else {
     S2 = W * W * (Sx * Sx + Sy * Sy + Sz * Sz);
   }
-  double S = sqrt(S2);
-  double tau = E - D;
-  bool good = act && D > 0.0 && E > 0.0 && tau > 0.0 && isfinite(S) && isfinite(E);
-  // features and guess in FP32: the guess only sets where the FP64 root
+  const double tau = E - D;
+  const bool good = act && D > 0.0 && E > 0.0 && tau > 0.0 && isfinite(S2) && isfinite(E);
+  // features and guess in FP32 with the hardware's approximate log2, exp2,
+  // reciprocal and square root: the guess only sets where the FP64 root
   // search starts
+  const float Df = (float)D, Ef = (float)E, tauf = (float)tau;
+  const float Sf = __builtin_amdgcn_sqrtf((float)S2);
+  const float kLg = 0.30102999566f;  // log10(2)
   float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
   if (good) {
-    f0 = (log10f((float)D) - w->xm[0]) / w->xs[0];
-    f1 = ((float)(S / E) - w->xm[1]) / w->xs[1];
-    f2 = (log10f((float)(tau / D)) - w->xm[2]) / w->xs[2];
+    const float iD = __builtin_amdgcn_rcpf(Df);
+    f0 = (__builtin_amdgcn_logf(Df) * kLg - w->xm[0]) * __builtin_amdgcn_rcpf(w->xs[0]);
+    f1 = (Sf * __builtin_amdgcn_rcpf(Ef) - w->xm[1]) * __builtin_amdgcn_rcpf(w->xs[1]);
+    f2 = (__builtin_amdgcn_logf(tauf * iD) * kLg - w->xm[2]) * __builtin_amdgcn_rcpf(w->xs[2]);
   }
   float y = mlp_forward_wave(w, f0, f1, f2);
   double zg = -1.0;
   if (good) {
-    float P0 = (float)D * exp10f(y * w->ys + w->ym);
-    float v0 = (float)S / ((float)E + P0);
-    if (v0 >= 0.0f && v0 < 1.0f) zg = (double)(v0 / sqrtf(1.0f - v0 * v0));
+    const float P0 = Df * __builtin_amdgcn_exp2f((y * w->ys + w->ym) * 3.32192809489f);  // 10^x = 2^(x log2 10)
+    const float v0 = Sf * __builtin_amdgcn_rcpf(Ef + P0);
+    if (v0 >= 0.0f && v0 < 1.0f) zg = (double)(v0 * __builtin_amdgcn_rsqf(1.0f - v0 * v0));
   }
   return zg;
 }
