@@ -413,20 +413,22 @@ __device__ C2PResult con2prim_cell(const EosK &e, const C2PK &cp, double W, cons
           // root
           const float zmf = (float)zm, zpf = (float)zp, qf = (float)qq, rf = (float)r, Gf = (float)e.Gth;
           float zf = fminf(fmaxf((float)zz, zmf), zpf);
+          // (hardware approximations of the square root and reciprocal:
+          // this stage only has to land near the root)
           for (int it = 0; it < 4; it++) {
-            float w = sqrtf(1.0f + zf * zf);
-            float eps = w * qf - zf * rf + zf * zf / (1.0f + w);
+            float w = __builtin_amdgcn_sqrtf(1.0f + zf * zf);
+            float eps = w * qf - zf * rf + zf * zf * __builtin_amdgcn_rcpf(1.0f + w);
             float f, df;
             if (eps > 0.0f) {
-              float ih = 1.0f / (1.0f + Gf * eps);
+              float ih = __builtin_amdgcn_rcpf(1.0f + Gf * eps);
               f = zf - rf * ih;
-              df = 1.0f + rf * Gf * (zf * (1.0f + qf) / w - rf) * ih * ih;
+              df = 1.0f + rf * Gf * (zf * (1.0f + qf) * __builtin_amdgcn_rcpf(w) - rf) * ih * ih;
             } else {
               f = zf - rf;
               df = 1.0f;
             }
             res.iters += 1;
-            float zn = fminf(fmaxf(zf - f / df, zmf), zpf);
+            float zn = fminf(fmaxf(zf - f * __builtin_amdgcn_rcpf(df), zmf), zpf);
             float dz = fabsf(zn - zf);
             zf = zn;
             if (!(dz > 1e-6f * zf)) break;
