@@ -280,13 +280,16 @@ template <int EK>
 __device__ __forceinline__ void c2p_f_df(const EosK &e, double D, double qq, double r, double z,
                                          double &f, double &df) {
   if (EK == GRHD_EOS_IDEAL) {
-    double w = sqrt(1.0 + z * z);
-    double eps = w * qq - z * r + z * z / (1.0 + w);
+    // refined hardware reciprocals and root (within an ulp): the Newton
+    // iteration this feeds stops within the solver tolerance of the same
+    // root, which the bracket safeguards
+    double w = fsqrt(1.0 + z * z);
+    double eps = w * qq - z * r + z * z * frcp(1.0 + w);
     if (eps > 0.0) {
       double h = 1.0 + e.Gth * eps;
-      double ih = 1.0 / h;
+      double ih = frcp(h);
       f = z - r * ih;
-      df = 1.0 + r * e.Gth * (z * (1.0 + qq) / w - r) * ih * ih;
+      df = 1.0 + r * e.Gth * (z * (1.0 + qq) * frcp(w) - r) * ih * ih;
     } else {
       f = z - r;
       df = 1.0;
@@ -451,7 +454,7 @@ __device__ C2PResult con2prim_cell(const EosK &e, const C2PK &cp, double W, cons
           }
           if (f0 < 0.0) { za = zz; ta = true; }
           else { zb = zz; tb = true; }
-          double zn = zz - f0 / df;
+          double zn = zz - f0 * frcp(df);
           bool newton = true;
           if (!(zn > za && zn < zb)) {
             newton = false;
