@@ -428,7 +428,7 @@ extern "C" int grhd_mlp_features(const grhd_cons *q, long long n, const double *
   if (n < 0) return fail(GRHD_ERR_INVALID, "n must be >= 0");
   if ((P == nullptr) != (y == nullptr)) return fail(GRHD_ERR_INVALID, "P and y go together");
   if (n == 0) return GRHD_OK;
-  if (n > (1LL << 40)) return fail(GRHD_ERR_UNSUPPORTED, "too many samples");
+  if (n > (1LL << 38)) return fail(GRHD_ERR_UNSUPPORTED, "too many samples");  // grid x < 2^31
   Q5 qq;
   for (int c = 0; c < 5; c++) qq.q[c] = q->q[c];
   hipLaunchKernelGGL(k_mlp_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)hip_stream,
